@@ -1,0 +1,179 @@
+/*
+ * tril.h -- C ABI of libtril: bounding-volume-hierarchy collision detection
+ * between two photon beams (Breit-Wheeler pair creation), hand-written HIP
+ * kernels for AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Sec. 1 and Sec. 2 of Jansen et al., "Tree Code for
+ * Collision Detection of Large Numbers of Particles -- Application for the
+ * Breit-Wheeler Process"): photons with position, momentum, energy and
+ * macro-particle weight go in; colliding photon pairs, pair counts, the pair
+ * yield and the pair-energy spectrum come out.
+ *
+ * Per time step k (step length dt, window [k dt, (k+1) dt]):
+ *   tril_build   -- one bounding-volume hierarchy (a linear BVH over Morton
+ *                   codes) over the target beam's photon segments swept over
+ *                   the step (boxes enlarged by one step's travel, Sec. 2.1);
+ *   tril_collide -- every query photon's swept box, enlarged by an upper
+ *                   bound of its collision radius, descends that hierarchy
+ *                   (depth-first, a failed box test skips the subtree,
+ *                   Sec. 2.2, box test Eq. 5); surviving leaf pairs get the
+ *                   exact narrow-phase test:
+ *                     s_ij = E_i E_j (1 - u_i.u_j) / (2 m_e^2) > 1   (Eq. 1, 2)
+ *                     min over the window of |X_i(t) - X_j(t)|^2 <= r_ij^2,
+ *                     r_ij^2 = sqrt(w_i w_j) sigma_BW(s_ij) / pi     (Eq. 1)
+ *                   with X(t) = x0 + t p/E (straight lines at c) and hits
+ *                   (i, j, k) appended to the caller's pair buffer;
+ *   tril_stats   -- after the last step: union of the hits over steps (each
+ *                   pair kept once, with its first step), sorted ascending by
+ *                   (i, j); pair count, yield sum sqrt(w_i w_j), pair-energy
+ *                   spectrum and per-step hit counts.
+ *
+ * Units: um for lengths, um/c for times (c = 1), MeV for energies, MeV/c for
+ * momenta. Constants: m_e c^2 = 0.51099895 MeV, r_e = 2.8179403262e-9 um.
+ *
+ * Memory: every pointer is a DEVICE pointer unless marked "host". The caller
+ * owns every input and output buffer and keeps it alive until the stream has
+ * passed the call; the context owns the hierarchy and all scratch memory.
+ * Every call is asynchronous on the context's HIP stream except tril_stats,
+ * which synchronises that stream. One context must not be used from two host
+ * threads at once; distinct contexts are independent.
+ *
+ * Errors: every int-returning call returns TRIL_OK (0) or a negative code;
+ * tril_strerror gives its text. On an error no output buffer is written past
+ * its capacity.
+ */
+#ifndef TRIL_H
+#define TRIL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRIL_OK           0
+#define TRIL_E_INVAL     -1  /* bad argument: NULL pointer, dt <= 0, n < 0, bad edges, bad offsets */
+#define TRIL_E_NOMEM     -2  /* device allocation failed */
+#define TRIL_E_OVERFLOW  -3  /* pair or candidate buffer too small; see tril_stats */
+#define TRIL_E_HIP       -4  /* HIP runtime error; tril_last_hip_error gives its text */
+#define TRIL_E_NOTIMPL   -5  /* flag or mode not implemented */
+#define TRIL_E_STATE     -6  /* call order: collide before any build, or beams of different instance counts */
+#define TRIL_E_DATA      -7  /* photon data rejected on the device: non-finite value, E <= 0 or w < 0 */
+#define TRIL_E_INTERNAL  -8  /* a device-side wait exceeded its bound (should not happen) */
+
+/* tril_params.flags */
+#define TRIL_TIMING        0x1u  /* record HIP events around each phase (ms_* in tril_stats_t) */
+#define TRIL_SORT_QUERIES_ONCE 0x2u /* Morton-order the query beam at its first step only */
+
+typedef struct tril_ctx tril_ctx;
+
+/* One beam as structure-of-arrays, FP64, length n (all instances together).
+ * Positions are at t = 0; photon i is at x_i + t * p_i / E_i at time t.
+ * Independent collision instances are contiguous slices given by the host CSR
+ * array inst_off[0..n_inst] (inst_off[0] = 0, non-decreasing, inst_off[n_inst] = n);
+ * inst_off may be NULL when n_inst == 1. Photons only collide with photons of
+ * the same instance of the other beam. Row indices in outputs are global rows. */
+typedef struct {
+    int64_t n;
+    const double *x, *y, *z;      /* device, n each: position at t = 0 [um] */
+    const double *px, *py, *pz;   /* device, n each: momentum [MeV/c] */
+    const double *E;              /* device, n: energy [MeV], finite and > 0 */
+    const double *w;              /* device, n: macro-particle weight, finite and >= 0 */
+    int32_t n_inst;               /* >= 1 */
+    const int64_t *inst_off;      /* host, n_inst + 1 entries, or NULL if n_inst == 1 */
+} tril_beam;
+
+/* Context parameters (copied at tril_create; the host arrays may be freed afterwards). */
+typedef struct {
+    double dt;                    /* step length [um/c], finite and > 0 */
+    uint32_t flags;               /* TRIL_* flags above */
+    int32_t n_bins;               /* pair-energy spectrum bins, >= 0 */
+    const double *bin_edges;      /* host, n_bins + 1 strictly increasing edges [MeV]; bin b
+                                     holds edges[b] <= E_i + E_j < edges[b+1] */
+    int64_t cand_cap;             /* broad-phase candidates one step may hold (0 = default) */
+    int32_t block_traverse;       /* traversal workgroup size: 64, 128, 256, 512 or 0 = default */
+    int32_t reserved;
+} tril_params;
+
+/* Caller-owned pair buffer. tril_collide appends raw hits (i, j, step) at
+ * positions *count, *count + 1, ... (order unspecified) and adds to *count;
+ * entries at positions >= cap are counted but not written. The caller sets
+ * *count = 0 before the first step of a run (e.g. with hipMemsetAsync). */
+typedef struct {
+    int64_t cap;
+    int32_t *i;                   /* device, cap: query row (beam passed to tril_collide) */
+    int32_t *j;                   /* device, cap: target row (beam passed to tril_build) */
+    int32_t *step;                /* device, cap: step index k */
+    int64_t *count;               /* device, 1 */
+} tril_pairs;
+
+typedef struct {
+    int64_t n_pairs;          /* unique colliding pairs (after the union over steps) */
+    int64_t n_hits;           /* raw (pair, step) hits */
+    int64_t n_candidates;     /* broad-phase candidate pairs, summed over steps */
+    int64_t n_node_visits;    /* hierarchy nodes whose box was tested, summed over steps */
+    int64_t n_queries;        /* query photons sent into the hierarchy, summed over steps */
+    int64_t n_sigma_evals;    /* candidates that needed the cross-section evaluation */
+    int64_t n_builds;         /* tril_build calls since the last reset */
+    int64_t n_collides;       /* tril_collide calls since the last reset */
+    double yield;             /* sum over unique pairs of sqrt(w_i w_j) */
+    double *spectrum;         /* host, n_bins, caller-owned, or NULL */
+    int64_t *step_counts;     /* host, n_step_counts, caller-owned, or NULL: raw hits per step */
+    int32_t n_step_counts;    /* steps 0 .. n_step_counts-1 are counted */
+    int32_t pad0;
+    double ms_build;          /* with TRIL_TIMING: summed event time of tril_build */
+    double ms_query_prep;     /* with TRIL_TIMING: query boxes + Morton order */
+    double ms_traverse;       /* with TRIL_TIMING: traversal kernel */
+    double ms_narrow;         /* with TRIL_TIMING: narrow-phase kernel */
+    int64_t n_timed_steps;    /* number of tril_collide calls the ms_* sums cover */
+} tril_stats_t;
+
+/* Create a context on the caller's HIP stream (hipStream_t, NULL = default stream).
+ * Validates p on the host before any device call: TRIL_E_INVAL for NULL ctx/p,
+ * non-finite or non-positive dt, n_bins < 0, edges NULL or not strictly increasing,
+ * negative cand_cap or an unsupported block size. */
+int tril_create(tril_ctx **ctx, const tril_params *p, void *hip_stream);
+
+/* Build the hierarchy over `target` for step `step` (>= 0): swept boxes over
+ * [step dt, (step+1) dt], Morton keys, radix sort, hierarchy emission, bottom-up
+ * box refit. The target arrays must stay unchanged until the step's tril_collide
+ * has passed on the stream. TRIL_E_INVAL on bad sizes/offsets; device-side data
+ * errors are reported by tril_stats as TRIL_E_DATA. */
+int tril_build(tril_ctx *ctx, const tril_beam *target, int32_t step);
+
+/* Query the last built hierarchy with every photon of `query` at the same step
+ * and append the hits to `out`. `query` must have the same n_inst as the target
+ * (instance m of the query meets instance m of the target). TRIL_E_STATE if no
+ * hierarchy was built or the step differs from the build's step. */
+int tril_collide(tril_ctx *ctx, const tril_beam *query, int32_t step, tril_pairs *out);
+
+/* Build + collide for steps k0 .. k0+n_steps-1 in one call. The step loop is
+ * captured once in a HIP graph and replayed, the step index living in device
+ * memory; equivalent to calling tril_build/tril_collide per step. */
+int tril_run(tril_ctx *ctx, const tril_beam *target, const tril_beam *query,
+             int32_t k0, int32_t n_steps, tril_pairs *out);
+
+/* Synchronise the stream, then finish the run held in `pairs`:
+ *   * if *count > cap: return TRIL_E_OVERFLOW, leave the buffers untouched and
+ *     report the required capacity in out->n_hits;
+ *   * otherwise rewrite pairs->i/j/step in place as the unique pairs in ascending
+ *     (i, j) order with their first step, set *count to the number of unique
+ *     pairs, and fill `out` (yield, spectrum, step counts, counters).
+ * Counters accumulate over builds/collides since create or tril_reset_counters.
+ * Also returns TRIL_E_DATA / TRIL_E_OVERFLOW (candidates) / TRIL_E_INTERNAL for
+ * errors flagged on the device during the run. `pairs` may be NULL to read the
+ * counters only. */
+int tril_stats(tril_ctx *ctx, tril_pairs *pairs, tril_stats_t *out);
+
+/* Zero the accumulated counters and device error flags (asynchronous). */
+int tril_reset_counters(tril_ctx *ctx);
+
+void tril_destroy(tril_ctx *ctx);
+const char *tril_strerror(int code);
+/* Text of the last HIP error this thread saw inside the library ("" if none). */
+const char *tril_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRIL_H */

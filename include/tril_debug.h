@@ -1,0 +1,59 @@
+/*
+ * tril_debug.h -- inspection entry points of libtril for tests and tools.
+ *
+ * Applications do not need these. They expose single stages of the pipeline
+ * (radix sort, Morton keys, the FP64 pair evaluation of the narrow phase) and
+ * copies of a context's internal state (hierarchy nodes, swept boxes, the
+ * candidate pairs of the last step) so each stage can be checked on its own.
+ * Same conventions as tril.h: device pointers unless marked host, asynchronous
+ * on the given stream unless stated, TRIL_OK or a negative TRIL_E_* code.
+ */
+#ifndef TRIL_DEBUG_H
+#define TRIL_DEBUG_H
+
+#include <stdint.h>
+
+#include "tril.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Stable sort of (keys, vals) by the low key_bits bits of the keys, in place.
+ * n in [0, 2^30); key_bits in [1, 32] resp. [1, 64]. Synchronises the stream. */
+int tril_dbg_sort_u32(uint32_t *keys, uint32_t *vals, int64_t n, int key_bits, void *stream);
+int tril_dbg_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits, void *stream);
+
+/* Morton keys of box centroids. boxes: device, n x 8 floats laid out as
+ * (lox, loy, loz, tag, hix, hiy, hiz, pad); bounds: host, 6 floats (min xyz, max xyz)
+ * of the quantisation box; keys: device, n. Each axis maps [min, max] to 0..1023,
+ * clamped, then bits interleave as x2 y1 z0 per level (x most significant). */
+int tril_dbg_morton(const float *boxes, int64_t n, const float *bounds, uint32_t *keys,
+                    void *stream);
+
+/* FP64 evaluation of the narrow-phase quantities for n photon pairs.
+ * in: device, n x 18 doubles per row:
+ *   E_i px_i py_i pz_i x_i y_i z_i w_i  E_j px_j py_j pz_j x_j y_j z_j w_j  t  dt
+ * out: device, n x 4 doubles per row: s, sigma(s) [um^2], d^2 (smallest squared
+ * distance over [t, t + dt]) and r^2 = sqrt(w_i w_j) sigma / pi. */
+int tril_dbg_pair_eval(int64_t n, const double *in, double *out, void *stream);
+
+/* Copy the last built hierarchy to host memory (synchronises the context stream).
+ * nodes: host, cap_nodes x 8 words (lox loy loz link hix hiy hiz rope as float/int32);
+ * *n_nodes receives 2n-1 (0 for an empty beam); roots/stops: host, n_inst each,
+ * or NULL. TRIL_E_OVERFLOW if cap_nodes < 2n-1. */
+int tril_dbg_tree(tril_ctx *ctx, void *nodes, int64_t cap_nodes, int64_t *n_nodes,
+                  int32_t *roots, int32_t *stops);
+
+/* Copy the swept boxes of the last target (which = 0) or query (which = 1) beam to
+ * host memory as n x 8 words (lox loy loz tag hix hiy hiz instance). */
+int tril_dbg_boxes(tril_ctx *ctx, int which, void *boxes, int64_t cap, int64_t *n);
+
+/* Copy the candidate pairs of the last tril_collide to host memory. *count gets the
+ * number found (may exceed cap; only min(count, cap) are written). */
+int tril_dbg_candidates(tril_ctx *ctx, int32_t *ci, int32_t *cj, int64_t cap, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRIL_DEBUG_H */

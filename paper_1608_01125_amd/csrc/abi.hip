@@ -1,0 +1,880 @@
+// C ABI of libtril: argument checks, context and scratch ownership, and the
+// per-step order of the kernels (build: boxes -> Morton -> sort -> hierarchy
+// -> refit; collide: query boxes -> query order -> traversal -> narrow phase).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tril_debug.h"
+#include "tril_internal.h"
+
+using namespace tril;
+
+namespace {
+
+thread_local std::string g_last_hip;
+
+int hip_fail(hipError_t e) {
+    g_last_hip = hipGetErrorString(e);
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? TRIL_E_NOMEM : TRIL_E_HIP;
+}
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return hip_fail(e_);  \
+    } while (0)
+
+#define CHK(x)                     \
+    do {                           \
+        int r_ = (x);              \
+        if (r_ != TRIL_OK) return r_; \
+    } while (0)
+
+template <typename T>
+int dev_alloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_fail(e);
+    }
+    return TRIL_OK;
+}
+
+template <typename T>
+void dev_free(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+int bits_for(uint64_t v) {  // smallest b with v < 2^b (v >= 1 -> >= 1)
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+}
+
+// Upper bound of the bits in an instance index: keys are (inst << 30) | morton.
+int inst_key_bits(int32_t n_inst) { return 30 + bits_for((uint64_t)(n_inst > 1 ? n_inst - 1 : 0)); }
+
+constexpr int64_t kMaxN = (int64_t)1 << 30;  // node ids 2n-1 fit int32, sort counts fit 30 bits
+
+}  // namespace
+
+struct tril_ctx {
+    hipStream_t st = nullptr;       // caller stream
+    hipStream_t gst = nullptr;      // internal stream for graph replay (non-blocking)
+    hipEvent_t ev_join_a = nullptr, ev_join_b = nullptr;
+    double dt = 0.0;
+    uint32_t flags = 0;
+    int32_t n_bins = 0;
+    double *d_edges = nullptr;
+    int64_t cand_cap_param = 0;
+    int block = 256;
+    double sigma_up = 0.0;
+    DevCounters *d_cnt = nullptr;
+    DevCounters *h_cnt = nullptr;   // pinned host mirror
+
+    // target (hierarchy) state
+    int64_t t_cap = 0;
+    int32_t t_inst_cap = 0;
+    int64_t nt = 0;
+    int32_t t_inst = 0;
+    bool built = false;
+    int32_t built_step = -1;
+    BeamDev tgt{};
+    int64_t *d_t_off = nullptr;
+    std::vector<int64_t> h_t_off;
+    PBox *t_box = nullptr;
+    uint32_t *t_k32a = nullptr, *t_k32b = nullptr;
+    unsigned long long *t_k64a = nullptr, *t_k64b = nullptr;
+    uint32_t *t_va = nullptr, *t_vb = nullptr;
+    int32_t *left = nullptr, *right = nullptr, *parent = nullptr, *range_hi = nullptr;
+    int32_t *split_right = nullptr, *nflags = nullptr;
+    Node *nodes = nullptr;
+    uint32_t *t_bounds = nullptr;
+    unsigned long long *t_emax = nullptr, *t_wmax = nullptr;
+    int32_t *inst_root = nullptr, *inst_stop = nullptr;
+
+    // query state
+    int64_t q_cap = 0;
+    int32_t q_inst_cap = 0;
+    int64_t *d_q_off = nullptr;
+    std::vector<int64_t> h_q_off;
+    PBox *q_box = nullptr;
+    uint32_t *q_k32a = nullptr, *q_k32b = nullptr;
+    unsigned long long *q_k64a = nullptr, *q_k64b = nullptr;
+    uint32_t *q_va = nullptr, *q_vb = nullptr;
+    uint32_t *q_bounds = nullptr;
+    const uint32_t *q_order = nullptr;     // sorted query rows (points into q_va or q_vb)
+    const void *q_order_key = nullptr;     // beam the stored order belongs to
+    int64_t q_order_n = -1;
+
+    // candidates of one step
+    int64_t cand_cap = 0;
+    int32_t *cand_i = nullptr, *cand_j = nullptr;
+
+    SortScratch ss;
+    StatsScratch sst;
+    int32_t max_step = -1;
+
+    // timing (TRIL_TIMING)
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::array<int, 2>> ev_build, ev_prep, ev_trav, ev_narrow;
+    size_t ev_next = 0;
+
+    // captured step graph
+    hipGraphExec_t gexec = nullptr;
+    std::vector<const void *> gkey;
+    uint64_t alloc_gen = 0;         // bumped on every (re)allocation of scratch
+
+    BeamDev last_q{};               // query beam of the last collide (for yield/spectrum)
+    int64_t max_nq = 0;
+};
+
+namespace {
+
+int ensure_sort_scratch(tril_ctx *c, int64_t n) {
+    if (n <= c->ss.cap_n) return TRIL_OK;
+    ++c->alloc_gen;
+    dev_free(c->ss.hist);
+    dev_free(c->ss.tile_ctr);
+    dev_free(c->ss.status);
+    c->ss.cap_n = 0;
+    CHK(dev_alloc(&c->ss.hist, 8 * 256));
+    CHK(dev_alloc(&c->ss.tile_ctr, 8));
+    CHK(dev_alloc(&c->ss.status, sort_status_words(n, 8)));
+    c->ss.cap_n = n;
+    c->ss.cap_passes = 8;
+    return TRIL_OK;
+}
+
+void free_target(tril_ctx *c) {
+    dev_free(c->t_box); dev_free(c->t_k32a); dev_free(c->t_k32b); dev_free(c->t_k64a);
+    dev_free(c->t_k64b); dev_free(c->t_va); dev_free(c->t_vb); dev_free(c->left);
+    dev_free(c->right); dev_free(c->parent); dev_free(c->range_hi); dev_free(c->split_right);
+    dev_free(c->nflags); dev_free(c->nodes);
+    c->t_cap = 0;
+}
+
+int ensure_target(tril_ctx *c, int64_t n, int32_t n_inst) {
+    if (n > c->t_cap) {
+        ++c->alloc_gen;
+        free_target(c);
+        const int64_t m = std::max<int64_t>(n, 1);
+        CHK(dev_alloc(&c->t_box, m));
+        CHK(dev_alloc(&c->t_k32a, m)); CHK(dev_alloc(&c->t_k32b, m));
+        CHK(dev_alloc(&c->t_k64a, m)); CHK(dev_alloc(&c->t_k64b, m));
+        CHK(dev_alloc(&c->t_va, m)); CHK(dev_alloc(&c->t_vb, m));
+        CHK(dev_alloc(&c->left, m)); CHK(dev_alloc(&c->right, m));
+        CHK(dev_alloc(&c->parent, 2 * m)); CHK(dev_alloc(&c->range_hi, m));
+        CHK(dev_alloc(&c->split_right, m)); CHK(dev_alloc(&c->nflags, m));
+        CHK(dev_alloc(&c->nodes, 2 * m));
+        c->t_cap = m;
+    }
+    if (n_inst > c->t_inst_cap) {
+        ++c->alloc_gen;
+        dev_free(c->d_t_off); dev_free(c->t_bounds); dev_free(c->t_emax); dev_free(c->t_wmax);
+        dev_free(c->inst_root); dev_free(c->inst_stop);
+        c->t_inst_cap = 0;
+        CHK(dev_alloc(&c->d_t_off, (size_t)n_inst + 1));
+        CHK(dev_alloc(&c->t_bounds, 6 * (size_t)n_inst));
+        CHK(dev_alloc(&c->t_emax, (size_t)n_inst));
+        CHK(dev_alloc(&c->t_wmax, (size_t)n_inst));
+        CHK(dev_alloc(&c->inst_root, (size_t)n_inst));
+        CHK(dev_alloc(&c->inst_stop, (size_t)n_inst));
+        c->t_inst_cap = n_inst;
+        c->h_t_off.clear();
+    }
+    return ensure_sort_scratch(c, n);
+}
+
+int ensure_query(tril_ctx *c, int64_t n, int32_t n_inst) {
+    if (n > c->q_cap) {
+        ++c->alloc_gen;
+        dev_free(c->q_box); dev_free(c->q_k32a); dev_free(c->q_k32b); dev_free(c->q_k64a);
+        dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
+        c->q_cap = 0;
+        c->q_order = nullptr;
+        c->q_order_key = nullptr;
+        const int64_t m = std::max<int64_t>(n, 1);
+        CHK(dev_alloc(&c->q_box, m));
+        CHK(dev_alloc(&c->q_k32a, m)); CHK(dev_alloc(&c->q_k32b, m));
+        CHK(dev_alloc(&c->q_k64a, m)); CHK(dev_alloc(&c->q_k64b, m));
+        CHK(dev_alloc(&c->q_va, m)); CHK(dev_alloc(&c->q_vb, m));
+        c->q_cap = m;
+    }
+    if (n_inst > c->q_inst_cap) {
+        ++c->alloc_gen;
+        dev_free(c->d_q_off); dev_free(c->q_bounds);
+        c->q_inst_cap = 0;
+        CHK(dev_alloc(&c->d_q_off, (size_t)n_inst + 1));
+        CHK(dev_alloc(&c->q_bounds, 6 * (size_t)n_inst));
+        c->q_inst_cap = n_inst;
+        c->h_q_off.clear();
+    }
+    int64_t cap = c->cand_cap_param > 0 ? c->cand_cap_param
+                                        : std::max<int64_t>((int64_t)1 << 22, 4 * n);
+    if (cap > c->cand_cap) {
+        ++c->alloc_gen;
+        dev_free(c->cand_i); dev_free(c->cand_j);
+        c->cand_cap = 0;
+        CHK(dev_alloc(&c->cand_i, cap));
+        CHK(dev_alloc(&c->cand_j, cap));
+        c->cand_cap = cap;
+    }
+    return ensure_sort_scratch(c, n);
+}
+
+int check_beam(const tril_beam *b) {
+    if (!b) return TRIL_E_INVAL;
+    if (b->n < 0 || b->n >= kMaxN) return TRIL_E_INVAL;
+    if (b->n_inst < 1) return TRIL_E_INVAL;
+    if (b->n > 0 && (!b->x || !b->y || !b->z || !b->px || !b->py || !b->pz || !b->E || !b->w))
+        return TRIL_E_INVAL;
+    if (b->n_inst > 1) {
+        if (!b->inst_off) return TRIL_E_INVAL;
+        if (b->n_inst > (1 << 24)) return TRIL_E_INVAL;
+        if (b->inst_off[0] != 0 || b->inst_off[b->n_inst] != b->n) return TRIL_E_INVAL;
+        for (int32_t m = 0; m < b->n_inst; ++m)
+            if (b->inst_off[m + 1] < b->inst_off[m]) return TRIL_E_INVAL;
+    } else if (b->inst_off && (b->inst_off[0] != 0 || b->inst_off[1] != b->n)) {
+        return TRIL_E_INVAL;
+    }
+    return TRIL_OK;
+}
+
+int check_pairs(const tril_pairs *p) {
+    if (!p || p->cap < 0 || !p->count) return TRIL_E_INVAL;
+    if (p->cap > 0 && (!p->i || !p->j || !p->step)) return TRIL_E_INVAL;
+    return TRIL_OK;
+}
+
+// Copy instance offsets to the device when they changed (synchronous copy from host memory).
+int upload_offsets(tril_ctx *c, const tril_beam *b, int64_t *d_off, std::vector<int64_t> &cache) {
+    if (b->n_inst <= 1) return TRIL_OK;
+    std::vector<int64_t> h(b->inst_off, b->inst_off + b->n_inst + 1);
+    if (h == cache) return TRIL_OK;
+    HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(hipMemcpy(d_off, h.data(), h.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    cache = std::move(h);
+    return TRIL_OK;
+}
+
+BeamDev view(const tril_beam *b, const int64_t *d_off) {
+    BeamDev v;
+    v.n = b->n;
+    v.x = b->x; v.y = b->y; v.z = b->z;
+    v.px = b->px; v.py = b->py; v.pz = b->pz;
+    v.E = b->E; v.w = b->w;
+    v.n_inst = b->n_inst;
+    v.inst_off = b->n_inst > 1 ? d_off : nullptr;
+    return v;
+}
+
+int timing_pair(tril_ctx *c, hipStream_t st, std::vector<std::array<int, 2>> &dst, bool begin) {
+    if (!(c->flags & TRIL_TIMING)) return TRIL_OK;
+    if (begin) {
+        if (c->ev_next + 2 > c->ev_pool.size()) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e));
+                c->ev_pool.push_back(e);
+            }
+        }
+        dst.push_back({(int)c->ev_next, (int)c->ev_next + 1});
+        c->ev_next += 2;
+        HIPCHK(hipEventRecord(c->ev_pool[dst.back()[0]], st));
+    } else {
+        HIPCHK(hipEventRecord(c->ev_pool[dst.back()[1]], st));
+    }
+    return TRIL_OK;
+}
+
+// Kernels of one build on stream st (target view already set in c->tgt).
+int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
+    const int64_t n = c->nt;
+    if (timed) CHK(timing_pair(c, st, c->ev_build, true));
+    launch_begin_step(c->d_cnt, 0, st);
+    launch_clear_inst(c->t_bounds, c->t_emax, c->t_wmax, c->t_inst, st);
+    launch_boxes(c->tgt, false, c->dt, c->sigma_up, nullptr, nullptr, c->t_box, c->t_bounds,
+                 c->t_emax, c->t_wmax, c->d_cnt, st);
+    const uint32_t *rows = nullptr;
+    if (c->t_inst == 1) {
+        launch_morton_u32(c->t_box, n, c->t_bounds, c->t_k32a, c->t_va, st);
+        const bool alt = radix_sort_u32(c->t_k32a, c->t_va, c->t_k32b, c->t_vb, n, 30, c->ss,
+                                        &c->d_cnt->err, st);
+        const uint32_t *keys = alt ? c->t_k32b : c->t_k32a;
+        rows = alt ? c->t_vb : c->t_va;
+        launch_karras_u32(keys, n, c->left, c->right, c->parent, c->range_hi, c->split_right,
+                          c->nflags, st);
+    } else {
+        launch_morton_u64(c->t_box, n, c->t_bounds, c->t_k64a, c->t_va, st);
+        const bool alt = radix_sort_u64(c->t_k64a, c->t_va, c->t_k64b, c->t_vb, n,
+                                        inst_key_bits(c->t_inst), c->ss, &c->d_cnt->err, st);
+        const unsigned long long *keys = alt ? c->t_k64b : c->t_k64a;
+        rows = alt ? c->t_vb : c->t_va;
+        launch_karras_u64(keys, n, c->left, c->right, c->parent, c->range_hi, c->split_right,
+                          c->nflags, c->inst_root, st);
+    }
+    launch_inst_roots(c->d_t_off, c->t_inst, n, c->t_inst == 1, c->split_right, c->inst_root,
+                      c->inst_stop, st);
+    launch_refit(c->t_box, rows, n, c->left, c->right, c->parent, c->range_hi, c->split_right,
+                 c->nflags, c->nodes, &c->d_cnt->err, st);
+    if (timed) CHK(timing_pair(c, st, c->ev_build, false));
+    HIPCHK(hipGetLastError());
+    return TRIL_OK;
+}
+
+int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStream_t st,
+                    bool timed, bool sort_queries) {
+    const int64_t n = q.n;
+    launch_begin_step(c->d_cnt, 1, st);
+    if (timed) CHK(timing_pair(c, st, c->ev_prep, true));
+    launch_clear_inst(c->q_bounds, nullptr, nullptr, q.n_inst, st);
+    launch_boxes(q, true, c->dt, c->sigma_up, c->t_emax, c->t_wmax, c->q_box, c->q_bounds, nullptr,
+                 nullptr, c->d_cnt, st);
+    if (sort_queries && n > 0) {
+        if (q.n_inst == 1) {
+            launch_morton_u32(c->q_box, n, c->q_bounds, c->q_k32a, c->q_va, st);
+            const bool alt = radix_sort_u32(c->q_k32a, c->q_va, c->q_k32b, c->q_vb, n, 30, c->ss,
+                                            &c->d_cnt->err, st);
+            c->q_order = (n <= 1) ? c->q_va : (alt ? c->q_vb : c->q_va);
+        } else {
+            launch_morton_u64(c->q_box, n, c->q_bounds, c->q_k64a, c->q_va, st);
+            const bool alt = radix_sort_u64(c->q_k64a, c->q_va, c->q_k64b, c->q_vb, n,
+                                            inst_key_bits(q.n_inst), c->ss, &c->d_cnt->err, st);
+            c->q_order = (n <= 1) ? c->q_va : (alt ? c->q_vb : c->q_va);
+        }
+    }
+    if (timed) CHK(timing_pair(c, st, c->ev_prep, false));
+    if (timed) CHK(timing_pair(c, st, c->ev_trav, true));
+    launch_traverse(c->nodes, c->nt, c->q_box, c->q_order, n, c->inst_root, c->inst_stop,
+                    c->cand_i, c->cand_j, c->cand_cap, c->d_cnt, c->block, st);
+    if (timed) CHK(timing_pair(c, st, c->ev_trav, false));
+    if (timed) CHK(timing_pair(c, st, c->ev_narrow, true));
+    launch_narrow(q, c->tgt, c->dt, c->sigma_up, c->cand_i, c->cand_j, c->cand_cap, out, c->d_cnt,
+                  st);
+    if (timed) CHK(timing_pair(c, st, c->ev_narrow, false));
+    HIPCHK(hipGetLastError());
+    return TRIL_OK;
+}
+
+bool need_query_sort(tril_ctx *c, const tril_beam *q) {
+    if (!(c->flags & TRIL_SORT_QUERIES_ONCE)) return true;
+    return !(c->q_order && c->q_order_key == (const void *)q->x && c->q_order_n == q->n);
+}
+
+void note_query_sorted(tril_ctx *c, const tril_beam *q) {
+    c->q_order_key = (const void *)q->x;
+    c->q_order_n = q->n;
+}
+
+int ensure_stats(tril_ctx *c, int64_t n_hits, int32_t n_steps) {
+    StatsScratch &s = c->sst;
+    if (n_hits > s.cap) {
+        dev_free(s.keys); dev_free(s.keys_alt); dev_free(s.vals); dev_free(s.vals_alt);
+        dev_free(s.flags); dev_free(s.pos); dev_free(s.block_sums);
+        dev_free(s.ti); dev_free(s.tj); dev_free(s.tk);
+        s.cap = 0;
+        const int64_t m = std::max<int64_t>(n_hits, 1024);
+        CHK(dev_alloc(&s.keys, m)); CHK(dev_alloc(&s.keys_alt, m));
+        CHK(dev_alloc(&s.vals, m)); CHK(dev_alloc(&s.vals_alt, m));
+        CHK(dev_alloc(&s.flags, m)); CHK(dev_alloc(&s.pos, m));
+        CHK(dev_alloc(&s.block_sums, (size_t)stats_block_sums_needed(m)));
+        CHK(dev_alloc(&s.ti, m)); CHK(dev_alloc(&s.tj, m)); CHK(dev_alloc(&s.tk, m));
+        s.cap = m;
+    }
+    if (!s.acc) {
+        CHK(dev_alloc(&s.acc, (size_t)c->n_bins + 1));
+        CHK(dev_alloc(&s.ucount, 1));
+    }
+    if (n_steps > s.cap_steps) {
+        dev_free(s.step_counts);
+        s.cap_steps = 0;
+        CHK(dev_alloc(&s.step_counts, (size_t)n_steps));
+        s.cap_steps = n_steps;
+    }
+    return ensure_sort_scratch(c, n_hits);
+}
+
+double sum_events(tril_ctx *c, const std::vector<std::array<int, 2>> &v) {
+    double tot = 0.0;
+    for (const auto &p : v) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev_pool[p[0]], c->ev_pool[p[1]]) == hipSuccess) tot += ms;
+    }
+    return tot;
+}
+
+}  // namespace
+
+namespace tril {
+
+// Breit-Wheeler cross-section on the host (same algebraic form as the device),
+// used only for the upper bound that pads query boxes.
+double host_sigma(double s) {
+    if (!(s > 1.0)) return 0.0;
+    const double k_sig = (0.5 * M_PI) * (kRe * kRe);
+    const double b2 = (s - 1.0) / s;
+    const double b = std::sqrt(b2);
+    const double L = 2.0 * std::log1p(b) + std::log(s);
+    return (k_sig / s) * ((3.0 - b2 * b2) * L - (2.0 * b) * (2.0 - b2));
+}
+
+// Maximum over s of the cross-section: it rises from zero at threshold to one
+// maximum near s = 2 and falls as ln(s)/s; golden-section search on [1, 10]
+// plus a scan of the neighbourhood.
+double host_sigma_max() {
+    double a = 1.0, b = 10.0;
+    const double g = 0.6180339887498949;
+    double x1 = b - g * (b - a), x2 = a + g * (b - a);
+    for (int it = 0; it < 200; ++it) {
+        if (host_sigma(x1) > host_sigma(x2)) b = x2; else a = x1;
+        x1 = b - g * (b - a);
+        x2 = a + g * (b - a);
+    }
+    double m = host_sigma(0.5 * (a + b));
+    for (int k = -200; k <= 200; ++k) m = std::max(m, host_sigma(0.5 * (a + b) * (1.0 + 1e-4 * k)));
+    return m;
+}
+
+}  // namespace tril
+
+// ------------------------------------------------------------------------ ABI
+
+extern "C" {
+
+const char *tril_strerror(int code) {
+    switch (code) {
+    case TRIL_OK: return "ok";
+    case TRIL_E_INVAL: return "invalid argument";
+    case TRIL_E_NOMEM: return "device out of memory";
+    case TRIL_E_OVERFLOW: return "buffer overflow (pairs or candidates)";
+    case TRIL_E_HIP: return "HIP runtime error";
+    case TRIL_E_NOTIMPL: return "not implemented";
+    case TRIL_E_STATE: return "call order or instance mismatch";
+    case TRIL_E_DATA: return "invalid photon data (non-finite, E <= 0 or w < 0)";
+    case TRIL_E_INTERNAL: return "device wait bound exceeded";
+    default: return "unknown error";
+    }
+}
+
+const char *tril_last_hip_error(void) { return g_last_hip.c_str(); }
+
+int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
+    if (!out || !p) return TRIL_E_INVAL;
+    *out = nullptr;
+    if (!std::isfinite(p->dt) || !(p->dt > 0.0)) return TRIL_E_INVAL;
+    if (p->n_bins < 0 || p->cand_cap < 0) return TRIL_E_INVAL;
+    if (p->flags & ~(TRIL_TIMING | TRIL_SORT_QUERIES_ONCE)) return TRIL_E_NOTIMPL;
+    if (p->n_bins > 0) {
+        if (!p->bin_edges) return TRIL_E_INVAL;
+        for (int32_t b = 0; b <= p->n_bins; ++b)
+            if (!std::isfinite(p->bin_edges[b])) return TRIL_E_INVAL;
+        for (int32_t b = 0; b < p->n_bins; ++b)
+            if (!(p->bin_edges[b + 1] > p->bin_edges[b])) return TRIL_E_INVAL;
+    }
+    const int blk = p->block_traverse == 0 ? 256 : p->block_traverse;
+    if (blk != 64 && blk != 128 && blk != 256 && blk != 512) return TRIL_E_INVAL;
+
+    tril_ctx *c = new tril_ctx();
+    c->st = reinterpret_cast<hipStream_t>(stream);
+    c->dt = p->dt;
+    c->flags = p->flags;
+    c->n_bins = p->n_bins;
+    c->cand_cap_param = p->cand_cap;
+    c->block = blk;
+    c->sigma_up = host_sigma_max() * (1.0 + 1e-6);
+    int r = TRIL_OK;
+    auto fail = [&](int code) {
+        tril_destroy(c);
+        return code;
+    };
+    if ((r = dev_alloc(&c->d_cnt, 1)) != TRIL_OK) return fail(r);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&c->h_cnt), sizeof(DevCounters));
+    if (e != hipSuccess) return fail(hip_fail(e));
+    std::memset(c->h_cnt, 0, sizeof(DevCounters));
+    e = hipMemcpy(c->d_cnt, c->h_cnt, sizeof(DevCounters), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(hip_fail(e));
+    if (c->n_bins > 0) {
+        if ((r = dev_alloc(&c->d_edges, (size_t)c->n_bins + 1)) != TRIL_OK) return fail(r);
+        e = hipMemcpy(c->d_edges, p->bin_edges, sizeof(double) * (c->n_bins + 1),
+                      hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(hip_fail(e));
+    }
+    e = hipStreamCreateWithFlags(&c->gst, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(hip_fail(e));
+    if ((e = hipEventCreateWithFlags(&c->ev_join_a, hipEventDisableTiming)) != hipSuccess)
+        return fail(hip_fail(e));
+    if ((e = hipEventCreateWithFlags(&c->ev_join_b, hipEventDisableTiming)) != hipSuccess)
+        return fail(hip_fail(e));
+    *out = c;
+    return TRIL_OK;
+}
+
+int tril_build(tril_ctx *c, const tril_beam *b, int32_t step) {
+    if (!c || step < 0) return TRIL_E_INVAL;
+    CHK(check_beam(b));
+    CHK(ensure_target(c, b->n, b->n_inst));
+    CHK(upload_offsets(c, b, c->d_t_off, c->h_t_off));
+    c->nt = b->n;
+    c->t_inst = b->n_inst;
+    c->tgt = view(b, c->d_t_off);
+    launch_set_step(c->d_cnt, step, c->st);
+    CHK(enqueue_build(c, c->st, (c->flags & TRIL_TIMING) != 0));
+    c->built = true;
+    c->built_step = step;
+    c->max_step = std::max(c->max_step, step);
+    return TRIL_OK;
+}
+
+int tril_collide(tril_ctx *c, const tril_beam *q, int32_t step, tril_pairs *out) {
+    if (!c) return TRIL_E_INVAL;
+    CHK(check_beam(q));
+    CHK(check_pairs(out));
+    if (!c->built || step != c->built_step || q->n_inst != c->t_inst) return TRIL_E_STATE;
+    CHK(ensure_query(c, q->n, q->n_inst));
+    CHK(upload_offsets(c, q, c->d_q_off, c->h_q_off));
+    const BeamDev qv = view(q, c->d_q_off);
+    const bool sort = need_query_sort(c, q);
+    CHK(enqueue_collide(c, qv, *out, c->st, (c->flags & TRIL_TIMING) != 0, sort));
+    if (sort) note_query_sorted(c, q);
+    c->last_q = qv;
+    c->max_nq = std::max(c->max_nq, q->n);
+    return TRIL_OK;
+}
+
+int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, int32_t n_steps,
+             tril_pairs *out) {
+    if (!c || k0 < 0 || n_steps < 0) return TRIL_E_INVAL;
+    CHK(check_beam(t));
+    CHK(check_beam(q));
+    CHK(check_pairs(out));
+    if (q->n_inst != t->n_inst) return TRIL_E_STATE;
+    if (n_steps == 0) return TRIL_OK;
+    if ((int64_t)k0 + n_steps - 1 > INT32_MAX) return TRIL_E_INVAL;
+    CHK(ensure_target(c, t->n, t->n_inst));
+    CHK(ensure_query(c, q->n, q->n_inst));
+    CHK(upload_offsets(c, t, c->d_t_off, c->h_t_off));
+    CHK(upload_offsets(c, q, c->d_q_off, c->h_q_off));
+    c->nt = t->n;
+    c->t_inst = t->n_inst;
+    c->tgt = view(t, c->d_t_off);
+    const BeamDev qv = view(q, c->d_q_off);
+    int32_t k = k0;
+    int32_t left = n_steps;
+    // with a query order kept from the first step, that step runs eagerly first
+    if (need_query_sort(c, q) && (c->flags & TRIL_SORT_QUERIES_ONCE)) {
+        CHK(tril_build(c, t, k));
+        CHK(tril_collide(c, q, k, out));
+        ++k;
+        --left;
+    }
+    if (left > 0) {
+        const bool sort = need_query_sort(c, q);
+        std::vector<const void *> key = {t->x, t->y, t->z, t->px, t->py, t->pz, t->E, t->w,
+                                         q->x, q->y, q->z, q->px, q->py, q->pz, q->E, q->w,
+                                         out->i, out->j, out->step, out->count,
+                                         (const void *)(intptr_t)t->n, (const void *)(intptr_t)q->n,
+                                         (const void *)(intptr_t)t->n_inst,
+                                         (const void *)(intptr_t)out->cap,
+                                         (const void *)(intptr_t)sort, c->q_order,
+                                         (const void *)(uintptr_t)c->alloc_gen};
+        if (!c->gexec || key != c->gkey) {
+            if (c->gexec) {
+                (void)hipGraphExecDestroy(c->gexec);
+                c->gexec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
+            int r1 = enqueue_build(c, c->gst, false);
+            int r2 = r1 == TRIL_OK ? enqueue_collide(c, qv, *out, c->gst, false, sort) : r1;
+            launch_advance_step(c->d_cnt, c->gst);
+            hipError_t e = hipStreamEndCapture(c->gst, &g);
+            if (r2 != TRIL_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return r2;
+            }
+            if (e != hipSuccess) return hip_fail(e);
+            e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                c->gexec = nullptr;
+                return hip_fail(e);
+            }
+            c->gkey = key;
+        }
+        launch_set_step(c->d_cnt, k, c->st);
+        HIPCHK(hipEventRecord(c->ev_join_a, c->st));
+        HIPCHK(hipStreamWaitEvent(c->gst, c->ev_join_a, 0));
+        for (int32_t s = 0; s < left; ++s) HIPCHK(hipGraphLaunch(c->gexec, c->gst));
+        HIPCHK(hipEventRecord(c->ev_join_b, c->gst));
+        HIPCHK(hipStreamWaitEvent(c->st, c->ev_join_b, 0));
+        if (sort) note_query_sorted(c, q);
+    }
+    c->built = true;
+    c->built_step = k0 + n_steps - 1;
+    c->max_step = std::max(c->max_step, c->built_step);
+    c->last_q = qv;
+    c->max_nq = std::max(c->max_nq, q->n);
+    return TRIL_OK;
+}
+
+int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
+    if (!c || !out) return TRIL_E_INVAL;
+    if (p) CHK(check_pairs(p));
+    if (out->n_step_counts < 0 || (out->n_step_counts > 0 && !out->step_counts))
+        return TRIL_E_INVAL;
+    HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(hipMemcpy(c->h_cnt, c->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost));
+    const DevCounters h = *c->h_cnt;
+    out->n_candidates = (int64_t)h.cand_total;
+    out->n_node_visits = (int64_t)h.visits;
+    out->n_queries = (int64_t)h.queries;
+    out->n_sigma_evals = (int64_t)h.sigma_evals;
+    out->n_builds = (int64_t)h.builds;
+    out->n_collides = (int64_t)h.collides;
+    out->ms_build = sum_events(c, c->ev_build);
+    out->ms_query_prep = sum_events(c, c->ev_prep);
+    out->ms_traverse = sum_events(c, c->ev_trav);
+    out->ms_narrow = sum_events(c, c->ev_narrow);
+    out->n_timed_steps = (int64_t)c->ev_trav.size();
+    out->n_pairs = 0;
+    out->n_hits = 0;
+    out->yield = 0.0;
+    if (h.err & kErrData) return TRIL_E_DATA;
+    if (h.err & kErrSpin) return TRIL_E_INTERNAL;
+    if (h.err & kErrCandOverflow) return TRIL_E_OVERFLOW;
+    if (!p) return TRIL_OK;
+    int64_t n_hits = 0;
+    HIPCHK(hipMemcpy(&n_hits, p->count, sizeof(int64_t), hipMemcpyDeviceToHost));
+    out->n_hits = n_hits;
+    if (n_hits > p->cap || (h.err & kErrPairOverflow)) return TRIL_E_OVERFLOW;
+    if (n_hits > 0 && (!c->built || c->last_q.n <= 0)) return TRIL_E_STATE;
+    const int step_bits = std::max(1, bits_for((uint64_t)std::max(c->max_step, 0)));
+    const int pair_bits = bits_for((uint64_t)std::max<int64_t>(c->max_nq, 1) *
+                                   (uint64_t)std::max<int64_t>(c->nt, 1));
+    if (pair_bits + step_bits > 64) return TRIL_E_NOTIMPL;
+    const int32_t nsc = out->step_counts ? out->n_step_counts : 0;
+    CHK(ensure_stats(c, n_hits, std::max(nsc, 1)));
+    run_union_stats(*p, n_hits, std::max<int64_t>(c->nt, 1), step_bits, pair_bits + step_bits,
+                    c->last_q.w, c->tgt.w, c->last_q.E, c->tgt.E, c->d_edges, c->n_bins, nsc,
+                    c->sst, c->ss, &c->d_cnt->err, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    unsigned long long uc = 0;
+    HIPCHK(hipMemcpy(&uc, c->sst.ucount, sizeof(uc), hipMemcpyDeviceToHost));
+    std::vector<double> acc((size_t)c->n_bins + 1, 0.0);
+    HIPCHK(hipMemcpy(acc.data(), c->sst.acc, acc.size() * sizeof(double), hipMemcpyDeviceToHost));
+    out->n_pairs = (int64_t)uc;
+    out->yield = acc[0];
+    if (out->spectrum)
+        for (int32_t b = 0; b < c->n_bins; ++b) out->spectrum[b] = acc[1 + b];
+    if (nsc > 0) {
+        std::vector<unsigned long long> sc((size_t)nsc);
+        HIPCHK(hipMemcpy(sc.data(), c->sst.step_counts, sc.size() * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost));
+        for (int32_t k = 0; k < nsc; ++k) out->step_counts[k] = (int64_t)sc[k];
+    }
+    HIPCHK(hipMemcpy(c->h_cnt, c->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost));
+    if (c->h_cnt->err & kErrSpin) return TRIL_E_INTERNAL;
+    return TRIL_OK;
+}
+
+int tril_reset_counters(tril_ctx *c) {
+    if (!c) return TRIL_E_INVAL;
+    HIPCHK(hipStreamSynchronize(c->st));
+    std::memset(c->h_cnt, 0, sizeof(DevCounters));
+    HIPCHK(hipMemcpy(c->d_cnt, c->h_cnt, sizeof(DevCounters), hipMemcpyHostToDevice));
+    c->ev_build.clear(); c->ev_prep.clear(); c->ev_trav.clear(); c->ev_narrow.clear();
+    c->ev_next = 0;
+    c->max_step = c->built ? c->built_step : -1;
+    return TRIL_OK;
+}
+
+void tril_destroy(tril_ctx *c) {
+    if (!c) return;
+    if (c->st) (void)hipStreamSynchronize(c->st);
+    if (c->gst) (void)hipStreamSynchronize(c->gst);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    free_target(c);
+    dev_free(c->d_t_off); dev_free(c->t_bounds); dev_free(c->t_emax); dev_free(c->t_wmax);
+    dev_free(c->inst_root); dev_free(c->inst_stop);
+    dev_free(c->q_box); dev_free(c->q_k32a); dev_free(c->q_k32b); dev_free(c->q_k64a);
+    dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb); dev_free(c->d_q_off);
+    dev_free(c->q_bounds); dev_free(c->cand_i); dev_free(c->cand_j);
+    dev_free(c->ss.hist); dev_free(c->ss.tile_ctr); dev_free(c->ss.status);
+    StatsScratch &s = c->sst;
+    dev_free(s.keys); dev_free(s.keys_alt); dev_free(s.vals); dev_free(s.vals_alt);
+    dev_free(s.flags); dev_free(s.pos); dev_free(s.block_sums); dev_free(s.ti); dev_free(s.tj);
+    dev_free(s.tk); dev_free(s.acc); dev_free(s.ucount); dev_free(s.step_counts);
+    dev_free(c->d_edges);
+    dev_free(c->d_cnt);
+    if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->ev_join_a) (void)hipEventDestroy(c->ev_join_a);
+    if (c->ev_join_b) (void)hipEventDestroy(c->ev_join_b);
+    if (c->gst) (void)hipStreamDestroy(c->gst);
+    delete c;
+}
+
+// ------------------------------------------------------------- inspection ABI
+
+int tril_dbg_sort_u32(uint32_t *keys, uint32_t *vals, int64_t n, int key_bits, void *stream) {
+    if (n < 0 || n >= kMaxN || key_bits < 1 || key_bits > 32) return TRIL_E_INVAL;
+    if (n > 0 && (!keys || !vals)) return TRIL_E_INVAL;
+    if (n <= 1) return TRIL_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    SortScratch ss;
+    uint32_t *ka = nullptr, *va = nullptr;
+    unsigned int *err = nullptr;
+    int r = TRIL_OK;
+    if ((r = dev_alloc(&ss.hist, 8 * 256)) == TRIL_OK && (r = dev_alloc(&ss.tile_ctr, 8)) == TRIL_OK &&
+        (r = dev_alloc(&ss.status, sort_status_words(n, 8))) == TRIL_OK &&
+        (r = dev_alloc(&ka, (size_t)n)) == TRIL_OK && (r = dev_alloc(&va, (size_t)n)) == TRIL_OK &&
+        (r = dev_alloc(&err, 1)) == TRIL_OK) {
+        hipError_t e = hipMemsetAsync(err, 0, sizeof(unsigned int), st);
+        if (e == hipSuccess) {
+            const bool alt = radix_sort_u32(keys, vals, ka, va, n, key_bits, ss, err, st);
+            if (alt) {
+                e = hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+            }
+        }
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        unsigned int h_err = 0;
+        if (e == hipSuccess) e = hipMemcpy(&h_err, err, sizeof(h_err), hipMemcpyDeviceToHost);
+        r = e != hipSuccess ? hip_fail(e) : (h_err ? TRIL_E_INTERNAL : TRIL_OK);
+    }
+    dev_free(ss.hist); dev_free(ss.tile_ctr); dev_free(ss.status);
+    dev_free(ka); dev_free(va); dev_free(err);
+    return r;
+}
+
+int tril_dbg_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits, void *stream) {
+    if (n < 0 || n >= kMaxN || key_bits < 1 || key_bits > 64) return TRIL_E_INVAL;
+    if (n > 0 && (!keys || !vals)) return TRIL_E_INVAL;
+    if (n <= 1) return TRIL_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    SortScratch ss;
+    unsigned long long *ka = nullptr;
+    uint32_t *va = nullptr;
+    unsigned int *err = nullptr;
+    unsigned long long *k = reinterpret_cast<unsigned long long *>(keys);
+    int r = TRIL_OK;
+    if ((r = dev_alloc(&ss.hist, 8 * 256)) == TRIL_OK && (r = dev_alloc(&ss.tile_ctr, 8)) == TRIL_OK &&
+        (r = dev_alloc(&ss.status, sort_status_words(n, 8))) == TRIL_OK &&
+        (r = dev_alloc(&ka, (size_t)n)) == TRIL_OK && (r = dev_alloc(&va, (size_t)n)) == TRIL_OK &&
+        (r = dev_alloc(&err, 1)) == TRIL_OK) {
+        hipError_t e = hipMemsetAsync(err, 0, sizeof(unsigned int), st);
+        if (e == hipSuccess) {
+            const bool alt = radix_sort_u64(k, vals, ka, va, n, key_bits, ss, err, st);
+            if (alt) {
+                e = hipMemcpyAsync(k, ka, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+            }
+        }
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        unsigned int h_err = 0;
+        if (e == hipSuccess) e = hipMemcpy(&h_err, err, sizeof(h_err), hipMemcpyDeviceToHost);
+        r = e != hipSuccess ? hip_fail(e) : (h_err ? TRIL_E_INTERNAL : TRIL_OK);
+    }
+    dev_free(ss.hist); dev_free(ss.tile_ctr); dev_free(ss.status);
+    dev_free(ka); dev_free(va); dev_free(err);
+    return r;
+}
+
+int tril_dbg_morton(const float *boxes, int64_t n, const float *bounds, uint32_t *keys,
+                    void *stream) {
+    if (n < 0 || n >= kMaxN || !bounds) return TRIL_E_INVAL;
+    if (n > 0 && (!boxes || !keys)) return TRIL_E_INVAL;
+    if (n == 0) return TRIL_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    uint32_t hb[6];
+    for (int a = 0; a < 6; ++a) {
+        uint32_t u;
+        std::memcpy(&u, bounds + a, 4);
+        hb[a] = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    }
+    uint32_t *db = nullptr, *dv = nullptr;
+    int r = dev_alloc(&db, 6);
+    if (r == TRIL_OK) r = dev_alloc(&dv, (size_t)n);
+    if (r == TRIL_OK) {
+        hipError_t e = hipMemcpy(db, hb, sizeof(hb), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            launch_morton_u32(reinterpret_cast<const PBox *>(boxes), n, db, keys, dv, st);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) r = hip_fail(e);
+    }
+    dev_free(db);
+    dev_free(dv);
+    return r;
+}
+
+int tril_dbg_pair_eval(int64_t n, const double *in, double *out, void *stream) {
+    if (n < 0 || (n > 0 && (!in || !out))) return TRIL_E_INVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    launch_pair_eval(n, in, out, st);
+    HIPCHK(hipGetLastError());
+    return TRIL_OK;
+}
+
+int tril_dbg_tree(tril_ctx *c, void *nodes, int64_t cap_nodes, int64_t *n_nodes, int32_t *roots,
+                  int32_t *stops) {
+    if (!c || !n_nodes) return TRIL_E_INVAL;
+    if (!c->built) return TRIL_E_STATE;
+    HIPCHK(hipStreamSynchronize(c->st));
+    const int64_t nn = c->nt > 0 ? 2 * c->nt - 1 : 0;
+    *n_nodes = nn;
+    if (nn > cap_nodes) return TRIL_E_OVERFLOW;
+    if (nn > 0) {
+        if (!nodes) return TRIL_E_INVAL;
+        HIPCHK(hipMemcpy(nodes, c->nodes, nn * sizeof(Node), hipMemcpyDeviceToHost));
+    }
+    if (roots) HIPCHK(hipMemcpy(roots, c->inst_root, c->t_inst * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (stops) HIPCHK(hipMemcpy(stops, c->inst_stop, c->t_inst * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return TRIL_OK;
+}
+
+int tril_dbg_boxes(tril_ctx *c, int which, void *boxes, int64_t cap, int64_t *n) {
+    if (!c || !n || (which != 0 && which != 1)) return TRIL_E_INVAL;
+    HIPCHK(hipStreamSynchronize(c->st));
+    const int64_t nn = which == 0 ? c->nt : c->last_q.n;
+    *n = nn;
+    if (nn > cap) return TRIL_E_OVERFLOW;
+    if (nn > 0) {
+        if (!boxes) return TRIL_E_INVAL;
+        HIPCHK(hipMemcpy(boxes, which == 0 ? c->t_box : c->q_box, nn * sizeof(PBox),
+                         hipMemcpyDeviceToHost));
+    }
+    return TRIL_OK;
+}
+
+int tril_dbg_candidates(tril_ctx *c, int32_t *ci, int32_t *cj, int64_t cap, int64_t *count) {
+    if (!c || !count || cap < 0) return TRIL_E_INVAL;
+    HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(hipMemcpy(c->h_cnt, c->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost));
+    const int64_t nc = (int64_t)c->h_cnt->cand_step;
+    *count = nc;
+    const int64_t m = std::min<int64_t>(std::min<int64_t>(nc, cap), c->cand_cap);
+    if (m > 0) {
+        if (!ci || !cj) return TRIL_E_INVAL;
+        HIPCHK(hipMemcpy(ci, c->cand_i, m * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(cj, c->cand_j, m * sizeof(int32_t), hipMemcpyDeviceToHost));
+    }
+    return TRIL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Internal declarations of libtril (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "tril.h"
+
+namespace tril {
+
+constexpr double kMe = 0.51099895000;      // electron rest energy [MeV]
+constexpr double kRe = 2.8179403262e-9;    // classical electron radius [um]
+
+// Device-side error bits (DevCounters::err).
+constexpr uint32_t kErrData = 1u;          // non-finite input, E <= 0 or w < 0
+constexpr uint32_t kErrCandOverflow = 2u;  // broad-phase candidate buffer full
+constexpr uint32_t kErrSpin = 4u;          // a bounded device wait ran out
+constexpr uint32_t kErrPairOverflow = 8u;  // caller pair buffer full
+
+// One hierarchy node, 32 bytes, two per 64-byte half-line.
+// Internal nodes occupy ids [0, n-1), leaves [n-1, 2n-1) in Morton order.
+//   link: internal node -> id of its left child (the right child follows the
+//         left subtree in depth-first order, reached through ropes);
+//         leaf          -> row of the target photon it holds.
+//   rope: id of the next node in depth-first order once this node's subtree is
+//         done (skipped or finished); -1 after the last node.
+struct alignas(16) Node {
+    float lox, loy, loz;
+    int32_t link;
+    float hix, hiy, hiz;
+    int32_t rope;
+};
+static_assert(sizeof(Node) == 32, "node layout");
+
+// Swept, padded box of one photon (FP32, rounded outward), 32 bytes.
+//   tag: instance index of the photon, or -1 when the photon can collide with
+//        nothing (query photons whose best case is below threshold).
+struct alignas(16) PBox {
+    float lox, loy, loz;
+    int32_t tag;
+    float hix, hiy, hiz;
+    int32_t pad;
+};
+static_assert(sizeof(PBox) == 32, "box layout");
+
+// Counters accumulated on the device across steps.
+struct DevCounters {
+    unsigned long long cand_step;      // candidates of the current step (reset per step)
+    unsigned long long cand_total;
+    unsigned long long visits;
+    unsigned long long queries;
+    unsigned long long sigma_evals;
+    unsigned long long builds;
+    unsigned long long collides;
+    unsigned int err;
+    unsigned int step;                 // current step index (device-resident for graphs)
+};
+
+// ---------------------------------------------------------------- radix sort
+struct SortScratch {
+    uint32_t *hist = nullptr;       // passes x 256
+    uint32_t *tile_ctr = nullptr;   // passes
+    uint32_t *status = nullptr;     // passes x tiles x 256
+    int64_t cap_n = 0;
+    int cap_passes = 0;
+};
+int sort_tile_size();
+size_t sort_status_words(int64_t n, int passes);
+// Stable LSD sort of (key, value) on the low key_bits bits. keys/vals hold the input;
+// the result ends in keys/vals or keys_alt/vals_alt; returns true if in *_alt.
+bool radix_sort_u32(uint32_t *keys, uint32_t *vals, uint32_t *keys_alt, uint32_t *vals_alt,
+                    int64_t n, int key_bits, const SortScratch &s, unsigned int *err,
+                    hipStream_t st);
+bool radix_sort_u64(unsigned long long *keys, uint32_t *vals, unsigned long long *keys_alt,
+                    uint32_t *vals_alt, int64_t n, int key_bits, const SortScratch &s,
+                    unsigned int *err, hipStream_t st);
+
+// ------------------------------------------------------------ hierarchy parts
+struct BeamDev {  // device view of a caller beam plus instance data
+    int64_t n;
+    const double *x, *y, *z, *px, *py, *pz, *E, *w;
+    int32_t n_inst;
+    const int64_t *inst_off;   // device copy, n_inst + 1
+};
+
+// Per-instance data of the target (device arrays of n_inst entries unless noted).
+struct InstDev {
+    uint32_t *bounds;                 // 6 per instance: ordered-float min xyz, max xyz
+    unsigned long long *emax_bits;    // max E of the target instance (FP64 bits)
+    unsigned long long *wmax_bits;    // max w of the target instance (FP64 bits)
+    int32_t *root;                    // root node id or -1 (empty instance)
+    int32_t *stop;                    // rope of the root (traversal ends there)
+};
+
+void launch_clear_inst(uint32_t *bounds, unsigned long long *emax, unsigned long long *wmax,
+                       int32_t n_inst, hipStream_t st);
+void launch_set_step(DevCounters *c, int32_t step, hipStream_t st);
+void launch_advance_step(DevCounters *c, hipStream_t st);
+void launch_begin_step(DevCounters *c, int kind, hipStream_t st);
+void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st);
+
+void launch_boxes(const BeamDev &b, bool query, double dt, double sigma_up,
+                  const unsigned long long *t_emax, const unsigned long long *t_wmax,
+                  PBox *out, uint32_t *bounds, unsigned long long *emax, unsigned long long *wmax,
+                  DevCounters *c, hipStream_t st);
+void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint32_t *keys,
+                       uint32_t *vals, hipStream_t st);
+void launch_morton_u64(const PBox *box, int64_t n, const uint32_t *bounds,
+                       unsigned long long *keys, uint32_t *vals, hipStream_t st);
+void launch_karras_u32(const uint32_t *keys, int64_t n, int32_t *left, int32_t *right,
+                       int32_t *parent, int32_t *range_hi, int32_t *split_right, int32_t *flags,
+                       hipStream_t st);
+void launch_karras_u64(const unsigned long long *keys, int64_t n, int32_t *left, int32_t *right,
+                       int32_t *parent, int32_t *range_hi, int32_t *split_right, int32_t *flags,
+                       int32_t *inst_root, hipStream_t st);
+void launch_inst_roots(const int64_t *inst_off, int32_t n_inst, int64_t n, bool single,
+                       const int32_t *split_right, int32_t *inst_root, int32_t *inst_stop,
+                       hipStream_t st);
+void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, const int32_t *left,
+                  const int32_t *right, const int32_t *parent, const int32_t *range_hi,
+                  const int32_t *split_right, int32_t *flags, Node *nodes, unsigned int *err,
+                  hipStream_t st);
+
+void launch_traverse(const Node *nodes, int64_t nt, const PBox *qbox, const uint32_t *qorder,
+                     int64_t nq, const int32_t *inst_root, const int32_t *inst_stop,
+                     int32_t *cand_i, int32_t *cand_j, int64_t cand_cap, DevCounters *c,
+                     int block, hipStream_t st);
+void launch_narrow(const BeamDev &q, const BeamDev &t, double dt, double sigma_up,
+                   const int32_t *cand_i, const int32_t *cand_j, int64_t cand_cap,
+                   const tril_pairs &out, DevCounters *c, hipStream_t st);
+
+void launch_pair_eval(int64_t n, const double *in, double *out, hipStream_t st);
+
+// ------------------------------------------------------------------ run stats
+struct StatsScratch {
+    unsigned long long *keys = nullptr, *keys_alt = nullptr;
+    uint32_t *vals = nullptr, *vals_alt = nullptr;
+    uint32_t *flags = nullptr, *pos = nullptr, *block_sums = nullptr;
+    int32_t *ti = nullptr, *tj = nullptr, *tk = nullptr;
+    double *acc = nullptr;                 // [0] yield, [1..n_bins] spectrum
+    unsigned long long *ucount = nullptr;  // unique pair count
+    unsigned long long *step_counts = nullptr;
+    int64_t cap = 0;
+    int32_t cap_steps = 0;
+};
+int stats_block_sums_needed(int64_t n);
+// Union over steps, sorted ascending (i, j), first step kept; yield, spectrum,
+// per-step counts. Writes the unique pairs back into p.i/j/step.
+void run_union_stats(const tril_pairs &p, int64_t n_hits, int64_t n_target, int step_bits,
+                     int key_bits, const double *w_q, const double *w_t, const double *E_q, const double *E_t,
+                     const double *d_edges, int32_t n_bins, int32_t n_steps_count,
+                     StatsScratch &s, SortScratch &ss, unsigned int *err, hipStream_t st);
+
+// Host-side maximum of the cross-section (same formula as the device).
+double host_sigma(double s);
+double host_sigma_max();
+
+}  // namespace tril

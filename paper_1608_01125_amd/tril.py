@@ -1,0 +1,379 @@
+"""Python binding of libtril (C ABI in include/tril.h and include/tril_debug.h).
+
+Argument marshalling only: every step of the collision path runs in the HIP
+kernels of libtril.so. PyTorch provides device memory and the HIP stream.
+Importing this module without the built library raises immediately; there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtril.so")
+
+TRIL_OK = 0
+TRIL_E_INVAL = -1
+TRIL_E_NOMEM = -2
+TRIL_E_OVERFLOW = -3
+TRIL_E_HIP = -4
+TRIL_E_NOTIMPL = -5
+TRIL_E_STATE = -6
+TRIL_E_DATA = -7
+TRIL_E_INTERNAL = -8
+
+TRIL_TIMING = 0x1
+TRIL_SORT_QUERIES_ONCE = 0x2
+
+FIELDS = ("x", "y", "z", "px", "py", "pz", "E", "w")
+_dp = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+class tril_beam(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64)] + [(f, ctypes.c_void_p) for f in FIELDS] + [
+        ("n_inst", ctypes.c_int32), ("inst_off", _i64p)]
+
+
+class tril_params(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("flags", ctypes.c_uint32), ("n_bins", ctypes.c_int32),
+                ("bin_edges", _dp), ("cand_cap", ctypes.c_int64),
+                ("block_traverse", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class tril_pairs(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_int64), ("i", ctypes.c_void_p), ("j", ctypes.c_void_p),
+                ("step", ctypes.c_void_p), ("count", ctypes.c_void_p)]
+
+
+class tril_stats_t(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("n_hits", ctypes.c_int64),
+                ("n_candidates", ctypes.c_int64), ("n_node_visits", ctypes.c_int64),
+                ("n_queries", ctypes.c_int64), ("n_sigma_evals", ctypes.c_int64),
+                ("n_builds", ctypes.c_int64), ("n_collides", ctypes.c_int64),
+                ("yield_", ctypes.c_double), ("spectrum", _dp), ("step_counts", _i64p),
+                ("n_step_counts", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("ms_build", ctypes.c_double), ("ms_query_prep", ctypes.c_double),
+                ("ms_traverse", ctypes.c_double), ("ms_narrow", ctypes.c_double),
+                ("n_timed_steps", ctypes.c_int64)]
+
+
+EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats",
+           "tril_reset_counters", "tril_destroy", "tril_strerror", "tril_last_hip_error",
+           "tril_dbg_sort_u32", "tril_dbg_sort_u64", "tril_dbg_morton", "tril_dbg_pair_eval",
+           "tril_dbg_tree", "tril_dbg_boxes", "tril_dbg_candidates")
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libtril.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libtril.so not built ({LIB_PATH}); run paper_1608_01125_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.tril_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(tril_params), vp]
+    L.tril_build.argtypes = [vp, ctypes.POINTER(tril_beam), i32]
+    L.tril_collide.argtypes = [vp, ctypes.POINTER(tril_beam), i32, ctypes.POINTER(tril_pairs)]
+    L.tril_run.argtypes = [vp, ctypes.POINTER(tril_beam), ctypes.POINTER(tril_beam), i32, i32,
+                           ctypes.POINTER(tril_pairs)]
+    L.tril_stats.argtypes = [vp, ctypes.POINTER(tril_pairs), ctypes.POINTER(tril_stats_t)]
+    L.tril_reset_counters.argtypes = [vp]
+    L.tril_destroy.argtypes = [vp]
+    L.tril_destroy.restype = None
+    L.tril_strerror.argtypes = [ctypes.c_int]
+    L.tril_strerror.restype = ctypes.c_char_p
+    L.tril_last_hip_error.argtypes = []
+    L.tril_last_hip_error.restype = ctypes.c_char_p
+    L.tril_dbg_sort_u32.argtypes = [vp, vp, i64, ctypes.c_int, vp]
+    L.tril_dbg_sort_u64.argtypes = [vp, vp, i64, ctypes.c_int, vp]
+    L.tril_dbg_morton.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_float), vp, vp]
+    L.tril_dbg_pair_eval.argtypes = [i64, vp, vp, vp]
+    L.tril_dbg_tree.argtypes = [vp, vp, i64, _i64p, _i32p, _i32p]
+    L.tril_dbg_boxes.argtypes = [vp, ctypes.c_int, vp, i64, _i64p]
+    L.tril_dbg_candidates.argtypes = [vp, _i32p, _i32p, i64, _i64p]
+    _lib = L
+    return L
+
+
+class TrilError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        L = lib()
+        msg = L.tril_strerror(code).decode()
+        hip = L.tril_last_hip_error().decode()
+        super().__init__(f"{where}: {msg} ({code})" + (f" [{hip}]" if hip and code == TRIL_E_HIP else ""))
+        self.code = code
+
+
+def _check(code: int, where: str) -> None:
+    if code != TRIL_OK:
+        raise TrilError(code, where)
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ marshalling
+
+
+class Beam:
+    """Device-resident beam (FP64 SoA torch tensors) plus host CSR instance offsets."""
+
+    def __init__(self, arrays: Dict[str, "object"], inst_off: Optional[Sequence[int]] = None,
+                 device: str = "cuda"):
+        import torch
+        self.t = {}
+        for f in FIELDS:
+            a = arrays[f]
+            if isinstance(a, np.ndarray):
+                a = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+            self.t[f] = a.to(device=device, dtype=torch.float64).contiguous()
+        self.n = int(self.t["E"].numel())
+        if inst_off is None:
+            self.off = None
+            self.n_inst = 1
+        else:
+            self.off = np.ascontiguousarray(np.asarray(inst_off, dtype=np.int64))
+            self.n_inst = len(self.off) - 1
+        self._c = tril_beam()
+        self._c.n = self.n
+        for f in FIELDS:
+            setattr(self._c, f, self.t[f].data_ptr() if self.n > 0 else None)
+        self._c.n_inst = self.n_inst
+        self._c.inst_off = (self.off.ctypes.data_as(_i64p) if self.off is not None else None)
+
+    @property
+    def c(self) -> tril_beam:
+        return self._c
+
+
+class Pairs:
+    """Caller-owned device pair buffer (i, j, step) with a device counter."""
+
+    def __init__(self, cap: int, device: str = "cuda"):
+        import torch
+        self.cap = int(cap)
+        self.i = torch.empty(max(self.cap, 1), dtype=torch.int32, device=device)
+        self.j = torch.empty(max(self.cap, 1), dtype=torch.int32, device=device)
+        self.step = torch.empty(max(self.cap, 1), dtype=torch.int32, device=device)
+        self.count = torch.zeros(1, dtype=torch.int64, device=device)
+        self._c = tril_pairs(self.cap, self.i.data_ptr(), self.j.data_ptr(),
+                             self.step.data_ptr(), self.count.data_ptr())
+
+    def reset(self) -> None:
+        self.count.zero_()
+
+    @property
+    def c(self) -> tril_pairs:
+        return self._c
+
+    def numpy(self):
+        n = int(self.count.item())
+        n = min(n, self.cap)
+        return (self.i[:n].cpu().numpy(), self.j[:n].cpu().numpy(), self.step[:n].cpu().numpy())
+
+
+# ------------------------------------------------------- C-named entry points
+
+
+def tril_create(dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
+                cand_cap: int = 0, block_traverse: int = 0, stream=None) -> ctypes.c_void_p:
+    L = lib()
+    p = tril_params()
+    p.dt = float(dt)
+    p.flags = int(flags)
+    keep = None
+    if edges is not None and len(edges) > 1:
+        keep = np.ascontiguousarray(edges, dtype=np.float64)
+        p.n_bins = len(keep) - 1
+        p.bin_edges = keep.ctypes.data_as(_dp)
+    else:
+        p.n_bins = 0
+        p.bin_edges = None
+    p.cand_cap = int(cand_cap)
+    p.block_traverse = int(block_traverse)
+    h = ctypes.c_void_p()
+    _check(L.tril_create(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(_stream(stream))),
+           "tril_create")
+    return h
+
+
+def tril_build(ctx, target: Beam, step: int) -> None:
+    _check(lib().tril_build(ctx, ctypes.byref(target.c), int(step)), "tril_build")
+
+
+def tril_collide(ctx, query: Beam, step: int, pairs: Pairs) -> None:
+    _check(lib().tril_collide(ctx, ctypes.byref(query.c), int(step), ctypes.byref(pairs.c)),
+           "tril_collide")
+
+
+def tril_run(ctx, target: Beam, query: Beam, k0: int, n_steps: int, pairs: Pairs) -> None:
+    _check(lib().tril_run(ctx, ctypes.byref(target.c), ctypes.byref(query.c), int(k0),
+                          int(n_steps), ctypes.byref(pairs.c)), "tril_run")
+
+
+def tril_stats(ctx, pairs: Optional[Pairs], n_bins: int = 0, n_step_counts: int = 0) -> dict:
+    st = tril_stats_t()
+    spec = np.zeros(max(n_bins, 1), dtype=np.float64)
+    sc = np.zeros(max(n_step_counts, 1), dtype=np.int64)
+    st.spectrum = spec.ctypes.data_as(_dp) if n_bins > 0 else None
+    st.step_counts = sc.ctypes.data_as(_i64p) if n_step_counts > 0 else None
+    st.n_step_counts = int(n_step_counts)
+    code = lib().tril_stats(ctx, ctypes.byref(pairs.c) if pairs is not None else None,
+                            ctypes.byref(st))
+    out = {k: getattr(st, k) for k, _ in tril_stats_t._fields_
+           if k not in ("spectrum", "step_counts", "pad0")}
+    out["yield"] = out.pop("yield_")
+    out["spectrum"] = spec[:n_bins].copy()
+    out["step_counts"] = sc[:n_step_counts].copy()
+    out["code"] = code
+    return out
+
+
+def tril_reset_counters(ctx) -> None:
+    _check(lib().tril_reset_counters(ctx), "tril_reset_counters")
+
+
+def tril_destroy(ctx) -> None:
+    if ctx:
+        lib().tril_destroy(ctx)
+
+
+def tril_strerror(code: int) -> str:
+    return lib().tril_strerror(code).decode()
+
+
+# ------------------------------------------------------------ inspection calls
+
+
+def tril_dbg_sort_u32(keys, vals, key_bits: int, stream=None) -> None:
+    _check(lib().tril_dbg_sort_u32(keys.data_ptr(), vals.data_ptr(), keys.numel(), key_bits,
+                                   _stream(stream)), "tril_dbg_sort_u32")
+
+
+def tril_dbg_sort_u64(keys, vals, key_bits: int, stream=None) -> None:
+    _check(lib().tril_dbg_sort_u64(keys.data_ptr(), vals.data_ptr(), keys.numel(), key_bits,
+                                   _stream(stream)), "tril_dbg_sort_u64")
+
+
+def tril_dbg_morton(boxes, bounds: Sequence[float], keys, stream=None) -> None:
+    b = (ctypes.c_float * 6)(*[float(v) for v in bounds])
+    _check(lib().tril_dbg_morton(boxes.data_ptr(), boxes.shape[0], b, keys.data_ptr(),
+                                 _stream(stream)), "tril_dbg_morton")
+
+
+def tril_dbg_pair_eval(inp, out, stream=None) -> None:
+    _check(lib().tril_dbg_pair_eval(inp.shape[0], inp.data_ptr(), out.data_ptr(), _stream(stream)),
+           "tril_dbg_pair_eval")
+
+
+def _h(ctx):
+    return ctx.h if isinstance(ctx, Context) else ctx
+
+
+def tril_dbg_tree(ctx, n_target: int, n_inst: int = 1):
+    ctx = _h(ctx)
+    cap = max(2 * n_target - 1, 1)
+    nodes = np.zeros((cap, 8), dtype=np.float32)
+    nn = ctypes.c_int64(0)
+    roots = np.zeros(max(n_inst, 1), dtype=np.int32)
+    stops = np.zeros(max(n_inst, 1), dtype=np.int32)
+    _check(lib().tril_dbg_tree(ctx, nodes.ctypes.data, cap, ctypes.byref(nn),
+                               roots.ctypes.data_as(_i32p), stops.ctypes.data_as(_i32p)),
+           "tril_dbg_tree")
+    nodes = nodes[: nn.value]
+    ints = nodes.view(np.int32)
+    return {"lo": nodes[:, 0:3].copy(), "hi": nodes[:, 4:7].copy(), "link": ints[:, 3].copy(),
+            "rope": ints[:, 7].copy(), "roots": roots[:n_inst], "stops": stops[:n_inst]}
+
+
+def tril_dbg_boxes(ctx, which: int, n: int):
+    ctx = _h(ctx)
+    boxes = np.zeros((max(n, 1), 8), dtype=np.float32)
+    nn = ctypes.c_int64(0)
+    _check(lib().tril_dbg_boxes(ctx, int(which), boxes.ctypes.data, max(n, 1), ctypes.byref(nn)),
+           "tril_dbg_boxes")
+    boxes = boxes[: nn.value]
+    ints = boxes.view(np.int32)
+    return {"lo": boxes[:, 0:3].copy(), "hi": boxes[:, 4:7].copy(), "tag": ints[:, 3].copy(),
+            "inst": ints[:, 7].copy()}
+
+
+def tril_dbg_candidates(ctx, cap: int = 1 << 22):
+    ctx = _h(ctx)
+    ci = np.zeros(cap, dtype=np.int32)
+    cj = np.zeros(cap, dtype=np.int32)
+    cnt = ctypes.c_int64(0)
+    _check(lib().tril_dbg_candidates(ctx, ci.ctypes.data_as(_i32p), cj.ctypes.data_as(_i32p), cap,
+                                     ctypes.byref(cnt)), "tril_dbg_candidates")
+    m = min(cnt.value, cap)
+    return ci[:m].copy(), cj[:m].copy(), cnt.value
+
+
+# ---------------------------------------------------------------- convenience
+
+
+class Context:
+    """One collision context (owns the hierarchy and scratch on the device)."""
+
+    def __init__(self, dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
+                 cand_cap: int = 0, block_traverse: int = 0, stream=None):
+        self.n_bins = 0 if edges is None else max(len(edges) - 1, 0)
+        self.h = tril_create(dt, edges, flags, cand_cap, block_traverse, stream)
+
+    def build(self, target: Beam, step: int) -> None:
+        tril_build(self.h, target, step)
+
+    def collide(self, query: Beam, step: int, pairs: Pairs) -> None:
+        tril_collide(self.h, query, step, pairs)
+
+    def run(self, target: Beam, query: Beam, k0: int, n_steps: int, pairs: Pairs) -> None:
+        tril_run(self.h, target, query, k0, n_steps, pairs)
+
+    def stats(self, pairs: Optional[Pairs], n_step_counts: int = 0, check: bool = True) -> dict:
+        out = tril_stats(self.h, pairs, self.n_bins, n_step_counts)
+        if check:
+            _check(out["code"], "tril_stats")
+        return out
+
+    def reset_counters(self) -> None:
+        tril_reset_counters(self.h)
+
+    def close(self) -> None:
+        if self.h:
+            tril_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_steps(ctx: Context, target: Beam, query: Beam, n_steps: int, pairs: Pairs,
+              k0: int = 0, graph: bool = True) -> None:
+    """Build + collide for steps k0 .. k0+n_steps-1 (graph replay or one call per step)."""
+    if graph:
+        ctx.run(target, query, k0, n_steps, pairs)
+    else:
+        for k in range(k0, k0 + n_steps):
+            ctx.build(target, k)
+            ctx.collide(query, k, pairs)

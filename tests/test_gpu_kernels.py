@@ -1,0 +1,233 @@
+"""Single-stage checks of the HIP kernels through the inspection ABI (GPU)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1608_01125_amd import beams
+from paper_1608_01125_amd import tril as T
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    return _t
+
+
+# ------------------------------------------------------------------ radix sort
+
+
+def _sort_case(torch, keys_np, bits, wide):
+    n = len(keys_np)
+    dt = torch.int64 if wide else torch.int32
+    keys = torch.from_numpy(keys_np.view(np.int64 if wide else np.int32).copy()).cuda()
+    vals = torch.arange(n, dtype=torch.int32, device="cuda")
+    (T.tril_dbg_sort_u64 if wide else T.tril_dbg_sort_u32)(keys, vals, bits)
+    got_k = keys.cpu().numpy().view(np.uint64 if wide else np.uint32)
+    got_v = vals.cpu().numpy()
+    masked = keys_np & np.array((1 << bits) - 1, dtype=keys_np.dtype) if bits < (64 if wide else 32) else keys_np
+    ref = np.argsort(masked, kind="stable")
+    assert np.array_equal(got_v, ref.astype(np.int32))
+    assert np.array_equal(got_k, keys_np[ref])
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 64, 255, 2047, 2048, 2049, 4096 + 17, 100_003, 1_000_000])
+def test_sort_u32_random(torch, n):
+    rng = np.random.default_rng(n)
+    keys = rng.integers(0, 1 << 30, n, dtype=np.uint32)
+    _sort_case(torch, keys, 30, False)
+
+
+@pytest.mark.parametrize("kind", ["equal", "sorted", "reversed", "few", "full32"])
+def test_sort_u32_patterns(torch, kind):
+    n = 50_001
+    rng = np.random.default_rng(1)
+    if kind == "equal":
+        keys = np.full(n, 12345, np.uint32)
+    elif kind == "sorted":
+        keys = np.sort(rng.integers(0, 1 << 30, n, dtype=np.uint32))
+    elif kind == "reversed":
+        keys = np.sort(rng.integers(0, 1 << 30, n, dtype=np.uint32))[::-1].copy()
+    elif kind == "few":
+        keys = rng.integers(0, 5, n, dtype=np.uint32) << 20
+    else:
+        keys = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+    _sort_case(torch, keys, 32 if kind == "full32" else 30, False)
+
+
+@pytest.mark.parametrize("bits", [36, 40, 64])
+def test_sort_u64(torch, bits):
+    rng = np.random.default_rng(bits)
+    n = 70_001
+    keys = rng.integers(0, 1 << min(bits, 63), n, dtype=np.uint64)
+    if bits == 64:
+        keys |= (rng.integers(0, 2, n, dtype=np.uint64) << np.uint64(63))
+    keys[::7] = keys[3]  # duplicates
+    _sort_case(torch, keys, bits, True)
+
+
+def test_sort_partial_bits_is_stable(torch):
+    rng = np.random.default_rng(9)
+    n = 30_000
+    keys = rng.integers(0, 1 << 30, n, dtype=np.uint32)
+    _sort_case(torch, keys, 8, False)
+
+
+# ------------------------------------------------------------------ Morton
+
+
+def _interleave(q):
+    out = np.zeros(len(q[0]), dtype=np.uint64)
+    for bit in range(10):
+        for a in range(3):
+            out |= ((q[a].astype(np.uint64) >> np.uint64(bit)) & np.uint64(1)) << np.uint64(3 * bit + (2 - a))
+    return out.astype(np.uint32)
+
+
+def test_morton_matches_scalar_interleave(torch):
+    rng = np.random.default_rng(4)
+    n = 10_000
+    lo = rng.uniform(-5, 5, (n, 3)).astype(np.float32)
+    hi = lo + rng.uniform(0, 0.5, (n, 3)).astype(np.float32)
+    boxes = np.zeros((n, 8), np.float32)
+    boxes[:, 0:3] = lo
+    boxes[:, 4:7] = hi
+    c = (np.float32(0.5) * (lo + hi)).astype(np.float32)
+    bmin = c.min(axis=0)
+    bmax = c.max(axis=0)
+    bounds = list(bmin) + list(bmax)
+    keys = torch.zeros(n, dtype=torch.int32, device="cuda")
+    T.tril_dbg_morton(torch.from_numpy(boxes).cuda(), bounds, keys)
+    got = keys.cpu().numpy().view(np.uint32)
+    q = []
+    for a in range(3):
+        ext = np.float32(bmax[a] - bmin[a])
+        sc = np.float32(1023.0) / ext
+        v = ((c[:, a] - bmin[a]).astype(np.float32) * sc).astype(np.float32)
+        q.append(np.clip(v, 0, 1023).astype(np.uint32))
+    ref = _interleave(q)
+    assert np.array_equal(got, ref)
+
+
+# ------------------------------------------------------------- pair physics
+
+
+def test_pair_eval_matches_oracle(torch):
+    """s and d^2 are IEEE operations in a fixed order: bit-identical to the oracle.
+    sigma uses log/log1p of the device math library: within a few ulp."""
+    rng = np.random.default_rng(8)
+    n = 20_000
+    rows = np.zeros((n, 18))
+    for side, off in ((0, 0), (1, 8)):
+        E = 10 ** rng.uniform(-1, 1.2, n)
+        u = rng.normal(size=(n, 3))
+        u /= np.linalg.norm(u, axis=1)[:, None]
+        rows[:, off] = E
+        rows[:, off + 1:off + 4] = E[:, None] * u
+        rows[:, off + 4:off + 7] = rng.uniform(-20, 20, (n, 3))
+        rows[:, off + 7] = 10 ** rng.uniform(8, 14, n)
+    rows[:, 16] = rng.integers(0, 400, n) * 0.1
+    rows[:, 17] = 0.1
+    inp = torch.from_numpy(rows).cuda()
+    out = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+    T.tril_dbg_pair_eval(inp, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for r in range(0, n, 7):
+        a = rows[r]
+        ui = tuple(a[1:4] / a[0])
+        uj = tuple(a[9:12] / a[8])
+        s = O.invariant(a[0], ui, a[8], uj)
+        assert got[r, 0] == s
+        d2 = O.step_d2(a[16], a[17], tuple(a[4:7]), ui, tuple(a[12:15]), uj)
+        assert got[r, 2] == d2
+        sig = O.sigma(s)
+        assert got[r, 1] == pytest.approx(sig, rel=8e-16, abs=0)
+        r2 = (np.sqrt(a[7] * a[15]) * sig) / np.pi
+        assert got[r, 3] == pytest.approx(r2, rel=2e-15, abs=0)
+
+
+# ---------------------------------------------------- hierarchy and traversal
+
+
+def _small_beams(n=3000, seed=2, boost=3e3):
+    wl = beams.gauss_headon_1m(n=n, seed=seed)
+    wl = beams.gauss_headon_1m(n=n, seed=seed, w=wl.a.w * boost)
+    A, B = beams.draw_pair(wl)
+    return wl, A, B
+
+
+def test_tree_invariants(torch):
+    wl, A, B = _small_beams()
+    ctx = T.Context(wl.dt)
+    tb = T.Beam(B)
+    ctx.build(tb, 200)
+    tree = T.tril_dbg_tree(ctx, len(B["E"]))
+    boxes = T.tril_dbg_boxes(ctx, 0, len(B["E"]))
+    ctx.close()
+    n = len(B["E"])
+    n_int = n - 1
+    assert len(tree["link"]) == 2 * n - 1
+    assert tree["roots"][0] == 0 and tree["stops"][0] == -1
+    # depth-first walk through links and ropes visits every node exactly once
+    seen = np.zeros(2 * n - 1, dtype=np.int32)
+    node, order = 0, []
+    while node != -1:
+        seen[node] += 1
+        order.append(node)
+        node = tree["link"][node] if node < n_int else tree["rope"][node]
+        assert len(order) <= 2 * n - 1
+    assert np.all(seen == 1)
+    # leaves hold every row once, with that row's box
+    rows = tree["link"][n_int:]
+    assert np.array_equal(np.sort(rows), np.arange(n))
+    assert np.array_equal(tree["lo"][n_int:], boxes["lo"][rows])
+    assert np.array_equal(tree["hi"][n_int:], boxes["hi"][rows])
+    # every internal box is the exact union of its two children; right = rope(left)
+    for p in range(n_int):
+        lc = tree["link"][p]
+        rc = tree["rope"][lc]
+        assert 0 <= rc < 2 * n - 1
+        assert np.array_equal(tree["lo"][p], np.minimum(tree["lo"][lc], tree["lo"][rc]))
+        assert np.array_equal(tree["hi"][p], np.maximum(tree["hi"][lc], tree["hi"][rc]))
+        assert tree["rope"][rc] == tree["rope"][p]
+
+
+def test_boxes_contain_swept_segments(torch):
+    wl, A, B = _small_beams(n=2000)
+    step = 150
+    ctx = T.Context(wl.dt)
+    ctx.build(T.Beam(B), step)
+    bx = T.tril_dbg_boxes(ctx, 0, len(B["E"]))
+    ctx.close()
+    t = step * wl.dt
+    for tau in (0.0, 0.5 * wl.dt, wl.dt):
+        P = np.c_[B["x"], B["y"], B["z"]] + (t + tau) * (np.c_[B["px"], B["py"], B["pz"]] / B["E"][:, None])
+        assert np.all(bx["lo"].astype(np.float64) <= P) and np.all(bx["hi"].astype(np.float64) >= P)
+
+
+def test_candidates_equal_bruteforce_box_overlap(torch):
+    wl, A, B = _small_beams(n=3000, boost=3e4)
+    step = 200
+    ctx = T.Context(wl.dt)
+    tb, qb = T.Beam(B), T.Beam(A)
+    pairs = T.Pairs(1 << 16)
+    ctx.build(tb, step)
+    ctx.collide(qb, step, pairs)
+    ci, cj, cnt = T.tril_dbg_candidates(ctx)
+    qbx = T.tril_dbg_boxes(ctx, 1, len(A["E"]))
+    tbx = T.tril_dbg_boxes(ctx, 0, len(B["E"]))
+    ctx.close()
+    got = set(zip(ci.tolist(), cj.tolist()))
+    assert len(got) == cnt
+    act = qbx["tag"] >= 0
+    ql, qh, tl, th = qbx["lo"], qbx["hi"], tbx["lo"], tbx["hi"]
+    ov = np.ones((len(A["E"]), len(B["E"])), dtype=bool)
+    for a in range(3):
+        ov &= (ql[:, a][:, None] <= th[:, a][None, :]) & (qh[:, a][:, None] >= tl[:, a][None, :])
+    ov &= act[:, None]
+    ref = set(zip(*[x.tolist() for x in np.nonzero(ov)]))
+    assert got == ref
+    assert cnt > 10
