@@ -1,0 +1,223 @@
+#!/usr/bin/env python
+"""Photon-pair queries resolved per second on one MI355X.
+
+One benchmark step is one whole collision run of the hot path over one pair of
+synthetic beams: for every time step, the hierarchy is built over beam B
+(swept boxes, Morton keys, radix sort, hierarchy emission, refit), beam A is
+prepared and traversed, candidates go through the FP64 narrow phase; after the
+last time step the hits are merged into the pair set with yield, spectrum and
+per-step counts. Inputs are resident in HBM before timing starts.
+
+    value = N_A * N_B * n_time_steps / (seconds per benchmark step)
+
+The JSON line also carries
+  * roofline: the traversal kernel's algorithmic bytes per launch (36 B per query
+    for its order entry and box, 32 B per node visit, 8 B per candidate written)
+    divided by its average launch time from HIP events recorded on the library's
+    stream during the timed region; HBM traffic per launch from the committed
+    rocprofv3 counter summary when it belongs to the current kernel source;
+  * cpu_baseline: the FP64 CPU oracle timed on a bounded sample of query rows of
+    the same workload (all pairs of those rows, all time steps).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "photon-pair queries resolved/s (N_A*N_B/t) at 1e6/beam; surrogate vs exact @≤1% err"
+HBM_PEAK_GBS = 8000.0
+TRAVERSE_SOURCES = ("paper_1608_01125_amd/csrc/traverse.hip", "paper_1608_01125_amd/csrc/tril_internal.h")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "traverse_gauss_headon_1m_pmc.txt")
+
+
+def traverse_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in TRAVERSE_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per traversal launch from the committed counter summary, or None
+    when it was taken from a different kernel source."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    vals = {}
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != traverse_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_workload(name: str, physics_steps: int):
+    from paper_1608_01125_amd import beams
+    if name == "gauss_headon_1m":
+        wl = beams.gauss_headon_1m()
+    elif name == "mono_headon_2k":
+        wl = beams.mono_headon_2k()
+    elif name == "broadband_16m":
+        wl = beams.broadband_16m()
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    A, B = beams.draw_pair(wl)
+    n_steps = physics_steps if physics_steps > 0 else wl.n_steps
+    return wl, A, B, n_steps
+
+
+def cpu_baseline(A, B, dt, n_steps, target_s: float):
+    """Oracle (as it stands) on a bounded random sample of query rows."""
+    import numpy as np
+    from oracle import oracle as O
+    O.build(force=False)
+    threads = O.num_threads()
+    rng = np.random.default_rng(12345)
+    nA = len(A["E"])
+    r = min(nA, 64)
+    while True:
+        rows = rng.choice(nA, r, replace=False)
+        t = time.perf_counter()
+        O.collide(A, B, dt, n_steps, rows=rows)
+        el = time.perf_counter() - t
+        if el >= 0.5 * target_s or r >= nA:
+            break
+        r = int(min(nA, r * max(2.0, 1.1 * target_s / max(el, 1e-3))))
+    nB = len(B["E"])
+    return {
+        "value": r * nB * n_steps / el,
+        "unit": "queries/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{r} random query rows x all {nB} target photons x {n_steps} steps "
+                  f"({el:.1f} s, FP64, pruned mode, OpenMP)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed benchmark steps (collision runs)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="gauss_headon_1m")
+    ap.add_argument("--mode", choices=("eager", "graph"), default="eager",
+                    help="eager: one build/collide call per time step with HIP events per phase; "
+                         "graph: replay of a captured step (no per-phase events)")
+    ap.add_argument("--physics-steps", type=int, default=0, help="0 = the workload's full run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this size first (counter calibration)")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--flags", type=int, default=0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; the collision path "
+                                   "is not sharded across GPUs in this build", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1608_01125_amd import beams
+    from paper_1608_01125_amd import tril as T
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl, A, B, n_steps = make_workload(args.workload, args.physics_steps)
+    nA, nB = len(A["E"]), len(B["E"])
+    edges = beams.spectrum_edges()
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    flags = args.flags | (T.TRIL_TIMING if args.mode == "eager" else 0)
+    ctx = T.Context(wl.dt, edges, flags=flags, block_traverse=args.block)
+    tb, qb = T.Beam(B), T.Beam(A)
+    pairs = T.Pairs(max(1 << 20, 4 * min(nA, nB)))
+    graph = args.mode == "graph"
+
+    def one_run():
+        pairs.reset()
+        T.run_steps(ctx, tb, qb, n_steps, pairs, graph=graph)
+        return ctx.stats(pairs)
+
+    for _ in range(args.warmup):
+        one_run()
+    ctx.reset_counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = one_run()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.close()
+
+    ms_per_step = 1e3 * elapsed / max(args.steps, 1)
+    value = nA * nB * n_steps / (elapsed / max(args.steps, 1))
+
+    launches = st["n_collides"]
+    roofline = None
+    if launches > 0:
+        alg_bytes = 36.0 * nA * launches + 32.0 * st["n_node_visits"] + 8.0 * st["n_candidates"]
+        per_launch = alg_bytes / launches
+        if st["n_timed_steps"] > 0 and st["ms_traverse"] > 0:
+            avg_s = st["ms_traverse"] * 1e-3 / st["n_timed_steps"]
+            achieved = per_launch / avg_s / 1e9
+            roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": committed_traffic(),
+                        "kernel": "k_traverse", "avg_launch_us": round(avg_s * 1e6, 3),
+                        "alg_bytes_per_launch": round(per_launch, 1),
+                        "node_visits_per_query": round(st["n_node_visits"] / max(st["n_queries"], 1), 3)}
+        else:
+            roofline = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": None, "traffic": committed_traffic(), "kernel": "k_traverse",
+                        "note": "graph mode records no per-phase events; use --mode eager"}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_per_beam": [nA, nB], "time_steps": n_steps,
+                   "dt_um_per_c": wl.dt, "weight": wl.a.w, "mode": args.mode,
+                   "pairs": st["n_pairs"], "hits": st["n_hits"],
+                   "ms_phases_per_run": {k: round(st[k] / max(args.steps, 1), 3) for k in
+                                         ("ms_build", "ms_query_prep", "ms_traverse", "ms_narrow")}},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, B, wl.dt, n_steps, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -91,10 +91,12 @@ struct tril_ctx {
     int64_t *d_t_off = nullptr;
     std::vector<int64_t> h_t_off;
     PBox *t_box = nullptr;
+    BoundsPartial *t_part = nullptr;
     uint32_t *t_k32a = nullptr, *t_k32b = nullptr;
     unsigned long long *t_k64a = nullptr, *t_k64b = nullptr;
     uint32_t *t_va = nullptr, *t_vb = nullptr;
     int32_t *left = nullptr, *right = nullptr, *parent = nullptr, *range_hi = nullptr;
+    int32_t *range_lo = nullptr;
     int32_t *split_right = nullptr, *nflags = nullptr;
     Node *nodes = nullptr;
     uint32_t *t_bounds = nullptr;
@@ -107,6 +109,7 @@ struct tril_ctx {
     int64_t *d_q_off = nullptr;
     std::vector<int64_t> h_q_off;
     PBox *q_box = nullptr;
+    BoundsPartial *q_part = nullptr;
     uint32_t *q_k32a = nullptr, *q_k32b = nullptr;
     unsigned long long *q_k64a = nullptr, *q_k64b = nullptr;
     uint32_t *q_va = nullptr, *q_vb = nullptr;
@@ -127,6 +130,8 @@ struct tril_ctx {
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::array<int, 2>> ev_build, ev_prep, ev_trav, ev_narrow;
     size_t ev_next = 0;
+    double ms_acc[4] = {0, 0, 0, 0};   // summed event times of pairs already read and recycled
+    int64_t timed_steps = 0;
 
     // captured step graph
     hipGraphExec_t gexec = nullptr;
@@ -155,9 +160,9 @@ int ensure_sort_scratch(tril_ctx *c, int64_t n) {
 }
 
 void free_target(tril_ctx *c) {
-    dev_free(c->t_box); dev_free(c->t_k32a); dev_free(c->t_k32b); dev_free(c->t_k64a);
+    dev_free(c->t_box); dev_free(c->t_part); dev_free(c->t_k32a); dev_free(c->t_k32b); dev_free(c->t_k64a);
     dev_free(c->t_k64b); dev_free(c->t_va); dev_free(c->t_vb); dev_free(c->left);
-    dev_free(c->right); dev_free(c->parent); dev_free(c->range_hi); dev_free(c->split_right);
+    dev_free(c->right); dev_free(c->parent); dev_free(c->range_hi); dev_free(c->range_lo); dev_free(c->split_right);
     dev_free(c->nflags); dev_free(c->nodes);
     c->t_cap = 0;
 }
@@ -168,11 +173,13 @@ int ensure_target(tril_ctx *c, int64_t n, int32_t n_inst) {
         free_target(c);
         const int64_t m = std::max<int64_t>(n, 1);
         CHK(dev_alloc(&c->t_box, m));
+        CHK(dev_alloc(&c->t_part, (size_t)boxes_partials_needed(m)));
         CHK(dev_alloc(&c->t_k32a, m)); CHK(dev_alloc(&c->t_k32b, m));
         CHK(dev_alloc(&c->t_k64a, m)); CHK(dev_alloc(&c->t_k64b, m));
         CHK(dev_alloc(&c->t_va, m)); CHK(dev_alloc(&c->t_vb, m));
         CHK(dev_alloc(&c->left, m)); CHK(dev_alloc(&c->right, m));
         CHK(dev_alloc(&c->parent, 2 * m)); CHK(dev_alloc(&c->range_hi, m));
+        CHK(dev_alloc(&c->range_lo, m));
         CHK(dev_alloc(&c->split_right, m)); CHK(dev_alloc(&c->nflags, m));
         CHK(dev_alloc(&c->nodes, 2 * m));
         c->t_cap = m;
@@ -197,13 +204,14 @@ int ensure_target(tril_ctx *c, int64_t n, int32_t n_inst) {
 int ensure_query(tril_ctx *c, int64_t n, int32_t n_inst) {
     if (n > c->q_cap) {
         ++c->alloc_gen;
-        dev_free(c->q_box); dev_free(c->q_k32a); dev_free(c->q_k32b); dev_free(c->q_k64a);
+        dev_free(c->q_box); dev_free(c->q_part); dev_free(c->q_k32a); dev_free(c->q_k32b); dev_free(c->q_k64a);
         dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
         c->q_cap = 0;
         c->q_order = nullptr;
         c->q_order_key = nullptr;
         const int64_t m = std::max<int64_t>(n, 1);
         CHK(dev_alloc(&c->q_box, m));
+        CHK(dev_alloc(&c->q_part, (size_t)boxes_partials_needed(m)));
         CHK(dev_alloc(&c->q_k32a, m)); CHK(dev_alloc(&c->q_k32b, m));
         CHK(dev_alloc(&c->q_k64a, m)); CHK(dev_alloc(&c->q_k64b, m));
         CHK(dev_alloc(&c->q_va, m)); CHK(dev_alloc(&c->q_vb, m));
@@ -302,8 +310,8 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
     if (timed) CHK(timing_pair(c, st, c->ev_build, true));
     launch_begin_step(c->d_cnt, 0, st);
     launch_clear_inst(c->t_bounds, c->t_emax, c->t_wmax, c->t_inst, st);
-    launch_boxes(c->tgt, false, c->dt, c->sigma_up, nullptr, nullptr, c->t_box, c->t_bounds,
-                 c->t_emax, c->t_wmax, c->d_cnt, st);
+    launch_boxes(c->tgt, false, c->dt, c->sigma_up, nullptr, nullptr, c->t_box, c->t_part,
+                 c->t_bounds, c->t_emax, c->t_wmax, c->d_cnt, st);
     const uint32_t *rows = nullptr;
     if (c->t_inst == 1) {
         launch_morton_u32(c->t_box, n, c->t_bounds, c->t_k32a, c->t_va, st);
@@ -311,21 +319,21 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
                                         &c->d_cnt->err, st);
         const uint32_t *keys = alt ? c->t_k32b : c->t_k32a;
         rows = alt ? c->t_vb : c->t_va;
-        launch_karras_u32(keys, n, c->left, c->right, c->parent, c->range_hi, c->split_right,
-                          c->nflags, st);
+        launch_karras_u32(keys, n, c->left, c->right, c->parent, c->range_lo, c->range_hi,
+                          c->split_right, c->nflags, st);
     } else {
         launch_morton_u64(c->t_box, n, c->t_bounds, c->t_k64a, c->t_va, st);
         const bool alt = radix_sort_u64(c->t_k64a, c->t_va, c->t_k64b, c->t_vb, n,
                                         inst_key_bits(c->t_inst), c->ss, &c->d_cnt->err, st);
         const unsigned long long *keys = alt ? c->t_k64b : c->t_k64a;
         rows = alt ? c->t_vb : c->t_va;
-        launch_karras_u64(keys, n, c->left, c->right, c->parent, c->range_hi, c->split_right,
-                          c->nflags, c->inst_root, st);
+        launch_karras_u64(keys, n, c->left, c->right, c->parent, c->range_lo, c->range_hi,
+                          c->split_right, c->nflags, c->inst_root, st);
     }
     launch_inst_roots(c->d_t_off, c->t_inst, n, c->t_inst == 1, c->split_right, c->inst_root,
                       c->inst_stop, st);
-    launch_refit(c->t_box, rows, n, c->left, c->right, c->parent, c->range_hi, c->split_right,
-                 c->nflags, c->nodes, &c->d_cnt->err, st);
+    launch_refit(c->t_box, rows, n, c->left, c->right, c->parent, c->range_lo, c->range_hi,
+                 c->split_right, c->nflags, c->nodes, &c->d_cnt->err, st);
     if (timed) CHK(timing_pair(c, st, c->ev_build, false));
     HIPCHK(hipGetLastError());
     return TRIL_OK;
@@ -337,8 +345,8 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
     launch_begin_step(c->d_cnt, 1, st);
     if (timed) CHK(timing_pair(c, st, c->ev_prep, true));
     launch_clear_inst(c->q_bounds, nullptr, nullptr, q.n_inst, st);
-    launch_boxes(q, true, c->dt, c->sigma_up, c->t_emax, c->t_wmax, c->q_box, c->q_bounds, nullptr,
-                 nullptr, c->d_cnt, st);
+    launch_boxes(q, true, c->dt, c->sigma_up, c->t_emax, c->t_wmax, c->q_box, c->q_part,
+                 c->q_bounds, nullptr, nullptr, c->d_cnt, st);
     if (sort_queries && n > 0) {
         if (q.n_inst == 1) {
             launch_morton_u32(c->q_box, n, c->q_bounds, c->q_k32a, c->q_va, st);
@@ -410,6 +418,21 @@ double sum_events(tril_ctx *c, const std::vector<std::array<int, 2>> &v) {
         if (hipEventElapsedTime(&ms, c->ev_pool[p[0]], c->ev_pool[p[1]]) == hipSuccess) tot += ms;
     }
     return tot;
+}
+
+// Fold the recorded event pairs into running sums and recycle the events (the
+// stream has been synchronised by the caller).
+void fold_events(tril_ctx *c) {
+    c->ms_acc[0] += sum_events(c, c->ev_build);
+    c->ms_acc[1] += sum_events(c, c->ev_prep);
+    c->ms_acc[2] += sum_events(c, c->ev_trav);
+    c->ms_acc[3] += sum_events(c, c->ev_narrow);
+    c->timed_steps += (int64_t)c->ev_trav.size();
+    c->ev_build.clear();
+    c->ev_prep.clear();
+    c->ev_trav.clear();
+    c->ev_narrow.clear();
+    c->ev_next = 0;
 }
 
 }  // namespace
@@ -635,16 +658,22 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     HIPCHK(hipMemcpy(c->h_cnt, c->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost));
     const DevCounters h = *c->h_cnt;
     out->n_candidates = (int64_t)h.cand_total;
-    out->n_node_visits = (int64_t)h.visits;
-    out->n_queries = (int64_t)h.queries;
+    int64_t visits = 0, queries = 0;
+    for (int k = 0; k < kCounterSlots; ++k) {
+        visits += (int64_t)h.visits[k];
+        queries += (int64_t)h.queries[k];
+    }
+    out->n_node_visits = visits;
+    out->n_queries = queries;
     out->n_sigma_evals = (int64_t)h.sigma_evals;
     out->n_builds = (int64_t)h.builds;
     out->n_collides = (int64_t)h.collides;
-    out->ms_build = sum_events(c, c->ev_build);
-    out->ms_query_prep = sum_events(c, c->ev_prep);
-    out->ms_traverse = sum_events(c, c->ev_trav);
-    out->ms_narrow = sum_events(c, c->ev_narrow);
-    out->n_timed_steps = (int64_t)c->ev_trav.size();
+    fold_events(c);
+    out->ms_build = c->ms_acc[0];
+    out->ms_query_prep = c->ms_acc[1];
+    out->ms_traverse = c->ms_acc[2];
+    out->ms_narrow = c->ms_acc[3];
+    out->n_timed_steps = c->timed_steps;
     out->n_pairs = 0;
     out->n_hits = 0;
     out->yield = 0.0;
@@ -694,6 +723,8 @@ int tril_reset_counters(tril_ctx *c) {
     HIPCHK(hipMemcpy(c->d_cnt, c->h_cnt, sizeof(DevCounters), hipMemcpyHostToDevice));
     c->ev_build.clear(); c->ev_prep.clear(); c->ev_trav.clear(); c->ev_narrow.clear();
     c->ev_next = 0;
+    for (double &m : c->ms_acc) m = 0.0;
+    c->timed_steps = 0;
     c->max_step = c->built ? c->built_step : -1;
     return TRIL_OK;
 }
@@ -706,8 +737,9 @@ void tril_destroy(tril_ctx *c) {
     free_target(c);
     dev_free(c->d_t_off); dev_free(c->t_bounds); dev_free(c->t_emax); dev_free(c->t_wmax);
     dev_free(c->inst_root); dev_free(c->inst_stop);
-    dev_free(c->q_box); dev_free(c->q_k32a); dev_free(c->q_k32b); dev_free(c->q_k64a);
-    dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb); dev_free(c->d_q_off);
+    dev_free(c->q_box); dev_free(c->q_part); dev_free(c->q_k32a); dev_free(c->q_k32b);
+    dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
+    dev_free(c->d_q_off);
     dev_free(c->q_bounds); dev_free(c->cand_i); dev_free(c->cand_j);
     dev_free(c->ss.hist); dev_free(c->ss.tile_ctr); dev_free(c->ss.status);
     StatsScratch &s = c->sst;

@@ -6,7 +6,9 @@
 //      give each lane the mask of lanes holding the same digit),
 //   2. publishes its per-digit counts and resolves the counts of all earlier tiles by
 //      decoupled look-back (tile ids come from an atomic counter, so every tile it
-//      waits for has already started and publishes without waiting itself),
+//      waits for has already started and publishes without waiting itself); a status
+//      word holds flag and count together, so device-scope relaxed atomics suffice and
+//      no release fence (an L2 write-back on this chip) is needed,
 //   3. stages keys in digit order in LDS and writes each digit's run to its global
 //      bucket with consecutive lanes on consecutive addresses.
 // Published methods: Merrill & Garland, "Single-pass parallel prefix scan with
@@ -157,9 +159,9 @@ __global__ void __launch_bounds__(kBlock) k_sort_pass(
         uint32_t *my = status + (size_t)tile * 256 + d;
         uint32_t excl = 0;
         if (tile == 0) {
-            __hip_atomic_store(my, kFlagInc | tcount, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(my, kFlagInc | tcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            __hip_atomic_store(my, kFlagAgg | tcount, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(my, kFlagAgg | tcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             int64_t t = (int64_t)tile - 1;
             uint32_t spins = 0;
             while (t >= 0) {
@@ -178,7 +180,7 @@ __global__ void __launch_bounds__(kBlock) k_sort_pass(
                 if (f == kFlagInc) break;
                 --t;
             }
-            __hip_atomic_store(my, kFlagInc | ((excl + tcount) & kValMask), __ATOMIC_RELEASE,
+            __hip_atomic_store(my, kFlagInc | ((excl + tcount) & kValMask), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
         s_gbase[d] = gpre + excl;

@@ -87,8 +87,9 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
     if ((threadIdx.x & 63) == 0) {
-        if (v) atomicAdd(&c->visits, v);
-        if (active_q) atomicAdd(&c->queries, (unsigned long long)__popcll(active_q));
+        const int slot = blockIdx.x & (kCounterSlots - 1);
+        if (v) atomicAdd(&c->visits[slot], v);
+        if (active_q) atomicAdd(&c->queries[slot], (unsigned long long)__popcll(active_q));
     }
 }
 

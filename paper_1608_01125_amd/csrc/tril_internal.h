@@ -46,17 +46,21 @@ struct alignas(16) PBox {
 };
 static_assert(sizeof(PBox) == 32, "box layout");
 
-// Counters accumulated on the device across steps.
+// Counters accumulated on the device across steps. Counters that every wave of a
+// large launch updates are spread over kCounterSlots addresses (slot = block index
+// modulo kCounterSlots): device-scope atomics to one address serialise at roughly
+// 10 ns each, so one address per counter would cost ~0.3 ms per million queries.
+constexpr int kCounterSlots = 256;
 struct DevCounters {
     unsigned long long cand_step;      // candidates of the current step (reset per step)
     unsigned long long cand_total;
-    unsigned long long visits;
-    unsigned long long queries;
     unsigned long long sigma_evals;
     unsigned long long builds;
     unsigned long long collides;
     unsigned int err;
     unsigned int step;                 // current step index (device-resident for graphs)
+    unsigned long long visits[kCounterSlots];
+    unsigned long long queries[kCounterSlots];
 };
 
 // ---------------------------------------------------------------- radix sort
@@ -86,6 +90,15 @@ struct BeamDev {  // device view of a caller beam plus instance data
     const int64_t *inst_off;   // device copy, n_inst + 1
 };
 
+// Partial reduction of one block for one instance (inst = -1: unused slot).
+struct BoundsPartial {
+    uint32_t mn[3], mx[3];   // centroid bounds as ordered floats
+    int32_t inst;
+    int32_t pad;
+    unsigned long long e, w; // largest E and w (FP64 bits)
+};
+int64_t boxes_partials_needed(int64_t n);
+
 // Per-instance data of the target (device arrays of n_inst entries unless noted).
 struct InstDev {
     uint32_t *bounds;                 // 6 per instance: ordered-float min xyz, max xyz
@@ -104,25 +117,25 @@ void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st);
 
 void launch_boxes(const BeamDev &b, bool query, double dt, double sigma_up,
                   const unsigned long long *t_emax, const unsigned long long *t_wmax,
-                  PBox *out, uint32_t *bounds, unsigned long long *emax, unsigned long long *wmax,
-                  DevCounters *c, hipStream_t st);
+                  PBox *out, BoundsPartial *partials, uint32_t *bounds, unsigned long long *emax,
+                  unsigned long long *wmax, DevCounters *c, hipStream_t st);
 void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint32_t *keys,
                        uint32_t *vals, hipStream_t st);
 void launch_morton_u64(const PBox *box, int64_t n, const uint32_t *bounds,
                        unsigned long long *keys, uint32_t *vals, hipStream_t st);
 void launch_karras_u32(const uint32_t *keys, int64_t n, int32_t *left, int32_t *right,
-                       int32_t *parent, int32_t *range_hi, int32_t *split_right, int32_t *flags,
-                       hipStream_t st);
+                       int32_t *parent, int32_t *range_lo, int32_t *range_hi, int32_t *split_right,
+                       int32_t *flags, hipStream_t st);
 void launch_karras_u64(const unsigned long long *keys, int64_t n, int32_t *left, int32_t *right,
-                       int32_t *parent, int32_t *range_hi, int32_t *split_right, int32_t *flags,
-                       int32_t *inst_root, hipStream_t st);
+                       int32_t *parent, int32_t *range_lo, int32_t *range_hi, int32_t *split_right,
+                       int32_t *flags, int32_t *inst_root, hipStream_t st);
 void launch_inst_roots(const int64_t *inst_off, int32_t n_inst, int64_t n, bool single,
                        const int32_t *split_right, int32_t *inst_root, int32_t *inst_stop,
                        hipStream_t st);
 void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, const int32_t *left,
-                  const int32_t *right, const int32_t *parent, const int32_t *range_hi,
-                  const int32_t *split_right, int32_t *flags, Node *nodes, unsigned int *err,
-                  hipStream_t st);
+                  const int32_t *right, const int32_t *parent, const int32_t *range_lo,
+                  const int32_t *range_hi, const int32_t *split_right, int32_t *flags, Node *nodes,
+                  unsigned int *err, hipStream_t st);
 
 void launch_traverse(const Node *nodes, int64_t nt, const PBox *qbox, const uint32_t *qorder,
                      int64_t nq, const int32_t *inst_root, const int32_t *inst_stop,
