@@ -114,9 +114,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="timed benchmark steps (collision runs)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="gauss_headon_1m")
-    ap.add_argument("--mode", choices=("eager", "graph"), default="eager",
-                    help="eager: one build/collide call per time step with HIP events per phase; "
-                         "graph: replay of a captured step (no per-phase events)")
+    ap.add_argument("--mode", choices=("batched", "graph", "per-step"), default="batched",
+                    help="batched: tril_run over step batches with HIP events around each phase; "
+                         "graph: tril_run replaying a captured step batch (no per-phase events); "
+                         "per-step: one tril_build/tril_collide call per time step with events")
+    ap.add_argument("--step-batch", type=int, default=0, help="time steps per launch (0 = automatic)")
     ap.add_argument("--physics-steps", type=int, default=0, help="0 = the workload's full run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -150,11 +152,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    flags = args.flags | (T.TRIL_TIMING if args.mode == "eager" else 0)
-    ctx = T.Context(wl.dt, edges, flags=flags, block_traverse=args.block)
+    flags = args.flags | (T.TRIL_TIMING if args.mode != "graph" else 0)
+    ctx = T.Context(wl.dt, edges, flags=flags, block_traverse=args.block,
+                    step_batch=args.step_batch)
     tb, qb = T.Beam(B), T.Beam(A)
     pairs = T.Pairs(max(1 << 20, 4 * min(nA, nB)))
-    graph = args.mode == "graph"
+    graph = args.mode != "per-step"
 
     def one_run():
         pairs.reset()
@@ -175,13 +178,15 @@ def main():
     ms_per_step = 1e3 * elapsed / max(args.steps, 1)
     value = nA * nB * n_steps / (elapsed / max(args.steps, 1))
 
-    launches = st["n_collides"]
     roofline = None
-    if launches > 0:
-        alg_bytes = 36.0 * nA * launches + 32.0 * st["n_node_visits"] + 8.0 * st["n_candidates"]
-        per_launch = alg_bytes / launches
-        if st["n_timed_steps"] > 0 and st["ms_traverse"] > 0:
-            avg_s = st["ms_traverse"] * 1e-3 / st["n_timed_steps"]
+    if st["n_collides"] > 0:
+        # traversal bytes over the timed region: 36 B per query (order entry + box), 32 B per
+        # node visit, 8 B per candidate written
+        alg_bytes = 36.0 * nA * st["n_collides"] + 32.0 * st["n_node_visits"] + 8.0 * st["n_candidates"]
+        if st["n_timed_launches"] > 0 and st["ms_traverse"] > 0:
+            n_launch = st["n_timed_launches"]
+            per_launch = alg_bytes / n_launch
+            avg_s = st["ms_traverse"] * 1e-3 / n_launch
             achieved = per_launch / avg_s / 1e9
             roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -192,7 +197,7 @@ def main():
         else:
             roofline = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": None, "traffic": committed_traffic(), "kernel": "k_traverse",
-                        "note": "graph mode records no per-phase events; use --mode eager"}
+                        "note": "graph mode records no per-phase events; use --mode batched"}
 
     out = {
         "metric": METRIC,
@@ -209,6 +214,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_per_beam": [nA, nB], "time_steps": n_steps,
                    "dt_um_per_c": wl.dt, "weight": wl.a.w, "mode": args.mode,
+                   "step_batch": args.step_batch, "traversal_launches": st["n_timed_launches"],
                    "pairs": st["n_pairs"], "hits": st["n_hits"],
                    "ms_phases_per_run": {k: round(st[k] / max(args.steps, 1), 3) for k in
                                          ("ms_build", "ms_query_prep", "ms_traverse", "ms_narrow")}},

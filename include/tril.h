@@ -92,7 +92,8 @@ typedef struct {
                                      holds edges[b] <= E_i + E_j < edges[b+1] */
     int64_t cand_cap;             /* broad-phase candidates one step may hold (0 = default) */
     int32_t block_traverse;       /* traversal workgroup size: 64, 128, 256, 512 or 0 = default */
-    int32_t reserved;
+    int32_t step_batch;           /* tril_run: steps per launch, >= 0 (0 = as many as keep one
+                                     launch near 2^24 photon-steps) */
 } tril_params;
 
 /* Caller-owned pair buffer. tril_collide appends raw hits (i, j, step) at
@@ -125,7 +126,8 @@ typedef struct {
     double ms_query_prep;     /* with TRIL_TIMING: query boxes + Morton order */
     double ms_traverse;       /* with TRIL_TIMING: traversal kernel */
     double ms_narrow;         /* with TRIL_TIMING: narrow-phase kernel */
-    int64_t n_timed_steps;    /* number of tril_collide calls the ms_* sums cover */
+    int64_t n_timed_launches; /* traversal launches the ms_* sums cover (one per collide call,
+                                 one per step batch of tril_run) */
 } tril_stats_t;
 
 /* Create a context on the caller's HIP stream (hipStream_t, NULL = default stream).
@@ -147,9 +149,14 @@ int tril_build(tril_ctx *ctx, const tril_beam *target, int32_t step);
  * hierarchy was built or the step differs from the build's step. */
 int tril_collide(tril_ctx *ctx, const tril_beam *query, int32_t step, tril_pairs *out);
 
-/* Build + collide for steps k0 .. k0+n_steps-1 in one call. The step loop is
- * captured once in a HIP graph and replayed, the step index living in device
- * memory; equivalent to calling tril_build/tril_collide per step. */
+/* Build + collide for steps k0 .. k0+n_steps-1 in one call; the result is the same
+ * as calling tril_build/tril_collide for each step. Steps are processed in batches of
+ * m consecutive steps (tril_params.step_batch): one set of launches builds the m
+ * per-step hierarchies (separate subtrees keyed by step and instance) and one
+ * traversal launch answers the queries of all m steps. Full batches are captured once
+ * in a HIP graph and replayed, the step index living in device memory; with
+ * TRIL_TIMING every batch runs eagerly with HIP events around each phase. Scratch
+ * grows with m x (photons per beam). */
 int tril_run(tril_ctx *ctx, const tril_beam *target, const tril_beam *query,
              int32_t k0, int32_t n_steps, tril_pairs *out);
 

@@ -1,6 +1,12 @@
 // C ABI of libtril: argument checks, context and scratch ownership, and the
 // per-step order of the kernels (build: boxes -> Morton -> sort -> hierarchy
 // -> refit; collide: query boxes -> query order -> traversal -> narrow phase).
+//
+// tril_run processes its steps in batches of m consecutive steps: one set of
+// launches builds the m per-step hierarchies (as subtrees with their own roots,
+// keyed by step and instance) and one traversal launch answers the queries of all
+// m steps. Every decision is the same as for one step at a time; batching only
+// fills the GPU with more independent work per launch.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -29,9 +35,9 @@ int hip_fail(hipError_t e) {
         if (e_ != hipSuccess) return hip_fail(e_);  \
     } while (0)
 
-#define CHK(x)                     \
-    do {                           \
-        int r_ = (x);              \
+#define CHK(x)                        \
+    do {                              \
+        int r_ = (x);                 \
         if (r_ != TRIL_OK) return r_; \
     } while (0)
 
@@ -53,16 +59,18 @@ void dev_free(T *&p) {
     p = nullptr;
 }
 
-int bits_for(uint64_t v) {  // smallest b with v < 2^b (v >= 1 -> >= 1)
+int bits_for(uint64_t v) {  // smallest b with v < 2^b
     int b = 0;
     while (b < 64 && (v >> b) != 0) ++b;
     return b;
 }
 
-// Upper bound of the bits in an instance index: keys are (inst << 30) | morton.
-int inst_key_bits(int32_t n_inst) { return 30 + bits_for((uint64_t)(n_inst > 1 ? n_inst - 1 : 0)); }
+// Key width for n_comb combined instances: (instance << 30) | 30-bit Morton code.
+int comb_key_bits(int64_t n_comb) { return 30 + bits_for((uint64_t)(n_comb > 1 ? n_comb - 1 : 0)); }
 
-constexpr int64_t kMaxN = (int64_t)1 << 30;  // node ids 2n-1 fit int32, sort counts fit 30 bits
+constexpr int64_t kMaxN = (int64_t)1 << 30;       // node ids 2n-1 fit int32, sort counts fit 30 bits
+constexpr int64_t kMaxComb = (int64_t)1 << 24;    // combined instances (steps x instances) per launch
+constexpr int64_t kBatchBudget = (int64_t)1 << 24;  // default virtual elements per launch
 
 }  // namespace
 
@@ -76,22 +84,24 @@ struct tril_ctx {
     double *d_edges = nullptr;
     int64_t cand_cap_param = 0;
     int block = 256;
+    int32_t step_batch = 0;         // steps per launch in tril_run (0 = automatic)
     double sigma_up = 0.0;
     DevCounters *d_cnt = nullptr;
     DevCounters *h_cnt = nullptr;   // pinned host mirror
 
-    // target (hierarchy) state
+    // target (hierarchy) state; capacities count virtual elements (steps x rows)
     int64_t t_cap = 0;
-    int32_t t_inst_cap = 0;
-    int64_t nt = 0;
-    int32_t t_inst = 0;
+    int64_t t_comb_cap = 0;
+    int32_t t_off_cap = 0;
+    int64_t nt = 0;                 // rows of the last target beam
     bool built = false;
     int32_t built_step = -1;
     BeamDev tgt{};
     int64_t *d_t_off = nullptr;
     std::vector<int64_t> h_t_off;
     PBox *t_box = nullptr;
-    BoundsPartial *t_part = nullptr;
+    StatsPartial *t_spart = nullptr;
+    InstStats *t_stats = nullptr;
     uint32_t *t_k32a = nullptr, *t_k32b = nullptr;
     unsigned long long *t_k64a = nullptr, *t_k64b = nullptr;
     uint32_t *t_va = nullptr, *t_vb = nullptr;
@@ -99,26 +109,27 @@ struct tril_ctx {
     int32_t *range_lo = nullptr;
     int32_t *split_right = nullptr, *nflags = nullptr;
     Node *nodes = nullptr;
-    uint32_t *t_bounds = nullptr;
-    unsigned long long *t_emax = nullptr, *t_wmax = nullptr;
     int32_t *inst_root = nullptr, *inst_stop = nullptr;
 
     // query state
     int64_t q_cap = 0;
-    int32_t q_inst_cap = 0;
+    int64_t q_comb_cap = 0;
+    int32_t q_off_cap = 0;
     int64_t *d_q_off = nullptr;
     std::vector<int64_t> h_q_off;
     PBox *q_box = nullptr;
-    BoundsPartial *q_part = nullptr;
+    StatsPartial *q_spart = nullptr;
+    InstStats *q_stats = nullptr;
+    uint32_t *q_keep = nullptr;            // query order kept from a first step (n entries)
     uint32_t *q_k32a = nullptr, *q_k32b = nullptr;
     unsigned long long *q_k64a = nullptr, *q_k64b = nullptr;
     uint32_t *q_va = nullptr, *q_vb = nullptr;
-    uint32_t *q_bounds = nullptr;
     const uint32_t *q_order = nullptr;     // sorted query rows (points into q_va or q_vb)
+    int64_t q_order_len = 0;
     const void *q_order_key = nullptr;     // beam the stored order belongs to
     int64_t q_order_n = -1;
 
-    // candidates of one step
+    // candidates of one launch
     int64_t cand_cap = 0;
     int32_t *cand_i = nullptr, *cand_j = nullptr;
 
@@ -131,9 +142,9 @@ struct tril_ctx {
     std::vector<std::array<int, 2>> ev_build, ev_prep, ev_trav, ev_narrow;
     size_t ev_next = 0;
     double ms_acc[4] = {0, 0, 0, 0};   // summed event times of pairs already read and recycled
-    int64_t timed_steps = 0;
+    int64_t timed_launches = 0;
 
-    // captured step graph
+    // captured step-batch graph
     hipGraphExec_t gexec = nullptr;
     std::vector<const void *> gkey;
     uint64_t alloc_gen = 0;         // bumped on every (re)allocation of scratch
@@ -160,20 +171,21 @@ int ensure_sort_scratch(tril_ctx *c, int64_t n) {
 }
 
 void free_target(tril_ctx *c) {
-    dev_free(c->t_box); dev_free(c->t_part); dev_free(c->t_k32a); dev_free(c->t_k32b); dev_free(c->t_k64a);
-    dev_free(c->t_k64b); dev_free(c->t_va); dev_free(c->t_vb); dev_free(c->left);
-    dev_free(c->right); dev_free(c->parent); dev_free(c->range_hi); dev_free(c->range_lo); dev_free(c->split_right);
-    dev_free(c->nflags); dev_free(c->nodes);
+    dev_free(c->t_box); dev_free(c->t_spart); dev_free(c->t_k32a); dev_free(c->t_k32b);
+    dev_free(c->t_k64a); dev_free(c->t_k64b); dev_free(c->t_va); dev_free(c->t_vb);
+    dev_free(c->left); dev_free(c->right); dev_free(c->parent); dev_free(c->range_hi);
+    dev_free(c->range_lo); dev_free(c->split_right); dev_free(c->nflags); dev_free(c->nodes);
     c->t_cap = 0;
 }
 
-int ensure_target(tril_ctx *c, int64_t n, int32_t n_inst) {
-    if (n > c->t_cap) {
+int ensure_target(tril_ctx *c, int64_t nv, int64_t n_comb, int32_t n_inst) {
+    if (nv > c->t_cap) {
         ++c->alloc_gen;
         free_target(c);
-        const int64_t m = std::max<int64_t>(n, 1);
+        c->built = false;
+        const int64_t m = std::max<int64_t>(nv, 1);
         CHK(dev_alloc(&c->t_box, m));
-        CHK(dev_alloc(&c->t_part, (size_t)boxes_partials_needed(m)));
+        CHK(dev_alloc(&c->t_spart, (size_t)stats_partials_needed(m)));
         CHK(dev_alloc(&c->t_k32a, m)); CHK(dev_alloc(&c->t_k32b, m));
         CHK(dev_alloc(&c->t_k64a, m)); CHK(dev_alloc(&c->t_k64b, m));
         CHK(dev_alloc(&c->t_va, m)); CHK(dev_alloc(&c->t_vb, m));
@@ -184,50 +196,57 @@ int ensure_target(tril_ctx *c, int64_t n, int32_t n_inst) {
         CHK(dev_alloc(&c->nodes, 2 * m));
         c->t_cap = m;
     }
-    if (n_inst > c->t_inst_cap) {
+    if (n_comb > c->t_comb_cap) {
         ++c->alloc_gen;
-        dev_free(c->d_t_off); dev_free(c->t_bounds); dev_free(c->t_emax); dev_free(c->t_wmax);
         dev_free(c->inst_root); dev_free(c->inst_stop);
-        c->t_inst_cap = 0;
+        c->t_comb_cap = 0;
+        c->built = false;
+        CHK(dev_alloc(&c->inst_root, (size_t)n_comb));
+        CHK(dev_alloc(&c->inst_stop, (size_t)n_comb));
+        c->t_comb_cap = n_comb;
+    }
+    if (n_inst > c->t_off_cap) {
+        ++c->alloc_gen;
+        dev_free(c->d_t_off); dev_free(c->t_stats);
+        c->t_off_cap = 0;
         CHK(dev_alloc(&c->d_t_off, (size_t)n_inst + 1));
-        CHK(dev_alloc(&c->t_bounds, 6 * (size_t)n_inst));
-        CHK(dev_alloc(&c->t_emax, (size_t)n_inst));
-        CHK(dev_alloc(&c->t_wmax, (size_t)n_inst));
-        CHK(dev_alloc(&c->inst_root, (size_t)n_inst));
-        CHK(dev_alloc(&c->inst_stop, (size_t)n_inst));
-        c->t_inst_cap = n_inst;
+        CHK(dev_alloc(&c->t_stats, (size_t)n_inst));
+        c->t_off_cap = n_inst;
         c->h_t_off.clear();
     }
-    return ensure_sort_scratch(c, n);
+    return ensure_sort_scratch(c, nv);
 }
 
-int ensure_query(tril_ctx *c, int64_t n, int32_t n_inst) {
-    if (n > c->q_cap) {
+int ensure_query(tril_ctx *c, int64_t nv, int64_t n_comb, int32_t n_inst) {
+    if (nv > c->q_cap) {
         ++c->alloc_gen;
-        dev_free(c->q_box); dev_free(c->q_part); dev_free(c->q_k32a); dev_free(c->q_k32b); dev_free(c->q_k64a);
-        dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
+        dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
+        dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
+        dev_free(c->q_keep);
         c->q_cap = 0;
         c->q_order = nullptr;
         c->q_order_key = nullptr;
-        const int64_t m = std::max<int64_t>(n, 1);
+        const int64_t m = std::max<int64_t>(nv, 1);
         CHK(dev_alloc(&c->q_box, m));
-        CHK(dev_alloc(&c->q_part, (size_t)boxes_partials_needed(m)));
+        CHK(dev_alloc(&c->q_spart, (size_t)stats_partials_needed(m)));
+        CHK(dev_alloc(&c->q_keep, m));
         CHK(dev_alloc(&c->q_k32a, m)); CHK(dev_alloc(&c->q_k32b, m));
         CHK(dev_alloc(&c->q_k64a, m)); CHK(dev_alloc(&c->q_k64b, m));
         CHK(dev_alloc(&c->q_va, m)); CHK(dev_alloc(&c->q_vb, m));
         c->q_cap = m;
     }
-    if (n_inst > c->q_inst_cap) {
+    if (n_comb > c->q_comb_cap) c->q_comb_cap = n_comb;
+    if (n_inst > c->q_off_cap) {
         ++c->alloc_gen;
-        dev_free(c->d_q_off); dev_free(c->q_bounds);
-        c->q_inst_cap = 0;
+        dev_free(c->d_q_off); dev_free(c->q_stats);
+        c->q_off_cap = 0;
         CHK(dev_alloc(&c->d_q_off, (size_t)n_inst + 1));
-        CHK(dev_alloc(&c->q_bounds, 6 * (size_t)n_inst));
-        c->q_inst_cap = n_inst;
+        CHK(dev_alloc(&c->q_stats, (size_t)n_inst));
+        c->q_off_cap = n_inst;
         c->h_q_off.clear();
     }
-    int64_t cap = c->cand_cap_param > 0 ? c->cand_cap_param
-                                        : std::max<int64_t>((int64_t)1 << 22, 4 * n);
+    const int64_t cap = c->cand_cap_param > 0 ? c->cand_cap_param
+                                              : std::max<int64_t>((int64_t)1 << 22, 2 * nv);
     if (cap > c->cand_cap) {
         ++c->alloc_gen;
         dev_free(c->cand_i); dev_free(c->cand_j);
@@ -236,18 +255,17 @@ int ensure_query(tril_ctx *c, int64_t n, int32_t n_inst) {
         CHK(dev_alloc(&c->cand_j, cap));
         c->cand_cap = cap;
     }
-    return ensure_sort_scratch(c, n);
+    return ensure_sort_scratch(c, nv);
 }
 
 int check_beam(const tril_beam *b) {
     if (!b) return TRIL_E_INVAL;
     if (b->n < 0 || b->n >= kMaxN) return TRIL_E_INVAL;
-    if (b->n_inst < 1) return TRIL_E_INVAL;
+    if (b->n_inst < 1 || b->n_inst > kMaxComb) return TRIL_E_INVAL;
     if (b->n > 0 && (!b->x || !b->y || !b->z || !b->px || !b->py || !b->pz || !b->E || !b->w))
         return TRIL_E_INVAL;
     if (b->n_inst > 1) {
         if (!b->inst_off) return TRIL_E_INVAL;
-        if (b->n_inst > (1 << 24)) return TRIL_E_INVAL;
         if (b->inst_off[0] != 0 || b->inst_off[b->n_inst] != b->n) return TRIL_E_INVAL;
         for (int32_t m = 0; m < b->n_inst; ++m)
             if (b->inst_off[m + 1] < b->inst_off[m]) return TRIL_E_INVAL;
@@ -274,7 +292,7 @@ int upload_offsets(tril_ctx *c, const tril_beam *b, int64_t *d_off, std::vector<
     return TRIL_OK;
 }
 
-BeamDev view(const tril_beam *b, const int64_t *d_off) {
+BeamDev view(const tril_beam *b, const int64_t *d_off, int32_t m) {
     BeamDev v;
     v.n = b->n;
     v.x = b->x; v.y = b->y; v.z = b->z;
@@ -282,6 +300,7 @@ BeamDev view(const tril_beam *b, const int64_t *d_off) {
     v.E = b->E; v.w = b->w;
     v.n_inst = b->n_inst;
     v.inst_off = b->n_inst > 1 ? d_off : nullptr;
+    v.m = m;
     return v;
 }
 
@@ -304,66 +323,70 @@ int timing_pair(tril_ctx *c, hipStream_t st, std::vector<std::array<int, 2>> &ds
     return TRIL_OK;
 }
 
-// Kernels of one build on stream st (target view already set in c->tgt).
+// Kernels of one build on stream st (target view, with its step count m, in c->tgt;
+// the target statistics c->t_stats are current).
 int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
-    const int64_t n = c->nt;
+    const BeamDev &t = c->tgt;
+    const int64_t nv = (int64_t)t.m * t.n;
+    const int32_t n_comb = t.m * t.n_inst;
+    const KeyLayout kl = key_layout(n_comb);
     if (timed) CHK(timing_pair(c, st, c->ev_build, true));
-    launch_begin_step(c->d_cnt, 0, st);
-    launch_clear_inst(c->t_bounds, c->t_emax, c->t_wmax, c->t_inst, st);
-    launch_boxes(c->tgt, false, c->dt, c->sigma_up, nullptr, nullptr, c->t_box, c->t_part,
-                 c->t_bounds, c->t_emax, c->t_wmax, c->d_cnt, st);
+    launch_prologue(c->d_cnt, 0, t.m, st);
+    launch_boxes_keys(t, false, c->dt, c->sigma_up, c->t_stats, c->t_stats, kl, c->t_box, c->t_k32a,
+                      c->t_k64a, c->t_va, c->d_cnt, st);
     const uint32_t *rows = nullptr;
-    if (c->t_inst == 1) {
-        launch_morton_u32(c->t_box, n, c->t_bounds, c->t_k32a, c->t_va, st);
-        const bool alt = radix_sort_u32(c->t_k32a, c->t_va, c->t_k32b, c->t_vb, n, 30, c->ss,
-                                        &c->d_cnt->err, st);
+    int32_t *roots = n_comb > 1 ? c->inst_root : nullptr;
+    if (!kl.wide) {
+        const bool alt = radix_sort_u32(c->t_k32a, c->t_va, c->t_k32b, c->t_vb, nv, kl.key_bits,
+                                        c->ss, &c->d_cnt->err, st);
         const uint32_t *keys = alt ? c->t_k32b : c->t_k32a;
         rows = alt ? c->t_vb : c->t_va;
-        launch_karras_u32(keys, n, c->left, c->right, c->parent, c->range_lo, c->range_hi,
-                          c->split_right, c->nflags, st);
+        launch_karras_u32(keys, nv, kl.prefix_shift, c->left, c->right, c->parent, c->range_lo,
+                          c->range_hi, c->split_right, c->nflags, roots, st);
     } else {
-        launch_morton_u64(c->t_box, n, c->t_bounds, c->t_k64a, c->t_va, st);
-        const bool alt = radix_sort_u64(c->t_k64a, c->t_va, c->t_k64b, c->t_vb, n,
-                                        inst_key_bits(c->t_inst), c->ss, &c->d_cnt->err, st);
+        const bool alt = radix_sort_u64(c->t_k64a, c->t_va, c->t_k64b, c->t_vb, nv, kl.key_bits,
+                                        c->ss, &c->d_cnt->err, st);
         const unsigned long long *keys = alt ? c->t_k64b : c->t_k64a;
         rows = alt ? c->t_vb : c->t_va;
-        launch_karras_u64(keys, n, c->left, c->right, c->parent, c->range_lo, c->range_hi,
-                          c->split_right, c->nflags, c->inst_root, st);
+        launch_karras_u64(keys, nv, kl.prefix_shift, c->left, c->right, c->parent, c->range_lo,
+                          c->range_hi, c->split_right, c->nflags, roots, st);
     }
-    launch_inst_roots(c->d_t_off, c->t_inst, n, c->t_inst == 1, c->split_right, c->inst_root,
-                      c->inst_stop, st);
-    launch_refit(c->t_box, rows, n, c->left, c->right, c->parent, c->range_lo, c->range_hi,
+    launch_inst_roots(t, n_comb == 1, c->split_right, c->inst_root, c->inst_stop, st);
+    launch_refit(c->t_box, rows, nv, c->left, c->right, c->parent, c->range_lo, c->range_hi,
                  c->split_right, c->nflags, c->nodes, &c->d_cnt->err, st);
     if (timed) CHK(timing_pair(c, st, c->ev_build, false));
     HIPCHK(hipGetLastError());
     return TRIL_OK;
 }
 
+// Kernels of one collide (query view q with the same step count as the target; the
+// query statistics c->q_stats are current). Without sorting, the query order kept in
+// c->q_keep (one step's order, repeated per step) is used.
 int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStream_t st,
                     bool timed, bool sort_queries) {
-    const int64_t n = q.n;
-    launch_begin_step(c->d_cnt, 1, st);
+    const int64_t nv = (int64_t)q.m * q.n;
+    const int32_t n_comb = q.m * q.n_inst;
+    const KeyLayout kl = key_layout(n_comb);
     if (timed) CHK(timing_pair(c, st, c->ev_prep, true));
-    launch_clear_inst(c->q_bounds, nullptr, nullptr, q.n_inst, st);
-    launch_boxes(q, true, c->dt, c->sigma_up, c->t_emax, c->t_wmax, c->q_box, c->q_part,
-                 c->q_bounds, nullptr, nullptr, c->d_cnt, st);
-    if (sort_queries && n > 0) {
-        if (q.n_inst == 1) {
-            launch_morton_u32(c->q_box, n, c->q_bounds, c->q_k32a, c->q_va, st);
-            const bool alt = radix_sort_u32(c->q_k32a, c->q_va, c->q_k32b, c->q_vb, n, 30, c->ss,
-                                            &c->d_cnt->err, st);
-            c->q_order = (n <= 1) ? c->q_va : (alt ? c->q_vb : c->q_va);
-        } else {
-            launch_morton_u64(c->q_box, n, c->q_bounds, c->q_k64a, c->q_va, st);
-            const bool alt = radix_sort_u64(c->q_k64a, c->q_va, c->q_k64b, c->q_vb, n,
-                                            inst_key_bits(q.n_inst), c->ss, &c->d_cnt->err, st);
-            c->q_order = (n <= 1) ? c->q_va : (alt ? c->q_vb : c->q_va);
-        }
+    launch_prologue(c->d_cnt, 1, q.m, st);
+    launch_boxes_keys(q, true, c->dt, c->sigma_up, c->t_stats, c->q_stats, kl, c->q_box, c->q_k32a,
+                      c->q_k64a, c->q_va, c->d_cnt, st);
+    if (sort_queries && nv > 0) {
+        bool alt;
+        if (!kl.wide)
+            alt = radix_sort_u32(c->q_k32a, c->q_va, c->q_k32b, c->q_vb, nv, kl.key_bits, c->ss,
+                                 &c->d_cnt->err, st);
+        else
+            alt = radix_sort_u64(c->q_k64a, c->q_va, c->q_k64b, c->q_vb, nv, kl.key_bits, c->ss,
+                                 &c->d_cnt->err, st);
+        c->q_order = (nv <= 1) ? c->q_va : (alt ? c->q_vb : c->q_va);
+        c->q_order_len = nv;
     }
     if (timed) CHK(timing_pair(c, st, c->ev_prep, false));
     if (timed) CHK(timing_pair(c, st, c->ev_trav, true));
-    launch_traverse(c->nodes, c->nt, c->q_box, c->q_order, n, c->inst_root, c->inst_stop,
-                    c->cand_i, c->cand_j, c->cand_cap, c->d_cnt, c->block, st);
+    const int64_t ntv = (int64_t)c->tgt.m * c->tgt.n;
+    launch_traverse(c->nodes, ntv, c->q_box, c->q_order, c->q_order_len, nv, q.n, c->inst_root,
+                    c->inst_stop, c->cand_i, c->cand_j, c->cand_cap, c->d_cnt, c->block, st);
     if (timed) CHK(timing_pair(c, st, c->ev_trav, false));
     if (timed) CHK(timing_pair(c, st, c->ev_narrow, true));
     launch_narrow(q, c->tgt, c->dt, c->sigma_up, c->cand_i, c->cand_j, c->cand_cap, out, c->d_cnt,
@@ -375,12 +398,23 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
 
 bool need_query_sort(tril_ctx *c, const tril_beam *q) {
     if (!(c->flags & TRIL_SORT_QUERIES_ONCE)) return true;
-    return !(c->q_order && c->q_order_key == (const void *)q->x && c->q_order_n == q->n);
+    return !(c->q_order && c->q_order_key == (const void *)q->x && c->q_order_n == q->n &&
+             c->q_order_len == q->n);
 }
 
-void note_query_sorted(tril_ctx *c, const tril_beam *q) {
+// Remember the order of a single-step query sort; with TRIL_SORT_QUERIES_ONCE it is
+// copied to c->q_keep so that later batches can reuse it while overwriting the sort
+// buffers.
+int note_query_sorted(tril_ctx *c, const tril_beam *q, int32_t m, hipStream_t st) {
     c->q_order_key = (const void *)q->x;
     c->q_order_n = q->n;
+    if ((c->flags & TRIL_SORT_QUERIES_ONCE) && m == 1 && q->n > 0) {
+        HIPCHK(hipMemcpyAsync(c->q_keep, c->q_order, q->n * sizeof(uint32_t),
+                              hipMemcpyDeviceToDevice, st));
+        c->q_order = c->q_keep;
+        c->q_order_len = q->n;
+    }
+    return TRIL_OK;
 }
 
 int ensure_stats(tril_ctx *c, int64_t n_hits, int32_t n_steps) {
@@ -427,12 +461,23 @@ void fold_events(tril_ctx *c) {
     c->ms_acc[1] += sum_events(c, c->ev_prep);
     c->ms_acc[2] += sum_events(c, c->ev_trav);
     c->ms_acc[3] += sum_events(c, c->ev_narrow);
-    c->timed_steps += (int64_t)c->ev_trav.size();
+    c->timed_launches += (int64_t)c->ev_trav.size();
     c->ev_build.clear();
     c->ev_prep.clear();
     c->ev_trav.clear();
     c->ev_narrow.clear();
     c->ev_next = 0;
+}
+
+// Steps per launch for tril_run: the parameter if set, else as many as keep the
+// virtual element count of one launch within kBatchBudget.
+int32_t pick_batch(const tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t n_steps) {
+    const int64_t rows = std::max<int64_t>(std::max(t->n, q->n), 1);
+    int64_t m = c->step_batch > 0 ? c->step_batch : std::max<int64_t>(1, kBatchBudget / rows);
+    m = std::min<int64_t>(m, n_steps);
+    m = std::min<int64_t>(m, std::max<int64_t>(1, (kMaxN - 1) / rows));
+    m = std::min<int64_t>(m, std::max<int64_t>(1, kMaxComb / std::max(t->n_inst, 1)));
+    return (int32_t)std::max<int64_t>(m, 1);
 }
 
 }  // namespace
@@ -494,7 +539,7 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
     if (!out || !p) return TRIL_E_INVAL;
     *out = nullptr;
     if (!std::isfinite(p->dt) || !(p->dt > 0.0)) return TRIL_E_INVAL;
-    if (p->n_bins < 0 || p->cand_cap < 0) return TRIL_E_INVAL;
+    if (p->n_bins < 0 || p->cand_cap < 0 || p->step_batch < 0) return TRIL_E_INVAL;
     if (p->flags & ~(TRIL_TIMING | TRIL_SORT_QUERIES_ONCE)) return TRIL_E_NOTIMPL;
     if (p->n_bins > 0) {
         if (!p->bin_edges) return TRIL_E_INVAL;
@@ -513,6 +558,7 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
     c->n_bins = p->n_bins;
     c->cand_cap_param = p->cand_cap;
     c->block = blk;
+    c->step_batch = p->step_batch;
     c->sigma_up = host_sigma_max() * (1.0 + 1e-6);
     int r = TRIL_OK;
     auto fail = [&](int code) {
@@ -544,12 +590,12 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
 int tril_build(tril_ctx *c, const tril_beam *b, int32_t step) {
     if (!c || step < 0) return TRIL_E_INVAL;
     CHK(check_beam(b));
-    CHK(ensure_target(c, b->n, b->n_inst));
+    CHK(ensure_target(c, b->n, b->n_inst, b->n_inst));
     CHK(upload_offsets(c, b, c->d_t_off, c->h_t_off));
     c->nt = b->n;
-    c->t_inst = b->n_inst;
-    c->tgt = view(b, c->d_t_off);
+    c->tgt = view(b, c->d_t_off, 1);
     launch_set_step(c->d_cnt, step, c->st);
+    launch_beam_stats(c->tgt, c->t_spart, c->t_stats, c->d_cnt, c->st);
     CHK(enqueue_build(c, c->st, (c->flags & TRIL_TIMING) != 0));
     c->built = true;
     c->built_step = step;
@@ -561,13 +607,15 @@ int tril_collide(tril_ctx *c, const tril_beam *q, int32_t step, tril_pairs *out)
     if (!c) return TRIL_E_INVAL;
     CHK(check_beam(q));
     CHK(check_pairs(out));
-    if (!c->built || step != c->built_step || q->n_inst != c->t_inst) return TRIL_E_STATE;
-    CHK(ensure_query(c, q->n, q->n_inst));
+    if (!c->built || c->tgt.m != 1 || step != c->built_step || q->n_inst != c->tgt.n_inst)
+        return TRIL_E_STATE;
+    CHK(ensure_query(c, q->n, q->n_inst, q->n_inst));
     CHK(upload_offsets(c, q, c->d_q_off, c->h_q_off));
-    const BeamDev qv = view(q, c->d_q_off);
+    const BeamDev qv = view(q, c->d_q_off, 1);
     const bool sort = need_query_sort(c, q);
+    launch_beam_stats(qv, c->q_spart, c->q_stats, c->d_cnt, c->st);
     CHK(enqueue_collide(c, qv, *out, c->st, (c->flags & TRIL_TIMING) != 0, sort));
-    if (sort) note_query_sorted(c, q);
+    if (sort) CHK(note_query_sorted(c, q, 1, c->st));
     c->last_q = qv;
     c->max_nq = std::max(c->max_nq, q->n);
     return TRIL_OK;
@@ -582,25 +630,42 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     if (q->n_inst != t->n_inst) return TRIL_E_STATE;
     if (n_steps == 0) return TRIL_OK;
     if ((int64_t)k0 + n_steps - 1 > INT32_MAX) return TRIL_E_INVAL;
-    CHK(ensure_target(c, t->n, t->n_inst));
-    CHK(ensure_query(c, q->n, q->n_inst));
+    const int32_t m = pick_batch(c, t, q, n_steps);
+    // capacities for the largest batch first, so that nothing is reallocated later
+    CHK(ensure_target(c, (int64_t)m * t->n, (int64_t)m * t->n_inst, t->n_inst));
+    CHK(ensure_query(c, (int64_t)m * q->n, (int64_t)m * q->n_inst, q->n_inst));
     CHK(upload_offsets(c, t, c->d_t_off, c->h_t_off));
     CHK(upload_offsets(c, q, c->d_q_off, c->h_q_off));
     c->nt = t->n;
-    c->t_inst = t->n_inst;
-    c->tgt = view(t, c->d_t_off);
-    const BeamDev qv = view(q, c->d_q_off);
+    launch_beam_stats(view(t, c->d_t_off, 1), c->t_spart, c->t_stats, c->d_cnt, c->st);
+    launch_beam_stats(view(q, c->d_q_off, 1), c->q_spart, c->q_stats, c->d_cnt, c->st);
     int32_t k = k0;
     int32_t left = n_steps;
-    // with a query order kept from the first step, that step runs eagerly first
-    if (need_query_sort(c, q) && (c->flags & TRIL_SORT_QUERIES_ONCE)) {
+    // with a query order kept from the first step, that step runs alone first
+    if ((c->flags & TRIL_SORT_QUERIES_ONCE) && need_query_sort(c, q)) {
         CHK(tril_build(c, t, k));
         CHK(tril_collide(c, q, k, out));
         ++k;
         --left;
     }
-    if (left > 0) {
+    const bool timed = (c->flags & TRIL_TIMING) != 0;
+    while (left > 0) {
+        const int32_t mb = std::min(m, left);
         const bool sort = need_query_sort(c, q);
+        c->tgt = view(t, c->d_t_off, mb);
+        const BeamDev qv = view(q, c->d_q_off, mb);
+        if (timed || mb != m) {
+            // eager batch (per-phase events, or the shorter last batch)
+            launch_set_step(c->d_cnt, k, c->st);
+            CHK(enqueue_build(c, c->st, timed));
+            CHK(enqueue_collide(c, qv, *out, c->st, timed, sort));
+            if (sort) CHK(note_query_sorted(c, q, mb, c->st));
+            k += mb;
+            left -= mb;
+            continue;
+        }
+        // full batches: one captured graph, replayed; the step index lives on the device
+        const int32_t n_rep = left / m;
         std::vector<const void *> key = {t->x, t->y, t->z, t->px, t->py, t->pz, t->E, t->w,
                                          q->x, q->y, q->z, q->px, q->py, q->pz, q->E, q->w,
                                          out->i, out->j, out->step, out->count,
@@ -608,6 +673,8 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
                                          (const void *)(intptr_t)t->n_inst,
                                          (const void *)(intptr_t)out->cap,
                                          (const void *)(intptr_t)sort, c->q_order,
+                                         (const void *)(intptr_t)c->q_order_len,
+                                         (const void *)(intptr_t)m,
                                          (const void *)(uintptr_t)c->alloc_gen};
         if (!c->gexec || key != c->gkey) {
             if (c->gexec) {
@@ -618,7 +685,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
             HIPCHK(hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
             int r1 = enqueue_build(c, c->gst, false);
             int r2 = r1 == TRIL_OK ? enqueue_collide(c, qv, *out, c->gst, false, sort) : r1;
-            launch_advance_step(c->d_cnt, c->gst);
+            launch_advance_step(c->d_cnt, m, c->gst);
             hipError_t e = hipStreamEndCapture(c->gst, &g);
             if (r2 != TRIL_OK) {
                 if (g) (void)hipGraphDestroy(g);
@@ -636,15 +703,17 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
         launch_set_step(c->d_cnt, k, c->st);
         HIPCHK(hipEventRecord(c->ev_join_a, c->st));
         HIPCHK(hipStreamWaitEvent(c->gst, c->ev_join_a, 0));
-        for (int32_t s = 0; s < left; ++s) HIPCHK(hipGraphLaunch(c->gexec, c->gst));
+        for (int32_t r = 0; r < n_rep; ++r) HIPCHK(hipGraphLaunch(c->gexec, c->gst));
         HIPCHK(hipEventRecord(c->ev_join_b, c->gst));
         HIPCHK(hipStreamWaitEvent(c->st, c->ev_join_b, 0));
-        if (sort) note_query_sorted(c, q);
+        if (sort) CHK(note_query_sorted(c, q, m, c->st));
+        k += n_rep * m;
+        left -= n_rep * m;
     }
     c->built = true;
     c->built_step = k0 + n_steps - 1;
     c->max_step = std::max(c->max_step, c->built_step);
-    c->last_q = qv;
+    c->last_q = view(q, c->d_q_off, 1);
     c->max_nq = std::max(c->max_nq, q->n);
     return TRIL_OK;
 }
@@ -656,7 +725,7 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
         return TRIL_E_INVAL;
     HIPCHK(hipStreamSynchronize(c->st));
     HIPCHK(hipMemcpy(c->h_cnt, c->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost));
-    const DevCounters h = *c->h_cnt;
+    const DevCounters &h = *c->h_cnt;
     out->n_candidates = (int64_t)h.cand_total;
     int64_t visits = 0, queries = 0;
     for (int k = 0; k < kCounterSlots; ++k) {
@@ -668,23 +737,24 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     out->n_sigma_evals = (int64_t)h.sigma_evals;
     out->n_builds = (int64_t)h.builds;
     out->n_collides = (int64_t)h.collides;
+    const unsigned int err = h.err;
     fold_events(c);
     out->ms_build = c->ms_acc[0];
     out->ms_query_prep = c->ms_acc[1];
     out->ms_traverse = c->ms_acc[2];
     out->ms_narrow = c->ms_acc[3];
-    out->n_timed_steps = c->timed_steps;
+    out->n_timed_launches = c->timed_launches;
     out->n_pairs = 0;
     out->n_hits = 0;
     out->yield = 0.0;
-    if (h.err & kErrData) return TRIL_E_DATA;
-    if (h.err & kErrSpin) return TRIL_E_INTERNAL;
-    if (h.err & kErrCandOverflow) return TRIL_E_OVERFLOW;
+    if (err & kErrData) return TRIL_E_DATA;
+    if (err & kErrSpin) return TRIL_E_INTERNAL;
+    if (err & kErrCandOverflow) return TRIL_E_OVERFLOW;
     if (!p) return TRIL_OK;
     int64_t n_hits = 0;
     HIPCHK(hipMemcpy(&n_hits, p->count, sizeof(int64_t), hipMemcpyDeviceToHost));
     out->n_hits = n_hits;
-    if (n_hits > p->cap || (h.err & kErrPairOverflow)) return TRIL_E_OVERFLOW;
+    if (n_hits > p->cap || (err & kErrPairOverflow)) return TRIL_E_OVERFLOW;
     if (n_hits > 0 && (!c->built || c->last_q.n <= 0)) return TRIL_E_STATE;
     const int step_bits = std::max(1, bits_for((uint64_t)std::max(c->max_step, 0)));
     const int pair_bits = bits_for((uint64_t)std::max<int64_t>(c->max_nq, 1) *
@@ -711,8 +781,9 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
                          hipMemcpyDeviceToHost));
         for (int32_t k = 0; k < nsc; ++k) out->step_counts[k] = (int64_t)sc[k];
     }
-    HIPCHK(hipMemcpy(c->h_cnt, c->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost));
-    if (c->h_cnt->err & kErrSpin) return TRIL_E_INTERNAL;
+    unsigned int err2 = 0;
+    HIPCHK(hipMemcpy(&err2, &c->d_cnt->err, sizeof(err2), hipMemcpyDeviceToHost));
+    if (err2 & kErrSpin) return TRIL_E_INTERNAL;
     return TRIL_OK;
 }
 
@@ -724,7 +795,7 @@ int tril_reset_counters(tril_ctx *c) {
     c->ev_build.clear(); c->ev_prep.clear(); c->ev_trav.clear(); c->ev_narrow.clear();
     c->ev_next = 0;
     for (double &m : c->ms_acc) m = 0.0;
-    c->timed_steps = 0;
+    c->timed_launches = 0;
     c->max_step = c->built ? c->built_step : -1;
     return TRIL_OK;
 }
@@ -735,12 +806,11 @@ void tril_destroy(tril_ctx *c) {
     if (c->gst) (void)hipStreamSynchronize(c->gst);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     free_target(c);
-    dev_free(c->d_t_off); dev_free(c->t_bounds); dev_free(c->t_emax); dev_free(c->t_wmax);
-    dev_free(c->inst_root); dev_free(c->inst_stop);
-    dev_free(c->q_box); dev_free(c->q_part); dev_free(c->q_k32a); dev_free(c->q_k32b);
+    dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->inst_root); dev_free(c->inst_stop);
+    dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
     dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
-    dev_free(c->d_q_off);
-    dev_free(c->q_bounds); dev_free(c->cand_i); dev_free(c->cand_j);
+    dev_free(c->q_keep); dev_free(c->d_q_off); dev_free(c->q_stats); dev_free(c->cand_i);
+    dev_free(c->cand_j);
     dev_free(c->ss.hist); dev_free(c->ss.tile_ctr); dev_free(c->ss.status);
     StatsScratch &s = c->sst;
     dev_free(s.keys); dev_free(s.keys_alt); dev_free(s.vals); dev_free(s.vals_alt);
@@ -756,15 +826,16 @@ void tril_destroy(tril_ctx *c) {
     delete c;
 }
 
+}  // extern "C"
+
 // ------------------------------------------------------------- inspection ABI
 
-int tril_dbg_sort_u32(uint32_t *keys, uint32_t *vals, int64_t n, int key_bits, void *stream) {
-    if (n < 0 || n >= kMaxN || key_bits < 1 || key_bits > 32) return TRIL_E_INVAL;
-    if (n > 0 && (!keys || !vals)) return TRIL_E_INVAL;
-    if (n <= 1) return TRIL_OK;
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+namespace {
+template <typename K, typename Sorter>
+int dbg_sort(K *keys, uint32_t *vals, int64_t n, hipStream_t st, Sorter sorter) {
     SortScratch ss;
-    uint32_t *ka = nullptr, *va = nullptr;
+    K *ka = nullptr;
+    uint32_t *va = nullptr;
     unsigned int *err = nullptr;
     int r = TRIL_OK;
     if ((r = dev_alloc(&ss.hist, 8 * 256)) == TRIL_OK && (r = dev_alloc(&ss.tile_ctr, 8)) == TRIL_OK &&
@@ -773,9 +844,9 @@ int tril_dbg_sort_u32(uint32_t *keys, uint32_t *vals, int64_t n, int key_bits, v
         (r = dev_alloc(&err, 1)) == TRIL_OK) {
         hipError_t e = hipMemsetAsync(err, 0, sizeof(unsigned int), st);
         if (e == hipSuccess) {
-            const bool alt = radix_sort_u32(keys, vals, ka, va, n, key_bits, ss, err, st);
+            const bool alt = sorter(keys, vals, ka, va, ss, err);
             if (alt) {
-                e = hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+                e = hipMemcpyAsync(keys, ka, n * sizeof(K), hipMemcpyDeviceToDevice, st);
                 if (e == hipSuccess)
                     e = hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
             }
@@ -790,40 +861,33 @@ int tril_dbg_sort_u32(uint32_t *keys, uint32_t *vals, int64_t n, int key_bits, v
     dev_free(ka); dev_free(va); dev_free(err);
     return r;
 }
+}  // namespace
+
+extern "C" {
+
+int tril_dbg_sort_u32(uint32_t *keys, uint32_t *vals, int64_t n, int key_bits, void *stream) {
+    if (n < 0 || n >= kMaxN || key_bits < 1 || key_bits > 32) return TRIL_E_INVAL;
+    if (n > 0 && (!keys || !vals)) return TRIL_E_INVAL;
+    if (n <= 1) return TRIL_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return dbg_sort(keys, vals, n, st,
+                    [&](uint32_t *k, uint32_t *v, uint32_t *ka, uint32_t *va, SortScratch &ss,
+                        unsigned int *err) {
+                        return radix_sort_u32(k, v, ka, va, n, key_bits, ss, err, st);
+                    });
+}
 
 int tril_dbg_sort_u64(uint64_t *keys, uint32_t *vals, int64_t n, int key_bits, void *stream) {
     if (n < 0 || n >= kMaxN || key_bits < 1 || key_bits > 64) return TRIL_E_INVAL;
     if (n > 0 && (!keys || !vals)) return TRIL_E_INVAL;
     if (n <= 1) return TRIL_OK;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    SortScratch ss;
-    unsigned long long *ka = nullptr;
-    uint32_t *va = nullptr;
-    unsigned int *err = nullptr;
-    unsigned long long *k = reinterpret_cast<unsigned long long *>(keys);
-    int r = TRIL_OK;
-    if ((r = dev_alloc(&ss.hist, 8 * 256)) == TRIL_OK && (r = dev_alloc(&ss.tile_ctr, 8)) == TRIL_OK &&
-        (r = dev_alloc(&ss.status, sort_status_words(n, 8))) == TRIL_OK &&
-        (r = dev_alloc(&ka, (size_t)n)) == TRIL_OK && (r = dev_alloc(&va, (size_t)n)) == TRIL_OK &&
-        (r = dev_alloc(&err, 1)) == TRIL_OK) {
-        hipError_t e = hipMemsetAsync(err, 0, sizeof(unsigned int), st);
-        if (e == hipSuccess) {
-            const bool alt = radix_sort_u64(k, vals, ka, va, n, key_bits, ss, err, st);
-            if (alt) {
-                e = hipMemcpyAsync(k, ka, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, st);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
-            }
-        }
-        if (e == hipSuccess) e = hipGetLastError();
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        unsigned int h_err = 0;
-        if (e == hipSuccess) e = hipMemcpy(&h_err, err, sizeof(h_err), hipMemcpyDeviceToHost);
-        r = e != hipSuccess ? hip_fail(e) : (h_err ? TRIL_E_INTERNAL : TRIL_OK);
-    }
-    dev_free(ss.hist); dev_free(ss.tile_ctr); dev_free(ss.status);
-    dev_free(ka); dev_free(va); dev_free(err);
-    return r;
+    unsigned long long *k64 = reinterpret_cast<unsigned long long *>(keys);
+    return dbg_sort(k64, vals, n, st,
+                    [&](unsigned long long *k, uint32_t *v, unsigned long long *ka, uint32_t *va,
+                        SortScratch &ss, unsigned int *err) {
+                        return radix_sort_u64(k, v, ka, va, n, key_bits, ss, err, st);
+                    });
 }
 
 int tril_dbg_morton(const float *boxes, int64_t n, const float *bounds, uint32_t *keys,
@@ -868,22 +932,24 @@ int tril_dbg_tree(tril_ctx *c, void *nodes, int64_t cap_nodes, int64_t *n_nodes,
     if (!c || !n_nodes) return TRIL_E_INVAL;
     if (!c->built) return TRIL_E_STATE;
     HIPCHK(hipStreamSynchronize(c->st));
-    const int64_t nn = c->nt > 0 ? 2 * c->nt - 1 : 0;
+    const int64_t nv = (int64_t)c->tgt.m * c->tgt.n;
+    const int64_t nn = nv > 0 ? 2 * nv - 1 : 0;
     *n_nodes = nn;
     if (nn > cap_nodes) return TRIL_E_OVERFLOW;
     if (nn > 0) {
         if (!nodes) return TRIL_E_INVAL;
         HIPCHK(hipMemcpy(nodes, c->nodes, nn * sizeof(Node), hipMemcpyDeviceToHost));
     }
-    if (roots) HIPCHK(hipMemcpy(roots, c->inst_root, c->t_inst * sizeof(int32_t), hipMemcpyDeviceToHost));
-    if (stops) HIPCHK(hipMemcpy(stops, c->inst_stop, c->t_inst * sizeof(int32_t), hipMemcpyDeviceToHost));
+    const size_t n_comb = (size_t)c->tgt.m * c->tgt.n_inst;
+    if (roots) HIPCHK(hipMemcpy(roots, c->inst_root, n_comb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (stops) HIPCHK(hipMemcpy(stops, c->inst_stop, n_comb * sizeof(int32_t), hipMemcpyDeviceToHost));
     return TRIL_OK;
 }
 
 int tril_dbg_boxes(tril_ctx *c, int which, void *boxes, int64_t cap, int64_t *n) {
     if (!c || !n || (which != 0 && which != 1)) return TRIL_E_INVAL;
     HIPCHK(hipStreamSynchronize(c->st));
-    const int64_t nn = which == 0 ? c->nt : c->last_q.n;
+    const int64_t nn = which == 0 ? (int64_t)c->tgt.m * c->tgt.n : c->last_q.n;
     *n = nn;
     if (nn > cap) return TRIL_E_OVERFLOW;
     if (nn > 0) {

@@ -1,5 +1,5 @@
-// Per-step hierarchy over swept photon boxes: box kernel, Morton keys, Karras
-// emission, instance roots and the atomic bottom-up refit.
+// Per-step hierarchy over swept photon boxes: beam statistics, box + Morton key
+// kernel, Karras emission, instance roots and the atomic bottom-up refit.
 //
 // The paper's hierarchy (Sec. 2.1) uses axis-aligned boxes enlarged by the
 // distance a particle travels in one step, so that collisions are found before
@@ -11,6 +11,12 @@
 // arrive at a node writing the union. Each node also gets a rope: the next node
 // in depth-first order after its subtree, which lets the traversal run without
 // a stack.
+//
+// One launch may cover several consecutive time steps of a beam. Photon row i at
+// step offset s is the virtual element e = s n + i; it belongs to the combined
+// instance c = s n_inst + (instance of row i). Keys carry c above the Morton
+// bits, so every (step, instance) pair gets its own subtree with its own root, and
+// a query only descends the subtree of its own step and instance.
 #include <cfloat>
 #include <cmath>
 
@@ -32,7 +38,7 @@ __device__ __forceinline__ float f32_up(double d) {
     return f;
 }
 
-// Order-preserving map float -> uint32 (for atomic min/max of floats).
+// Order-preserving maps float -> uint32 and double -> uint64 (for min/max reductions).
 __device__ __forceinline__ uint32_t f2ord(float f) {
     uint32_t u = __float_as_uint(f);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
@@ -40,6 +46,14 @@ __device__ __forceinline__ uint32_t f2ord(float f) {
 __device__ __forceinline__ float ord2f(uint32_t u) {
     u = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
     return __uint_as_float(u);
+}
+__device__ __forceinline__ unsigned long long d2ord(double d) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(d);
+    return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+__device__ __forceinline__ double ord2d(unsigned long long u) {
+    u = (u >> 63) ? (u & ~(1ull << 63)) : ~u;
+    return __longlong_as_double((long long)u);
 }
 
 __device__ __forceinline__ int32_t find_inst(const int64_t *off, int32_t n_inst, int64_t i) {
@@ -52,6 +66,32 @@ __device__ __forceinline__ int32_t find_inst(const int64_t *off, int32_t n_inst,
     return lo;
 }
 
+// Step offset, row, base instance and combined instance of virtual element e.
+struct VIdx {
+    int32_t s;
+    int64_t i;
+    int32_t mi;
+    int32_t c;
+};
+__device__ __forceinline__ VIdx vdecode(const BeamDev &b, int64_t e) {
+    VIdx v;
+    v.s = b.m > 1 ? (int32_t)(e / b.n) : 0;
+    v.i = e - (int64_t)v.s * b.n;
+    v.mi = b.n_inst > 1 ? find_inst(b.inst_off, b.n_inst, v.i) : 0;
+    v.c = v.s * b.n_inst + v.mi;
+    return v;
+}
+
+// First virtual element and count of combined instance c.
+__device__ __forceinline__ void comb_range(const BeamDev &b, int32_t c, int64_t &a, int64_t &cnt) {
+    const int32_t s = c / b.n_inst;
+    const int32_t mi = c - s * b.n_inst;
+    const int64_t o0 = b.n_inst > 1 ? b.inst_off[mi] : 0;
+    const int64_t o1 = b.n_inst > 1 ? b.inst_off[mi + 1] : b.n;
+    a = (int64_t)s * b.n + o0;
+    cnt = o1 - o0;
+}
+
 __device__ __forceinline__ uint32_t expand10(uint32_t v) {
     v &= 1023u;
     v = (v | (v << 16)) & 0x030000FFu;
@@ -61,41 +101,40 @@ __device__ __forceinline__ uint32_t expand10(uint32_t v) {
     return v;
 }
 
-__global__ void k_clear_inst(uint32_t *bounds, unsigned long long *emax, unsigned long long *wmax,
-                             int32_t n_inst) {
-    int32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n_inst) return;
+// 30-bit Morton code of point c in the box [lo, hi] (10 bits per axis, x most
+// significant within each level; coordinates outside the box are clamped).
+__device__ __forceinline__ uint32_t morton30(const float c[3], const float lo[3], const float hi[3]) {
+    uint32_t q[3];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-        bounds[6 * m + a] = 0xFFFFFFFFu;   // running min (ordered)
-        bounds[6 * m + 3 + a] = 0u;        // running max (ordered)
+        const float ext = hi[a] - lo[a];
+        const float sc = ext > 0.0f ? 1023.0f / ext : 0.0f;
+        float v = (c[a] - lo[a]) * sc;
+        v = fminf(fmaxf(v, 0.0f), 1023.0f);  // NaN -> 0
+        q[a] = (uint32_t)v;
     }
-    if (emax) emax[m] = 0ull;
-    if (wmax) wmax[m] = 0ull;
+    return (expand10(q[0]) << 2) | (expand10(q[1]) << 1) | expand10(q[2]);
 }
 
-__global__ void k_set_step(DevCounters *c, int32_t step) { c->step = (unsigned)step; }
-__global__ void k_advance_step(DevCounters *c) { c->step += 1u; }
-
-// kind 0: build, kind 1: collide (resets the per-step candidate counter)
-__global__ void k_begin_step(DevCounters *c, int kind) {
+// Per-batch bookkeeping. kind 0: build (counts m steps built); kind 1: collide
+// (counts m steps, resets the candidate counter of the batch).
+__global__ void k_prologue(DevCounters *c, int kind, int32_t m) {
     if (kind == 0) {
-        c->builds += 1ull;
+        c->builds += (unsigned long long)m;
     } else {
-        c->collides += 1ull;
+        c->collides += (unsigned long long)m;
         c->cand_step = 0ull;
     }
 }
+
+__global__ void k_set_step(DevCounters *c, int32_t step) { c->step = (unsigned)step; }
+__global__ void k_advance_step(DevCounters *c, int32_t m) { c->step += (unsigned)m; }
 
 __global__ void k_fill_i64(int64_t *p, int64_t v, int64_t n) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
-// Swept box of each photon over [t_k, t_k + dt], rounded outward to FP32.
-// Query photons are padded by an upper bound of their collision radius with any
-// photon of the same target instance: r^2 = sqrt(w_i w_j) sigma / pi <=
-// sqrt(w_i w_max) sigma_up / pi. A query photon that cannot exceed threshold with the
-// most energetic target photon (s <= E_i E_max / m_e^2 <= 1) is tagged -1.
 template <typename T>
 __device__ __forceinline__ T wave_min(T v) {
 #pragma unroll
@@ -115,106 +154,198 @@ __device__ __forceinline__ T wave_max(T v) {
     return v;
 }
 
-constexpr int kBoxThreads = 256;
-constexpr int kBoxItems = 4;
-constexpr int kBoxSpan = kBoxThreads * kBoxItems;  // photons per block
+// ------------------------------------------------------------ beam statistics
 
-// Running reduction of one instance slot: centroid bounds (ordered floats) and,
-// for the target, the largest energy and weight (FP64 bit patterns, >= 0).
-struct Red {
-    uint32_t mn[3], mx[3];
-    unsigned long long e, w;
-};
+constexpr int kStatThreads = 256;
+constexpr int kStatItems = 4;
+constexpr int kStatSpan = kStatThreads * kStatItems;  // rows per block
 
-__device__ __forceinline__ void red_init(Red &r) {
-    for (int a = 0; a < 3; ++a) {
-        r.mn[a] = 0xFFFFFFFFu;
-        r.mx[a] = 0u;
+__device__ __forceinline__ void st_init(InstStats &r) {
+    for (int a = 0; a < 6; ++a) {
+        r.mn[a] = ~0ull;
+        r.mx[a] = 0ull;
     }
-    r.e = 0ull;
-    r.w = 0ull;
+    r.emax = 0ull;
+    r.wmax = 0ull;
 }
 
-__device__ __forceinline__ void red_wave(Red &r) {
-    for (int a = 0; a < 3; ++a) {
-        r.mn[a] = wave_min(r.mn[a]);
-        r.mx[a] = wave_max(r.mx[a]);
-    }
-    r.e = wave_max(r.e);
-    r.w = wave_max(r.w);
-}
-
-__device__ __forceinline__ void red_merge(Red &r, const Red &o) {
-    for (int a = 0; a < 3; ++a) {
+__device__ __forceinline__ void st_merge(InstStats &r, const InstStats &o) {
+    for (int a = 0; a < 6; ++a) {
         r.mn[a] = o.mn[a] < r.mn[a] ? o.mn[a] : r.mn[a];
         r.mx[a] = o.mx[a] > r.mx[a] ? o.mx[a] : r.mx[a];
     }
-    r.e = o.e > r.e ? o.e : r.e;
-    r.w = o.w > r.w ? o.w : r.w;
+    r.emax = o.emax > r.emax ? o.emax : r.emax;
+    r.wmax = o.wmax > r.wmax ? o.wmax : r.wmax;
 }
 
-__device__ __forceinline__ void red_atomic(uint32_t *bounds, unsigned long long *emax,
-                                           unsigned long long *wmax, int32_t m, const Red &r) {
-    uint32_t *bb = bounds + 6 * m;
-    for (int a = 0; a < 3; ++a) {
-        if (r.mn[a] != 0xFFFFFFFFu) atomicMin(bb + a, r.mn[a]);
-        if (r.mx[a] != 0u) atomicMax(bb + 3 + a, r.mx[a]);
+__device__ __forceinline__ void st_wave(InstStats &r) {
+    for (int a = 0; a < 6; ++a) {
+        r.mn[a] = wave_min(r.mn[a]);
+        r.mx[a] = wave_max(r.mx[a]);
     }
-    if (emax && r.e) atomicMax(emax + m, r.e);
-    if (wmax && r.w) atomicMax(wmax + m, r.w);
+    r.emax = wave_max(r.emax);
+    r.wmax = wave_max(r.wmax);
 }
 
-// Swept box of each photon over [t_k, t_k + dt], rounded outward to FP32, plus the
-// per-instance reductions the next kernels need. Each block covers kBoxSpan photons
-// and writes two partial reductions (for the instances of its first and last photon)
-// that k_fold_bounds combines; a photon whose instance lies strictly inside one block
-// (instances smaller than a block) adds to the instance totals with atomics.
-__global__ void __launch_bounds__(kBoxThreads) k_boxes(BeamDev b, int query, double dt,
-                                                       double sigma_up,
-                                                       const unsigned long long *__restrict__ t_emax,
-                                                       const unsigned long long *__restrict__ t_wmax,
-                                                       PBox *__restrict__ out,
-                                                       BoundsPartial *__restrict__ partials,
-                                                       uint32_t *bounds, unsigned long long *emax,
-                                                       unsigned long long *wmax, DevCounters *c) {
-    __shared__ Red s_red[kBoxThreads / 64][2];
-    const int64_t base = blockIdx.x * (int64_t)kBoxSpan;
-    const int64_t last = (base + kBoxSpan < b.n ? base + kBoxSpan : b.n) - 1;
+__device__ __forceinline__ void st_atomic(InstStats *dst, const InstStats &r) {
+    for (int a = 0; a < 6; ++a) {
+        if (r.mn[a] != ~0ull) atomicMin(&dst->mn[a], r.mn[a]);
+        if (r.mx[a] != 0ull) atomicMax(&dst->mx[a], r.mx[a]);
+    }
+    if (r.emax) atomicMax(&dst->emax, r.emax);
+    if (r.wmax) atomicMax(&dst->wmax, r.wmax);
+}
+
+__global__ void k_stats_clear(InstStats *stats, int32_t n_inst) {
+    const int32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n_inst) return;
+    InstStats r;
+    st_init(r);
+    stats[m] = r;
+}
+
+// Each block reduces kStatSpan rows into two partials (for the instances of its first
+// and last row); rows of an instance lying strictly inside one block (instances
+// smaller than a block) go to the instance totals with atomics. Invalid rows
+// (non-finite values, E <= 0, w < 0) raise the data error flag and are left out.
+__global__ void __launch_bounds__(kStatThreads) k_beam_stats(BeamDev b, StatsPartial *partials,
+                                                            InstStats *stats, DevCounters *c) {
+    __shared__ InstStats s_red[kStatThreads / 64][2];
+    const int64_t base = blockIdx.x * (int64_t)kStatSpan;
+    const int64_t last = (base + kStatSpan < b.n ? base + kStatSpan : b.n) - 1;
     const int32_t m_lo = b.n_inst > 1 ? find_inst(b.inst_off, b.n_inst, base) : 0;
     const int32_t m_hi = b.n_inst > 1 ? find_inst(b.inst_off, b.n_inst, last) : 0;
-    Red r0, r1;
-    red_init(r0);
-    red_init(r1);
-    const double t = (double)c->step * dt;
-    for (int it = 0; it < kBoxItems; ++it) {
-        const int64_t i = base + it * kBoxThreads + threadIdx.x;
+    InstStats r0, r1;
+    st_init(r0);
+    st_init(r1);
+    for (int it = 0; it < kStatItems; ++it) {
+        const int64_t i = base + it * kStatThreads + threadIdx.x;
         if (i >= b.n) break;
-        const int32_t m = b.n_inst > 1 ? find_inst(b.inst_off, b.n_inst, i) : 0;
         const double E = b.E[i], w = b.w[i];
         const double px = b.px[i], py = b.py[i], pz = b.pz[i];
         const double x = b.x[i], y = b.y[i], z = b.z[i];
         const bool ok = isfinite(E) && isfinite(w) && isfinite(px) && isfinite(py) &&
                         isfinite(pz) && isfinite(x) && isfinite(y) && isfinite(z) && E > 0.0 &&
                         w >= 0.0;
-        PBox o;
-        o.pad = m;
         if (!ok) {
             atomicOr(&c->err, kErrData);
-            o.lox = o.loy = o.loz = INFINITY;
-            o.hix = o.hiy = o.hiz = -INFINITY;
-            o.tag = -1;
-            out[i] = o;
             continue;
         }
+        const double v[6] = {x, y, z, px / E, py / E, pz / E};
+        InstStats one;
+        for (int a = 0; a < 6; ++a) {
+            one.mn[a] = d2ord(v[a]);
+            one.mx[a] = one.mn[a];
+        }
+        one.emax = (unsigned long long)__double_as_longlong(E);
+        one.wmax = (unsigned long long)__double_as_longlong(w);
+        const int32_t m = b.n_inst > 1 ? find_inst(b.inst_off, b.n_inst, i) : 0;
+        if (m == m_lo) st_merge(r0, one);
+        else if (m == m_hi) st_merge(r1, one);
+        else st_atomic(stats + m, one);
+    }
+    st_wave(r0);
+    st_wave(r1);
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_red[wave][0] = r0;
+        s_red[wave][1] = r1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kStatThreads / 64; ++w) {
+            st_merge(r0, s_red[w][0]);
+            st_merge(r1, s_red[w][1]);
+        }
+        StatsPartial p0, p1;
+        p0.s = r0;
+        p0.inst = m_lo;
+        p0.pad = 0;
+        p1.s = r1;
+        p1.inst = (m_hi != m_lo) ? m_hi : -1;
+        p1.pad = 0;
+        partials[2 * blockIdx.x] = p0;
+        partials[2 * blockIdx.x + 1] = p1;
+    }
+}
+
+// One workgroup per instance folds that instance's block partials into its totals.
+__global__ void __launch_bounds__(256) k_fold_stats(const StatsPartial *__restrict__ partials,
+                                                    BeamDev b, InstStats *stats) {
+    __shared__ InstStats s_red[4];
+    const int32_t m = blockIdx.x;
+    const int64_t a = b.n_inst > 1 ? b.inst_off[m] : 0;
+    const int64_t e = b.n_inst > 1 ? b.inst_off[m + 1] : b.n;
+    InstStats r;
+    st_init(r);
+    if (e > a) {
+        const int64_t b0 = a / kStatSpan, b1 = (e - 1) / kStatSpan;
+        for (int64_t blk = b0 + threadIdx.x; blk <= b1; blk += blockDim.x) {
+            for (int sl = 0; sl < 2; ++sl) {
+                const StatsPartial &p = partials[2 * blk + sl];
+                if (p.inst == m) st_merge(r, p.s);
+            }
+        }
+    }
+    st_wave(r);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / 64); ++w) st_merge(r, s_red[w]);
+        st_atomic(stats + m, r);
+    }
+}
+
+// ------------------------------------------------------------ boxes and keys
+
+// Swept box of each virtual element over its step window [t_k, t_k + dt], rounded
+// outward to FP32, and its sort key. Query photons are padded by an upper bound of
+// their collision radius with any photon of the same target instance:
+// r^2 = sqrt(w_i w_j) sigma / pi <= sqrt(w_i w_max) sigma_up / pi. A query photon that
+// cannot exceed threshold with the most energetic target photon of its instance
+// (s <= E_i E_max / m_e^2 <= 1) is tagged -1.
+// Morton quantisation box of instance m at step k: the box centre is x0 + tau u with
+// tau = t_k + dt/2 >= 0, so [min x0 + tau min u, max x0 + tau max u] per axis contains
+// every centre (clamping absorbs rounding).
+template <bool kWide>
+__global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, double dt,
+                                                    double sigma_up,
+                                                    const InstStats *__restrict__ t_stats,
+                                                    const InstStats *__restrict__ self_stats,
+                                                    KeyLayout kl, PBox *__restrict__ out,
+                                                    uint32_t *__restrict__ keys32,
+                                                    unsigned long long *__restrict__ keys64,
+                                                    uint32_t *__restrict__ vals,
+                                                    const DevCounters *__restrict__ c) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nv = (int64_t)b.m * b.n;
+    if (e >= nv) return;
+    const VIdx v = vdecode(b, e);
+    const int64_t i = v.i;
+    const double E = b.E[i], w = b.w[i];
+    const double px = b.px[i], py = b.py[i], pz = b.pz[i];
+    const double x = b.x[i], y = b.y[i], z = b.z[i];
+    const bool ok = isfinite(E) && isfinite(w) && isfinite(px) && isfinite(py) && isfinite(pz) &&
+                    isfinite(x) && isfinite(y) && isfinite(z) && E > 0.0 && w >= 0.0;
+    const double t = (double)(c->step + (unsigned)v.s) * dt;
+    PBox o;
+    o.pad = v.c;
+    float cen[3] = {0.f, 0.f, 0.f};
+    if (!ok) {
+        o.lox = o.loy = o.loz = INFINITY;
+        o.hix = o.hiy = o.hiz = -INFINITY;
+        o.tag = -1;
+    } else {
         const double ux = px / E, uy = py / E, uz = pz / E;
         // position at t_k exactly as the narrow phase forms it, and one step later
         const double ax = x + t * ux, ay = y + t * uy, az = z + t * uz;
         const double bx = ax + dt * ux, by = ay + dt * uy, bz = az + dt * uz;
         double pad = 0.0;
-        int32_t tag = m;
+        int32_t tag = v.c;
         if (query) {
-            const double emax_t = __longlong_as_double((long long)t_emax[m]);
-            const double wmax_t = __longlong_as_double((long long)t_wmax[m]);
+            const InstStats &ts = t_stats[v.mi];
+            const double emax_t = __longlong_as_double((long long)ts.emax);
+            const double wmax_t = __longlong_as_double((long long)ts.wmax);
             const double smax = (E * emax_t) / (kMe * kMe);
             if (!(smax > 1.0)) tag = -1;
             pad = sqrt((sqrt(w * wmax_t) * sigma_up) / M_PI) * (1.0 + 1e-6);
@@ -227,108 +358,27 @@ __global__ void __launch_bounds__(kBoxThreads) k_boxes(BeamDev b, int query, dou
         for (int a = 0; a < 3; ++a) {
             lo32[a] = f32_down(lo[a] - (pad + 1e-12 * (1.0 + fabs(lo[a]))));
             hi32[a] = f32_up(hi[a] + (pad + 1e-12 * (1.0 + fabs(hi[a]))));
+            cen[a] = (float)(0.5 * (lo[a] + hi[a]));
         }
         o.lox = lo32[0]; o.loy = lo32[1]; o.loz = lo32[2];
         o.hix = hi32[0]; o.hiy = hi32[1]; o.hiz = hi32[2];
         o.tag = tag;
-        out[i] = o;
-        Red one;
-        red_init(one);
-        if (tag >= 0) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const uint32_t cc = f2ord(0.5f * (lo32[a] + hi32[a]));
-                one.mn[a] = cc;
-                one.mx[a] = cc;
-            }
-        }
-        if (!query) {
-            one.e = (unsigned long long)__double_as_longlong(E);
-            one.w = (unsigned long long)__double_as_longlong(w);
-        }
-        if (m == m_lo) red_merge(r0, one);
-        else if (m == m_hi) red_merge(r1, one);
-        else red_atomic(bounds, emax, wmax, m, one);
     }
-    red_wave(r0);
-    red_wave(r1);
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        s_red[wave][0] = r0;
-        s_red[wave][1] = r1;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < kBoxThreads / 64; ++w) {
-            red_merge(r0, s_red[w][0]);
-            red_merge(r1, s_red[w][1]);
-        }
-        BoundsPartial p0, p1;
-        for (int a = 0; a < 3; ++a) {
-            p0.mn[a] = r0.mn[a]; p0.mx[a] = r0.mx[a];
-            p1.mn[a] = r1.mn[a]; p1.mx[a] = r1.mx[a];
-        }
-        p0.e = r0.e; p0.w = r0.w; p0.inst = m_lo;
-        p1.e = r1.e; p1.w = r1.w; p1.inst = (m_hi != m_lo) ? m_hi : -1;
-        p0.pad = p1.pad = 0;
-        partials[2 * blockIdx.x] = p0;
-        partials[2 * blockIdx.x + 1] = p1;
-    }
-}
-
-// Combine the block partials of each instance (one workgroup per instance) into the
-// instance totals.
-__global__ void __launch_bounds__(256) k_fold_bounds(const BoundsPartial *__restrict__ partials,
-                                                     int64_t n, const int64_t *__restrict__ off,
-                                                     int32_t n_inst, uint32_t *bounds,
-                                                     unsigned long long *emax,
-                                                     unsigned long long *wmax) {
-    __shared__ Red s_red[4];
-    const int32_t m = blockIdx.x;
-    const int64_t a = n_inst > 1 ? off[m] : 0;
-    const int64_t e = n_inst > 1 ? off[m + 1] : n;
-    Red r;
-    red_init(r);
-    if (e > a) {
-        const int64_t b0 = a / kBoxSpan, b1 = (e - 1) / kBoxSpan;
-        for (int64_t blk = b0 + threadIdx.x; blk <= b1; blk += blockDim.x) {
-            for (int sl = 0; sl < 2; ++sl) {
-                const BoundsPartial &p = partials[2 * blk + sl];
-                if (p.inst != m) continue;
-                Red o;
-                for (int q = 0; q < 3; ++q) {
-                    o.mn[q] = p.mn[q];
-                    o.mx[q] = p.mx[q];
-                }
-                o.e = p.e;
-                o.w = p.w;
-                red_merge(r, o);
-            }
-        }
-    }
-    red_wave(r);
-    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = r;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x / 64); ++w) red_merge(r, s_red[w]);
-        red_atomic(bounds, emax, wmax, m, r);
-    }
-}
-
-__device__ __forceinline__ uint32_t morton_code(const PBox &bx, const uint32_t *bb) {
-    const float lo[3] = {ord2f(bb[0]), ord2f(bb[1]), ord2f(bb[2])};
-    const float hi[3] = {ord2f(bb[3]), ord2f(bb[4]), ord2f(bb[5])};
-    const float c[3] = {0.5f * (bx.lox + bx.hix), 0.5f * (bx.loy + bx.hiy), 0.5f * (bx.loz + bx.hiz)};
-    uint32_t q[3];
+    out[e] = o;
+    const InstStats &ss = self_stats[v.mi];
+    const double tau = t + 0.5 * dt;
+    float blo[3], bhi[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float ext = hi[a] - lo[a];
-        const float sc = ext > 0.0f ? 1023.0f / ext : 0.0f;
-        float v = (c[a] - lo[a]) * sc;
-        v = fminf(fmaxf(v, 0.0f), 1023.0f);  // NaN -> 0
-        q[a] = (uint32_t)v;
+        blo[a] = (float)(ord2d(ss.mn[a]) + tau * ord2d(ss.mn[3 + a]));
+        bhi[a] = (float)(ord2d(ss.mx[a]) + tau * ord2d(ss.mx[3 + a]));
     }
-    return (expand10(q[0]) << 2) | (expand10(q[1]) << 1) | expand10(q[2]);
+    const uint32_t code = morton30(cen, blo, bhi) >> (30 - kl.morton_bits);
+    if (kWide)
+        keys64[e] = ((unsigned long long)(uint32_t)v.c << kl.prefix_shift) | code;
+    else
+        keys32[e] = ((uint32_t)v.c << kl.prefix_shift) | code;
+    vals[e] = (uint32_t)e;
 }
 
 __global__ void __launch_bounds__(256) k_morton_u32(const PBox *__restrict__ box, int64_t n,
@@ -338,22 +388,14 @@ __global__ void __launch_bounds__(256) k_morton_u32(const PBox *__restrict__ box
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const PBox bx = box[i];
-    keys[i] = morton_code(bx, bounds);
+    const float lo[3] = {ord2f(bounds[0]), ord2f(bounds[1]), ord2f(bounds[2])};
+    const float hi[3] = {ord2f(bounds[3]), ord2f(bounds[4]), ord2f(bounds[5])};
+    const float c[3] = {0.5f * (bx.lox + bx.hix), 0.5f * (bx.loy + bx.hiy), 0.5f * (bx.loz + bx.hiz)};
+    keys[i] = morton30(c, lo, hi);
     vals[i] = (uint32_t)i;
 }
 
-__global__ void __launch_bounds__(256) k_morton_u64(const PBox *__restrict__ box, int64_t n,
-                                                    const uint32_t *__restrict__ bounds,
-                                                    unsigned long long *__restrict__ keys,
-                                                    uint32_t *__restrict__ vals) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const PBox bx = box[i];
-    // the instance prefix keeps instances contiguous in key order
-    const int32_t m = bx.pad;
-    keys[i] = ((unsigned long long)(uint32_t)m << 30) | morton_code(bx, bounds + 6 * m);
-    vals[i] = (uint32_t)i;
-}
+// ------------------------------------------------------------ Karras emission
 
 __device__ __forceinline__ int clz_key(uint32_t v) { return __clz(v); }
 __device__ __forceinline__ int clz_key(unsigned long long v) { return __clzll(v); }
@@ -370,6 +412,7 @@ __device__ __forceinline__ int delta(const K *__restrict__ keys, int64_t n, int6
 
 template <typename K>
 __global__ void __launch_bounds__(256) k_karras(const K *__restrict__ keys, int64_t n,
+                                                int prefix_shift,
                                                 int32_t *__restrict__ left,
                                                 int32_t *__restrict__ right,
                                                 int32_t *__restrict__ parent,
@@ -410,44 +453,53 @@ __global__ void __launch_bounds__(256) k_karras(const K *__restrict__ keys, int6
     flags[i] = 0;
     if (i == 0) parent[0] = -1;
     if (inst_root != nullptr) {
-        // node whose range is exactly one instance's run of keys (same 34-bit prefix)
-        const K pl = keys[lo] >> 30, ph = keys[hi] >> 30;
-        if (pl == ph && (lo == 0 || (keys[lo - 1] >> 30) != pl) &&
-            (hi == n - 1 || (keys[hi + 1] >> 30) != ph))
+        // node whose range is exactly one combined instance's run of keys (same prefix)
+        const K pl = keys[lo] >> prefix_shift, ph = keys[hi] >> prefix_shift;
+        if (pl == ph && (lo == 0 || (keys[lo - 1] >> prefix_shift) != pl) &&
+            (hi == n - 1 || (keys[hi + 1] >> prefix_shift) != ph))
             inst_root[(int64_t)pl] = (int32_t)i;
     }
 }
 
-// Instance roots that are leaves or empty, and the node where each instance's
-// traversal ends (rope of its root).
-__global__ void k_inst_roots(const int64_t *__restrict__ off, int32_t n_inst, int64_t n, int single,
-                             const int32_t *__restrict__ split_right, int32_t *inst_root,
-                             int32_t *inst_stop) {
-    const int32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n_inst) return;
-    const int64_t a = single ? 0 : off[m];
-    const int64_t b = single ? n : off[m + 1];
-    const int64_t cnt = b - a;
+// Roots that are leaves or empty, and the node where each combined instance's
+// traversal ends (rope of its root). `single`: one combined instance.
+__global__ void k_inst_roots(BeamDev b, int single, const int32_t *__restrict__ split_right,
+                             int32_t *inst_root, int32_t *inst_stop) {
+    const int32_t cc = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t n_comb = b.m * b.n_inst;
+    if (cc >= n_comb) return;
+    const int64_t nv = (int64_t)b.m * b.n;
+    int64_t a, cnt;
+    comb_range(b, cc, a, cnt);
     if (cnt <= 0) {
-        inst_root[m] = -1;
-        inst_stop[m] = -1;
+        inst_root[cc] = -1;
+        inst_stop[cc] = -1;
         return;
     }
-    if (cnt == 1) inst_root[m] = (int32_t)(n - 1 + a);
-    else if (single) inst_root[m] = 0;
-    inst_stop[m] = (b == n) ? -1 : split_right[b - 1];
+    if (cnt == 1) inst_root[cc] = (int32_t)(nv - 1 + a);
+    else if (single) inst_root[cc] = 0;
+    const int64_t e = a + cnt;
+    inst_stop[cc] = (e == nv) ? -1 : split_right[e - 1];
 }
 
-// Node stores and loads of the refit use device-scope relaxed atomics (write-through
-// and coherent across the chip's L2 slices), so a node box written on one XCD is seen
-// by the sibling's thread on another without a full L2 write-back fence. Ordering
-// within a thread comes from workgroup-scope fences (wait for the thread's own memory
-// operations to complete).
-__device__ __forceinline__ void store_node(Node *n, const Node &v) {
+// ------------------------------------------------------------------- refit
+
+// Node stores that another thread of the same launch may read use device-scope
+// relaxed atomics (write-through, coherent across the chip's L2 slices), so a node
+// box written on one XCD is seen by the sibling's thread on another without a full L2
+// write-back fence. Ordering within a thread comes from workgroup-scope fences (wait
+// for the thread's own memory operations to complete).
+__device__ __forceinline__ void store_node_coherent(Node *n, const Node &v) {
     unsigned long long *p = reinterpret_cast<unsigned long long *>(n);
     const unsigned long long *s = reinterpret_cast<const unsigned long long *>(&v);
 #pragma unroll
     for (int k = 0; k < 4; ++k) __hip_atomic_store(p + k, s[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_node_plain(Node *n, const Node &v) {
+    float4 *p = reinterpret_cast<float4 *>(n);
+    p[0] = make_float4(v.lox, v.loy, v.loz, __int_as_float(v.link));
+    p[1] = make_float4(v.hix, v.hiy, v.hiz, __int_as_float(v.rope));
 }
 
 __device__ __forceinline__ void load_box(const Node *n, float lo[3], float hi[3]) {
@@ -472,7 +524,9 @@ constexpr int kRefitChunk = 1024;  // leaves (and threads) per workgroup
 // chunk too (a node's id is one end of its range), so its arrival flag and box live in
 // LDS and the second child to arrive merges the boxes there. Nodes whose range crosses
 // a chunk boundary (the few levels of the top of the tree) use global arrival flags and
-// device-coherent node loads and stores. All nodes are also written to global memory.
+// device-coherent loads and stores. A node is written once, when its thread knows its
+// parent: with a coherent store if the parent crosses the chunk (a thread elsewhere may
+// read it), with plain stores otherwise.
 __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ box,
                                                        const uint32_t *__restrict__ rows, int64_t n,
                                                        const int32_t *__restrict__ left,
@@ -490,44 +544,62 @@ __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ 
     s_flag[threadIdx.x] = 0;
     const int64_t j = c0 + threadIdx.x;
     const bool in = j < n;
-    float lo[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f};
+    Node cn;  // node of `cur`, not yet stored
     int32_t cur = -1;
     if (in) {
         const uint32_t row = rows[j];
         const PBox bx = box[row];
-        lo[0] = bx.lox; lo[1] = bx.loy; lo[2] = bx.loz;
-        hi[0] = bx.hix; hi[1] = bx.hiy; hi[2] = bx.hiz;
-        Node lf;
-        lf.lox = lo[0]; lf.loy = lo[1]; lf.loz = lo[2];
-        lf.hix = hi[0]; lf.hiy = hi[1]; lf.hiz = hi[2];
-        lf.link = (int32_t)row;
-        lf.rope = (j == n - 1) ? -1 : split_right[j];
+        cn.lox = bx.lox; cn.loy = bx.loy; cn.loz = bx.loz;
+        cn.hix = bx.hix; cn.hiy = bx.hiy; cn.hiz = bx.hiz;
+        cn.link = (int32_t)row;
+        cn.rope = (j == n - 1) ? -1 : split_right[j];
         cur = (int32_t)(n - 1 + j);
-        store_node(nodes + cur, lf);
-        for (int a = 0; a < 3; ++a) {
-            s_leaf[a][threadIdx.x] = lo[a];
-            s_leaf[3 + a][threadIdx.x] = hi[a];
-        }
+        s_leaf[0][threadIdx.x] = cn.lox; s_leaf[1][threadIdx.x] = cn.loy;
+        s_leaf[2][threadIdx.x] = cn.loz; s_leaf[3][threadIdx.x] = cn.hix;
+        s_leaf[4][threadIdx.x] = cn.hiy; s_leaf[5][threadIdx.x] = cn.hiz;
     }
     __syncthreads();
-    if (!in || n == 1) return;
+    if (!in) return;
+    if (n == 1) {  // a single leaf is the root (no hierarchy was emitted)
+        store_node_plain(nodes + cur, cn);
+        return;
+    }
     const int64_t leaf0 = n - 1;
     for (int level = 0;; ++level) {
         const int32_t p = parent[cur];
-        if (p < 0) return;
+        if (p < 0) {  // cur is the root
+            store_node_plain(nodes + cur, cn);
+            return;
+        }
         if (level > 128) {
             atomicOr(err, kErrSpin);
             return;
         }
-        const int32_t lc = left[p];
-        const int32_t sib = (lc == cur) ? right[p] : lc;
         const int32_t plo = range_lo[p], phi = range_hi[p];
+        const bool local = plo >= c0 && phi <= c1;
         float slo[3], shi[3];
-        if (plo >= c0 && phi <= c1) {
+        if (local) {
+            store_node_plain(nodes + cur, cn);
+            if (cur < leaf0) {
+                const int64_t k = cur - c0;
+                s_int[0][k] = cn.lox; s_int[1][k] = cn.loy; s_int[2][k] = cn.loz;
+                s_int[3][k] = cn.hix; s_int[4][k] = cn.hiy; s_int[5][k] = cn.hiz;
+            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             const int32_t old = atomicAdd(&s_flag[p - c0], 1);
+            if (old == 0) return;  // the sibling subtree is not finished; its thread continues
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        } else {
+            store_node_coherent(nodes + cur, cn);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            const int32_t old = __hip_atomic_fetch_add(flags + p, 1, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
             if (old == 0) return;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+        const int32_t lc = left[p];
+        const int32_t sib = (lc == cur) ? right[p] : lc;
+        if (local) {
             if (sib >= leaf0) {
                 const int64_t k = sib - leaf0 - c0;
                 for (int a = 0; a < 3; ++a) {
@@ -542,31 +614,14 @@ __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ 
                 }
             }
         } else {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            const int32_t old = __hip_atomic_fetch_add(flags + p, 1, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-            if (old == 0) return;  // the sibling subtree is not finished; its thread continues
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             load_box(nodes + sib, slo, shi);
         }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = fminf(lo[a], slo[a]);
-            hi[a] = fmaxf(hi[a], shi[a]);
-        }
         Node u;
-        u.lox = lo[0]; u.loy = lo[1]; u.loz = lo[2];
-        u.hix = hi[0]; u.hiy = hi[1]; u.hiz = hi[2];
+        u.lox = fminf(cn.lox, slo[0]); u.loy = fminf(cn.loy, slo[1]); u.loz = fminf(cn.loz, slo[2]);
+        u.hix = fmaxf(cn.hix, shi[0]); u.hiy = fmaxf(cn.hiy, shi[1]); u.hiz = fmaxf(cn.hiz, shi[2]);
         u.link = lc;
         u.rope = (phi == n - 1) ? -1 : split_right[phi];
-        store_node(nodes + p, u);
-        if (plo >= c0 && phi <= c1) {
-            const int64_t k = p - c0;
-            for (int a = 0; a < 3; ++a) {
-                s_int[a][k] = lo[a];
-                s_int[3 + a][k] = hi[a];
-            }
-        }
+        cn = u;
         cur = p;
     }
 }
@@ -575,22 +630,34 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 
 }  // namespace
 
-void launch_clear_inst(uint32_t *bounds, unsigned long long *emax, unsigned long long *wmax,
-                       int32_t n_inst, hipStream_t st) {
-    hipLaunchKernelGGL(k_clear_inst, dim3(grid_for(n_inst, 64)), dim3(64), 0, st, bounds, emax,
-                       wmax, n_inst);
+KeyLayout key_layout(int64_t n_comb) {
+    int p = 0;
+    while (p < 63 && ((uint64_t)(n_comb > 1 ? n_comb - 1 : 0) >> p) != 0) ++p;
+    KeyLayout kl;
+    if (p <= 5) {
+        kl.wide = false;
+        kl.morton_bits = p <= 2 ? 30 : 32 - p;
+        kl.prefix_shift = kl.morton_bits;
+        kl.key_bits = kl.morton_bits + p;
+    } else {
+        kl.wide = true;
+        kl.morton_bits = 30;
+        kl.prefix_shift = 30;
+        kl.key_bits = 30 + p;
+    }
+    return kl;
+}
+
+void launch_prologue(DevCounters *c, int kind, int32_t m, hipStream_t st) {
+    hipLaunchKernelGGL(k_prologue, dim3(1), dim3(1), 0, st, c, kind, m);
 }
 
 void launch_set_step(DevCounters *c, int32_t step, hipStream_t st) {
     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, st, c, step);
 }
 
-void launch_advance_step(DevCounters *c, hipStream_t st) {
-    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(1), 0, st, c);
-}
-
-void launch_begin_step(DevCounters *c, int kind, hipStream_t st) {
-    hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, st, c, kind);
+void launch_advance_step(DevCounters *c, int32_t m, hipStream_t st) {
+    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(1), 0, st, c, m);
 }
 
 void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st) {
@@ -598,19 +665,34 @@ void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, v, n);
 }
 
-void launch_boxes(const BeamDev &b, bool query, double dt, double sigma_up,
-                  const unsigned long long *t_emax, const unsigned long long *t_wmax, PBox *out,
-                  BoundsPartial *partials, uint32_t *bounds, unsigned long long *emax,
-                  unsigned long long *wmax, DevCounters *c, hipStream_t st) {
+int64_t stats_partials_needed(int64_t n) { return 2 * ((n + kStatSpan - 1) / kStatSpan) + 2; }
+
+void launch_beam_stats(const BeamDev &b, StatsPartial *partials, InstStats *stats, DevCounters *c,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_stats_clear, dim3(grid_for(b.n_inst, 64)), dim3(64), 0, st, stats,
+                       b.n_inst);
     if (b.n <= 0) return;
-    const unsigned grid = (unsigned)((b.n + kBoxSpan - 1) / kBoxSpan);
-    hipLaunchKernelGGL(k_boxes, dim3(grid), dim3(kBoxThreads), 0, st, b, query ? 1 : 0, dt,
-                       sigma_up, t_emax, t_wmax, out, partials, bounds, emax, wmax, c);
-    hipLaunchKernelGGL(k_fold_bounds, dim3((unsigned)b.n_inst), dim3(256), 0, st, partials, b.n,
-                       b.inst_off, b.n_inst, bounds, emax, wmax);
+    hipLaunchKernelGGL(k_beam_stats, dim3(grid_for(b.n, kStatSpan)), dim3(kStatThreads), 0, st, b,
+                       partials, stats, c);
+    hipLaunchKernelGGL(k_fold_stats, dim3((unsigned)b.n_inst), dim3(256), 0, st, partials, b,
+                       stats);
 }
 
-int64_t boxes_partials_needed(int64_t n) { return 2 * ((n + kBoxSpan - 1) / kBoxSpan) + 2; }
+void launch_boxes_keys(const BeamDev &b, bool query, double dt, double sigma_up,
+                       const InstStats *t_stats, const InstStats *self_stats, KeyLayout kl,
+                       PBox *out, uint32_t *keys32, unsigned long long *keys64, uint32_t *vals,
+                       DevCounters *c, hipStream_t st) {
+    const int64_t nv = (int64_t)b.m * b.n;
+    if (nv <= 0) return;
+    if (kl.wide)
+        hipLaunchKernelGGL(k_boxes_keys<true>, dim3(grid_for(nv, 256)), dim3(256), 0, st, b,
+                           query ? 1 : 0, dt, sigma_up, t_stats, self_stats, kl, out, keys32,
+                           keys64, vals, c);
+    else
+        hipLaunchKernelGGL(k_boxes_keys<false>, dim3(grid_for(nv, 256)), dim3(256), 0, st, b,
+                           query ? 1 : 0, dt, sigma_up, t_stats, self_stats, kl, out, keys32,
+                           keys64, vals, c);
+}
 
 void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint32_t *keys,
                        uint32_t *vals, hipStream_t st) {
@@ -619,36 +701,29 @@ void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint3
                        vals);
 }
 
-void launch_morton_u64(const PBox *box, int64_t n, const uint32_t *bounds,
-                       unsigned long long *keys, uint32_t *vals, hipStream_t st) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_morton_u64, dim3(grid_for(n, 256)), dim3(256), 0, st, box, n, bounds, keys,
-                       vals);
-}
-
-void launch_karras_u32(const uint32_t *keys, int64_t n, int32_t *left, int32_t *right,
-                       int32_t *parent, int32_t *range_lo, int32_t *range_hi, int32_t *split_right,
-                       int32_t *flags, hipStream_t st) {
+void launch_karras_u32(const uint32_t *keys, int64_t n, int prefix_shift, int32_t *left,
+                       int32_t *right, int32_t *parent, int32_t *range_lo, int32_t *range_hi,
+                       int32_t *split_right, int32_t *flags, int32_t *inst_root, hipStream_t st) {
     if (n <= 1) return;
     hipLaunchKernelGGL(k_karras<uint32_t>, dim3(grid_for(n - 1, 256)), dim3(256), 0, st, keys, n,
-                       left, right, parent, range_lo, range_hi, split_right, flags,
-                       (int32_t *)nullptr);
-}
-
-void launch_karras_u64(const unsigned long long *keys, int64_t n, int32_t *left, int32_t *right,
-                       int32_t *parent, int32_t *range_lo, int32_t *range_hi, int32_t *split_right,
-                       int32_t *flags, int32_t *inst_root, hipStream_t st) {
-    if (n <= 1) return;
-    hipLaunchKernelGGL(k_karras<unsigned long long>, dim3(grid_for(n - 1, 256)), dim3(256), 0, st,
-                       keys, n, left, right, parent, range_lo, range_hi, split_right, flags,
+                       prefix_shift, left, right, parent, range_lo, range_hi, split_right, flags,
                        inst_root);
 }
 
-void launch_inst_roots(const int64_t *inst_off, int32_t n_inst, int64_t n, bool single,
-                       const int32_t *split_right, int32_t *inst_root, int32_t *inst_stop,
-                       hipStream_t st) {
-    hipLaunchKernelGGL(k_inst_roots, dim3(grid_for(n_inst, 64)), dim3(64), 0, st, inst_off, n_inst,
-                       n, single ? 1 : 0, split_right, inst_root, inst_stop);
+void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shift, int32_t *left,
+                       int32_t *right, int32_t *parent, int32_t *range_lo, int32_t *range_hi,
+                       int32_t *split_right, int32_t *flags, int32_t *inst_root, hipStream_t st) {
+    if (n <= 1) return;
+    hipLaunchKernelGGL(k_karras<unsigned long long>, dim3(grid_for(n - 1, 256)), dim3(256), 0, st,
+                       keys, n, prefix_shift, left, right, parent, range_lo, range_hi, split_right,
+                       flags, inst_root);
+}
+
+void launch_inst_roots(const BeamDev &b, bool single, const int32_t *split_right,
+                       int32_t *inst_root, int32_t *inst_stop, hipStream_t st) {
+    const int32_t n_comb = b.m * b.n_inst;
+    hipLaunchKernelGGL(k_inst_roots, dim3(grid_for(n_comb, 64)), dim3(64), 0, st, b,
+                       single ? 1 : 0, split_right, inst_root, inst_stop);
 }
 
 void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, const int32_t *left,

@@ -47,8 +47,7 @@ __global__ void __launch_bounds__(256) k_narrow(BeamDev q, BeamDev t, double dt,
     const unsigned long long nc_raw = c->cand_step;
     const int64_t nc = (int64_t)(nc_raw < (unsigned long long)cand_cap ? nc_raw
                                                                        : (unsigned long long)cand_cap);
-    const int32_t step = (int32_t)c->step;
-    const double tk = (double)step * dt;
+    const int32_t step0 = (int32_t)c->step;
     const double two_me2 = 2.0 * kMe * kMe;
     uint32_t n_sigma = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -57,10 +56,15 @@ __global__ void __launch_bounds__(256) k_narrow(BeamDev q, BeamDev t, double dt,
     for (int64_t wb = base0; wb < nc; wb += stride) {
         const int64_t idx = wb + (threadIdx.x & 63);
         bool hit = false;
-        int32_t i = 0, j = 0;
+        int32_t i = 0, j = 0, step = step0;
         if (idx < nc) {
-            i = cand_i[idx];
-            j = cand_j[idx];
+            // candidates hold virtual rows (step offset s, row): e = s n + row
+            const int64_t eq = cand_i[idx], et = cand_j[idx];
+            const int64_t so = q.m > 1 ? eq / q.n : 0;
+            i = (int32_t)(eq - so * q.n);
+            j = (int32_t)(et - so * t.n);
+            step = step0 + (int32_t)so;
+            const double tk = (double)step * dt;
             const double Ei = q.E[i], Ej = t.E[j];
             const double uix = q.px[i] / Ei, uiy = q.py[i] / Ei, uiz = q.pz[i] / Ei;
             const double ujx = t.px[j] / Ej, ujy = t.py[j] / Ej, ujz = t.pz[j] / Ej;

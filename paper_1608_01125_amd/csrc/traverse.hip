@@ -25,7 +25,8 @@ __device__ __forceinline__ uint32_t count_below(unsigned long long mask) {
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nodes, int32_t n_int,
                                                     const PBox *__restrict__ qbox,
-                                                    const uint32_t *__restrict__ qorder, int64_t nq,
+                                                    const uint32_t *__restrict__ qorder,
+                                                    int64_t order_len, int64_t nq, int64_t nq_base,
                                                     const int32_t *__restrict__ inst_root,
                                                     const int32_t *__restrict__ inst_stop,
                                                     int32_t *__restrict__ cand_i,
@@ -35,7 +36,14 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
     int32_t node = -1, stop = -1, qi = 0;
     float lx = 0.f, ly = 0.f, lz = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
     if (q < nq) {
-        qi = (int32_t)(qorder ? qorder[q] : (uint32_t)q);
+        if (qorder == nullptr) {
+            qi = (int32_t)q;
+        } else if (order_len == nq) {
+            qi = (int32_t)qorder[q];
+        } else {  // one step's order, repeated for every step of the launch
+            const int64_t s = q / nq_base;
+            qi = (int32_t)(s * nq_base + qorder[q - s * nq_base]);
+        }
         const float4 *bp = reinterpret_cast<const float4 *>(qbox + qi);
         const float4 a = bp[0], b = bp[1];
         lx = a.x; ly = a.y; lz = a.z;
@@ -96,7 +104,8 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
 }  // namespace
 
 void launch_traverse(const Node *nodes, int64_t nt, const PBox *qbox, const uint32_t *qorder,
-                     int64_t nq, const int32_t *inst_root, const int32_t *inst_stop,
+                     int64_t order_len, int64_t nq, int64_t nq_base,
+                     const int32_t *inst_root, const int32_t *inst_stop,
                      int32_t *cand_i, int32_t *cand_j, int64_t cand_cap, DevCounters *c, int block,
                      hipStream_t st) {
     if (nq <= 0 || nt <= 0) return;
@@ -105,19 +114,19 @@ void launch_traverse(const Node *nodes, int64_t nt, const PBox *qbox, const uint
     switch (block) {
     case 64:
         hipLaunchKernelGGL(k_traverse<64>, dim3(grid), dim3(64), 0, st, nodes, n_int, qbox, qorder,
-                           nq, inst_root, inst_stop, cand_i, cand_j, cand_cap, c);
+                           order_len, nq, nq_base, inst_root, inst_stop, cand_i, cand_j, cand_cap, c);
         break;
     case 128:
         hipLaunchKernelGGL(k_traverse<128>, dim3(grid), dim3(128), 0, st, nodes, n_int, qbox,
-                           qorder, nq, inst_root, inst_stop, cand_i, cand_j, cand_cap, c);
+                           qorder, order_len, nq, nq_base, inst_root, inst_stop, cand_i, cand_j, cand_cap, c);
         break;
     case 512:
         hipLaunchKernelGGL(k_traverse<512>, dim3(grid), dim3(512), 0, st, nodes, n_int, qbox,
-                           qorder, nq, inst_root, inst_stop, cand_i, cand_j, cand_cap, c);
+                           qorder, order_len, nq, nq_base, inst_root, inst_stop, cand_i, cand_j, cand_cap, c);
         break;
     default:
         hipLaunchKernelGGL(k_traverse<256>, dim3(grid), dim3(256), 0, st, nodes, n_int, qbox,
-                           qorder, nq, inst_root, inst_stop, cand_i, cand_j, cand_cap, c);
+                           qorder, order_len, nq, nq_base, inst_root, inst_stop, cand_i, cand_j, cand_cap, c);
         break;
     }
 }

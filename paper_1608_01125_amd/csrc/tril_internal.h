@@ -83,62 +83,80 @@ bool radix_sort_u64(unsigned long long *keys, uint32_t *vals, unsigned long long
                     unsigned int *err, hipStream_t st);
 
 // ------------------------------------------------------------ hierarchy parts
-struct BeamDev {  // device view of a caller beam plus instance data
-    int64_t n;
+// Device view of a caller beam plus instance data. A launch covers m consecutive
+// steps: virtual element e = s n + i is row i at step offset s, combined instance
+// c = s n_inst + (instance of row i).
+struct BeamDev {
+    int64_t n;                 // rows of the beam (all instances)
     const double *x, *y, *z, *px, *py, *pz, *E, *w;
     int32_t n_inst;
     const int64_t *inst_off;   // device copy, n_inst + 1
+    int32_t m;                 // steps covered by the launch (>= 1)
 };
 
-// Partial reduction of one block for one instance (inst = -1: unused slot).
-struct BoundsPartial {
-    uint32_t mn[3], mx[3];   // centroid bounds as ordered floats
-    int32_t inst;
+// Per-instance statistics of a beam over its rows (the same for every step):
+// bounds of the positions at t = 0 and of the directions u = p/E (ordered 64-bit
+// encodings of doubles), and the largest energy and weight (FP64 bits, both >= 0).
+struct InstStats {
+    unsigned long long mn[6], mx[6];   // x0 y0 z0 ux uy uz
+    unsigned long long emax, wmax;
+};
+struct StatsPartial {
+    InstStats s;
+    int32_t inst;   // instance the partial belongs to, -1 = unused slot
     int32_t pad;
-    unsigned long long e, w; // largest E and w (FP64 bits)
 };
-int64_t boxes_partials_needed(int64_t n);
+int64_t stats_partials_needed(int64_t n);
 
-// Per-instance data of the target (device arrays of n_inst entries unless noted).
-struct InstDev {
-    uint32_t *bounds;                 // 6 per instance: ordered-float min xyz, max xyz
-    unsigned long long *emax_bits;    // max E of the target instance (FP64 bits)
-    unsigned long long *wmax_bits;    // max w of the target instance (FP64 bits)
-    int32_t *root;                    // root node id or -1 (empty instance)
-    int32_t *stop;                    // rope of the root (traversal ends there)
+// Sort-key layout for n_comb combined instances: 32-bit keys (prefix above
+// morton_bits of the Morton code) while the prefix needs at most 5 bits, else 64-bit
+// keys (prefix above all 30 Morton bits).
+struct KeyLayout {
+    bool wide;
+    int morton_bits;    // Morton bits kept (top bits of the 30-bit code)
+    int prefix_shift;   // key >> prefix_shift = combined instance
+    int key_bits;       // bits the sort must order
 };
+KeyLayout key_layout(int64_t n_comb);
 
-void launch_clear_inst(uint32_t *bounds, unsigned long long *emax, unsigned long long *wmax,
-                       int32_t n_inst, hipStream_t st);
+void launch_prologue(DevCounters *c, int kind, int32_t m, hipStream_t st);
 void launch_set_step(DevCounters *c, int32_t step, hipStream_t st);
-void launch_advance_step(DevCounters *c, hipStream_t st);
-void launch_begin_step(DevCounters *c, int kind, hipStream_t st);
+void launch_advance_step(DevCounters *c, int32_t m, hipStream_t st);
 void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st);
 
-void launch_boxes(const BeamDev &b, bool query, double dt, double sigma_up,
-                  const unsigned long long *t_emax, const unsigned long long *t_wmax,
-                  PBox *out, BoundsPartial *partials, uint32_t *bounds, unsigned long long *emax,
-                  unsigned long long *wmax, DevCounters *c, hipStream_t st);
+// Per-instance statistics of beam b (rows only; b.m is ignored); flags invalid data.
+void launch_beam_stats(const BeamDev &b, StatsPartial *partials, InstStats *stats, DevCounters *c,
+                       hipStream_t st);
+// Swept boxes of all virtual elements of b plus their sort keys and values (the
+// virtual element index). Morton quantisation bounds come from self_stats; query
+// padding and the threshold prune from t_stats (target instance statistics).
+void launch_boxes_keys(const BeamDev &b, bool query, double dt, double sigma_up,
+                       const InstStats *t_stats, const InstStats *self_stats, KeyLayout kl,
+                       PBox *out, uint32_t *keys32, unsigned long long *keys64, uint32_t *vals,
+                       DevCounters *c, hipStream_t st);
+// Morton keys of given boxes over given bounds (6 ordered floats), 30 bits.
 void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint32_t *keys,
                        uint32_t *vals, hipStream_t st);
-void launch_morton_u64(const PBox *box, int64_t n, const uint32_t *bounds,
-                       unsigned long long *keys, uint32_t *vals, hipStream_t st);
-void launch_karras_u32(const uint32_t *keys, int64_t n, int32_t *left, int32_t *right,
-                       int32_t *parent, int32_t *range_lo, int32_t *range_hi, int32_t *split_right,
-                       int32_t *flags, hipStream_t st);
-void launch_karras_u64(const unsigned long long *keys, int64_t n, int32_t *left, int32_t *right,
-                       int32_t *parent, int32_t *range_lo, int32_t *range_hi, int32_t *split_right,
-                       int32_t *flags, int32_t *inst_root, hipStream_t st);
-void launch_inst_roots(const int64_t *inst_off, int32_t n_inst, int64_t n, bool single,
-                       const int32_t *split_right, int32_t *inst_root, int32_t *inst_stop,
-                       hipStream_t st);
+// inst_root may be NULL (one combined instance); otherwise the node whose range is
+// exactly one instance's run of keys (key >> prefix_shift equal) is recorded.
+void launch_karras_u32(const uint32_t *keys, int64_t n, int prefix_shift, int32_t *left,
+                       int32_t *right, int32_t *parent, int32_t *range_lo, int32_t *range_hi,
+                       int32_t *split_right, int32_t *flags, int32_t *inst_root, hipStream_t st);
+void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shift, int32_t *left,
+                       int32_t *right, int32_t *parent, int32_t *range_lo, int32_t *range_hi,
+                       int32_t *split_right, int32_t *flags, int32_t *inst_root, hipStream_t st);
+void launch_inst_roots(const BeamDev &b, bool single, const int32_t *split_right,
+                       int32_t *inst_root, int32_t *inst_stop, hipStream_t st);
 void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, const int32_t *left,
                   const int32_t *right, const int32_t *parent, const int32_t *range_lo,
                   const int32_t *range_hi, const int32_t *split_right, int32_t *flags, Node *nodes,
                   unsigned int *err, hipStream_t st);
 
+// nt, nq: virtual counts (steps x rows). qorder: NULL (identity), nq entries (order of
+// all virtual queries) or nq_base entries (order of one step, repeated per step).
 void launch_traverse(const Node *nodes, int64_t nt, const PBox *qbox, const uint32_t *qorder,
-                     int64_t nq, const int32_t *inst_root, const int32_t *inst_stop,
+                     int64_t order_len, int64_t nq, int64_t nq_base,
+                     const int32_t *inst_root, const int32_t *inst_stop,
                      int32_t *cand_i, int32_t *cand_j, int64_t cand_cap, DevCounters *c,
                      int block, hipStream_t st);
 void launch_narrow(const BeamDev &q, const BeamDev &t, double dt, double sigma_up,

@@ -43,7 +43,7 @@ class tril_beam(ctypes.Structure):
 class tril_params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("flags", ctypes.c_uint32), ("n_bins", ctypes.c_int32),
                 ("bin_edges", _dp), ("cand_cap", ctypes.c_int64),
-                ("block_traverse", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("block_traverse", ctypes.c_int32), ("step_batch", ctypes.c_int32)]
 
 
 class tril_pairs(ctypes.Structure):
@@ -60,7 +60,7 @@ class tril_stats_t(ctypes.Structure):
                 ("n_step_counts", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("ms_build", ctypes.c_double), ("ms_query_prep", ctypes.c_double),
                 ("ms_traverse", ctypes.c_double), ("ms_narrow", ctypes.c_double),
-                ("n_timed_steps", ctypes.c_int64)]
+                ("n_timed_launches", ctypes.c_int64)]
 
 
 EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats",
@@ -188,7 +188,8 @@ class Pairs:
 
 
 def tril_create(dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
-                cand_cap: int = 0, block_traverse: int = 0, stream=None) -> ctypes.c_void_p:
+                cand_cap: int = 0, block_traverse: int = 0, step_batch: int = 0,
+                stream=None) -> ctypes.c_void_p:
     L = lib()
     p = tril_params()
     p.dt = float(dt)
@@ -203,6 +204,7 @@ def tril_create(dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
         p.bin_edges = None
     p.cand_cap = int(cand_cap)
     p.block_traverse = int(block_traverse)
+    p.step_batch = int(step_batch)
     h = ctypes.c_void_p()
     _check(L.tril_create(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(_stream(stream))),
            "tril_create")
@@ -328,9 +330,9 @@ class Context:
     """One collision context (owns the hierarchy and scratch on the device)."""
 
     def __init__(self, dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
-                 cand_cap: int = 0, block_traverse: int = 0, stream=None):
+                 cand_cap: int = 0, block_traverse: int = 0, step_batch: int = 0, stream=None):
         self.n_bins = 0 if edges is None else max(len(edges) - 1, 0)
-        self.h = tril_create(dt, edges, flags, cand_cap, block_traverse, stream)
+        self.h = tril_create(dt, edges, flags, cand_cap, block_traverse, step_batch, stream)
 
     def build(self, target: Beam, step: int) -> None:
         tril_build(self.h, target, step)

@@ -61,6 +61,38 @@ def test_gauss_headon_reduced_all_steps(torch, graph, flags):
     assert_parity(gpu, raw, S, wl.n_steps)
 
 
+@pytest.mark.parametrize("step_batch,flags", [
+    (1, 0), (7, 0), (64, T.TRIL_TIMING), (0, T.TRIL_SORT_QUERIES_ONCE),
+    (13, T.TRIL_SORT_QUERIES_ONCE | T.TRIL_TIMING), (400, 0)])
+def test_step_batches(torch, step_batch, flags):
+    """tril_run with several time steps per launch (each step its own subtree) equals the
+    oracle for any batch size, including a shorter last batch."""
+    wl, A, B = _gauss_small(8000, 1.5e4, seed=4)
+    raw, S = oracle_run(A, B, wl.dt, wl.n_steps, EDGES)
+    gpu = gpu_run(A, B, wl.dt, wl.n_steps, EDGES, graph=True, flags=flags, step_batch=step_batch)
+    assert S.n_pairs > 100
+    assert_parity(gpu, raw, S, wl.n_steps)
+
+
+def test_step_batches_with_instances(torch):
+    """Step batches combined with ragged instances: combined (step, instance) subtrees."""
+    parts_a, parts_b = [], []
+    for m, (na, nb) in enumerate([(1200, 900), (0, 50), (1, 1), (900, 1500), (3, 700)]):
+        wl = beams.batch64_instance(m)
+        wl = beams.batch64_instance(m, w=wl.a.w * 800.0)
+        A, B = beams.draw_pair(wl)
+        parts_a.append(beams.head(A, na))
+        parts_b.append(beams.head(B, nb))
+    A, offA = beams.concat(parts_a)
+    B, offB = beams.concat(parts_b)
+    raw, S = oracle_run(A, B, 0.1, 400, EDGES, offA=offA, offB=offB)
+    for sb, flags in [(9, 0), (50, T.TRIL_SORT_QUERIES_ONCE), (0, T.TRIL_TIMING)]:
+        gpu = gpu_run(A, B, 0.1, 400, EDGES, graph=True, offA=offA, offB=offB, step_batch=sb,
+                      flags=flags)
+        assert_parity(gpu, raw, S, 400)
+    assert S.n_pairs > 20
+
+
 def test_gauss_headon_1m_sampled_rows(torch):
     """Full size (1e6 per beam, calibrated weight, 400 steps, graph replay, the launch
     configuration of the benchmark): every pair of 300 sampled query rows, 150 of them
