@@ -39,14 +39,19 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "traverse_gauss_headon_1m_pmc.txt")
 
 
 def traverse_source_hash() -> str:
+    """Hash of the traversal kernel's source and of the node and box layouts it reads."""
     h = hashlib.sha256()
-    for rel in TRAVERSE_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+    with open(os.path.join(ROOT, TRAVERSE_SOURCES[0]), "rb") as f:
+        h.update(f.read())
+    with open(os.path.join(ROOT, TRAVERSE_SOURCES[1]), "rb") as f:
+        text = f.read().decode()
+    a = text.index("struct alignas(16) Node")
+    b = text.index("static_assert(sizeof(PBox)")
+    h.update(text[a:b].encode())
     return h.hexdigest()[:16]
 
 
-def committed_traffic():
+def committed_traffic(steps_per_dispatch=None):
     """HBM bytes per traversal launch from the committed counter summary, or None
     when it was taken from a different kernel source."""
     if not os.path.exists(PMC_SUMMARY):
@@ -58,6 +63,8 @@ def committed_traffic():
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("source_sha256") != traverse_source_hash():
+        return None
+    if steps_per_dispatch is not None and vals.get("steps_per_dispatch") != str(steps_per_dispatch):
         return None
     try:
         return float(vals["traffic_bytes_per_dispatch"])
@@ -121,6 +128,8 @@ def main():
     ap.add_argument("--step-batch", type=int, default=0, help="time steps per launch (0 = automatic)")
     ap.add_argument("--physics-steps", type=int, default=0, help="0 = the workload's full run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the timed run with the query order taken from the first step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
@@ -152,37 +161,56 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    flags = args.flags | (T.TRIL_TIMING if args.mode != "graph" else 0)
-    ctx = T.Context(wl.dt, edges, flags=flags, block_traverse=args.block,
-                    step_batch=args.step_batch)
-    tb, qb = T.Beam(B), T.Beam(A)
-    pairs = T.Pairs(max(1 << 20, 4 * min(nA, nB)))
     graph = args.mode != "per-step"
 
-    def one_run():
-        pairs.reset()
-        T.run_steps(ctx, tb, qb, n_steps, pairs, graph=graph)
-        return ctx.stats(pairs)
+    def timed(flags):
+        """Warm-up runs, then args.steps timed collision runs; returns (seconds, stats)."""
+        ctx = T.Context(wl.dt, edges, flags=flags, block_traverse=args.block,
+                        step_batch=args.step_batch)
+        pairs = T.Pairs(max(1 << 20, 4 * min(nA, nB)))
 
-    for _ in range(args.warmup):
-        one_run()
-    ctx.reset_counters()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st = one_run()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ctx.close()
+        def one_run():
+            pairs.reset()
+            T.run_steps(ctx, tb, qb, n_steps, pairs, graph=graph)
+            return ctx.stats(pairs)
 
+        try:
+            for _ in range(args.warmup):
+                one_run()
+            ctx.reset_counters()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                st = one_run()
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, st
+        finally:
+            ctx.close()
+
+    tb, qb = T.Beam(B), T.Beam(A)
+    timing = T.TRIL_TIMING if args.mode != "graph" else 0
+    elapsed, st = timed(args.flags | timing)
     ms_per_step = 1e3 * elapsed / max(args.steps, 1)
     value = nA * nB * n_steps / (elapsed / max(args.steps, 1))
+    launches_per_run = st["n_timed_launches"] // max(args.steps, 1) if timing else 0
+    steps_per_dispatch = (n_steps // launches_per_run
+                          if launches_per_run and n_steps % launches_per_run == 0 else None)
+
+    variants = {}
+    if not args.no_variants and not (args.flags & T.TRIL_SORT_QUERIES_ONCE):
+        # same run with the query beam put in Morton order at its first step only (the pair
+        # set is identical; only the traversal order of the queries differs)
+        e2, st2 = timed(args.flags | T.TRIL_SORT_QUERIES_ONCE | timing)
+        variants["query_order_from_first_step"] = {
+            "value": nA * nB * n_steps / (e2 / max(args.steps, 1)),
+            "ms_per_step": 1e3 * e2 / max(args.steps, 1), "pairs": st2["n_pairs"]}
 
     roofline = None
     if st["n_collides"] > 0:
         # traversal bytes over the timed region: 36 B per query (order entry + box), 32 B per
         # node visit, 8 B per candidate written
         alg_bytes = 36.0 * nA * st["n_collides"] + 32.0 * st["n_node_visits"] + 8.0 * st["n_candidates"]
+        traffic = committed_traffic(steps_per_dispatch)
         if st["n_timed_launches"] > 0 and st["ms_traverse"] > 0:
             n_launch = st["n_timed_launches"]
             per_launch = alg_bytes / n_launch
@@ -190,13 +218,16 @@ def main():
             achieved = per_launch / avg_s / 1e9
             roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": committed_traffic(),
+                        "traffic": traffic,
                         "kernel": "k_traverse", "avg_launch_us": round(avg_s * 1e6, 3),
+                        "steps_per_launch": steps_per_dispatch,
                         "alg_bytes_per_launch": round(per_launch, 1),
+                        "traffic_achieved_GBs": (round(traffic / avg_s / 1e9, 2)
+                                                 if traffic else None),
                         "node_visits_per_query": round(st["n_node_visits"] / max(st["n_queries"], 1), 3)}
         else:
             roofline = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": None, "traffic": committed_traffic(), "kernel": "k_traverse",
+                        "frac": None, "traffic": None, "kernel": "k_traverse",
                         "note": "graph mode records no per-phase events; use --mode batched"}
 
     out = {
@@ -214,12 +245,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_per_beam": [nA, nB], "time_steps": n_steps,
                    "dt_um_per_c": wl.dt, "weight": wl.a.w, "mode": args.mode,
-                   "step_batch": args.step_batch, "traversal_launches": st["n_timed_launches"],
+                   "step_batch": args.step_batch, "steps_per_launch": steps_per_dispatch,
+                   "query_order": ("first step's Morton order" if args.flags & T.TRIL_SORT_QUERIES_ONCE
+                                   else "Morton order of every step"),
+                   "traversal_launches": st["n_timed_launches"],
                    "pairs": st["n_pairs"], "hits": st["n_hits"],
                    "ms_phases_per_run": {k: round(st[k] / max(args.steps, 1), 3) for k in
                                          ("ms_build", "ms_query_prep", "ms_traverse", "ms_narrow")}},
         "roofline": roofline,
     }
+    if variants:
+        out["variants"] = variants
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, B, wl.dt, n_steps, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -94,6 +94,14 @@ typedef struct {
     int32_t block_traverse;       /* traversal workgroup size: 64, 128, 256, 512 or 0 = default */
     int32_t step_batch;           /* tril_run: steps per launch, >= 0 (0 = as many as keep one
                                      launch near 2^24 photon-steps) */
+    int32_t morton_bits;          /* Morton bits of the sort keys, 3..30, or 0 = automatic:
+                                     30 (10 per axis) for tril_build/tril_collide; for tril_run,
+                                     which first puts both beams in the order of their full
+                                     30-bit codes, as many as fit three 8-bit radix passes
+                                     beside the step/instance prefix (18..30). Photons with
+                                     equal codes keep their order (stable sort). The pair set
+                                     does not depend on it. */
+    int32_t pad0;
 } tril_params;
 
 /* Caller-owned pair buffer. tril_collide appends raw hits (i, j, step) at

@@ -74,6 +74,12 @@ constexpr int64_t kBatchBudget = (int64_t)1 << 24;  // default virtual elements 
 
 }  // namespace
 
+struct WorkBeam {
+    double *soa = nullptr;          // x, y, z, px, py, pz, E, w: 8 arrays of n
+    int32_t *perm = nullptr;        // working row -> caller row
+    int64_t cap = 0;
+};
+
 struct tril_ctx {
     hipStream_t st = nullptr;       // caller stream
     hipStream_t gst = nullptr;      // internal stream for graph replay (non-blocking)
@@ -85,6 +91,8 @@ struct tril_ctx {
     int64_t cand_cap_param = 0;
     int block = 256;
     int32_t step_batch = 0;         // steps per launch in tril_run (0 = automatic)
+    int morton_param = 0;           // Morton bits requested (0 = automatic)
+    int morton_bits = 30;           // Morton bits of the sort keys of the current build/collide
     double sigma_up = 0.0;
     DevCounters *d_cnt = nullptr;
     DevCounters *h_cnt = nullptr;   // pinned host mirror
@@ -105,8 +113,7 @@ struct tril_ctx {
     uint32_t *t_k32a = nullptr, *t_k32b = nullptr;
     unsigned long long *t_k64a = nullptr, *t_k64b = nullptr;
     uint32_t *t_va = nullptr, *t_vb = nullptr;
-    int32_t *left = nullptr, *right = nullptr, *parent = nullptr, *range_hi = nullptr;
-    int32_t *range_lo = nullptr;
+    PRec *prec = nullptr;
     int32_t *split_right = nullptr, *nflags = nullptr;
     Node *nodes = nullptr;
     int32_t *inst_root = nullptr, *inst_stop = nullptr;
@@ -144,12 +151,20 @@ struct tril_ctx {
     double ms_acc[4] = {0, 0, 0, 0};   // summed event times of pairs already read and recycled
     int64_t timed_launches = 0;
 
-    // captured step-batch graph
-    hipGraphExec_t gexec = nullptr;
-    std::vector<const void *> gkey;
+    // working copies of the two beams for tril_run (two buffers each): rows in the Morton
+    // order of the first step of the previous batch, so that the gathers of the build and
+    // of the traversal touch nearby memory
+    WorkBeam wt[2], wq[2];
+    const uint32_t *t_rows = nullptr;      // sorted rows of the last build
+
+    // captured step-batch graphs (one per working-buffer parity)
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    std::vector<const void *> gkey[2];
+    int g_next = 0;
     uint64_t alloc_gen = 0;         // bumped on every (re)allocation of scratch
 
-    BeamDev last_q{};               // query beam of the last collide (for yield/spectrum)
+    BeamDev res_t{};                // caller's target beam of the last build or run (statistics)
+    BeamDev last_q{};               // caller's query beam of the last collide (statistics)
     int64_t max_nq = 0;
 };
 
@@ -173,8 +188,7 @@ int ensure_sort_scratch(tril_ctx *c, int64_t n) {
 void free_target(tril_ctx *c) {
     dev_free(c->t_box); dev_free(c->t_spart); dev_free(c->t_k32a); dev_free(c->t_k32b);
     dev_free(c->t_k64a); dev_free(c->t_k64b); dev_free(c->t_va); dev_free(c->t_vb);
-    dev_free(c->left); dev_free(c->right); dev_free(c->parent); dev_free(c->range_hi);
-    dev_free(c->range_lo); dev_free(c->split_right); dev_free(c->nflags); dev_free(c->nodes);
+    dev_free(c->prec); dev_free(c->split_right); dev_free(c->nflags); dev_free(c->nodes);
     c->t_cap = 0;
 }
 
@@ -189,9 +203,7 @@ int ensure_target(tril_ctx *c, int64_t nv, int64_t n_comb, int32_t n_inst) {
         CHK(dev_alloc(&c->t_k32a, m)); CHK(dev_alloc(&c->t_k32b, m));
         CHK(dev_alloc(&c->t_k64a, m)); CHK(dev_alloc(&c->t_k64b, m));
         CHK(dev_alloc(&c->t_va, m)); CHK(dev_alloc(&c->t_vb, m));
-        CHK(dev_alloc(&c->left, m)); CHK(dev_alloc(&c->right, m));
-        CHK(dev_alloc(&c->parent, 2 * m)); CHK(dev_alloc(&c->range_hi, m));
-        CHK(dev_alloc(&c->range_lo, m));
+        CHK(dev_alloc(&c->prec, 2 * m));
         CHK(dev_alloc(&c->split_right, m)); CHK(dev_alloc(&c->nflags, m));
         CHK(dev_alloc(&c->nodes, 2 * m));
         c->t_cap = m;
@@ -301,7 +313,63 @@ BeamDev view(const tril_beam *b, const int64_t *d_off, int32_t m) {
     v.n_inst = b->n_inst;
     v.inst_off = b->n_inst > 1 ? d_off : nullptr;
     v.m = m;
+    v.perm = nullptr;
     return v;
+}
+
+void free_work(WorkBeam &w) {
+    dev_free(w.soa);
+    dev_free(w.perm);
+    w.cap = 0;
+}
+
+int ensure_work(tril_ctx *c, WorkBeam *w, int64_t n) {
+    if (n <= w[0].cap) return TRIL_OK;
+    ++c->alloc_gen;
+    for (int p = 0; p < 2; ++p) {
+        free_work(w[p]);
+        const int64_t m = std::max<int64_t>(n, 1);
+        CHK(dev_alloc(&w[p].soa, (size_t)(8 * m)));
+        CHK(dev_alloc(&w[p].perm, (size_t)m));
+        w[p].cap = m;
+    }
+    return TRIL_OK;
+}
+
+// View of a working copy (same rows and instances as the caller's beam b).
+BeamDev wview(const tril_beam *b, const int64_t *d_off, int32_t m, const WorkBeam &w) {
+    BeamDev v = view(b, d_off, m);
+    const int64_t n = b->n;
+    v.x = w.soa; v.y = w.soa + n; v.z = w.soa + 2 * n;
+    v.px = w.soa + 3 * n; v.py = w.soa + 4 * n; v.pz = w.soa + 5 * n;
+    v.E = w.soa + 6 * n; v.w = w.soa + 7 * n;
+    v.perm = w.perm;
+    return v;
+}
+
+// Working copy w of beam b (one step) in the order of the full-precision Morton codes
+// of its boxes at the device step index, using the box and key scratch of its side
+// (sized for at least b.n elements).
+int enqueue_order(tril_ctx *c, const BeamDev &b, bool query_side, WorkBeam &w, hipStream_t st) {
+    if (b.n <= 0) return TRIL_OK;
+    const KeyLayout kl = key_layout(b.n_inst, 30);
+    const InstStats *stats = query_side ? c->q_stats : c->t_stats;
+    PBox *box = query_side ? c->q_box : c->t_box;
+    uint32_t *k32a = query_side ? c->q_k32a : c->t_k32a, *k32b = query_side ? c->q_k32b : c->t_k32b;
+    unsigned long long *k64a = query_side ? c->q_k64a : c->t_k64a;
+    unsigned long long *k64b = query_side ? c->q_k64b : c->t_k64b;
+    uint32_t *va = query_side ? c->q_va : c->t_va, *vb = query_side ? c->q_vb : c->t_vb;
+    launch_boxes_keys(b, false, c->dt, c->sigma_up, stats, stats, kl, box, k32a, k64a, va,
+                      c->d_cnt, st);
+    const uint32_t *rows;
+    if (!kl.wide)
+        rows = radix_sort_u32(k32a, va, k32b, vb, b.n, kl.key_bits, c->ss, &c->d_cnt->err, st)
+                   ? vb : va;
+    else
+        rows = radix_sort_u64(k64a, va, k64b, vb, b.n, kl.key_bits, c->ss, &c->d_cnt->err, st)
+                   ? vb : va;
+    launch_gather_beam(b, rows, w.soa, w.perm, st);
+    return TRIL_OK;
 }
 
 int timing_pair(tril_ctx *c, hipStream_t st, std::vector<std::array<int, 2>> &dst, bool begin) {
@@ -329,7 +397,7 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
     const BeamDev &t = c->tgt;
     const int64_t nv = (int64_t)t.m * t.n;
     const int32_t n_comb = t.m * t.n_inst;
-    const KeyLayout kl = key_layout(n_comb);
+    const KeyLayout kl = key_layout(n_comb, c->morton_bits);
     if (timed) CHK(timing_pair(c, st, c->ev_build, true));
     launch_prologue(c->d_cnt, 0, t.m, st);
     launch_boxes_keys(t, false, c->dt, c->sigma_up, c->t_stats, c->t_stats, kl, c->t_box, c->t_k32a,
@@ -341,19 +409,17 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
                                         c->ss, &c->d_cnt->err, st);
         const uint32_t *keys = alt ? c->t_k32b : c->t_k32a;
         rows = alt ? c->t_vb : c->t_va;
-        launch_karras_u32(keys, nv, kl.prefix_shift, c->left, c->right, c->parent, c->range_lo,
-                          c->range_hi, c->split_right, c->nflags, roots, st);
+        launch_karras_u32(keys, nv, kl.prefix_shift, c->prec, c->split_right, c->nflags, roots, st);
     } else {
         const bool alt = radix_sort_u64(c->t_k64a, c->t_va, c->t_k64b, c->t_vb, nv, kl.key_bits,
                                         c->ss, &c->d_cnt->err, st);
         const unsigned long long *keys = alt ? c->t_k64b : c->t_k64a;
         rows = alt ? c->t_vb : c->t_va;
-        launch_karras_u64(keys, nv, kl.prefix_shift, c->left, c->right, c->parent, c->range_lo,
-                          c->range_hi, c->split_right, c->nflags, roots, st);
+        launch_karras_u64(keys, nv, kl.prefix_shift, c->prec, c->split_right, c->nflags, roots, st);
     }
+    c->t_rows = rows;
     launch_inst_roots(t, n_comb == 1, c->split_right, c->inst_root, c->inst_stop, st);
-    launch_refit(c->t_box, rows, nv, c->left, c->right, c->parent, c->range_lo, c->range_hi,
-                 c->split_right, c->nflags, c->nodes, &c->d_cnt->err, st);
+    launch_refit(c->t_box, rows, nv, c->prec, c->split_right, c->nflags, c->nodes, &c->d_cnt->err, st);
     if (timed) CHK(timing_pair(c, st, c->ev_build, false));
     HIPCHK(hipGetLastError());
     return TRIL_OK;
@@ -366,7 +432,7 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
                     bool timed, bool sort_queries) {
     const int64_t nv = (int64_t)q.m * q.n;
     const int32_t n_comb = q.m * q.n_inst;
-    const KeyLayout kl = key_layout(n_comb);
+    const KeyLayout kl = key_layout(n_comb, c->morton_bits);
     if (timed) CHK(timing_pair(c, st, c->ev_prep, true));
     launch_prologue(c->d_cnt, 1, q.m, st);
     launch_boxes_keys(q, true, c->dt, c->sigma_up, c->t_stats, c->q_stats, kl, c->q_box, c->q_k32a,
@@ -471,6 +537,15 @@ void fold_events(tril_ctx *c) {
 
 // Steps per launch for tril_run: the parameter if set, else as many as keep the
 // virtual element count of one launch within kBatchBudget.
+// Morton bits for the batches of tril_run (both beams already in full-precision Morton
+// order): the parameter if set, else as many as keep prefix + Morton bits within three
+// 8-bit radix passes, between 18 and 30.
+int run_morton_bits(const tril_ctx *c, int64_t n_comb) {
+    if (c->morton_param > 0) return c->morton_param;
+    const int p = bits_for((uint64_t)(n_comb > 1 ? n_comb - 1 : 0));
+    return std::min(30, std::max(18, 24 - p));
+}
+
 int32_t pick_batch(const tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t n_steps) {
     const int64_t rows = std::max<int64_t>(std::max(t->n, q->n), 1);
     int64_t m = c->step_batch > 0 ? c->step_batch : std::max<int64_t>(1, kBatchBudget / rows);
@@ -540,6 +615,7 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
     *out = nullptr;
     if (!std::isfinite(p->dt) || !(p->dt > 0.0)) return TRIL_E_INVAL;
     if (p->n_bins < 0 || p->cand_cap < 0 || p->step_batch < 0) return TRIL_E_INVAL;
+    if (p->morton_bits != 0 && (p->morton_bits < 3 || p->morton_bits > 30)) return TRIL_E_INVAL;
     if (p->flags & ~(TRIL_TIMING | TRIL_SORT_QUERIES_ONCE)) return TRIL_E_NOTIMPL;
     if (p->n_bins > 0) {
         if (!p->bin_edges) return TRIL_E_INVAL;
@@ -559,6 +635,7 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
     c->cand_cap_param = p->cand_cap;
     c->block = blk;
     c->step_batch = p->step_batch;
+    c->morton_param = p->morton_bits;
     c->sigma_up = host_sigma_max() * (1.0 + 1e-6);
     int r = TRIL_OK;
     auto fail = [&](int code) {
@@ -590,10 +667,12 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
 int tril_build(tril_ctx *c, const tril_beam *b, int32_t step) {
     if (!c || step < 0) return TRIL_E_INVAL;
     CHK(check_beam(b));
+    c->morton_bits = c->morton_param > 0 ? c->morton_param : 30;
     CHK(ensure_target(c, b->n, b->n_inst, b->n_inst));
     CHK(upload_offsets(c, b, c->d_t_off, c->h_t_off));
     c->nt = b->n;
     c->tgt = view(b, c->d_t_off, 1);
+    c->res_t = c->tgt;
     launch_set_step(c->d_cnt, step, c->st);
     launch_beam_stats(c->tgt, c->t_spart, c->t_stats, c->d_cnt, c->st);
     CHK(enqueue_build(c, c->st, (c->flags & TRIL_TIMING) != 0));
@@ -609,6 +688,7 @@ int tril_collide(tril_ctx *c, const tril_beam *q, int32_t step, tril_pairs *out)
     CHK(check_pairs(out));
     if (!c->built || c->tgt.m != 1 || step != c->built_step || q->n_inst != c->tgt.n_inst)
         return TRIL_E_STATE;
+    c->morton_bits = c->morton_param > 0 ? c->morton_param : 30;
     CHK(ensure_query(c, q->n, q->n_inst, q->n_inst));
     CHK(upload_offsets(c, q, c->d_q_off, c->h_q_off));
     const BeamDev qv = view(q, c->d_q_off, 1);
@@ -634,86 +714,122 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     // capacities for the largest batch first, so that nothing is reallocated later
     CHK(ensure_target(c, (int64_t)m * t->n, (int64_t)m * t->n_inst, t->n_inst));
     CHK(ensure_query(c, (int64_t)m * q->n, (int64_t)m * q->n_inst, q->n_inst));
+    CHK(ensure_work(c, c->wt, t->n));
+    CHK(ensure_work(c, c->wq, q->n));
     CHK(upload_offsets(c, t, c->d_t_off, c->h_t_off));
     CHK(upload_offsets(c, q, c->d_q_off, c->h_q_off));
     c->nt = t->n;
-    launch_beam_stats(view(t, c->d_t_off, 1), c->t_spart, c->t_stats, c->d_cnt, c->st);
-    launch_beam_stats(view(q, c->d_q_off, 1), c->q_spart, c->q_stats, c->d_cnt, c->st);
+    c->q_order_key = nullptr;  // the sort buffers are reused below
+    const BeamDev t1 = view(t, c->d_t_off, 1), q1 = view(q, c->d_q_off, 1);
+    launch_beam_stats(t1, c->t_spart, c->t_stats, c->d_cnt, c->st);
+    launch_beam_stats(q1, c->q_spart, c->q_stats, c->d_cnt, c->st);
+    // working copies in the caller's order; after every batch they are rewritten in the
+    // Morton order of that batch's first step (a relabelling of rows: the pair set does
+    // not depend on it, and the narrow phase reports caller rows)
+    // first, both beams in the order of their full 30-bit Morton codes at step k0
+    int pt = 0, pq = 0;
+    launch_set_step(c->d_cnt, k0, c->st);
+    CHK(enqueue_order(c, t1, false, c->wt[0], c->st));
+    CHK(enqueue_order(c, q1, true, c->wq[0], c->st));
+    c->morton_bits = run_morton_bits(c, (int64_t)m * t->n_inst);
+    const bool once = (c->flags & TRIL_SORT_QUERIES_ONCE) != 0;
+    bool q_sorted = false;
+    const bool timed = (c->flags & TRIL_TIMING) != 0;
+
+    // Batch of mb steps with working buffers (pt, pq) on stream st: build, collide, and
+    // rewrite the working copies for the next batch.
+    auto enqueue_batch = [&](int32_t mb, bool sort, hipStream_t st, bool tm) -> int {
+        c->tgt = wview(t, c->d_t_off, mb, c->wt[pt]);
+        const BeamDev qv = wview(q, c->d_q_off, mb, c->wq[pq]);
+        CHK(enqueue_build(c, st, tm));
+        if (!sort) {
+            c->q_order = nullptr;  // the working copy is already in Morton order
+            c->q_order_len = 0;
+        }
+        CHK(enqueue_collide(c, qv, *out, st, tm, sort));
+        launch_gather_beam(wview(t, c->d_t_off, 1, c->wt[pt]), c->t_rows, c->wt[pt ^ 1].soa,
+                           c->wt[pt ^ 1].perm, st);
+        if (sort)
+            launch_gather_beam(wview(q, c->d_q_off, 1, c->wq[pq]), c->q_order, c->wq[pq ^ 1].soa,
+                               c->wq[pq ^ 1].perm, st);
+        return TRIL_OK;
+    };
+    auto flip = [&](bool sort) {
+        pt ^= 1;
+        if (sort) pq ^= 1;
+    };
+
     int32_t k = k0;
     int32_t left = n_steps;
-    // with a query order kept from the first step, that step runs alone first
-    if ((c->flags & TRIL_SORT_QUERIES_ONCE) && need_query_sort(c, q)) {
-        CHK(tril_build(c, t, k));
-        CHK(tril_collide(c, q, k, out));
-        ++k;
-        --left;
-    }
-    const bool timed = (c->flags & TRIL_TIMING) != 0;
     while (left > 0) {
         const int32_t mb = std::min(m, left);
-        const bool sort = need_query_sort(c, q);
-        c->tgt = view(t, c->d_t_off, mb);
-        const BeamDev qv = view(q, c->d_q_off, mb);
-        if (timed || mb != m) {
-            // eager batch (per-phase events, or the shorter last batch)
+        const bool sort = !once || !q_sorted;
+        if (timed || mb != m || sort != (!once)) {
+            // eager batch (per-phase events, the shorter last batch, or the one batch that
+            // orders the queries when they are ordered once)
             launch_set_step(c->d_cnt, k, c->st);
-            CHK(enqueue_build(c, c->st, timed));
-            CHK(enqueue_collide(c, qv, *out, c->st, timed, sort));
-            if (sort) CHK(note_query_sorted(c, q, mb, c->st));
+            CHK(enqueue_batch(mb, sort, c->st, timed));
+            flip(sort);
+            q_sorted = q_sorted || sort;
             k += mb;
             left -= mb;
             continue;
         }
-        // full batches: one captured graph, replayed; the step index lives on the device
+        // full batches: captured graphs (one per buffer parity), replayed; the step index
+        // lives on the device
         const int32_t n_rep = left / m;
-        std::vector<const void *> key = {t->x, t->y, t->z, t->px, t->py, t->pz, t->E, t->w,
-                                         q->x, q->y, q->z, q->px, q->py, q->pz, q->E, q->w,
-                                         out->i, out->j, out->step, out->count,
-                                         (const void *)(intptr_t)t->n, (const void *)(intptr_t)q->n,
-                                         (const void *)(intptr_t)t->n_inst,
-                                         (const void *)(intptr_t)out->cap,
-                                         (const void *)(intptr_t)sort, c->q_order,
-                                         (const void *)(intptr_t)c->q_order_len,
-                                         (const void *)(intptr_t)m,
-                                         (const void *)(uintptr_t)c->alloc_gen};
-        if (!c->gexec || key != c->gkey) {
-            if (c->gexec) {
-                (void)hipGraphExecDestroy(c->gexec);
-                c->gexec = nullptr;
-            }
-            hipGraph_t g = nullptr;
-            HIPCHK(hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
-            int r1 = enqueue_build(c, c->gst, false);
-            int r2 = r1 == TRIL_OK ? enqueue_collide(c, qv, *out, c->gst, false, sort) : r1;
-            launch_advance_step(c->d_cnt, m, c->gst);
-            hipError_t e = hipStreamEndCapture(c->gst, &g);
-            if (r2 != TRIL_OK) {
-                if (g) (void)hipGraphDestroy(g);
-                return r2;
-            }
-            if (e != hipSuccess) return hip_fail(e);
-            e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) {
-                c->gexec = nullptr;
-                return hip_fail(e);
-            }
-            c->gkey = key;
-        }
         launch_set_step(c->d_cnt, k, c->st);
         HIPCHK(hipEventRecord(c->ev_join_a, c->st));
         HIPCHK(hipStreamWaitEvent(c->gst, c->ev_join_a, 0));
-        for (int32_t r = 0; r < n_rep; ++r) HIPCHK(hipGraphLaunch(c->gexec, c->gst));
+        for (int32_t r = 0; r < n_rep; ++r) {
+            std::vector<const void *> key = {
+                c->wt[pt].soa, c->wq[pq].soa, c->wt[pt ^ 1].soa, c->wq[pq ^ 1].soa,
+                out->i, out->j, out->step, out->count,
+                (const void *)(intptr_t)t->n, (const void *)(intptr_t)q->n,
+                (const void *)(intptr_t)t->n_inst, (const void *)(intptr_t)out->cap,
+                (const void *)(intptr_t)sort, c->d_t_off, c->d_q_off,
+                (const void *)(intptr_t)m, (const void *)(intptr_t)c->morton_bits,
+                (const void *)(uintptr_t)c->alloc_gen};
+            int slot = (c->gexec[0] && key == c->gkey[0]) ? 0
+                       : (c->gexec[1] && key == c->gkey[1]) ? 1 : -1;
+            if (slot < 0) {
+                slot = c->g_next;
+                c->g_next ^= 1;
+                if (c->gexec[slot]) {
+                    (void)hipGraphExecDestroy(c->gexec[slot]);
+                    c->gexec[slot] = nullptr;
+                }
+                hipGraph_t g = nullptr;
+                HIPCHK(hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
+                int r1 = enqueue_batch(m, sort, c->gst, false);
+                launch_advance_step(c->d_cnt, m, c->gst);
+                hipError_t e = hipStreamEndCapture(c->gst, &g);
+                if (r1 != TRIL_OK) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return r1;
+                }
+                if (e != hipSuccess) return hip_fail(e);
+                e = hipGraphInstantiate(&c->gexec[slot], g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) {
+                    c->gexec[slot] = nullptr;
+                    return hip_fail(e);
+                }
+                c->gkey[slot] = key;
+            }
+            HIPCHK(hipGraphLaunch(c->gexec[slot], c->gst));
+            flip(sort);
+        }
         HIPCHK(hipEventRecord(c->ev_join_b, c->gst));
         HIPCHK(hipStreamWaitEvent(c->st, c->ev_join_b, 0));
-        if (sort) CHK(note_query_sorted(c, q, m, c->st));
         k += n_rep * m;
         left -= n_rep * m;
     }
     c->built = true;
     c->built_step = k0 + n_steps - 1;
     c->max_step = std::max(c->max_step, c->built_step);
-    c->last_q = view(q, c->d_q_off, 1);
+    c->res_t = t1;
+    c->last_q = q1;
     c->max_nq = std::max(c->max_nq, q->n);
     return TRIL_OK;
 }
@@ -763,7 +879,7 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     const int32_t nsc = out->step_counts ? out->n_step_counts : 0;
     CHK(ensure_stats(c, n_hits, std::max(nsc, 1)));
     run_union_stats(*p, n_hits, std::max<int64_t>(c->nt, 1), step_bits, pair_bits + step_bits,
-                    c->last_q.w, c->tgt.w, c->last_q.E, c->tgt.E, c->d_edges, c->n_bins, nsc,
+                    c->last_q.w, c->res_t.w, c->last_q.E, c->res_t.E, c->d_edges, c->n_bins, nsc,
                     c->sst, c->ss, &c->d_cnt->err, c->st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->st));
@@ -804,8 +920,13 @@ void tril_destroy(tril_ctx *c) {
     if (!c) return;
     if (c->st) (void)hipStreamSynchronize(c->st);
     if (c->gst) (void)hipStreamSynchronize(c->gst);
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    for (hipGraphExec_t &g : c->gexec)
+        if (g) (void)hipGraphExecDestroy(g);
     free_target(c);
+    for (int p = 0; p < 2; ++p) {
+        free_work(c->wt[p]);
+        free_work(c->wq[p]);
+    }
     dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->inst_root); dev_free(c->inst_stop);
     dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
     dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);

@@ -307,6 +307,8 @@ __global__ void __launch_bounds__(256) k_fold_stats(const StatsPartial *__restri
 // Morton quantisation box of instance m at step k: the box centre is x0 + tau u with
 // tau = t_k + dt/2 >= 0, so [min x0 + tau min u, max x0 + tau max u] per axis contains
 // every centre (clamping absorbs rounding).
+// One thread per row, looping over the m steps of the launch: the row's photon data
+// is read once and its m boxes and keys are written at the virtual elements s n + i.
 template <bool kWide>
 __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, double dt,
                                                     double sigma_up,
@@ -317,68 +319,98 @@ __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, double
                                                     unsigned long long *__restrict__ keys64,
                                                     uint32_t *__restrict__ vals,
                                                     const DevCounters *__restrict__ c) {
-    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t nv = (int64_t)b.m * b.n;
-    if (e >= nv) return;
-    const VIdx v = vdecode(b, e);
-    const int64_t i = v.i;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= b.n) return;
+    const int32_t mi = b.n_inst > 1 ? find_inst(b.inst_off, b.n_inst, i) : 0;
     const double E = b.E[i], w = b.w[i];
     const double px = b.px[i], py = b.py[i], pz = b.pz[i];
     const double x = b.x[i], y = b.y[i], z = b.z[i];
     const bool ok = isfinite(E) && isfinite(w) && isfinite(px) && isfinite(py) && isfinite(pz) &&
                     isfinite(x) && isfinite(y) && isfinite(z) && E > 0.0 && w >= 0.0;
-    const double t = (double)(c->step + (unsigned)v.s) * dt;
-    PBox o;
-    o.pad = v.c;
-    float cen[3] = {0.f, 0.f, 0.f};
-    if (!ok) {
-        o.lox = o.loy = o.loz = INFINITY;
-        o.hix = o.hiy = o.hiz = -INFINITY;
-        o.tag = -1;
-    } else {
-        const double ux = px / E, uy = py / E, uz = pz / E;
-        // position at t_k exactly as the narrow phase forms it, and one step later
-        const double ax = x + t * ux, ay = y + t * uy, az = z + t * uz;
-        const double bx = ax + dt * ux, by = ay + dt * uy, bz = az + dt * uz;
-        double pad = 0.0;
-        int32_t tag = v.c;
-        if (query) {
-            const InstStats &ts = t_stats[v.mi];
-            const double emax_t = __longlong_as_double((long long)ts.emax);
-            const double wmax_t = __longlong_as_double((long long)ts.wmax);
-            const double smax = (E * emax_t) / (kMe * kMe);
-            if (!(smax > 1.0)) tag = -1;
-            pad = sqrt((sqrt(w * wmax_t) * sigma_up) / M_PI) * (1.0 + 1e-6);
-        }
-        // slack far above FP64 rounding of the positions (1e-12 of the magnitude)
-        const double lo[3] = {fmin(ax, bx), fmin(ay, by), fmin(az, bz)};
-        const double hi[3] = {fmax(ax, bx), fmax(ay, by), fmax(az, bz)};
-        float lo32[3], hi32[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            lo32[a] = f32_down(lo[a] - (pad + 1e-12 * (1.0 + fabs(lo[a]))));
-            hi32[a] = f32_up(hi[a] + (pad + 1e-12 * (1.0 + fabs(hi[a]))));
-            cen[a] = (float)(0.5 * (lo[a] + hi[a]));
-        }
-        o.lox = lo32[0]; o.loy = lo32[1]; o.loz = lo32[2];
-        o.hix = hi32[0]; o.hiy = hi32[1]; o.hiz = hi32[2];
-        o.tag = tag;
+    const double ux = px / E, uy = py / E, uz = pz / E;
+    double pad = 0.0;
+    bool below = false;
+    if (query && ok) {
+        const InstStats &ts = t_stats[mi];
+        const double emax_t = __longlong_as_double((long long)ts.emax);
+        const double wmax_t = __longlong_as_double((long long)ts.wmax);
+        const double smax = (E * emax_t) / (kMe * kMe);
+        below = !(smax > 1.0);
+        pad = sqrt((sqrt(w * wmax_t) * sigma_up) / M_PI) * (1.0 + 1e-6);
     }
-    out[e] = o;
-    const InstStats &ss = self_stats[v.mi];
-    const double tau = t + 0.5 * dt;
-    float blo[3], bhi[3];
+    const InstStats &ss = self_stats[mi];
+    double mn0[3], mnu[3], mx0[3], mxu[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        blo[a] = (float)(ord2d(ss.mn[a]) + tau * ord2d(ss.mn[3 + a]));
-        bhi[a] = (float)(ord2d(ss.mx[a]) + tau * ord2d(ss.mx[3 + a]));
+        mn0[a] = ord2d(ss.mn[a]);
+        mnu[a] = ord2d(ss.mn[3 + a]);
+        mx0[a] = ord2d(ss.mx[a]);
+        mxu[a] = ord2d(ss.mx[3 + a]);
     }
-    const uint32_t code = morton30(cen, blo, bhi) >> (30 - kl.morton_bits);
-    if (kWide)
-        keys64[e] = ((unsigned long long)(uint32_t)v.c << kl.prefix_shift) | code;
-    else
-        keys32[e] = ((uint32_t)v.c << kl.prefix_shift) | code;
-    vals[e] = (uint32_t)e;
+    const unsigned step0 = c->step;
+    for (int32_t s = 0; s < b.m; ++s) {
+        const int64_t e = (int64_t)s * b.n + i;
+        const int32_t cc = s * b.n_inst + mi;
+        const double t = (double)(step0 + (unsigned)s) * dt;
+        PBox o;
+        o.pad = cc;
+        float cen[3] = {0.f, 0.f, 0.f};
+        if (!ok) {
+            o.lox = o.loy = o.loz = INFINITY;
+            o.hix = o.hiy = o.hiz = -INFINITY;
+            o.tag = -1;
+        } else {
+            // position at t_k exactly as the narrow phase forms it, and one step later
+            const double ax = x + t * ux, ay = y + t * uy, az = z + t * uz;
+            const double bx = ax + dt * ux, by = ay + dt * uy, bz = az + dt * uz;
+            // slack far above FP64 rounding of the positions (1e-12 of the magnitude)
+            const double lo[3] = {fmin(ax, bx), fmin(ay, by), fmin(az, bz)};
+            const double hi[3] = {fmax(ax, bx), fmax(ay, by), fmax(az, bz)};
+            float lo32[3], hi32[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo32[a] = f32_down(lo[a] - (pad + 1e-12 * (1.0 + fabs(lo[a]))));
+                hi32[a] = f32_up(hi[a] + (pad + 1e-12 * (1.0 + fabs(hi[a]))));
+                cen[a] = (float)(0.5 * (lo[a] + hi[a]));
+            }
+            o.lox = lo32[0]; o.loy = lo32[1]; o.loz = lo32[2];
+            o.hix = hi32[0]; o.hiy = hi32[1]; o.hiz = hi32[2];
+            o.tag = below ? -1 : cc;
+        }
+        out[e] = o;
+        const double tau = t + 0.5 * dt;
+        float blo[3], bhi[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            blo[a] = (float)(mn0[a] + tau * mnu[a]);
+            bhi[a] = (float)(mx0[a] + tau * mxu[a]);
+        }
+        const uint32_t code = morton30(cen, blo, bhi) >> (30 - kl.morton_bits);
+        if (kWide)
+            keys64[e] = ((unsigned long long)(uint32_t)cc << kl.prefix_shift) | code;
+        else
+            keys32[e] = ((uint32_t)cc << kl.prefix_shift) | code;
+        vals[e] = (uint32_t)e;
+    }
+}
+
+// Working copy of a beam in another row order (see launch_gather_beam).
+__global__ void __launch_bounds__(256) k_gather_beam(BeamDev src, const uint32_t *__restrict__ order,
+                                                     double *__restrict__ dst,
+                                                     int32_t *__restrict__ dst_perm) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t n = src.n;
+    if (k >= n) return;
+    const int64_t r = order ? (int64_t)order[k] : k;
+    dst[k] = src.x[r];
+    dst[n + k] = src.y[r];
+    dst[2 * n + k] = src.z[r];
+    dst[3 * n + k] = src.px[r];
+    dst[4 * n + k] = src.py[r];
+    dst[5 * n + k] = src.pz[r];
+    dst[6 * n + k] = src.E[r];
+    dst[7 * n + k] = src.w[r];
+    dst_perm[k] = src.perm ? src.perm[r] : (int32_t)r;
 }
 
 __global__ void __launch_bounds__(256) k_morton_u32(const PBox *__restrict__ box, int64_t n,
@@ -412,12 +444,7 @@ __device__ __forceinline__ int delta(const K *__restrict__ keys, int64_t n, int6
 
 template <typename K>
 __global__ void __launch_bounds__(256) k_karras(const K *__restrict__ keys, int64_t n,
-                                                int prefix_shift,
-                                                int32_t *__restrict__ left,
-                                                int32_t *__restrict__ right,
-                                                int32_t *__restrict__ parent,
-                                                int32_t *__restrict__ range_lo,
-                                                int32_t *__restrict__ range_hi,
+                                                int prefix_shift, PRec *__restrict__ prec,
                                                 int32_t *__restrict__ split_right,
                                                 int32_t *__restrict__ flags,
                                                 int32_t *__restrict__ inst_root) {
@@ -443,15 +470,14 @@ __global__ void __launch_bounds__(256) k_karras(const K *__restrict__ keys, int6
     const int32_t leaf0 = (int32_t)(n - 1);
     const int32_t lc = (lo == gamma) ? (int32_t)(leaf0 + gamma) : (int32_t)gamma;
     const int32_t rc = (hi == gamma + 1) ? (int32_t)(leaf0 + gamma + 1) : (int32_t)(gamma + 1);
-    left[i] = lc;
-    right[i] = rc;
-    parent[lc] = (int32_t)i;
-    parent[rc] = (int32_t)i;
-    range_lo[i] = (int32_t)lo;
-    range_hi[i] = (int32_t)hi;
+    const int4 rl = make_int4((int32_t)i, rc, (int32_t)lo, (int32_t)hi);
+    const int4 rr = make_int4((int32_t)i, (int32_t)((uint32_t)lc | 0x80000000u), (int32_t)lo,
+                              (int32_t)hi);
+    reinterpret_cast<int4 *>(prec)[lc] = rl;
+    reinterpret_cast<int4 *>(prec)[rc] = rr;
     split_right[gamma] = rc;
     flags[i] = 0;
-    if (i == 0) parent[0] = -1;
+    if (i == 0) reinterpret_cast<int4 *>(prec)[0] = make_int4(-1, 0, 0, (int32_t)(n - 1));
     if (inst_root != nullptr) {
         // node whose range is exactly one combined instance's run of keys (same prefix)
         const K pl = keys[lo] >> prefix_shift, ph = keys[hi] >> prefix_shift;
@@ -517,46 +543,61 @@ __device__ __forceinline__ void load_box(const Node *n, float lo[3], float hi[3]
     hi[2] = __uint_as_float((uint32_t)w[3]);
 }
 
-constexpr int kRefitChunk = 1024;  // leaves (and threads) per workgroup
+constexpr int kRefitChunk = 512;  // leaves (and threads) per workgroup
 
-// Bottom-up box refit in two regimes. A workgroup owns a chunk of 1024 consecutive
-// leaves; every internal node whose leaf range lies inside the chunk has its id in the
-// chunk too (a node's id is one end of its range), so its arrival flag and box live in
-// LDS and the second child to arrive merges the boxes there. Nodes whose range crosses
-// a chunk boundary (the few levels of the top of the tree) use global arrival flags and
-// device-coherent loads and stores. A node is written once, when its thread knows its
-// parent: with a coherent store if the parent crosses the chunk (a thread elsewhere may
-// read it), with plain stores otherwise.
+// Bottom-up box refit in two regimes. A workgroup owns a chunk of consecutive leaves;
+// every internal node whose leaf range lies inside the chunk has its id in the chunk
+// too (a node's id is one end of its range). The chunk's parent records, leaf boxes
+// and split targets are staged in LDS first, so the levels inside the chunk touch no
+// global memory but their node stores: the arrival flag and the box of such a node
+// live in LDS, and the second child to arrive merges the boxes there. Nodes whose
+// parent range crosses a chunk boundary (the few levels of the top of the tree) use
+// global arrival flags and device-coherent loads and stores. A node is written once,
+// when its thread knows its parent: with a coherent store if the parent crosses the
+// chunk (a thread elsewhere may read it), with plain stores otherwise.
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ box,
                                                        const uint32_t *__restrict__ rows, int64_t n,
-                                                       const int32_t *__restrict__ left,
-                                                       const int32_t *__restrict__ right,
-                                                       const int32_t *__restrict__ parent,
-                                                       const int32_t *__restrict__ range_lo,
-                                                       const int32_t *__restrict__ range_hi,
+                                                       const PRec *__restrict__ prec,
                                                        const int32_t *__restrict__ split_right,
                                                        int32_t *flags, Node *nodes, unsigned int *err) {
     __shared__ float s_leaf[6][kRefitChunk];
     __shared__ float s_int[6][kRefitChunk];
     __shared__ int32_t s_flag[kRefitChunk];
+    // records: [0, chunk) the chunk's leaves, [chunk, 2 chunk) internal ids in the chunk
+    __shared__ i32x4 s_rec[2 * kRefitChunk];
+    __shared__ int32_t s_split[kRefitChunk];
+    const i32x4 *grec = reinterpret_cast<const i32x4 *>(prec);
     const int64_t c0 = blockIdx.x * (int64_t)kRefitChunk;
     const int64_t c1 = (c0 + kRefitChunk < n ? c0 + kRefitChunk : n) - 1;  // last leaf of the chunk
-    s_flag[threadIdx.x] = 0;
-    const int64_t j = c0 + threadIdx.x;
+    const int64_t leaf0 = n - 1;
+    const int tid = threadIdx.x;
+    s_flag[tid] = 0;
+    const int64_t j = c0 + tid;
     const bool in = j < n;
     Node cn;  // node of `cur`, not yet stored
     int32_t cur = -1;
     if (in) {
+        // independent loads first, the box gather (needs the row) last
         const uint32_t row = rows[j];
+        i32x4 rl = {0, 0, 0, 0}, ri = {0, 0, 0, 0};
+        if (n > 1) {
+            rl = grec[leaf0 + j];
+            if (j < leaf0) ri = grec[j];
+        }
+        const int32_t sr = (j == n - 1) ? -1 : split_right[j];
         const PBox bx = box[row];
+        s_rec[tid] = rl;
+        s_rec[kRefitChunk + tid] = ri;
+        s_split[tid] = sr;
         cn.lox = bx.lox; cn.loy = bx.loy; cn.loz = bx.loz;
         cn.hix = bx.hix; cn.hiy = bx.hiy; cn.hiz = bx.hiz;
         cn.link = (int32_t)row;
-        cn.rope = (j == n - 1) ? -1 : split_right[j];
-        cur = (int32_t)(n - 1 + j);
-        s_leaf[0][threadIdx.x] = cn.lox; s_leaf[1][threadIdx.x] = cn.loy;
-        s_leaf[2][threadIdx.x] = cn.loz; s_leaf[3][threadIdx.x] = cn.hix;
-        s_leaf[4][threadIdx.x] = cn.hiy; s_leaf[5][threadIdx.x] = cn.hiz;
+        cn.rope = sr;
+        cur = (int32_t)(leaf0 + j);
+        s_leaf[0][tid] = cn.lox; s_leaf[1][tid] = cn.loy; s_leaf[2][tid] = cn.loz;
+        s_leaf[3][tid] = cn.hix; s_leaf[4][tid] = cn.hiy; s_leaf[5][tid] = cn.hiz;
     }
     __syncthreads();
     if (!in) return;
@@ -564,10 +605,54 @@ __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ 
         store_node_plain(nodes + cur, cn);
         return;
     }
-    const int64_t leaf0 = n - 1;
-    for (int level = 0;; ++level) {
-        const int32_t p = parent[cur];
+    // Inside the chunk: cur is one of the chunk's leaves (first level) or an internal
+    // node with its id in the chunk, so its record is in LDS.
+    i32x4 r;
+    for (;;) {
+        r = s_rec[cur >= leaf0 ? (int32_t)(cur - leaf0 - c0) : (int32_t)(kRefitChunk + cur - c0)];
+        const int32_t p = r.x;
         if (p < 0) {  // cur is the root
+            store_node_plain(nodes + cur, cn);
+            return;
+        }
+        const int32_t plo = r.z, phi = r.w;
+        if (!(plo >= c0 && phi <= c1)) break;  // the parent crosses the chunk
+        const bool is_right = r.y < 0;
+        const int32_t sib = (int32_t)((uint32_t)r.y & 0x7fffffffu);
+        const int32_t prope = (phi == n - 1) ? -1 : s_split[phi - c0];
+        store_node_plain(nodes + cur, cn);
+        if (cur < leaf0) {
+            const int64_t k = cur - c0;
+            s_int[0][k] = cn.lox; s_int[1][k] = cn.loy; s_int[2][k] = cn.loz;
+            s_int[3][k] = cn.hix; s_int[4][k] = cn.hiy; s_int[5][k] = cn.hiz;
+        }
+        // the sibling's thread reads this box from LDS only: order LDS accesses
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        const int32_t old = atomicAdd(&s_flag[p - c0], 1);
+        if (old == 0) return;  // the sibling subtree is not finished; its thread continues
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        const bool sleaf = sib >= leaf0;
+        const int64_t k = sleaf ? sib - leaf0 - c0 : sib - c0;
+        float slo[3], shi[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            slo[a] = sleaf ? s_leaf[a][k] : s_int[a][k];
+            shi[a] = sleaf ? s_leaf[3 + a][k] : s_int[3 + a][k];
+        }
+        Node u;
+        u.lox = fminf(cn.lox, slo[0]); u.loy = fminf(cn.loy, slo[1]); u.loz = fminf(cn.loz, slo[2]);
+        u.hix = fmaxf(cn.hix, shi[0]); u.hiy = fmaxf(cn.hiy, shi[1]); u.hiz = fmaxf(cn.hiz, shi[2]);
+        u.link = is_right ? sib : cur;
+        u.rope = prope;
+        cn = u;
+        cur = p;
+    }
+    // Crossing levels: the parent's range leaves the chunk, and so does every range
+    // above it. Arrival flags, boxes and records go through global memory. A radix
+    // tree over (key, index) pairs is at most 96 levels deep; the bound only guards.
+    for (int level = 0;; ++level) {
+        const int32_t p = r.x;
+        if (p < 0) {
             store_node_plain(nodes + cur, cn);
             return;
         }
@@ -575,54 +660,26 @@ __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ 
             atomicOr(err, kErrSpin);
             return;
         }
-        const int32_t plo = range_lo[p], phi = range_hi[p];
-        const bool local = plo >= c0 && phi <= c1;
+        const int32_t phi = r.w;
+        const bool is_right = r.y < 0;
+        const int32_t sib = (int32_t)((uint32_t)r.y & 0x7fffffffu);
+        const int32_t prope = (phi == n - 1) ? -1 : split_right[phi];
+        store_node_coherent(nodes + cur, cn);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const int32_t old = __hip_atomic_fetch_add(flags + p, 1, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         float slo[3], shi[3];
-        if (local) {
-            store_node_plain(nodes + cur, cn);
-            if (cur < leaf0) {
-                const int64_t k = cur - c0;
-                s_int[0][k] = cn.lox; s_int[1][k] = cn.loy; s_int[2][k] = cn.loz;
-                s_int[3][k] = cn.hix; s_int[4][k] = cn.hiy; s_int[5][k] = cn.hiz;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            const int32_t old = atomicAdd(&s_flag[p - c0], 1);
-            if (old == 0) return;  // the sibling subtree is not finished; its thread continues
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        } else {
-            store_node_coherent(nodes + cur, cn);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            const int32_t old = __hip_atomic_fetch_add(flags + p, 1, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-            if (old == 0) return;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        }
-        const int32_t lc = left[p];
-        const int32_t sib = (lc == cur) ? right[p] : lc;
-        if (local) {
-            if (sib >= leaf0) {
-                const int64_t k = sib - leaf0 - c0;
-                for (int a = 0; a < 3; ++a) {
-                    slo[a] = s_leaf[a][k];
-                    shi[a] = s_leaf[3 + a][k];
-                }
-            } else {
-                const int64_t k = sib - c0;
-                for (int a = 0; a < 3; ++a) {
-                    slo[a] = s_int[a][k];
-                    shi[a] = s_int[3 + a][k];
-                }
-            }
-        } else {
-            load_box(nodes + sib, slo, shi);
-        }
+        load_box(nodes + sib, slo, shi);
         Node u;
         u.lox = fminf(cn.lox, slo[0]); u.loy = fminf(cn.loy, slo[1]); u.loz = fminf(cn.loz, slo[2]);
         u.hix = fmaxf(cn.hix, shi[0]); u.hiy = fmaxf(cn.hiy, shi[1]); u.hiz = fmaxf(cn.hiz, shi[2]);
-        u.link = lc;
-        u.rope = (phi == n - 1) ? -1 : split_right[phi];
+        u.link = is_right ? sib : cur;
+        u.rope = prope;
         cn = u;
         cur = p;
+        r = grec[cur];
     }
 }
 
@@ -630,21 +687,23 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 
 }  // namespace
 
-KeyLayout key_layout(int64_t n_comb) {
+KeyLayout key_layout(int64_t n_comb, int max_morton) {
     int p = 0;
     while (p < 63 && ((uint64_t)(n_comb > 1 ? n_comb - 1 : 0) >> p) != 0) ++p;
+    const int mcap = max_morton < 1 ? 1 : (max_morton > 30 ? 30 : max_morton);
     KeyLayout kl;
-    if (p <= 5) {
+    if (32 - p >= (mcap < 27 ? mcap : 27)) {
         kl.wide = false;
-        kl.morton_bits = p <= 2 ? 30 : 32 - p;
-        kl.prefix_shift = kl.morton_bits;
-        kl.key_bits = kl.morton_bits + p;
+        int mb = 32 - p;
+        if (mb > 30) mb = 30;
+        if (mb > mcap) mb = mcap;
+        kl.morton_bits = mb;
     } else {
         kl.wide = true;
-        kl.morton_bits = 30;
-        kl.prefix_shift = 30;
-        kl.key_bits = 30 + p;
+        kl.morton_bits = mcap;
     }
+    kl.prefix_shift = kl.morton_bits;
+    kl.key_bits = kl.morton_bits + p;
     return kl;
 }
 
@@ -682,16 +741,22 @@ void launch_boxes_keys(const BeamDev &b, bool query, double dt, double sigma_up,
                        const InstStats *t_stats, const InstStats *self_stats, KeyLayout kl,
                        PBox *out, uint32_t *keys32, unsigned long long *keys64, uint32_t *vals,
                        DevCounters *c, hipStream_t st) {
-    const int64_t nv = (int64_t)b.m * b.n;
-    if (nv <= 0) return;
+    if (b.n <= 0 || b.m <= 0) return;
     if (kl.wide)
-        hipLaunchKernelGGL(k_boxes_keys<true>, dim3(grid_for(nv, 256)), dim3(256), 0, st, b,
+        hipLaunchKernelGGL(k_boxes_keys<true>, dim3(grid_for(b.n, 256)), dim3(256), 0, st, b,
                            query ? 1 : 0, dt, sigma_up, t_stats, self_stats, kl, out, keys32,
                            keys64, vals, c);
     else
-        hipLaunchKernelGGL(k_boxes_keys<false>, dim3(grid_for(nv, 256)), dim3(256), 0, st, b,
+        hipLaunchKernelGGL(k_boxes_keys<false>, dim3(grid_for(b.n, 256)), dim3(256), 0, st, b,
                            query ? 1 : 0, dt, sigma_up, t_stats, self_stats, kl, out, keys32,
                            keys64, vals, c);
+}
+
+void launch_gather_beam(const BeamDev &src, const uint32_t *order, double *dst_soa,
+                        int32_t *dst_perm, hipStream_t st) {
+    if (src.n <= 0) return;
+    hipLaunchKernelGGL(k_gather_beam, dim3(grid_for(src.n, 256)), dim3(256), 0, st, src, order,
+                       dst_soa, dst_perm);
 }
 
 void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint32_t *keys,
@@ -701,22 +766,18 @@ void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint3
                        vals);
 }
 
-void launch_karras_u32(const uint32_t *keys, int64_t n, int prefix_shift, int32_t *left,
-                       int32_t *right, int32_t *parent, int32_t *range_lo, int32_t *range_hi,
+void launch_karras_u32(const uint32_t *keys, int64_t n, int prefix_shift, PRec *prec,
                        int32_t *split_right, int32_t *flags, int32_t *inst_root, hipStream_t st) {
     if (n <= 1) return;
     hipLaunchKernelGGL(k_karras<uint32_t>, dim3(grid_for(n - 1, 256)), dim3(256), 0, st, keys, n,
-                       prefix_shift, left, right, parent, range_lo, range_hi, split_right, flags,
-                       inst_root);
+                       prefix_shift, prec, split_right, flags, inst_root);
 }
 
-void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shift, int32_t *left,
-                       int32_t *right, int32_t *parent, int32_t *range_lo, int32_t *range_hi,
+void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shift, PRec *prec,
                        int32_t *split_right, int32_t *flags, int32_t *inst_root, hipStream_t st) {
     if (n <= 1) return;
     hipLaunchKernelGGL(k_karras<unsigned long long>, dim3(grid_for(n - 1, 256)), dim3(256), 0, st,
-                       keys, n, prefix_shift, left, right, parent, range_lo, range_hi, split_right,
-                       flags, inst_root);
+                       keys, n, prefix_shift, prec, split_right, flags, inst_root);
 }
 
 void launch_inst_roots(const BeamDev &b, bool single, const int32_t *split_right,
@@ -726,14 +787,12 @@ void launch_inst_roots(const BeamDev &b, bool single, const int32_t *split_right
                        single ? 1 : 0, split_right, inst_root, inst_stop);
 }
 
-void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, const int32_t *left,
-                  const int32_t *right, const int32_t *parent, const int32_t *range_lo,
-                  const int32_t *range_hi, const int32_t *split_right, int32_t *flags, Node *nodes,
-                  unsigned int *err, hipStream_t st) {
+void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, const PRec *prec,
+                  const int32_t *split_right, int32_t *flags, Node *nodes, unsigned int *err,
+                  hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_refit, dim3(grid_for(n, kRefitChunk)), dim3(kRefitChunk), 0, st, box,
-                       sorted_rows, n, left, right, parent, range_lo, range_hi, split_right, flags,
-                       nodes, err);
+                       sorted_rows, n, prec, split_right, flags, nodes, err);
 }
 
 }  // namespace tril

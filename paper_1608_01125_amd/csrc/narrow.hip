@@ -104,8 +104,8 @@ __global__ void __launch_bounds__(256) k_narrow(BeamDev q, BeamDev t, double dt,
             if (hit) {
                 const unsigned long long pos = base + count_below(m);
                 if (pos < (unsigned long long)out.cap) {
-                    out.i[pos] = i;
-                    out.j[pos] = j;
+                    out.i[pos] = q.perm ? q.perm[i] : i;
+                    out.j[pos] = t.perm ? t.perm[j] : j;
                     out.step[pos] = step;
                 }
             }

@@ -27,6 +27,7 @@ constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1u;
 constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kLookWin = 8;  // status words of earlier tiles loaded together in the look-back
 
 __device__ __forceinline__ uint32_t lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
@@ -69,10 +70,29 @@ __global__ void __launch_bounds__(kBlock) k_sort_hist(const K *__restrict__ keys
     __shared__ uint32_t h[8 * 256];
     for (int i = threadIdx.x; i < passes * 256; i += kBlock) h[i] = 0u;
     __syncthreads();
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
-        K k = keys[i];
-        for (int p = 0; p < passes; ++p) atomicAdd(&h[p * 256 + (uint32_t)((k >> (8 * p)) & 255u)], 1u);
+    // Lanes of a wave hold consecutive keys; for each digit position the first lane of
+    // every run of equal digits adds the run's length (input that is already nearly in
+    // order would otherwise send all 64 lanes to one LDS counter).
+    const uint32_t lane = lane_id();
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t base = blockIdx.x * (int64_t)kBlock + (threadIdx.x & ~63); base < n;
+         base += stride) {
+        const int64_t i = base + lane;
+        const bool valid = i < n;
+        const K k = valid ? keys[i] : (K)0;
+        const unsigned long long live = __ballot(valid);
+        for (int p = 0; p < passes; ++p) {
+            const uint32_t d = (uint32_t)((k >> (8 * p)) & 255u);
+            const uint32_t prev = __shfl_up(d, 1);
+            const bool head = valid && (lane == 0 || d != prev);
+            const unsigned long long heads = __ballot(head);
+            if (head) {
+                const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+                const uint32_t end = above ? (uint32_t)(__ffsll((long long)above) - 1)
+                                           : (uint32_t)(64 - __clzll(live));
+                atomicAdd(&h[p * 256 + d], end - lane);
+            }
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < passes * 256; i += kBlock) {
@@ -162,23 +182,37 @@ __global__ void __launch_bounds__(kBlock) k_sort_pass(
             __hip_atomic_store(my, kFlagInc | tcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             __hip_atomic_store(my, kFlagAgg | tcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // walk back over earlier tiles, kLookWin status words in flight at a time; add
+            // counts in order until an inclusive one, re-polling at a tile not yet published
             int64_t t = (int64_t)tile - 1;
             uint32_t spins = 0;
-            while (t >= 0) {
-                uint32_t v = __hip_atomic_load(status + (size_t)t * 256 + d, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                uint32_t f = v & ~kValMask;
-                if (f == 0u) {
+            bool done = false;
+            while (t >= 0 && !done) {
+                uint32_t v[kLookWin];
+#pragma unroll
+                for (int w = 0; w < kLookWin; ++w)
+                    v[w] = (t - w >= 0) ? __hip_atomic_load(status + (size_t)(t - w) * 256 + d,
+                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                        : kFlagInc;
+                int w = 0;
+                for (; w < kLookWin && t - w >= 0; ++w) {
+                    const uint32_t f = v[w] & ~kValMask;
+                    if (f == 0u) break;
+                    excl += v[w] & kValMask;
+                    if (f == kFlagInc) {
+                        done = true;
+                        break;
+                    }
+                }
+                if (done) break;
+                t -= w;
+                if (t >= 0 && w < kLookWin) {  // stopped at a tile that has not published
                     if (++spins > kSpinLimit) {
                         atomicOr(err, kErrSpin);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
-                    continue;
                 }
-                excl += v & kValMask;
-                if (f == kFlagInc) break;
-                --t;
             }
             __hip_atomic_store(my, kFlagInc | ((excl + tcount) & kValMask), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);

@@ -35,6 +35,19 @@ struct alignas(16) Node {
 };
 static_assert(sizeof(Node) == 32, "node layout");
 
+// Parent record of a hierarchy node (internal or leaf), 16 bytes, written by the
+// emission kernel for both children of every internal node:
+//   parent: id of the parent (-1 for the root, node 0);
+//   sib:    id of the sibling, bit 31 set when this node is the right child;
+//   lo, hi: the parent's range of sorted leaf positions.
+struct alignas(16) PRec {
+    int32_t parent;
+    int32_t sib;
+    int32_t lo;
+    int32_t hi;
+};
+static_assert(sizeof(PRec) == 16, "record layout");
+
 // Swept, padded box of one photon (FP32, rounded outward), 32 bytes.
 //   tag: instance index of the photon, or -1 when the photon can collide with
 //        nothing (query photons whose best case is below threshold).
@@ -92,6 +105,7 @@ struct BeamDev {
     int32_t n_inst;
     const int64_t *inst_off;   // device copy, n_inst + 1
     int32_t m;                 // steps covered by the launch (>= 1)
+    const int32_t *perm;       // row of this view -> caller's row (nullptr: identity)
 };
 
 // Per-instance statistics of a beam over its rows (the same for every step):
@@ -108,16 +122,17 @@ struct StatsPartial {
 };
 int64_t stats_partials_needed(int64_t n);
 
-// Sort-key layout for n_comb combined instances: 32-bit keys (prefix above
-// morton_bits of the Morton code) while the prefix needs at most 5 bits, else 64-bit
-// keys (prefix above all 30 Morton bits).
+// Sort-key layout for n_comb combined instances and at most max_morton Morton bits:
+// 32-bit keys (prefix above the top morton_bits of the 30-bit Morton code) while the
+// prefix leaves room for min(max_morton, 27) of them, else 64-bit keys (prefix above
+// min(max_morton, 30) Morton bits).
 struct KeyLayout {
     bool wide;
     int morton_bits;    // Morton bits kept (top bits of the 30-bit code)
     int prefix_shift;   // key >> prefix_shift = combined instance
     int key_bits;       // bits the sort must order
 };
-KeyLayout key_layout(int64_t n_comb);
+KeyLayout key_layout(int64_t n_comb, int max_morton);
 
 void launch_prologue(DevCounters *c, int kind, int32_t m, hipStream_t st);
 void launch_set_step(DevCounters *c, int32_t step, hipStream_t st);
@@ -135,22 +150,24 @@ void launch_boxes_keys(const BeamDev &b, bool query, double dt, double sigma_up,
                        PBox *out, uint32_t *keys32, unsigned long long *keys64, uint32_t *vals,
                        DevCounters *c, hipStream_t st);
 // Morton keys of given boxes over given bounds (6 ordered floats), 30 bits.
+// dst_soa holds x, y, z, px, py, pz, E, w of src.n rows, array a at offset a * src.n.
+// Row k of dst is row order[k] of src (order nullptr: row k); dst_perm[k] is the caller's
+// row of it (through src.perm).
+void launch_gather_beam(const BeamDev &src, const uint32_t *order, double *dst_soa,
+                        int32_t *dst_perm, hipStream_t st);
 void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint32_t *keys,
                        uint32_t *vals, hipStream_t st);
 // inst_root may be NULL (one combined instance); otherwise the node whose range is
 // exactly one instance's run of keys (key >> prefix_shift equal) is recorded.
-void launch_karras_u32(const uint32_t *keys, int64_t n, int prefix_shift, int32_t *left,
-                       int32_t *right, int32_t *parent, int32_t *range_lo, int32_t *range_hi,
+void launch_karras_u32(const uint32_t *keys, int64_t n, int prefix_shift, PRec *prec,
                        int32_t *split_right, int32_t *flags, int32_t *inst_root, hipStream_t st);
-void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shift, int32_t *left,
-                       int32_t *right, int32_t *parent, int32_t *range_lo, int32_t *range_hi,
+void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shift, PRec *prec,
                        int32_t *split_right, int32_t *flags, int32_t *inst_root, hipStream_t st);
 void launch_inst_roots(const BeamDev &b, bool single, const int32_t *split_right,
                        int32_t *inst_root, int32_t *inst_stop, hipStream_t st);
-void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, const int32_t *left,
-                  const int32_t *right, const int32_t *parent, const int32_t *range_lo,
-                  const int32_t *range_hi, const int32_t *split_right, int32_t *flags, Node *nodes,
-                  unsigned int *err, hipStream_t st);
+void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, const PRec *prec,
+                  const int32_t *split_right, int32_t *flags, Node *nodes, unsigned int *err,
+                  hipStream_t st);
 
 // nt, nq: virtual counts (steps x rows). qorder: NULL (identity), nq entries (order of
 // all virtual queries) or nq_base entries (order of one step, repeated per step).

@@ -43,7 +43,8 @@ class tril_beam(ctypes.Structure):
 class tril_params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("flags", ctypes.c_uint32), ("n_bins", ctypes.c_int32),
                 ("bin_edges", _dp), ("cand_cap", ctypes.c_int64),
-                ("block_traverse", ctypes.c_int32), ("step_batch", ctypes.c_int32)]
+                ("block_traverse", ctypes.c_int32), ("step_batch", ctypes.c_int32),
+                ("morton_bits", ctypes.c_int32), ("pad0", ctypes.c_int32)]
 
 
 class tril_pairs(ctypes.Structure):
@@ -189,7 +190,7 @@ class Pairs:
 
 def tril_create(dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
                 cand_cap: int = 0, block_traverse: int = 0, step_batch: int = 0,
-                stream=None) -> ctypes.c_void_p:
+                stream=None, morton_bits: int = 0) -> ctypes.c_void_p:
     L = lib()
     p = tril_params()
     p.dt = float(dt)
@@ -205,6 +206,7 @@ def tril_create(dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
     p.cand_cap = int(cand_cap)
     p.block_traverse = int(block_traverse)
     p.step_batch = int(step_batch)
+    p.morton_bits = int(morton_bits)
     h = ctypes.c_void_p()
     _check(L.tril_create(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(_stream(stream))),
            "tril_create")
@@ -330,9 +332,11 @@ class Context:
     """One collision context (owns the hierarchy and scratch on the device)."""
 
     def __init__(self, dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
-                 cand_cap: int = 0, block_traverse: int = 0, step_batch: int = 0, stream=None):
+                 cand_cap: int = 0, block_traverse: int = 0, step_batch: int = 0, stream=None,
+                 morton_bits: int = 0):
         self.n_bins = 0 if edges is None else max(len(edges) - 1, 0)
-        self.h = tril_create(dt, edges, flags, cand_cap, block_traverse, step_batch, stream)
+        self.h = tril_create(dt, edges, flags, cand_cap, block_traverse, step_batch, stream,
+                             morton_bits)
 
     def build(self, target: Beam, step: int) -> None:
         tril_build(self.h, target, step)

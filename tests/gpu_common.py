@@ -9,10 +9,11 @@ from paper_1608_01125_amd import tril as T
 
 
 def gpu_run(A, B, dt, n_steps, edges, graph=False, flags=0, cap=1 << 20, k0=0,
-            offA=None, offB=None, block=0, step_batch=0):
+            offA=None, offB=None, block=0, step_batch=0, morton_bits=0):
     """Tree over B (target), queries from A. Returns unique pairs + stats dict.
     graph=True goes through tril_run (step batches), else one build/collide per step."""
-    ctx = T.Context(dt, edges, flags=flags, block_traverse=block, step_batch=step_batch)
+    ctx = T.Context(dt, edges, flags=flags, block_traverse=block, step_batch=step_batch,
+                    morton_bits=morton_bits)
     try:
         tb = T.Beam(B, offB)
         qb = T.Beam(A, offA)

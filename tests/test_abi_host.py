@@ -52,6 +52,8 @@ def _create(**kw):
         p.bin_edges = None
     p.cand_cap = kw.get("cand_cap", 0)
     p.block_traverse = kw.get("block", 0)
+    p.step_batch = kw.get("step_batch", 0)
+    p.morton_bits = kw.get("morton_bits", 0)
     h = ctypes.c_void_p()
     return T.lib().tril_create(ctypes.byref(h), ctypes.byref(p), None)
 
@@ -60,7 +62,8 @@ def _create(**kw):
     {"dt": 0.0}, {"dt": -1.0}, {"dt": float("nan")}, {"dt": float("inf")},
     {"n_bins": -1}, {"n_bins": 3},                      # edges missing
     {"edges": [0.0, 1.0, 1.0]}, {"edges": [0.0, 2.0, 1.0]}, {"edges": [0.0, float("nan")]},
-    {"cand_cap": -5}, {"block": 100}, {"block": 1024},
+    {"cand_cap": -5}, {"block": 100}, {"block": 1024}, {"step_batch": -1},
+    {"morton_bits": 2}, {"morton_bits": -3}, {"morton_bits": 31},
 ])
 def test_create_rejects_bad_params(kw):
     assert _create(**kw) == T.TRIL_E_INVAL

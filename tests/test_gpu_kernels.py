@@ -57,6 +57,24 @@ def test_sort_u32_patterns(torch, kind):
     _sort_case(torch, keys, 32 if kind == "full32" else 30, False)
 
 
+@pytest.mark.parametrize("kind", ["nearly_sorted", "runs", "sorted_ties"])
+def test_sort_u32_large_ordered_inputs(torch, kind):
+    """Millions of keys that arrive (nearly) in order: long runs of equal digits in every
+    wave (histogram run aggregation) and thousands of tiles (look-back windows)."""
+    n = 6_000_017
+    rng = np.random.default_rng(11)
+    keys = np.sort(rng.integers(0, 1 << 32, n, dtype=np.uint64)).astype(np.uint32)
+    if kind == "nearly_sorted":
+        sw = rng.integers(0, n - 40, n // 50)
+        off = rng.integers(1, 40, n // 50)
+        keys[sw], keys[sw + off] = keys[sw + off], keys[sw].copy()
+    elif kind == "runs":
+        keys = np.repeat(rng.integers(0, 1 << 32, n // 1000 + 1, dtype=np.uint64).astype(np.uint32), 1000)[:n]
+    else:
+        keys = (keys >> np.uint32(12)) << np.uint32(12)
+    _sort_case(torch, keys, 32, False)
+
+
 @pytest.mark.parametrize("bits", [36, 40, 64])
 def test_sort_u64(torch, bits):
     rng = np.random.default_rng(bits)

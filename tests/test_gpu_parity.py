@@ -61,15 +61,18 @@ def test_gauss_headon_reduced_all_steps(torch, graph, flags):
     assert_parity(gpu, raw, S, wl.n_steps)
 
 
-@pytest.mark.parametrize("step_batch,flags", [
-    (1, 0), (7, 0), (64, T.TRIL_TIMING), (0, T.TRIL_SORT_QUERIES_ONCE),
-    (13, T.TRIL_SORT_QUERIES_ONCE | T.TRIL_TIMING), (400, 0)])
-def test_step_batches(torch, step_batch, flags):
+@pytest.mark.parametrize("step_batch,flags,morton", [
+    (1, 0, 0), (7, 0, 0), (64, T.TRIL_TIMING, 0), (0, T.TRIL_SORT_QUERIES_ONCE, 0),
+    (13, T.TRIL_SORT_QUERIES_ONCE | T.TRIL_TIMING, 0), (400, 0, 0), (16, 0, 12),
+    (9, T.TRIL_SORT_QUERIES_ONCE, 3), (64, T.TRIL_TIMING, 20)])
+def test_step_batches(torch, step_batch, flags, morton):
     """tril_run with several time steps per launch (each step its own subtree) equals the
-    oracle for any batch size, including a shorter last batch."""
+    oracle for any batch size, including a shorter last batch, and for any number of
+    Morton bits in the sort keys."""
     wl, A, B = _gauss_small(8000, 1.5e4, seed=4)
     raw, S = oracle_run(A, B, wl.dt, wl.n_steps, EDGES)
-    gpu = gpu_run(A, B, wl.dt, wl.n_steps, EDGES, graph=True, flags=flags, step_batch=step_batch)
+    gpu = gpu_run(A, B, wl.dt, wl.n_steps, EDGES, graph=True, flags=flags, step_batch=step_batch,
+                  morton_bits=morton)
     assert S.n_pairs > 100
     assert_parity(gpu, raw, S, wl.n_steps)
 
@@ -86,9 +89,10 @@ def test_step_batches_with_instances(torch):
     A, offA = beams.concat(parts_a)
     B, offB = beams.concat(parts_b)
     raw, S = oracle_run(A, B, 0.1, 400, EDGES, offA=offA, offB=offB)
-    for sb, flags in [(9, 0), (50, T.TRIL_SORT_QUERIES_ONCE), (0, T.TRIL_TIMING)]:
+    for sb, flags, mb in [(9, 0, 0), (50, T.TRIL_SORT_QUERIES_ONCE, 0), (0, T.TRIL_TIMING, 0),
+                          (16, 0, 12)]:
         gpu = gpu_run(A, B, 0.1, 400, EDGES, graph=True, offA=offA, offB=offB, step_batch=sb,
-                      flags=flags)
+                      flags=flags, morton_bits=mb)
         assert_parity(gpu, raw, S, 400)
     assert S.n_pairs > 20
 
