@@ -250,6 +250,9 @@ def main():
                                    else "Morton order of every step"),
                    "traversal_launches": st["n_timed_launches"],
                    "pairs": st["n_pairs"], "hits": st["n_hits"],
+                   "candidates_per_run": st["n_candidates"] // max(args.steps, 1),
+                   "fp64_recheck_fraction": (round(st["n_fp64_rechecks"] / st["n_candidates"], 5)
+                                             if st["n_candidates"] else None),
                    "ms_phases_per_run": {k: round(st[k] / max(args.steps, 1), 3) for k in
                                          ("ms_build", "ms_query_prep", "ms_traverse", "ms_narrow")}},
         "roofline": roofline,

@@ -22,7 +22,12 @@
  *                     min over the window of |X_i(t) - X_j(t)|^2 <= r_ij^2,
  *                     r_ij^2 = sqrt(w_i w_j) sigma_BW(s_ij) / pi     (Eq. 1)
  *                   with X(t) = x0 + t p/E (straight lines at c) and hits
- *                   (i, j, k) appended to the caller's pair buffer;
+ *                   (i, j, k) appended to the caller's pair buffer. The decision
+ *                   is that of FP64 arithmetic: a single-precision stage with a
+ *                   running bound on its rounding error decides the candidates
+ *                   that clear the criterion by more than that bound (plus
+ *                   1e-5 r^2), FP64 the rest (precision contract of the paper's
+ *                   exact test, Eq. 1 and 2);
  *   tril_stats   -- after the last step: union of the hits over steps (each
  *                   pair kept once, with its first step), sorted ascending by
  *                   (i, j); pair count, yield sum sqrt(w_i w_j), pair-energy
@@ -64,6 +69,7 @@ extern "C" {
 /* tril_params.flags */
 #define TRIL_TIMING        0x1u  /* record HIP events around each phase (ms_* in tril_stats_t) */
 #define TRIL_SORT_QUERIES_ONCE 0x2u /* Morton-order the query beam at its first step only */
+#define TRIL_FP64_NARROW   0x4u  /* decide every candidate in FP64 (no FP32 stage) */
 
 typedef struct tril_ctx tril_ctx;
 
@@ -136,6 +142,8 @@ typedef struct {
     double ms_narrow;         /* with TRIL_TIMING: narrow-phase kernel */
     int64_t n_timed_launches; /* traversal launches the ms_* sums cover (one per collide call,
                                  one per step batch of tril_run) */
+    int64_t n_fp64_rechecks;  /* candidates the FP32 stage of the narrow phase could not decide
+                                 and passed to FP64 (0 with TRIL_FP64_NARROW) */
 } tril_stats_t;
 
 /* Create a context on the caller's HIP stream (hipStream_t, NULL = default stream).

@@ -38,6 +38,14 @@ int tril_dbg_morton(const float *boxes, int64_t n, const float *bounds, uint32_t
  * distance over [t, t + dt]) and r^2 = sqrt(w_i w_j) sigma / pi. */
 int tril_dbg_pair_eval(int64_t n, const double *in, double *out, void *stream);
 
+/* The FP32 stage of the narrow phase on the same n x 18 input rows (sigma bound of the
+ * library): out, device, n x 8 doubles per row: s, bound on |s - s_exact|, d^2, its
+ * bound, r^2, its bound (r^2 and its bound are 0 when the stage stopped at the threshold,
+ * and the radius upper bound when it stopped there), decision (0 no pair, 1 pair,
+ * 2 left to FP64), 0. Bounds are relative to exact arithmetic on the FP64 inputs.
+ * Synchronises the stream. */
+int tril_dbg_pair_eval32(int64_t n, const double *in, double *out, void *stream);
+
 /* Copy the last built hierarchy to host memory (synchronises the context stream).
  * nodes: host, cap_nodes x 8 words (lox loy loz link hix hiy hiz rope as float/int32);
  * *n_nodes receives 2n-1 (0 for an empty beam); roots/stops: host, n_inst each,

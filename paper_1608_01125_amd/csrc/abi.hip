@@ -456,7 +456,7 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
     if (timed) CHK(timing_pair(c, st, c->ev_trav, false));
     if (timed) CHK(timing_pair(c, st, c->ev_narrow, true));
     launch_narrow(q, c->tgt, c->dt, c->sigma_up, c->cand_i, c->cand_j, c->cand_cap, out, c->d_cnt,
-                  st);
+                  (c->flags & TRIL_FP64_NARROW) == 0, st);
     if (timed) CHK(timing_pair(c, st, c->ev_narrow, false));
     HIPCHK(hipGetLastError());
     return TRIL_OK;
@@ -616,7 +616,7 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
     if (!std::isfinite(p->dt) || !(p->dt > 0.0)) return TRIL_E_INVAL;
     if (p->n_bins < 0 || p->cand_cap < 0 || p->step_batch < 0) return TRIL_E_INVAL;
     if (p->morton_bits != 0 && (p->morton_bits < 3 || p->morton_bits > 30)) return TRIL_E_INVAL;
-    if (p->flags & ~(TRIL_TIMING | TRIL_SORT_QUERIES_ONCE)) return TRIL_E_NOTIMPL;
+    if (p->flags & ~(TRIL_TIMING | TRIL_SORT_QUERIES_ONCE | TRIL_FP64_NARROW)) return TRIL_E_NOTIMPL;
     if (p->n_bins > 0) {
         if (!p->bin_edges) return TRIL_E_INVAL;
         for (int32_t b = 0; b <= p->n_bins; ++b)
@@ -851,6 +851,7 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     out->n_node_visits = visits;
     out->n_queries = queries;
     out->n_sigma_evals = (int64_t)h.sigma_evals;
+    out->n_fp64_rechecks = (int64_t)h.fp64_rechecks;
     out->n_builds = (int64_t)h.builds;
     out->n_collides = (int64_t)h.collides;
     const unsigned int err = h.err;
@@ -1045,6 +1046,15 @@ int tril_dbg_pair_eval(int64_t n, const double *in, double *out, void *stream) {
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     launch_pair_eval(n, in, out, st);
     HIPCHK(hipGetLastError());
+    return TRIL_OK;
+}
+
+int tril_dbg_pair_eval32(int64_t n, const double *in, double *out, void *stream) {
+    if (n < 0 || (n > 0 && (!in || !out))) return TRIL_E_INVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    launch_pair_eval32(n, in, host_sigma_max() * (1.0 + 1e-6), out, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
     return TRIL_OK;
 }
 

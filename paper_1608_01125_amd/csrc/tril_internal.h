@@ -68,6 +68,7 @@ struct DevCounters {
     unsigned long long cand_step;      // candidates of the current step (reset per step)
     unsigned long long cand_total;
     unsigned long long sigma_evals;
+    unsigned long long fp64_rechecks;  // candidates the FP32 stage left to FP64
     unsigned long long builds;
     unsigned long long collides;
     unsigned int err;
@@ -178,8 +179,8 @@ void launch_traverse(const Node *nodes, int64_t nt, const PBox *qbox, const uint
                      int block, hipStream_t st);
 void launch_narrow(const BeamDev &q, const BeamDev &t, double dt, double sigma_up,
                    const int32_t *cand_i, const int32_t *cand_j, int64_t cand_cap,
-                   const tril_pairs &out, DevCounters *c, hipStream_t st);
-
+                   const tril_pairs &out, DevCounters *c, bool fp32_stage, hipStream_t st);
+void launch_pair_eval32(int64_t n, const double *in, double sigma_up, double *out, hipStream_t st);
 void launch_pair_eval(int64_t n, const double *in, double *out, hipStream_t st);
 
 // ------------------------------------------------------------------ run stats

@@ -28,6 +28,7 @@ TRIL_E_INTERNAL = -8
 
 TRIL_TIMING = 0x1
 TRIL_SORT_QUERIES_ONCE = 0x2
+TRIL_FP64_NARROW = 0x4
 
 FIELDS = ("x", "y", "z", "px", "py", "pz", "E", "w")
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -61,12 +62,13 @@ class tril_stats_t(ctypes.Structure):
                 ("n_step_counts", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("ms_build", ctypes.c_double), ("ms_query_prep", ctypes.c_double),
                 ("ms_traverse", ctypes.c_double), ("ms_narrow", ctypes.c_double),
-                ("n_timed_launches", ctypes.c_int64)]
+                ("n_timed_launches", ctypes.c_int64), ("n_fp64_rechecks", ctypes.c_int64)]
 
 
 EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats",
            "tril_reset_counters", "tril_destroy", "tril_strerror", "tril_last_hip_error",
            "tril_dbg_sort_u32", "tril_dbg_sort_u64", "tril_dbg_morton", "tril_dbg_pair_eval",
+           "tril_dbg_pair_eval32",
            "tril_dbg_tree", "tril_dbg_boxes", "tril_dbg_candidates")
 
 _lib = None
@@ -98,6 +100,7 @@ def lib() -> ctypes.CDLL:
     L.tril_dbg_sort_u64.argtypes = [vp, vp, i64, ctypes.c_int, vp]
     L.tril_dbg_morton.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_float), vp, vp]
     L.tril_dbg_pair_eval.argtypes = [i64, vp, vp, vp]
+    L.tril_dbg_pair_eval32.argtypes = [i64, vp, vp, vp]
     L.tril_dbg_tree.argtypes = [vp, vp, i64, _i64p, _i32p, _i32p]
     L.tril_dbg_boxes.argtypes = [vp, ctypes.c_int, vp, i64, _i64p]
     L.tril_dbg_candidates.argtypes = [vp, _i32p, _i32p, i64, _i64p]
@@ -280,6 +283,11 @@ def tril_dbg_morton(boxes, bounds: Sequence[float], keys, stream=None) -> None:
 def tril_dbg_pair_eval(inp, out, stream=None) -> None:
     _check(lib().tril_dbg_pair_eval(inp.shape[0], inp.data_ptr(), out.data_ptr(), _stream(stream)),
            "tril_dbg_pair_eval")
+
+
+def tril_dbg_pair_eval32(inp, out, stream=None) -> None:
+    _check(lib().tril_dbg_pair_eval32(inp.shape[0], inp.data_ptr(), out.data_ptr(), _stream(stream)),
+           "tril_dbg_pair_eval32")
 
 
 def _h(ctx):
