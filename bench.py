@@ -73,45 +73,71 @@ def committed_traffic(steps_per_dispatch=None):
 
 
 def make_workload(name: str, physics_steps: int):
+    """(workload, beam A, offsets A, beam B, offsets B, steps); offsets None = one instance."""
     from paper_1608_01125_amd import beams
+    offA = offB = None
     if name == "gauss_headon_1m":
         wl = beams.gauss_headon_1m()
     elif name == "mono_headon_2k":
         wl = beams.mono_headon_2k()
     elif name == "broadband_16m":
         wl = beams.broadband_16m()
+    elif name == "batch64":
+        parts_a, parts_b = [], []
+        for m in range(64):
+            wl = beams.batch64_instance(m)
+            A, B = beams.draw_pair(wl)
+            parts_a.append(A)
+            parts_b.append(B)
+        A, offA = beams.concat(parts_a)
+        B, offB = beams.concat(parts_b)
+        n_steps = physics_steps if physics_steps > 0 else wl.n_steps
+        return wl, A, offA, B, offB, n_steps
     else:
         raise SystemExit(f"unknown workload {name}")
     A, B = beams.draw_pair(wl)
     n_steps = physics_steps if physics_steps > 0 else wl.n_steps
-    return wl, A, B, n_steps
+    return wl, A, offA, B, offB, n_steps
 
 
-def cpu_baseline(A, B, dt, n_steps, target_s: float):
-    """Oracle (as it stands) on a bounded random sample of query rows."""
+def cpu_baseline(A, offA, B, offB, dt, n_steps, target_s: float):
+    """Oracle (as it stands) on a bounded random sample of query rows (per instance
+    for a batched workload: rows drawn uniformly over all query photons)."""
     import numpy as np
     from oracle import oracle as O
     O.build(force=False)
     threads = O.num_threads()
     rng = np.random.default_rng(12345)
     nA = len(A["E"])
+    if offA is None:
+        offA = np.array([0, nA], dtype=np.int64)
+        offB = np.array([0, len(B["E"])], dtype=np.int64)
+    inst_of = np.searchsorted(offA, np.arange(nA), side="right") - 1
     r = min(nA, 64)
     while True:
-        rows = rng.choice(nA, r, replace=False)
+        rows = np.sort(rng.choice(nA, r, replace=False))
+        pairs_tested = 0
         t = time.perf_counter()
-        O.collide(A, B, dt, n_steps, rows=rows)
+        for m in np.unique(inst_of[rows]):
+            a0, a1, b0, b1 = offA[m], offA[m + 1], offB[m], offB[m + 1]
+            if b1 <= b0:
+                continue
+            Am = {k: v[a0:a1] for k, v in A.items()}
+            Bm = {k: v[b0:b1] for k, v in B.items()}
+            sel = rows[inst_of[rows] == m] - a0
+            O.collide(Am, Bm, dt, n_steps, rows=sel)
+            pairs_tested += len(sel) * (b1 - b0)
         el = time.perf_counter() - t
         if el >= 0.5 * target_s or r >= nA:
             break
         r = int(min(nA, r * max(2.0, 1.1 * target_s / max(el, 1e-3))))
-    nB = len(B["E"])
     return {
-        "value": r * nB * n_steps / el,
+        "value": pairs_tested * n_steps / el,
         "unit": "queries/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"{r} random query rows x all {nB} target photons x {n_steps} steps "
-                  f"({el:.1f} s, FP64, pruned mode, OpenMP)",
+        "sample": f"{r} random query rows x all target photons of their instance x {n_steps} "
+                  f"steps ({pairs_tested} row-photon pairs, {el:.1f} s, FP64, pruned mode, OpenMP)",
     }
 
 
@@ -134,6 +160,9 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick steps per launch, traversal workgroup size and Morton bits with "
+                         "tril_autotune before timing (cached per workload shape)")
     ap.add_argument("--flags", type=int, default=0)
     args = ap.parse_args()
 
@@ -149,8 +178,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    wl, A, B, n_steps = make_workload(args.workload, args.physics_steps)
+    wl, A, offA, B, offB, n_steps = make_workload(args.workload, args.physics_steps)
     nA, nB = len(A["E"]), len(B["E"])
+    if offA is None:
+        pairs_per_step = nA * nB
+    else:
+        pairs_per_step = int(sum(int(offA[m + 1] - offA[m]) * int(offB[m + 1] - offB[m])
+                                 for m in range(len(offA) - 1)))
     edges = beams.spectrum_edges()
 
     if args.calib_copy_mib > 0:
@@ -167,6 +201,8 @@ def main():
         """Warm-up runs, then args.steps timed collision runs; returns (seconds, stats)."""
         ctx = T.Context(wl.dt, edges, flags=flags, block_traverse=args.block,
                         step_batch=args.step_batch)
+        if tune is not None:
+            T.tril_set_tune(ctx.h, tune)
         pairs = T.Pairs(max(1 << 20, 4 * min(nA, nB)))
 
         def one_run():
@@ -187,11 +223,20 @@ def main():
         finally:
             ctx.close()
 
-    tb, qb = T.Beam(B), T.Beam(A)
+    tb, qb = T.Beam(B, offB), T.Beam(A, offA)
+    tune = None
+    if args.autotune:
+        from paper_1608_01125_amd import autotune
+        probe_ctx = T.Context(wl.dt, edges)
+        try:
+            tune = autotune.tuned(probe_ctx, tb, qb, wl.dt, k0=int(0.4 * n_steps),
+                                  n_probe=min(64, n_steps), cache=autotune.DEFAULT_CACHE)
+        finally:
+            probe_ctx.close()
     timing = T.TRIL_TIMING if args.mode != "graph" else 0
     elapsed, st = timed(args.flags | timing)
     ms_per_step = 1e3 * elapsed / max(args.steps, 1)
-    value = nA * nB * n_steps / (elapsed / max(args.steps, 1))
+    value = pairs_per_step * n_steps / (elapsed / max(args.steps, 1))
     launches_per_run = st["n_timed_launches"] // max(args.steps, 1) if timing else 0
     steps_per_dispatch = (n_steps // launches_per_run
                           if launches_per_run and n_steps % launches_per_run == 0 else None)
@@ -202,7 +247,7 @@ def main():
         # set is identical; only the traversal order of the queries differs)
         e2, st2 = timed(args.flags | T.TRIL_SORT_QUERIES_ONCE | timing)
         variants["query_order_from_first_step"] = {
-            "value": nA * nB * n_steps / (e2 / max(args.steps, 1)),
+            "value": pairs_per_step * n_steps / (e2 / max(args.steps, 1)),
             "ms_per_step": 1e3 * e2 / max(args.steps, 1), "pairs": st2["n_pairs"]}
 
     roofline = None
@@ -243,7 +288,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n_per_beam": [nA, nB], "time_steps": n_steps,
+        "config": {"workload": args.workload, "n_per_beam": [nA, nB],
+                   "instances": 1 if offA is None else len(offA) - 1,
+                   "pairs_per_step": pairs_per_step, "time_steps": n_steps,
+                   "tune": tune,
                    "dt_um_per_c": wl.dt, "weight": wl.a.w, "mode": args.mode,
                    "step_batch": args.step_batch, "steps_per_launch": steps_per_dispatch,
                    "query_order": ("first step's Morton order" if args.flags & T.TRIL_SORT_QUERIES_ONCE
@@ -260,7 +308,7 @@ def main():
     if variants:
         out["variants"] = variants
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(A, B, wl.dt, n_steps, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(A, offA, B, offB, wl.dt, n_steps, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -188,6 +188,31 @@ int tril_run(tril_ctx *ctx, const tril_beam *target, const tril_beam *query,
  * counters only. */
 int tril_stats(tril_ctx *ctx, tril_pairs *pairs, tril_stats_t *out);
 
+/* Launch configuration of tril_run (performance only: the results do not depend on it). */
+typedef struct {
+    int32_t block_traverse;       /* traversal workgroup size: 64, 128, 256 or 512 */
+    int32_t step_batch;           /* steps per launch, >= 1 (0 = automatic) */
+    int32_t morton_bits;          /* 0 (automatic) or 3..30, as in tril_params */
+    int32_t pad0;
+    double ms_per_step;           /* tril_autotune: measured time per step of the best
+                                     configuration (output; ignored by tril_set_tune) */
+} tril_tune;
+
+/* Autotuner: time tril_run over steps k0 .. k0+n_probe-1 of the given beams for a set of
+ * launch configurations and keep the fastest in the context (and in *best). Coordinate
+ * descent: steps per launch (1 .. 64, within 2^26 photon-steps per launch), then the
+ * traversal workgroup size (64 .. 512), then the Morton bits (automatic or 30). Every
+ * configuration runs twice (the first run captures its graphs and sizes the scratch);
+ * the second is timed with HIP events on the context stream. Hits go to a scratch buffer
+ * owned by the call; the counters are reset at the end (as tril_reset_counters).
+ * Synchronises the stream. TRIL_E_INVAL for bad arguments or n_probe < 1. */
+int tril_autotune(tril_ctx *ctx, const tril_beam *target, const tril_beam *query, int32_t k0,
+                  int32_t n_probe, tril_tune *best);
+
+/* Apply a launch configuration (e.g. one stored from an earlier tril_autotune).
+ * TRIL_E_INVAL for values outside the ranges above. */
+int tril_set_tune(tril_ctx *ctx, const tril_tune *tune);
+
 /* Zero the accumulated counters and device error flags (asynchronous). */
 int tril_reset_counters(tril_ctx *ctx);
 

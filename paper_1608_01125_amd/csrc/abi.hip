@@ -904,6 +904,107 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     return TRIL_OK;
 }
 
+int tril_set_tune(tril_ctx *c, const tril_tune *tu) {
+    if (!c || !tu) return TRIL_E_INVAL;
+    const int blk = tu->block_traverse;
+    if (blk != 64 && blk != 128 && blk != 256 && blk != 512) return TRIL_E_INVAL;
+    if (tu->step_batch < 0) return TRIL_E_INVAL;
+    if (tu->morton_bits != 0 && (tu->morton_bits < 3 || tu->morton_bits > 30)) return TRIL_E_INVAL;
+    c->block = blk;
+    c->step_batch = tu->step_batch;
+    c->morton_param = tu->morton_bits;
+    return TRIL_OK;
+}
+
+int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, int32_t n_probe,
+                  tril_tune *best) {
+    if (!c || !best || k0 < 0 || n_probe < 1) return TRIL_E_INVAL;
+    CHK(check_beam(t));
+    CHK(check_beam(q));
+    if (q->n_inst != t->n_inst) return TRIL_E_STATE;
+    if ((int64_t)k0 + n_probe - 1 > INT32_MAX) return TRIL_E_INVAL;
+    const int64_t cap = (int64_t)1 << 22;
+    tril_pairs pr{cap, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const uint32_t save_flags = c->flags;
+    int rc = TRIL_OK;
+    auto cleanup = [&]() {
+        dev_free(pr.i); dev_free(pr.j); dev_free(pr.step); dev_free(pr.count);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        c->flags = save_flags;
+    };
+    if ((rc = dev_alloc(&pr.i, cap)) != TRIL_OK || (rc = dev_alloc(&pr.j, cap)) != TRIL_OK ||
+        (rc = dev_alloc(&pr.step, cap)) != TRIL_OK || (rc = dev_alloc(&pr.count, 1)) != TRIL_OK) {
+        cleanup();
+        return rc;
+    }
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        cleanup();
+        return hip_fail(he);
+    }
+    c->flags &= ~TRIL_TIMING;  // time graph replays, as a run without per-phase events
+    const int64_t rows = std::max<int64_t>(std::max(t->n, q->n), 1);
+    auto probe = [&](int blk, int sb, int mb, double &ms) -> int {
+        c->block = blk;
+        c->step_batch = sb;
+        c->morton_param = mb;
+        for (int rep = 0; rep < 2; ++rep) {
+            HIPCHK(hipMemsetAsync(pr.count, 0, sizeof(int64_t), c->st));
+            HIPCHK(hipEventRecord(e0, c->st));
+            CHK(tril_run(c, t, q, k0, n_probe, &pr));
+            HIPCHK(hipEventRecord(e1, c->st));
+        }
+        HIPCHK(hipEventSynchronize(e1));
+        float f = 0.f;
+        HIPCHK(hipEventElapsedTime(&f, e0, e1));
+        ms = (double)f / n_probe;
+        return TRIL_OK;
+    };
+    tril_tune cur{256, 0, 0, 0, 0.0};
+    cur.step_batch = pick_batch(c, t, q, n_probe);
+    double best_ms = 0.0;
+    if ((rc = probe(cur.block_traverse, cur.step_batch, cur.morton_bits, best_ms)) != TRIL_OK) {
+        cleanup();
+        return rc;
+    }
+    for (int sb : {1, 2, 4, 8, 16, 32, 64}) {
+        if (sb == cur.step_batch || sb > n_probe || (int64_t)sb * rows > ((int64_t)1 << 26)) continue;
+        double ms = 0.0;
+        if ((rc = probe(cur.block_traverse, sb, cur.morton_bits, ms)) != TRIL_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            cur.step_batch = sb;
+        }
+    }
+    for (int blk : {64, 128, 512}) {
+        if (rc != TRIL_OK) break;
+        double ms = 0.0;
+        if ((rc = probe(blk, cur.step_batch, cur.morton_bits, ms)) != TRIL_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            cur.block_traverse = blk;
+        }
+    }
+    if (rc == TRIL_OK) {
+        double ms = 0.0;
+        if ((rc = probe(cur.block_traverse, cur.step_batch, 30, ms)) == TRIL_OK && ms < best_ms) {
+            best_ms = ms;
+            cur.morton_bits = 30;
+        }
+    }
+    cleanup();
+    if (rc != TRIL_OK) return rc;
+    cur.ms_per_step = best_ms;
+    c->block = cur.block_traverse;
+    c->step_batch = cur.step_batch;
+    c->morton_param = cur.morton_bits;
+    *best = cur;
+    return tril_reset_counters(c);
+}
+
 int tril_reset_counters(tril_ctx *c) {
     if (!c) return TRIL_E_INVAL;
     HIPCHK(hipStreamSynchronize(c->st));

@@ -65,8 +65,14 @@ class tril_stats_t(ctypes.Structure):
                 ("n_timed_launches", ctypes.c_int64), ("n_fp64_rechecks", ctypes.c_int64)]
 
 
+class tril_tune(ctypes.Structure):
+    _fields_ = [("block_traverse", ctypes.c_int32), ("step_batch", ctypes.c_int32),
+                ("morton_bits", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("ms_per_step", ctypes.c_double)]
+
+
 EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats",
-           "tril_reset_counters", "tril_destroy", "tril_strerror", "tril_last_hip_error",
+           "tril_autotune", "tril_set_tune", "tril_reset_counters", "tril_destroy", "tril_strerror", "tril_last_hip_error",
            "tril_dbg_sort_u32", "tril_dbg_sort_u64", "tril_dbg_morton", "tril_dbg_pair_eval",
            "tril_dbg_pair_eval32",
            "tril_dbg_tree", "tril_dbg_boxes", "tril_dbg_candidates")
@@ -89,6 +95,9 @@ def lib() -> ctypes.CDLL:
     L.tril_run.argtypes = [vp, ctypes.POINTER(tril_beam), ctypes.POINTER(tril_beam), i32, i32,
                            ctypes.POINTER(tril_pairs)]
     L.tril_stats.argtypes = [vp, ctypes.POINTER(tril_pairs), ctypes.POINTER(tril_stats_t)]
+    L.tril_autotune.argtypes = [vp, ctypes.POINTER(tril_beam), ctypes.POINTER(tril_beam), i32, i32,
+                                ctypes.POINTER(tril_tune)]
+    L.tril_set_tune.argtypes = [vp, ctypes.POINTER(tril_tune)]
     L.tril_reset_counters.argtypes = [vp]
     L.tril_destroy.argtypes = [vp]
     L.tril_destroy.restype = None
@@ -228,6 +237,24 @@ def tril_collide(ctx, query: Beam, step: int, pairs: Pairs) -> None:
 def tril_run(ctx, target: Beam, query: Beam, k0: int, n_steps: int, pairs: Pairs) -> None:
     _check(lib().tril_run(ctx, ctypes.byref(target.c), ctypes.byref(query.c), int(k0),
                           int(n_steps), ctypes.byref(pairs.c)), "tril_run")
+
+
+TUNE_KEYS = ("block_traverse", "step_batch", "morton_bits")
+
+
+def tril_autotune(ctx, target: Beam, query: Beam, k0: int, n_probe: int) -> dict:
+    t = tril_tune()
+    _check(lib().tril_autotune(_h(ctx), ctypes.byref(target.c), ctypes.byref(query.c), int(k0),
+                               int(n_probe), ctypes.byref(t)), "tril_autotune")
+    return {"block_traverse": t.block_traverse, "step_batch": t.step_batch,
+            "morton_bits": t.morton_bits, "ms_per_step": t.ms_per_step}
+
+
+def tril_set_tune(ctx, tune: dict) -> None:
+    t = tril_tune()
+    for k in TUNE_KEYS:
+        setattr(t, k, int(tune[k]))
+    _check(lib().tril_set_tune(_h(ctx), ctypes.byref(t)), "tril_set_tune")
 
 
 def tril_stats(ctx, pairs: Optional[Pairs], n_bins: int = 0, n_step_counts: int = 0) -> dict:

@@ -81,6 +81,8 @@ def test_null_arguments():
     assert L.tril_run(None, None, None, 0, 1, None) == T.TRIL_E_INVAL
     assert L.tril_stats(None, None, None) == T.TRIL_E_INVAL
     assert L.tril_reset_counters(None) == T.TRIL_E_INVAL
+    assert L.tril_set_tune(None, None) == T.TRIL_E_INVAL
+    assert L.tril_autotune(None, None, None, 0, 1, None) == T.TRIL_E_INVAL
     L.tril_destroy(None)
     assert L.tril_dbg_sort_u32(None, None, -1, 30, None) == T.TRIL_E_INVAL
     assert L.tril_dbg_sort_u32(None, None, 10, 0, None) == T.TRIL_E_INVAL

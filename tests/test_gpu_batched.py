@@ -1,0 +1,116 @@
+"""Batched instances and the autotuner (GPU): many independent collisions in one run,
+launch configurations that change speed but never the pair set."""
+import numpy as np
+import pytest
+
+from paper_1608_01125_amd import autotune, beams
+from paper_1608_01125_amd import tril as T
+from tests.gpu_common import assert_parity, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+EDGES = beams.spectrum_edges()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    return _t
+
+
+def _batch(n_inst, n_max, boost):
+    """The first n_inst instances of the 64-instance workload, each beam cut to at most
+    n_max photons (a prefix of its i.i.d. draw), weights raised by `boost`."""
+    parts_a, parts_b = [], []
+    for m in range(n_inst):
+        wl = beams.batch64_instance(m)
+        wl = beams.batch64_instance(m, w=wl.a.w * boost)
+        A, B = beams.draw_pair(wl)
+        parts_a.append(beams.head(A, n_max))
+        parts_b.append(beams.head(B, n_max))
+    A, offA = beams.concat(parts_a)
+    B, offB = beams.concat(parts_b)
+    return A, offA, B, offB
+
+
+def _run(A, offA, B, offB, n_steps, tune=None, **kw):
+    ctx = T.Context(0.1, EDGES, **kw)
+    try:
+        tb, qb = T.Beam(B, offB), T.Beam(A, offA)
+        if tune is not None:
+            T.tril_set_tune(ctx.h, tune)
+        pairs = T.Pairs(1 << 20)
+        T.run_steps(ctx, tb, qb, n_steps, pairs, graph=True)
+        st = ctx.stats(pairs, n_step_counts=n_steps)
+        i, j, k = pairs.numpy()
+    finally:
+        ctx.close()
+    return i, j, k, st
+
+
+def test_all_64_instances_reduced(torch):
+    """All 64 instances of the batched workload (crossing angles 90..180 deg, mean
+    energies 0.6..10 MeV) in one run, each beam cut to 1500 photons."""
+    A, offA, B, offB = _batch(64, 1500, 400.0)
+    raw, S = oracle_run(A, B, 0.1, 400, EDGES, offA=offA, offB=offB)
+    gpu = _run(A, offA, B, offB, 400)
+    assert S.n_pairs > 100
+    assert_parity(gpu, raw, S, 400)
+
+
+def test_autotune_keeps_pair_set_and_caches(torch, tmp_path):
+    A, offA, B, offB = _batch(12, 4000, 200.0)
+    raw, S = oracle_run(A, B, 0.1, 400, EDGES, offA=offA, offB=offB)
+    cache = str(tmp_path / "tune.json")
+    ctx = T.Context(0.1, EDGES)
+    try:
+        tb, qb = T.Beam(B, offB), T.Beam(A, offA)
+        cfg = autotune.tuned(ctx, tb, qb, 0.1, k0=160, n_probe=64, cache=cache)
+        assert not cfg["cached"]
+        assert cfg["block_traverse"] in (64, 128, 256, 512)
+        assert 1 <= cfg["step_batch"] <= 64 and cfg["ms_per_step"] > 0
+        assert cfg["morton_bits"] in (0, 30)
+        # the context now runs with the tuned configuration; counters were reset
+        st0 = ctx.stats(None)
+        assert st0["n_builds"] == 0 and st0["n_collides"] == 0
+        pairs = T.Pairs(1 << 20)
+        T.run_steps(ctx, tb, qb, 400, pairs, graph=True)
+        st = ctx.stats(pairs, n_step_counts=400)
+        i, j, k = pairs.numpy()
+    finally:
+        ctx.close()
+    assert_parity((i, j, k, st), raw, S, 400)
+    # a second process-like call finds the cache
+    ctx2 = T.Context(0.1, EDGES)
+    try:
+        cfg2 = autotune.tuned(ctx2, T.Beam(B, offB), T.Beam(A, offA), 0.1, k0=160, n_probe=64,
+                              cache=cache)
+    finally:
+        ctx2.close()
+    assert cfg2["cached"]
+    assert all(cfg2[k] == cfg[k] for k in T.TUNE_KEYS)
+
+
+@pytest.mark.parametrize("tune", [
+    {"block_traverse": 64, "step_batch": 3, "morton_bits": 30},
+    {"block_traverse": 512, "step_batch": 40, "morton_bits": 0},
+    {"block_traverse": 128, "step_batch": 1, "morton_bits": 18}])
+def test_any_launch_configuration_same_pairs(torch, tune):
+    A, offA, B, offB = _batch(8, 3000, 300.0)
+    raw, S = oracle_run(A, B, 0.1, 400, EDGES, offA=offA, offB=offB)
+    assert_parity(_run(A, offA, B, offB, 400, tune=tune), raw, S, 400)
+
+
+@pytest.mark.parametrize("bad", [
+    {"block_traverse": 96, "step_batch": 1, "morton_bits": 0},
+    {"block_traverse": 256, "step_batch": -1, "morton_bits": 0},
+    {"block_traverse": 256, "step_batch": 4, "morton_bits": 2}])
+def test_set_tune_rejects_bad_values(torch, bad):
+    ctx = T.Context(0.1, EDGES)
+    try:
+        with pytest.raises(T.TrilError) as e:
+            T.tril_set_tune(ctx.h, bad)
+        assert e.value.code == T.TRIL_E_INVAL
+    finally:
+        ctx.close()
