@@ -213,6 +213,63 @@ int tril_autotune(tril_ctx *ctx, const tril_beam *target, const tril_beam *query
  * TRIL_E_INVAL for values outside the ranges above. */
 int tril_set_tune(tril_ctx *ctx, const tril_tune *tune);
 
+/* ---------------------------------------------------------------------------------
+ * Statistical (ST) regime (Sec. 2.2, rate between two clouds of particles). Every
+ * photon macro-particle is a uniform cloud filling a box of the binning grid's cell
+ * size c = (c_x, c_y, c_z) about its position, density n = w / V with V = c_x c_y c_z.
+ * Over step k, with mid-step time t_m = k dt + dt/2, the pair (i, j) yields
+ *   Y_ij,k = n_i n_j sigma_BW(s_ij) (1 - u_i.u_j) dt V_ov(t_m)
+ * (V_ov: intersection volume of the two clouds at t_m; (1 - u_i.u_j) c the two-photon
+ * rate factor of the paper's reactivity; sigma = 0 at and below threshold). Yields are
+ * summed over steps and over the macro-particle pairs of each bin pair.
+ * ------------------------------------------------------------------------------- */
+
+/* Binning grid of one beam: position cell of X(t_bin) in the lab box [lo, hi]
+ * (n_pos cells per axis), energy bin log-spaced on [e_lo, e_hi] (n_e bins), polar-angle
+ * bin of the direction about `axis` on [0, th_max] (n_th bins); values outside a range
+ * fall in its edge bin. bin = (((ix ny + iy) nz + iz) n_e + ie) n_th + ith. */
+typedef struct {
+    double lo[3], hi[3];          /* [um], hi > lo */
+    int32_t n_pos[3];             /* >= 1 each */
+    int32_t n_e;                  /* >= 1 */
+    double e_lo, e_hi;            /* [MeV], 0 < e_lo < e_hi */
+    int32_t n_th;                 /* >= 1 */
+    int32_t pad0;
+    double th_max;                /* [rad], > 0 */
+    double axis[3];               /* unit vector */
+    double t_bin;                 /* [um/c] */
+} tril_st_grid;
+
+/* Bin index of every photon (device bins[n], -1 for invalid photon data) and, if sums is
+ * not NULL, per-bin sums (device sums[5 x number of bins], caller-zeroed, accumulated):
+ * w, w E, w ux, w uy, w uz. Asynchronous on the HIP stream (NULL = default).
+ * TRIL_E_INVAL for bad arguments or more than 2^31 - 1 bins. */
+int tril_st_bin(const tril_beam *beam, const tril_st_grid *grid, int32_t *bins, double *sums,
+                void *hip_stream);
+
+/* Caller-owned bin-pair table (open addressing): cap slots, a power of two;
+ * key[slot] = query bin x n_target_bins + target bin, or -1 for an empty slot;
+ * yield[slot] = summed yield. tril_st_exact clears it first. */
+typedef struct {
+    int64_t cap;
+    int64_t *key;                 /* device, cap */
+    double *yield;                /* device, cap */
+} tril_st_table;
+
+/* Exact ST yields for steps k0 .. k0+n_steps-1: clouds of the target beam in a
+ * hierarchy per step (boxes of edges `cell` about the mid-step positions), clouds of the
+ * query beam descending it, Y evaluated in FP64 for every overlapping pair and added to
+ * the table under (q_bins[i], t_bins[j]). Bins are per caller row (from tril_st_bin);
+ * pairs with a negative bin are skipped. *total (host) receives the sum of all yields.
+ * Synchronous. TRIL_E_OVERFLOW if the table filled up; TRIL_E_DATA for invalid photon
+ * data; TRIL_E_INVAL for bad arguments (cell not finite and > 0, cap not a power of two,
+ * n_target_bins < 1 or >= 2^31). Counters accumulate as for tril_run (node visits; cloud
+ * pair-steps with a yield in n_candidates). */
+int tril_st_exact(tril_ctx *ctx, const tril_beam *target, const int32_t *t_bins,
+                  int64_t n_target_bins, const tril_beam *query, const int32_t *q_bins,
+                  const double cell[3], int32_t k0, int32_t n_steps, tril_st_table *table,
+                  double *total);
+
 /* Zero the accumulated counters and device error flags (asynchronous). */
 int tril_reset_counters(tril_ctx *ctx);
 

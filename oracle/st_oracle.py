@@ -1,0 +1,102 @@
+"""Statistical (cloud) regime oracle: binning and bin-pair yields, plain numpy + the C
+oracle's per-pair yields (oracle/tril_oracle.c, orc_st_pairs).
+
+TEST INFRASTRUCTURE ONLY: used by the test suite and the benchmark's CPU baseline,
+never by the product library.
+
+Binning (one beam, grid g): position cell of X(t_bin) = x0 + t_bin p/E in the box
+[lo, hi] with n_pos cells per axis; energy bin log-spaced on [e_lo, e_hi] (n_e bins);
+polar-angle bin of the direction about the unit axis on [0, th_max] (n_th bins);
+out-of-range values fall in the edge bin; bin = (((ix ny + iy) nz + iz) n_e + ie) n_th + ith.
+Each index is floor(fraction of the range x number of bins), evaluated in FP64 in that
+order: ((X - lo) / (hi - lo)) n, (log(E / e_lo) / log(e_hi / e_lo)) n_e,
+(acos(u.axis / |u|) / th_max) n_th.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+from . import oracle as O
+
+
+@dataclass
+class Grid:
+    lo: Tuple[float, float, float]
+    hi: Tuple[float, float, float]
+    n_pos: Tuple[int, int, int]
+    n_e: int
+    e_lo: float
+    e_hi: float
+    n_th: int
+    th_max: float
+    axis: Tuple[float, float, float]
+    t_bin: float
+
+    @property
+    def n_bins(self) -> int:
+        return int(np.prod(self.n_pos)) * self.n_e * self.n_th
+
+    @property
+    def cell(self) -> np.ndarray:
+        return (np.asarray(self.hi) - np.asarray(self.lo)) / np.asarray(self.n_pos)
+
+
+def _cell(v: np.ndarray, n: int) -> np.ndarray:
+    f = np.floor(v)
+    f = np.where(np.isnan(f), 0.0, f)
+    return np.clip(f, 0, n - 1).astype(np.int64)
+
+
+def bin_beam(beam: Dict[str, np.ndarray], g: Grid) -> Tuple[np.ndarray, np.ndarray]:
+    """Bin index per photon and per-bin sums (w, w E, w ux, w uy, w uz) as a dict
+    {bin: 5-vector} over occupied bins."""
+    E = beam["E"]
+    u = np.stack([beam["px"] / E, beam["py"] / E, beam["pz"] / E], axis=1)
+    X = np.stack([beam["x"], beam["y"], beam["z"]], axis=1) + g.t_bin * u
+    ip = [_cell(((X[:, a] - g.lo[a]) / (g.hi[a] - g.lo[a])) * g.n_pos[a], g.n_pos[a]) for a in range(3)]
+    ie = _cell((np.log(E / g.e_lo) / np.log(g.e_hi / g.e_lo)) * g.n_e, g.n_e)
+    uu = (u[:, 0] * u[:, 0] + u[:, 1] * u[:, 1]) + u[:, 2] * u[:, 2]
+    cth = ((u[:, 0] * g.axis[0] + u[:, 1] * g.axis[1]) + u[:, 2] * g.axis[2]) / np.sqrt(uu)
+    cth = np.clip(cth, -1.0, 1.0)
+    ith = _cell((np.arccos(cth) / g.th_max) * g.n_th, g.n_th)
+    b = (((ip[0] * g.n_pos[1] + ip[1]) * g.n_pos[2] + ip[2]) * g.n_e + ie) * g.n_th + ith
+    w = beam["w"]
+    vals = np.stack([w, w * E, w * u[:, 0], w * u[:, 1], w * u[:, 2]], axis=1)
+    occ, inv = np.unique(b, return_inverse=True)
+    sums = np.zeros((len(occ), 5))
+    np.add.at(sums, inv, vals)
+    return b.astype(np.int64), dict(zip(occ.tolist(), sums))
+
+
+def bin_margin(beam: Dict[str, np.ndarray], g: Grid) -> np.ndarray:
+    """Distance of each photon's bin coordinates from the nearest bin edge (in units of
+    one bin): photons closer than ~1e-12 are knife-edge cases where rounding of log and
+    acos on two platforms may pick different bins."""
+    E = beam["E"]
+    u = np.stack([beam["px"] / E, beam["py"] / E, beam["pz"] / E], axis=1)
+    X = np.stack([beam["x"], beam["y"], beam["z"]], axis=1) + g.t_bin * u
+    parts = [((X[:, a] - g.lo[a]) / (g.hi[a] - g.lo[a])) * g.n_pos[a] for a in range(3)]
+    parts.append((np.log(E / g.e_lo) / np.log(g.e_hi / g.e_lo)) * g.n_e)
+    uu = (u[:, 0] * u[:, 0] + u[:, 1] * u[:, 1]) + u[:, 2] * u[:, 2]
+    cth = np.clip(((u[:, 0] * g.axis[0] + u[:, 1] * g.axis[1]) + u[:, 2] * g.axis[2]) / np.sqrt(uu), -1, 1)
+    parts.append((np.arccos(cth) / g.th_max) * g.n_th)
+    return np.min([np.abs(p - np.round(p)) for p in parts], axis=0)
+
+
+def st_table(A, bins_a, B, bins_b, n_bins_b: int, dt: float, k0: int, n_steps: int, cell,
+             rows: Optional[np.ndarray] = None) -> Tuple[Dict[int, float], float]:
+    """Bin-pair yields {bin_a * n_bins_b + bin_b: Y} and the total, from the per-pair
+    yields of the C oracle (query beam A, target beam B)."""
+    Y = O.st_pairs(A, B, dt, k0, n_steps, cell, rows=rows)
+    ra = bins_a if rows is None else bins_a[rows]
+    keys = ra[:, None] * n_bins_b + bins_b[None, :]
+    nz = Y > 0.0
+    k = keys[nz]
+    v = Y[nz]
+    uk, inv = np.unique(k, return_inverse=True)
+    tot = np.zeros(len(uk))
+    np.add.at(tot, inv, v)
+    return dict(zip(uk.tolist(), tot.tolist())), float(Y.sum())

@@ -229,6 +229,65 @@ void orc_collide(const orc_beam *A, const orc_beam *B,
     o->pairs_full += full;
 }
 
+/* ---- statistical (cloud) regime ------------------------------------------------
+ *
+ * Each macro-particle is a uniform cloud filling a box of edges cell[0..2] about its
+ * position, with number density w / V, V = cell[0] cell[1] cell[2] (the paper's rate
+ * picture of Sec. 2.2: rate n_I n_II <sigma v> between two clouds, <sigma v> for two
+ * photons carrying the factor (1 - cos phi) c). Over step k the pair (i, j) yields
+ *   Y = n_i n_j sigma(s) (1 - u_i.u_j) dt V_ov,
+ * V_ov the volume common to the two clouds at the middle of the step, t = k dt + dt/2.
+ * out[a * nB + j] receives Y summed over steps k0 .. k0+n_steps-1 for query row
+ * rows[a] (all rows of A when rows is NULL, then a = i). */
+static double orc_cloud_overlap(double dx, double dy, double dz, const double cell[3])
+{
+    double ov = 1.0;
+    const double d[3] = {dx, dy, dz};
+    for (int a = 0; a < 3; ++a) {
+        const double len = cell[a] - fabs(d[a]);
+        if (!(len > 0.0))
+            return 0.0;
+        ov *= len;
+    }
+    return ov;
+}
+
+void orc_st_pairs(const orc_beam *A, const orc_beam *B, const int64_t *rows, int64_t n_rows,
+                  double dt, int32_t k0, int32_t n_steps, const double *cell, double *out)
+{
+    const int64_t nr = rows ? n_rows : A->n;
+    const double vol = cell[0] * cell[1] * cell[2];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (int64_t a = 0; a < nr; ++a) {
+        const int64_t i = rows ? rows[a] : a;
+        const double Ei = A->E[i];
+        const double ui[3] = {A->px[i] / Ei, A->py[i] / Ei, A->pz[i] / Ei};
+        for (int64_t j = 0; j < B->n; ++j) {
+            const double Ej = B->E[j];
+            const double uj[3] = {B->px[j] / Ej, B->py[j] / Ej, B->pz[j] / Ej};
+            const double s = orc_invariant(Ei, ui[0], ui[1], ui[2], Ej, uj[0], uj[1], uj[2]);
+            double y = 0.0;
+            if (s > 1.0) {
+                const double dens2 = (A->w[i] * B->w[j]) / (vol * vol);
+                const double rate = dens2 * orc_sigma(s);
+                const double cosphi = (ui[0] * uj[0] + ui[1] * uj[1]) + ui[2] * uj[2];
+                for (int32_t k = k0; k < k0 + n_steps; ++k) {
+                    const double tm = (double)k * dt + 0.5 * dt;
+                    const double dx = (A->x[i] + tm * ui[0]) - (B->x[j] + tm * uj[0]);
+                    const double dy = (A->y[i] + tm * ui[1]) - (B->y[j] + tm * uj[1]);
+                    const double dz = (A->z[i] + tm * ui[2]) - (B->z[j] + tm * uj[2]);
+                    const double ov = orc_cloud_overlap(dx, dy, dz, cell);
+                    if (ov > 0.0)
+                        y += ((rate * (1.0 - cosphi)) * dt) * ov;
+                }
+            }
+            out[a * B->n + j] = y;
+        }
+    }
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -234,6 +234,58 @@ def broadband_16m(seed: int = 0, w: Optional[float] = None, n: int = 16_000_000)
     return Workload("broadband_16m", a, b, 0.04, 1000, seed)
 
 
+def st_headon(n_mp: int = 10_000_000, physical: float = 1e9, seed: int = 0) -> Workload:
+    """Statistical regime: beams shaped like the 1e6 head-on workload (Gaussian sigma_r =
+    2 um, sigma_z = 5 um, N(2, 0.2) MeV, 10 mrad), ``physical`` photons per beam carried by
+    ``n_mp`` macro-particles of equal weight, 400 steps of 0.1 um/c."""
+    base = gauss_headon_1m()
+    a = replace(base.a, n=n_mp, w=physical / n_mp)
+    b = replace(base.b, n=n_mp, w=physical / n_mp)
+    return Workload(f"st_headon_{n_mp}", a, b, base.dt, base.n_steps, seed)
+
+
+@dataclass(frozen=True)
+class StGridSpec:
+    """Binning grid of one beam in the statistical regime (field meanings as in
+    tril_st_grid): lab box, cells per axis, energy range and bins, polar-angle range and
+    bins about the beam axis, time at which positions are binned."""
+    lo: Tuple[float, float, float]
+    hi: Tuple[float, float, float]
+    n_pos: Tuple[int, int, int]
+    n_e: int
+    e_lo: float
+    e_hi: float
+    n_th: int
+    th_max: float
+    axis: Tuple[float, float, float]
+    t_bin: float
+
+    @property
+    def n_bins(self) -> int:
+        return int(np.prod(self.n_pos)) * self.n_e * self.n_th
+
+    @property
+    def cell(self) -> Tuple[float, float, float]:
+        return tuple((self.hi[a] - self.lo[a]) / self.n_pos[a] for a in range(3))
+
+
+def st_grid(wl: Workload, which: str, beam: Dict[str, np.ndarray], n_pos: int = 32,
+            n_e: int = 16, n_th: int = 8) -> StGridSpec:
+    """Grid of beam ``which`` ("a" or "b"): the lab box [+-4 sigma_r]^2 x [+-4 sigma_z]
+    about the origin (where both centres meet at mid-run, the time at which positions are
+    binned), n_e log-spaced energy bins over the beam's sampled energy range (widened by
+    1e-6 of itself at both ends, so no photon sits on an edge), n_th
+    polar-angle bins over [0, opening/2] about the beam's own axis."""
+    spec = wl.a if which == "a" else wl.b
+    phi = math.radians(spec.phi_deg)
+    axis = (math.sin(phi), 0.0, math.cos(phi))
+    r, zz = 4.0 * spec.size_r, 4.0 * spec.size_z
+    e = beam["E"]
+    return StGridSpec((-r, -r, -zz), (r, r, zz), (n_pos, n_pos, n_pos), n_e,
+                      float(e.min()) * (1.0 - 1e-6), float(e.max()) * (1.0 + 1e-6), n_th,
+                      0.5 * spec.opening, axis, 0.5 * wl.n_steps * wl.dt)
+
+
 def spectrum_edges(lo: float = 0.0, hi: float = 25.0, n_bins: int = 50) -> np.ndarray:
     """Default pair-energy (E_i + E_j) histogram edges in MeV, strictly increasing."""
     return np.linspace(lo, hi, n_bins + 1)

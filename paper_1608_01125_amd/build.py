@@ -20,7 +20,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtril.so")
 
-SOURCES = ["abi.hip", "radix_sort.hip", "lbvh.hip", "traverse.hip", "narrow.hip", "stats.hip"]
+SOURCES = ["abi.hip", "radix_sort.hip", "lbvh.hip", "traverse.hip", "narrow.hip", "stats.hip",
+           "st.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -92,6 +92,8 @@ struct tril_ctx {
     int block = 256;
     int32_t step_batch = 0;         // steps per launch in tril_run (0 = automatic)
     int morton_param = 0;           // Morton bits requested (0 = automatic)
+    CloudBox cloud{0, {0.0, 0.0, 0.0}};  // box kind of the builds (statistical regime: clouds)
+    double *st_slots = nullptr;     // statistical regime: per-wave yield sums (kCounterSlots)
     int morton_bits = 30;           // Morton bits of the sort keys of the current build/collide
     double sigma_up = 0.0;
     DevCounters *d_cnt = nullptr;
@@ -359,7 +361,7 @@ int enqueue_order(tril_ctx *c, const BeamDev &b, bool query_side, WorkBeam &w, h
     unsigned long long *k64a = query_side ? c->q_k64a : c->t_k64a;
     unsigned long long *k64b = query_side ? c->q_k64b : c->t_k64b;
     uint32_t *va = query_side ? c->q_va : c->t_va, *vb = query_side ? c->q_vb : c->t_vb;
-    launch_boxes_keys(b, false, c->dt, c->sigma_up, stats, stats, kl, box, k32a, k64a, va,
+    launch_boxes_keys(b, false, c->cloud, c->dt, c->sigma_up, stats, stats, kl, box, k32a, k64a, va,
                       c->d_cnt, st);
     const uint32_t *rows;
     if (!kl.wide)
@@ -400,7 +402,8 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
     const KeyLayout kl = key_layout(n_comb, c->morton_bits);
     if (timed) CHK(timing_pair(c, st, c->ev_build, true));
     launch_prologue(c->d_cnt, 0, t.m, st);
-    launch_boxes_keys(t, false, c->dt, c->sigma_up, c->t_stats, c->t_stats, kl, c->t_box, c->t_k32a,
+    launch_boxes_keys(t, false, c->cloud, c->dt, c->sigma_up, c->t_stats, c->t_stats, kl, c->t_box,
+                      c->t_k32a,
                       c->t_k64a, c->t_va, c->d_cnt, st);
     const uint32_t *rows = nullptr;
     int32_t *roots = n_comb > 1 ? c->inst_root : nullptr;
@@ -428,14 +431,13 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
 // Kernels of one collide (query view q with the same step count as the target; the
 // query statistics c->q_stats are current). Without sorting, the query order kept in
 // c->q_keep (one step's order, repeated per step) is used.
-int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStream_t st,
-                    bool timed, bool sort_queries) {
+// Query boxes and, when sort_queries, their Morton order (c->q_order).
+int enqueue_query_prep(tril_ctx *c, const BeamDev &q, hipStream_t st, bool sort_queries) {
     const int64_t nv = (int64_t)q.m * q.n;
     const int32_t n_comb = q.m * q.n_inst;
     const KeyLayout kl = key_layout(n_comb, c->morton_bits);
-    if (timed) CHK(timing_pair(c, st, c->ev_prep, true));
-    launch_prologue(c->d_cnt, 1, q.m, st);
-    launch_boxes_keys(q, true, c->dt, c->sigma_up, c->t_stats, c->q_stats, kl, c->q_box, c->q_k32a,
+    launch_boxes_keys(q, true, c->cloud, c->dt, c->sigma_up, c->t_stats, c->q_stats, kl, c->q_box,
+                      c->q_k32a,
                       c->q_k64a, c->q_va, c->d_cnt, st);
     if (sort_queries && nv > 0) {
         bool alt;
@@ -448,6 +450,15 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
         c->q_order = (nv <= 1) ? c->q_va : (alt ? c->q_vb : c->q_va);
         c->q_order_len = nv;
     }
+    return TRIL_OK;
+}
+
+int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStream_t st,
+                    bool timed, bool sort_queries) {
+    const int64_t nv = (int64_t)q.m * q.n;
+    if (timed) CHK(timing_pair(c, st, c->ev_prep, true));
+    launch_prologue(c->d_cnt, 1, q.m, st);
+    CHK(enqueue_query_prep(c, q, st, sort_queries));
     if (timed) CHK(timing_pair(c, st, c->ev_prep, false));
     if (timed) CHK(timing_pair(c, st, c->ev_trav, true));
     const int64_t ntv = (int64_t)c->tgt.m * c->tgt.n;
@@ -842,7 +853,7 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     HIPCHK(hipStreamSynchronize(c->st));
     HIPCHK(hipMemcpy(c->h_cnt, c->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost));
     const DevCounters &h = *c->h_cnt;
-    out->n_candidates = (int64_t)h.cand_total;
+    out->n_candidates = (int64_t)h.cand_total + (int64_t)h.st_pairs;
     int64_t visits = 0, queries = 0;
     for (int k = 0; k < kCounterSlots; ++k) {
         visits += (int64_t)h.visits[k];
@@ -901,6 +912,112 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     unsigned int err2 = 0;
     HIPCHK(hipMemcpy(&err2, &c->d_cnt->err, sizeof(err2), hipMemcpyDeviceToHost));
     if (err2 & kErrSpin) return TRIL_E_INTERNAL;
+    return TRIL_OK;
+}
+
+int tril_st_bin(const tril_beam *b, const tril_st_grid *g, int32_t *bins, double *sums,
+                void *stream) {
+    CHK(check_beam(b));
+    if (!g || (b->n > 0 && !bins)) return TRIL_E_INVAL;
+    int64_t nb = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (g->n_pos[a] < 1 || !std::isfinite(g->lo[a]) || !std::isfinite(g->hi[a]) ||
+            !(g->hi[a] > g->lo[a]))
+            return TRIL_E_INVAL;
+        nb *= g->n_pos[a];
+    }
+    if (g->n_e < 1 || g->n_th < 1 || !(g->e_lo > 0.0) || !(g->e_hi > g->e_lo) ||
+        !std::isfinite(g->e_hi) || !(g->th_max > 0.0) || !std::isfinite(g->th_max) ||
+        !std::isfinite(g->t_bin))
+        return TRIL_E_INVAL;
+    nb *= (int64_t)g->n_e * g->n_th;
+    if (nb > INT32_MAX) return TRIL_E_INVAL;
+    const double an = std::sqrt(g->axis[0] * g->axis[0] + g->axis[1] * g->axis[1] +
+                                g->axis[2] * g->axis[2]);
+    if (!(std::fabs(an - 1.0) < 1e-9)) return TRIL_E_INVAL;
+    StGridDev d;
+    for (int a = 0; a < 3; ++a) {
+        d.lo[a] = g->lo[a];
+        d.hi[a] = g->hi[a];
+        d.n_pos[a] = g->n_pos[a];
+        d.axis[a] = g->axis[a];
+    }
+    d.n_e = g->n_e; d.e_lo = g->e_lo; d.e_hi = g->e_hi;
+    d.n_th = g->n_th; d.th_max = g->th_max; d.t_bin = g->t_bin;
+    BeamDev v = view(b, nullptr, 1);
+    v.inst_off = nullptr;
+    v.n_inst = 1;
+    launch_st_bin(v, d, bins, sums, reinterpret_cast<hipStream_t>(stream));
+    HIPCHK(hipGetLastError());
+    return TRIL_OK;
+}
+
+int tril_st_exact(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_t n_t_bins,
+                  const tril_beam *q, const int32_t *q_bins, const double cell[3], int32_t k0,
+                  int32_t n_steps, tril_st_table *tab, double *total) {
+    if (!c || !cell || !tab || !total || k0 < 0 || n_steps < 0) return TRIL_E_INVAL;
+    CHK(check_beam(t));
+    CHK(check_beam(q));
+    if ((t->n > 0 && !t_bins) || (q->n > 0 && !q_bins)) return TRIL_E_INVAL;
+    if (n_t_bins < 1 || n_t_bins > INT32_MAX) return TRIL_E_INVAL;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(cell[a]) || !(cell[a] > 0.0)) return TRIL_E_INVAL;
+    if (tab->cap < 1 || (tab->cap & (tab->cap - 1)) != 0 || !tab->key || !tab->yield)
+        return TRIL_E_INVAL;
+    if (q->n_inst != t->n_inst) return TRIL_E_STATE;
+    if ((int64_t)k0 + n_steps - 1 > INT32_MAX) return TRIL_E_INVAL;
+    *total = 0.0;
+    if (!c->st_slots) CHK(dev_alloc(&c->st_slots, (size_t)kCounterSlots));
+    launch_st_clear(reinterpret_cast<long long *>(tab->key), tab->yield, tab->cap, c->st_slots,
+                    c->st);
+    const int32_t m = n_steps > 0 ? pick_batch(c, t, q, n_steps) : 1;
+    CHK(ensure_target(c, (int64_t)m * t->n, (int64_t)m * t->n_inst, t->n_inst));
+    CHK(ensure_query(c, (int64_t)m * q->n, (int64_t)m * q->n_inst, q->n_inst));
+    CHK(upload_offsets(c, t, c->d_t_off, c->h_t_off));
+    CHK(upload_offsets(c, q, c->d_q_off, c->h_q_off));
+    c->nt = t->n;
+    c->q_order_key = nullptr;
+    const BeamDev t1 = view(t, c->d_t_off, 1), q1 = view(q, c->d_q_off, 1);
+    launch_beam_stats(t1, c->t_spart, c->t_stats, c->d_cnt, c->st);
+    launch_beam_stats(q1, c->q_spart, c->q_stats, c->d_cnt, c->st);
+    const StCell sc{{cell[0], cell[1], cell[2]}};
+    c->cloud = CloudBox{1, {0.5 * cell[0], 0.5 * cell[1], 0.5 * cell[2]}};
+    c->morton_bits = c->morton_param > 0 ? c->morton_param : 30;
+    int rc = TRIL_OK;
+    for (int32_t k = k0, left = n_steps; left > 0 && rc == TRIL_OK;) {
+        const int32_t mb = std::min(m, left);
+        c->tgt = view(t, c->d_t_off, mb);
+        const BeamDev qv = view(q, c->d_q_off, mb);
+        launch_set_step(c->d_cnt, k, c->st);
+        if ((rc = enqueue_build(c, c->st, false)) != TRIL_OK) break;
+        launch_prologue(c->d_cnt, 1, mb, c->st);
+        if ((rc = enqueue_query_prep(c, qv, c->st, true)) != TRIL_OK) break;
+        const int64_t nqv = (int64_t)mb * q->n;
+        launch_st_traverse(c->nodes, (int64_t)mb * t->n, c->q_box, nqv > 0 ? c->q_order : nullptr,
+                           nqv, c->inst_root, c->inst_stop, qv, c->tgt, q_bins, t_bins,
+                           n_t_bins, c->dt, sc, reinterpret_cast<long long *>(tab->key),
+                           tab->yield, tab->cap, c->st_slots, c->d_cnt, c->st);
+        k += mb;
+        left -= mb;
+    }
+    c->cloud.on = 0;
+    CHK(rc);
+    HIPCHK(hipGetLastError());
+    c->built = true;
+    c->built_step = k0 + std::max(n_steps, 1) - 1;
+    c->res_t = t1;
+    c->last_q = q1;
+    HIPCHK(hipStreamSynchronize(c->st));
+    double slots[kCounterSlots];
+    HIPCHK(hipMemcpy(slots, c->st_slots, sizeof(slots), hipMemcpyDeviceToHost));
+    double tot = 0.0;
+    for (double v : slots) tot += v;
+    *total = tot;
+    unsigned int err = 0;
+    HIPCHK(hipMemcpy(&err, &c->d_cnt->err, sizeof(err), hipMemcpyDeviceToHost));
+    if (err & kErrData) return TRIL_E_DATA;
+    if (err & kErrSpin) return TRIL_E_INTERNAL;
+    if (err & kErrTableFull) return TRIL_E_OVERFLOW;
     return TRIL_OK;
 }
 
@@ -1029,6 +1146,7 @@ void tril_destroy(tril_ctx *c) {
         free_work(c->wt[p]);
         free_work(c->wq[p]);
     }
+    dev_free(c->st_slots);
     dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->inst_root); dev_free(c->inst_stop);
     dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
     dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);

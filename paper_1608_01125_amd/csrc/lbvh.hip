@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(256) k_fold_stats(const StatsPartial *__restri
 // One thread per row, looping over the m steps of the launch: the row's photon data
 // is read once and its m boxes and keys are written at the virtual elements s n + i.
 template <bool kWide>
-__global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, double dt,
+__global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, CloudBox cloud, double dt,
                                                     double sigma_up,
                                                     const InstStats *__restrict__ t_stats,
                                                     const InstStats *__restrict__ self_stats,
@@ -330,13 +330,13 @@ __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, double
     const double ux = px / E, uy = py / E, uz = pz / E;
     double pad = 0.0;
     bool below = false;
-    if (query && ok) {
+    if (query && ok) {  // (the cloud regime needs no radius pad: clouds overlap or not)
         const InstStats &ts = t_stats[mi];
         const double emax_t = __longlong_as_double((long long)ts.emax);
         const double wmax_t = __longlong_as_double((long long)ts.wmax);
         const double smax = (E * emax_t) / (kMe * kMe);
         below = !(smax > 1.0);
-        pad = sqrt((sqrt(w * wmax_t) * sigma_up) / M_PI) * (1.0 + 1e-6);
+        if (!cloud.on) pad = sqrt((sqrt(w * wmax_t) * sigma_up) / M_PI) * (1.0 + 1e-6);
     }
     const InstStats &ss = self_stats[mi];
     double mn0[3], mnu[3], mx0[3], mxu[3];
@@ -360,12 +360,21 @@ __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, double
             o.hix = o.hiy = o.hiz = -INFINITY;
             o.tag = -1;
         } else {
-            // position at t_k exactly as the narrow phase forms it, and one step later
-            const double ax = x + t * ux, ay = y + t * uy, az = z + t * uz;
-            const double bx = ax + dt * ux, by = ay + dt * uy, bz = az + dt * uz;
+            double lo[3], hi[3];
+            if (cloud.on) {
+                // cloud of the statistical regime: cell-sized box about the mid-step position
+                const double tm = t + 0.5 * dt;
+                const double cx = x + tm * ux, cy = y + tm * uy, cz = z + tm * uz;
+                lo[0] = cx - cloud.h[0]; lo[1] = cy - cloud.h[1]; lo[2] = cz - cloud.h[2];
+                hi[0] = cx + cloud.h[0]; hi[1] = cy + cloud.h[1]; hi[2] = cz + cloud.h[2];
+            } else {
+                // position at t_k exactly as the narrow phase forms it, and one step later
+                const double ax = x + t * ux, ay = y + t * uy, az = z + t * uz;
+                const double bx = ax + dt * ux, by = ay + dt * uy, bz = az + dt * uz;
+                lo[0] = fmin(ax, bx); lo[1] = fmin(ay, by); lo[2] = fmin(az, bz);
+                hi[0] = fmax(ax, bx); hi[1] = fmax(ay, by); hi[2] = fmax(az, bz);
+            }
             // slack far above FP64 rounding of the positions (1e-12 of the magnitude)
-            const double lo[3] = {fmin(ax, bx), fmin(ay, by), fmin(az, bz)};
-            const double hi[3] = {fmax(ax, bx), fmax(ay, by), fmax(az, bz)};
             float lo32[3], hi32[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -737,19 +746,19 @@ void launch_beam_stats(const BeamDev &b, StatsPartial *partials, InstStats *stat
                        stats);
 }
 
-void launch_boxes_keys(const BeamDev &b, bool query, double dt, double sigma_up,
+void launch_boxes_keys(const BeamDev &b, bool query, const CloudBox &cloud, double dt, double sigma_up,
                        const InstStats *t_stats, const InstStats *self_stats, KeyLayout kl,
                        PBox *out, uint32_t *keys32, unsigned long long *keys64, uint32_t *vals,
                        DevCounters *c, hipStream_t st) {
     if (b.n <= 0 || b.m <= 0) return;
     if (kl.wide)
         hipLaunchKernelGGL(k_boxes_keys<true>, dim3(grid_for(b.n, 256)), dim3(256), 0, st, b,
-                           query ? 1 : 0, dt, sigma_up, t_stats, self_stats, kl, out, keys32,
-                           keys64, vals, c);
+                           query ? 1 : 0, cloud, dt, sigma_up, t_stats, self_stats, kl, out,
+                           keys32, keys64, vals, c);
     else
         hipLaunchKernelGGL(k_boxes_keys<false>, dim3(grid_for(b.n, 256)), dim3(256), 0, st, b,
-                           query ? 1 : 0, dt, sigma_up, t_stats, self_stats, kl, out, keys32,
-                           keys64, vals, c);
+                           query ? 1 : 0, cloud, dt, sigma_up, t_stats, self_stats, kl, out,
+                           keys32, keys64, vals, c);
 }
 
 void launch_gather_beam(const BeamDev &src, const uint32_t *order, double *dst_soa,

@@ -30,16 +30,6 @@ __device__ __forceinline__ uint32_t count_below(unsigned long long mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__device__ __forceinline__ double bw_sigma(double s) {
-    if (!(s > 1.0)) return 0.0;
-    const double k_sig = (0.5 * M_PI) * (kRe * kRe);
-    const double b2 = (s - 1.0) / s;
-    const double b = sqrt(b2);
-    const double L = 2.0 * log1p(b) + log(s);
-    const double br = (3.0 - b2 * b2) * L - (2.0 * b) * (2.0 - b2);
-    return (k_sig / s) * br;
-}
-
 // ---------------------------------------------------------------- FP32 stage
 //
 // The FP32 stage evaluates s, d^2 and r^2 in single precision together with a running

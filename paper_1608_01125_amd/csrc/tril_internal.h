@@ -19,6 +19,20 @@ constexpr uint32_t kErrData = 1u;          // non-finite input, E <= 0 or w < 0
 constexpr uint32_t kErrCandOverflow = 2u;  // broad-phase candidate buffer full
 constexpr uint32_t kErrSpin = 4u;          // a bounded device wait ran out
 constexpr uint32_t kErrPairOverflow = 8u;  // caller pair buffer full
+constexpr uint32_t kErrTableFull = 16u;    // statistical-regime bin-pair table full
+
+// Breit-Wheeler total cross-section (Eq. 1) [um^2], 0 at and below threshold, written
+// as (pi r_e^2 / 2) / s [ (3 - b^4) L - 2 b (2 - b^2) ] with b^2 = (s-1)/s and
+// L = 2 log1p(b) + ln s (Eq. 1 with 1 - beta^2 = 1/s, free of its cancellations).
+__device__ __forceinline__ double bw_sigma(double s) {
+    if (!(s > 1.0)) return 0.0;
+    const double k_sig = (0.5 * M_PI) * (kRe * kRe);
+    const double b2 = (s - 1.0) / s;
+    const double b = sqrt(b2);
+    const double L = 2.0 * log1p(b) + log(s);
+    const double br = (3.0 - b2 * b2) * L - (2.0 * b) * (2.0 - b2);
+    return (k_sig / s) * br;
+}
 
 // One hierarchy node, 32 bytes, two per 64-byte half-line.
 // Internal nodes occupy ids [0, n-1), leaves [n-1, 2n-1) in Morton order.
@@ -69,6 +83,7 @@ struct DevCounters {
     unsigned long long cand_total;
     unsigned long long sigma_evals;
     unsigned long long fp64_rechecks;  // candidates the FP32 stage left to FP64
+    unsigned long long st_pairs;       // statistical regime: cloud pair-steps with a yield
     unsigned long long builds;
     unsigned long long collides;
     unsigned int err;
@@ -146,7 +161,14 @@ void launch_beam_stats(const BeamDev &b, StatsPartial *partials, InstStats *stat
 // Swept boxes of all virtual elements of b plus their sort keys and values (the
 // virtual element index). Morton quantisation bounds come from self_stats; query
 // padding and the threshold prune from t_stats (target instance statistics).
-void launch_boxes_keys(const BeamDev &b, bool query, double dt, double sigma_up,
+// Box kind for launch_boxes_keys: the swept segment of a step (on = 0), or the cloud of
+// the statistical regime (on = 1): a box of half-widths h about the position at mid-step.
+struct CloudBox {
+    int on;
+    double h[3];
+};
+
+void launch_boxes_keys(const BeamDev &b, bool query, const CloudBox &cloud, double dt, double sigma_up,
                        const InstStats *t_stats, const InstStats *self_stats, KeyLayout kl,
                        PBox *out, uint32_t *keys32, unsigned long long *keys64, uint32_t *vals,
                        DevCounters *c, hipStream_t st);
@@ -182,6 +204,30 @@ void launch_narrow(const BeamDev &q, const BeamDev &t, double dt, double sigma_u
                    const tril_pairs &out, DevCounters *c, bool fp32_stage, hipStream_t st);
 void launch_pair_eval32(int64_t n, const double *in, double sigma_up, double *out, hipStream_t st);
 void launch_pair_eval(int64_t n, const double *in, double *out, hipStream_t st);
+
+// Statistical regime (st.hip).
+struct StGridDev {
+    double lo[3], hi[3];
+    int32_t n_pos[3];
+    int32_t n_e;
+    double e_lo, e_hi;
+    int32_t n_th;
+    double th_max;
+    double axis[3];
+    double t_bin;
+};
+struct StCell {
+    double c[3];  // cloud box edge lengths (the grid's cell size) [um]
+};
+void launch_st_bin(const BeamDev &b, const StGridDev &g, int32_t *bins, double *sums,
+                   hipStream_t st);
+void launch_st_clear(long long *keys, double *vals, int64_t cap, double *slots, hipStream_t st);
+void launch_st_traverse(const Node *nodes, int64_t nt, const PBox *qbox, const uint32_t *qorder,
+                        int64_t nq, const int32_t *inst_root, const int32_t *inst_stop,
+                        const BeamDev &q, const BeamDev &t, const int32_t *q_bins,
+                        const int32_t *t_bins, int64_t n_t_bins, double dt, const StCell &cell,
+                        long long *keys, double *vals, int64_t cap, double *slots, DevCounters *c,
+                        hipStream_t st);
 
 // ------------------------------------------------------------------ run stats
 struct StatsScratch {

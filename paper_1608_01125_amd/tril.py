@@ -71,8 +71,21 @@ class tril_tune(ctypes.Structure):
                 ("ms_per_step", ctypes.c_double)]
 
 
+class tril_st_grid(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("n_pos", ctypes.c_int32 * 3), ("n_e", ctypes.c_int32),
+                ("e_lo", ctypes.c_double), ("e_hi", ctypes.c_double),
+                ("n_th", ctypes.c_int32), ("pad0", ctypes.c_int32), ("th_max", ctypes.c_double),
+                ("axis", ctypes.c_double * 3), ("t_bin", ctypes.c_double)]
+
+
+class tril_st_table(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_int64), ("key", ctypes.c_void_p), ("yield_", ctypes.c_void_p)]
+
+
 EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats",
-           "tril_autotune", "tril_set_tune", "tril_reset_counters", "tril_destroy", "tril_strerror", "tril_last_hip_error",
+           "tril_autotune", "tril_set_tune", "tril_st_bin", "tril_st_exact",
+           "tril_reset_counters", "tril_destroy", "tril_strerror", "tril_last_hip_error",
            "tril_dbg_sort_u32", "tril_dbg_sort_u64", "tril_dbg_morton", "tril_dbg_pair_eval",
            "tril_dbg_pair_eval32",
            "tril_dbg_tree", "tril_dbg_boxes", "tril_dbg_candidates")
@@ -98,6 +111,10 @@ def lib() -> ctypes.CDLL:
     L.tril_autotune.argtypes = [vp, ctypes.POINTER(tril_beam), ctypes.POINTER(tril_beam), i32, i32,
                                 ctypes.POINTER(tril_tune)]
     L.tril_set_tune.argtypes = [vp, ctypes.POINTER(tril_tune)]
+    L.tril_st_bin.argtypes = [ctypes.POINTER(tril_beam), ctypes.POINTER(tril_st_grid), vp, vp, vp]
+    L.tril_st_exact.argtypes = [vp, ctypes.POINTER(tril_beam), vp, i64, ctypes.POINTER(tril_beam),
+                                vp, ctypes.POINTER(ctypes.c_double), i32, i32,
+                                ctypes.POINTER(tril_st_table), ctypes.POINTER(ctypes.c_double)]
     L.tril_reset_counters.argtypes = [vp]
     L.tril_destroy.argtypes = [vp]
     L.tril_destroy.restype = None
@@ -255,6 +272,63 @@ def tril_set_tune(ctx, tune: dict) -> None:
     for k in TUNE_KEYS:
         setattr(t, k, int(tune[k]))
     _check(lib().tril_set_tune(_h(ctx), ctypes.byref(t)), "tril_set_tune")
+
+
+def st_grid(g) -> tril_st_grid:
+    """tril_st_grid from any object with the fields lo, hi, n_pos, n_e, e_lo, e_hi, n_th,
+    th_max, axis, t_bin."""
+    c = tril_st_grid()
+    for a in range(3):
+        c.lo[a] = float(g.lo[a])
+        c.hi[a] = float(g.hi[a])
+        c.n_pos[a] = int(g.n_pos[a])
+        c.axis[a] = float(g.axis[a])
+    c.n_e, c.e_lo, c.e_hi = int(g.n_e), float(g.e_lo), float(g.e_hi)
+    c.n_th, c.th_max, c.t_bin = int(g.n_th), float(g.th_max), float(g.t_bin)
+    return c
+
+
+def tril_st_bin(beam: Beam, grid, bins, sums=None, stream=None) -> None:
+    """bins: int32 device tensor (n); sums: float64 device tensor (n_bins, 5) or None."""
+    g = st_grid(grid)
+    _check(lib().tril_st_bin(ctypes.byref(beam.c), ctypes.byref(g), bins.data_ptr(),
+                             sums.data_ptr() if sums is not None else None, _stream(stream)),
+           "tril_st_bin")
+
+
+class StTable:
+    """Caller-owned bin-pair table on the device (open addressing, power-of-two slots)."""
+
+    def __init__(self, cap_log2: int, device: str = "cuda"):
+        import torch
+        self.cap = 1 << int(cap_log2)
+        self.key = torch.empty(self.cap, dtype=torch.int64, device=device)
+        self.yield_ = torch.empty(self.cap, dtype=torch.float64, device=device)
+        self._c = tril_st_table(self.cap, self.key.data_ptr(), self.yield_.data_ptr())
+
+    @property
+    def c(self) -> tril_st_table:
+        return self._c
+
+    def items(self):
+        """(keys, yields) of the occupied slots, as numpy arrays sorted by key."""
+        k = self.key.cpu().numpy()
+        y = self.yield_.cpu().numpy()
+        occ = k >= 0
+        order = np.argsort(k[occ], kind="stable")
+        return k[occ][order], y[occ][order]
+
+
+def tril_st_exact(ctx, target: Beam, t_bins, n_target_bins: int, query: Beam, q_bins, cell,
+                  k0: int, n_steps: int, table: StTable) -> float:
+    c3 = (ctypes.c_double * 3)(*[float(v) for v in cell])
+    tot = ctypes.c_double(0.0)
+    _check(lib().tril_st_exact(_h(ctx), ctypes.byref(target.c),
+                               t_bins.data_ptr() if target.n > 0 else None, int(n_target_bins),
+                               ctypes.byref(query.c), q_bins.data_ptr() if query.n > 0 else None,
+                               c3, int(k0), int(n_steps), ctypes.byref(table.c),
+                               ctypes.byref(tot)), "tril_st_exact")
+    return tot.value
 
 
 def tril_stats(ctx, pairs: Optional[Pairs], n_bins: int = 0, n_step_counts: int = 0) -> dict:

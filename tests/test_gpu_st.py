@@ -1,0 +1,128 @@
+"""Statistical (cloud) regime on the GPU against the oracle: binning, and bin-pair
+yields through the hierarchy."""
+import numpy as np
+import pytest
+
+from oracle import st_oracle as SO
+from paper_1608_01125_amd import beams
+from paper_1608_01125_amd import tril as T
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    return _t
+
+
+def _gpu_bins(torch, beam_np, grid, offs=None):
+    b = T.Beam(beam_np, offs)
+    bins = torch.empty(max(b.n, 1), dtype=torch.int32, device="cuda")
+    sums = torch.zeros((grid.n_bins, 5), dtype=torch.float64, device="cuda")
+    T.tril_st_bin(b, grid, bins, sums)
+    torch.cuda.synchronize()
+    return b, bins, sums
+
+
+def test_binning_matches_oracle(torch):
+    wl = beams.st_headon(200_000)
+    A, B = beams.draw_pair(wl)
+    for which, beam in (("a", A), ("b", B)):
+        g = beams.st_grid(wl, which, beam)
+        assert SO.bin_margin(beam, g).min() > 1e-9
+        ref, sums_ref = SO.bin_beam(beam, g)
+        _, bins, sums = _gpu_bins(torch, beam, g)
+        assert np.array_equal(bins.cpu().numpy(), ref)
+        s = sums.cpu().numpy()
+        occ = np.array(sorted(sums_ref))
+        assert np.count_nonzero(s[:, 0]) == len(occ)
+        np.testing.assert_allclose(s[occ], np.stack([sums_ref[k] for k in occ]), rtol=1e-12, atol=0)
+
+
+def _exact(torch, A, B, wl, k0, n_steps, offA=None, offB=None, cap_log2=20, grids=None, **kw):
+    ga, gb = grids if grids else (beams.st_grid(wl, "a", A), beams.st_grid(wl, "b", B))
+    qa, qbins, _ = _gpu_bins(torch, A, ga, offA)
+    tb, tbins, _ = _gpu_bins(torch, B, gb, offB)
+    ctx = T.Context(wl.dt, None, **kw)
+    tab = T.StTable(cap_log2)
+    try:
+        tot = T.tril_st_exact(ctx, tb, tbins, gb.n_bins, qa, qbins, ga.cell, k0, n_steps, tab)
+        st = ctx.stats(None)
+    finally:
+        ctx.close()
+    keys, ys = tab.items()
+    return keys, ys, tot, st, ga, gb
+
+
+def _oracle_table(A, B, wl, k0, n_steps, offA=None, offB=None):
+    ga, gb = beams.st_grid(wl, "a", A), beams.st_grid(wl, "b", B)
+    ba, _ = SO.bin_beam(A, ga)
+    bb, _ = SO.bin_beam(B, gb)
+    if offA is None:
+        return SO.st_table(A, ba, B, bb, gb.n_bins, wl.dt, k0, n_steps, ga.cell)
+    tab, tot = {}, 0.0
+    for m in range(len(offA) - 1):
+        Am = {k: v[offA[m]:offA[m + 1]] for k, v in A.items()}
+        Bm = {k: v[offB[m]:offB[m + 1]] for k, v in B.items()}
+        if len(Am["E"]) == 0 or len(Bm["E"]) == 0:
+            continue
+        t, s = SO.st_table(Am, ba[offA[m]:offA[m + 1]], Bm, bb[offB[m]:offB[m + 1]], gb.n_bins,
+                           wl.dt, k0, n_steps, ga.cell)
+        for k, v in t.items():
+            tab[k] = tab.get(k, 0.0) + v
+        tot += s
+    return tab, tot
+
+
+def _assert_tables(keys, ys, tot, ref, ref_tot, rel=1e-9):
+    rk = np.array(sorted(ref), dtype=np.int64)
+    assert np.array_equal(keys, rk)
+    np.testing.assert_allclose(ys, np.array([ref[k] for k in rk]), rtol=rel, atol=0)
+    assert abs(tot - ref_tot) <= rel * abs(ref_tot)
+
+
+@pytest.mark.parametrize("step_batch", [0, 1, 7])
+def test_st_exact_matches_oracle(torch, step_batch):
+    """2000 macro-particles per beam (1e9 physical photons each), the 100 steps around
+    the crossing."""
+    wl = beams.st_headon(2000)
+    A, B = beams.draw_pair(wl)
+    ref, ref_tot = _oracle_table(A, B, wl, 150, 100)
+    keys, ys, tot, st, _, _ = _exact(torch, A, B, wl, 150, 100, step_batch=step_batch)
+    assert len(ref) > 200 and ref_tot > 0
+    _assert_tables(keys, ys, tot, ref, ref_tot)
+    assert st["n_candidates"] > 0
+
+
+def test_st_exact_instances(torch):
+    parts_a, parts_b = [], []
+    for m, (na, nb) in enumerate([(800, 600), (0, 300), (500, 1), (700, 900)]):
+        wl = beams.st_headon(1000, seed=m)
+        A, B = beams.draw_pair(wl)
+        parts_a.append(beams.head(A, na))
+        parts_b.append(beams.head(B, nb))
+    A, offA = beams.concat(parts_a)
+    B, offB = beams.concat(parts_b)
+    wl = beams.st_headon(1000)
+    ref, ref_tot = _oracle_table(A, B, wl, 170, 60, offA, offB)
+    keys, ys, tot, _, _, _ = _exact(torch, A, B, wl, 170, 60, offA, offB)
+    assert len(ref) > 50
+    _assert_tables(keys, ys, tot, ref, ref_tot)
+
+
+def test_st_table_overflow_reported(torch):
+    wl = beams.st_headon(2000)
+    A, B = beams.draw_pair(wl)
+    with pytest.raises(T.TrilError) as e:
+        _exact(torch, A, B, wl, 150, 100, cap_log2=4)
+    assert e.value.code == T.TRIL_E_OVERFLOW
+
+
+def test_st_empty_beams(torch):
+    wl = beams.st_headon(500)
+    A, B = beams.draw_pair(wl)
+    grids = (beams.st_grid(wl, "a", A), beams.st_grid(wl, "b", B))
+    keys, ys, tot, _, _, _ = _exact(torch, beams.head(A, 0), B, wl, 0, 50, grids=grids)
+    assert len(keys) == 0 and tot == 0.0
