@@ -270,6 +270,43 @@ int tril_st_exact(tril_ctx *ctx, const tril_beam *target, const int32_t *t_bins,
                   const double cell[3], int32_t k0, int32_t n_steps, tril_st_table *table,
                   double *total);
 
+/* ---------------------------------------------------------------------------------
+ * Surrogate of the statistical regime: an ensemble of K multilayer perceptrons
+ * 6 -> 256 -> 256 -> 256 -> 1 (SiLU) mapping the six features of a bin pair to its log
+ * yield; BF16 weights and activations on the matrix cores with FP32 accumulation, FP32
+ * master weights trained with Adam on the mean squared error. Parameters of one member,
+ * flattened FP32 (133,633): W1 [256][6], b1 [256], W2 [256][256], b2, W3 [256][256], b3,
+ * W4 [256], b4 [1]. Inputs and targets are standardised with the model's normalisation
+ * (tril_mlp_set_norm or tril_mlp_fit_norm) before the first layer; outputs are returned
+ * de-standardised. Device buffers are row-major FP32: x [n][6], y [n].
+ * ------------------------------------------------------------------------------- */
+typedef struct tril_mlp tril_mlp;
+
+/* K members (1..64) initialised from `seed` (He-uniform, member k from its own stream),
+ * working on the given HIP stream. */
+int tril_mlp_create(tril_mlp **out, int32_t n_members, uint64_t seed, void *hip_stream);
+void tril_mlp_destroy(tril_mlp *m);
+/* Member's FP32 parameters to or from host memory (n must be 133,633). */
+int tril_mlp_set_params(tril_mlp *m, int32_t member, const float *host, int64_t n);
+int tril_mlp_get_params(tril_mlp *m, int32_t member, float *host, int64_t n);
+/* Normalisation: given (host, 6 means and 6 sd > 0; target mean and sd > 0), or fitted
+ * as the column means and standard deviations of the device data x [n][6], y [n]. */
+int tril_mlp_set_norm(tril_mlp *m, const float *mu_x, const float *sd_x, float mu_y, float sd_y);
+int tril_mlp_fit_norm(tril_mlp *m, const float *x, const float *y, int64_t n);
+/* Loss (mean squared error of the standardised output over the n rows, host) and its
+ * gradient with respect to every parameter of `member` (host, 133,633), no update. */
+int tril_mlp_grad(tril_mlp *m, int32_t member, const float *x, const float *y, int64_t n,
+                  float *host_grad, double *host_loss);
+/* Train every member for n_steps Adam steps (beta 0.9, 0.999, eps 1e-8, learning rate
+ * lr) on minibatches of `batch` rows drawn with replacement by a counter-based hash of
+ * (seed, member, step, row). host_loss: NULL or K values, the mean loss of the last tenth
+ * of the steps. Synchronous. */
+int tril_mlp_train(tril_mlp *m, const float *x, const float *y, int64_t n, int32_t n_steps,
+                   int32_t batch, float lr, uint64_t seed, double *host_loss);
+/* Ensemble mean and sample standard deviation over the members of the de-standardised
+ * output, per row (device, n each). Synchronous. */
+int tril_mlp_predict(tril_mlp *m, const float *x, int64_t n, float *mean, float *sdev);
+
 /* Zero the accumulated counters and device error flags (asynchronous). */
 int tril_reset_counters(tril_ctx *ctx);
 

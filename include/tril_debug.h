@@ -46,6 +46,12 @@ int tril_dbg_pair_eval(int64_t n, const double *in, double *out, void *stream);
  * Synchronises the stream. */
 int tril_dbg_pair_eval32(int64_t n, const double *in, double *out, void *stream);
 
+/* The surrogate's matrix-core product C = A B: A(m, k) = A[m sam + k sak] and
+ * B(k, n) = B[k sbk + n sbn] as BF16 bit patterns (device), C [M][N] row-major FP32
+ * (device). Synchronises the stream. */
+int tril_dbg_gemm_bf16(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk,
+                       int64_t sbn, int32_t M, int32_t N, int32_t K, float *C, void *stream);
+
 /* Copy the last built hierarchy to host memory (synchronises the context stream).
  * nodes: host, cap_nodes x 8 words (lox loy loz link hix hiy hiz rope as float/int32);
  * *n_nodes receives 2n-1 (0 for an empty beam); roots/stops: host, n_inst each,

@@ -1021,6 +1021,178 @@ int tril_st_exact(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_
     return TRIL_OK;
 }
 
+// ------------------------------------------------------------ surrogate network
+
+struct tril_mlp {
+    MlpModel m;
+};
+
+int tril_mlp_create(tril_mlp **out, int32_t n_members, uint64_t seed, void *stream) {
+    if (!out || n_members < 1 || n_members > 64) return TRIL_E_INVAL;
+    *out = nullptr;
+    tril_mlp *p = new tril_mlp();
+    const int r = mlp_init(&p->m, n_members, seed, reinterpret_cast<hipStream_t>(stream));
+    if (r != TRIL_OK) {
+        delete p;
+        return r;
+    }
+    *out = p;
+    return TRIL_OK;
+}
+
+void tril_mlp_destroy(tril_mlp *p) {
+    if (!p) return;
+    (void)hipStreamSynchronize(p->m.st);
+    delete p;
+}
+
+int tril_mlp_set_params(tril_mlp *p, int32_t member, const float *host, int64_t n) {
+    if (!p || !host || member < 0 || member >= p->m.K || n != kMlpParams) return TRIL_E_INVAL;
+    HIPCHK(hipStreamSynchronize(p->m.st));
+    HIPCHK(hipMemcpy(p->m.w + (int64_t)member * kMlpParams, host, kMlpParams * sizeof(float),
+                     hipMemcpyHostToDevice));
+    mlp_cast(&p->m);
+    HIPCHK(hipGetLastError());
+    return TRIL_OK;
+}
+
+int tril_mlp_get_params(tril_mlp *p, int32_t member, float *host, int64_t n) {
+    if (!p || !host || member < 0 || member >= p->m.K || n != kMlpParams) return TRIL_E_INVAL;
+    HIPCHK(hipStreamSynchronize(p->m.st));
+    HIPCHK(hipMemcpy(host, p->m.w + (int64_t)member * kMlpParams, kMlpParams * sizeof(float),
+                     hipMemcpyDeviceToHost));
+    return TRIL_OK;
+}
+
+int tril_mlp_set_norm(tril_mlp *p, const float *mu_x, const float *sd_x, float mu_y, float sd_y) {
+    if (!p || !mu_x || !sd_x || !std::isfinite(mu_y) || !(sd_y > 0.0f) || !std::isfinite(sd_y))
+        return TRIL_E_INVAL;
+    float h[2 * kMlpIn];
+    for (int c = 0; c < kMlpIn; ++c) {
+        if (!std::isfinite(mu_x[c]) || !(sd_x[c] > 0.0f) || !std::isfinite(sd_x[c])) return TRIL_E_INVAL;
+        h[c] = mu_x[c];
+        h[kMlpIn + c] = sd_x[c];
+    }
+    HIPCHK(hipStreamSynchronize(p->m.st));
+    HIPCHK(hipMemcpy(p->m.norm, h, sizeof(h), hipMemcpyHostToDevice));
+    p->m.mu_y = mu_y;
+    p->m.sd_y = sd_y;
+    return TRIL_OK;
+}
+
+int tril_mlp_fit_norm(tril_mlp *p, const float *x, const float *y, int64_t n) {
+    if (!p || !x || !y || n < 2) return TRIL_E_INVAL;
+    double *mom = nullptr;
+    CHK(dev_alloc(&mom, 2 * (kMlpIn + 1)));
+    HIPCHK(hipMemsetAsync(mom, 0, 2 * (kMlpIn + 1) * sizeof(double), p->m.st));
+    mlp_moments(x, n, kMlpIn, mom, p->m.st);
+    mlp_moments(y, n, 1, mom + 2 * kMlpIn, p->m.st);
+    double h[2 * (kMlpIn + 1)];
+    hipError_t e = hipStreamSynchronize(p->m.st);
+    if (e == hipSuccess) e = hipMemcpy(h, mom, sizeof(h), hipMemcpyDeviceToHost);
+    dev_free(mom);
+    if (e != hipSuccess) return hip_fail(e);
+    float mu[kMlpIn], sd[kMlpIn];
+    for (int c = 0; c <= kMlpIn; ++c) {
+        const double m1 = h[2 * c] / n;
+        const double var = std::max(h[2 * c + 1] / n - m1 * m1, 0.0);
+        const double sdv = var > 1e-30 ? std::sqrt(var) : 1.0;
+        if (c < kMlpIn) {
+            mu[c] = (float)m1;
+            sd[c] = (float)sdv;
+        } else {
+            return tril_mlp_set_norm(p, mu, sd, (float)m1, (float)sdv);
+        }
+    }
+    return TRIL_OK;
+}
+
+int tril_mlp_grad(tril_mlp *p, int32_t member, const float *x, const float *y, int64_t n,
+                  float *host_grad, double *host_loss) {
+    if (!p || !x || !y || !host_grad || !host_loss || member < 0 || member >= p->m.K || n < 1 ||
+        n > INT32_MAX)
+        return TRIL_E_INVAL;
+    MlpModel &m = p->m;
+    CHK(mlp_scratch(&m, n));
+    HIPCHK(hipMemsetAsync(m.loss, 0, sizeof(float), m.st));
+    mlp_input(&m, x, nullptr, n);
+    mlp_forward(&m, member, n, m.yhat);
+    mlp_loss(&m, y, nullptr, n);
+    mlp_backward(&m, member, n);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(m.st));
+    HIPCHK(hipMemcpy(host_grad, m.g, kMlpParams * sizeof(float), hipMemcpyDeviceToHost));
+    float l = 0.f;
+    HIPCHK(hipMemcpy(&l, m.loss, sizeof(float), hipMemcpyDeviceToHost));
+    *host_loss = (double)l / (double)n;
+    return TRIL_OK;
+}
+
+int tril_mlp_train(tril_mlp *p, const float *x, const float *y, int64_t n, int32_t n_steps,
+                   int32_t batch, float lr, uint64_t seed, double *host_loss) {
+    if (!p || !x || !y || n < 1 || n > INT32_MAX || n_steps < 0 || batch < 1 || !(lr > 0.0f))
+        return TRIL_E_INVAL;
+    MlpModel &m = p->m;
+    CHK(mlp_scratch(&m, batch));
+    const int32_t tail = std::max(1, n_steps / 10);
+    std::vector<double> acc((size_t)m.K, 0.0);
+    for (int k = 0; k < m.K; ++k) {
+        HIPCHK(hipMemsetAsync(m.loss, 0, sizeof(float), m.st));
+        for (int32_t s = 0; s < n_steps; ++s) {
+            mlp_batch_idx(&m, seed, k, m.adam_t + s, n, batch);
+            mlp_input(&m, x, m.idx, batch);
+            mlp_forward(&m, k, batch, m.yhat);
+            if (s == n_steps - tail) HIPCHK(hipMemsetAsync(m.loss, 0, sizeof(float), m.st));
+            mlp_loss(&m, y, m.idx, batch);
+            mlp_backward(&m, k, batch);
+            mlp_adam(&m, k, lr, m.adam_t + s + 1);
+        }
+        HIPCHK(hipGetLastError());
+        if (host_loss && n_steps > 0) {
+            float l = 0.f;
+            HIPCHK(hipStreamSynchronize(m.st));
+            HIPCHK(hipMemcpy(&l, m.loss, sizeof(float), hipMemcpyDeviceToHost));
+            acc[(size_t)k] = (double)l / ((double)tail * batch);
+        }
+    }
+    m.adam_t += n_steps;
+    HIPCHK(hipStreamSynchronize(m.st));
+    if (host_loss)
+        for (int k = 0; k < m.K; ++k) host_loss[k] = acc[(size_t)k];
+    return TRIL_OK;
+}
+
+int tril_mlp_predict(tril_mlp *p, const float *x, int64_t n, float *mean, float *sdev) {
+    if (!p || n < 0 || (n > 0 && (!x || !mean || !sdev))) return TRIL_E_INVAL;
+    if (n == 0) return TRIL_OK;
+    MlpModel &m = p->m;
+    const int64_t chunk = std::min<int64_t>(n, (int64_t)1 << 16);
+    CHK(mlp_scratch(&m, chunk));
+    float *outs = nullptr;
+    CHK(dev_alloc(&outs, (size_t)(m.K * chunk)));
+    for (int64_t a = 0; a < n; a += chunk) {
+        const int64_t c = std::min(chunk, n - a);
+        mlp_input(&m, x + a * kMlpIn, nullptr, c);
+        for (int k = 0; k < m.K; ++k) mlp_forward(&m, k, c, outs + (int64_t)k * c);
+        mlp_reduce(&m, outs, c, mean + a, sdev + a);
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(m.st);
+    dev_free(outs);
+    if (e != hipSuccess) return hip_fail(e);
+    return TRIL_OK;
+}
+
+int tril_dbg_gemm_bf16(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk,
+                       int64_t sbn, int32_t M, int32_t N, int32_t K, float *C, void *stream) {
+    if (!A || !B || !C || M < 1 || N < 1 || K < 0) return TRIL_E_INVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    mlp_gemm(A, sam, sak, B, sbk, sbn, M, N, K, 0, nullptr, nullptr, C, nullptr, nullptr, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return TRIL_OK;
+}
+
 int tril_set_tune(tril_ctx *c, const tril_tune *tu) {
     if (!c || !tu) return TRIL_E_INVAL;
     const int blk = tu->block_traverse;

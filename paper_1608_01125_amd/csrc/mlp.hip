@@ -1,0 +1,428 @@
+// Surrogate network of the statistical regime: an ensemble of K multilayer perceptrons
+// 6 -> 256 -> 256 -> 256 -> 1 (SiLU between layers) that maps the features of a bin pair
+// to its log yield. Weights are kept in FP32 (master copy, Adam moments) and used in
+// BF16; every product runs on the matrix cores (v_mfma_f32_16x16x32_bf16: BF16 operands,
+// FP32 accumulation). Training (forward, mean-squared-error loss, backward, Adam) and
+// inference run in the kernels of this file.
+//
+// Rounding points, which the CPU reference reproduces: the network input, every hidden
+// activation and every back-propagated pre-activation gradient are rounded to BF16
+// (round to nearest, ties to even) where they enter a product; bias additions, the
+// activation and its derivative, the loss and Adam are FP32.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "tril_internal.h"
+
+namespace tril {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+constexpr int kTM = 64, kTN = 64, kTK = 32, kLdsK = kTK + 8;
+
+enum : int { kEpiBias = 1, kEpiSilu = 2, kEpiDSilu = 4 };
+
+struct GemmArgs {
+    const uint16_t *A;
+    int64_t sam, sak;   // A(m, k) = A[m sam + k sak]
+    const uint16_t *B;
+    int64_t sbk, sbn;   // B(k, n) = B[k sbk + n sbn]
+    int M, N, K;
+    int epi;
+    const float *bias;  // [N]
+    const float *aux;   // [M x N] row-major: pre-activation for kEpiDSilu
+    float *out;         // [M x N] row-major FP32 (z, silu(z) or the gradient), or null
+    uint16_t *out_bf;   // [M x N] row-major BF16 copy, or null
+    float *out_pre;     // [M x N] pre-activation (with kEpiSilu), or null
+};
+
+// C = A B with a 64 x 64 tile per workgroup (four waves of 32 x 32, each 2 x 2 MFMA
+// 16 x 16 tiles), K in steps of 32 staged in LDS (A as [m][k], B as [n][k]).
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+    __shared__ __align__(16) uint16_t sA[kTM][kLdsK];
+    __shared__ __align__(16) uint16_t sB[kTN][kLdsK];
+    const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < g.K; k0 += kTK) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = tid * 8 + e;
+            const int r = idx >> 5, kk = idx & 31;
+            const int m = m0 + r, n = n0 + r, k = k0 + kk;
+            sA[r][kk] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : (uint16_t)0;
+            sB[r][kk] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : (uint16_t)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sA[wm + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const bf16x8 b =
+                    *reinterpret_cast<const bf16x8 *>(&sB[wn + j * 16 + (lane & 15)][8 * (lane >> 4)]);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+                const int col = n0 + wn + j * 16 + (lane & 15);
+                if (row >= g.M || col >= g.N) continue;
+                const int64_t o = (int64_t)row * g.N + col;
+                float v = acc[i][j][r];
+                if (g.epi & kEpiBias) v += g.bias[col];
+                if (g.epi & kEpiSilu) {
+                    if (g.out_pre) g.out_pre[o] = v;
+                    v = v * sigmoidf_(v);
+                }
+                if (g.epi & kEpiDSilu) {
+                    const float z = g.aux[o];
+                    const float sg = sigmoidf_(z);
+                    v = v * (sg * (1.0f + z * (1.0f - sg)));
+                }
+                if (g.out) g.out[o] = v;
+                if (g.out_bf) g.out_bf[o] = to_bf16(v);
+            }
+}
+
+// Network input: rows idx[i] (or i) of x [n x 6], standardised with mean/sd, BF16.
+__global__ void k_mlp_input(const float *__restrict__ x, const int32_t *__restrict__ idx, int64_t n,
+                            const float *__restrict__ mu, const float *__restrict__ sd,
+                            uint16_t *__restrict__ xb) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t r = idx ? (int64_t)idx[i] : i;
+#pragma unroll
+    for (int c = 0; c < kMlpIn; ++c) xb[i * kMlpIn + c] = to_bf16((x[r * kMlpIn + c] - mu[c]) / sd[c]);
+}
+
+// Targets of a batch, standardised; loss terms and d loss / d output (mean over n).
+__global__ void k_mlp_loss(const float *__restrict__ yhat, const float *__restrict__ y,
+                           const int32_t *__restrict__ idx, int64_t n, float mu_y, float sd_y,
+                           float *__restrict__ dy, uint16_t *__restrict__ dy_bf,
+                           float *__restrict__ loss_sum) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    float l = 0.f;
+    if (i < n) {
+        const int64_t r = idx ? (int64_t)idx[i] : i;
+        const float t = (y[r] - mu_y) / sd_y;
+        const float d = yhat[i] - t;
+        l = d * d;
+        const float g = 2.0f * d / (float)n;
+        dy[i] = g;
+        dy_bf[i] = to_bf16(g);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) l += __shfl_xor(l, off);
+    if ((threadIdx.x & 63) == 0 && l != 0.f) atomicAdd(loss_sum, l);
+}
+
+// Column sums of a [n x c] row-major FP32 matrix (bias gradients).
+__global__ void k_colsum(const float *__restrict__ a, int64_t n, int c, float *__restrict__ out) {
+    const int col = blockIdx.x;
+    float s = 0.f;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += a[i * c + col];
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[col] = red[0];
+}
+
+__global__ void k_cast_bf16(const float *__restrict__ a, int64_t n, uint16_t *__restrict__ b) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) b[i] = to_bf16(a[i]);
+}
+
+// Adam (Kingma & Ba 2015) on FP32 master weights, then their BF16 copy.
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2, uint16_t *__restrict__ wb) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    wb[i] = to_bf16(wi);
+}
+
+// Mean and spread over the ensemble of de-standardised outputs.
+__global__ void k_mlp_reduce(const float *__restrict__ out, int64_t n, int K, float mu_y, float sd_y,
+                             float *__restrict__ mean, float *__restrict__ sdev) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f, s2 = 0.f;
+    for (int k = 0; k < K; ++k) {
+        const float v = out[(int64_t)k * n + i] * sd_y + mu_y;
+        s += v;
+        s2 += v * v;
+    }
+    const float mu = s / (float)K;
+    mean[i] = mu;
+    sdev[i] = K > 1 ? sqrtf(fmaxf(s2 / (float)K - mu * mu, 0.0f) * (float)K / (float)(K - 1)) : 0.0f;
+}
+
+// Minibatch rows of member k at a training step: a counter-based hash of (seed, k,
+// step, i) reduced to [0, n) (rows drawn with replacement).
+__global__ void k_batch_idx(uint64_t seed, int k, int64_t step, int64_t n, int64_t batch,
+                            int32_t *__restrict__ idx) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= batch) return;
+    uint64_t h = seed ^ ((uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)step << 24) ^ (uint64_t)i;
+    h ^= h >> 33;
+    h *= 0xff51afd7ed558ccdull;
+    h ^= h >> 33;
+    h *= 0xc4ceb9fe1a85ec53ull;
+    h ^= h >> 33;
+    idx[i] = (int32_t)(h % (uint64_t)n);
+}
+
+// Per-column sum and sum of squares (FP64) of a [n x c] row-major matrix: out[2 col],
+// out[2 col + 1]; caller-zeroed, one workgroup per (column, slice).
+__global__ void k_moments(const float *__restrict__ a, int64_t n, int c, double *__restrict__ out) {
+    const int col = blockIdx.y;
+    double s = 0.0, s2 = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = a[i * c + col];
+        s += v;
+        s2 += v * v;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        s += __shfl_xor(s, off);
+        s2 += __shfl_xor(s2, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(out + 2 * col, s);
+        atomicAdd(out + 2 * col + 1, s2);
+    }
+}
+
+inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+void mlp_batch_idx(MlpModel *m, uint64_t seed, int k, int64_t step, int64_t n, int64_t batch) {
+    hipLaunchKernelGGL(k_batch_idx, dim3(blocks(batch, 256)), dim3(256), 0, m->st, seed, k, step, n,
+                       batch, m->idx);
+}
+
+void mlp_moments(const float *a, int64_t n, int c, double *out, hipStream_t st) {
+    if (n <= 0) return;
+    const unsigned gx = std::min<unsigned>(blocks(n, 256), 256u);
+    hipLaunchKernelGGL(k_moments, dim3(gx, (unsigned)c), dim3(256), 0, st, a, n, c, out);
+}
+
+void mlp_gemm(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk,
+              int64_t sbn, int M, int N, int K, int epi, const float *bias, const float *aux,
+              float *out, uint16_t *out_bf, float *out_pre, hipStream_t st) {
+    if (M <= 0 || N <= 0) return;
+    GemmArgs g{A, sam, sak, B, sbk, sbn, M, N, K, epi, bias, aux, out, out_bf, out_pre};
+    hipLaunchKernelGGL(k_gemm, dim3(blocks(N, kTN), blocks(M, kTM)), dim3(256), 0, st, g);
+}
+
+// ---------------------------------------------------------------------------- model
+
+namespace {
+
+// Parameter offsets of one member in its flat FP32 vector (W row-major [out][in]).
+constexpr int64_t kOffW1 = 0;
+constexpr int64_t kOffB1 = kOffW1 + (int64_t)kMlpHidden * kMlpIn;
+constexpr int64_t kOffW2 = kOffB1 + kMlpHidden;
+constexpr int64_t kOffB2 = kOffW2 + (int64_t)kMlpHidden * kMlpHidden;
+constexpr int64_t kOffW3 = kOffB2 + kMlpHidden;
+constexpr int64_t kOffB3 = kOffW3 + (int64_t)kMlpHidden * kMlpHidden;
+constexpr int64_t kOffW4 = kOffB3 + kMlpHidden;
+constexpr int64_t kOffB4 = kOffW4 + kMlpHidden;
+static_assert(kOffB4 + 1 == kMlpParams, "parameter count");
+
+}  // namespace
+
+MlpModel::~MlpModel() {
+    for (void *p : allocs) (void)hipFree(p);
+}
+
+template <typename T>
+static int mlp_alloc(MlpModel *m, T **p, size_t n) {
+    *p = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        return TRIL_E_NOMEM;
+    }
+    m->allocs.push_back(*p);
+    return TRIL_OK;
+}
+
+int mlp_init(MlpModel *m, int K, uint64_t seed, hipStream_t st) {
+    m->K = K;
+    m->st = st;
+    const size_t P = (size_t)K * kMlpParams;
+    int r;
+    if ((r = mlp_alloc(m, &m->w, P)) || (r = mlp_alloc(m, &m->wb, P)) ||
+        (r = mlp_alloc(m, &m->g, kMlpParams)) || (r = mlp_alloc(m, &m->am, P)) ||
+        (r = mlp_alloc(m, &m->av, P)) || (r = mlp_alloc(m, &m->norm, 2 * kMlpIn)))
+        return r;
+    // He-uniform weights scaled for SiLU, zero biases; member k from its own stream
+    std::vector<float> h(P, 0.0f);
+    for (int k = 0; k < K; ++k) {
+        std::mt19937_64 gen(seed * 0x9E3779B97F4A7C15ull + (uint64_t)k + 1u);
+        float *w = h.data() + (size_t)k * kMlpParams;
+        auto fill = [&](int64_t off, int fan_in, int64_t count) {
+            std::uniform_real_distribution<float> U(-1.0f, 1.0f);
+            const float a = std::sqrt(6.0f / (float)fan_in);
+            for (int64_t i = 0; i < count; ++i) w[off + i] = a * U(gen);
+        };
+        fill(kOffW1, kMlpIn, (int64_t)kMlpHidden * kMlpIn);
+        fill(kOffW2, kMlpHidden, (int64_t)kMlpHidden * kMlpHidden);
+        fill(kOffW3, kMlpHidden, (int64_t)kMlpHidden * kMlpHidden);
+        fill(kOffW4, kMlpHidden, kMlpHidden);
+        for (int64_t i = kOffW4; i < kOffB4; ++i) w[i] *= 0.1f;
+    }
+    if (hipMemcpy(m->w, h.data(), P * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return TRIL_E_HIP;
+    if (hipMemset(m->am, 0, P * sizeof(float)) != hipSuccess ||
+        hipMemset(m->av, 0, P * sizeof(float)) != hipSuccess)
+        return TRIL_E_HIP;
+    std::vector<float> nrm(2 * kMlpIn);
+    for (int c = 0; c < kMlpIn; ++c) {
+        nrm[c] = 0.0f;
+        nrm[kMlpIn + c] = 1.0f;
+    }
+    if (hipMemcpy(m->norm, nrm.data(), nrm.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return TRIL_E_HIP;
+    hipLaunchKernelGGL(k_cast_bf16, dim3(blocks((int64_t)P, 256)), dim3(256), 0, st, m->w, (int64_t)P, m->wb);
+    return hipGetLastError() == hipSuccess ? TRIL_OK : TRIL_E_HIP;
+}
+
+int mlp_scratch(MlpModel *m, int64_t rows) {
+    if (rows <= m->rows) return TRIL_OK;
+    const int64_t H = kMlpHidden;
+    int r;
+    if ((r = mlp_alloc(m, &m->xb, (size_t)(rows * kMlpIn))) ||
+        (r = mlp_alloc(m, &m->z1, (size_t)(rows * H))) || (r = mlp_alloc(m, &m->z2, (size_t)(rows * H))) ||
+        (r = mlp_alloc(m, &m->z3, (size_t)(rows * H))) || (r = mlp_alloc(m, &m->h1, (size_t)(rows * H))) ||
+        (r = mlp_alloc(m, &m->h2, (size_t)(rows * H))) || (r = mlp_alloc(m, &m->h3, (size_t)(rows * H))) ||
+        (r = mlp_alloc(m, &m->dz, (size_t)(rows * H))) || (r = mlp_alloc(m, &m->dzb, (size_t)(rows * H))) ||
+        (r = mlp_alloc(m, &m->dz2, (size_t)(rows * H))) || (r = mlp_alloc(m, &m->dz2b, (size_t)(rows * H))) ||
+        (r = mlp_alloc(m, &m->yhat, (size_t)rows)) || (r = mlp_alloc(m, &m->dy, (size_t)rows)) ||
+        (r = mlp_alloc(m, &m->dyb, (size_t)rows)) || (r = mlp_alloc(m, &m->loss, 1)) ||
+        (r = mlp_alloc(m, &m->idx, (size_t)rows)))
+        return r;
+    m->rows = rows;
+    return TRIL_OK;
+}
+
+// Forward of member k on m->xb (n rows): z/h of every layer, output in yhat_out.
+void mlp_forward(MlpModel *m, int k, int64_t n, float *yhat_out) {
+    const float *w = m->w + (int64_t)k * kMlpParams;
+    const uint16_t *wb = m->wb + (int64_t)k * kMlpParams;
+    const int H = kMlpHidden;
+    hipStream_t st = m->st;
+    // layer l: Z = X W^T + b: A = X (n x in), B(k, j) = W[j][k]
+    mlp_gemm(m->xb, kMlpIn, 1, wb + kOffW1, 1, kMlpIn, (int)n, H, kMlpIn, kEpiBias | kEpiSilu,
+             w + kOffB1, nullptr, nullptr, m->h1, m->z1, st);
+    mlp_gemm(m->h1, H, 1, wb + kOffW2, 1, H, (int)n, H, H, kEpiBias | kEpiSilu, w + kOffB2, nullptr,
+             nullptr, m->h2, m->z2, st);
+    mlp_gemm(m->h2, H, 1, wb + kOffW3, 1, H, (int)n, H, H, kEpiBias | kEpiSilu, w + kOffB3, nullptr,
+             nullptr, m->h3, m->z3, st);
+    mlp_gemm(m->h3, H, 1, wb + kOffW4, 1, 1, (int)n, 1, H, kEpiBias, w + kOffB4, nullptr, yhat_out,
+             nullptr, nullptr, st);
+}
+
+// Backward of member k for the batch in m->xb / m->dy (set by k_mlp_loss): gradient of
+// the loss into m->g (all parameters of one member).
+void mlp_backward(MlpModel *m, int k, int64_t n) {
+    const uint16_t *wb = m->wb + (int64_t)k * kMlpParams;
+    const int H = kMlpHidden;
+    hipStream_t st = m->st;
+    float *g = m->g;
+    // output layer: dW4[j] = sum_i dy_i h3[i][j]; db4 = sum_i dy_i
+    mlp_gemm(m->dyb, 0, 1, m->h3, H, 1, 1, H, (int)n, 0, nullptr, nullptr, g + kOffW4, nullptr,
+             nullptr, st);
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, m->dy, n, 1, g + kOffB4);
+    // dZ3 = (dy w4^T) * silu'(z3)
+    mlp_gemm(m->dyb, 1, 1, wb + kOffW4, 1, 1, (int)n, H, 1, kEpiDSilu, nullptr, m->z3, m->dz,
+             m->dzb, nullptr, st);
+    // layer 3: dW3 = dZ3^T H2, db3 = colsum dZ3, dZ2 = (dZ3 W3) * silu'(z2)
+    mlp_gemm(m->dzb, 1, H, m->h2, H, 1, H, H, (int)n, 0, nullptr, nullptr, g + kOffW3, nullptr,
+             nullptr, st);
+    hipLaunchKernelGGL(k_colsum, dim3(H), dim3(256), 0, st, m->dz, n, H, g + kOffB3);
+    mlp_gemm(m->dzb, H, 1, wb + kOffW3, H, 1, (int)n, H, H, kEpiDSilu, nullptr, m->z2, m->dz2,
+             m->dz2b, nullptr, st);
+    // layer 2
+    mlp_gemm(m->dz2b, 1, H, m->h1, H, 1, H, H, (int)n, 0, nullptr, nullptr, g + kOffW2, nullptr,
+             nullptr, st);
+    hipLaunchKernelGGL(k_colsum, dim3(H), dim3(256), 0, st, m->dz2, n, H, g + kOffB2);
+    mlp_gemm(m->dz2b, H, 1, wb + kOffW2, H, 1, (int)n, H, H, kEpiDSilu, nullptr, m->z1, m->dz,
+             m->dzb, nullptr, st);
+    // layer 1: dW1 = dZ1^T X, db1 = colsum dZ1
+    mlp_gemm(m->dzb, 1, H, m->xb, kMlpIn, 1, H, kMlpIn, (int)n, 0, nullptr, nullptr, g + kOffW1,
+             nullptr, nullptr, st);
+    hipLaunchKernelGGL(k_colsum, dim3(H), dim3(256), 0, st, m->dz, n, H, g + kOffB1);
+}
+
+void mlp_input(MlpModel *m, const float *x, const int32_t *idx, int64_t n) {
+    hipLaunchKernelGGL(k_mlp_input, dim3(blocks(n, 256)), dim3(256), 0, m->st, x, idx, n, m->norm,
+                       m->norm + kMlpIn, m->xb);
+}
+
+void mlp_loss(MlpModel *m, const float *y, const int32_t *idx, int64_t n) {
+    hipLaunchKernelGGL(k_mlp_loss, dim3(blocks(n, 256)), dim3(256), 0, m->st, m->yhat, y, idx, n,
+                       m->mu_y, m->sd_y, m->dy, m->dyb, m->loss);
+}
+
+void mlp_adam(MlpModel *m, int k, float lr, int64_t t) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.0f - std::pow(b1, (float)t), c2 = 1.0f - std::pow(b2, (float)t);
+    const int64_t o = (int64_t)k * kMlpParams;
+    hipLaunchKernelGGL(k_adam, dim3(blocks(kMlpParams, 256)), dim3(256), 0, m->st, m->w + o, m->g,
+                       m->am + o, m->av + o, (int64_t)kMlpParams, lr, b1, b2, eps, c1, c2, m->wb + o);
+}
+
+void mlp_reduce(MlpModel *m, const float *out, int64_t n, float *mean, float *sdev) {
+    hipLaunchKernelGGL(k_mlp_reduce, dim3(blocks(n, 256)), dim3(256), 0, m->st, out, n, m->K,
+                       m->mu_y, m->sd_y, mean, sdev);
+}
+
+void mlp_cast(MlpModel *m) {
+    const int64_t P = (int64_t)m->K * kMlpParams;
+    hipLaunchKernelGGL(k_cast_bf16, dim3(blocks(P, 256)), dim3(256), 0, m->st, m->w, P, m->wb);
+}
+
+}  // namespace tril

@@ -205,6 +205,50 @@ void launch_narrow(const BeamDev &q, const BeamDev &t, double dt, double sigma_u
 void launch_pair_eval32(int64_t n, const double *in, double sigma_up, double *out, hipStream_t st);
 void launch_pair_eval(int64_t n, const double *in, double *out, hipStream_t st);
 
+// Surrogate network (mlp.hip): 6 -> 256 -> 256 -> 256 -> 1, K members.
+constexpr int kMlpIn = 6;
+constexpr int kMlpHidden = 256;
+constexpr int64_t kMlpParams = (int64_t)kMlpHidden * kMlpIn + kMlpHidden +
+                               2 * ((int64_t)kMlpHidden * kMlpHidden + kMlpHidden) + kMlpHidden + 1;
+
+struct MlpModel {
+    int K = 0;
+    hipStream_t st = nullptr;
+    float *w = nullptr;         // FP32 master parameters, K x kMlpParams
+    uint16_t *wb = nullptr;     // BF16 copy
+    float *g = nullptr;         // gradient of one member
+    float *am = nullptr, *av = nullptr;  // Adam moments
+    float *norm = nullptr;      // input mean [6], sd [6]
+    float mu_y = 0.f, sd_y = 1.f;
+    int64_t rows = 0;           // scratch capacity (rows of a batch)
+    uint16_t *xb = nullptr;
+    float *z1 = nullptr, *z2 = nullptr, *z3 = nullptr;
+    uint16_t *h1 = nullptr, *h2 = nullptr, *h3 = nullptr;
+    float *dz = nullptr, *dz2 = nullptr;
+    uint16_t *dzb = nullptr, *dz2b = nullptr;
+    float *yhat = nullptr, *dy = nullptr;
+    uint16_t *dyb = nullptr;
+    float *loss = nullptr;
+    int32_t *idx = nullptr;
+    int64_t adam_t = 0;
+    std::vector<void *> allocs;
+    ~MlpModel();
+};
+int mlp_init(MlpModel *m, int K, uint64_t seed, hipStream_t st);
+int mlp_scratch(MlpModel *m, int64_t rows);
+void mlp_input(MlpModel *m, const float *x, const int32_t *idx, int64_t n);
+void mlp_forward(MlpModel *m, int k, int64_t n, float *yhat_out);
+void mlp_loss(MlpModel *m, const float *y, const int32_t *idx, int64_t n);
+void mlp_backward(MlpModel *m, int k, int64_t n);
+void mlp_adam(MlpModel *m, int k, float lr, int64_t t);
+void mlp_reduce(MlpModel *m, const float *out, int64_t n, float *mean, float *sdev);
+void mlp_cast(MlpModel *m);
+void mlp_batch_idx(MlpModel *m, uint64_t seed, int k, int64_t step, int64_t n, int64_t batch);
+void mlp_moments(const float *a, int64_t n, int c, double *out, hipStream_t st);
+void mlp_gemm(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk,
+              int64_t sbn, int M, int N, int K, int epi, const float *bias, const float *aux,
+              float *out, uint16_t *out_bf, float *out_pre, hipStream_t st);
+
 // Statistical regime (st.hip).
 struct StGridDev {
     double lo[3], hi[3];

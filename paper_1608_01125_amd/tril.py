@@ -85,6 +85,9 @@ class tril_st_table(ctypes.Structure):
 
 EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats",
            "tril_autotune", "tril_set_tune", "tril_st_bin", "tril_st_exact",
+           "tril_mlp_create", "tril_mlp_destroy", "tril_mlp_set_params", "tril_mlp_get_params",
+           "tril_mlp_set_norm", "tril_mlp_fit_norm", "tril_mlp_grad", "tril_mlp_train",
+           "tril_mlp_predict", "tril_dbg_gemm_bf16",
            "tril_reset_counters", "tril_destroy", "tril_strerror", "tril_last_hip_error",
            "tril_dbg_sort_u32", "tril_dbg_sort_u64", "tril_dbg_morton", "tril_dbg_pair_eval",
            "tril_dbg_pair_eval32",
@@ -115,6 +118,18 @@ def lib() -> ctypes.CDLL:
     L.tril_st_exact.argtypes = [vp, ctypes.POINTER(tril_beam), vp, i64, ctypes.POINTER(tril_beam),
                                 vp, ctypes.POINTER(ctypes.c_double), i32, i32,
                                 ctypes.POINTER(tril_st_table), ctypes.POINTER(ctypes.c_double)]
+    fp, dp = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)
+    L.tril_mlp_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_uint64, vp]
+    L.tril_mlp_destroy.argtypes = [vp]
+    L.tril_mlp_destroy.restype = None
+    L.tril_mlp_set_params.argtypes = [vp, i32, fp, i64]
+    L.tril_mlp_get_params.argtypes = [vp, i32, fp, i64]
+    L.tril_mlp_set_norm.argtypes = [vp, fp, fp, ctypes.c_float, ctypes.c_float]
+    L.tril_mlp_fit_norm.argtypes = [vp, vp, vp, i64]
+    L.tril_mlp_grad.argtypes = [vp, i32, vp, vp, i64, fp, dp]
+    L.tril_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_float, ctypes.c_uint64, dp]
+    L.tril_mlp_predict.argtypes = [vp, vp, i64, vp, vp]
+    L.tril_dbg_gemm_bf16.argtypes = [vp, i64, i64, vp, i64, i64, i32, i32, i32, vp, vp]
     L.tril_reset_counters.argtypes = [vp]
     L.tril_destroy.argtypes = [vp]
     L.tril_destroy.restype = None
@@ -329,6 +344,78 @@ def tril_st_exact(ctx, target: Beam, t_bins, n_target_bins: int, query: Beam, q_
                                c3, int(k0), int(n_steps), ctypes.byref(table.c),
                                ctypes.byref(tot)), "tril_st_exact")
     return tot.value
+
+
+MLP_PARAMS = 133_633
+
+
+class Mlp:
+    """Surrogate ensemble (tril_mlp_*): device tensors in, device tensors out."""
+
+    def __init__(self, n_members: int, seed: int = 0, stream=None):
+        self.K = int(n_members)
+        h = ctypes.c_void_p()
+        _check(lib().tril_mlp_create(ctypes.byref(h), self.K, ctypes.c_uint64(seed),
+                                     ctypes.c_void_p(_stream(stream))), "tril_mlp_create")
+        self.h = h
+
+    def close(self) -> None:
+        if self.h:
+            lib().tril_mlp_destroy(self.h)
+            self.h = None
+
+    def get_params(self, member: int) -> np.ndarray:
+        out = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(lib().tril_mlp_get_params(self.h, member, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                         MLP_PARAMS), "tril_mlp_get_params")
+        return out
+
+    def set_params(self, member: int, p: np.ndarray) -> None:
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        _check(lib().tril_mlp_set_params(self.h, member, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                         len(a)), "tril_mlp_set_params")
+
+    def set_norm(self, mu_x, sd_x, mu_y: float, sd_y: float) -> None:
+        mx = np.ascontiguousarray(mu_x, dtype=np.float32)
+        sx = np.ascontiguousarray(sd_x, dtype=np.float32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        _check(lib().tril_mlp_set_norm(self.h, mx.ctypes.data_as(fp), sx.ctypes.data_as(fp),
+                                       float(mu_y), float(sd_y)), "tril_mlp_set_norm")
+
+    def fit_norm(self, x, y) -> None:
+        _check(lib().tril_mlp_fit_norm(self.h, x.data_ptr(), y.data_ptr(), x.shape[0]),
+               "tril_mlp_fit_norm")
+
+    def grad(self, member: int, x, y):
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double(0.0)
+        _check(lib().tril_mlp_grad(self.h, member, x.data_ptr(), y.data_ptr(), x.shape[0],
+                                   g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                   ctypes.byref(loss)), "tril_mlp_grad")
+        return loss.value, g
+
+    def train(self, x, y, n_steps: int, batch: int, lr: float, seed: int = 0) -> np.ndarray:
+        losses = np.zeros(self.K, dtype=np.float64)
+        _check(lib().tril_mlp_train(self.h, x.data_ptr(), y.data_ptr(), x.shape[0], int(n_steps),
+                                    int(batch), float(lr), ctypes.c_uint64(seed),
+                                    losses.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "tril_mlp_train")
+        return losses
+
+    def predict(self, x):
+        import torch
+        n = x.shape[0]
+        mean = torch.empty(max(n, 1), dtype=torch.float32, device=x.device)
+        sdev = torch.empty(max(n, 1), dtype=torch.float32, device=x.device)
+        _check(lib().tril_mlp_predict(self.h, x.data_ptr() if n else None, n, mean.data_ptr(),
+                                      sdev.data_ptr()), "tril_mlp_predict")
+        return mean[:n], sdev[:n]
+
+
+def tril_dbg_gemm_bf16(A, sam, sak, B, sbk, sbn, M, N, K, C, stream=None) -> None:
+    """A, B: int16 device tensors holding BF16 bit patterns; C: float32 device [M, N]."""
+    _check(lib().tril_dbg_gemm_bf16(A.data_ptr(), sam, sak, B.data_ptr(), sbk, sbn, M, N, K,
+                                    C.data_ptr(), _stream(stream)), "tril_dbg_gemm_bf16")
 
 
 def tril_stats(ctx, pairs: Optional[Pairs], n_bins: int = 0, n_step_counts: int = 0) -> dict:
