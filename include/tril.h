@@ -72,6 +72,7 @@ extern "C" {
 #define TRIL_FP64_NARROW   0x4u  /* decide every candidate in FP64 (no FP32 stage) */
 
 typedef struct tril_ctx tril_ctx;
+typedef struct tril_mlp tril_mlp;
 
 /* One beam as structure-of-arrays, FP64, length n (all instances together).
  * Positions are at t = 0; photon i is at x_i + t * p_i / E_i at time t.
@@ -241,8 +242,9 @@ typedef struct {
 } tril_st_grid;
 
 /* Bin index of every photon (device bins[n], -1 for invalid photon data) and, if sums is
- * not NULL, per-bin sums (device sums[5 x number of bins], caller-zeroed, accumulated):
- * w, w E, w ux, w uy, w uz. Asynchronous on the HIP stream (NULL = default).
+ * not NULL, per-bin sums (device sums[8 x number of bins], caller-zeroed, accumulated):
+ * w, w E, w ux, w uy, w uz, w X, w Y, w Z (X the position at t_bin). Asynchronous on
+ * the HIP stream (NULL = default).
  * TRIL_E_INVAL for bad arguments or more than 2^31 - 1 bins. */
 int tril_st_bin(const tril_beam *beam, const tril_st_grid *grid, int32_t *bins, double *sums,
                 void *hip_stream);
@@ -271,6 +273,67 @@ int tril_st_exact(tril_ctx *ctx, const tril_beam *target, const int32_t *t_bins,
                   double *total);
 
 /* ---------------------------------------------------------------------------------
+ * Surrogate path of the statistical regime (uses the network declared below).
+ *
+ * Every occupied bin becomes one cloud: the bin's total weight at its weighted-mean
+ * position (at t_bin), mean direction and mean energy. Bin clouds of edge
+ * cloud_factor x cell go through the same hierarchy. A bin's mean position lies in its
+ * cell at t_bin, so when two macro-particle clouds overlap at time t their bins' mean
+ * positions differ by less than 3 cells plus 2 theta |t - t_bin| per axis (theta the
+ * largest angle between a photon's direction and its bin's mean direction): with
+ * cloud_factor above that bound every overlapping pair of an interior cell is a candidate
+ * (3.5 for 10 mrad beams over +-20 um/c of 0.5 um cells; edge cells, which also hold the
+ * photons outside the grid, have no such bound). Each candidate bin pair gets
+ * Omega_ab = sum over steps of dt V_ov. Features of a bin pair: log E_a, log E_b,
+ * log(1 - cos theta_ab), log rho_a, log rho_b, log Omega_ab (rho = total weight / cell
+ * volume, theta between the mean directions). The bin-level yield
+ * Y0 = rho_a rho_b sigma(s_ab) (1 - cos theta_ab) Omega_ab is the estimate without
+ * the network; the network predicts log((Y + eps Y0) / Y0) of the exact bin-pair yield Y,
+ * so Y = Y0 (exp(prediction) - eps). A bin pair whose ensemble standard deviation of the
+ * prediction exceeds `gate` (about its relative yield error) is computed exactly.
+ * ------------------------------------------------------------------------------- */
+typedef struct {
+    double cloud_factor;          /* bin cloud edge / cell edge, >= 1 (0 = 3.5) */
+    double eps;                   /* floor of the predicted yield ratio (0 = 1e-3) */
+    double gate;                  /* ensemble standard deviation above which a bin pair
+                                     takes the exact path (0 = 0.01) */
+} tril_st_sur_params;
+
+typedef struct {
+    double total;                 /* surrogate part + exact part */
+    double surrogate_part;        /* sum over confident bin pairs of the predicted yield */
+    double exact_part;            /* exact yield of the gated bin pairs */
+    int64_t n_bin_pairs;          /* candidate bin pairs (feature rows) */
+    int64_t n_gated;              /* bin pairs sent to the exact path */
+    double ms;                    /* event time of the whole call on the context stream */
+} tril_st_sur_result;
+
+/* Feature rows of all candidate bin pairs of the two beams' per-bin sums (as written by
+ * tril_st_bin) over steps k0 .. k0+n_steps-1: x [n][6] FP32, y0 [n] FP64, key [n]
+ * (query bin x n_target_bins + target bin), all device. *n receives the number of rows;
+ * TRIL_E_OVERFLOW when it exceeds cap. The two grids must have the same cell. Uses the
+ * context's stream and scratch and clears its device error flags. Synchronous. */
+int tril_st_features(tril_ctx *ctx, const double *q_sums, const tril_st_grid *q_grid,
+                     const double *t_sums, const tril_st_grid *t_grid, int32_t k0, int32_t n_steps,
+                     const tril_st_sur_params *params, float *x, double *y0, int64_t *key,
+                     int64_t cap, int64_t *n);
+
+/* Training targets of feature rows: target[i] = log((Y + eps y0[i]) / y0[i]) with Y the
+ * yield of key[i] in an exact table (0 if absent); y_exact (device, or NULL) receives Y.
+ * Asynchronous on the HIP stream. */
+int tril_st_targets(const int64_t *key, const double *y0, int64_t n, const tril_st_table *exact,
+                    double eps, float *target, double *y_exact, void *hip_stream);
+
+/* Surrogate path for one instance: features, ensemble prediction, gate, and an exact
+ * pass (tril_st_exact restricted to the photons of gated bins and to the gated bin
+ * pairs) for the gated bin pairs. Synchronous. */
+int tril_st_surrogate(tril_ctx *ctx, struct tril_mlp *mlp, const tril_beam *target,
+                      const int32_t *t_bins, const double *t_sums, const tril_st_grid *t_grid,
+                      const tril_beam *query, const int32_t *q_bins, const double *q_sums,
+                      const tril_st_grid *q_grid, int32_t k0, int32_t n_steps,
+                      const tril_st_sur_params *params, tril_st_sur_result *out);
+
+/* ---------------------------------------------------------------------------------
  * Surrogate of the statistical regime: an ensemble of K multilayer perceptrons
  * 6 -> 256 -> 256 -> 256 -> 1 (SiLU) mapping the six features of a bin pair to its log
  * yield; BF16 weights and activations on the matrix cores with FP32 accumulation, FP32
@@ -280,8 +343,6 @@ int tril_st_exact(tril_ctx *ctx, const tril_beam *target, const int32_t *t_bins,
  * (tril_mlp_set_norm or tril_mlp_fit_norm) before the first layer; outputs are returned
  * de-standardised. Device buffers are row-major FP32: x [n][6], y [n].
  * ------------------------------------------------------------------------------- */
-typedef struct tril_mlp tril_mlp;
-
 /* K members (1..64) initialised from `seed` (He-uniform, member k from its own stream),
  * working on the given HIP stream. */
 int tril_mlp_create(tril_mlp **out, int32_t n_members, uint64_t seed, void *hip_stream);

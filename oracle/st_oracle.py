@@ -51,8 +51,8 @@ def _cell(v: np.ndarray, n: int) -> np.ndarray:
 
 
 def bin_beam(beam: Dict[str, np.ndarray], g: Grid) -> Tuple[np.ndarray, np.ndarray]:
-    """Bin index per photon and per-bin sums (w, w E, w ux, w uy, w uz) as a dict
-    {bin: 5-vector} over occupied bins."""
+    """Bin index per photon and per-bin sums (w, w E, w ux, w uy, w uz, w X, w Y, w Z
+    with X the position at t_bin) as a dict {bin: 8-vector} over occupied bins."""
     E = beam["E"]
     u = np.stack([beam["px"] / E, beam["py"] / E, beam["pz"] / E], axis=1)
     X = np.stack([beam["x"], beam["y"], beam["z"]], axis=1) + g.t_bin * u
@@ -64,9 +64,10 @@ def bin_beam(beam: Dict[str, np.ndarray], g: Grid) -> Tuple[np.ndarray, np.ndarr
     ith = _cell((np.arccos(cth) / g.th_max) * g.n_th, g.n_th)
     b = (((ip[0] * g.n_pos[1] + ip[1]) * g.n_pos[2] + ip[2]) * g.n_e + ie) * g.n_th + ith
     w = beam["w"]
-    vals = np.stack([w, w * E, w * u[:, 0], w * u[:, 1], w * u[:, 2]], axis=1)
+    vals = np.stack([w, w * E, w * u[:, 0], w * u[:, 1], w * u[:, 2],
+                     w * X[:, 0], w * X[:, 1], w * X[:, 2]], axis=1)
     occ, inv = np.unique(b, return_inverse=True)
-    sums = np.zeros((len(occ), 5))
+    sums = np.zeros((len(occ), 8))
     np.add.at(sums, inv, vals)
     return b.astype(np.int64), dict(zip(occ.tolist(), sums))
 

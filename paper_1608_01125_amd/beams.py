@@ -244,6 +244,20 @@ def st_headon(n_mp: int = 10_000_000, physical: float = 1e9, seed: int = 0) -> W
     return Workload(f"st_headon_{n_mp}", a, b, base.dt, base.n_steps, seed)
 
 
+def st_train_instance(m: int, n_mp: int, physical: float = 1e9) -> Workload:
+    """Training instance m of the statistical-regime surrogate (seed 2000 + m), drawn from
+    the batched workload's parameter ranges: crossing angle uniform in [90, 180] deg, mean
+    energy log-uniform in [0.6, 10] MeV with 10% rms; Gaussian profiles as the 1e6 head-on
+    workload; ``physical`` photons per beam on ``n_mp`` macro-particles; 400 steps."""
+    seed = 2000 + m
+    prng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 11])))
+    phi = float(prng.uniform(90.0, 180.0))
+    mu = float(10.0 ** prng.uniform(math.log10(0.6), 1.0))
+    a = BeamSpec(n_mp, "gauss", 2.0, 5.0, 20.0, 0.0, "gauss", (mu, 0.1 * mu), 0.010, physical / n_mp)
+    b = replace(a, phi_deg=phi)
+    return Workload(f"st_train_{m}", a, b, 0.1, 400, seed)
+
+
 @dataclass(frozen=True)
 class StGridSpec:
     """Binning grid of one beam in the statistical regime (field meanings as in

@@ -80,6 +80,10 @@ struct WorkBeam {
     int64_t cap = 0;
 };
 
+struct tril_mlp {
+    MlpModel m;
+};
+
 struct tril_ctx {
     hipStream_t st = nullptr;       // caller stream
     hipStream_t gst = nullptr;      // internal stream for graph replay (non-blocking)
@@ -94,6 +98,20 @@ struct tril_ctx {
     int morton_param = 0;           // Morton bits requested (0 = automatic)
     CloudBox cloud{0, {0.0, 0.0, 0.0}};  // box kind of the builds (statistical regime: clouds)
     double *st_slots = nullptr;     // statistical regime: per-wave yield sums (kCounterSlots)
+    // surrogate path scratch: bin clouds, bin-pair overlap table, features, exact fallback
+    WorkBeam sr_q, sr_t;
+    int32_t *sr_q_bin = nullptr, *sr_t_bin = nullptr;
+    int64_t sr_q_cap = 0, sr_t_cap = 0, sr_nq = 0, sr_nt = 0;
+    long long *sg_key = nullptr;
+    double *sg_val = nullptr;
+    int64_t sg_cap = 0;
+    float *sf_x = nullptr, *sf_mean = nullptr, *sf_sd = nullptr;
+    double *sf_y0 = nullptr;
+    int64_t *sf_key = nullptr;
+    int64_t sf_cap = 0;
+    long long *se_key = nullptr;
+    double *se_val = nullptr;
+    int64_t se_cap = 0;
     int morton_bits = 30;           // Morton bits of the sort keys of the current build/collide
     double sigma_up = 0.0;
     DevCounters *d_cnt = nullptr;
@@ -952,24 +970,20 @@ int tril_st_bin(const tril_beam *b, const tril_st_grid *g, int32_t *bins, double
     return TRIL_OK;
 }
 
-int tril_st_exact(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_t n_t_bins,
-                  const tril_beam *q, const int32_t *q_bins, const double cell[3], int32_t k0,
-                  int32_t n_steps, tril_st_table *tab, double *total) {
-    if (!c || !cell || !tab || !total || k0 < 0 || n_steps < 0) return TRIL_E_INVAL;
-    CHK(check_beam(t));
-    CHK(check_beam(q));
-    if ((t->n > 0 && !t_bins) || (q->n > 0 && !q_bins)) return TRIL_E_INVAL;
-    if (n_t_bins < 1 || n_t_bins > INT32_MAX) return TRIL_E_INVAL;
-    for (int a = 0; a < 3; ++a)
-        if (!std::isfinite(cell[a]) || !(cell[a] > 0.0)) return TRIL_E_INVAL;
-    if (tab->cap < 1 || (tab->cap & (tab->cap - 1)) != 0 || !tab->key || !tab->yield)
-        return TRIL_E_INVAL;
-    if (q->n_inst != t->n_inst) return TRIL_E_STATE;
-    if ((int64_t)k0 + n_steps - 1 > INT32_MAX) return TRIL_E_INVAL;
-    *total = 0.0;
+}  // extern "C"
+
+namespace {
+
+// Statistical-regime pass over steps k0 .. k0+n_steps-1 (asynchronous): clouds of edges
+// `cell` in a hierarchy per step, yields (or, geometric, overlap integrals) added to the
+// table under (q_bins[i], t_bins[j]); with a filter set, only its keys. Per-wave sums go
+// to c->st_slots (cleared here together with the table).
+int st_run(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_t n_t_bins,
+           const tril_beam *q, const int32_t *q_bins, const double cell[3], int32_t k0,
+           int32_t n_steps, int geometric, const long long *filter, int64_t filter_cap,
+           long long *keys, double *vals, int64_t cap) {
     if (!c->st_slots) CHK(dev_alloc(&c->st_slots, (size_t)kCounterSlots));
-    launch_st_clear(reinterpret_cast<long long *>(tab->key), tab->yield, tab->cap, c->st_slots,
-                    c->st);
+    launch_st_clear(keys, vals, cap, c->st_slots, c->st);
     const int32_t m = n_steps > 0 ? pick_batch(c, t, q, n_steps) : 1;
     CHK(ensure_target(c, (int64_t)m * t->n, (int64_t)m * t->n_inst, t->n_inst));
     CHK(ensure_query(c, (int64_t)m * q->n, (int64_t)m * q->n_inst, q->n_inst));
@@ -994,9 +1008,9 @@ int tril_st_exact(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_
         if ((rc = enqueue_query_prep(c, qv, c->st, true)) != TRIL_OK) break;
         const int64_t nqv = (int64_t)mb * q->n;
         launch_st_traverse(c->nodes, (int64_t)mb * t->n, c->q_box, nqv > 0 ? c->q_order : nullptr,
-                           nqv, c->inst_root, c->inst_stop, qv, c->tgt, q_bins, t_bins,
-                           n_t_bins, c->dt, sc, reinterpret_cast<long long *>(tab->key),
-                           tab->yield, tab->cap, c->st_slots, c->d_cnt, c->st);
+                           nqv, c->inst_root, c->inst_stop, qv, c->tgt, q_bins, t_bins, n_t_bins,
+                           c->dt, sc, geometric, filter, filter_cap, keys, vals, cap, c->st_slots,
+                           c->d_cnt, c->st);
         k += mb;
         left -= mb;
     }
@@ -1007,12 +1021,17 @@ int tril_st_exact(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_
     c->built_step = k0 + std::max(n_steps, 1) - 1;
     c->res_t = t1;
     c->last_q = q1;
+    return TRIL_OK;
+}
+
+// Sum of the per-wave slots and the device error flags after a pass (synchronises).
+int st_finish(tril_ctx *c, double *total) {
     HIPCHK(hipStreamSynchronize(c->st));
     double slots[kCounterSlots];
     HIPCHK(hipMemcpy(slots, c->st_slots, sizeof(slots), hipMemcpyDeviceToHost));
     double tot = 0.0;
     for (double v : slots) tot += v;
-    *total = tot;
+    if (total) *total = tot;
     unsigned int err = 0;
     HIPCHK(hipMemcpy(&err, &c->d_cnt->err, sizeof(err), hipMemcpyDeviceToHost));
     if (err & kErrData) return TRIL_E_DATA;
@@ -1021,11 +1040,296 @@ int tril_st_exact(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_
     return TRIL_OK;
 }
 
-// ------------------------------------------------------------ surrogate network
+int check_cell(const double cell[3]) {
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(cell[a]) || !(cell[a] > 0.0)) return TRIL_E_INVAL;
+    return TRIL_OK;
+}
 
-struct tril_mlp {
-    MlpModel m;
-};
+int64_t pow2_at_least(int64_t v) {
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+int64_t grid_bins(const tril_st_grid *g) {
+    return (int64_t)g->n_pos[0] * g->n_pos[1] * g->n_pos[2] * g->n_e * g->n_th;
+}
+
+void grid_cell(const tril_st_grid *g, double cell[3]) {
+    for (int a = 0; a < 3; ++a) cell[a] = (g->hi[a] - g->lo[a]) / g->n_pos[a];
+}
+
+int check_grid(const tril_st_grid *g) {
+    if (!g) return TRIL_E_INVAL;
+    for (int a = 0; a < 3; ++a)
+        if (g->n_pos[a] < 1 || !std::isfinite(g->lo[a]) || !std::isfinite(g->hi[a]) ||
+            !(g->hi[a] > g->lo[a]))
+            return TRIL_E_INVAL;
+    if (g->n_e < 1 || g->n_th < 1) return TRIL_E_INVAL;
+    const int64_t nb = grid_bins(g);
+    return (nb > 0 && nb <= INT32_MAX) ? TRIL_OK : TRIL_E_INVAL;
+}
+
+// Bin clouds of one beam from its per-bin sums: records in the scratch beam w (SoA of
+// 8 x cap doubles), their bins in rec_bin; returns the record count in *n.
+int st_records(tril_ctx *c, const double *sums, const tril_st_grid *g, WorkBeam &w,
+               int32_t *&rec_bin, int64_t &rec_cap, int64_t *n) {
+    unsigned long long *cnt = nullptr;
+    CHK(dev_alloc(&cnt, 1));
+    int rc = TRIL_OK;
+    for (int pass = 0; pass < 2; ++pass) {
+        if (hipMemsetAsync(cnt, 0, sizeof(*cnt), c->st) != hipSuccess) {
+            rc = TRIL_E_HIP;
+            break;
+        }
+        launch_st_records(sums, grid_bins(g), g->t_bin, w.soa, w.cap, rec_bin, cnt, c->st);
+        unsigned long long h = 0;
+        if (hipMemcpy(&h, cnt, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) {
+            rc = TRIL_E_HIP;
+            break;
+        }
+        *n = (int64_t)h;
+        if ((int64_t)h <= w.cap) break;
+        free_work(w);
+        dev_free(rec_bin);
+        if ((rc = dev_alloc(&w.soa, (size_t)(8 * h))) != TRIL_OK) break;
+        if ((rc = dev_alloc(&w.perm, 1)) != TRIL_OK) break;
+        if ((rc = dev_alloc(&rec_bin, (size_t)h)) != TRIL_OK) break;
+        w.cap = (int64_t)h;
+        rec_cap = (int64_t)h;
+    }
+    dev_free(cnt);
+    return rc;
+}
+
+tril_beam record_beam(const WorkBeam &w, int64_t n) {
+    tril_beam b;
+    std::memset(&b, 0, sizeof(b));
+    b.n = n;
+    b.x = w.soa; b.y = w.soa + w.cap; b.z = w.soa + 2 * w.cap;
+    b.px = w.soa + 3 * w.cap; b.py = w.soa + 4 * w.cap; b.pz = w.soa + 5 * w.cap;
+    b.E = w.soa + 6 * w.cap; b.w = w.soa + 7 * w.cap;
+    b.n_inst = 1;
+    b.inst_off = nullptr;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tril_st_exact(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_t n_t_bins,
+                  const tril_beam *q, const int32_t *q_bins, const double cell[3], int32_t k0,
+                  int32_t n_steps, tril_st_table *tab, double *total) {
+    if (!c || !cell || !tab || !total || k0 < 0 || n_steps < 0) return TRIL_E_INVAL;
+    CHK(check_beam(t));
+    CHK(check_beam(q));
+    if ((t->n > 0 && !t_bins) || (q->n > 0 && !q_bins)) return TRIL_E_INVAL;
+    if (n_t_bins < 1 || n_t_bins > INT32_MAX) return TRIL_E_INVAL;
+    CHK(check_cell(cell));
+    if (tab->cap < 1 || (tab->cap & (tab->cap - 1)) != 0 || !tab->key || !tab->yield)
+        return TRIL_E_INVAL;
+    if (q->n_inst != t->n_inst) return TRIL_E_STATE;
+    if ((int64_t)k0 + n_steps - 1 > INT32_MAX) return TRIL_E_INVAL;
+    *total = 0.0;
+    CHK(st_run(c, t, t_bins, n_t_bins, q, q_bins, cell, k0, n_steps, 0, nullptr, 0,
+               reinterpret_cast<long long *>(tab->key), tab->yield, tab->cap));
+    return st_finish(c, total);
+}
+
+int tril_st_features(tril_ctx *c, const double *q_sums, const tril_st_grid *gq,
+                     const double *t_sums, const tril_st_grid *gt, int32_t k0, int32_t n_steps,
+                     const tril_st_sur_params *p, float *x, double *y0, int64_t *key, int64_t cap,
+                     int64_t *n) {
+    if (!c || !q_sums || !t_sums || !n || cap < 0 || (cap > 0 && (!x || !y0 || !key)) || k0 < 0 ||
+        n_steps < 0)
+        return TRIL_E_INVAL;
+    CHK(check_grid(gq));
+    CHK(check_grid(gt));
+    const double factor = (p && p->cloud_factor > 0.0) ? p->cloud_factor : 3.5;
+    if (!(factor >= 1.0) || !std::isfinite(factor)) return TRIL_E_INVAL;
+    double cq[3], ct[3];
+    grid_cell(gq, cq);
+    grid_cell(gt, ct);
+    for (int a = 0; a < 3; ++a)
+        if (!(std::fabs(cq[a] - ct[a]) <= 1e-12 * cq[a])) return TRIL_E_INVAL;
+    *n = 0;
+    // bin clouds of both beams
+    CHK(st_records(c, q_sums, gq, c->sr_q, c->sr_q_bin, c->sr_q_cap, &c->sr_nq));
+    CHK(st_records(c, t_sums, gt, c->sr_t, c->sr_t_bin, c->sr_t_cap, &c->sr_nt));
+    const tril_beam bq = record_beam(c->sr_q, c->sr_nq), bt = record_beam(c->sr_t, c->sr_nt);
+    const double big[3] = {factor * cq[0], factor * cq[1], factor * cq[2]};
+    // geometric overlap of the bin clouds; the table grows until it holds every pair
+    const double vol_ratio = factor * factor * factor;
+    int64_t tcap = std::max<int64_t>(
+        c->sg_cap,
+        pow2_at_least((int64_t)(64.0 * vol_ratio) * std::max(c->sr_nq, c->sr_nt) + ((int64_t)1 << 20)));
+    for (int attempt = 0;; ++attempt) {
+        if (tcap > c->sg_cap) {
+            dev_free(c->sg_key);
+            dev_free(c->sg_val);
+            c->sg_cap = 0;
+            CHK(dev_alloc(&c->sg_key, (size_t)tcap));
+            CHK(dev_alloc(&c->sg_val, (size_t)tcap));
+            c->sg_cap = tcap;
+        }
+        HIPCHK(hipMemsetAsync(&c->d_cnt->err, 0, sizeof(unsigned int), c->st));
+        CHK(st_run(c, &bt, c->sr_t_bin, grid_bins(gt), &bq, c->sr_q_bin, big, k0, n_steps, 1,
+                   nullptr, 0, c->sg_key, c->sg_val, c->sg_cap));
+        const int r = st_finish(c, nullptr);
+        if (r == TRIL_OK) break;
+        if (r != TRIL_E_OVERFLOW || attempt >= 4) return r;
+        tcap = c->sg_cap * 4;
+    }
+    // one feature row per occupied slot
+    unsigned long long *cnt = nullptr;
+    CHK(dev_alloc(&cnt, 1));
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(*cnt), c->st);
+    const double vol = (cq[0] * cq[1]) * cq[2];
+    launch_st_features(c->sg_key, c->sg_val, c->sg_cap, grid_bins(gt), q_sums, t_sums, vol, x, y0,
+                       reinterpret_cast<long long *>(key), cap, cnt, c->st);
+    unsigned long long h = 0;
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(&h, cnt, sizeof(h), hipMemcpyDeviceToHost);
+    dev_free(cnt);
+    if (e != hipSuccess) return hip_fail(e);
+    *n = (int64_t)h;
+    return (int64_t)h > cap ? TRIL_E_OVERFLOW : TRIL_OK;
+}
+
+int tril_st_targets(const int64_t *key, const double *y0, int64_t n, const tril_st_table *exact,
+                    double eps, float *target, double *y_exact, void *stream) {
+    if (n < 0 || !exact || !(eps > 0.0) || (n > 0 && (!key || !y0 || !target))) return TRIL_E_INVAL;
+    if (exact->cap < 1 || (exact->cap & (exact->cap - 1)) != 0 || !exact->key || !exact->yield)
+        return TRIL_E_INVAL;
+    launch_st_targets(reinterpret_cast<const long long *>(key), y0, n,
+                      reinterpret_cast<const long long *>(exact->key), exact->yield, exact->cap, eps,
+                      target, y_exact, reinterpret_cast<hipStream_t>(stream));
+    HIPCHK(hipGetLastError());
+    return TRIL_OK;
+}
+
+int tril_st_surrogate(tril_ctx *c, tril_mlp *mlp, const tril_beam *t, const int32_t *t_bins,
+                      const double *t_sums, const tril_st_grid *gt, const tril_beam *q,
+                      const int32_t *q_bins, const double *q_sums, const tril_st_grid *gq,
+                      int32_t k0, int32_t n_steps, const tril_st_sur_params *p,
+                      tril_st_sur_result *out) {
+    if (!c || !mlp || !out) return TRIL_E_INVAL;
+    CHK(check_beam(t));
+    CHK(check_beam(q));
+    if ((t->n > 0 && !t_bins) || (q->n > 0 && !q_bins)) return TRIL_E_INVAL;
+    if (q->n_inst != 1 || t->n_inst != 1) return TRIL_E_NOTIMPL;
+    const double eps = (p && p->eps > 0.0) ? p->eps : 1e-3;
+    const double gate = (p && p->gate > 0.0) ? p->gate : 0.01;
+    std::memset(out, 0, sizeof(*out));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, c->st));
+    // features of every candidate bin pair
+    int64_t cap = std::max<int64_t>(c->sf_cap, 1 << 16), nrow = 0;
+    for (int attempt = 0;; ++attempt) {
+        if (cap > c->sf_cap) {
+            dev_free(c->sf_x); dev_free(c->sf_y0); dev_free(c->sf_key);
+            dev_free(c->sf_mean); dev_free(c->sf_sd);
+            c->sf_cap = 0;
+            CHK(dev_alloc(&c->sf_x, (size_t)(kMlpIn * cap)));
+            CHK(dev_alloc(&c->sf_y0, (size_t)cap));
+            CHK(dev_alloc(&c->sf_key, (size_t)cap));
+            CHK(dev_alloc(&c->sf_mean, (size_t)cap));
+            CHK(dev_alloc(&c->sf_sd, (size_t)cap));
+            c->sf_cap = cap;
+        }
+        const int r = tril_st_features(c, q_sums, gq, t_sums, gt, k0, n_steps, p, c->sf_x, c->sf_y0,
+                                       c->sf_key, c->sf_cap, &nrow);
+        if (r == TRIL_OK) break;
+        if (r != TRIL_E_OVERFLOW || attempt >= 2) return r;
+        cap = pow2_at_least(nrow + 1);
+    }
+    out->n_bin_pairs = nrow;
+    // ensemble prediction on the same stream
+    if (mlp->m.st != c->st) HIPCHK(hipStreamSynchronize(c->st));
+    CHK(tril_mlp_predict(mlp, c->sf_x, nrow, c->sf_mean, c->sf_sd));
+    // gate: surrogate yields for confident rows; the rest to an exact pass
+    const int64_t nbq = grid_bins(gq), nbt = grid_bins(gt);
+    const int64_t fcap = pow2_at_least(2 * nrow + 16);
+    long long *filter = nullptr;
+    uint8_t *qmark = nullptr, *tmark = nullptr;
+    int32_t *qb2 = nullptr, *tb2 = nullptr;
+    unsigned long long *nflag = nullptr;
+    int rc = TRIL_OK;
+    auto cleanup = [&]() {
+        dev_free(filter); dev_free(qmark); dev_free(tmark); dev_free(qb2); dev_free(tb2);
+        dev_free(nflag);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    };
+    if ((rc = dev_alloc(&filter, (size_t)fcap)) || (rc = dev_alloc(&qmark, (size_t)nbq)) ||
+        (rc = dev_alloc(&tmark, (size_t)nbt)) || (rc = dev_alloc(&qb2, (size_t)std::max<int64_t>(q->n, 1))) ||
+        (rc = dev_alloc(&tb2, (size_t)std::max<int64_t>(t->n, 1))) || (rc = dev_alloc(&nflag, 1))) {
+        cleanup();
+        return rc;
+    }
+    launch_fill_keys(filter, fcap, c->st);
+    hipError_t he = hipMemsetAsync(qmark, 0, (size_t)nbq, c->st);
+    if (he == hipSuccess) he = hipMemsetAsync(tmark, 0, (size_t)nbt, c->st);
+    if (he == hipSuccess) he = hipMemsetAsync(nflag, 0, sizeof(*nflag), c->st);
+    if (he == hipSuccess) he = hipMemsetAsync(c->st_slots, 0, kCounterSlots * sizeof(double), c->st);
+    if (he != hipSuccess) {
+        cleanup();
+        return hip_fail(he);
+    }
+    launch_st_gate(reinterpret_cast<const long long *>(c->sf_key), c->sf_y0, c->sf_mean, c->sf_sd,
+                   nrow, eps, gate, nbt, filter, fcap, qmark, tmark, c->st_slots, nflag,
+                   &c->d_cnt->err, c->st);
+    double sur = 0.0;
+    if ((rc = st_finish(c, &sur)) != TRIL_OK) {
+        cleanup();
+        return rc;
+    }
+    unsigned long long hf = 0;
+    if ((he = hipMemcpy(&hf, nflag, sizeof(hf), hipMemcpyDeviceToHost)) != hipSuccess) {
+        cleanup();
+        return hip_fail(he);
+    }
+    out->surrogate_part = sur;
+    out->n_gated = (int64_t)hf;
+    double exact = 0.0;
+    if (hf > 0) {
+        launch_st_mask_bins(q_bins, q->n, qmark, qb2, c->st);
+        launch_st_mask_bins(t_bins, t->n, tmark, tb2, c->st);
+        double cell[3];
+        grid_cell(gq, cell);
+        const int64_t ecap = pow2_at_least(4 * (int64_t)hf + 1024);
+        if (ecap > c->se_cap) {
+            dev_free(c->se_key);
+            dev_free(c->se_val);
+            c->se_cap = 0;
+            if ((rc = dev_alloc(&c->se_key, (size_t)ecap)) || (rc = dev_alloc(&c->se_val, (size_t)ecap))) {
+                cleanup();
+                return rc;
+            }
+            c->se_cap = ecap;
+        }
+        if ((rc = st_run(c, t, tb2, nbt, q, qb2, cell, k0, n_steps, 0, filter, fcap, c->se_key,
+                         c->se_val, c->se_cap)) != TRIL_OK ||
+            (rc = st_finish(c, &exact)) != TRIL_OK) {
+            cleanup();
+            return rc;
+        }
+    }
+    out->exact_part = exact;
+    out->total = sur + exact;
+    float ms = 0.f;
+    if (hipEventRecord(e1, c->st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+        hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+        out->ms = ms;
+    cleanup();
+    return TRIL_OK;
+}
+
+// ------------------------------------------------------------ surrogate network
 
 int tril_mlp_create(tril_mlp **out, int32_t n_members, uint64_t seed, void *stream) {
     if (!out || n_members < 1 || n_members > 64) return TRIL_E_INVAL;
@@ -1319,6 +1623,11 @@ void tril_destroy(tril_ctx *c) {
         free_work(c->wq[p]);
     }
     dev_free(c->st_slots);
+    free_work(c->sr_q); free_work(c->sr_t);
+    dev_free(c->sr_q_bin); dev_free(c->sr_t_bin);
+    dev_free(c->sg_key); dev_free(c->sg_val);
+    dev_free(c->sf_x); dev_free(c->sf_mean); dev_free(c->sf_sd); dev_free(c->sf_y0);
+    dev_free(c->sf_key); dev_free(c->se_key); dev_free(c->se_val);
     dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->inst_root); dev_free(c->inst_stop);
     dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
     dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);

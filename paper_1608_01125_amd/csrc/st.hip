@@ -67,12 +67,15 @@ __global__ void __launch_bounds__(256) k_st_bin(BeamDev b, StGridDev g, int32_t 
         ((((int64_t)ip[0] * g.n_pos[1] + ip[1]) * g.n_pos[2] + ip[2]) * g.n_e + ie) * g.n_th + ith;
     bins[i] = (int32_t)bin;
     if (sums) {
-        double *s = sums + 5 * bin;
+        double *s = sums + kStSums * bin;
         atomicAdd(s + 0, w);
         atomicAdd(s + 1, w * E);
         atomicAdd(s + 2, w * ux);
         atomicAdd(s + 3, w * uy);
         atomicAdd(s + 4, w * uz);
+        atomicAdd(s + 5, w * X[0]);
+        atomicAdd(s + 6, w * X[1]);
+        atomicAdd(s + 7, w * X[2]);
     }
 }
 
@@ -95,10 +98,14 @@ __device__ __forceinline__ uint64_t mix64(uint64_t k) {
     return k;
 }
 
+// Linear probing gives up (and flags a full table) after this many slots: a table that
+// holds its keys at moderate load never gets near it.
+constexpr uint64_t kMaxProbe = 1024;
+
 __device__ void table_add(long long *keys, double *vals, uint64_t mask, long long key, double v,
                           unsigned int *err) {
     uint64_t h = mix64((uint64_t)key) & mask;
-    for (uint64_t probe = 0; probe <= mask; ++probe) {
+    for (uint64_t probe = 0; probe <= mask && probe < kMaxProbe; ++probe) {
         const long long cur = __hip_atomic_load(keys + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cur == key) {
             atomicAdd(vals + h, v);
@@ -117,9 +124,21 @@ __device__ void table_add(long long *keys, double *vals, uint64_t mask, long lon
     atomicOr(err, kErrTableFull);
 }
 
-// Y_ij,k of one cloud pair (see the file comment), FP64.
+__device__ __forceinline__ bool set_has(const long long *keys, uint64_t mask, long long key) {
+    uint64_t h = mix64((uint64_t)key) & mask;
+    for (uint64_t probe = 0; probe <= mask && probe < kMaxProbe; ++probe) {
+        const long long cur = keys[h];
+        if (cur == key) return true;
+        if (cur == -1ll) return false;
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
+// Y_ij,k of one cloud pair (see the file comment), FP64 (geometric = 1: dt V_ov only, the
+// clouds' overlap integrated over the step; pairs at or below threshold still give nothing).
 __device__ __forceinline__ double st_yield(const BeamDev &q, int64_t i, const BeamDev &t, int64_t j,
-                                           double tk, double dt, const StCell &cell) {
+                                           double tk, double dt, const StCell &cell, int geometric) {
     const double Ei = q.E[i], Ej = t.E[j];
     const double uix = q.px[i] / Ei, uiy = q.py[i] / Ei, uiz = q.pz[i] / Ei;
     const double ujx = t.px[j] / Ej, ujy = t.py[j] / Ej, ujz = t.pz[j] / Ej;
@@ -132,6 +151,7 @@ __device__ __forceinline__ double st_yield(const BeamDev &q, int64_t i, const Be
     const double oz = cell.c[2] - fabs((q.z[i] + tm * uiz) - (t.z[j] + tm * ujz));
     if (!(ox > 0.0 && oy > 0.0 && oz > 0.0)) return 0.0;
     const double vov = (ox * oy) * oz;
+    if (geometric) return dt * vov;
     const double V = (cell.c[0] * cell.c[1]) * cell.c[2];
     return (((((q.w[i] * t.w[j]) / (V * V)) * bw_sigma(s)) * (1.0 - cphi)) * dt) * vov;
 }
@@ -141,8 +161,9 @@ __global__ void __launch_bounds__(BLOCK) k_st_traverse(
     const Node *__restrict__ nodes, int32_t n_int, const PBox *__restrict__ qbox,
     const uint32_t *__restrict__ qorder, int64_t nq, const int32_t *__restrict__ inst_root,
     const int32_t *__restrict__ inst_stop, BeamDev q, BeamDev t, const int32_t *__restrict__ q_bins,
-    const int32_t *__restrict__ t_bins, int64_t n_t_bins, double dt, StCell cell, long long *keys,
-    double *vals, uint64_t mask, double *__restrict__ slots, DevCounters *c) {
+    const int32_t *__restrict__ t_bins, int64_t n_t_bins, double dt, StCell cell, int geometric,
+    const long long *__restrict__ filter, uint64_t fmask, long long *keys, double *vals,
+    uint64_t mask, double *__restrict__ slots, DevCounters *c) {
     const int64_t e = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
     int32_t node = -1, stop = -1, qi = 0;
     float lx = 0.f, ly = 0.f, lz = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
@@ -181,11 +202,12 @@ __global__ void __launch_bounds__(BLOCK) k_st_traverse(
         if (ov && leaf) {
             const int64_t j = (int64_t)__float_as_int(a.w) - so * t.n;
             const int32_t bt = t_bins[j];
-            const double Y = bt >= 0 ? st_yield(q, i, t, j, tk, dt, cell) : 0.0;
+            const long long key = (long long)bq * n_t_bins + bt;
+            const bool keep = bt >= 0 && (filter == nullptr || set_has(filter, fmask, key));
+            const double Y = keep ? st_yield(q, i, t, j, tk, dt, cell, geometric) : 0.0;
             if (Y > 0.0) {
                 ++n_pairs;
                 lane_total += Y;
-                const long long key = (long long)bq * n_t_bins + bt;
                 if (key != cur_key) {
                     if (cur_key >= 0) table_add(keys, vals, mask, cur_key, acc, &c->err);
                     cur_key = key;
@@ -215,9 +237,196 @@ __global__ void __launch_bounds__(BLOCK) k_st_traverse(
     }
 }
 
+// One cloud per occupied bin: weighted-mean energy, direction and position (at the grid
+// time, carried back to t = 0 along the mean direction), weight = the bin's total.
+// Appended in arbitrary order; rec_bin[r] is the bin of record r.
+__global__ void k_st_records(const double *__restrict__ sums, int64_t n_bins, double t_bin,
+                             double *__restrict__ soa, int64_t cap, int32_t *__restrict__ rec_bin,
+                             unsigned long long *__restrict__ count) {
+    const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (b >= n_bins) return;
+    const double *s = sums + kStSums * b;
+    const double w = s[0];
+    if (!(w > 0.0)) return;
+    const unsigned long long r = atomicAdd(count, 1ull);
+    if ((int64_t)r >= cap) return;
+    const double E = s[1] / w;
+    const double u[3] = {s[2] / w, s[3] / w, s[4] / w};
+    const double X[3] = {s[5] / w, s[6] / w, s[7] / w};
+    for (int a = 0; a < 3; ++a) {
+        soa[a * cap + r] = X[a] - t_bin * u[a];
+        soa[(3 + a) * cap + r] = E * u[a];
+    }
+    soa[6 * cap + r] = E;
+    soa[7 * cap + r] = w;
+    rec_bin[r] = (int32_t)b;
+}
+
+// Features of every occupied table slot (bin pair a, b with overlap integral Omega):
+// log E_a, log E_b, log(1 - cos theta_ab) (theta between the mean directions), log rho_a,
+// log rho_b, log Omega (rho = bin total / cell volume); and the bin-level yield
+// Y0 = rho_a rho_b sigma(s_ab) (1 - cos theta_ab) Omega.
+__global__ void k_st_features(const long long *__restrict__ keys, const double *__restrict__ vals,
+                              int64_t cap, int64_t n_t_bins, const double *__restrict__ q_sums,
+                              const double *__restrict__ t_sums, double vol, float *__restrict__ x,
+                              double *__restrict__ y0, long long *__restrict__ key_out,
+                              int64_t out_cap, unsigned long long *__restrict__ count) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= cap) return;
+    const long long key = keys[k];
+    if (key < 0) return;
+    const double om = vals[k];
+    if (!(om > 0.0)) return;
+    const int64_t a = key / n_t_bins, b = key - a * n_t_bins;
+    const double *sa = q_sums + kStSums * a, *sb = t_sums + kStSums * b;
+    const double Ea = sa[1] / sa[0], Eb = sb[1] / sb[0];
+    const double ua[3] = {sa[2], sa[3], sa[4]}, ub[3] = {sb[2], sb[3], sb[4]};
+    const double na = sqrt((ua[0] * ua[0] + ua[1] * ua[1]) + ua[2] * ua[2]);
+    const double nb = sqrt((ub[0] * ub[0] + ub[1] * ub[1]) + ub[2] * ub[2]);
+    const double cth = ((ua[0] * ub[0] + ua[1] * ub[1]) + ua[2] * ub[2]) / (na * nb);
+    const double qf = fmax(1.0 - cth, 1e-300);
+    const double s = ((Ea * Eb) * qf) / (2.0 * kMe * kMe);
+    const double ra = sa[0] / vol, rb = sb[0] / vol;
+    const unsigned long long r = atomicAdd(count, 1ull);
+    if ((int64_t)r >= out_cap) return;
+    float *f = x + kMlpIn * r;
+    f[0] = (float)log(Ea);
+    f[1] = (float)log(Eb);
+    f[2] = (float)log(qf);
+    f[3] = (float)log(ra);
+    f[4] = (float)log(rb);
+    f[5] = (float)log(om);
+    y0[r] = ((ra * rb) * bw_sigma(s)) * qf * om;
+    key_out[r] = key;
+}
+
+// Training targets log((Y + eps Y0) / Y0), Y the exact yield of the row's bin pair (0 when
+// the pair is absent from the exact table).
+__global__ void k_st_targets(const long long *__restrict__ key, const double *__restrict__ y0,
+                             int64_t n, const long long *__restrict__ tkeys,
+                             const double *__restrict__ tvals, uint64_t tmask, double eps,
+                             float *__restrict__ target, double *__restrict__ y_exact) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double Y = 0.0;
+    uint64_t h = mix64((uint64_t)key[i]) & tmask;
+    for (uint64_t probe = 0; probe <= tmask && probe < kMaxProbe; ++probe) {
+        const long long cur = tkeys[h];
+        if (cur == key[i]) {
+            Y = tvals[h];
+            break;
+        }
+        if (cur == -1ll) break;
+        h = (h + 1) & tmask;
+    }
+    const double z = y0[i];
+    target[i] = z > 0.0 ? (float)log((Y + eps * z) / z) : 0.0f;
+    if (y_exact) y_exact[i] = Y;
+}
+
+// Gate: rows whose ensemble spread of the predicted log ratio exceeds `gate` go to the
+// exact path (key into the filter set, bins marked); the others add Y0 (e^mean - eps).
+__global__ void k_st_gate(const long long *__restrict__ key, const double *__restrict__ y0,
+                          const float *__restrict__ mean, const float *__restrict__ sdev, int64_t n,
+                          double eps, double gate, int64_t n_t_bins, long long *filter,
+                          uint64_t fmask, uint8_t *__restrict__ qmark, uint8_t *__restrict__ tmark,
+                          double *__restrict__ slots, unsigned long long *__restrict__ n_flag,
+                          unsigned int *err) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double add = 0.0;
+    unsigned long long fl = 0;
+    if (i < n) {
+        if (sdev[i] > gate) {
+            fl = 1;
+            const long long k = key[i];
+            const int64_t a = k / n_t_bins;
+            qmark[a] = 1;
+            tmark[k - a * n_t_bins] = 1;
+            uint64_t h = mix64((uint64_t)k) & fmask;
+            bool done = false;
+            for (uint64_t probe = 0; probe <= fmask && probe < kMaxProbe && !done; ++probe) {
+                const long long prev = (long long)atomicCAS(
+                    reinterpret_cast<unsigned long long *>(filter + h), ~0ull, (unsigned long long)k);
+                if (prev == -1ll || prev == k) done = true;
+                else h = (h + 1) & fmask;
+            }
+            if (!done) atomicOr(err, kErrTableFull);
+        } else {
+            add = fmax(y0[i] * (exp((double)mean[i]) - eps), 0.0);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        add += __shfl_xor(add, off);
+        fl += __shfl_xor(fl, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (add != 0.0) atomicAdd(&slots[blockIdx.x & (kCounterSlots - 1)], add);
+        if (fl) atomicAdd(n_flag, fl);
+    }
+}
+
+// Photons whose bin is not marked get bin -1 (skipped by the exact pass).
+__global__ void k_st_mask_bins(const int32_t *__restrict__ bins, int64_t n,
+                               const uint8_t *__restrict__ mark, int32_t *__restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = bins[i];
+    out[i] = (b >= 0 && mark[b]) ? b : -1;
+}
+
+__global__ void k_fill_i64v(long long *p, long long v, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace
+
+void launch_st_records(const double *sums, int64_t n_bins, double t_bin, double *soa, int64_t cap,
+                       int32_t *rec_bin, unsigned long long *count, hipStream_t st) {
+    if (n_bins <= 0) return;
+    hipLaunchKernelGGL(k_st_records, dim3(grid_for(n_bins, 256)), dim3(256), 0, st, sums, n_bins,
+                       t_bin, soa, cap, rec_bin, count);
+}
+
+void launch_st_features(const long long *keys, const double *vals, int64_t cap, int64_t n_t_bins,
+                        const double *q_sums, const double *t_sums, double vol, float *x,
+                        double *y0, long long *key_out, int64_t out_cap, unsigned long long *count,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_st_features, dim3(grid_for(cap, 256)), dim3(256), 0, st, keys, vals, cap,
+                       n_t_bins, q_sums, t_sums, vol, x, y0, key_out, out_cap, count);
+}
+
+void launch_st_targets(const long long *key, const double *y0, int64_t n, const long long *tkeys,
+                       const double *tvals, int64_t tcap, double eps, float *target, double *y_exact,
+                       hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_st_targets, dim3(grid_for(n, 256)), dim3(256), 0, st, key, y0, n, tkeys,
+                       tvals, (uint64_t)(tcap - 1), eps, target, y_exact);
+}
+
+void launch_st_gate(const long long *key, const double *y0, const float *mean, const float *sdev,
+                    int64_t n, double eps, double gate, int64_t n_t_bins, long long *filter,
+                    int64_t fcap, uint8_t *qmark, uint8_t *tmark, double *slots,
+                    unsigned long long *n_flag, unsigned int *err, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_st_gate, dim3(grid_for(n, 256)), dim3(256), 0, st, key, y0, mean, sdev, n,
+                       eps, gate, n_t_bins, filter, (uint64_t)(fcap - 1), qmark, tmark, slots,
+                       n_flag, err);
+}
+
+void launch_st_mask_bins(const int32_t *bins, int64_t n, const uint8_t *mark, int32_t *out,
+                         hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_st_mask_bins, dim3(grid_for(n, 256)), dim3(256), 0, st, bins, n, mark, out);
+}
+
+void launch_fill_keys(long long *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_i64v, dim3(grid_for(n, 256)), dim3(256), 0, st, p, -1ll, n);
+}
 
 void launch_st_bin(const BeamDev &b, const StGridDev &g, int32_t *bins, double *sums,
                    hipStream_t st) {
@@ -234,13 +443,15 @@ void launch_st_traverse(const Node *nodes, int64_t nt, const PBox *qbox, const u
                         int64_t nq, const int32_t *inst_root, const int32_t *inst_stop,
                         const BeamDev &q, const BeamDev &t, const int32_t *q_bins,
                         const int32_t *t_bins, int64_t n_t_bins, double dt, const StCell &cell,
+                        int geometric, const long long *filter, int64_t filter_cap,
                         long long *keys, double *vals, int64_t cap, double *slots, DevCounters *c,
                         hipStream_t st) {
     if (nq <= 0 || nt <= 0) return;
     const int32_t n_int = (int32_t)(nt - 1);
     hipLaunchKernelGGL(k_st_traverse<256>, dim3(grid_for(nq, 256)), dim3(256), 0, st, nodes, n_int,
                        qbox, qorder, nq, inst_root, inst_stop, q, t, q_bins, t_bins, n_t_bins, dt,
-                       cell, keys, vals, (uint64_t)(cap - 1), slots, c);
+                       cell, geometric, filter, (uint64_t)(filter ? filter_cap - 1 : 0), keys, vals,
+                       (uint64_t)(cap - 1), slots, c);
 }
 
 }  // namespace tril

@@ -263,13 +263,31 @@ struct StGridDev {
 struct StCell {
     double c[3];  // cloud box edge lengths (the grid's cell size) [um]
 };
+constexpr int kStSums = 8;  // per-bin sums: w, w E, w u (3), w X(t_bin) (3)
 void launch_st_bin(const BeamDev &b, const StGridDev &g, int32_t *bins, double *sums,
                    hipStream_t st);
+void launch_st_records(const double *sums, int64_t n_bins, double t_bin, double *soa, int64_t cap,
+                       int32_t *rec_bin, unsigned long long *count, hipStream_t st);
+void launch_st_features(const long long *keys, const double *vals, int64_t cap, int64_t n_t_bins,
+                        const double *q_sums, const double *t_sums, double vol, float *x,
+                        double *y0, long long *key_out, int64_t out_cap, unsigned long long *count,
+                        hipStream_t st);
+void launch_st_targets(const long long *key, const double *y0, int64_t n, const long long *tkeys,
+                       const double *tvals, int64_t tcap, double eps, float *target, double *y_exact,
+                       hipStream_t st);
+void launch_st_gate(const long long *key, const double *y0, const float *mean, const float *sdev,
+                    int64_t n, double eps, double gate, int64_t n_t_bins, long long *filter,
+                    int64_t fcap, uint8_t *qmark, uint8_t *tmark, double *slots,
+                    unsigned long long *n_flag, unsigned int *err, hipStream_t st);
+void launch_st_mask_bins(const int32_t *bins, int64_t n, const uint8_t *mark, int32_t *out,
+                         hipStream_t st);
+void launch_fill_keys(long long *p, int64_t n, hipStream_t st);
 void launch_st_clear(long long *keys, double *vals, int64_t cap, double *slots, hipStream_t st);
 void launch_st_traverse(const Node *nodes, int64_t nt, const PBox *qbox, const uint32_t *qorder,
                         int64_t nq, const int32_t *inst_root, const int32_t *inst_stop,
                         const BeamDev &q, const BeamDev &t, const int32_t *q_bins,
                         const int32_t *t_bins, int64_t n_t_bins, double dt, const StCell &cell,
+                        int geometric, const long long *filter, int64_t filter_cap,
                         long long *keys, double *vals, int64_t cap, double *slots, DevCounters *c,
                         hipStream_t st);
 

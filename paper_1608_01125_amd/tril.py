@@ -83,11 +83,23 @@ class tril_st_table(ctypes.Structure):
     _fields_ = [("cap", ctypes.c_int64), ("key", ctypes.c_void_p), ("yield_", ctypes.c_void_p)]
 
 
+class tril_st_sur_params(ctypes.Structure):
+    _fields_ = [("cloud_factor", ctypes.c_double), ("eps", ctypes.c_double),
+                ("gate", ctypes.c_double)]
+
+
+class tril_st_sur_result(ctypes.Structure):
+    _fields_ = [("total", ctypes.c_double), ("surrogate_part", ctypes.c_double),
+                ("exact_part", ctypes.c_double), ("n_bin_pairs", ctypes.c_int64),
+                ("n_gated", ctypes.c_int64), ("ms", ctypes.c_double)]
+
+
 EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats",
            "tril_autotune", "tril_set_tune", "tril_st_bin", "tril_st_exact",
            "tril_mlp_create", "tril_mlp_destroy", "tril_mlp_set_params", "tril_mlp_get_params",
            "tril_mlp_set_norm", "tril_mlp_fit_norm", "tril_mlp_grad", "tril_mlp_train",
-           "tril_mlp_predict", "tril_dbg_gemm_bf16",
+           "tril_mlp_predict", "tril_st_features", "tril_st_targets", "tril_st_surrogate",
+           "tril_dbg_gemm_bf16",
            "tril_reset_counters", "tril_destroy", "tril_strerror", "tril_last_hip_error",
            "tril_dbg_sort_u32", "tril_dbg_sort_u64", "tril_dbg_morton", "tril_dbg_pair_eval",
            "tril_dbg_pair_eval32",
@@ -130,6 +142,15 @@ def lib() -> ctypes.CDLL:
     L.tril_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_float, ctypes.c_uint64, dp]
     L.tril_mlp_predict.argtypes = [vp, vp, i64, vp, vp]
     L.tril_dbg_gemm_bf16.argtypes = [vp, i64, i64, vp, i64, i64, i32, i32, i32, vp, vp]
+    gp = ctypes.POINTER(tril_st_grid)
+    L.tril_st_features.argtypes = [vp, vp, gp, vp, gp, i32, i32, ctypes.POINTER(tril_st_sur_params),
+                                   vp, vp, vp, i64, ctypes.POINTER(ctypes.c_int64)]
+    L.tril_st_targets.argtypes = [vp, vp, i64, ctypes.POINTER(tril_st_table), ctypes.c_double, vp,
+                                  vp, vp]
+    L.tril_st_surrogate.argtypes = [vp, vp, ctypes.POINTER(tril_beam), vp, vp, gp,
+                                    ctypes.POINTER(tril_beam), vp, vp, gp, i32, i32,
+                                    ctypes.POINTER(tril_st_sur_params),
+                                    ctypes.POINTER(tril_st_sur_result)]
     L.tril_reset_counters.argtypes = [vp]
     L.tril_destroy.argtypes = [vp]
     L.tril_destroy.restype = None
@@ -410,6 +431,59 @@ class Mlp:
         _check(lib().tril_mlp_predict(self.h, x.data_ptr() if n else None, n, mean.data_ptr(),
                                       sdev.data_ptr()), "tril_mlp_predict")
         return mean[:n], sdev[:n]
+
+
+def sur_params(cloud_factor: float = 0.0, eps: float = 0.0, gate: float = 0.0) -> tril_st_sur_params:
+    return tril_st_sur_params(cloud_factor, eps, gate)
+
+
+def tril_st_features(ctx, q_sums, q_grid, t_sums, t_grid, k0: int, n_steps: int, params=None,
+                     cap: int = 1 << 20):
+    """Feature rows of the candidate bin pairs: (x [n, 6] float32, y0 [n] float64,
+    key [n] int64), device tensors; grows the buffers once if cap is too small."""
+    import torch
+    gq, gt = st_grid(q_grid), st_grid(t_grid)
+    p = params or sur_params()
+    for _ in range(2):
+        x = torch.empty((max(cap, 1), 6), dtype=torch.float32, device="cuda")
+        y0 = torch.empty(max(cap, 1), dtype=torch.float64, device="cuda")
+        key = torch.empty(max(cap, 1), dtype=torch.int64, device="cuda")
+        n = ctypes.c_int64(0)
+        code = lib().tril_st_features(_h(ctx), q_sums.data_ptr(), ctypes.byref(gq), t_sums.data_ptr(),
+                                      ctypes.byref(gt), int(k0), int(n_steps), ctypes.byref(p),
+                                      x.data_ptr(), y0.data_ptr(), key.data_ptr(), cap, ctypes.byref(n))
+        if code == TRIL_E_OVERFLOW and n.value > cap:
+            cap = n.value
+            continue
+        _check(code, "tril_st_features")
+        m = n.value
+        return x[:m], y0[:m], key[:m]
+    raise TrilError(TRIL_E_OVERFLOW, "tril_st_features")
+
+
+def tril_st_targets(key, y0, exact: "StTable", eps: float = 1e-3, stream=None):
+    import torch
+    n = key.shape[0]
+    target = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+    y_exact = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+    _check(lib().tril_st_targets(key.data_ptr() if n else None, y0.data_ptr() if n else None, n,
+                                 ctypes.byref(exact.c), float(eps), target.data_ptr(),
+                                 y_exact.data_ptr(), _stream(stream)), "tril_st_targets")
+    return target[:n], y_exact[:n]
+
+
+def tril_st_surrogate(ctx, mlp: "Mlp", target: Beam, t_bins, t_sums, t_grid, query: Beam, q_bins,
+                      q_sums, q_grid, k0: int, n_steps: int, params=None) -> dict:
+    r = tril_st_sur_result()
+    gq, gt = st_grid(q_grid), st_grid(t_grid)
+    p = params or sur_params()
+    _check(lib().tril_st_surrogate(_h(ctx), mlp.h, ctypes.byref(target.c),
+                                   t_bins.data_ptr() if target.n else None, t_sums.data_ptr(),
+                                   ctypes.byref(gt), ctypes.byref(query.c),
+                                   q_bins.data_ptr() if query.n else None, q_sums.data_ptr(),
+                                   ctypes.byref(gq), int(k0), int(n_steps), ctypes.byref(p),
+                                   ctypes.byref(r)), "tril_st_surrogate")
+    return {k: getattr(r, k) for k, _ in tril_st_sur_result._fields_}
 
 
 def tril_dbg_gemm_bf16(A, sam, sak, B, sbk, sbn, M, N, K, C, stream=None) -> None:

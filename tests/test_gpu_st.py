@@ -20,7 +20,7 @@ def torch():
 def _gpu_bins(torch, beam_np, grid, offs=None):
     b = T.Beam(beam_np, offs)
     bins = torch.empty(max(b.n, 1), dtype=torch.int32, device="cuda")
-    sums = torch.zeros((grid.n_bins, 5), dtype=torch.float64, device="cuda")
+    sums = torch.zeros((grid.n_bins, 8), dtype=torch.float64, device="cuda")
     T.tril_st_bin(b, grid, bins, sums)
     torch.cuda.synchronize()
     return b, bins, sums
