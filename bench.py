@@ -100,6 +100,77 @@ def make_workload(name: str, physics_steps: int):
     return wl, A, offA, B, offB, n_steps
 
 
+def st_bench(args):
+    """Statistical regime, head-on shape: exact cell-pair yields through the hierarchy, and
+    the surrogate path (ensemble trained on exact yields of the same shape at other seeds,
+    budget gate at 1%); both timed on the same inputs."""
+    import numpy as np
+    import torch
+    from paper_1608_01125_amd import beams, surrogate
+    from paper_1608_01125_amd import tril as T
+    eps = 1e-3
+    ctx = T.Context(0.1, None)
+    net = T.Mlp(4, seed=11)
+    try:
+        t0 = time.perf_counter()
+        insts = [surrogate.Instance(beams.st_headon(args.st_mp, seed=2000 + m))
+                 for m in range(args.st_train)]
+        x, t, y0, y = surrogate.training_rows(ctx, insts, eps=eps)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(0)
+        keep = (y > 0) | (torch.rand(y.shape[0], device="cuda", generator=g) < 0.25)
+        surrogate.train(net, x[keep].contiguous(), t[keep].contiguous(), n_steps=args.st_train_steps,
+                        batch=8192, lr=1e-3)
+        scale = surrogate.yield_scale(net, x, y0, y, eps)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        n_rows = int(keep.sum())
+        del insts, x, t, y0, y, keep
+        inst = surrogate.Instance(beams.st_headon(args.st_mp))
+        p = T.sur_params(eps=eps, gate=0.01, scale=scale)
+        for _ in range(args.warmup):
+            inst.exact(ctx)
+            inst.surrogate(ctx, net, p)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            _, exact_total = inst.exact(ctx)
+        torch.cuda.synchronize()
+        t_exact = (time.perf_counter() - t1) / max(args.steps, 1)
+        st = ctx.stats(None)
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            res = inst.surrogate(ctx, net, p)
+        torch.cuda.synchronize()
+        t_sur = (time.perf_counter() - t1) / max(args.steps, 1)
+    finally:
+        net.close()
+        ctx.close()
+    n = args.st_mp
+    q = float(n) * n * 400
+    out = {
+        "metric": METRIC, "value": q / t_sur, "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t_sur,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "st_headon", "macro_particles_per_beam": n,
+                   "physical_photons_per_beam": 1e9, "time_steps": 400,
+                   "grid": "32^3 cells (surrogate on cell pairs)", "ensemble": 4,
+                   "training": {"instances": args.st_train, "rows": n_rows,
+                                "adam_steps": args.st_train_steps, "seconds": round(train_s, 1),
+                                "yield_scale": round(scale, 5)}},
+        "surrogate": {"queries_per_s": q / t_sur, "ms": 1e3 * t_sur, "total": res["total"],
+                      "rel_error_vs_exact": abs(res["total"] - exact_total) / exact_total,
+                      "bin_pairs": res["n_bin_pairs"], "bin_pairs_exact": res["n_gated"],
+                      "exact_part": res["exact_part"] / max(res["total"], 1e-300),
+                      "predicted_spread": res["predicted_spread"],
+                      "speedup_vs_exact": t_exact / t_sur},
+        "exact": {"queries_per_s": q / t_exact, "ms": 1e3 * t_exact, "total": exact_total,
+                  "cloud_pair_steps_per_run": st["n_candidates"] // max(args.steps + args.warmup, 1)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(A, offA, B, offB, dt, n_steps, target_s: float):
     """Oracle (as it stands) on a bounded random sample of query rows (per instance
     for a batched workload: rows drawn uniformly over all query photons)."""
@@ -160,6 +231,10 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--st-mp", type=int, default=200_000,
+                    help="st_headon: macro-particles per beam")
+    ap.add_argument("--st-train", type=int, default=8, help="st_headon: training instances")
+    ap.add_argument("--st-train-steps", type=int, default=4000, help="st_headon: Adam steps")
     ap.add_argument("--autotune", action="store_true",
                     help="pick steps per launch, traversal workgroup size and Morton bits with "
                          "tril_autotune before timing (cached per workload shape)")
@@ -178,6 +253,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "st_headon":
+        return st_bench(args)
     wl, A, offA, B, offB, n_steps = make_workload(args.workload, args.physics_steps)
     nA, nB = len(A["E"]), len(B["E"])
     if offA is None:

@@ -289,14 +289,23 @@ int tril_st_exact(tril_ctx *ctx, const tril_beam *target, const int32_t *t_bins,
  * volume, theta between the mean directions). The bin-level yield
  * Y0 = rho_a rho_b sigma(s_ab) (1 - cos theta_ab) Omega_ab is the estimate without
  * the network; the network predicts log((Y + eps Y0) / Y0) of the exact bin-pair yield Y,
- * so Y = Y0 (exp(prediction) - eps). A bin pair whose ensemble standard deviation of the
- * prediction exceeds `gate` (about its relative yield error) is computed exactly.
+ * so Y = Y0 (exp(prediction) - eps). Bin pairs the ensemble is unsure of (see gate_mode)
+ * are computed exactly.
  * ------------------------------------------------------------------------------- */
 typedef struct {
     double cloud_factor;          /* bin cloud edge / cell edge, >= 1 (0 = 3.5) */
     double eps;                   /* floor of the predicted yield ratio (0 = 1e-3) */
     double gate;                  /* ensemble standard deviation above which a bin pair
                                      takes the exact path (0 = 0.01) */
+    double scale;                 /* factor on the predicted yields (0 = 1): the ratio of
+                                     exact to predicted total on the training rows, which
+                                     removes the bias of predicting a mean logarithm */
+    int32_t gate_mode;            /* 0 (budget): the bin pairs with the largest uncertainty
+                                     contributions u = Yhat x ensemble spread go to the exact
+                                     path until the spread of the remaining predicted total,
+                                     sqrt(sum u^2), is at most gate x the predicted total;
+                                     1 (per pair): every bin pair whose spread exceeds gate */
+    int32_t pad0;
 } tril_st_sur_params;
 
 typedef struct {
@@ -306,13 +315,17 @@ typedef struct {
     int64_t n_bin_pairs;          /* candidate bin pairs (feature rows) */
     int64_t n_gated;              /* bin pairs sent to the exact path */
     double ms;                    /* event time of the whole call on the context stream */
+    double predicted_spread;      /* budget mode: ensemble spread of the surrogate part
+                                     relative to the predicted total */
 } tril_st_sur_result;
 
 /* Feature rows of all candidate bin pairs of the two beams' per-bin sums (as written by
  * tril_st_bin) over steps k0 .. k0+n_steps-1: x [n][6] FP32, y0 [n] FP64, key [n]
  * (query bin x n_target_bins + target bin), all device. *n receives the number of rows;
- * TRIL_E_OVERFLOW when it exceeds cap. The two grids must have the same cell. Uses the
- * context's stream and scratch and clears its device error flags. Synchronous. */
+ * TRIL_E_OVERFLOW when it exceeds cap; TRIL_E_NOMEM when the context's bin-pair table
+ * could not hold the candidate pairs after growing 64-fold. The two grids must have the
+ * same cell. Uses the context's stream and scratch and clears its device error flags.
+ * Synchronous. */
 int tril_st_features(tril_ctx *ctx, const double *q_sums, const tril_st_grid *q_grid,
                      const double *t_sums, const tril_st_grid *t_grid, int32_t k0, int32_t n_steps,
                      const tril_st_sur_params *params, float *x, double *y0, int64_t *key,

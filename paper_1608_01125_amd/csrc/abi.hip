@@ -1179,7 +1179,8 @@ int tril_st_features(tril_ctx *c, const double *q_sums, const tril_st_grid *gq,
                    nullptr, 0, c->sg_key, c->sg_val, c->sg_cap));
         const int r = st_finish(c, nullptr);
         if (r == TRIL_OK) break;
-        if (r != TRIL_E_OVERFLOW || attempt >= 4) return r;
+        if (r != TRIL_E_OVERFLOW) return r;
+        if (attempt >= 3) return TRIL_E_NOMEM;  // the pair table did not fit the scratch it may take
         tcap = c->sg_cap * 4;
     }
     // one feature row per occupied slot
@@ -1222,6 +1223,7 @@ int tril_st_surrogate(tril_ctx *c, tril_mlp *mlp, const tril_beam *t, const int3
     if (q->n_inst != 1 || t->n_inst != 1) return TRIL_E_NOTIMPL;
     const double eps = (p && p->eps > 0.0) ? p->eps : 1e-3;
     const double gate = (p && p->gate > 0.0) ? p->gate : 0.01;
+    const double scale = (p && p->scale > 0.0) ? p->scale : 1.0;
     std::memset(out, 0, sizeof(*out));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
@@ -1280,8 +1282,49 @@ int tril_st_surrogate(tril_ctx *c, tril_mlp *mlp, const tril_beam *t, const int3
         cleanup();
         return hip_fail(he);
     }
+    int cut = -1;  // per-pair mode
+    if (!(p && p->gate_mode == 1)) {
+        // budget mode: pairs with the largest uncertainty contributions go exact until the
+        // remaining ensemble spread of the total is within gate x the predicted total
+        double *hist = nullptr;
+        if ((rc = dev_alloc(&hist, kUncBuckets)) != TRIL_OK) {
+            cleanup();
+            return rc;
+        }
+        he = hipMemsetAsync(hist, 0, kUncBuckets * sizeof(double), c->st);
+        if (he == hipSuccess)
+            launch_st_unc(c->sf_y0, c->sf_mean, c->sf_sd, nrow, eps, scale, hist, c->st_slots, c->st);
+        std::vector<double> h((size_t)kUncBuckets);
+        double pred_total = 0.0;
+        if (he == hipSuccess) he = hipGetLastError();
+        if (he == hipSuccess) he = hipStreamSynchronize(c->st);
+        if (he == hipSuccess) he = hipMemcpy(h.data(), hist, kUncBuckets * sizeof(double), hipMemcpyDeviceToHost);
+        if (he == hipSuccess) {
+            double sl[kCounterSlots];
+            he = hipMemcpy(sl, c->st_slots, sizeof(sl), hipMemcpyDeviceToHost);
+            for (double v : sl) pred_total += v;
+        }
+        dev_free(hist);
+        if (he == hipSuccess) he = hipMemsetAsync(c->st_slots, 0, kCounterSlots * sizeof(double), c->st);
+        if (he != hipSuccess) {
+            cleanup();
+            return hip_fail(he);
+        }
+        const double budget = (gate * pred_total) * (gate * pred_total);
+        double acc = 0.0;
+        cut = kUncBuckets - 1;
+        for (int b = 0; b < kUncBuckets; ++b) {
+            if (acc + h[(size_t)b] > budget) {
+                cut = b - 1;
+                break;
+            }
+            acc += h[(size_t)b];
+        }
+        if (cut < 0) cut = 0;
+        out->predicted_spread = pred_total > 0.0 ? std::sqrt(acc) / pred_total : 0.0;
+    }
     launch_st_gate(reinterpret_cast<const long long *>(c->sf_key), c->sf_y0, c->sf_mean, c->sf_sd,
-                   nrow, eps, gate, nbt, filter, fcap, qmark, tmark, c->st_slots, nflag,
+                   nrow, eps, gate, scale, cut, nbt, filter, fcap, qmark, tmark, c->st_slots, nflag,
                    &c->d_cnt->err, c->st);
     double sur = 0.0;
     if ((rc = st_finish(c, &sur)) != TRIL_OK) {

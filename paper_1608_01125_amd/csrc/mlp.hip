@@ -52,6 +52,51 @@ struct GemmArgs {
     float *out_pre;     // [M x N] pre-activation (with kEpiSilu), or null
 };
 
+// One 64 x 32 operand tile into LDS as [row][k]: element (r, k) at P[(r0 + r) sr + (k0 + k) sk],
+// zero outside [0, R) x [0, K). 256 threads, 8 elements each: with the operand
+// contiguous along k, one 16-byte load per thread; contiguous along rows, one 16-byte load
+// of 8 rows at one k, written transposed; otherwise element by element.
+__device__ __forceinline__ void load_tile(const uint16_t *__restrict__ P, int64_t sr, int64_t sk,
+                                          int r0, int R, int k0, int K, uint16_t (*S)[kLdsK],
+                                          int tid) {
+    if (sk == 1 && (sr & 7) == 0) {
+        const int r = tid >> 2, kc = (tid & 3) * 8;
+        const int row = r0 + r, k = k0 + kc;
+        const uint16_t *src = P + (int64_t)row * sr + k;
+        if (row < R && k + 8 <= K && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+            *reinterpret_cast<uint4 *>(&S[r][kc]) = *reinterpret_cast<const uint4 *>(src);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                S[r][kc + e] = (row < R && k + e < K) ? P[(int64_t)row * sr + k + e] : (uint16_t)0;
+        }
+        return;
+    }
+    if (sr == 1 && (sk & 7) == 0) {
+        const int kk = tid >> 3, rc = (tid & 7) * 8;
+        const int k = k0 + kk, row = r0 + rc;
+        const uint16_t *src = P + (int64_t)k * sk + row;
+        if (k < K && row + 8 <= R && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(src);
+            const uint16_t *h = reinterpret_cast<const uint16_t *>(&v);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) S[rc + e][kk] = h[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                S[rc + e][kk] = (k < K && row + e < R) ? P[(int64_t)k * sk + row + e] : (uint16_t)0;
+        }
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int idx = tid * 8 + e;
+        const int r = idx >> 5, kk = idx & 31;
+        const int row = r0 + r, k = k0 + kk;
+        S[r][kk] = (row < R && k < K) ? P[(int64_t)row * sr + (int64_t)k * sk] : (uint16_t)0;
+    }
+}
+
 // C = A B with a 64 x 64 tile per workgroup (four waves of 32 x 32, each 2 x 2 MFMA
 // 16 x 16 tiles), K in steps of 32 staged in LDS (A as [m][k], B as [n][k]).
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
@@ -66,14 +111,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < g.K; k0 += kTK) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = tid * 8 + e;
-            const int r = idx >> 5, kk = idx & 31;
-            const int m = m0 + r, n = n0 + r, k = k0 + kk;
-            sA[r][kk] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : (uint16_t)0;
-            sB[r][kk] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : (uint16_t)0;
-        }
+        load_tile(g.A, g.sam, g.sak, m0, g.M, k0, g.K, sA, tid);
+        load_tile(g.B, g.sbn, g.sbk, n0, g.N, k0, g.K, sB, tid);
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 2; ++i) {

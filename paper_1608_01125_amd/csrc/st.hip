@@ -324,19 +324,51 @@ __global__ void k_st_targets(const long long *__restrict__ key, const double *__
     if (y_exact) y_exact[i] = Y;
 }
 
-// Gate: rows whose ensemble spread of the predicted log ratio exceeds `gate` go to the
-// exact path (key into the filter set, bins marked); the others add Y0 (e^mean - eps).
+__device__ __forceinline__ double st_pred(const double *y0, const float *mean, int64_t i,
+                                          double eps, double scale) {
+    return scale * fmax(y0[i] * (exp((double)mean[i]) - eps), 0.0);
+}
+
+// Bucket of an uncertainty contribution u > 0 on a log2 scale, 16 buckets per octave.
+__device__ __forceinline__ int unc_bucket(double u) {
+    if (!(u > 0.0)) return 0;
+    const int b = (int)floor(log2(u) * 16.0) + kUncBuckets / 2;
+    return b < 1 ? 1 : (b >= kUncBuckets ? kUncBuckets - 1 : b);
+}
+
+// Histogram of the rows' uncertainty contributions u_i = Yhat_i sd_i (absolute spread of
+// the predicted yield): per bucket the sum of u_i^2; and the predicted total in slots.
+__global__ void k_st_unc(const double *__restrict__ y0, const float *__restrict__ mean,
+                         const float *__restrict__ sdev, int64_t n, double eps, double scale,
+                         double *__restrict__ var_hist, double *__restrict__ slots) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double yh = 0.0;
+    if (i < n) {
+        yh = st_pred(y0, mean, i, eps, scale);
+        const double u = yh * (double)sdev[i];
+        if (u > 0.0) atomicAdd(&var_hist[unc_bucket(u)], u * u);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) yh += __shfl_xor(yh, off);
+    if ((threadIdx.x & 63) == 0 && yh != 0.0) atomicAdd(&slots[blockIdx.x & (kCounterSlots - 1)], yh);
+}
+
+// Gate: a row goes to the exact path (key into the filter set, bins marked) when its
+// ensemble spread exceeds `gate` (per-pair mode, cut < 0) or its uncertainty bucket lies
+// above `cut` (budget mode); the others add their predicted yield.
 __global__ void k_st_gate(const long long *__restrict__ key, const double *__restrict__ y0,
                           const float *__restrict__ mean, const float *__restrict__ sdev, int64_t n,
-                          double eps, double gate, int64_t n_t_bins, long long *filter,
-                          uint64_t fmask, uint8_t *__restrict__ qmark, uint8_t *__restrict__ tmark,
-                          double *__restrict__ slots, unsigned long long *__restrict__ n_flag,
-                          unsigned int *err) {
+                          double eps, double gate, double scale, int cut, int64_t n_t_bins,
+                          long long *filter, uint64_t fmask, uint8_t *__restrict__ qmark,
+                          uint8_t *__restrict__ tmark, double *__restrict__ slots,
+                          unsigned long long *__restrict__ n_flag, unsigned int *err) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double add = 0.0;
     unsigned long long fl = 0;
     if (i < n) {
-        if (sdev[i] > gate) {
+        const double yh = st_pred(y0, mean, i, eps, scale);
+        const bool flag = cut < 0 ? (sdev[i] > gate) : (unc_bucket(yh * (double)sdev[i]) > cut);
+        if (flag) {
             fl = 1;
             const long long k = key[i];
             const int64_t a = k / n_t_bins;
@@ -352,7 +384,7 @@ __global__ void k_st_gate(const long long *__restrict__ key, const double *__res
             }
             if (!done) atomicOr(err, kErrTableFull);
         } else {
-            add = fmax(y0[i] * (exp((double)mean[i]) - eps), 0.0);
+            add = yh;
         }
     }
 #pragma unroll
@@ -408,13 +440,20 @@ void launch_st_targets(const long long *key, const double *y0, int64_t n, const 
 }
 
 void launch_st_gate(const long long *key, const double *y0, const float *mean, const float *sdev,
-                    int64_t n, double eps, double gate, int64_t n_t_bins, long long *filter,
-                    int64_t fcap, uint8_t *qmark, uint8_t *tmark, double *slots,
+                    int64_t n, double eps, double gate, double scale, int cut, int64_t n_t_bins,
+                    long long *filter, int64_t fcap, uint8_t *qmark, uint8_t *tmark, double *slots,
                     unsigned long long *n_flag, unsigned int *err, hipStream_t st) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_st_gate, dim3(grid_for(n, 256)), dim3(256), 0, st, key, y0, mean, sdev, n,
-                       eps, gate, n_t_bins, filter, (uint64_t)(fcap - 1), qmark, tmark, slots,
+                       eps, gate, scale, cut, n_t_bins, filter, (uint64_t)(fcap - 1), qmark, tmark, slots,
                        n_flag, err);
+}
+
+void launch_st_unc(const double *y0, const float *mean, const float *sdev, int64_t n, double eps,
+                   double scale, double *var_hist, double *slots, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_st_unc, dim3(grid_for(n, 256)), dim3(256), 0, st, y0, mean, sdev, n, eps,
+                       scale, var_hist, slots);
 }
 
 void launch_st_mask_bins(const int32_t *bins, int64_t n, const uint8_t *mark, int32_t *out,

@@ -276,9 +276,12 @@ void launch_st_targets(const long long *key, const double *y0, int64_t n, const 
                        const double *tvals, int64_t tcap, double eps, float *target, double *y_exact,
                        hipStream_t st);
 void launch_st_gate(const long long *key, const double *y0, const float *mean, const float *sdev,
-                    int64_t n, double eps, double gate, int64_t n_t_bins, long long *filter,
-                    int64_t fcap, uint8_t *qmark, uint8_t *tmark, double *slots,
+                    int64_t n, double eps, double gate, double scale, int cut, int64_t n_t_bins,
+                    long long *filter, int64_t fcap, uint8_t *qmark, uint8_t *tmark, double *slots,
                     unsigned long long *n_flag, unsigned int *err, hipStream_t st);
+constexpr int kUncBuckets = 4096;  // uncertainty histogram of the budget gate
+void launch_st_unc(const double *y0, const float *mean, const float *sdev, int64_t n, double eps,
+                   double scale, double *var_hist, double *slots, hipStream_t st);
 void launch_st_mask_bins(const int32_t *bins, int64_t n, const uint8_t *mark, int32_t *out,
                          hipStream_t st);
 void launch_fill_keys(long long *p, int64_t n, hipStream_t st);

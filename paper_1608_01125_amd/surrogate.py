@@ -76,3 +76,12 @@ def train(net: T.Mlp, x, t, n_steps: int = 3000, batch: int = 4096, lr: float = 
           seed: int = 0):
     net.fit_norm(x, t)
     return net.train(x, t, n_steps, batch, lr, seed)
+
+
+def yield_scale(net: T.Mlp, x, y0, y, eps: float = 1e-3) -> float:
+    """Exact over predicted total yield on training rows: the network fits the mean of
+    log((Y + eps Y0) / Y0), whose exponential falls short of the mean ratio."""
+    import torch
+    mean, _ = net.predict(x)
+    pred = (y0 * (torch.exp(mean.double()) - eps)).clamp(min=0)
+    return float(y.sum() / pred.sum())

@@ -85,13 +85,15 @@ class tril_st_table(ctypes.Structure):
 
 class tril_st_sur_params(ctypes.Structure):
     _fields_ = [("cloud_factor", ctypes.c_double), ("eps", ctypes.c_double),
-                ("gate", ctypes.c_double)]
+                ("gate", ctypes.c_double), ("scale", ctypes.c_double),
+                ("gate_mode", ctypes.c_int32), ("pad0", ctypes.c_int32)]
 
 
 class tril_st_sur_result(ctypes.Structure):
     _fields_ = [("total", ctypes.c_double), ("surrogate_part", ctypes.c_double),
                 ("exact_part", ctypes.c_double), ("n_bin_pairs", ctypes.c_int64),
-                ("n_gated", ctypes.c_int64), ("ms", ctypes.c_double)]
+                ("n_gated", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("predicted_spread", ctypes.c_double)]
 
 
 EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats",
@@ -433,8 +435,9 @@ class Mlp:
         return mean[:n], sdev[:n]
 
 
-def sur_params(cloud_factor: float = 0.0, eps: float = 0.0, gate: float = 0.0) -> tril_st_sur_params:
-    return tril_st_sur_params(cloud_factor, eps, gate)
+def sur_params(cloud_factor: float = 0.0, eps: float = 0.0, gate: float = 0.0,
+               scale: float = 0.0, per_pair: bool = False) -> tril_st_sur_params:
+    return tril_st_sur_params(cloud_factor, eps, gate, scale, 1 if per_pair else 0, 0)
 
 
 def tril_st_features(ctx, q_sums, q_grid, t_sums, t_grid, k0: int, n_steps: int, params=None,
@@ -455,7 +458,7 @@ def tril_st_features(ctx, q_sums, q_grid, t_sums, t_grid, k0: int, n_steps: int,
         if code == TRIL_E_OVERFLOW and n.value > cap:
             cap = n.value
             continue
-        _check(code, "tril_st_features")
+        _check(code, f"tril_st_features (rows {n.value}, capacity {cap})")
         m = n.value
         return x[:m], y0[:m], key[:m]
     raise TrilError(TRIL_E_OVERFLOW, "tril_st_features")

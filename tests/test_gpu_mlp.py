@@ -28,7 +28,10 @@ def _bits(a):
 
 @pytest.mark.parametrize("M_,N,K,transA,transB", [
     (1, 1, 1, False, False), (17, 33, 45, False, False), (64, 64, 32, False, False),
-    (130, 70, 300, True, False), (65, 129, 7, False, True), (200, 1, 256, True, True)])
+    (130, 70, 300, True, False), (65, 129, 7, False, True), (200, 1, 256, True, True),
+    # strides that take the 16-byte load paths (contiguous along k, and along rows)
+    (256, 256, 256, False, False), (128, 64, 512, True, True), (64, 256, 4096, True, False),
+    (72, 200, 264, False, True)])
 def test_gemm_matches_numpy(torch, M_, N, K, transA, transB):
     rng = np.random.default_rng(M_ * 1000 + N + K)
     a = M.bf16(rng.normal(size=(M_, K)))

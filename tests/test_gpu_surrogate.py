@@ -82,8 +82,8 @@ def test_trained_ensemble_beats_bin_level_estimate_and_gate_holds_1pct(torch, ct
         _, ye = T.tril_st_targets(ke, y0e, tab, eps)
         mean, sd = net.predict(xe)
         pred = (y0e * (torch.exp(mean.double()) - eps)).clamp(min=0)
-        res = inst.surrogate(ctx, net, T.sur_params(eps=eps, gate=0.01))
-        never = inst.surrogate(ctx, net, T.sur_params(eps=eps, gate=1e30))
+        res = inst.surrogate(ctx, net, T.sur_params(eps=eps, gate=0.01, per_pair=True))
+        never = inst.surrogate(ctx, net, T.sur_params(eps=eps, gate=1e30, per_pair=True))
     finally:
         net.close()
     l1_base = float((kappa * y0e - ye).abs().sum() / ye.sum())
@@ -95,3 +95,32 @@ def test_trained_ensemble_beats_bin_level_estimate_and_gate_holds_1pct(torch, ct
     assert never["n_gated"] == 0 and res["n_gated"] > 0
     assert l1_net < 0.5 * l1_base
     assert err_gated <= 0.01
+
+
+def test_budget_gate_with_same_shape_training(torch, ctx):
+    """Trained on head-on instances of the same shape (seeds 2000 + m), the ensemble's
+    spread is a fair error estimate: the budget gate (largest uncertainty contributions
+    exact until the spread of the rest is within 1% of the total) holds the total within
+    1% while most bin pairs stay with the network."""
+    eps = 1e-3
+    insts = [surrogate.Instance(beams.st_headon(N_MP, seed=2000 + m)) for m in range(4)]
+    x, t, y0, y = surrogate.training_rows(ctx, insts, eps=eps)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    keep = (y > 0) | (torch.rand(y.shape[0], device="cuda", generator=g) < 0.25)
+    net = T.Mlp(4, seed=12)
+    try:
+        surrogate.train(net, x[keep].contiguous(), t[keep].contiguous(), n_steps=1500, batch=8192,
+                        lr=1e-3)
+        scale = surrogate.yield_scale(net, x, y0, y, eps)
+        inst = surrogate.Instance(beams.st_headon(N_MP))
+        _, exact_total = inst.exact(ctx)
+        res = inst.surrogate(ctx, net, T.sur_params(eps=eps, gate=0.01, scale=scale))
+    finally:
+        net.close()
+    err = abs(res["total"] - exact_total) / exact_total
+    print(f"\nbudget gate: error {err:.5f}, {res['n_gated']} of {res['n_bin_pairs']} pairs exact, "
+          f"predicted spread {res['predicted_spread']:.4f}")
+    assert res["predicted_spread"] <= 0.01
+    assert err <= 0.01
+    assert res["n_gated"] < 0.2 * res["n_bin_pairs"]
