@@ -1,7 +1,7 @@
 // Onesweep LSD radix sort of (key, value) pairs for gfx950.
 //
 // One histogram pass counts all 8-bit digits of every pass at once; then each pass
-// is a single kernel in which a tile of 2048 keys
+// is a single kernel in which a tile of 4096 keys
 //   1. ranks its keys per digit with a wave-level multi-split (eight 64-lane ballots
 //      give each lane the mask of lanes holding the same digit),
 //   2. publishes its per-digit counts and resolves the counts of all earlier tiles by
@@ -21,8 +21,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kItems = 8;
-constexpr int kTile = kBlock * kItems;  // 2048 keys per tile
+constexpr int kItems = 16;
+constexpr int kTile = kBlock * kItems;  // 4096 keys per tile
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagInc = 2u << 30;
 constexpr uint32_t kValMask = (1u << 30) - 1u;
