@@ -85,5 +85,16 @@ def loss_and_grad(p, x, y, mu_x, sd_x, mu_y, sd_y, H: int, bf16_points: bool = F
     return loss, g
 
 
+def forward(p, x, mu_x, sd_x, H: int, bf16_points: bool = False) -> np.ndarray:
+    """Standardised network output per row (same rounding points as loss_and_grad)."""
+    r = bf16 if bf16_points else (lambda a: np.asarray(a, dtype=np.float64))
+    W1, b1, W2, b2, W3, b3, W4, b4 = unpack(p, H, len(mu_x))
+    X = r((np.asarray(x, np.float64) - mu_x) / sd_x)
+    H1 = r(_silu(X @ r(W1).T + b1))
+    H2 = r(_silu(H1 @ r(W2).T + b2))
+    H3 = r(_silu(H2 @ r(W3).T + b3))
+    return H3 @ r(W4) + b4[0]
+
+
 def loss_only(p, x, y, mu_x, sd_x, mu_y, sd_y, H: int) -> float:
     return loss_and_grad(p, x, y, mu_x, sd_x, mu_y, sd_y, H)[0]

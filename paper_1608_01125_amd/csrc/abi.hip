@@ -1513,14 +1513,12 @@ int tril_mlp_predict(tril_mlp *p, const float *x, int64_t n, float *mean, float 
     if (!p || n < 0 || (n > 0 && (!x || !mean || !sdev))) return TRIL_E_INVAL;
     if (n == 0) return TRIL_OK;
     MlpModel &m = p->m;
-    const int64_t chunk = std::min<int64_t>(n, (int64_t)1 << 16);
-    CHK(mlp_scratch(&m, chunk));
+    const int64_t chunk = std::min<int64_t>(n, (int64_t)1 << 20);
     float *outs = nullptr;
     CHK(dev_alloc(&outs, (size_t)(m.K * chunk)));
     for (int64_t a = 0; a < n; a += chunk) {
         const int64_t c = std::min(chunk, n - a);
-        mlp_input(&m, x + a * kMlpIn, nullptr, c);
-        for (int k = 0; k < m.K; ++k) mlp_forward(&m, k, c, outs + (int64_t)k * c);
+        for (int k = 0; k < m.K; ++k) mlp_fused_forward(&m, k, x + a * kMlpIn, c, outs + (int64_t)k * c);
         mlp_reduce(&m, outs, c, mean + a, sdev + a);
     }
     hipError_t e = hipGetLastError();

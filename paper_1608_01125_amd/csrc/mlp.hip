@@ -34,6 +34,23 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(
 
 __device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
 
+// Inference-only SiLU from the hardware exponential and reciprocal (about 1 ulp of FP32
+// each); its result is rounded to BF16 (8 significant bits) right after.
+__device__ __forceinline__ float silu_fast(float z) {
+    return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
+
+// Parameter offsets of one member in its flat FP32 vector (W row-major [out][in]).
+constexpr int64_t kOffW1 = 0;
+constexpr int64_t kOffB1 = kOffW1 + (int64_t)kMlpHidden * kMlpIn;
+constexpr int64_t kOffW2 = kOffB1 + kMlpHidden;
+constexpr int64_t kOffB2 = kOffW2 + (int64_t)kMlpHidden * kMlpHidden;
+constexpr int64_t kOffW3 = kOffB2 + kMlpHidden;
+constexpr int64_t kOffB3 = kOffW3 + (int64_t)kMlpHidden * kMlpHidden;
+constexpr int64_t kOffW4 = kOffB3 + kMlpHidden;
+constexpr int64_t kOffB4 = kOffW4 + kMlpHidden;
+static_assert(kOffB4 + 1 == kMlpParams, "parameter count");
+
 constexpr int kTM = 64, kTN = 64, kTK = 32, kLdsK = kTK + 8;
 
 enum : int { kEpiBias = 1, kEpiSilu = 2, kEpiDSilu = 4 };
@@ -236,6 +253,97 @@ __global__ void k_mlp_reduce(const float *__restrict__ out, int64_t n, int K, fl
     sdev[i] = K > 1 ? sqrtf(fmaxf(s2 / (float)K - mu * mu, 0.0f) * (float)K / (float)(K - 1)) : 0.0f;
 }
 
+// Inference of one member, all four layers in one kernel: a workgroup takes 128 rows; the
+// standardised input (rounded to BF16) and layer 1 (K = 6) run on the vector units; the
+// 128 x 256 hidden activations stay in LDS as BF16; layers 2 and 3 run on the matrix cores
+// (each wave 64 output columns for all 128 rows: 8 x 4 tiles of 16 x 16, weight fragments
+// read once per k step from L2 and reused over the 8 row tiles), their results held in
+// registers until every wave has read the old activations, then written back in place;
+// layer 4 is a dot product per row. Same rounding points as the layer-by-layer path; the
+// activation uses the hardware exponential and reciprocal.
+constexpr int kFR = 128;                 // rows per workgroup
+constexpr int kHL = kMlpHidden + 8;      // LDS row stride (BF16 elements), padded
+
+__global__ void __launch_bounds__(256, 2) k_mlp_fused(const float *__restrict__ x, int64_t n,
+                                                      const float *__restrict__ norm,
+                                                      const uint16_t *__restrict__ wb,
+                                                      const float *__restrict__ w,
+                                                      float *__restrict__ out) {
+    __shared__ __align__(16) uint16_t sH[kFR][kHL];
+    __shared__ float sX[kFR][kMlpIn];
+    const int64_t r0 = blockIdx.x * (int64_t)kFR;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < kFR * kMlpIn; i += 256) {
+        const int r = i / kMlpIn, c = i - r * kMlpIn;
+        float v = 0.0f;
+        if (r0 + r < n) v = from_bf16(to_bf16((x[(r0 + r) * kMlpIn + c] - norm[c]) / norm[kMlpIn + c]));
+        sX[r][c] = v;
+    }
+    __syncthreads();
+    {   // layer 1: thread = output column
+        const int j = tid;
+        float wj[kMlpIn];
+#pragma unroll
+        for (int c = 0; c < kMlpIn; ++c) wj[c] = from_bf16(wb[kOffW1 + j * kMlpIn + c]);
+        const float bj = w[kOffB1 + j];
+        for (int r = 0; r < kFR; ++r) {
+            float z = 0.0f;
+#pragma unroll
+            for (int c = 0; c < kMlpIn; ++c) z += sX[r][c] * wj[c];
+            z += bj;
+            sH[r][j] = to_bf16(silu_fast(z));
+        }
+    }
+    __syncthreads();
+    const int nb = wave * 64;
+#pragma unroll 1
+    for (int layer = 0; layer < 2; ++layer) {
+        const uint16_t *W = wb + (layer == 0 ? kOffW2 : kOffW3);
+        const float *bias = w + (layer == 0 ? kOffB2 : kOffB3);
+        f32x4 acc[8][4];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < kMlpHidden; k0 += 32) {
+            bf16x8 bfr[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int ncol = nb + j * 16 + (lane & 15);
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)ncol * kMlpHidden + k0 + 8 * (lane >> 4));
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sH[i * 16 + (lane & 15)][k0 + 8 * (lane >> 4)]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wave has read the previous activations
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = i * 16 + 4 * (lane >> 4) + r;
+                    const int col = nb + j * 16 + (lane & 15);
+                    const float z = acc[i][j][r] + bias[col];
+                    sH[row][col] = to_bf16(silu_fast(z));
+                }
+        __syncthreads();
+    }
+    {   // layer 4: two threads per row
+        const int row = tid >> 1, half = tid & 1;
+        float s = 0.0f;
+        for (int c = half * 128; c < half * 128 + 128; ++c)
+            s += from_bf16(sH[row][c]) * from_bf16(wb[kOffW4 + c]);
+        s += __shfl_xor(s, 1);
+        if (half == 0 && r0 + row < n) out[r0 + row] = s + w[kOffB4];
+    }
+}
+
 // Minibatch rows of member k at a training step: a counter-based hash of (seed, k,
 // step, i) reduced to [0, n) (rows drawn with replacement).
 __global__ void k_batch_idx(uint64_t seed, int k, int64_t step, int64_t n, int64_t batch,
@@ -277,6 +385,13 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
+void mlp_fused_forward(MlpModel *m, int k, const float *x, int64_t n, float *out) {
+    if (n <= 0) return;
+    const int64_t o = (int64_t)k * kMlpParams;
+    hipLaunchKernelGGL(k_mlp_fused, dim3(blocks(n, kFR)), dim3(256), 0, m->st, x, n, m->norm,
+                       m->wb + o, m->w + o, out);
+}
+
 void mlp_batch_idx(MlpModel *m, uint64_t seed, int k, int64_t step, int64_t n, int64_t batch) {
     hipLaunchKernelGGL(k_batch_idx, dim3(blocks(batch, 256)), dim3(256), 0, m->st, seed, k, step, n,
                        batch, m->idx);
@@ -297,21 +412,6 @@ void mlp_gemm(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, in
 }
 
 // ---------------------------------------------------------------------------- model
-
-namespace {
-
-// Parameter offsets of one member in its flat FP32 vector (W row-major [out][in]).
-constexpr int64_t kOffW1 = 0;
-constexpr int64_t kOffB1 = kOffW1 + (int64_t)kMlpHidden * kMlpIn;
-constexpr int64_t kOffW2 = kOffB1 + kMlpHidden;
-constexpr int64_t kOffB2 = kOffW2 + (int64_t)kMlpHidden * kMlpHidden;
-constexpr int64_t kOffW3 = kOffB2 + kMlpHidden;
-constexpr int64_t kOffB3 = kOffW3 + (int64_t)kMlpHidden * kMlpHidden;
-constexpr int64_t kOffW4 = kOffB3 + kMlpHidden;
-constexpr int64_t kOffB4 = kOffW4 + kMlpHidden;
-static_assert(kOffB4 + 1 == kMlpParams, "parameter count");
-
-}  // namespace
 
 MlpModel::~MlpModel() {
     for (void *p : allocs) (void)hipFree(p);

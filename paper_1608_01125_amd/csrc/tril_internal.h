@@ -238,6 +238,7 @@ int mlp_init(MlpModel *m, int K, uint64_t seed, hipStream_t st);
 int mlp_scratch(MlpModel *m, int64_t rows);
 void mlp_input(MlpModel *m, const float *x, const int32_t *idx, int64_t n);
 void mlp_forward(MlpModel *m, int k, int64_t n, float *yhat_out);
+void mlp_fused_forward(MlpModel *m, int k, const float *x, int64_t n, float *out);
 void mlp_loss(MlpModel *m, const float *y, const int32_t *idx, int64_t n);
 void mlp_backward(MlpModel *m, int k, int64_t n);
 void mlp_adam(MlpModel *m, int k, float lr, int64_t t);

@@ -110,3 +110,28 @@ def test_training_fits_a_smooth_function(torch):
     assert np.all(l1 < 0.05 * l0)
     assert rmse < 0.1 * float(np.std(yt))
     assert np.all(sd.cpu().numpy() >= 0)
+
+
+@pytest.mark.parametrize("n", [1, 127, 129, 5000])
+def test_predict_matches_reference(torch, n):
+    """Ensemble mean and spread of the de-standardised output against the CPU reference
+    with BF16 rounding emulated (all four layers fused in one kernel on the device)."""
+    x, y = _data(n, 7)
+    mu_x, sd_x = x.mean(0) if n > 1 else np.zeros(6, np.float32), (x.std(0) + 0.5 if n > 1 else np.ones(6, np.float32))
+    mu_y, sd_y = 0.3, 1.7
+    net = T.Mlp(3, seed=9)
+    try:
+        net.set_norm(mu_x, sd_x, mu_y, sd_y)
+        ps = [net.get_params(k) for k in range(3)]
+        mean, sd = net.predict(torch.from_numpy(x).cuda())
+    finally:
+        net.close()
+    mx = np.asarray(mu_x, np.float32).astype(np.float64)
+    sx = np.asarray(sd_x, np.float32).astype(np.float64)
+    outs = np.stack([M.forward(p.astype(np.float64), x.astype(np.float64), mx, sx, H, bf16_points=True)
+                     for p in ps]) * np.float32(sd_y) + np.float32(mu_y)
+    ref_mean = outs.mean(0)
+    ref_sd = outs.std(0, ddof=1)
+    scale = np.abs(outs).max() + 1e-6
+    assert np.max(np.abs(mean.cpu().numpy() - ref_mean)) <= 2e-3 * scale
+    assert np.max(np.abs(sd.cpu().numpy() - ref_sd)) <= 2e-3 * scale

@@ -41,3 +41,10 @@ def test_bf16_rounding():
     x = np.random.default_rng(0).normal(size=1000)
     r = M.bf16(x)
     assert np.all(np.abs(r - x) <= np.abs(x) * 2.0 ** -8)
+
+
+def test_forward_matches_loss_path():
+    p, x, y, mx, sx, my, sy = _setup(5, 17, 4)
+    out = M.forward(p, x, mx, sx, 5)
+    t = (y - my) / sy
+    assert M.loss_only(p, x, y, mx, sx, my, sy, 5) == pytest.approx(float(np.mean((out - t) ** 2)))
