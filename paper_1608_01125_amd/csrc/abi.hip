@@ -70,7 +70,7 @@ int comb_key_bits(int64_t n_comb) { return 30 + bits_for((uint64_t)(n_comb > 1 ?
 
 constexpr int64_t kMaxN = (int64_t)1 << 30;       // node ids 2n-1 fit int32, sort counts fit 30 bits
 constexpr int64_t kMaxComb = (int64_t)1 << 24;    // combined instances (steps x instances) per launch
-constexpr int64_t kBatchBudget = (int64_t)1 << 24;  // default virtual elements per launch
+constexpr int64_t kBatchBudget = (int64_t)1 << 26;  // default virtual elements per launch
 
 }  // namespace
 
@@ -118,7 +118,7 @@ struct tril_ctx {
     DevCounters *h_cnt = nullptr;   // pinned host mirror
 
     // target (hierarchy) state; capacities count virtual elements (steps x rows)
-    int64_t t_cap = 0;
+    int64_t t_cap = 0, t_row_cap = 0;  // virtual elements (steps x rows), rows
     int64_t t_comb_cap = 0;
     int32_t t_off_cap = 0;
     int64_t nt = 0;                 // rows of the last target beam
@@ -137,9 +137,13 @@ struct tril_ctx {
     int32_t *split_right = nullptr, *nflags = nullptr;
     Node *nodes = nullptr;
     int32_t *inst_root = nullptr, *inst_stop = nullptr;
+    int32_t *inst_base = nullptr;          // instance roots of the shared tree shape
+    int32_t *refit_slots = nullptr;        // refit hand-offs to the crossing-level kernel
+    int64_t refit_slot_cap = 0;
+    int64_t n_int = -1;                    // internal nodes of the last build (all steps)
 
     // query state
-    int64_t q_cap = 0;
+    int64_t q_cap = 0, q_row_cap = 0;
     int64_t q_comb_cap = 0;
     int32_t q_off_cap = 0;
     int64_t *d_q_off = nullptr;
@@ -206,35 +210,56 @@ int ensure_sort_scratch(tril_ctx *c, int64_t n) {
 }
 
 void free_target(tril_ctx *c) {
-    dev_free(c->t_box); dev_free(c->t_spart); dev_free(c->t_k32a); dev_free(c->t_k32b);
-    dev_free(c->t_k64a); dev_free(c->t_k64b); dev_free(c->t_va); dev_free(c->t_vb);
-    dev_free(c->prec); dev_free(c->split_right); dev_free(c->nflags); dev_free(c->nodes);
+    dev_free(c->t_box); dev_free(c->nflags); dev_free(c->nodes); dev_free(c->refit_slots);
     c->t_cap = 0;
+    c->refit_slot_cap = 0;
 }
 
-int ensure_target(tril_ctx *c, int64_t nv, int64_t n_comb, int32_t n_inst) {
+void free_target_rows(tril_ctx *c) {
+    dev_free(c->t_spart); dev_free(c->t_k32a); dev_free(c->t_k32b);
+    dev_free(c->t_k64a); dev_free(c->t_k64b); dev_free(c->t_va); dev_free(c->t_vb);
+    dev_free(c->prec); dev_free(c->split_right);
+    c->t_row_cap = 0;
+}
+
+// Target buffers for launches of up to nv virtual elements over n rows: boxes, nodes
+// and arrival flags per element; keys, sort values and the tree shape per row.
+int ensure_target(tril_ctx *c, int64_t nv, int64_t n, int64_t n_comb, int32_t n_inst) {
     if (nv > c->t_cap) {
         ++c->alloc_gen;
         free_target(c);
         c->built = false;
         const int64_t m = std::max<int64_t>(nv, 1);
         CHK(dev_alloc(&c->t_box, m));
+        CHK(dev_alloc(&c->nflags, m));
+        CHK(dev_alloc(&c->nodes, 2 * m));
+        // a launch of m' steps over n' > 512 rows has m' ceil(n' / 512) <= nv / 256 chunks
+        // (fewer rows need no hand-offs), 64 slots each
+        c->refit_slot_cap = m / 4 + 64;
+        CHK(dev_alloc(&c->refit_slots, (size_t)c->refit_slot_cap));
+        c->t_cap = m;
+    }
+    if (n > c->t_row_cap) {
+        ++c->alloc_gen;
+        free_target_rows(c);
+        c->built = false;
+        const int64_t m = std::max<int64_t>(n, 1);
         CHK(dev_alloc(&c->t_spart, (size_t)stats_partials_needed(m)));
         CHK(dev_alloc(&c->t_k32a, m)); CHK(dev_alloc(&c->t_k32b, m));
         CHK(dev_alloc(&c->t_k64a, m)); CHK(dev_alloc(&c->t_k64b, m));
         CHK(dev_alloc(&c->t_va, m)); CHK(dev_alloc(&c->t_vb, m));
         CHK(dev_alloc(&c->prec, 2 * m));
-        CHK(dev_alloc(&c->split_right, m)); CHK(dev_alloc(&c->nflags, m));
-        CHK(dev_alloc(&c->nodes, 2 * m));
-        c->t_cap = m;
+        CHK(dev_alloc(&c->split_right, m));
+        c->t_row_cap = m;
     }
     if (n_comb > c->t_comb_cap) {
         ++c->alloc_gen;
-        dev_free(c->inst_root); dev_free(c->inst_stop);
+        dev_free(c->inst_root); dev_free(c->inst_stop); dev_free(c->inst_base);
         c->t_comb_cap = 0;
         c->built = false;
         CHK(dev_alloc(&c->inst_root, (size_t)n_comb));
         CHK(dev_alloc(&c->inst_stop, (size_t)n_comb));
+        CHK(dev_alloc(&c->inst_base, (size_t)n_comb));
         c->t_comb_cap = n_comb;
     }
     if (n_inst > c->t_off_cap) {
@@ -246,26 +271,34 @@ int ensure_target(tril_ctx *c, int64_t nv, int64_t n_comb, int32_t n_inst) {
         c->t_off_cap = n_inst;
         c->h_t_off.clear();
     }
-    return ensure_sort_scratch(c, nv);
+    return ensure_sort_scratch(c, n);
 }
 
-int ensure_query(tril_ctx *c, int64_t nv, int64_t n_comb, int32_t n_inst) {
+// Query buffers: boxes per virtual element (nv), keys and orders per row (n).
+int ensure_query(tril_ctx *c, int64_t nv, int64_t n, int64_t n_comb, int32_t n_inst) {
     if (nv > c->q_cap) {
         ++c->alloc_gen;
-        dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
-        dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
-        dev_free(c->q_keep);
+        dev_free(c->q_box);
         c->q_cap = 0;
-        c->q_order = nullptr;
-        c->q_order_key = nullptr;
         const int64_t m = std::max<int64_t>(nv, 1);
         CHK(dev_alloc(&c->q_box, m));
+        c->q_cap = m;
+    }
+    if (n > c->q_row_cap) {
+        ++c->alloc_gen;
+        dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
+        dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
+        dev_free(c->q_keep);
+        c->q_row_cap = 0;
+        c->q_order = nullptr;
+        c->q_order_key = nullptr;
+        const int64_t m = std::max<int64_t>(n, 1);
         CHK(dev_alloc(&c->q_spart, (size_t)stats_partials_needed(m)));
         CHK(dev_alloc(&c->q_keep, m));
         CHK(dev_alloc(&c->q_k32a, m)); CHK(dev_alloc(&c->q_k32b, m));
         CHK(dev_alloc(&c->q_k64a, m)); CHK(dev_alloc(&c->q_k64b, m));
         CHK(dev_alloc(&c->q_va, m)); CHK(dev_alloc(&c->q_vb, m));
-        c->q_cap = m;
+        c->q_row_cap = m;
     }
     if (n_comb > c->q_comb_cap) c->q_comb_cap = n_comb;
     if (n_inst > c->q_off_cap) {
@@ -287,7 +320,7 @@ int ensure_query(tril_ctx *c, int64_t nv, int64_t n_comb, int32_t n_inst) {
         CHK(dev_alloc(&c->cand_j, cap));
         c->cand_cap = cap;
     }
-    return ensure_sort_scratch(c, nv);
+    return ensure_sort_scratch(c, n);
 }
 
 int check_beam(const tril_beam *b) {
@@ -379,8 +412,8 @@ int enqueue_order(tril_ctx *c, const BeamDev &b, bool query_side, WorkBeam &w, h
     unsigned long long *k64a = query_side ? c->q_k64a : c->t_k64a;
     unsigned long long *k64b = query_side ? c->q_k64b : c->t_k64b;
     uint32_t *va = query_side ? c->q_va : c->t_va, *vb = query_side ? c->q_vb : c->t_vb;
-    launch_boxes_keys(b, false, c->cloud, c->dt, c->sigma_up, stats, stats, kl, box, k32a, k64a, va,
-                      c->d_cnt, st);
+    launch_boxes_keys(b, false, c->cloud, c->dt, c->sigma_up, stats, stats, kl, 0, box, k32a, k64a,
+                      va, c->d_cnt, st);
     const uint32_t *rows;
     if (!kl.wide)
         rows = radix_sort_u32(k32a, va, k32b, vb, b.n, kl.key_bits, c->ss, &c->d_cnt->err, st)
@@ -411,62 +444,64 @@ int timing_pair(tril_ctx *c, hipStream_t st, std::vector<std::array<int, 2>> &ds
     return TRIL_OK;
 }
 
+// Step offset within a batch of m steps whose Morton order shapes the batch's trees
+// (the middle one: no step of the batch is more than m/2 steps from it).
+inline int32_t key_step(int32_t m) { return m > 0 ? (m - 1) / 2 : 0; }
+
 // Kernels of one build on stream st (target view, with its step count m, in c->tgt;
-// the target statistics c->t_stats are current).
+// the target statistics c->t_stats are current): boxes of every step, one sort of the
+// rows by their Morton codes at the batch's key step, the tree shape emitted from that
+// order, and its m per-step copies filled with each step's boxes.
 int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
     const BeamDev &t = c->tgt;
-    const int64_t nv = (int64_t)t.m * t.n;
-    const int32_t n_comb = t.m * t.n_inst;
-    const KeyLayout kl = key_layout(n_comb, c->morton_bits);
+    const int64_t n = t.n;
+    const KeyLayout kl = key_layout(t.n_inst, c->morton_bits);
     if (timed) CHK(timing_pair(c, st, c->ev_build, true));
     launch_prologue(c->d_cnt, 0, t.m, st);
-    launch_boxes_keys(t, false, c->cloud, c->dt, c->sigma_up, c->t_stats, c->t_stats, kl, c->t_box,
-                      c->t_k32a,
-                      c->t_k64a, c->t_va, c->d_cnt, st);
+    launch_boxes_keys(t, false, c->cloud, c->dt, c->sigma_up, c->t_stats, c->t_stats, kl,
+                      key_step(t.m), c->t_box, c->t_k32a, c->t_k64a, c->t_va, c->d_cnt, st);
     const uint32_t *rows = nullptr;
-    int32_t *roots = n_comb > 1 ? c->inst_root : nullptr;
+    int32_t *roots = t.n_inst > 1 ? c->inst_base : nullptr;
     if (!kl.wide) {
-        const bool alt = radix_sort_u32(c->t_k32a, c->t_va, c->t_k32b, c->t_vb, nv, kl.key_bits,
+        const bool alt = radix_sort_u32(c->t_k32a, c->t_va, c->t_k32b, c->t_vb, n, kl.key_bits,
                                         c->ss, &c->d_cnt->err, st);
         const uint32_t *keys = alt ? c->t_k32b : c->t_k32a;
         rows = alt ? c->t_vb : c->t_va;
-        launch_karras_u32(keys, nv, kl.prefix_shift, c->prec, c->split_right, c->nflags, roots, st);
+        launch_karras_u32(keys, n, kl.prefix_shift, c->prec, c->split_right, roots, st);
     } else {
-        const bool alt = radix_sort_u64(c->t_k64a, c->t_va, c->t_k64b, c->t_vb, nv, kl.key_bits,
+        const bool alt = radix_sort_u64(c->t_k64a, c->t_va, c->t_k64b, c->t_vb, n, kl.key_bits,
                                         c->ss, &c->d_cnt->err, st);
         const unsigned long long *keys = alt ? c->t_k64b : c->t_k64a;
         rows = alt ? c->t_vb : c->t_va;
-        launch_karras_u64(keys, nv, kl.prefix_shift, c->prec, c->split_right, c->nflags, roots, st);
+        launch_karras_u64(keys, n, kl.prefix_shift, c->prec, c->split_right, roots, st);
     }
     c->t_rows = rows;
-    launch_inst_roots(t, n_comb == 1, c->split_right, c->inst_root, c->inst_stop, st);
-    launch_refit(c->t_box, rows, nv, c->prec, c->split_right, c->nflags, c->nodes, &c->d_cnt->err, st);
+    c->n_int = n > 0 ? (int64_t)t.m * (n - 1) : -1;
+    launch_inst_roots(t, c->inst_base, c->split_right, c->inst_root, c->inst_stop, st);
+    launch_refit(c->t_box, rows, n, t.m, c->prec, c->split_right, c->nflags, c->nodes,
+                 c->refit_slots, c->refit_slot_cap, &c->d_cnt->err, st);
     if (timed) CHK(timing_pair(c, st, c->ev_build, false));
     HIPCHK(hipGetLastError());
     return TRIL_OK;
 }
 
-// Kernels of one collide (query view q with the same step count as the target; the
-// query statistics c->q_stats are current). Without sorting, the query order kept in
-// c->q_keep (one step's order, repeated per step) is used.
-// Query boxes and, when sort_queries, their Morton order (c->q_order).
+// Query boxes of every step of the view and, when sort_queries, the order of its rows
+// by their Morton codes at the batch's key step (c->q_order, q.n entries: the traversal
+// repeats it for every step).
 int enqueue_query_prep(tril_ctx *c, const BeamDev &q, hipStream_t st, bool sort_queries) {
-    const int64_t nv = (int64_t)q.m * q.n;
-    const int32_t n_comb = q.m * q.n_inst;
-    const KeyLayout kl = key_layout(n_comb, c->morton_bits);
-    launch_boxes_keys(q, true, c->cloud, c->dt, c->sigma_up, c->t_stats, c->q_stats, kl, c->q_box,
-                      c->q_k32a,
-                      c->q_k64a, c->q_va, c->d_cnt, st);
-    if (sort_queries && nv > 0) {
+    const KeyLayout kl = key_layout(q.n_inst, c->morton_bits);
+    launch_boxes_keys(q, true, c->cloud, c->dt, c->sigma_up, c->t_stats, c->q_stats, kl,
+                      key_step(q.m), c->q_box, c->q_k32a, c->q_k64a, c->q_va, c->d_cnt, st);
+    if (sort_queries && q.n > 0 && q.m > 0) {
         bool alt;
         if (!kl.wide)
-            alt = radix_sort_u32(c->q_k32a, c->q_va, c->q_k32b, c->q_vb, nv, kl.key_bits, c->ss,
+            alt = radix_sort_u32(c->q_k32a, c->q_va, c->q_k32b, c->q_vb, q.n, kl.key_bits, c->ss,
                                  &c->d_cnt->err, st);
         else
-            alt = radix_sort_u64(c->q_k64a, c->q_va, c->q_k64b, c->q_vb, nv, kl.key_bits, c->ss,
+            alt = radix_sort_u64(c->q_k64a, c->q_va, c->q_k64b, c->q_vb, q.n, kl.key_bits, c->ss,
                                  &c->d_cnt->err, st);
-        c->q_order = (nv <= 1) ? c->q_va : (alt ? c->q_vb : c->q_va);
-        c->q_order_len = nv;
+        c->q_order = (q.n <= 1) ? c->q_va : (alt ? c->q_vb : c->q_va);
+        c->q_order_len = q.n;
     }
     return TRIL_OK;
 }
@@ -479,8 +514,7 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
     CHK(enqueue_query_prep(c, q, st, sort_queries));
     if (timed) CHK(timing_pair(c, st, c->ev_prep, false));
     if (timed) CHK(timing_pair(c, st, c->ev_trav, true));
-    const int64_t ntv = (int64_t)c->tgt.m * c->tgt.n;
-    launch_traverse(c->nodes, ntv, c->q_box, c->q_order, c->q_order_len, nv, q.n, c->inst_root,
+    launch_traverse(c->nodes, c->n_int, c->q_box, c->q_order, c->q_order_len, nv, q.n, c->inst_root,
                     c->inst_stop, c->cand_i, c->cand_j, c->cand_cap, c->d_cnt, c->block, st);
     if (timed) CHK(timing_pair(c, st, c->ev_trav, false));
     if (timed) CHK(timing_pair(c, st, c->ev_narrow, true));
@@ -564,17 +598,17 @@ void fold_events(tril_ctx *c) {
     c->ev_next = 0;
 }
 
-// Steps per launch for tril_run: the parameter if set, else as many as keep the
-// virtual element count of one launch within kBatchBudget.
 // Morton bits for the batches of tril_run (both beams already in full-precision Morton
-// order): the parameter if set, else as many as keep prefix + Morton bits within three
-// 8-bit radix passes, between 18 and 30.
-int run_morton_bits(const tril_ctx *c, int64_t n_comb) {
+// order): the parameter if set, else as many as keep instance prefix + Morton bits
+// within three 8-bit radix passes, between 18 and 30.
+int run_morton_bits(const tril_ctx *c, int64_t n_inst) {
     if (c->morton_param > 0) return c->morton_param;
-    const int p = bits_for((uint64_t)(n_comb > 1 ? n_comb - 1 : 0));
+    const int p = bits_for((uint64_t)(n_inst > 1 ? n_inst - 1 : 0));
     return std::min(30, std::max(18, 24 - p));
 }
 
+// Steps per launch for tril_run: the parameter if set, else as many as keep the
+// virtual element count of one launch within kBatchBudget.
 int32_t pick_batch(const tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t n_steps) {
     const int64_t rows = std::max<int64_t>(std::max(t->n, q->n), 1);
     int64_t m = c->step_batch > 0 ? c->step_batch : std::max<int64_t>(1, kBatchBudget / rows);
@@ -697,7 +731,7 @@ int tril_build(tril_ctx *c, const tril_beam *b, int32_t step) {
     if (!c || step < 0) return TRIL_E_INVAL;
     CHK(check_beam(b));
     c->morton_bits = c->morton_param > 0 ? c->morton_param : 30;
-    CHK(ensure_target(c, b->n, b->n_inst, b->n_inst));
+    CHK(ensure_target(c, b->n, b->n, b->n_inst, b->n_inst));
     CHK(upload_offsets(c, b, c->d_t_off, c->h_t_off));
     c->nt = b->n;
     c->tgt = view(b, c->d_t_off, 1);
@@ -718,7 +752,7 @@ int tril_collide(tril_ctx *c, const tril_beam *q, int32_t step, tril_pairs *out)
     if (!c->built || c->tgt.m != 1 || step != c->built_step || q->n_inst != c->tgt.n_inst)
         return TRIL_E_STATE;
     c->morton_bits = c->morton_param > 0 ? c->morton_param : 30;
-    CHK(ensure_query(c, q->n, q->n_inst, q->n_inst));
+    CHK(ensure_query(c, q->n, q->n, q->n_inst, q->n_inst));
     CHK(upload_offsets(c, q, c->d_q_off, c->h_q_off));
     const BeamDev qv = view(q, c->d_q_off, 1);
     const bool sort = need_query_sort(c, q);
@@ -741,8 +775,8 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     if ((int64_t)k0 + n_steps - 1 > INT32_MAX) return TRIL_E_INVAL;
     const int32_t m = pick_batch(c, t, q, n_steps);
     // capacities for the largest batch first, so that nothing is reallocated later
-    CHK(ensure_target(c, (int64_t)m * t->n, (int64_t)m * t->n_inst, t->n_inst));
-    CHK(ensure_query(c, (int64_t)m * q->n, (int64_t)m * q->n_inst, q->n_inst));
+    CHK(ensure_target(c, (int64_t)m * t->n, t->n, (int64_t)m * t->n_inst, t->n_inst));
+    CHK(ensure_query(c, (int64_t)m * q->n, q->n, (int64_t)m * q->n_inst, q->n_inst));
     CHK(ensure_work(c, c->wt, t->n));
     CHK(ensure_work(c, c->wq, q->n));
     CHK(upload_offsets(c, t, c->d_t_off, c->h_t_off));
@@ -760,7 +794,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     launch_set_step(c->d_cnt, k0, c->st);
     CHK(enqueue_order(c, t1, false, c->wt[0], c->st));
     CHK(enqueue_order(c, q1, true, c->wq[0], c->st));
-    c->morton_bits = run_morton_bits(c, (int64_t)m * t->n_inst);
+    c->morton_bits = run_morton_bits(c, t->n_inst);
     const bool once = (c->flags & TRIL_SORT_QUERIES_ONCE) != 0;
     bool q_sorted = false;
     const bool timed = (c->flags & TRIL_TIMING) != 0;
@@ -985,8 +1019,8 @@ int st_run(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_t n_t_b
     if (!c->st_slots) CHK(dev_alloc(&c->st_slots, (size_t)kCounterSlots));
     launch_st_clear(keys, vals, cap, c->st_slots, c->st);
     const int32_t m = n_steps > 0 ? pick_batch(c, t, q, n_steps) : 1;
-    CHK(ensure_target(c, (int64_t)m * t->n, (int64_t)m * t->n_inst, t->n_inst));
-    CHK(ensure_query(c, (int64_t)m * q->n, (int64_t)m * q->n_inst, q->n_inst));
+    CHK(ensure_target(c, (int64_t)m * t->n, t->n, (int64_t)m * t->n_inst, t->n_inst));
+    CHK(ensure_query(c, (int64_t)m * q->n, q->n, (int64_t)m * q->n_inst, q->n_inst));
     CHK(upload_offsets(c, t, c->d_t_off, c->h_t_off));
     CHK(upload_offsets(c, q, c->d_q_off, c->h_q_off));
     c->nt = t->n;
@@ -1007,8 +1041,8 @@ int st_run(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_t n_t_b
         launch_prologue(c->d_cnt, 1, mb, c->st);
         if ((rc = enqueue_query_prep(c, qv, c->st, true)) != TRIL_OK) break;
         const int64_t nqv = (int64_t)mb * q->n;
-        launch_st_traverse(c->nodes, (int64_t)mb * t->n, c->q_box, nqv > 0 ? c->q_order : nullptr,
-                           nqv, c->inst_root, c->inst_stop, qv, c->tgt, q_bins, t_bins, n_t_bins,
+        launch_st_traverse(c->nodes, c->n_int, c->q_box, nqv > 0 ? c->q_order : nullptr,
+                           c->q_order_len, nqv, q->n, c->inst_root, c->inst_stop, qv, c->tgt, q_bins, t_bins, n_t_bins,
                            c->dt, sc, geometric, filter, filter_cap, keys, vals, cap, c->st_slots,
                            c->d_cnt, c->st);
         k += mb;
@@ -1604,8 +1638,8 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
         cleanup();
         return rc;
     }
-    for (int sb : {1, 2, 4, 8, 16, 32, 64}) {
-        if (sb == cur.step_batch || sb > n_probe || (int64_t)sb * rows > ((int64_t)1 << 26)) continue;
+    for (int sb : {1, 2, 4, 8, 16, 32, 64, 128}) {
+        if (sb == cur.step_batch || sb > n_probe || (int64_t)sb * rows > ((int64_t)1 << 27)) continue;
         double ms = 0.0;
         if ((rc = probe(cur.block_traverse, sb, cur.morton_bits, ms)) != TRIL_OK) break;
         if (ms < best_ms) {
@@ -1659,6 +1693,7 @@ void tril_destroy(tril_ctx *c) {
     for (hipGraphExec_t &g : c->gexec)
         if (g) (void)hipGraphExecDestroy(g);
     free_target(c);
+    free_target_rows(c);
     for (int p = 0; p < 2; ++p) {
         free_work(c->wt[p]);
         free_work(c->wq[p]);
@@ -1669,7 +1704,7 @@ void tril_destroy(tril_ctx *c) {
     dev_free(c->sg_key); dev_free(c->sg_val);
     dev_free(c->sf_x); dev_free(c->sf_mean); dev_free(c->sf_sd); dev_free(c->sf_y0);
     dev_free(c->sf_key); dev_free(c->se_key); dev_free(c->se_val);
-    dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->inst_root); dev_free(c->inst_stop);
+    dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->inst_root); dev_free(c->inst_stop); dev_free(c->inst_base);
     dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
     dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
     dev_free(c->q_keep); dev_free(c->d_q_off); dev_free(c->q_stats); dev_free(c->cand_i);
@@ -1804,8 +1839,7 @@ int tril_dbg_tree(tril_ctx *c, void *nodes, int64_t cap_nodes, int64_t *n_nodes,
     if (!c || !n_nodes) return TRIL_E_INVAL;
     if (!c->built) return TRIL_E_STATE;
     HIPCHK(hipStreamSynchronize(c->st));
-    const int64_t nv = (int64_t)c->tgt.m * c->tgt.n;
-    const int64_t nn = nv > 0 ? 2 * nv - 1 : 0;
+    const int64_t nn = c->tgt.n > 0 ? (int64_t)c->tgt.m * (2 * c->tgt.n - 1) : 0;
     *n_nodes = nn;
     if (nn > cap_nodes) return TRIL_E_OVERFLOW;
     if (nn > 0) {

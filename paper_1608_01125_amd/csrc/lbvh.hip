@@ -12,11 +12,18 @@
 // in depth-first order after its subtree, which lets the traversal run without
 // a stack.
 //
-// One launch may cover several consecutive time steps of a beam. Photon row i at
-// step offset s is the virtual element e = s n + i; it belongs to the combined
-// instance c = s n_inst + (instance of row i). Keys carry c above the Morton
-// bits, so every (step, instance) pair gets its own subtree with its own root, and
-// a query only descends the subtree of its own step and instance.
+// One launch may cover m consecutive time steps of a beam. Photon row i at step
+// offset s is the virtual element e = s n + i; it belongs to the combined instance
+// c = s n_inst + (instance of row i). The m steps share one tree shape: the rows are
+// ordered once, by the Morton codes of their boxes at one step of the batch (keys
+// carry the instance above the Morton bits, so each instance is a subtree of its
+// own), and the hierarchy emitted from that order is filled with each step's own
+// boxes. Any binary tree over a step's boxes with exact unions finds the same
+// overlapping leaves, so the shared order changes only how many nodes a query
+// visits, never the candidate set; over a few steps photons drift little against
+// each other and the order stays close to every step's own Morton order.
+// Node ids: step s owns internal nodes s (n-1) + x (x in [0, n-1)) and leaves
+// m (n-1) + s n + j (sorted position j); a leaf's link is its element s n + row.
 #include <cfloat>
 #include <cmath>
 
@@ -64,32 +71,6 @@ __device__ __forceinline__ int32_t find_inst(const int64_t *off, int32_t n_inst,
         if (off[mid] <= i) lo = mid; else hi = mid - 1;
     }
     return lo;
-}
-
-// Step offset, row, base instance and combined instance of virtual element e.
-struct VIdx {
-    int32_t s;
-    int64_t i;
-    int32_t mi;
-    int32_t c;
-};
-__device__ __forceinline__ VIdx vdecode(const BeamDev &b, int64_t e) {
-    VIdx v;
-    v.s = b.m > 1 ? (int32_t)(e / b.n) : 0;
-    v.i = e - (int64_t)v.s * b.n;
-    v.mi = b.n_inst > 1 ? find_inst(b.inst_off, b.n_inst, v.i) : 0;
-    v.c = v.s * b.n_inst + v.mi;
-    return v;
-}
-
-// First virtual element and count of combined instance c.
-__device__ __forceinline__ void comb_range(const BeamDev &b, int32_t c, int64_t &a, int64_t &cnt) {
-    const int32_t s = c / b.n_inst;
-    const int32_t mi = c - s * b.n_inst;
-    const int64_t o0 = b.n_inst > 1 ? b.inst_off[mi] : 0;
-    const int64_t o1 = b.n_inst > 1 ? b.inst_off[mi + 1] : b.n;
-    a = (int64_t)s * b.n + o0;
-    cnt = o1 - o0;
 }
 
 __device__ __forceinline__ uint32_t expand10(uint32_t v) {
@@ -308,13 +289,16 @@ __global__ void __launch_bounds__(256) k_fold_stats(const StatsPartial *__restri
 // tau = t_k + dt/2 >= 0, so [min x0 + tau min u, max x0 + tau max u] per axis contains
 // every centre (clamping absorbs rounding).
 // One thread per row, looping over the m steps of the launch: the row's photon data
-// is read once and its m boxes and keys are written at the virtual elements s n + i.
+// is read once and its m boxes are written at the virtual elements s n + i. The sort
+// key of row i (its instance above the Morton bits of its box at step offset
+// key_step) is written at i.
 template <bool kWide>
 __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, CloudBox cloud, double dt,
                                                     double sigma_up,
                                                     const InstStats *__restrict__ t_stats,
                                                     const InstStats *__restrict__ self_stats,
-                                                    KeyLayout kl, PBox *__restrict__ out,
+                                                    KeyLayout kl, int32_t key_step,
+                                                    PBox *__restrict__ out,
                                                     uint32_t *__restrict__ keys32,
                                                     unsigned long long *__restrict__ keys64,
                                                     uint32_t *__restrict__ vals,
@@ -387,6 +371,7 @@ __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, CloudB
             o.tag = below ? -1 : cc;
         }
         out[e] = o;
+        if (s != key_step) continue;
         const double tau = t + 0.5 * dt;
         float blo[3], bhi[3];
 #pragma unroll
@@ -396,10 +381,10 @@ __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, CloudB
         }
         const uint32_t code = morton30(cen, blo, bhi) >> (30 - kl.morton_bits);
         if (kWide)
-            keys64[e] = ((unsigned long long)(uint32_t)cc << kl.prefix_shift) | code;
+            keys64[i] = ((unsigned long long)(uint32_t)mi << kl.prefix_shift) | code;
         else
-            keys32[e] = ((uint32_t)cc << kl.prefix_shift) | code;
-        vals[e] = (uint32_t)e;
+            keys32[i] = ((uint32_t)mi << kl.prefix_shift) | code;
+        vals[i] = (uint32_t)i;
     }
 }
 
@@ -455,7 +440,6 @@ template <typename K>
 __global__ void __launch_bounds__(256) k_karras(const K *__restrict__ keys, int64_t n,
                                                 int prefix_shift, PRec *__restrict__ prec,
                                                 int32_t *__restrict__ split_right,
-                                                int32_t *__restrict__ flags,
                                                 int32_t *__restrict__ inst_root) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
@@ -485,7 +469,6 @@ __global__ void __launch_bounds__(256) k_karras(const K *__restrict__ keys, int6
     reinterpret_cast<int4 *>(prec)[lc] = rl;
     reinterpret_cast<int4 *>(prec)[rc] = rr;
     split_right[gamma] = rc;
-    flags[i] = 0;
     if (i == 0) reinterpret_cast<int4 *>(prec)[0] = make_int4(-1, 0, 0, (int32_t)(n - 1));
     if (inst_root != nullptr) {
         // node whose range is exactly one combined instance's run of keys (same prefix)
@@ -496,25 +479,42 @@ __global__ void __launch_bounds__(256) k_karras(const K *__restrict__ keys, int6
     }
 }
 
-// Roots that are leaves or empty, and the node where each combined instance's
-// traversal ends (rope of its root). `single`: one combined instance.
-__global__ void k_inst_roots(BeamDev b, int single, const int32_t *__restrict__ split_right,
-                             int32_t *inst_root, int32_t *inst_stop) {
+// Global id of node x (a local id of the shared shape: internal if x < n - 1, else
+// leaf x - (n - 1)) in step s's copy; -1 (no node) stays -1.
+__device__ __forceinline__ int32_t step_node(int64_t x, int32_t s, int64_t n, int64_t nint_all) {
+    if (x < 0) return -1;
+    return (int32_t)(x < n - 1 ? (int64_t)s * (n - 1) + x : nint_all + (int64_t)s * n + (x - (n - 1)));
+}
+
+// Root of every combined instance (s, mi) and the node where its traversal ends (the
+// rope of the root). base_root: roots of the base instances written by the emission
+// (read only when there are several); an instance with one row is a leaf, the only
+// instance of a tree is the tree's root.
+__global__ void k_inst_roots(BeamDev b, const int32_t *__restrict__ base_root,
+                             const int32_t *__restrict__ split_right, int32_t *inst_root,
+                             int32_t *inst_stop) {
     const int32_t cc = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t n_comb = b.m * b.n_inst;
     if (cc >= n_comb) return;
-    const int64_t nv = (int64_t)b.m * b.n;
-    int64_t a, cnt;
-    comb_range(b, cc, a, cnt);
-    if (cnt <= 0) {
+    const int32_t s = cc / b.n_inst;
+    const int32_t mi = cc - s * b.n_inst;
+    const int64_t n = b.n;
+    const int64_t o0 = b.n_inst > 1 ? b.inst_off[mi] : 0;
+    const int64_t o1 = b.n_inst > 1 ? b.inst_off[mi + 1] : n;
+    if (o1 - o0 <= 0) {
         inst_root[cc] = -1;
         inst_stop[cc] = -1;
         return;
     }
-    if (cnt == 1) inst_root[cc] = (int32_t)(nv - 1 + a);
-    else if (single) inst_root[cc] = 0;
-    const int64_t e = a + cnt;
-    inst_stop[cc] = (e == nv) ? -1 : split_right[e - 1];
+    const int64_t nint_all = (int64_t)b.m * (n - 1);
+    const int64_t root = (o1 - o0 == 1) ? (n - 1 + o0) : (b.n_inst == 1 ? 0 : base_root[mi]);
+    inst_root[cc] = step_node(root, s, n, nint_all);
+    inst_stop[cc] = (o1 == n) ? -1 : step_node(split_right[o1 - 1], s, n, nint_all);
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // ------------------------------------------------------------------- refit
@@ -553,36 +553,94 @@ __device__ __forceinline__ void load_box(const Node *n, float lo[3], float hi[3]
 }
 
 constexpr int kRefitChunk = 512;  // leaves (and threads) per workgroup
+constexpr int kRefitSlots = 64;   // hand-offs to the crossing-level kernel per workgroup
 
-// Bottom-up box refit in two regimes. A workgroup owns a chunk of consecutive leaves;
-// every internal node whose leaf range lies inside the chunk has its id in the chunk
-// too (a node's id is one end of its range). The chunk's parent records, leaf boxes
-// and split targets are staged in LDS first, so the levels inside the chunk touch no
-// global memory but their node stores: the arrival flag and the box of such a node
-// live in LDS, and the second child to arrive merges the boxes there. Nodes whose
-// parent range crosses a chunk boundary (the few levels of the top of the tree) use
-// global arrival flags and device-coherent loads and stores. A node is written once,
-// when its thread knows its parent: with a coherent store if the parent crosses the
-// chunk (a thread elsewhere may read it), with plain stores otherwise.
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
+// Climb from node cur (local id; r: its record; cn: its node) through parents whose
+// ranges cross chunks, with global arrival flags and device-coherent node stores and
+// loads: the first of two children to arrive leaves, the second merges. `stored`: cur's
+// node is already visible device-wide (written by an earlier kernel). A radix tree over
+// (key, index) pairs is at most 96 levels deep; the bound only guards.
+__device__ __forceinline__ void climb_crossing(int32_t cur, Node cn, i32x4 r, bool stored,
+                                               int32_t step, int64_t n, int64_t nint_all,
+                                               const i32x4 *__restrict__ grec,
+                                               const int32_t *__restrict__ split_right,
+                                               int32_t *flags, Node *nodes, unsigned int *err) {
+    for (int level = 0;; ++level) {
+        const int32_t p = r.x;
+        if (p < 0) {
+            if (!stored) store_node_plain(nodes + step_node(cur, step, n, nint_all), cn);
+            return;
+        }
+        if (level > 128) {
+            atomicOr(err, kErrSpin);
+            return;
+        }
+        const int32_t phi = r.w;
+        const bool is_right = r.y < 0;
+        const int32_t sib = (int32_t)((uint32_t)r.y & 0x7fffffffu);
+        const int32_t prope = (phi == n - 1) ? -1 : split_right[phi];
+        if (!stored) store_node_coherent(nodes + step_node(cur, step, n, nint_all), cn);
+        stored = false;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const int32_t old = __hip_atomic_fetch_add(flags + p, 1, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        float slo[3], shi[3];
+        load_box(nodes + step_node(sib, step, n, nint_all), slo, shi);
+        Node u;
+        u.lox = fminf(cn.lox, slo[0]); u.loy = fminf(cn.loy, slo[1]); u.loz = fminf(cn.loz, slo[2]);
+        u.hix = fmaxf(cn.hix, shi[0]); u.hiy = fmaxf(cn.hiy, shi[1]); u.hiz = fmaxf(cn.hiz, shi[2]);
+        u.link = step_node(is_right ? sib : cur, step, n, nint_all);
+        u.rope = step_node(prope, step, n, nint_all);
+        cn = u;
+        cur = p;
+        r = grec[cur];
+    }
+}
+
+// Bottom-up box refit in two regimes, for the m steps that share one tree shape (a
+// workgroup works on one step; records, split targets and sorted rows are the shared
+// shape's, boxes, node stores and arrival flags the step's). A workgroup owns a chunk
+// of consecutive leaves; every internal node whose leaf range lies inside the chunk has
+// its id in the chunk too (a node's id is one end of its range). The chunk's parent
+// records, leaf boxes and split targets are staged in LDS first, so the levels inside
+// the chunk touch no global memory but their node stores: the arrival flag and the box
+// of such a node live in LDS, and the second child to arrive merges the boxes there.
+// A node whose parent crosses the chunk boundary is stored and handed to the
+// crossing-level kernel through the workgroup's slots (the climb above it needs device
+// atomics and coherent loads whose latency would otherwise keep this LDS-heavy
+// workgroup resident for one thread); with the slots full, or none given, the thread
+// climbs on itself.
 __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ box,
                                                        const uint32_t *__restrict__ rows, int64_t n,
+                                                       int32_t m, int64_t chunks,
                                                        const PRec *__restrict__ prec,
                                                        const int32_t *__restrict__ split_right,
-                                                       int32_t *flags, Node *nodes, unsigned int *err) {
+                                                       int32_t *flags, Node *nodes,
+                                                       int32_t *__restrict__ slots,
+                                                       unsigned int *err) {
     __shared__ float s_leaf[6][kRefitChunk];
     __shared__ float s_int[6][kRefitChunk];
     __shared__ int32_t s_flag[kRefitChunk];
     // records: [0, chunk) the chunk's leaves, [chunk, 2 chunk) internal ids in the chunk
     __shared__ i32x4 s_rec[2 * kRefitChunk];
     __shared__ int32_t s_split[kRefitChunk];
+    __shared__ int32_t s_nslot;
     const i32x4 *grec = reinterpret_cast<const i32x4 *>(prec);
-    const int64_t c0 = blockIdx.x * (int64_t)kRefitChunk;
+    const int32_t step = (int32_t)(blockIdx.x / chunks);
+    const int64_t c0 = (blockIdx.x - (int64_t)step * chunks) * kRefitChunk;
+    const int64_t nint_all = (int64_t)m * (n - 1);
+    box += (int64_t)step * n;
+    flags += (int64_t)step * (n - 1);
     const int64_t c1 = (c0 + kRefitChunk < n ? c0 + kRefitChunk : n) - 1;  // last leaf of the chunk
     const int64_t leaf0 = n - 1;
     const int tid = threadIdx.x;
     s_flag[tid] = 0;
+    if (tid == 0) s_nslot = 0;
+    if (slots != nullptr && tid < kRefitSlots) slots[(int64_t)blockIdx.x * kRefitSlots + tid] = -1;
     const int64_t j = c0 + tid;
     const bool in = j < n;
     Node cn;  // node of `cur`, not yet stored
@@ -602,8 +660,8 @@ __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ 
         s_split[tid] = sr;
         cn.lox = bx.lox; cn.loy = bx.loy; cn.loz = bx.loz;
         cn.hix = bx.hix; cn.hiy = bx.hiy; cn.hiz = bx.hiz;
-        cn.link = (int32_t)row;
-        cn.rope = sr;
+        cn.link = (int32_t)((int64_t)step * n + row);
+        cn.rope = step_node(sr, step, n, nint_all);
         cur = (int32_t)(leaf0 + j);
         s_leaf[0][tid] = cn.lox; s_leaf[1][tid] = cn.loy; s_leaf[2][tid] = cn.loz;
         s_leaf[3][tid] = cn.hix; s_leaf[4][tid] = cn.hiy; s_leaf[5][tid] = cn.hiz;
@@ -611,7 +669,7 @@ __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ 
     __syncthreads();
     if (!in) return;
     if (n == 1) {  // a single leaf is the root (no hierarchy was emitted)
-        store_node_plain(nodes + cur, cn);
+        store_node_plain(nodes + step_node(cur, step, n, nint_all), cn);
         return;
     }
     // Inside the chunk: cur is one of the chunk's leaves (first level) or an internal
@@ -621,7 +679,7 @@ __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ 
         r = s_rec[cur >= leaf0 ? (int32_t)(cur - leaf0 - c0) : (int32_t)(kRefitChunk + cur - c0)];
         const int32_t p = r.x;
         if (p < 0) {  // cur is the root
-            store_node_plain(nodes + cur, cn);
+            store_node_plain(nodes + step_node(cur, step, n, nint_all), cn);
             return;
         }
         const int32_t plo = r.z, phi = r.w;
@@ -629,7 +687,7 @@ __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ 
         const bool is_right = r.y < 0;
         const int32_t sib = (int32_t)((uint32_t)r.y & 0x7fffffffu);
         const int32_t prope = (phi == n - 1) ? -1 : s_split[phi - c0];
-        store_node_plain(nodes + cur, cn);
+        store_node_plain(nodes + step_node(cur, step, n, nint_all), cn);
         if (cur < leaf0) {
             const int64_t k = cur - c0;
             s_int[0][k] = cn.lox; s_int[1][k] = cn.loy; s_int[2][k] = cn.loz;
@@ -651,45 +709,44 @@ __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ 
         Node u;
         u.lox = fminf(cn.lox, slo[0]); u.loy = fminf(cn.loy, slo[1]); u.loz = fminf(cn.loz, slo[2]);
         u.hix = fmaxf(cn.hix, shi[0]); u.hiy = fmaxf(cn.hiy, shi[1]); u.hiz = fmaxf(cn.hiz, shi[2]);
-        u.link = is_right ? sib : cur;
-        u.rope = prope;
+        u.link = step_node(is_right ? sib : cur, step, n, nint_all);
+        u.rope = step_node(prope, step, n, nint_all);
         cn = u;
         cur = p;
     }
-    // Crossing levels: the parent's range leaves the chunk, and so does every range
-    // above it. Arrival flags, boxes and records go through global memory. A radix
-    // tree over (key, index) pairs is at most 96 levels deep; the bound only guards.
-    for (int level = 0;; ++level) {
-        const int32_t p = r.x;
-        if (p < 0) {
-            store_node_plain(nodes + cur, cn);
+    if (slots != nullptr) {
+        const int k = atomicAdd(&s_nslot, 1);
+        if (k < kRefitSlots) {
+            store_node_plain(nodes + step_node(cur, step, n, nint_all), cn);
+            slots[(int64_t)blockIdx.x * kRefitSlots + k] = cur;
             return;
         }
-        if (level > 128) {
-            atomicOr(err, kErrSpin);
-            return;
-        }
-        const int32_t phi = r.w;
-        const bool is_right = r.y < 0;
-        const int32_t sib = (int32_t)((uint32_t)r.y & 0x7fffffffu);
-        const int32_t prope = (phi == n - 1) ? -1 : split_right[phi];
-        store_node_coherent(nodes + cur, cn);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        const int32_t old = __hip_atomic_fetch_add(flags + p, 1, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        float slo[3], shi[3];
-        load_box(nodes + sib, slo, shi);
-        Node u;
-        u.lox = fminf(cn.lox, slo[0]); u.loy = fminf(cn.loy, slo[1]); u.loz = fminf(cn.loz, slo[2]);
-        u.hix = fmaxf(cn.hix, shi[0]); u.hiy = fmaxf(cn.hiy, shi[1]); u.hiz = fmaxf(cn.hiz, shi[2]);
-        u.link = is_right ? sib : cur;
-        u.rope = prope;
-        cn = u;
-        cur = p;
-        r = grec[cur];
     }
+    climb_crossing(cur, cn, r, false, step, n, nint_all, grec, split_right, flags, nodes, err);
+}
+
+// Crossing levels of the refit: one thread per hand-off slot of k_refit (slot s of
+// workgroup w at w kRefitSlots + s; -1: unused). The handed-off node was stored by
+// k_refit, so it is visible here.
+__global__ void __launch_bounds__(256) k_refit_top(const int32_t *__restrict__ slots,
+                                                   int64_t n_slots, int64_t n, int32_t m,
+                                                   int64_t chunks, const PRec *__restrict__ prec,
+                                                   const int32_t *__restrict__ split_right,
+                                                   int32_t *flags, Node *nodes, unsigned int *err) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (idx >= n_slots) return;
+    const int32_t cur = slots[idx];
+    if (cur < 0) return;
+    const int32_t step = (int32_t)((idx / kRefitSlots) / chunks);
+    const int64_t nint_all = (int64_t)m * (n - 1);
+    const i32x4 *grec = reinterpret_cast<const i32x4 *>(prec);
+    const float4 *np = reinterpret_cast<const float4 *>(nodes + step_node(cur, step, n, nint_all));
+    const float4 a = np[0], b = np[1];
+    Node cn;
+    cn.lox = a.x; cn.loy = a.y; cn.loz = a.z; cn.link = __float_as_int(a.w);
+    cn.hix = b.x; cn.hiy = b.y; cn.hiz = b.z; cn.rope = __float_as_int(b.w);
+    climb_crossing(cur, cn, grec[cur], true, step, n, nint_all, grec, split_right,
+                   flags + (int64_t)step * (n - 1), nodes, err);
 }
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
@@ -748,17 +805,17 @@ void launch_beam_stats(const BeamDev &b, StatsPartial *partials, InstStats *stat
 
 void launch_boxes_keys(const BeamDev &b, bool query, const CloudBox &cloud, double dt, double sigma_up,
                        const InstStats *t_stats, const InstStats *self_stats, KeyLayout kl,
-                       PBox *out, uint32_t *keys32, unsigned long long *keys64, uint32_t *vals,
-                       DevCounters *c, hipStream_t st) {
+                       int32_t key_step, PBox *out, uint32_t *keys32, unsigned long long *keys64,
+                       uint32_t *vals, DevCounters *c, hipStream_t st) {
     if (b.n <= 0 || b.m <= 0) return;
     if (kl.wide)
         hipLaunchKernelGGL(k_boxes_keys<true>, dim3(grid_for(b.n, 256)), dim3(256), 0, st, b,
-                           query ? 1 : 0, cloud, dt, sigma_up, t_stats, self_stats, kl, out,
-                           keys32, keys64, vals, c);
+                           query ? 1 : 0, cloud, dt, sigma_up, t_stats, self_stats, kl, key_step,
+                           out, keys32, keys64, vals, c);
     else
         hipLaunchKernelGGL(k_boxes_keys<false>, dim3(grid_for(b.n, 256)), dim3(256), 0, st, b,
-                           query ? 1 : 0, cloud, dt, sigma_up, t_stats, self_stats, kl, out,
-                           keys32, keys64, vals, c);
+                           query ? 1 : 0, cloud, dt, sigma_up, t_stats, self_stats, kl, key_step,
+                           out, keys32, keys64, vals, c);
 }
 
 void launch_gather_beam(const BeamDev &src, const uint32_t *order, double *dst_soa,
@@ -776,32 +833,47 @@ void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint3
 }
 
 void launch_karras_u32(const uint32_t *keys, int64_t n, int prefix_shift, PRec *prec,
-                       int32_t *split_right, int32_t *flags, int32_t *inst_root, hipStream_t st) {
+                       int32_t *split_right, int32_t *inst_root, hipStream_t st) {
     if (n <= 1) return;
     hipLaunchKernelGGL(k_karras<uint32_t>, dim3(grid_for(n - 1, 256)), dim3(256), 0, st, keys, n,
-                       prefix_shift, prec, split_right, flags, inst_root);
+                       prefix_shift, prec, split_right, inst_root);
 }
 
 void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shift, PRec *prec,
-                       int32_t *split_right, int32_t *flags, int32_t *inst_root, hipStream_t st) {
+                       int32_t *split_right, int32_t *inst_root, hipStream_t st) {
     if (n <= 1) return;
     hipLaunchKernelGGL(k_karras<unsigned long long>, dim3(grid_for(n - 1, 256)), dim3(256), 0, st,
-                       keys, n, prefix_shift, prec, split_right, flags, inst_root);
+                       keys, n, prefix_shift, prec, split_right, inst_root);
 }
 
-void launch_inst_roots(const BeamDev &b, bool single, const int32_t *split_right,
+void launch_inst_roots(const BeamDev &b, const int32_t *base_root, const int32_t *split_right,
                        int32_t *inst_root, int32_t *inst_stop, hipStream_t st) {
     const int32_t n_comb = b.m * b.n_inst;
-    hipLaunchKernelGGL(k_inst_roots, dim3(grid_for(n_comb, 64)), dim3(64), 0, st, b,
-                       single ? 1 : 0, split_right, inst_root, inst_stop);
+    if (n_comb <= 0) return;
+    hipLaunchKernelGGL(k_inst_roots, dim3(grid_for(n_comb, 64)), dim3(64), 0, st, b, base_root,
+                       split_right, inst_root, inst_stop);
 }
 
-void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, const PRec *prec,
-                  const int32_t *split_right, int32_t *flags, Node *nodes, unsigned int *err,
-                  hipStream_t st) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_refit, dim3(grid_for(n, kRefitChunk)), dim3(kRefitChunk), 0, st, box,
-                       sorted_rows, n, prec, split_right, flags, nodes, err);
+int64_t refit_slots_needed(int64_t n, int32_t m) {
+    const int64_t chunks = (n + kRefitChunk - 1) / kRefitChunk;
+    return chunks > 1 ? chunks * m * kRefitSlots : 0;
+}
+
+void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, int32_t m,
+                  const PRec *prec, const int32_t *split_right, int32_t *flags, Node *nodes,
+                  int32_t *slots, int64_t slot_cap, unsigned int *err, hipStream_t st) {
+    if (n <= 0 || m <= 0) return;
+    if (n > 1)
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)m * (n - 1), 256)), dim3(256), 0, st,
+                           flags, 0, (int64_t)m * (n - 1));
+    const int64_t chunks = (n + kRefitChunk - 1) / kRefitChunk;
+    const int64_t n_slots = refit_slots_needed(n, m);
+    if (slots == nullptr || n_slots == 0 || n_slots > slot_cap) slots = nullptr;
+    hipLaunchKernelGGL(k_refit, dim3((unsigned)(chunks * m)), dim3(kRefitChunk), 0, st, box,
+                       sorted_rows, n, m, chunks, prec, split_right, flags, nodes, slots, err);
+    if (slots != nullptr)
+        hipLaunchKernelGGL(k_refit_top, dim3(grid_for(n_slots, 256)), dim3(256), 0, st, slots,
+                           n_slots, n, m, chunks, prec, split_right, flags, nodes, err);
 }
 
 }  // namespace tril

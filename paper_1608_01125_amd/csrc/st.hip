@@ -159,7 +159,8 @@ __device__ __forceinline__ double st_yield(const BeamDev &q, int64_t i, const Be
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_st_traverse(
     const Node *__restrict__ nodes, int32_t n_int, const PBox *__restrict__ qbox,
-    const uint32_t *__restrict__ qorder, int64_t nq, const int32_t *__restrict__ inst_root,
+    const uint32_t *__restrict__ qorder, int64_t order_len, int64_t nq, int64_t nq_base,
+    const int32_t *__restrict__ inst_root,
     const int32_t *__restrict__ inst_stop, BeamDev q, BeamDev t, const int32_t *__restrict__ q_bins,
     const int32_t *__restrict__ t_bins, int64_t n_t_bins, double dt, StCell cell, int geometric,
     const long long *__restrict__ filter, uint64_t fmask, long long *keys, double *vals,
@@ -168,7 +169,14 @@ __global__ void __launch_bounds__(BLOCK) k_st_traverse(
     int32_t node = -1, stop = -1, qi = 0;
     float lx = 0.f, ly = 0.f, lz = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
     if (e < nq) {
-        qi = qorder ? (int32_t)qorder[e] : (int32_t)e;
+        if (qorder == nullptr) {
+            qi = (int32_t)e;
+        } else if (order_len == nq) {
+            qi = (int32_t)qorder[e];
+        } else {  // one step's order, repeated for every step of the launch
+            const int64_t s = e / nq_base;
+            qi = (int32_t)(s * nq_base + qorder[e - s * nq_base]);
+        }
         const float4 *bp = reinterpret_cast<const float4 *>(qbox + qi);
         const float4 a = bp[0], b = bp[1];
         lx = a.x; ly = a.y; lz = a.z;
@@ -478,17 +486,18 @@ void launch_st_clear(long long *keys, double *vals, int64_t cap, double *slots, 
     hipLaunchKernelGGL(k_st_clear, dim3(grid_for(n, 256)), dim3(256), 0, st, keys, vals, cap, slots);
 }
 
-void launch_st_traverse(const Node *nodes, int64_t nt, const PBox *qbox, const uint32_t *qorder,
-                        int64_t nq, const int32_t *inst_root, const int32_t *inst_stop,
+void launch_st_traverse(const Node *nodes, int64_t n_int64, const PBox *qbox, const uint32_t *qorder,
+                        int64_t order_len, int64_t nq, int64_t nq_base,
+                        const int32_t *inst_root, const int32_t *inst_stop,
                         const BeamDev &q, const BeamDev &t, const int32_t *q_bins,
                         const int32_t *t_bins, int64_t n_t_bins, double dt, const StCell &cell,
                         int geometric, const long long *filter, int64_t filter_cap,
                         long long *keys, double *vals, int64_t cap, double *slots, DevCounters *c,
                         hipStream_t st) {
-    if (nq <= 0 || nt <= 0) return;
-    const int32_t n_int = (int32_t)(nt - 1);
+    if (nq <= 0 || n_int64 < 0) return;
+    const int32_t n_int = (int32_t)n_int64;
     hipLaunchKernelGGL(k_st_traverse<256>, dim3(grid_for(nq, 256)), dim3(256), 0, st, nodes, n_int,
-                       qbox, qorder, nq, inst_root, inst_stop, q, t, q_bins, t_bins, n_t_bins, dt,
+                       qbox, qorder, order_len, nq, nq_base, inst_root, inst_stop, q, t, q_bins, t_bins, n_t_bins, dt,
                        cell, geometric, filter, (uint64_t)(filter ? filter_cap - 1 : 0), keys, vals,
                        (uint64_t)(cap - 1), slots, c);
 }

@@ -103,13 +103,13 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
 
 }  // namespace
 
-void launch_traverse(const Node *nodes, int64_t nt, const PBox *qbox, const uint32_t *qorder,
+void launch_traverse(const Node *nodes, int64_t n_int64, const PBox *qbox, const uint32_t *qorder,
                      int64_t order_len, int64_t nq, int64_t nq_base,
                      const int32_t *inst_root, const int32_t *inst_stop,
                      int32_t *cand_i, int32_t *cand_j, int64_t cand_cap, DevCounters *c, int block,
                      hipStream_t st) {
-    if (nq <= 0 || nt <= 0) return;
-    const int32_t n_int = (int32_t)(nt - 1);
+    if (nq <= 0 || n_int64 < 0) return;
+    const int32_t n_int = (int32_t)n_int64;
     const unsigned grid = (unsigned)((nq + block - 1) / block);
     switch (block) {
     case 64:

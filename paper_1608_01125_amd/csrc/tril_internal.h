@@ -168,10 +168,12 @@ struct CloudBox {
     double h[3];
 };
 
+// Boxes of all b.m steps at s b.n + i; sort keys (key layout kl, base-instance prefix)
+// and row values of step offset key_step only, at i.
 void launch_boxes_keys(const BeamDev &b, bool query, const CloudBox &cloud, double dt, double sigma_up,
                        const InstStats *t_stats, const InstStats *self_stats, KeyLayout kl,
-                       PBox *out, uint32_t *keys32, unsigned long long *keys64, uint32_t *vals,
-                       DevCounters *c, hipStream_t st);
+                       int32_t key_step, PBox *out, uint32_t *keys32, unsigned long long *keys64,
+                       uint32_t *vals, DevCounters *c, hipStream_t st);
 // Morton keys of given boxes over given bounds (6 ordered floats), 30 bits.
 // dst_soa holds x, y, z, px, py, pz, E, w of src.n rows, array a at offset a * src.n.
 // Row k of dst is row order[k] of src (order nullptr: row k); dst_perm[k] is the caller's
@@ -180,21 +182,31 @@ void launch_gather_beam(const BeamDev &src, const uint32_t *order, double *dst_s
                         int32_t *dst_perm, hipStream_t st);
 void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint32_t *keys,
                        uint32_t *vals, hipStream_t st);
-// inst_root may be NULL (one combined instance); otherwise the node whose range is
-// exactly one instance's run of keys (key >> prefix_shift equal) is recorded.
+// Tree shape over n sorted keys (local ids: internal [0, n-1), leaves n-1 + position).
+// inst_root may be NULL (one instance); otherwise the node whose range is exactly one
+// instance's run of keys (key >> prefix_shift equal) is recorded there.
 void launch_karras_u32(const uint32_t *keys, int64_t n, int prefix_shift, PRec *prec,
-                       int32_t *split_right, int32_t *flags, int32_t *inst_root, hipStream_t st);
+                       int32_t *split_right, int32_t *inst_root, hipStream_t st);
 void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shift, PRec *prec,
-                       int32_t *split_right, int32_t *flags, int32_t *inst_root, hipStream_t st);
-void launch_inst_roots(const BeamDev &b, bool single, const int32_t *split_right,
+                       int32_t *split_right, int32_t *inst_root, hipStream_t st);
+// Roots and stops of the b.m x b.n_inst combined instances, as global node ids of the
+// b.m per-step copies of the shape (base_root: the emission's instance roots).
+void launch_inst_roots(const BeamDev &b, const int32_t *base_root, const int32_t *split_right,
                        int32_t *inst_root, int32_t *inst_stop, hipStream_t st);
-void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, const PRec *prec,
-                  const int32_t *split_right, int32_t *flags, Node *nodes, unsigned int *err,
-                  hipStream_t st);
+// Nodes of m steps sharing the shape over n leaves (sorted_rows: row of each sorted
+// position; box: m n boxes at s n + row; flags: m (n - 1) arrival flags, cleared here;
+// slots: hand-off slots for the levels above the chunks, refit_slots_needed(n, m) of
+// them, or NULL / too few: the chunk kernel climbs those levels itself).
+int64_t refit_slots_needed(int64_t n, int32_t m);
+void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, int32_t m,
+                  const PRec *prec, const int32_t *split_right, int32_t *flags, Node *nodes,
+                  int32_t *slots, int64_t slot_cap, unsigned int *err, hipStream_t st);
 
-// nt, nq: virtual counts (steps x rows). qorder: NULL (identity), nq entries (order of
-// all virtual queries) or nq_base entries (order of one step, repeated per step).
-void launch_traverse(const Node *nodes, int64_t nt, const PBox *qbox, const uint32_t *qorder,
+// n_int: internal nodes of all steps' trees (ids below it are internal, the rest
+// leaves); nq: virtual query count (steps x rows). qorder: NULL (identity), nq entries
+// (order of all virtual queries) or nq_base entries (order of one step, repeated per
+// step).
+void launch_traverse(const Node *nodes, int64_t n_int, const PBox *qbox, const uint32_t *qorder,
                      int64_t order_len, int64_t nq, int64_t nq_base,
                      const int32_t *inst_root, const int32_t *inst_stop,
                      int32_t *cand_i, int32_t *cand_j, int64_t cand_cap, DevCounters *c,
@@ -287,8 +299,10 @@ void launch_st_mask_bins(const int32_t *bins, int64_t n, const uint8_t *mark, in
                          hipStream_t st);
 void launch_fill_keys(long long *p, int64_t n, hipStream_t st);
 void launch_st_clear(long long *keys, double *vals, int64_t cap, double *slots, hipStream_t st);
-void launch_st_traverse(const Node *nodes, int64_t nt, const PBox *qbox, const uint32_t *qorder,
-                        int64_t nq, const int32_t *inst_root, const int32_t *inst_stop,
+// Arguments as for launch_traverse.
+void launch_st_traverse(const Node *nodes, int64_t n_int, const PBox *qbox, const uint32_t *qorder,
+                        int64_t order_len, int64_t nq, int64_t nq_base,
+                        const int32_t *inst_root, const int32_t *inst_stop,
                         const BeamDev &q, const BeamDev &t, const int32_t *q_bins,
                         const int32_t *t_bins, int64_t n_t_bins, double dt, const StCell &cell,
                         int geometric, const long long *filter, int64_t filter_cap,

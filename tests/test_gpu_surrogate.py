@@ -58,13 +58,17 @@ def test_candidate_cell_pairs_cover_exact_pairs(ctx):
     assert abs(yv.sum() - ys[covered].sum()) <= 1e-9 * tot
 
 
-def test_trained_ensemble_beats_bin_level_estimate_and_gate_holds_1pct(torch, ctx):
+def test_trained_ensemble_beats_bin_level_estimate_and_gate_removes_most_bias(torch, ctx):
     """Trained on six instances from the batched workload's parameter ranges, tested on
     the head-on shape (held out). The method without the network is the bin-level yield
     Y0 with one global scale fitted on the training rows. The network recovers the
     distribution of the yield over cell pairs far better (L1 distance to the exact
-    distribution); its total carries a bias, which the gate (ensemble spread above 0.01 ->
-    exact path) removes: the gated total is within 1% of the exact one."""
+    distribution); its total carries a bias of several percent, most of which the
+    per-pair gate (ensemble spread above 0.01 of a pair's prediction -> exact path)
+    removes. The per-pair gate bounds each kept pair's spread, not the bias the members
+    share, so it fixes no bound on the total: trainings on rows that differ only in the
+    rounding order of their atomically summed yields left 0.15% to 1.06% here. The 1%
+    bound on the total is the budget gate's (next test)."""
     eps = 1e-3
     train_insts = [surrogate.Instance(beams.st_train_instance(m, N_MP)) for m in range(6)]
     x, t, y0, y = surrogate.training_rows(ctx, train_insts, eps=eps)
@@ -89,12 +93,15 @@ def test_trained_ensemble_beats_bin_level_estimate_and_gate_holds_1pct(torch, ct
     l1_base = float((kappa * y0e - ye).abs().sum() / ye.sum())
     l1_net = float((pred - ye).abs().sum() / ye.sum())
     err_gated = abs(res["total"] - exact_total) / exact_total
+    err_never = abs(never["total"] - exact_total) / exact_total
     print(f"\nexact {exact_total:.6g}  L1 bin-level {l1_base:.3f}  L1 network {l1_net:.3f}  "
-          f"gated error {err_gated:.5f} ({res['n_gated']} of {res['n_bin_pairs']} pairs exact)")
+          f"ungated error {err_never:.5f}  gated error {err_gated:.5f} "
+          f"({res['n_gated']} of {res['n_bin_pairs']} pairs exact)")
     assert abs(never["total"] - float(pred.sum())) <= 1e-4 * float(pred.sum())
     assert never["n_gated"] == 0 and res["n_gated"] > 0
     assert l1_net < 0.5 * l1_base
-    assert err_gated <= 0.01
+    assert err_gated <= 0.25 * err_never
+    assert err_gated <= 0.02
 
 
 def test_budget_gate_with_same_shape_training(torch, ctx):
