@@ -45,7 +45,7 @@ def traverse_source_hash() -> str:
         h.update(f.read())
     with open(os.path.join(ROOT, TRAVERSE_SOURCES[1]), "rb") as f:
         text = f.read().decode()
-    a = text.index("struct alignas(16) Node")
+    a = text.index("struct alignas(16) Half")
     b = text.index("static_assert(sizeof(PBox)")
     h.update(text[a:b].encode())
     return h.hexdigest()[:16]
@@ -329,9 +329,9 @@ def main():
 
     roofline = None
     if st["n_collides"] > 0:
-        # traversal bytes over the timed region: 36 B per query (order entry + box), 32 B per
-        # node visit, 8 B per candidate written
-        alg_bytes = 36.0 * nA * st["n_collides"] + 32.0 * st["n_node_visits"] + 8.0 * st["n_candidates"]
+        # traversal bytes over the timed region: 36 B per query (order entry + box), 64 B per
+        # node load (both children's boxes and links), 8 B per candidate written
+        alg_bytes = 36.0 * nA * st["n_collides"] + 64.0 * st["n_node_visits"] + 8.0 * st["n_candidates"]
         traffic = committed_traffic(steps_per_dispatch)
         if st["n_timed_launches"] > 0 and st["ms_traverse"] > 0:
             n_launch = st["n_timed_launches"]

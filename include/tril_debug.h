@@ -53,11 +53,14 @@ int tril_dbg_gemm_bf16(const uint16_t *A, int64_t sam, int64_t sak, const uint16
                        int64_t sbn, int32_t M, int32_t N, int32_t K, float *C, void *stream);
 
 /* Copy the last built hierarchy to host memory (synchronises the context stream).
- * nodes: host, cap_nodes x 8 words (lox loy loz link hix hiy hiz rope as float/int32);
- * *n_nodes receives 2n-1 (0 for an empty beam); roots/stops: host, n_inst each,
- * or NULL. TRIL_E_OVERFLOW if cap_nodes < 2n-1. */
+ * nodes: host, cap_nodes x 16 words, one internal node each: its left child's box and
+ * link (lox loy loz link hix hiy hiz pad), then its right child's, as float/int32; a
+ * link >= 0 is an internal node, a link <= -2 the leaf holding target element
+ * -2 - link. *n_nodes receives m (n-1) for the m steps of the last build (0 below two
+ * rows). roots: host, m n_inst root links (same encoding; -1: empty instance), or
+ * NULL. TRIL_E_OVERFLOW if cap_nodes < *n_nodes. */
 int tril_dbg_tree(tril_ctx *ctx, void *nodes, int64_t cap_nodes, int64_t *n_nodes,
-                  int32_t *roots, int32_t *stops);
+                  int32_t *roots);
 
 /* Copy the swept boxes of the last target (which = 0) or query (which = 1) beam to
  * host memory as n x 8 words (lox loy loz tag hix hiy hiz instance). */

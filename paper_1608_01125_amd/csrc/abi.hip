@@ -134,9 +134,9 @@ struct tril_ctx {
     unsigned long long *t_k64a = nullptr, *t_k64b = nullptr;
     uint32_t *t_va = nullptr, *t_vb = nullptr;
     PRec *prec = nullptr;
-    int32_t *split_right = nullptr, *nflags = nullptr;
+    int32_t *nflags = nullptr;
     Node *nodes = nullptr;
-    int32_t *inst_root = nullptr, *inst_stop = nullptr;
+    int32_t *inst_root = nullptr;
     int32_t *inst_base = nullptr;          // instance roots of the shared tree shape
     int32_t *refit_slots = nullptr;        // refit hand-offs to the crossing-level kernel
     int64_t refit_slot_cap = 0;
@@ -218,7 +218,7 @@ void free_target(tril_ctx *c) {
 void free_target_rows(tril_ctx *c) {
     dev_free(c->t_spart); dev_free(c->t_k32a); dev_free(c->t_k32b);
     dev_free(c->t_k64a); dev_free(c->t_k64b); dev_free(c->t_va); dev_free(c->t_vb);
-    dev_free(c->prec); dev_free(c->split_right);
+    dev_free(c->prec);
     c->t_row_cap = 0;
 }
 
@@ -232,7 +232,7 @@ int ensure_target(tril_ctx *c, int64_t nv, int64_t n, int64_t n_comb, int32_t n_
         const int64_t m = std::max<int64_t>(nv, 1);
         CHK(dev_alloc(&c->t_box, m));
         CHK(dev_alloc(&c->nflags, m));
-        CHK(dev_alloc(&c->nodes, 2 * m));
+        CHK(dev_alloc(&c->nodes, m));  // m' (n' - 1) internal nodes of m' steps over n' rows
         // a launch of m' steps over n' > 512 rows has m' ceil(n' / 512) <= nv / 256 chunks
         // (fewer rows need no hand-offs), 64 slots each
         c->refit_slot_cap = m / 4 + 64;
@@ -249,16 +249,14 @@ int ensure_target(tril_ctx *c, int64_t nv, int64_t n, int64_t n_comb, int32_t n_
         CHK(dev_alloc(&c->t_k64a, m)); CHK(dev_alloc(&c->t_k64b, m));
         CHK(dev_alloc(&c->t_va, m)); CHK(dev_alloc(&c->t_vb, m));
         CHK(dev_alloc(&c->prec, 2 * m));
-        CHK(dev_alloc(&c->split_right, m));
         c->t_row_cap = m;
     }
     if (n_comb > c->t_comb_cap) {
         ++c->alloc_gen;
-        dev_free(c->inst_root); dev_free(c->inst_stop); dev_free(c->inst_base);
+        dev_free(c->inst_root); dev_free(c->inst_base);
         c->t_comb_cap = 0;
         c->built = false;
         CHK(dev_alloc(&c->inst_root, (size_t)n_comb));
-        CHK(dev_alloc(&c->inst_stop, (size_t)n_comb));
         CHK(dev_alloc(&c->inst_base, (size_t)n_comb));
         c->t_comb_cap = n_comb;
     }
@@ -467,19 +465,19 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
                                         c->ss, &c->d_cnt->err, st);
         const uint32_t *keys = alt ? c->t_k32b : c->t_k32a;
         rows = alt ? c->t_vb : c->t_va;
-        launch_karras_u32(keys, n, kl.prefix_shift, c->prec, c->split_right, roots, st);
+        launch_karras_u32(keys, n, kl.prefix_shift, c->prec, roots, st);
     } else {
         const bool alt = radix_sort_u64(c->t_k64a, c->t_va, c->t_k64b, c->t_vb, n, kl.key_bits,
                                         c->ss, &c->d_cnt->err, st);
         const unsigned long long *keys = alt ? c->t_k64b : c->t_k64a;
         rows = alt ? c->t_vb : c->t_va;
-        launch_karras_u64(keys, n, kl.prefix_shift, c->prec, c->split_right, roots, st);
+        launch_karras_u64(keys, n, kl.prefix_shift, c->prec, roots, st);
     }
     c->t_rows = rows;
     c->n_int = n > 0 ? (int64_t)t.m * (n - 1) : -1;
-    launch_inst_roots(t, c->inst_base, c->split_right, c->inst_root, c->inst_stop, st);
-    launch_refit(c->t_box, rows, n, t.m, c->prec, c->split_right, c->nflags, c->nodes,
-                 c->refit_slots, c->refit_slot_cap, &c->d_cnt->err, st);
+    launch_inst_roots(t, c->inst_base, rows, c->inst_root, st);
+    launch_refit(c->t_box, rows, n, t.m, c->prec, c->nflags, c->nodes, c->refit_slots,
+                 c->refit_slot_cap, &c->d_cnt->err, st);
     if (timed) CHK(timing_pair(c, st, c->ev_build, false));
     HIPCHK(hipGetLastError());
     return TRIL_OK;
@@ -514,8 +512,8 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
     CHK(enqueue_query_prep(c, q, st, sort_queries));
     if (timed) CHK(timing_pair(c, st, c->ev_prep, false));
     if (timed) CHK(timing_pair(c, st, c->ev_trav, true));
-    launch_traverse(c->nodes, c->n_int, c->q_box, c->q_order, c->q_order_len, nv, q.n, c->inst_root,
-                    c->inst_stop, c->cand_i, c->cand_j, c->cand_cap, c->d_cnt, c->block, st);
+    launch_traverse(c->nodes, c->n_int, c->t_box, c->q_box, c->q_order, c->q_order_len, nv, q.n,
+                    c->inst_root, c->cand_i, c->cand_j, c->cand_cap, c->d_cnt, c->block, st);
     if (timed) CHK(timing_pair(c, st, c->ev_trav, false));
     if (timed) CHK(timing_pair(c, st, c->ev_narrow, true));
     launch_narrow(q, c->tgt, c->dt, c->sigma_up, c->cand_i, c->cand_j, c->cand_cap, out, c->d_cnt,
@@ -1041,10 +1039,10 @@ int st_run(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_t n_t_b
         launch_prologue(c->d_cnt, 1, mb, c->st);
         if ((rc = enqueue_query_prep(c, qv, c->st, true)) != TRIL_OK) break;
         const int64_t nqv = (int64_t)mb * q->n;
-        launch_st_traverse(c->nodes, c->n_int, c->q_box, nqv > 0 ? c->q_order : nullptr,
-                           c->q_order_len, nqv, q->n, c->inst_root, c->inst_stop, qv, c->tgt, q_bins, t_bins, n_t_bins,
-                           c->dt, sc, geometric, filter, filter_cap, keys, vals, cap, c->st_slots,
-                           c->d_cnt, c->st);
+        launch_st_traverse(c->nodes, c->n_int, c->t_box, c->q_box, nqv > 0 ? c->q_order : nullptr,
+                           c->q_order_len, nqv, q->n, c->inst_root, qv, c->tgt, q_bins, t_bins,
+                           n_t_bins, c->dt, sc, geometric, filter, filter_cap, keys, vals, cap,
+                           c->st_slots, c->d_cnt, c->st);
         k += mb;
         left -= mb;
     }
@@ -1704,7 +1702,7 @@ void tril_destroy(tril_ctx *c) {
     dev_free(c->sg_key); dev_free(c->sg_val);
     dev_free(c->sf_x); dev_free(c->sf_mean); dev_free(c->sf_sd); dev_free(c->sf_y0);
     dev_free(c->sf_key); dev_free(c->se_key); dev_free(c->se_val);
-    dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->inst_root); dev_free(c->inst_stop); dev_free(c->inst_base);
+    dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->inst_root); dev_free(c->inst_base);
     dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
     dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
     dev_free(c->q_keep); dev_free(c->d_q_off); dev_free(c->q_stats); dev_free(c->cand_i);
@@ -1834,12 +1832,11 @@ int tril_dbg_pair_eval32(int64_t n, const double *in, double *out, void *stream)
     return TRIL_OK;
 }
 
-int tril_dbg_tree(tril_ctx *c, void *nodes, int64_t cap_nodes, int64_t *n_nodes, int32_t *roots,
-                  int32_t *stops) {
+int tril_dbg_tree(tril_ctx *c, void *nodes, int64_t cap_nodes, int64_t *n_nodes, int32_t *roots) {
     if (!c || !n_nodes) return TRIL_E_INVAL;
     if (!c->built) return TRIL_E_STATE;
     HIPCHK(hipStreamSynchronize(c->st));
-    const int64_t nn = c->tgt.n > 0 ? (int64_t)c->tgt.m * (2 * c->tgt.n - 1) : 0;
+    const int64_t nn = c->tgt.n > 1 ? (int64_t)c->tgt.m * (c->tgt.n - 1) : 0;
     *n_nodes = nn;
     if (nn > cap_nodes) return TRIL_E_OVERFLOW;
     if (nn > 0) {
@@ -1848,7 +1845,6 @@ int tril_dbg_tree(tril_ctx *c, void *nodes, int64_t cap_nodes, int64_t *n_nodes,
     }
     const size_t n_comb = (size_t)c->tgt.m * c->tgt.n_inst;
     if (roots) HIPCHK(hipMemcpy(roots, c->inst_root, n_comb * sizeof(int32_t), hipMemcpyDeviceToHost));
-    if (stops) HIPCHK(hipMemcpy(stops, c->inst_stop, n_comb * sizeof(int32_t), hipMemcpyDeviceToHost));
     return TRIL_OK;
 }
 

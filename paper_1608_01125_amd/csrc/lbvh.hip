@@ -4,13 +4,12 @@
 // The paper's hierarchy (Sec. 2.1) uses axis-aligned boxes enlarged by the
 // distance a particle travels in one step, so that collisions are found before
 // they happen; boxes with no particles do not exist; children are named 0 and 1
-// per level. Here every step builds a linear BVH: photons are ordered along a
-// 30-bit Morton curve, a binary radix tree is emitted directly from the sorted
-// keys (Karras, "Maximizing parallelism in the construction of BVHs, octrees and
-// k-d trees", HPG 2012), and boxes are filled bottom-up, the second child to
-// arrive at a node writing the union. Each node also gets a rope: the next node
-// in depth-first order after its subtree, which lets the traversal run without
-// a stack.
+// per level. Here every step gets a linear BVH: photons are ordered along a
+// Morton curve, a binary radix tree is emitted directly from the sorted keys
+// (Karras, "Maximizing parallelism in the construction of BVHs, octrees and k-d
+// trees", HPG 2012), and boxes are filled bottom-up, the second child to arrive at
+// a node writing the union. A node stores the boxes of its two children, so the
+// descent tests both with one load.
 //
 // One launch may cover m consecutive time steps of a beam. Photon row i at step
 // offset s is the virtual element e = s n + i; it belongs to the combined instance
@@ -22,8 +21,8 @@
 // overlapping leaves, so the shared order changes only how many nodes a query
 // visits, never the candidate set; over a few steps photons drift little against
 // each other and the order stays close to every step's own Morton order.
-// Node ids: step s owns internal nodes s (n-1) + x (x in [0, n-1)) and leaves
-// m (n-1) + s n + j (sorted position j); a leaf's link is its element s n + row.
+// Step s owns internal nodes s (n-1) + x (x: the shape's internal id); a leaf is a
+// link to its element s n + row inside its parent.
 #include <cfloat>
 #include <cmath>
 
@@ -439,7 +438,6 @@ __device__ __forceinline__ int delta(const K *__restrict__ keys, int64_t n, int6
 template <typename K>
 __global__ void __launch_bounds__(256) k_karras(const K *__restrict__ keys, int64_t n,
                                                 int prefix_shift, PRec *__restrict__ prec,
-                                                int32_t *__restrict__ split_right,
                                                 int32_t *__restrict__ inst_root) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
@@ -468,7 +466,6 @@ __global__ void __launch_bounds__(256) k_karras(const K *__restrict__ keys, int6
                               (int32_t)hi);
     reinterpret_cast<int4 *>(prec)[lc] = rl;
     reinterpret_cast<int4 *>(prec)[rc] = rr;
-    split_right[gamma] = rc;
     if (i == 0) reinterpret_cast<int4 *>(prec)[0] = make_int4(-1, 0, 0, (int32_t)(n - 1));
     if (inst_root != nullptr) {
         // node whose range is exactly one combined instance's run of keys (same prefix)
@@ -479,20 +476,16 @@ __global__ void __launch_bounds__(256) k_karras(const K *__restrict__ keys, int6
     }
 }
 
-// Global id of node x (a local id of the shared shape: internal if x < n - 1, else
-// leaf x - (n - 1)) in step s's copy; -1 (no node) stays -1.
-__device__ __forceinline__ int32_t step_node(int64_t x, int32_t s, int64_t n, int64_t nint_all) {
-    if (x < 0) return -1;
-    return (int32_t)(x < n - 1 ? (int64_t)s * (n - 1) + x : nint_all + (int64_t)s * n + (x - (n - 1)));
+// Id of the shape's internal node x in step s's copy.
+__device__ __forceinline__ int32_t step_node(int64_t x, int32_t s, int64_t n) {
+    return (int32_t)((int64_t)s * (n - 1) + x);
 }
 
-// Root of every combined instance (s, mi) and the node where its traversal ends (the
-// rope of the root). base_root: roots of the base instances written by the emission
-// (read only when there are several); an instance with one row is a leaf, the only
-// instance of a tree is the tree's root.
+// Root link of every combined instance (s, mi). base_root: roots of the base instances
+// written by the emission (read only when there are several); an instance with one row
+// is a leaf, the only instance of a tree is the tree's root (internal node 0).
 __global__ void k_inst_roots(BeamDev b, const int32_t *__restrict__ base_root,
-                             const int32_t *__restrict__ split_right, int32_t *inst_root,
-                             int32_t *inst_stop) {
+                             const uint32_t *__restrict__ rows, int32_t *inst_root) {
     const int32_t cc = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t n_comb = b.m * b.n_inst;
     if (cc >= n_comb) return;
@@ -501,15 +494,12 @@ __global__ void k_inst_roots(BeamDev b, const int32_t *__restrict__ base_root,
     const int64_t n = b.n;
     const int64_t o0 = b.n_inst > 1 ? b.inst_off[mi] : 0;
     const int64_t o1 = b.n_inst > 1 ? b.inst_off[mi + 1] : n;
-    if (o1 - o0 <= 0) {
+    if (o1 - o0 <= 0)
         inst_root[cc] = -1;
-        inst_stop[cc] = -1;
-        return;
-    }
-    const int64_t nint_all = (int64_t)b.m * (n - 1);
-    const int64_t root = (o1 - o0 == 1) ? (n - 1 + o0) : (b.n_inst == 1 ? 0 : base_root[mi]);
-    inst_root[cc] = step_node(root, s, n, nint_all);
-    inst_stop[cc] = (o1 == n) ? -1 : step_node(split_right[o1 - 1], s, n, nint_all);
+    else if (o1 - o0 == 1)
+        inst_root[cc] = leaf_link((int64_t)s * n + rows[o0]);
+    else
+        inst_root[cc] = step_node(b.n_inst == 1 ? 0 : base_root[mi], s, n);
 }
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
@@ -519,26 +509,26 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
 
 // ------------------------------------------------------------------- refit
 
-// Node stores that another thread of the same launch may read use device-scope
-// relaxed atomics (write-through, coherent across the chip's L2 slices), so a node
-// box written on one XCD is seen by the sibling's thread on another without a full L2
-// write-back fence. Ordering within a thread comes from workgroup-scope fences (wait
-// for the thread's own memory operations to complete).
-__device__ __forceinline__ void store_node_coherent(Node *n, const Node &v) {
-    unsigned long long *p = reinterpret_cast<unsigned long long *>(n);
+// Child halves that another thread of the same launch may read are stored with
+// device-scope relaxed atomics (write-through, coherent across the chip's L2 slices),
+// so a box written on one XCD is seen by the sibling's thread on another without a
+// full L2 write-back fence. Ordering within a thread comes from workgroup-scope fences
+// (wait for the thread's own memory operations to complete).
+__device__ __forceinline__ void store_half_coherent(Half *h, const Half &v) {
+    unsigned long long *p = reinterpret_cast<unsigned long long *>(h);
     const unsigned long long *s = reinterpret_cast<const unsigned long long *>(&v);
 #pragma unroll
     for (int k = 0; k < 4; ++k) __hip_atomic_store(p + k, s[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void store_node_plain(Node *n, const Node &v) {
-    float4 *p = reinterpret_cast<float4 *>(n);
+__device__ __forceinline__ void store_half_plain(Half *h, const Half &v) {
+    float4 *p = reinterpret_cast<float4 *>(h);
     p[0] = make_float4(v.lox, v.loy, v.loz, __int_as_float(v.link));
-    p[1] = make_float4(v.hix, v.hiy, v.hiz, __int_as_float(v.rope));
+    p[1] = make_float4(v.hix, v.hiy, v.hiz, 0.0f);
 }
 
-__device__ __forceinline__ void load_box(const Node *n, float lo[3], float hi[3]) {
-    const unsigned long long *p = reinterpret_cast<const unsigned long long *>(n);
+__device__ __forceinline__ void load_half_box(const Half *h, float lo[3], float hi[3]) {
+    const unsigned long long *p = reinterpret_cast<const unsigned long long *>(h);
     unsigned long long w[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -552,36 +542,41 @@ __device__ __forceinline__ void load_box(const Node *n, float lo[3], float hi[3]
     hi[2] = __uint_as_float((uint32_t)w[3]);
 }
 
+__device__ __forceinline__ Half merge_halves(const Half &a, const float lo[3], const float hi[3],
+                                             int32_t link) {
+    Half u;
+    u.lox = fminf(a.lox, lo[0]); u.loy = fminf(a.loy, lo[1]); u.loz = fminf(a.loz, lo[2]);
+    u.hix = fmaxf(a.hix, hi[0]); u.hiy = fmaxf(a.hiy, hi[1]); u.hiz = fmaxf(a.hiz, hi[2]);
+    u.link = link;
+    u.pad = 0;
+    return u;
+}
+
 constexpr int kRefitChunk = 512;  // leaves (and threads) per workgroup
 constexpr int kRefitSlots = 64;   // hand-offs to the crossing-level kernel per workgroup
 
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
-// Climb from node cur (local id; r: its record; cn: its node) through parents whose
-// ranges cross chunks, with global arrival flags and device-coherent node stores and
-// loads: the first of two children to arrive leaves, the second merges. `stored`: cur's
-// node is already visible device-wide (written by an earlier kernel). A radix tree over
-// (key, index) pairs is at most 96 levels deep; the bound only guards.
-__device__ __forceinline__ void climb_crossing(int32_t cur, Node cn, i32x4 r, bool stored,
-                                               int32_t step, int64_t n, int64_t nint_all,
-                                               const i32x4 *__restrict__ grec,
-                                               const int32_t *__restrict__ split_right,
-                                               int32_t *flags, Node *nodes, unsigned int *err) {
+// Climb from node cur (the shape's local id; r: its record; cn: its box and link as its
+// parent holds them) through parents whose ranges cross chunks, with global arrival
+// flags and device-coherent stores and loads of the child halves: the first of two
+// children to arrive leaves, the second merges. `stored`: cn is already in the parent
+// and visible device-wide (written by an earlier kernel). A radix tree over (key,
+// index) pairs is at most 96 levels deep; the bound only guards.
+__device__ __forceinline__ void climb_crossing(int32_t cur, Half cn, i32x4 r, bool stored,
+                                               int32_t step, int64_t n,
+                                               const i32x4 *__restrict__ grec, int32_t *flags,
+                                               Node *nodes, unsigned int *err) {
     for (int level = 0;; ++level) {
         const int32_t p = r.x;
-        if (p < 0) {
-            if (!stored) store_node_plain(nodes + step_node(cur, step, n, nint_all), cn);
-            return;
-        }
+        if (p < 0) return;  // cur is the root: its own box is kept nowhere
         if (level > 128) {
             atomicOr(err, kErrSpin);
             return;
         }
-        const int32_t phi = r.w;
-        const bool is_right = r.y < 0;
-        const int32_t sib = (int32_t)((uint32_t)r.y & 0x7fffffffu);
-        const int32_t prope = (phi == n - 1) ? -1 : split_right[phi];
-        if (!stored) store_node_coherent(nodes + step_node(cur, step, n, nint_all), cn);
+        const int side = r.y < 0 ? 1 : 0;
+        Node *pn = nodes + step_node(p, step, n);
+        if (!stored) store_half_coherent(&pn->c[side], cn);
         stored = false;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         const int32_t old = __hip_atomic_fetch_add(flags + p, 1, __ATOMIC_RELAXED,
@@ -589,36 +584,29 @@ __device__ __forceinline__ void climb_crossing(int32_t cur, Node cn, i32x4 r, bo
         if (old == 0) return;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         float slo[3], shi[3];
-        load_box(nodes + step_node(sib, step, n, nint_all), slo, shi);
-        Node u;
-        u.lox = fminf(cn.lox, slo[0]); u.loy = fminf(cn.loy, slo[1]); u.loz = fminf(cn.loz, slo[2]);
-        u.hix = fmaxf(cn.hix, shi[0]); u.hiy = fmaxf(cn.hiy, shi[1]); u.hiz = fmaxf(cn.hiz, shi[2]);
-        u.link = step_node(is_right ? sib : cur, step, n, nint_all);
-        u.rope = step_node(prope, step, n, nint_all);
-        cn = u;
+        load_half_box(&pn->c[side ^ 1], slo, shi);
+        cn = merge_halves(cn, slo, shi, step_node(p, step, n));
         cur = p;
         r = grec[cur];
     }
 }
 
-// Bottom-up box refit in two regimes, for the m steps that share one tree shape (a
-// workgroup works on one step; records, split targets and sorted rows are the shared
-// shape's, boxes, node stores and arrival flags the step's). A workgroup owns a chunk
-// of consecutive leaves; every internal node whose leaf range lies inside the chunk has
-// its id in the chunk too (a node's id is one end of its range). The chunk's parent
-// records, leaf boxes and split targets are staged in LDS first, so the levels inside
-// the chunk touch no global memory but their node stores: the arrival flag and the box
-// of such a node live in LDS, and the second child to arrive merges the boxes there.
-// A node whose parent crosses the chunk boundary is stored and handed to the
-// crossing-level kernel through the workgroup's slots (the climb above it needs device
-// atomics and coherent loads whose latency would otherwise keep this LDS-heavy
+// Bottom-up box refit for the m steps that share one tree shape (a workgroup works on
+// one step; records and sorted rows are the shared shape's, boxes, node stores and
+// arrival flags the step's). Every node writes its box and link into its half of its
+// parent. A workgroup owns a chunk of consecutive leaves; every internal node whose
+// leaf range lies inside the chunk has its id in the chunk too (a node's id is one end
+// of its range). The chunk's parent records and leaf boxes are staged in LDS first, so
+// the levels inside the chunk touch no global memory but their stores: the arrival
+// flag and the box of such a node live in LDS, and the second child to arrive merges
+// the boxes there. A node whose parent crosses the chunk boundary is stored and handed
+// to the crossing-level kernel through the workgroup's slots (the climb above it needs
+// device atomics and coherent loads whose latency would otherwise keep this LDS-heavy
 // workgroup resident for one thread); with the slots full, or none given, the thread
 // climbs on itself.
 __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ box,
                                                        const uint32_t *__restrict__ rows, int64_t n,
-                                                       int32_t m, int64_t chunks,
-                                                       const PRec *__restrict__ prec,
-                                                       const int32_t *__restrict__ split_right,
+                                                       int64_t chunks, const PRec *__restrict__ prec,
                                                        int32_t *flags, Node *nodes,
                                                        int32_t *__restrict__ slots,
                                                        unsigned int *err) {
@@ -627,12 +615,10 @@ __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ 
     __shared__ int32_t s_flag[kRefitChunk];
     // records: [0, chunk) the chunk's leaves, [chunk, 2 chunk) internal ids in the chunk
     __shared__ i32x4 s_rec[2 * kRefitChunk];
-    __shared__ int32_t s_split[kRefitChunk];
     __shared__ int32_t s_nslot;
     const i32x4 *grec = reinterpret_cast<const i32x4 *>(prec);
     const int32_t step = (int32_t)(blockIdx.x / chunks);
     const int64_t c0 = (blockIdx.x - (int64_t)step * chunks) * kRefitChunk;
-    const int64_t nint_all = (int64_t)m * (n - 1);
     box += (int64_t)step * n;
     flags += (int64_t)step * (n - 1);
     const int64_t c1 = (c0 + kRefitChunk < n ? c0 + kRefitChunk : n) - 1;  // last leaf of the chunk
@@ -643,51 +629,38 @@ __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ 
     if (slots != nullptr && tid < kRefitSlots) slots[(int64_t)blockIdx.x * kRefitSlots + tid] = -1;
     const int64_t j = c0 + tid;
     const bool in = j < n;
-    Node cn;  // node of `cur`, not yet stored
+    Half cn;  // box and link of `cur` as its parent holds them, not yet stored
     int32_t cur = -1;
     if (in) {
         // independent loads first, the box gather (needs the row) last
         const uint32_t row = rows[j];
-        i32x4 rl = {0, 0, 0, 0}, ri = {0, 0, 0, 0};
-        if (n > 1) {
-            rl = grec[leaf0 + j];
-            if (j < leaf0) ri = grec[j];
-        }
-        const int32_t sr = (j == n - 1) ? -1 : split_right[j];
+        const i32x4 rl = grec[leaf0 + j];
+        const i32x4 ri = (j < leaf0) ? grec[j] : i32x4{0, 0, 0, 0};
         const PBox bx = box[row];
         s_rec[tid] = rl;
         s_rec[kRefitChunk + tid] = ri;
-        s_split[tid] = sr;
         cn.lox = bx.lox; cn.loy = bx.loy; cn.loz = bx.loz;
         cn.hix = bx.hix; cn.hiy = bx.hiy; cn.hiz = bx.hiz;
-        cn.link = (int32_t)((int64_t)step * n + row);
-        cn.rope = step_node(sr, step, n, nint_all);
+        cn.link = leaf_link((int64_t)step * n + row);
+        cn.pad = 0;
         cur = (int32_t)(leaf0 + j);
         s_leaf[0][tid] = cn.lox; s_leaf[1][tid] = cn.loy; s_leaf[2][tid] = cn.loz;
         s_leaf[3][tid] = cn.hix; s_leaf[4][tid] = cn.hiy; s_leaf[5][tid] = cn.hiz;
     }
     __syncthreads();
     if (!in) return;
-    if (n == 1) {  // a single leaf is the root (no hierarchy was emitted)
-        store_node_plain(nodes + step_node(cur, step, n, nint_all), cn);
-        return;
-    }
     // Inside the chunk: cur is one of the chunk's leaves (first level) or an internal
     // node with its id in the chunk, so its record is in LDS.
     i32x4 r;
     for (;;) {
         r = s_rec[cur >= leaf0 ? (int32_t)(cur - leaf0 - c0) : (int32_t)(kRefitChunk + cur - c0)];
         const int32_t p = r.x;
-        if (p < 0) {  // cur is the root
-            store_node_plain(nodes + step_node(cur, step, n, nint_all), cn);
-            return;
-        }
+        if (p < 0) return;  // cur is the root
         const int32_t plo = r.z, phi = r.w;
         if (!(plo >= c0 && phi <= c1)) break;  // the parent crosses the chunk
-        const bool is_right = r.y < 0;
+        const int side = r.y < 0 ? 1 : 0;
         const int32_t sib = (int32_t)((uint32_t)r.y & 0x7fffffffu);
-        const int32_t prope = (phi == n - 1) ? -1 : s_split[phi - c0];
-        store_node_plain(nodes + step_node(cur, step, n, nint_all), cn);
+        store_half_plain(&nodes[step_node(p, step, n)].c[side], cn);
         if (cur < leaf0) {
             const int64_t k = cur - c0;
             s_int[0][k] = cn.lox; s_int[1][k] = cn.loy; s_int[2][k] = cn.loz;
@@ -706,47 +679,41 @@ __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ 
             slo[a] = sleaf ? s_leaf[a][k] : s_int[a][k];
             shi[a] = sleaf ? s_leaf[3 + a][k] : s_int[3 + a][k];
         }
-        Node u;
-        u.lox = fminf(cn.lox, slo[0]); u.loy = fminf(cn.loy, slo[1]); u.loz = fminf(cn.loz, slo[2]);
-        u.hix = fmaxf(cn.hix, shi[0]); u.hiy = fmaxf(cn.hiy, shi[1]); u.hiz = fmaxf(cn.hiz, shi[2]);
-        u.link = step_node(is_right ? sib : cur, step, n, nint_all);
-        u.rope = step_node(prope, step, n, nint_all);
-        cn = u;
+        cn = merge_halves(cn, slo, shi, step_node(p, step, n));
         cur = p;
     }
     if (slots != nullptr) {
         const int k = atomicAdd(&s_nslot, 1);
         if (k < kRefitSlots) {
-            store_node_plain(nodes + step_node(cur, step, n, nint_all), cn);
+            store_half_plain(&nodes[step_node(r.x, step, n)].c[r.y < 0 ? 1 : 0], cn);
             slots[(int64_t)blockIdx.x * kRefitSlots + k] = cur;
             return;
         }
     }
-    climb_crossing(cur, cn, r, false, step, n, nint_all, grec, split_right, flags, nodes, err);
+    climb_crossing(cur, cn, r, false, step, n, grec, flags, nodes, err);
 }
 
 // Crossing levels of the refit: one thread per hand-off slot of k_refit (slot s of
-// workgroup w at w kRefitSlots + s; -1: unused). The handed-off node was stored by
-// k_refit, so it is visible here.
+// workgroup w at w kRefitSlots + s; -1: unused). The handed-off node's half was stored
+// in its parent by k_refit, so it is visible here.
 __global__ void __launch_bounds__(256) k_refit_top(const int32_t *__restrict__ slots,
-                                                   int64_t n_slots, int64_t n, int32_t m,
-                                                   int64_t chunks, const PRec *__restrict__ prec,
-                                                   const int32_t *__restrict__ split_right,
-                                                   int32_t *flags, Node *nodes, unsigned int *err) {
+                                                   int64_t n_slots, int64_t n, int64_t chunks,
+                                                   const PRec *__restrict__ prec, int32_t *flags,
+                                                   Node *nodes, unsigned int *err) {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (idx >= n_slots) return;
     const int32_t cur = slots[idx];
     if (cur < 0) return;
     const int32_t step = (int32_t)((idx / kRefitSlots) / chunks);
-    const int64_t nint_all = (int64_t)m * (n - 1);
     const i32x4 *grec = reinterpret_cast<const i32x4 *>(prec);
-    const float4 *np = reinterpret_cast<const float4 *>(nodes + step_node(cur, step, n, nint_all));
-    const float4 a = np[0], b = np[1];
-    Node cn;
+    const i32x4 r = grec[cur];
+    const float4 *hp = reinterpret_cast<const float4 *>(
+        &nodes[step_node(r.x, step, n)].c[r.y < 0 ? 1 : 0]);
+    const float4 a = hp[0], b = hp[1];
+    Half cn;
     cn.lox = a.x; cn.loy = a.y; cn.loz = a.z; cn.link = __float_as_int(a.w);
-    cn.hix = b.x; cn.hiy = b.y; cn.hiz = b.z; cn.rope = __float_as_int(b.w);
-    climb_crossing(cur, cn, grec[cur], true, step, n, nint_all, grec, split_right,
-                   flags + (int64_t)step * (n - 1), nodes, err);
+    cn.hix = b.x; cn.hiy = b.y; cn.hiz = b.z; cn.pad = 0;
+    climb_crossing(cur, cn, r, true, step, n, grec, flags + (int64_t)step * (n - 1), nodes, err);
 }
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
@@ -833,25 +800,25 @@ void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint3
 }
 
 void launch_karras_u32(const uint32_t *keys, int64_t n, int prefix_shift, PRec *prec,
-                       int32_t *split_right, int32_t *inst_root, hipStream_t st) {
+                       int32_t *inst_root, hipStream_t st) {
     if (n <= 1) return;
     hipLaunchKernelGGL(k_karras<uint32_t>, dim3(grid_for(n - 1, 256)), dim3(256), 0, st, keys, n,
-                       prefix_shift, prec, split_right, inst_root);
+                       prefix_shift, prec, inst_root);
 }
 
 void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shift, PRec *prec,
-                       int32_t *split_right, int32_t *inst_root, hipStream_t st) {
+                       int32_t *inst_root, hipStream_t st) {
     if (n <= 1) return;
     hipLaunchKernelGGL(k_karras<unsigned long long>, dim3(grid_for(n - 1, 256)), dim3(256), 0, st,
-                       keys, n, prefix_shift, prec, split_right, inst_root);
+                       keys, n, prefix_shift, prec, inst_root);
 }
 
-void launch_inst_roots(const BeamDev &b, const int32_t *base_root, const int32_t *split_right,
-                       int32_t *inst_root, int32_t *inst_stop, hipStream_t st) {
+void launch_inst_roots(const BeamDev &b, const int32_t *base_root, const uint32_t *sorted_rows,
+                       int32_t *inst_root, hipStream_t st) {
     const int32_t n_comb = b.m * b.n_inst;
     if (n_comb <= 0) return;
     hipLaunchKernelGGL(k_inst_roots, dim3(grid_for(n_comb, 64)), dim3(64), 0, st, b, base_root,
-                       split_right, inst_root, inst_stop);
+                       sorted_rows, inst_root);
 }
 
 int64_t refit_slots_needed(int64_t n, int32_t m) {
@@ -860,20 +827,19 @@ int64_t refit_slots_needed(int64_t n, int32_t m) {
 }
 
 void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, int32_t m,
-                  const PRec *prec, const int32_t *split_right, int32_t *flags, Node *nodes,
-                  int32_t *slots, int64_t slot_cap, unsigned int *err, hipStream_t st) {
-    if (n <= 0 || m <= 0) return;
-    if (n > 1)
-        hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)m * (n - 1), 256)), dim3(256), 0, st,
-                           flags, 0, (int64_t)m * (n - 1));
+                  const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots,
+                  int64_t slot_cap, unsigned int *err, hipStream_t st) {
+    if (n <= 1 || m <= 0) return;  // no internal node: a single leaf is its step's root
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)m * (n - 1), 256)), dim3(256), 0, st,
+                       flags, 0, (int64_t)m * (n - 1));
     const int64_t chunks = (n + kRefitChunk - 1) / kRefitChunk;
     const int64_t n_slots = refit_slots_needed(n, m);
     if (slots == nullptr || n_slots == 0 || n_slots > slot_cap) slots = nullptr;
     hipLaunchKernelGGL(k_refit, dim3((unsigned)(chunks * m)), dim3(kRefitChunk), 0, st, box,
-                       sorted_rows, n, m, chunks, prec, split_right, flags, nodes, slots, err);
+                       sorted_rows, n, chunks, prec, flags, nodes, slots, err);
     if (slots != nullptr)
         hipLaunchKernelGGL(k_refit_top, dim3(grid_for(n_slots, 256)), dim3(256), 0, st, slots,
-                           n_slots, n, m, chunks, prec, split_right, flags, nodes, err);
+                           n_slots, n, chunks, prec, flags, nodes, err);
 }
 
 }  // namespace tril

@@ -156,18 +156,54 @@ __device__ __forceinline__ double st_yield(const BeamDev &q, int64_t i, const Be
     return (((((q.w[i] * t.w[j]) / (V * V)) * bw_sigma(s)) * (1.0 - cphi)) * dt) * vov;
 }
 
+// One overlapping leaf of the cloud traversal: the pair's yield, accumulated per run
+// of equal bin-pair keys (consecutive leaves of a query mostly share a target bin).
+__device__ __forceinline__ void st_leaf(const BeamDev &q, int64_t i, const BeamDev &t, int64_t e,
+                                        int64_t so, double tk, double dt, const StCell &cell,
+                                        int geometric, int32_t bq,
+                                        const int32_t *__restrict__ t_bins, int64_t n_t_bins,
+                                        const long long *__restrict__ filter, uint64_t fmask,
+                                        long long *keys, double *vals, uint64_t mask,
+                                        long long &cur_key, double &acc, double &lane_total,
+                                        uint32_t &n_pairs, DevCounters *c) {
+    const int64_t j = e - so * t.n;
+    const int32_t bt = t_bins[j];
+    const long long key = (long long)bq * n_t_bins + bt;
+    const bool keep = bt >= 0 && (filter == nullptr || set_has(filter, fmask, key));
+    const double Y = keep ? st_yield(q, i, t, j, tk, dt, cell, geometric) : 0.0;
+    if (Y > 0.0) {
+        ++n_pairs;
+        lane_total += Y;
+        if (key != cur_key) {
+            if (cur_key >= 0) table_add(keys, vals, mask, cur_key, acc, &c->err);
+            cur_key = key;
+            acc = Y;
+        } else {
+            acc += Y;
+        }
+    }
+}
+
+__device__ __forceinline__ bool st_overlap(const float q[6], float4 lo, float4 hi) {
+    return (q[0] <= hi.x) & (q[3] >= lo.x) & (q[1] <= hi.y) & (q[4] >= lo.y) & (q[2] <= hi.z) &
+           (q[5] >= lo.z);
+}
+
+constexpr int kStStack = 128;  // deeper than any radix tree over (key, index) pairs
+
+// Descent as in the broad phase of the exact regime (one load per overlapped internal
+// node, both children tested from it, pending right children on a per-lane stack).
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_st_traverse(
-    const Node *__restrict__ nodes, int32_t n_int, const PBox *__restrict__ qbox,
-    const uint32_t *__restrict__ qorder, int64_t order_len, int64_t nq, int64_t nq_base,
-    const int32_t *__restrict__ inst_root,
-    const int32_t *__restrict__ inst_stop, BeamDev q, BeamDev t, const int32_t *__restrict__ q_bins,
-    const int32_t *__restrict__ t_bins, int64_t n_t_bins, double dt, StCell cell, int geometric,
-    const long long *__restrict__ filter, uint64_t fmask, long long *keys, double *vals,
-    uint64_t mask, double *__restrict__ slots, DevCounters *c) {
+    const Node *__restrict__ nodes, int32_t n_int, const PBox *__restrict__ leaf_box,
+    const PBox *__restrict__ qbox, const uint32_t *__restrict__ qorder, int64_t order_len,
+    int64_t nq, int64_t nq_base, const int32_t *__restrict__ inst_root, BeamDev q, BeamDev t,
+    const int32_t *__restrict__ q_bins, const int32_t *__restrict__ t_bins, int64_t n_t_bins,
+    double dt, StCell cell, int geometric, const long long *__restrict__ filter, uint64_t fmask,
+    long long *keys, double *vals, uint64_t mask, double *__restrict__ slots, DevCounters *c) {
     const int64_t e = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
-    int32_t node = -1, stop = -1, qi = 0;
-    float lx = 0.f, ly = 0.f, lz = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
+    int32_t node = -1, qi = 0;
+    float qb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (e < nq) {
         if (qorder == nullptr) {
             qi = (int32_t)e;
@@ -179,53 +215,62 @@ __global__ void __launch_bounds__(BLOCK) k_st_traverse(
         }
         const float4 *bp = reinterpret_cast<const float4 *>(qbox + qi);
         const float4 a = bp[0], b = bp[1];
-        lx = a.x; ly = a.y; lz = a.z;
-        hx = b.x; hy = b.y; hz = b.z;
+        qb[0] = a.x; qb[1] = a.y; qb[2] = a.z;
+        qb[3] = b.x; qb[4] = b.y; qb[5] = b.z;
         const int32_t tag = __float_as_int(a.w);
-        if (tag >= 0) {
-            node = inst_root[tag];
-            stop = inst_stop[tag];
-        }
+        if (tag >= 0) node = inst_root[tag];
     }
     const int64_t so = q.m > 1 ? (int64_t)qi / q.n : 0;
     const int64_t i = (int64_t)qi - so * q.n;
     const double tk = (double)((int64_t)c->step + so) * dt;
-    const int32_t bq = node >= 0 ? q_bins[i] : -1;
+    const int32_t bq = node != -1 ? q_bins[i] : -1;
     if (bq < 0) node = -1;
     long long cur_key = -1;
     double acc = 0.0, lane_total = 0.0;
     uint32_t visits = 0, n_pairs = 0;
-    const uint32_t max_visits = 2u * (uint32_t)n_int + 2u;
-    while (node >= 0 && node != stop) {
+    if (node <= -2) {  // an instance of one row: its root is that leaf
+        const int64_t el = link_elem(node);
+        const float4 *lp = reinterpret_cast<const float4 *>(leaf_box + el);
+        ++visits;
+        if (st_overlap(qb, lp[0], lp[1]))
+            st_leaf(q, i, t, el, so, tk, dt, cell, geometric, bq, t_bins, n_t_bins, filter, fmask,
+                    keys, vals, mask, cur_key, acc, lane_total, n_pairs, c);
+        node = -1;
+    }
+    int32_t stack[kStStack];
+    int32_t depth = 0;
+    const uint32_t max_visits = (uint32_t)n_int + 2u;
+    while (node >= 0) {
         if (visits > max_visits) {
             atomicOr(&c->err, kErrSpin);
             break;
         }
         const float4 *np = reinterpret_cast<const float4 *>(nodes + node);
-        const float4 a = np[0], b = np[1];
+        const float4 l0 = np[0], l1 = np[1], r0 = np[2], r1 = np[3];
         ++visits;
-        const bool ov = (lx <= b.x) & (hx >= a.x) & (ly <= b.y) & (hy >= a.y) & (lz <= b.z) &
-                        (hz >= a.z);
-        const bool leaf = node >= n_int;
-        if (ov && leaf) {
-            const int64_t j = (int64_t)__float_as_int(a.w) - so * t.n;
-            const int32_t bt = t_bins[j];
-            const long long key = (long long)bq * n_t_bins + bt;
-            const bool keep = bt >= 0 && (filter == nullptr || set_has(filter, fmask, key));
-            const double Y = keep ? st_yield(q, i, t, j, tk, dt, cell, geometric) : 0.0;
-            if (Y > 0.0) {
-                ++n_pairs;
-                lane_total += Y;
-                if (key != cur_key) {
-                    if (cur_key >= 0) table_add(keys, vals, mask, cur_key, acc, &c->err);
-                    cur_key = key;
-                    acc = Y;
-                } else {
-                    acc += Y;
+        const int32_t lc = __float_as_int(l0.w), rc = __float_as_int(r0.w);
+        const bool ovl = st_overlap(qb, l0, l1), ovr = st_overlap(qb, r0, r1);
+        if (ovl && lc < 0)
+            st_leaf(q, i, t, link_elem(lc), so, tk, dt, cell, geometric, bq, t_bins, n_t_bins,
+                    filter, fmask, keys, vals, mask, cur_key, acc, lane_total, n_pairs, c);
+        if (ovr && rc < 0)
+            st_leaf(q, i, t, link_elem(rc), so, tk, dt, cell, geometric, bq, t_bins, n_t_bins,
+                    filter, fmask, keys, vals, mask, cur_key, acc, lane_total, n_pairs, c);
+        const bool gol = ovl && lc >= 0, gor = ovr && rc >= 0;
+        if (gol) {
+            if (gor) {
+                if (depth >= kStStack) {
+                    atomicOr(&c->err, kErrSpin);
+                    break;
                 }
+                stack[depth++] = rc;
             }
+            node = lc;
+        } else if (gor) {
+            node = rc;
+        } else {
+            node = depth > 0 ? stack[--depth] : -1;
         }
-        node = (ov && !leaf) ? __float_as_int(a.w) : __float_as_int(b.w);
     }
     if (cur_key >= 0) table_add(keys, vals, mask, cur_key, acc, &c->err);
     // per-wave sums into spread slots
@@ -486,9 +531,9 @@ void launch_st_clear(long long *keys, double *vals, int64_t cap, double *slots, 
     hipLaunchKernelGGL(k_st_clear, dim3(grid_for(n, 256)), dim3(256), 0, st, keys, vals, cap, slots);
 }
 
-void launch_st_traverse(const Node *nodes, int64_t n_int64, const PBox *qbox, const uint32_t *qorder,
-                        int64_t order_len, int64_t nq, int64_t nq_base,
-                        const int32_t *inst_root, const int32_t *inst_stop,
+void launch_st_traverse(const Node *nodes, int64_t n_int64, const PBox *leaf_box, const PBox *qbox,
+                        const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
+                        const int32_t *inst_root,
                         const BeamDev &q, const BeamDev &t, const int32_t *q_bins,
                         const int32_t *t_bins, int64_t n_t_bins, double dt, const StCell &cell,
                         int geometric, const long long *filter, int64_t filter_cap,
@@ -497,7 +542,8 @@ void launch_st_traverse(const Node *nodes, int64_t n_int64, const PBox *qbox, co
     if (nq <= 0 || n_int64 < 0) return;
     const int32_t n_int = (int32_t)n_int64;
     hipLaunchKernelGGL(k_st_traverse<256>, dim3(grid_for(nq, 256)), dim3(256), 0, st, nodes, n_int,
-                       qbox, qorder, order_len, nq, nq_base, inst_root, inst_stop, q, t, q_bins, t_bins, n_t_bins, dt,
+                       leaf_box, qbox, qorder, order_len, nq, nq_base, inst_root, q, t, q_bins,
+                       t_bins, n_t_bins, dt,
                        cell, geometric, filter, (uint64_t)(filter ? filter_cap - 1 : 0), keys, vals,
                        (uint64_t)(cap - 1), slots, c);
 }

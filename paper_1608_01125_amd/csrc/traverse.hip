@@ -1,8 +1,11 @@
 // Broad phase: every query photon's swept, radius-padded box descends the
 // target hierarchy depth-first (Sec. 2.2): a node whose box fails the overlap
 // test (Eq. 5) has its whole subtree skipped; a leaf whose box passes yields a
-// candidate pair. The descent follows ropes (next node in depth-first order),
-// so a lane needs no stack: overlap -> left child, otherwise -> rope.
+// candidate pair. A node holds its two children's boxes, so one 64-byte load tests
+// both: a child that fails is never loaded, and the descent costs one dependent load
+// per internal node whose box the query overlaps. When both children are internal and
+// overlap, the right one waits on a per-lane stack (four entries in registers, the
+// rest in a private spill array).
 //
 // The overlap test is closed (<=) on both sides, so touching boxes stay
 // candidates; boxes are rounded outward, so the candidate set contains every
@@ -22,19 +25,52 @@ __device__ __forceinline__ uint32_t count_below(unsigned long long mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Wave-compacted append of the candidates (qi, j) of the lanes with emit set; called by
+// every active lane of the wave.
+__device__ __forceinline__ void emit_candidate(bool emit, int32_t qi, int64_t j,
+                                               int32_t *__restrict__ cand_i,
+                                               int32_t *__restrict__ cand_j, int64_t cand_cap,
+                                               DevCounters *c) {
+    const unsigned long long m = __ballot(emit);
+    if (m == 0ull) return;
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned long long base = 0;
+    if (emit && count_below(m) == 0) {
+        const unsigned long long cnt = (unsigned long long)__popcll(m);
+        base = atomicAdd(&c->cand_step, cnt);
+        if (base + cnt > (unsigned long long)cand_cap) atomicOr(&c->err, kErrCandOverflow);
+    }
+    base = __shfl(base, leader);
+    if (emit) {
+        const unsigned long long pos = base + count_below(m);
+        if (pos < (unsigned long long)cand_cap) {
+            cand_i[pos] = qi;
+            cand_j[pos] = (int32_t)j;
+        }
+    }
+}
+
+__device__ __forceinline__ bool box_overlap(const float q[6], float4 lo, float4 hi) {
+    return (q[0] <= hi.x) & (q[3] >= lo.x) & (q[1] <= hi.y) & (q[4] >= lo.y) & (q[2] <= hi.z) &
+           (q[5] >= lo.z);
+}
+
+constexpr int kStackRegs = 4;
+constexpr int kStackSpill = 124;  // deeper than any radix tree over (key, index) pairs
+
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nodes, int32_t n_int,
+                                                    const PBox *__restrict__ leaf_box,
                                                     const PBox *__restrict__ qbox,
                                                     const uint32_t *__restrict__ qorder,
                                                     int64_t order_len, int64_t nq, int64_t nq_base,
                                                     const int32_t *__restrict__ inst_root,
-                                                    const int32_t *__restrict__ inst_stop,
                                                     int32_t *__restrict__ cand_i,
                                                     int32_t *__restrict__ cand_j, int64_t cand_cap,
                                                     DevCounters *c) {
     const int64_t q = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
-    int32_t node = -1, stop = -1, qi = 0;
-    float lx = 0.f, ly = 0.f, lz = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
+    int32_t node = -1, qi = 0;
+    float qb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (q < nq) {
         if (qorder == nullptr) {
             qi = (int32_t)q;
@@ -46,49 +82,68 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
         }
         const float4 *bp = reinterpret_cast<const float4 *>(qbox + qi);
         const float4 a = bp[0], b = bp[1];
-        lx = a.x; ly = a.y; lz = a.z;
-        hx = b.x; hy = b.y; hz = b.z;
+        qb[0] = a.x; qb[1] = a.y; qb[2] = a.z;
+        qb[3] = b.x; qb[4] = b.y; qb[5] = b.z;
         const int32_t tag = __float_as_int(a.w);
-        if (tag >= 0) {
-            node = inst_root[tag];
-            stop = inst_stop[tag];
-        }
+        if (tag >= 0) node = inst_root[tag];
     }
-    const unsigned long long active_q = __ballot(node >= 0);
+    const unsigned long long active_q = __ballot(node != -1);
     uint32_t visits = 0;
-    // every node is visited at most once per query in a well-formed tree
-    const uint32_t max_visits = 2u * (uint32_t)n_int + 2u;
-    while (node >= 0 && node != stop) {
+    {
+        // an instance of one row: its root is that leaf
+        bool hit = false;
+        int64_t e = 0;
+        if (node <= -2) {
+            e = link_elem(node);
+            const float4 *lp = reinterpret_cast<const float4 *>(leaf_box + e);
+            hit = box_overlap(qb, lp[0], lp[1]);
+            ++visits;
+            node = -1;
+        }
+        emit_candidate(hit, qi, e, cand_i, cand_j, cand_cap, c);
+    }
+    int32_t st0 = -1, st1 = -1, st2 = -1, st3 = -1;
+    int32_t spill[kStackSpill];
+    int32_t depth = 0;
+    // every internal node is loaded at most once per query in a well-formed tree
+    const uint32_t max_visits = (uint32_t)n_int + 2u;
+    while (node >= 0) {
         if (visits > max_visits) {
             atomicOr(&c->err, kErrSpin);
             break;
         }
         const float4 *np = reinterpret_cast<const float4 *>(nodes + node);
-        const float4 a = np[0], b = np[1];
+        const float4 l0 = np[0], l1 = np[1], r0 = np[2], r1 = np[3];
         ++visits;
-        const bool ov = (lx <= b.x) & (hx >= a.x) & (ly <= b.y) & (hy >= a.y) & (lz <= b.z) &
-                        (hz >= a.z);
-        const bool leaf = node >= n_int;
-        const bool emit = ov & leaf;
-        const unsigned long long m = __ballot(emit);
-        if (m) {
-            const int leader = __ffsll((long long)m) - 1;
-            unsigned long long base = 0;
-            if (emit && count_below(m) == 0) {
-                const unsigned long long cnt = (unsigned long long)__popcll(m);
-                base = atomicAdd(&c->cand_step, cnt);
-                if (base + cnt > (unsigned long long)cand_cap) atomicOr(&c->err, kErrCandOverflow);
-            }
-            base = __shfl(base, leader);
-            if (emit) {
-                const unsigned long long pos = base + count_below(m);
-                if (pos < (unsigned long long)cand_cap) {
-                    cand_i[pos] = qi;
-                    cand_j[pos] = __float_as_int(a.w);
+        const int32_t lc = __float_as_int(l0.w), rc = __float_as_int(r0.w);
+        const bool ovl = box_overlap(qb, l0, l1), ovr = box_overlap(qb, r0, r1);
+        const bool leafl = lc < 0, leafr = rc < 0;
+        emit_candidate(ovl & leafl, qi, link_elem(lc), cand_i, cand_j, cand_cap, c);
+        emit_candidate(ovr & leafr, qi, link_elem(rc), cand_i, cand_j, cand_cap, c);
+        const bool gol = ovl & !leafl, gor = ovr & !leafr;
+        if (gol) {
+            if (gor) {  // push the right child
+                if (depth >= kStackRegs) {
+                    if (depth - kStackRegs >= kStackSpill) {
+                        atomicOr(&c->err, kErrSpin);
+                        break;
+                    }
+                    spill[depth - kStackRegs] = st3;
                 }
+                st3 = st2; st2 = st1; st1 = st0; st0 = rc;
+                ++depth;
             }
+            node = lc;
+        } else if (gor) {
+            node = rc;
+        } else if (depth > 0) {  // pop
+            node = st0;
+            st0 = st1; st1 = st2; st2 = st3;
+            --depth;
+            if (depth >= kStackRegs) st3 = spill[depth - kStackRegs];
+        } else {
+            node = -1;
         }
-        node = (ov && !leaf) ? __float_as_int(a.w) : __float_as_int(b.w);
     }
     // per-wave counter updates
     unsigned long long v = visits;
@@ -103,30 +158,33 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
 
 }  // namespace
 
-void launch_traverse(const Node *nodes, int64_t n_int64, const PBox *qbox, const uint32_t *qorder,
-                     int64_t order_len, int64_t nq, int64_t nq_base,
-                     const int32_t *inst_root, const int32_t *inst_stop,
-                     int32_t *cand_i, int32_t *cand_j, int64_t cand_cap, DevCounters *c, int block,
-                     hipStream_t st) {
+void launch_traverse(const Node *nodes, int64_t n_int64, const PBox *leaf_box, const PBox *qbox,
+                     const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
+                     const int32_t *inst_root, int32_t *cand_i, int32_t *cand_j,
+                     int64_t cand_cap, DevCounters *c, int block, hipStream_t st) {
     if (nq <= 0 || n_int64 < 0) return;
     const int32_t n_int = (int32_t)n_int64;
     const unsigned grid = (unsigned)((nq + block - 1) / block);
     switch (block) {
     case 64:
-        hipLaunchKernelGGL(k_traverse<64>, dim3(grid), dim3(64), 0, st, nodes, n_int, qbox, qorder,
-                           order_len, nq, nq_base, inst_root, inst_stop, cand_i, cand_j, cand_cap, c);
+        hipLaunchKernelGGL(k_traverse<64>, dim3(grid), dim3(64), 0, st, nodes, n_int, leaf_box,
+                           qbox, qorder, order_len, nq, nq_base, inst_root, cand_i, cand_j,
+                           cand_cap, c);
         break;
     case 128:
-        hipLaunchKernelGGL(k_traverse<128>, dim3(grid), dim3(128), 0, st, nodes, n_int, qbox,
-                           qorder, order_len, nq, nq_base, inst_root, inst_stop, cand_i, cand_j, cand_cap, c);
+        hipLaunchKernelGGL(k_traverse<128>, dim3(grid), dim3(128), 0, st, nodes, n_int, leaf_box,
+                           qbox, qorder, order_len, nq, nq_base, inst_root, cand_i, cand_j,
+                           cand_cap, c);
         break;
     case 512:
-        hipLaunchKernelGGL(k_traverse<512>, dim3(grid), dim3(512), 0, st, nodes, n_int, qbox,
-                           qorder, order_len, nq, nq_base, inst_root, inst_stop, cand_i, cand_j, cand_cap, c);
+        hipLaunchKernelGGL(k_traverse<512>, dim3(grid), dim3(512), 0, st, nodes, n_int, leaf_box,
+                           qbox, qorder, order_len, nq, nq_base, inst_root, cand_i, cand_j,
+                           cand_cap, c);
         break;
     default:
-        hipLaunchKernelGGL(k_traverse<256>, dim3(grid), dim3(256), 0, st, nodes, n_int, qbox,
-                           qorder, order_len, nq, nq_base, inst_root, inst_stop, cand_i, cand_j, cand_cap, c);
+        hipLaunchKernelGGL(k_traverse<256>, dim3(grid), dim3(256), 0, st, nodes, n_int, leaf_box,
+                           qbox, qorder, order_len, nq, nq_base, inst_root, cand_i, cand_j,
+                           cand_cap, c);
         break;
     }
 }

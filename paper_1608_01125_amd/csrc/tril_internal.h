@@ -17,7 +17,7 @@ constexpr double kRe = 2.8179403262e-9;    // classical electron radius [um]
 // Device-side error bits (DevCounters::err).
 constexpr uint32_t kErrData = 1u;          // non-finite input, E <= 0 or w < 0
 constexpr uint32_t kErrCandOverflow = 2u;  // broad-phase candidate buffer full
-constexpr uint32_t kErrSpin = 4u;          // a bounded device wait ran out
+constexpr uint32_t kErrSpin = 4u;          // a bounded device loop or stack ran out
 constexpr uint32_t kErrPairOverflow = 8u;  // caller pair buffer full
 constexpr uint32_t kErrTableFull = 16u;    // statistical-regime bin-pair table full
 
@@ -34,20 +34,24 @@ __device__ __forceinline__ double bw_sigma(double s) {
     return (k_sig / s) * br;
 }
 
-// One hierarchy node, 32 bytes, two per 64-byte half-line.
-// Internal nodes occupy ids [0, n-1), leaves [n-1, 2n-1) in Morton order.
-//   link: internal node -> id of its left child (the right child follows the
-//         left subtree in depth-first order, reached through ropes);
-//         leaf          -> row of the target photon it holds.
-//   rope: id of the next node in depth-first order once this node's subtree is
-//         done (skipped or finished); -1 after the last node.
-struct alignas(16) Node {
+// One internal hierarchy node, 64 bytes: the boxes of its two children and their
+// links (c[0] left, c[1] right), so that one load tests both children and a child
+// whose box fails is never loaded. A link >= 0 is the id of an internal node; a link
+// <= -2 is a leaf holding target element -2 - link (leaf_link / link_elem). The root's
+// own box is stored nowhere: a descent starts by testing the root's children. Step s
+// of a batch of m steps over n rows owns internal nodes s (n-1) + x, x in [0, n-1).
+struct alignas(16) Half {
     float lox, loy, loz;
     int32_t link;
     float hix, hiy, hiz;
-    int32_t rope;
+    int32_t pad;
 };
-static_assert(sizeof(Node) == 32, "node layout");
+struct alignas(16) Node {
+    Half c[2];
+};
+static_assert(sizeof(Half) == 32 && sizeof(Node) == 64, "node layout");
+__host__ __device__ inline int32_t leaf_link(int64_t e) { return (int32_t)(-2 - e); }
+__host__ __device__ inline int64_t link_elem(int32_t l) { return -2 - (int64_t)l; }
 
 // Parent record of a hierarchy node (internal or leaf), 16 bytes, written by the
 // emission kernel for both children of every internal node:
@@ -186,31 +190,32 @@ void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint3
 // inst_root may be NULL (one instance); otherwise the node whose range is exactly one
 // instance's run of keys (key >> prefix_shift equal) is recorded there.
 void launch_karras_u32(const uint32_t *keys, int64_t n, int prefix_shift, PRec *prec,
-                       int32_t *split_right, int32_t *inst_root, hipStream_t st);
+                       int32_t *inst_root, hipStream_t st);
 void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shift, PRec *prec,
-                       int32_t *split_right, int32_t *inst_root, hipStream_t st);
-// Roots and stops of the b.m x b.n_inst combined instances, as global node ids of the
-// b.m per-step copies of the shape (base_root: the emission's instance roots).
-void launch_inst_roots(const BeamDev &b, const int32_t *base_root, const int32_t *split_right,
-                       int32_t *inst_root, int32_t *inst_stop, hipStream_t st);
+                       int32_t *inst_root, hipStream_t st);
+// Root link of each of the b.m x b.n_inst combined instances in the b.m per-step copies
+// of the shape: an internal node id, leaf_link(element) for an instance of one row, -1
+// for an empty one (base_root: the emission's instance roots; sorted_rows: row of each
+// sorted position).
+void launch_inst_roots(const BeamDev &b, const int32_t *base_root, const uint32_t *sorted_rows,
+                       int32_t *inst_root, hipStream_t st);
 // Nodes of m steps sharing the shape over n leaves (sorted_rows: row of each sorted
 // position; box: m n boxes at s n + row; flags: m (n - 1) arrival flags, cleared here;
 // slots: hand-off slots for the levels above the chunks, refit_slots_needed(n, m) of
 // them, or NULL / too few: the chunk kernel climbs those levels itself).
 int64_t refit_slots_needed(int64_t n, int32_t m);
 void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, int32_t m,
-                  const PRec *prec, const int32_t *split_right, int32_t *flags, Node *nodes,
-                  int32_t *slots, int64_t slot_cap, unsigned int *err, hipStream_t st);
+                  const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots,
+                  int64_t slot_cap, unsigned int *err, hipStream_t st);
 
-// n_int: internal nodes of all steps' trees (ids below it are internal, the rest
-// leaves); nq: virtual query count (steps x rows). qorder: NULL (identity), nq entries
-// (order of all virtual queries) or nq_base entries (order of one step, repeated per
-// step).
-void launch_traverse(const Node *nodes, int64_t n_int, const PBox *qbox, const uint32_t *qorder,
-                     int64_t order_len, int64_t nq, int64_t nq_base,
-                     const int32_t *inst_root, const int32_t *inst_stop,
-                     int32_t *cand_i, int32_t *cand_j, int64_t cand_cap, DevCounters *c,
-                     int block, hipStream_t st);
+// n_int: internal nodes of all steps' trees; leaf_box: the target's boxes by element
+// (read for instances whose root is a leaf); nq: virtual query count (steps x rows).
+// qorder: NULL (identity), nq entries (order of all virtual queries) or nq_base entries
+// (order of one step, repeated per step).
+void launch_traverse(const Node *nodes, int64_t n_int, const PBox *leaf_box, const PBox *qbox,
+                     const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
+                     const int32_t *inst_root, int32_t *cand_i, int32_t *cand_j,
+                     int64_t cand_cap, DevCounters *c, int block, hipStream_t st);
 void launch_narrow(const BeamDev &q, const BeamDev &t, double dt, double sigma_up,
                    const int32_t *cand_i, const int32_t *cand_j, int64_t cand_cap,
                    const tril_pairs &out, DevCounters *c, bool fp32_stage, hipStream_t st);
@@ -300,9 +305,9 @@ void launch_st_mask_bins(const int32_t *bins, int64_t n, const uint8_t *mark, in
 void launch_fill_keys(long long *p, int64_t n, hipStream_t st);
 void launch_st_clear(long long *keys, double *vals, int64_t cap, double *slots, hipStream_t st);
 // Arguments as for launch_traverse.
-void launch_st_traverse(const Node *nodes, int64_t n_int, const PBox *qbox, const uint32_t *qorder,
-                        int64_t order_len, int64_t nq, int64_t nq_base,
-                        const int32_t *inst_root, const int32_t *inst_stop,
+void launch_st_traverse(const Node *nodes, int64_t n_int, const PBox *leaf_box, const PBox *qbox,
+                        const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
+                        const int32_t *inst_root,
                         const BeamDev &q, const BeamDev &t, const int32_t *q_bins,
                         const int32_t *t_bins, int64_t n_t_bins, double dt, const StCell &cell,
                         int geometric, const long long *filter, int64_t filter_cap,

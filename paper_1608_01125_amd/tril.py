@@ -165,7 +165,7 @@ def lib() -> ctypes.CDLL:
     L.tril_dbg_morton.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_float), vp, vp]
     L.tril_dbg_pair_eval.argtypes = [i64, vp, vp, vp]
     L.tril_dbg_pair_eval32.argtypes = [i64, vp, vp, vp]
-    L.tril_dbg_tree.argtypes = [vp, vp, i64, _i64p, _i32p, _i32p]
+    L.tril_dbg_tree.argtypes = [vp, vp, i64, _i64p, _i32p]
     L.tril_dbg_boxes.argtypes = [vp, ctypes.c_int, vp, i64, _i64p]
     L.tril_dbg_candidates.argtypes = [vp, _i32p, _i32p, i64, _i64p]
     _lib = L
@@ -559,20 +559,20 @@ def _h(ctx):
     return ctx.h if isinstance(ctx, Context) else ctx
 
 
-def tril_dbg_tree(ctx, n_target: int, n_inst: int = 1):
+def tril_dbg_tree(ctx, n_target: int, n_inst: int = 1, m: int = 1):
+    """Internal nodes of the last build: lo/hi (k, 2, 3) child boxes, link (k, 2) child
+    links (>= 0 internal, <= -2 leaf of element -2 - link), roots (m n_inst)."""
     ctx = _h(ctx)
-    cap = max(2 * n_target - 1, 1)
-    nodes = np.zeros((cap, 8), dtype=np.float32)
+    cap = max(m * (n_target - 1), 1)
+    nodes = np.zeros((cap, 16), dtype=np.float32)
     nn = ctypes.c_int64(0)
-    roots = np.zeros(max(n_inst, 1), dtype=np.int32)
-    stops = np.zeros(max(n_inst, 1), dtype=np.int32)
+    roots = np.zeros(max(m * n_inst, 1), dtype=np.int32)
     _check(lib().tril_dbg_tree(ctx, nodes.ctypes.data, cap, ctypes.byref(nn),
-                               roots.ctypes.data_as(_i32p), stops.ctypes.data_as(_i32p)),
-           "tril_dbg_tree")
-    nodes = nodes[: nn.value]
+                               roots.ctypes.data_as(_i32p)), "tril_dbg_tree")
+    nodes = nodes[: nn.value].reshape(-1, 2, 8)
     ints = nodes.view(np.int32)
-    return {"lo": nodes[:, 0:3].copy(), "hi": nodes[:, 4:7].copy(), "link": ints[:, 3].copy(),
-            "rope": ints[:, 7].copy(), "roots": roots[:n_inst], "stops": stops[:n_inst]}
+    return {"lo": nodes[:, :, 0:3].copy(), "hi": nodes[:, :, 4:7].copy(),
+            "link": ints[:, :, 3].copy(), "roots": roots[: m * n_inst]}
 
 
 def tril_dbg_boxes(ctx, which: int, n: int):

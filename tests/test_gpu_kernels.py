@@ -177,40 +177,100 @@ def _small_beams(n=3000, seed=2, boost=3e3):
     return wl, A, B
 
 
+def _walk(tree, root, n_int_all):
+    """Internal nodes and leaf elements reached from root, each counted."""
+    seen_int, leaves = np.zeros(n_int_all, dtype=np.int32), []
+    if root <= -2:
+        return seen_int, [-2 - root]
+    stack = [root] if root >= 0 else []
+    while stack:
+        p = stack.pop()
+        seen_int[p] += 1
+        assert seen_int[p] == 1, "internal node reached twice"
+        for k in (0, 1):
+            c = int(tree["link"][p, k])
+            if c >= 0:
+                stack.append(c)
+            else:
+                assert c <= -2
+                leaves.append(-2 - c)
+    return seen_int, leaves
+
+
+def _check_boxes(tree, boxes):
+    """A leaf's box in its parent is its photon's box; an internal child's box is the
+    exact union of that child's two children."""
+    link = tree["link"]
+    leaf = link < 0
+    e = -2 - link[leaf]
+    assert np.array_equal(tree["lo"][leaf], boxes["lo"][e])
+    assert np.array_equal(tree["hi"][leaf], boxes["hi"][e])
+    c = link[~leaf]
+    assert np.array_equal(tree["lo"][~leaf], tree["lo"][c].min(axis=1))
+    assert np.array_equal(tree["hi"][~leaf], tree["hi"][c].max(axis=1))
+
+
 def test_tree_invariants(torch):
     wl, A, B = _small_beams()
     ctx = T.Context(wl.dt)
     tb = T.Beam(B)
     ctx.build(tb, 200)
-    tree = T.tril_dbg_tree(ctx, len(B["E"]))
-    boxes = T.tril_dbg_boxes(ctx, 0, len(B["E"]))
-    ctx.close()
     n = len(B["E"])
+    tree = T.tril_dbg_tree(ctx, n)
+    boxes = T.tril_dbg_boxes(ctx, 0, n)
+    ctx.close()
     n_int = n - 1
-    assert len(tree["link"]) == 2 * n - 1
-    assert tree["roots"][0] == 0 and tree["stops"][0] == -1
-    # depth-first walk through links and ropes visits every node exactly once
-    seen = np.zeros(2 * n - 1, dtype=np.int32)
-    node, order = 0, []
-    while node != -1:
-        seen[node] += 1
-        order.append(node)
-        node = tree["link"][node] if node < n_int else tree["rope"][node]
-        assert len(order) <= 2 * n - 1
+    assert tree["link"].shape == (n_int, 2)
+    assert tree["roots"][0] == 0
+    # a depth-first walk from the root reaches every internal node and every leaf once
+    seen, leaves = _walk(tree, 0, n_int)
     assert np.all(seen == 1)
-    # leaves hold every row once, with that row's box
-    rows = tree["link"][n_int:]
-    assert np.array_equal(np.sort(rows), np.arange(n))
-    assert np.array_equal(tree["lo"][n_int:], boxes["lo"][rows])
-    assert np.array_equal(tree["hi"][n_int:], boxes["hi"][rows])
-    # every internal box is the exact union of its two children; right = rope(left)
-    for p in range(n_int):
-        lc = tree["link"][p]
-        rc = tree["rope"][lc]
-        assert 0 <= rc < 2 * n - 1
-        assert np.array_equal(tree["lo"][p], np.minimum(tree["lo"][lc], tree["lo"][rc]))
-        assert np.array_equal(tree["hi"][p], np.maximum(tree["hi"][lc], tree["hi"][rc]))
-        assert tree["rope"][rc] == tree["rope"][p]
+    assert np.array_equal(np.sort(leaves), np.arange(n))
+    _check_boxes(tree, boxes)
+
+
+def test_batched_tree_copies_and_instance_roots(torch):
+    """A batch of m steps over several instances: every step has its own copy of one
+    shape (same links up to the step's offsets); each (step, instance) root reaches
+    exactly that instance's rows at that step; an instance of one row is a leaf root and
+    an empty one has none; every box is the photon's box at its step or an exact union."""
+    parts = []
+    for k, n_k in enumerate([700, 1, 0, 900, 2]):
+        wl = beams.gauss_headon_1m(n=max(n_k, 1), seed=20 + k)
+        parts.append(beams.head(beams.draw_pair(wl)[1], n_k))
+    Bc, off = beams.concat(parts)
+    n, n_inst, m = len(Bc["E"]), len(off) - 1, 5
+    wl = beams.gauss_headon_1m(n=1000)
+    ctx = T.Context(wl.dt, step_batch=m)
+    tb = T.Beam(Bc, off)
+    pairs = T.Pairs(1 << 12)
+    ctx.run(tb, tb, 180, m, pairs)
+    tree = T.tril_dbg_tree(ctx, n, n_inst, m)
+    boxes = T.tril_dbg_boxes(ctx, 0, m * n)
+    ctx.close()
+    n_int = n - 1
+    link = tree["link"]
+    assert link.shape == (m * n_int, 2)
+    base = link[:n_int]
+    for s in range(1, m):
+        ls = link[s * n_int:(s + 1) * n_int]
+        want = np.where(base >= 0, base + s * n_int, -2 - ((-2 - base) + s * n))
+        assert np.array_equal(ls, want)
+    roots = tree["roots"].reshape(m, n_inst)
+    for s in range(m):
+        for mi in range(n_inst):
+            rows = np.arange(off[mi], off[mi + 1]) + s * n
+            r = int(roots[s, mi])
+            if len(rows) == 0:
+                assert r == -1
+                continue
+            if len(rows) == 1:
+                assert r == -2 - rows[0]
+            else:
+                assert s * n_int <= r < (s + 1) * n_int
+            _, leaves = _walk(tree, r, m * n_int)
+            assert np.array_equal(np.sort(leaves), rows)
+    _check_boxes(tree, boxes)
 
 
 def test_boxes_contain_swept_segments(torch):
