@@ -62,8 +62,10 @@ int tril_dbg_gemm_bf16(const uint16_t *A, int64_t sam, int64_t sak, const uint16
 int tril_dbg_tree(tril_ctx *ctx, void *nodes, int64_t cap_nodes, int64_t *n_nodes,
                   int32_t *roots);
 
-/* Copy the swept boxes of the last target (which = 0) or query (which = 1) beam to
- * host memory as n x 8 words (lox loy loz tag hix hiy hiz instance). */
+/* Copy the swept boxes of the last target (which = 0: all m n of the last build's m
+ * steps, formed again here exactly as the build's refit formed them) or query
+ * (which = 1) beam to host memory as n x 8 words (lox loy loz tag hix hiy hiz
+ * instance). Synchronises the context stream. */
 int tril_dbg_boxes(tril_ctx *ctx, int which, void *boxes, int64_t cap, int64_t *n);
 
 /* Copy the candidate pairs of the last tril_collide to host memory. *count gets the

@@ -138,9 +138,12 @@ struct tril_ctx {
     Node *nodes = nullptr;
     int32_t *inst_root = nullptr;
     int32_t *inst_base = nullptr;          // instance roots of the shared tree shape
+    PBox *root_box = nullptr;              // boxes of combined instances of one row
     int32_t *refit_slots = nullptr;        // refit hand-offs to the crossing-level kernel
     int64_t refit_slot_cap = 0;
     int64_t n_int = -1;                    // internal nodes of the last build (all steps)
+    int32_t tgt_k0 = 0;                    // first step of the last build
+    CloudBox tgt_cloud{0, {0.0, 0.0, 0.0}};  // box kind of the last build
 
     // query state
     int64_t q_cap = 0, q_row_cap = 0;
@@ -253,10 +256,11 @@ int ensure_target(tril_ctx *c, int64_t nv, int64_t n, int64_t n_comb, int32_t n_
     }
     if (n_comb > c->t_comb_cap) {
         ++c->alloc_gen;
-        dev_free(c->inst_root); dev_free(c->inst_base);
+        dev_free(c->inst_root); dev_free(c->inst_base); dev_free(c->root_box);
         c->t_comb_cap = 0;
         c->built = false;
         CHK(dev_alloc(&c->inst_root, (size_t)n_comb));
+        CHK(dev_alloc(&c->root_box, (size_t)n_comb));
         CHK(dev_alloc(&c->inst_base, (size_t)n_comb));
         c->t_comb_cap = n_comb;
     }
@@ -456,8 +460,9 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
     const KeyLayout kl = key_layout(t.n_inst, c->morton_bits);
     if (timed) CHK(timing_pair(c, st, c->ev_build, true));
     launch_prologue(c->d_cnt, 0, t.m, st);
+    // sort keys only: the refit forms every step's leaf boxes from the photons itself
     launch_boxes_keys(t, false, c->cloud, c->dt, c->sigma_up, c->t_stats, c->t_stats, kl,
-                      key_step(t.m), c->t_box, c->t_k32a, c->t_k64a, c->t_va, c->d_cnt, st);
+                      key_step(t.m), nullptr, c->t_k32a, c->t_k64a, c->t_va, c->d_cnt, st);
     const uint32_t *rows = nullptr;
     int32_t *roots = t.n_inst > 1 ? c->inst_base : nullptr;
     if (!kl.wide) {
@@ -475,9 +480,11 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
     }
     c->t_rows = rows;
     c->n_int = n > 0 ? (int64_t)t.m * (n - 1) : -1;
-    launch_inst_roots(t, c->inst_base, rows, c->inst_root, st);
-    launch_refit(c->t_box, rows, n, t.m, c->prec, c->nflags, c->nodes, c->refit_slots,
-                 c->refit_slot_cap, &c->d_cnt->err, st);
+    c->tgt_cloud = c->cloud;
+    launch_inst_roots(t, c->cloud, c->dt, c->inst_base, rows, c->inst_root, c->root_box, c->d_cnt,
+                      st);
+    launch_refit(t, c->cloud, c->dt, rows, c->prec, c->nflags, c->nodes, c->refit_slots,
+                 c->refit_slot_cap, c->d_cnt, &c->d_cnt->err, st);
     if (timed) CHK(timing_pair(c, st, c->ev_build, false));
     HIPCHK(hipGetLastError());
     return TRIL_OK;
@@ -512,7 +519,7 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
     CHK(enqueue_query_prep(c, q, st, sort_queries));
     if (timed) CHK(timing_pair(c, st, c->ev_prep, false));
     if (timed) CHK(timing_pair(c, st, c->ev_trav, true));
-    launch_traverse(c->nodes, c->n_int, c->t_box, c->q_box, c->q_order, c->q_order_len, nv, q.n,
+    launch_traverse(c->nodes, c->n_int, c->root_box, c->q_box, c->q_order, c->q_order_len, nv, q.n,
                     c->inst_root, c->cand_i, c->cand_j, c->cand_cap, c->d_cnt, c->block, st);
     if (timed) CHK(timing_pair(c, st, c->ev_trav, false));
     if (timed) CHK(timing_pair(c, st, c->ev_narrow, true));
@@ -739,6 +746,7 @@ int tril_build(tril_ctx *c, const tril_beam *b, int32_t step) {
     CHK(enqueue_build(c, c->st, (c->flags & TRIL_TIMING) != 0));
     c->built = true;
     c->built_step = step;
+    c->tgt_k0 = step;
     c->max_step = std::max(c->max_step, step);
     return TRIL_OK;
 }
@@ -886,8 +894,12 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
         k += n_rep * m;
         left -= n_rep * m;
     }
+    // the last batch's view (its working-copy buffer: graph replays leave the host view
+    // of the last capture)
+    c->tgt = wview(t, c->d_t_off, c->tgt.m, c->wt[pt ^ 1]);
     c->built = true;
     c->built_step = k0 + n_steps - 1;
+    c->tgt_k0 = k0 + n_steps - c->tgt.m;
     c->max_step = std::max(c->max_step, c->built_step);
     c->res_t = t1;
     c->last_q = q1;
@@ -1035,11 +1047,12 @@ int st_run(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_t n_t_b
         c->tgt = view(t, c->d_t_off, mb);
         const BeamDev qv = view(q, c->d_q_off, mb);
         launch_set_step(c->d_cnt, k, c->st);
+        c->tgt_k0 = k;
         if ((rc = enqueue_build(c, c->st, false)) != TRIL_OK) break;
         launch_prologue(c->d_cnt, 1, mb, c->st);
         if ((rc = enqueue_query_prep(c, qv, c->st, true)) != TRIL_OK) break;
         const int64_t nqv = (int64_t)mb * q->n;
-        launch_st_traverse(c->nodes, c->n_int, c->t_box, c->q_box, nqv > 0 ? c->q_order : nullptr,
+        launch_st_traverse(c->nodes, c->n_int, c->root_box, c->q_box, nqv > 0 ? c->q_order : nullptr,
                            c->q_order_len, nqv, q->n, c->inst_root, qv, c->tgt, q_bins, t_bins,
                            n_t_bins, c->dt, sc, geometric, filter, filter_cap, keys, vals, cap,
                            c->st_slots, c->d_cnt, c->st);
@@ -1702,7 +1715,7 @@ void tril_destroy(tril_ctx *c) {
     dev_free(c->sg_key); dev_free(c->sg_val);
     dev_free(c->sf_x); dev_free(c->sf_mean); dev_free(c->sf_sd); dev_free(c->sf_y0);
     dev_free(c->sf_key); dev_free(c->se_key); dev_free(c->se_val);
-    dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->inst_root); dev_free(c->inst_base);
+    dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->inst_root); dev_free(c->inst_base); dev_free(c->root_box);
     dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
     dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
     dev_free(c->q_keep); dev_free(c->d_q_off); dev_free(c->q_stats); dev_free(c->cand_i);
@@ -1856,6 +1869,16 @@ int tril_dbg_boxes(tril_ctx *c, int which, void *boxes, int64_t cap, int64_t *n)
     if (nn > cap) return TRIL_E_OVERFLOW;
     if (nn > 0) {
         if (!boxes) return TRIL_E_INVAL;
+        if (which == 0) {
+            // the refit forms the target's leaf boxes itself: recompute them as it did
+            if (!c->built) return TRIL_E_STATE;
+            launch_set_step(c->d_cnt, c->tgt_k0, c->st);
+            launch_boxes_keys(c->tgt, false, c->tgt_cloud, c->dt, c->sigma_up, c->t_stats,
+                              c->t_stats, key_layout(1, 30), -1, c->t_box, nullptr, nullptr,
+                              nullptr, c->d_cnt, c->st);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipStreamSynchronize(c->st));
+        }
         HIPCHK(hipMemcpy(boxes, which == 0 ? c->t_box : c->q_box, nn * sizeof(PBox),
                          hipMemcpyDeviceToHost));
     }

@@ -278,6 +278,62 @@ __global__ void __launch_bounds__(256) k_fold_stats(const StatsPartial *__restri
 
 // ------------------------------------------------------------ boxes and keys
 
+// Photon of one row as the box computations read it: start position, direction
+// (p / E) and whether its data are usable (finite, E > 0, w >= 0).
+struct RowPhoton {
+    double x, y, z, ux, uy, uz;
+    bool ok;
+};
+
+__device__ __forceinline__ RowPhoton load_photon(const BeamDev &b, int64_t i, double &E, double &w) {
+    RowPhoton r;
+    E = b.E[i];
+    w = b.w[i];
+    const double px = b.px[i], py = b.py[i], pz = b.pz[i];
+    r.x = b.x[i]; r.y = b.y[i]; r.z = b.z[i];
+    r.ok = isfinite(E) && isfinite(w) && isfinite(px) && isfinite(py) && isfinite(pz) &&
+           isfinite(r.x) && isfinite(r.y) && isfinite(r.z) && E > 0.0 && w >= 0.0;
+    r.ux = px / E; r.uy = py / E; r.uz = pz / E;
+    return r;
+}
+
+// Box of photon r in the step window [t, t + dt], padded by pad and rounded outward to
+// FP32, and its centre: the swept segment (position at t exactly as the narrow phase
+// forms it, and one step later) or, in the statistical regime, the cloud (half-widths
+// cloud.h about the mid-step position). A photon with unusable data gets an empty box.
+__device__ __forceinline__ void photon_box(const RowPhoton &r, double t, double dt,
+                                           const CloudBox &cloud, double pad, float lo32[3],
+                                           float hi32[3], float cen[3]) {
+    if (!r.ok) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo32[a] = INFINITY;
+            hi32[a] = -INFINITY;
+            cen[a] = 0.0f;
+        }
+        return;
+    }
+    double lo[3], hi[3];
+    if (cloud.on) {
+        const double tm = t + 0.5 * dt;
+        const double cx = r.x + tm * r.ux, cy = r.y + tm * r.uy, cz = r.z + tm * r.uz;
+        lo[0] = cx - cloud.h[0]; lo[1] = cy - cloud.h[1]; lo[2] = cz - cloud.h[2];
+        hi[0] = cx + cloud.h[0]; hi[1] = cy + cloud.h[1]; hi[2] = cz + cloud.h[2];
+    } else {
+        const double ax = r.x + t * r.ux, ay = r.y + t * r.uy, az = r.z + t * r.uz;
+        const double bx = ax + dt * r.ux, by = ay + dt * r.uy, bz = az + dt * r.uz;
+        lo[0] = fmin(ax, bx); lo[1] = fmin(ay, by); lo[2] = fmin(az, bz);
+        hi[0] = fmax(ax, bx); hi[1] = fmax(ay, by); hi[2] = fmax(az, bz);
+    }
+    // slack far above FP64 rounding of the positions (1e-12 of the magnitude)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo32[a] = f32_down(lo[a] - (pad + 1e-12 * (1.0 + fabs(lo[a]))));
+        hi32[a] = f32_up(hi[a] + (pad + 1e-12 * (1.0 + fabs(hi[a]))));
+        cen[a] = (float)(0.5 * (lo[a] + hi[a]));
+    }
+}
+
 // Swept box of each virtual element over its step window [t_k, t_k + dt], rounded
 // outward to FP32, and its sort key. Query photons are padded by an upper bound of
 // their collision radius with any photon of the same target instance:
@@ -288,9 +344,9 @@ __global__ void __launch_bounds__(256) k_fold_stats(const StatsPartial *__restri
 // tau = t_k + dt/2 >= 0, so [min x0 + tau min u, max x0 + tau max u] per axis contains
 // every centre (clamping absorbs rounding).
 // One thread per row, looping over the m steps of the launch: the row's photon data
-// is read once and its m boxes are written at the virtual elements s n + i. The sort
-// key of row i (its instance above the Morton bits of its box at step offset
-// key_step) is written at i.
+// is read once and its m boxes are written at the virtual elements s n + i (out NULL:
+// none). The sort key of row i (its instance above the Morton bits of its box at step
+// offset key_step) is written at i (vals NULL: none).
 template <bool kWide>
 __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, CloudBox cloud, double dt,
                                                     double sigma_up,
@@ -305,15 +361,11 @@ __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, CloudB
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= b.n) return;
     const int32_t mi = b.n_inst > 1 ? find_inst(b.inst_off, b.n_inst, i) : 0;
-    const double E = b.E[i], w = b.w[i];
-    const double px = b.px[i], py = b.py[i], pz = b.pz[i];
-    const double x = b.x[i], y = b.y[i], z = b.z[i];
-    const bool ok = isfinite(E) && isfinite(w) && isfinite(px) && isfinite(py) && isfinite(pz) &&
-                    isfinite(x) && isfinite(y) && isfinite(z) && E > 0.0 && w >= 0.0;
-    const double ux = px / E, uy = py / E, uz = pz / E;
+    double E, w;
+    const RowPhoton r = load_photon(b, i, E, w);
     double pad = 0.0;
     bool below = false;
-    if (query && ok) {  // (the cloud regime needs no radius pad: clouds overlap or not)
+    if (query && r.ok) {  // (the cloud regime needs no radius pad: clouds overlap or not)
         const InstStats &ts = t_stats[mi];
         const double emax_t = __longlong_as_double((long long)ts.emax);
         const double wmax_t = __longlong_as_double((long long)ts.wmax);
@@ -321,62 +373,29 @@ __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, CloudB
         below = !(smax > 1.0);
         if (!cloud.on) pad = sqrt((sqrt(w * wmax_t) * sigma_up) / M_PI) * (1.0 + 1e-6);
     }
-    const InstStats &ss = self_stats[mi];
-    double mn0[3], mnu[3], mx0[3], mxu[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        mn0[a] = ord2d(ss.mn[a]);
-        mnu[a] = ord2d(ss.mn[3 + a]);
-        mx0[a] = ord2d(ss.mx[a]);
-        mxu[a] = ord2d(ss.mx[3 + a]);
-    }
     const unsigned step0 = c->step;
     for (int32_t s = 0; s < b.m; ++s) {
-        const int64_t e = (int64_t)s * b.n + i;
+        if (out == nullptr && (vals == nullptr || s != key_step)) continue;
         const int32_t cc = s * b.n_inst + mi;
         const double t = (double)(step0 + (unsigned)s) * dt;
-        PBox o;
-        o.pad = cc;
-        float cen[3] = {0.f, 0.f, 0.f};
-        if (!ok) {
-            o.lox = o.loy = o.loz = INFINITY;
-            o.hix = o.hiy = o.hiz = -INFINITY;
-            o.tag = -1;
-        } else {
-            double lo[3], hi[3];
-            if (cloud.on) {
-                // cloud of the statistical regime: cell-sized box about the mid-step position
-                const double tm = t + 0.5 * dt;
-                const double cx = x + tm * ux, cy = y + tm * uy, cz = z + tm * uz;
-                lo[0] = cx - cloud.h[0]; lo[1] = cy - cloud.h[1]; lo[2] = cz - cloud.h[2];
-                hi[0] = cx + cloud.h[0]; hi[1] = cy + cloud.h[1]; hi[2] = cz + cloud.h[2];
-            } else {
-                // position at t_k exactly as the narrow phase forms it, and one step later
-                const double ax = x + t * ux, ay = y + t * uy, az = z + t * uz;
-                const double bx = ax + dt * ux, by = ay + dt * uy, bz = az + dt * uz;
-                lo[0] = fmin(ax, bx); lo[1] = fmin(ay, by); lo[2] = fmin(az, bz);
-                hi[0] = fmax(ax, bx); hi[1] = fmax(ay, by); hi[2] = fmax(az, bz);
-            }
-            // slack far above FP64 rounding of the positions (1e-12 of the magnitude)
-            float lo32[3], hi32[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                lo32[a] = f32_down(lo[a] - (pad + 1e-12 * (1.0 + fabs(lo[a]))));
-                hi32[a] = f32_up(hi[a] + (pad + 1e-12 * (1.0 + fabs(hi[a]))));
-                cen[a] = (float)(0.5 * (lo[a] + hi[a]));
-            }
+        float lo32[3], hi32[3], cen[3];
+        photon_box(r, t, dt, cloud, pad, lo32, hi32, cen);
+        if (out != nullptr) {
+            PBox o;
             o.lox = lo32[0]; o.loy = lo32[1]; o.loz = lo32[2];
             o.hix = hi32[0]; o.hiy = hi32[1]; o.hiz = hi32[2];
-            o.tag = below ? -1 : cc;
+            o.tag = (!r.ok || below) ? -1 : cc;
+            o.pad = cc;
+            out[(int64_t)s * b.n + i] = o;
         }
-        out[e] = o;
-        if (s != key_step) continue;
+        if (vals == nullptr || s != key_step) continue;
+        const InstStats &ss = self_stats[mi];
         const double tau = t + 0.5 * dt;
         float blo[3], bhi[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            blo[a] = (float)(mn0[a] + tau * mnu[a]);
-            bhi[a] = (float)(mx0[a] + tau * mxu[a]);
+            blo[a] = (float)(ord2d(ss.mn[a]) + tau * ord2d(ss.mn[3 + a]));
+            bhi[a] = (float)(ord2d(ss.mx[a]) + tau * ord2d(ss.mx[3 + a]));
         }
         const uint32_t code = morton30(cen, blo, bhi) >> (30 - kl.morton_bits);
         if (kWide)
@@ -483,9 +502,12 @@ __device__ __forceinline__ int32_t step_node(int64_t x, int32_t s, int64_t n) {
 
 // Root link of every combined instance (s, mi). base_root: roots of the base instances
 // written by the emission (read only when there are several); an instance with one row
-// is a leaf, the only instance of a tree is the tree's root (internal node 0).
-__global__ void k_inst_roots(BeamDev b, const int32_t *__restrict__ base_root,
-                             const uint32_t *__restrict__ rows, int32_t *inst_root) {
+// is a leaf, whose box at step s (kept in no node) goes to root_box[cc]; the only
+// instance of a tree is the tree's root (internal node 0).
+__global__ void k_inst_roots(BeamDev b, CloudBox cloud, double dt,
+                             const int32_t *__restrict__ base_root,
+                             const uint32_t *__restrict__ rows, int32_t *inst_root,
+                             PBox *__restrict__ root_box, const DevCounters *__restrict__ c) {
     const int32_t cc = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t n_comb = b.m * b.n_inst;
     if (cc >= n_comb) return;
@@ -494,12 +516,24 @@ __global__ void k_inst_roots(BeamDev b, const int32_t *__restrict__ base_root,
     const int64_t n = b.n;
     const int64_t o0 = b.n_inst > 1 ? b.inst_off[mi] : 0;
     const int64_t o1 = b.n_inst > 1 ? b.inst_off[mi + 1] : n;
-    if (o1 - o0 <= 0)
+    if (o1 - o0 <= 0) {
         inst_root[cc] = -1;
-    else if (o1 - o0 == 1)
-        inst_root[cc] = leaf_link((int64_t)s * n + rows[o0]);
-    else
+    } else if (o1 - o0 == 1) {
+        const uint32_t row = rows[o0];
+        inst_root[cc] = leaf_link((int64_t)s * n + row);
+        double E, w;
+        const RowPhoton r = load_photon(b, row, E, w);
+        float lo[3], hi[3], cen[3];
+        photon_box(r, (double)(c->step + (unsigned)s) * dt, dt, cloud, 0.0, lo, hi, cen);
+        PBox o;
+        o.lox = lo[0]; o.loy = lo[1]; o.loz = lo[2];
+        o.hix = hi[0]; o.hiy = hi[1]; o.hiz = hi[2];
+        o.tag = cc;
+        o.pad = cc;
+        root_box[cc] = o;
+    } else {
         inst_root[cc] = step_node(b.n_inst == 1 ? 0 : base_root[mi], s, n);
+    }
 }
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
@@ -591,24 +625,24 @@ __device__ __forceinline__ void climb_crossing(int32_t cur, Half cn, i32x4 r, bo
     }
 }
 
-// Bottom-up box refit for the m steps that share one tree shape (a workgroup works on
-// one step; records and sorted rows are the shared shape's, boxes, node stores and
-// arrival flags the step's). Every node writes its box and link into its half of its
-// parent. A workgroup owns a chunk of consecutive leaves; every internal node whose
-// leaf range lies inside the chunk has its id in the chunk too (a node's id is one end
-// of its range). The chunk's parent records and leaf boxes are staged in LDS first, so
-// the levels inside the chunk touch no global memory but their stores: the arrival
-// flag and the box of such a node live in LDS, and the second child to arrive merges
-// the boxes there. A node whose parent crosses the chunk boundary is stored and handed
-// to the crossing-level kernel through the workgroup's slots (the climb above it needs
-// device atomics and coherent loads whose latency would otherwise keep this LDS-heavy
-// workgroup resident for one thread); with the slots full, or none given, the thread
-// climbs on itself.
-__global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ box,
-                                                       const uint32_t *__restrict__ rows, int64_t n,
+// Bottom-up box refit for the m steps that share one tree shape. A workgroup owns a
+// chunk of consecutive leaves (sorted positions) for all m steps: the chunk's parent
+// records are staged in LDS and each leaf's photon is read once, and every step's leaf
+// boxes are computed from it in registers, so a step costs no global traffic but its
+// node stores. Every node writes its box and link into its half of its parent. Every
+// internal node whose leaf range lies inside the chunk has its id in the chunk too (a
+// node's id is one end of its range); the arrival flag and the box of such a node
+// live in LDS, and the second child to arrive merges the boxes there. A node whose
+// parent crosses the chunk boundary is stored and handed to the crossing-level kernel
+// through the (step, chunk) slots (the climb above it needs device atomics and
+// coherent loads whose latency would otherwise stall this LDS-heavy workgroup); with
+// the slots full, or none given, the thread climbs on itself.
+__global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cloud, double dt,
+                                                       const uint32_t *__restrict__ rows,
                                                        int64_t chunks, const PRec *__restrict__ prec,
                                                        int32_t *flags, Node *nodes,
                                                        int32_t *__restrict__ slots,
+                                                       const DevCounters *__restrict__ cnt,
                                                        unsigned int *err) {
     __shared__ float s_leaf[6][kRefitChunk];
     __shared__ float s_int[6][kRefitChunk];
@@ -617,80 +651,100 @@ __global__ void __launch_bounds__(kRefitChunk) k_refit(const PBox *__restrict__ 
     __shared__ i32x4 s_rec[2 * kRefitChunk];
     __shared__ int32_t s_nslot;
     const i32x4 *grec = reinterpret_cast<const i32x4 *>(prec);
-    const int32_t step = (int32_t)(blockIdx.x / chunks);
-    const int64_t c0 = (blockIdx.x - (int64_t)step * chunks) * kRefitChunk;
-    box += (int64_t)step * n;
-    flags += (int64_t)step * (n - 1);
+    const int64_t n = b.n;
+    const int64_t c0 = blockIdx.x * (int64_t)kRefitChunk;
     const int64_t c1 = (c0 + kRefitChunk < n ? c0 + kRefitChunk : n) - 1;  // last leaf of the chunk
     const int64_t leaf0 = n - 1;
     const int tid = threadIdx.x;
-    s_flag[tid] = 0;
-    if (tid == 0) s_nslot = 0;
-    if (slots != nullptr && tid < kRefitSlots) slots[(int64_t)blockIdx.x * kRefitSlots + tid] = -1;
     const int64_t j = c0 + tid;
     const bool in = j < n;
-    Half cn;  // box and link of `cur` as its parent holds them, not yet stored
-    int32_t cur = -1;
+    uint32_t row = 0;
+    RowPhoton ph;
+    ph.ok = false;
+    ph.x = ph.y = ph.z = ph.ux = ph.uy = ph.uz = 0.0;
     if (in) {
-        // independent loads first, the box gather (needs the row) last
-        const uint32_t row = rows[j];
-        const i32x4 rl = grec[leaf0 + j];
-        const i32x4 ri = (j < leaf0) ? grec[j] : i32x4{0, 0, 0, 0};
-        const PBox bx = box[row];
-        s_rec[tid] = rl;
-        s_rec[kRefitChunk + tid] = ri;
-        cn.lox = bx.lox; cn.loy = bx.loy; cn.loz = bx.loz;
-        cn.hix = bx.hix; cn.hiy = bx.hiy; cn.hiz = bx.hiz;
-        cn.link = leaf_link((int64_t)step * n + row);
-        cn.pad = 0;
-        cur = (int32_t)(leaf0 + j);
-        s_leaf[0][tid] = cn.lox; s_leaf[1][tid] = cn.loy; s_leaf[2][tid] = cn.loz;
-        s_leaf[3][tid] = cn.hix; s_leaf[4][tid] = cn.hiy; s_leaf[5][tid] = cn.hiz;
+        row = rows[j];
+        s_rec[tid] = grec[leaf0 + j];
+        s_rec[kRefitChunk + tid] = (j < leaf0) ? grec[j] : i32x4{0, 0, 0, 0};
+        double E, w;
+        ph = load_photon(b, row, E, w);
     }
-    __syncthreads();
-    if (!in) return;
-    // Inside the chunk: cur is one of the chunk's leaves (first level) or an internal
-    // node with its id in the chunk, so its record is in LDS.
-    i32x4 r;
-    for (;;) {
-        r = s_rec[cur >= leaf0 ? (int32_t)(cur - leaf0 - c0) : (int32_t)(kRefitChunk + cur - c0)];
-        const int32_t p = r.x;
-        if (p < 0) return;  // cur is the root
-        const int32_t plo = r.z, phi = r.w;
-        if (!(plo >= c0 && phi <= c1)) break;  // the parent crosses the chunk
-        const int side = r.y < 0 ? 1 : 0;
-        const int32_t sib = (int32_t)((uint32_t)r.y & 0x7fffffffu);
-        store_half_plain(&nodes[step_node(p, step, n)].c[side], cn);
-        if (cur < leaf0) {
-            const int64_t k = cur - c0;
-            s_int[0][k] = cn.lox; s_int[1][k] = cn.loy; s_int[2][k] = cn.loz;
-            s_int[3][k] = cn.hix; s_int[4][k] = cn.hiy; s_int[5][k] = cn.hiz;
+    const unsigned step0 = cnt->step;
+    for (int32_t step = 0; step < b.m; ++step) {
+        s_flag[tid] = 0;
+        if (tid == 0) s_nslot = 0;
+        int32_t *slot = slots ? slots + ((int64_t)step * chunks + blockIdx.x) * kRefitSlots : nullptr;
+        if (slot != nullptr && tid < kRefitSlots) slot[tid] = -1;
+        Half cn;  // box and link of `cur` as its parent holds them, not yet stored
+        int32_t cur = -1;
+        if (in) {
+            float lo[3], hi[3], cen[3];
+            photon_box(ph, (double)(step0 + (unsigned)step) * dt, dt, cloud, 0.0, lo, hi, cen);
+            cn.lox = lo[0]; cn.loy = lo[1]; cn.loz = lo[2];
+            cn.hix = hi[0]; cn.hiy = hi[1]; cn.hiz = hi[2];
+            cn.link = leaf_link((int64_t)step * n + row);
+            cn.pad = 0;
+            cur = (int32_t)(leaf0 + j);
+            s_leaf[0][tid] = cn.lox; s_leaf[1][tid] = cn.loy; s_leaf[2][tid] = cn.loz;
+            s_leaf[3][tid] = cn.hix; s_leaf[4][tid] = cn.hiy; s_leaf[5][tid] = cn.hiz;
         }
-        // the sibling's thread reads this box from LDS only: order LDS accesses
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-        const int32_t old = atomicAdd(&s_flag[p - c0], 1);
-        if (old == 0) return;  // the sibling subtree is not finished; its thread continues
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-        const bool sleaf = sib >= leaf0;
-        const int64_t k = sleaf ? sib - leaf0 - c0 : sib - c0;
-        float slo[3], shi[3];
+        __syncthreads();
+        int32_t *sflags = flags + (int64_t)step * (n - 1);
+        // Inside the chunk: cur is one of the chunk's leaves (first level) or an internal
+        // node with its id in the chunk, so its record is in LDS. done: this thread's
+        // climb for the step is over (first to arrive somewhere, or the root reached).
+        bool done = !in;
+        i32x4 r = {0, 0, 0, 0};
+        while (!done) {
+            r = s_rec[cur >= leaf0 ? (int32_t)(cur - leaf0 - c0) : (int32_t)(kRefitChunk + cur - c0)];
+            const int32_t p = r.x;
+            if (p < 0) {  // cur is the root
+                done = true;
+                break;
+            }
+            const int32_t plo = r.z, phi = r.w;
+            if (!(plo >= c0 && phi <= c1)) break;  // the parent crosses the chunk
+            const int side = r.y < 0 ? 1 : 0;
+            const int32_t sib = (int32_t)((uint32_t)r.y & 0x7fffffffu);
+            store_half_plain(&nodes[step_node(p, step, n)].c[side], cn);
+            if (cur < leaf0) {
+                const int64_t k = cur - c0;
+                s_int[0][k] = cn.lox; s_int[1][k] = cn.loy; s_int[2][k] = cn.loz;
+                s_int[3][k] = cn.hix; s_int[4][k] = cn.hiy; s_int[5][k] = cn.hiz;
+            }
+            // the sibling's thread reads this box from LDS only: order LDS accesses
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+            const int32_t old = atomicAdd(&s_flag[p - c0], 1);
+            if (old == 0) {  // the sibling subtree is not finished; its thread continues
+                done = true;
+                break;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+            const bool sleaf = sib >= leaf0;
+            const int64_t k = sleaf ? sib - leaf0 - c0 : sib - c0;
+            float slo[3], shi[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            slo[a] = sleaf ? s_leaf[a][k] : s_int[a][k];
-            shi[a] = sleaf ? s_leaf[3 + a][k] : s_int[3 + a][k];
+            for (int a = 0; a < 3; ++a) {
+                slo[a] = sleaf ? s_leaf[a][k] : s_int[a][k];
+                shi[a] = sleaf ? s_leaf[3 + a][k] : s_int[3 + a][k];
+            }
+            cn = merge_halves(cn, slo, shi, step_node(p, step, n));
+            cur = p;
         }
-        cn = merge_halves(cn, slo, shi, step_node(p, step, n));
-        cur = p;
-    }
-    if (slots != nullptr) {
-        const int k = atomicAdd(&s_nslot, 1);
-        if (k < kRefitSlots) {
-            store_half_plain(&nodes[step_node(r.x, step, n)].c[r.y < 0 ? 1 : 0], cn);
-            slots[(int64_t)blockIdx.x * kRefitSlots + k] = cur;
-            return;
+        if (!done) {  // the parent of cur crosses the chunk
+            bool handed = false;
+            if (slot != nullptr) {
+                const int k = atomicAdd(&s_nslot, 1);
+                if (k < kRefitSlots) {
+                    store_half_plain(&nodes[step_node(r.x, step, n)].c[r.y < 0 ? 1 : 0], cn);
+                    slot[k] = cur;
+                    handed = true;
+                }
+            }
+            if (!handed) climb_crossing(cur, cn, r, false, step, n, grec, sflags, nodes, err);
         }
+        __syncthreads();  // the chunk's LDS boxes and flags are reused by the next step
     }
-    climb_crossing(cur, cn, r, false, step, n, grec, flags, nodes, err);
 }
 
 // Crossing levels of the refit: one thread per hand-off slot of k_refit (slot s of
@@ -813,12 +867,13 @@ void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shi
                        keys, n, prefix_shift, prec, inst_root);
 }
 
-void launch_inst_roots(const BeamDev &b, const int32_t *base_root, const uint32_t *sorted_rows,
-                       int32_t *inst_root, hipStream_t st) {
+void launch_inst_roots(const BeamDev &b, const CloudBox &cloud, double dt, const int32_t *base_root,
+                       const uint32_t *sorted_rows, int32_t *inst_root, PBox *root_box,
+                       const DevCounters *c, hipStream_t st) {
     const int32_t n_comb = b.m * b.n_inst;
     if (n_comb <= 0) return;
-    hipLaunchKernelGGL(k_inst_roots, dim3(grid_for(n_comb, 64)), dim3(64), 0, st, b, base_root,
-                       sorted_rows, inst_root);
+    hipLaunchKernelGGL(k_inst_roots, dim3(grid_for(n_comb, 64)), dim3(64), 0, st, b, cloud, dt,
+                       base_root, sorted_rows, inst_root, root_box, c);
 }
 
 int64_t refit_slots_needed(int64_t n, int32_t m) {
@@ -826,17 +881,19 @@ int64_t refit_slots_needed(int64_t n, int32_t m) {
     return chunks > 1 ? chunks * m * kRefitSlots : 0;
 }
 
-void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, int32_t m,
-                  const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots,
-                  int64_t slot_cap, unsigned int *err, hipStream_t st) {
+void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint32_t *sorted_rows,
+                  const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots, int64_t slot_cap,
+                  const DevCounters *c, unsigned int *err, hipStream_t st) {
+    const int64_t n = b.n;
+    const int32_t m = b.m;
     if (n <= 1 || m <= 0) return;  // no internal node: a single leaf is its step's root
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)m * (n - 1), 256)), dim3(256), 0, st,
                        flags, 0, (int64_t)m * (n - 1));
     const int64_t chunks = (n + kRefitChunk - 1) / kRefitChunk;
     const int64_t n_slots = refit_slots_needed(n, m);
     if (slots == nullptr || n_slots == 0 || n_slots > slot_cap) slots = nullptr;
-    hipLaunchKernelGGL(k_refit, dim3((unsigned)(chunks * m)), dim3(kRefitChunk), 0, st, box,
-                       sorted_rows, n, chunks, prec, flags, nodes, slots, err);
+    hipLaunchKernelGGL(k_refit, dim3((unsigned)chunks), dim3(kRefitChunk), 0, st, b, cloud, dt,
+                       sorted_rows, chunks, prec, flags, nodes, slots, c, err);
     if (slots != nullptr)
         hipLaunchKernelGGL(k_refit_top, dim3(grid_for(n_slots, 256)), dim3(256), 0, st, slots,
                            n_slots, n, chunks, prec, flags, nodes, err);

@@ -195,14 +195,14 @@ constexpr int kStStack = 128;  // deeper than any radix tree over (key, index) p
 // node, both children tested from it, pending right children on a per-lane stack).
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_st_traverse(
-    const Node *__restrict__ nodes, int32_t n_int, const PBox *__restrict__ leaf_box,
+    const Node *__restrict__ nodes, int32_t n_int, const PBox *__restrict__ root_box,
     const PBox *__restrict__ qbox, const uint32_t *__restrict__ qorder, int64_t order_len,
     int64_t nq, int64_t nq_base, const int32_t *__restrict__ inst_root, BeamDev q, BeamDev t,
     const int32_t *__restrict__ q_bins, const int32_t *__restrict__ t_bins, int64_t n_t_bins,
     double dt, StCell cell, int geometric, const long long *__restrict__ filter, uint64_t fmask,
     long long *keys, double *vals, uint64_t mask, double *__restrict__ slots, DevCounters *c) {
     const int64_t e = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
-    int32_t node = -1, qi = 0;
+    int32_t node = -1, qi = 0, tag = -1;
     float qb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (e < nq) {
         if (qorder == nullptr) {
@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(BLOCK) k_st_traverse(
         const float4 a = bp[0], b = bp[1];
         qb[0] = a.x; qb[1] = a.y; qb[2] = a.z;
         qb[3] = b.x; qb[4] = b.y; qb[5] = b.z;
-        const int32_t tag = __float_as_int(a.w);
+        tag = __float_as_int(a.w);
         if (tag >= 0) node = inst_root[tag];
     }
     const int64_t so = q.m > 1 ? (int64_t)qi / q.n : 0;
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(BLOCK) k_st_traverse(
     uint32_t visits = 0, n_pairs = 0;
     if (node <= -2) {  // an instance of one row: its root is that leaf
         const int64_t el = link_elem(node);
-        const float4 *lp = reinterpret_cast<const float4 *>(leaf_box + el);
+        const float4 *lp = reinterpret_cast<const float4 *>(root_box + tag);
         ++visits;
         if (st_overlap(qb, lp[0], lp[1]))
             st_leaf(q, i, t, el, so, tk, dt, cell, geometric, bq, t_bins, n_t_bins, filter, fmask,
@@ -531,7 +531,7 @@ void launch_st_clear(long long *keys, double *vals, int64_t cap, double *slots, 
     hipLaunchKernelGGL(k_st_clear, dim3(grid_for(n, 256)), dim3(256), 0, st, keys, vals, cap, slots);
 }
 
-void launch_st_traverse(const Node *nodes, int64_t n_int64, const PBox *leaf_box, const PBox *qbox,
+void launch_st_traverse(const Node *nodes, int64_t n_int64, const PBox *root_box, const PBox *qbox,
                         const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
                         const int32_t *inst_root,
                         const BeamDev &q, const BeamDev &t, const int32_t *q_bins,
@@ -542,7 +542,7 @@ void launch_st_traverse(const Node *nodes, int64_t n_int64, const PBox *leaf_box
     if (nq <= 0 || n_int64 < 0) return;
     const int32_t n_int = (int32_t)n_int64;
     hipLaunchKernelGGL(k_st_traverse<256>, dim3(grid_for(nq, 256)), dim3(256), 0, st, nodes, n_int,
-                       leaf_box, qbox, qorder, order_len, nq, nq_base, inst_root, q, t, q_bins,
+                       root_box, qbox, qorder, order_len, nq, nq_base, inst_root, q, t, q_bins,
                        t_bins, n_t_bins, dt,
                        cell, geometric, filter, (uint64_t)(filter ? filter_cap - 1 : 0), keys, vals,
                        (uint64_t)(cap - 1), slots, c);

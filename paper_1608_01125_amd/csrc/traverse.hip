@@ -60,7 +60,7 @@ constexpr int kStackSpill = 124;  // deeper than any radix tree over (key, index
 
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nodes, int32_t n_int,
-                                                    const PBox *__restrict__ leaf_box,
+                                                    const PBox *__restrict__ root_box,
                                                     const PBox *__restrict__ qbox,
                                                     const uint32_t *__restrict__ qorder,
                                                     int64_t order_len, int64_t nq, int64_t nq_base,
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
                                                     int32_t *__restrict__ cand_j, int64_t cand_cap,
                                                     DevCounters *c) {
     const int64_t q = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
-    int32_t node = -1, qi = 0;
+    int32_t node = -1, qi = 0, tag = -1;
     float qb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (q < nq) {
         if (qorder == nullptr) {
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
         const float4 a = bp[0], b = bp[1];
         qb[0] = a.x; qb[1] = a.y; qb[2] = a.z;
         qb[3] = b.x; qb[4] = b.y; qb[5] = b.z;
-        const int32_t tag = __float_as_int(a.w);
+        tag = __float_as_int(a.w);
         if (tag >= 0) node = inst_root[tag];
     }
     const unsigned long long active_q = __ballot(node != -1);
@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
         int64_t e = 0;
         if (node <= -2) {
             e = link_elem(node);
-            const float4 *lp = reinterpret_cast<const float4 *>(leaf_box + e);
+            const float4 *lp = reinterpret_cast<const float4 *>(root_box + tag);
             hit = box_overlap(qb, lp[0], lp[1]);
             ++visits;
             node = -1;
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
 
 }  // namespace
 
-void launch_traverse(const Node *nodes, int64_t n_int64, const PBox *leaf_box, const PBox *qbox,
+void launch_traverse(const Node *nodes, int64_t n_int64, const PBox *root_box, const PBox *qbox,
                      const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
                      const int32_t *inst_root, int32_t *cand_i, int32_t *cand_j,
                      int64_t cand_cap, DevCounters *c, int block, hipStream_t st) {
@@ -167,22 +167,22 @@ void launch_traverse(const Node *nodes, int64_t n_int64, const PBox *leaf_box, c
     const unsigned grid = (unsigned)((nq + block - 1) / block);
     switch (block) {
     case 64:
-        hipLaunchKernelGGL(k_traverse<64>, dim3(grid), dim3(64), 0, st, nodes, n_int, leaf_box,
+        hipLaunchKernelGGL(k_traverse<64>, dim3(grid), dim3(64), 0, st, nodes, n_int, root_box,
                            qbox, qorder, order_len, nq, nq_base, inst_root, cand_i, cand_j,
                            cand_cap, c);
         break;
     case 128:
-        hipLaunchKernelGGL(k_traverse<128>, dim3(grid), dim3(128), 0, st, nodes, n_int, leaf_box,
+        hipLaunchKernelGGL(k_traverse<128>, dim3(grid), dim3(128), 0, st, nodes, n_int, root_box,
                            qbox, qorder, order_len, nq, nq_base, inst_root, cand_i, cand_j,
                            cand_cap, c);
         break;
     case 512:
-        hipLaunchKernelGGL(k_traverse<512>, dim3(grid), dim3(512), 0, st, nodes, n_int, leaf_box,
+        hipLaunchKernelGGL(k_traverse<512>, dim3(grid), dim3(512), 0, st, nodes, n_int, root_box,
                            qbox, qorder, order_len, nq, nq_base, inst_root, cand_i, cand_j,
                            cand_cap, c);
         break;
     default:
-        hipLaunchKernelGGL(k_traverse<256>, dim3(grid), dim3(256), 0, st, nodes, n_int, leaf_box,
+        hipLaunchKernelGGL(k_traverse<256>, dim3(grid), dim3(256), 0, st, nodes, n_int, root_box,
                            qbox, qorder, order_len, nq, nq_base, inst_root, cand_i, cand_j,
                            cand_cap, c);
         break;

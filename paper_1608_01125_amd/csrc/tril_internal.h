@@ -194,25 +194,28 @@ void launch_karras_u32(const uint32_t *keys, int64_t n, int prefix_shift, PRec *
 void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shift, PRec *prec,
                        int32_t *inst_root, hipStream_t st);
 // Root link of each of the b.m x b.n_inst combined instances in the b.m per-step copies
-// of the shape: an internal node id, leaf_link(element) for an instance of one row, -1
-// for an empty one (base_root: the emission's instance roots; sorted_rows: row of each
-// sorted position).
-void launch_inst_roots(const BeamDev &b, const int32_t *base_root, const uint32_t *sorted_rows,
-                       int32_t *inst_root, hipStream_t st);
-// Nodes of m steps sharing the shape over n leaves (sorted_rows: row of each sorted
-// position; box: m n boxes at s n + row; flags: m (n - 1) arrival flags, cleared here;
-// slots: hand-off slots for the levels above the chunks, refit_slots_needed(n, m) of
-// them, or NULL / too few: the chunk kernel climbs those levels itself).
+// of the shape: an internal node id, leaf_link(element) for an instance of one row
+// (whose box, kept in no node, goes to root_box[combined instance]), -1 for an empty
+// one (base_root: the emission's instance roots; sorted_rows: row of each sorted
+// position).
+void launch_inst_roots(const BeamDev &b, const CloudBox &cloud, double dt, const int32_t *base_root,
+                       const uint32_t *sorted_rows, int32_t *inst_root, PBox *root_box,
+                       const DevCounters *c, hipStream_t st);
+// Nodes of the b.m steps of view b sharing the shape over its b.n rows, each step's
+// leaf boxes computed from the photons (sorted_rows: row of each sorted position;
+// flags: b.m (b.n - 1) arrival flags, cleared here; slots: hand-off slots for the
+// levels above the chunks, refit_slots_needed(b.n, b.m) of them, or NULL / too few:
+// the chunk kernel climbs those levels itself).
 int64_t refit_slots_needed(int64_t n, int32_t m);
-void launch_refit(const PBox *box, const uint32_t *sorted_rows, int64_t n, int32_t m,
-                  const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots,
-                  int64_t slot_cap, unsigned int *err, hipStream_t st);
+void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint32_t *sorted_rows,
+                  const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots, int64_t slot_cap,
+                  const DevCounters *c, unsigned int *err, hipStream_t st);
 
-// n_int: internal nodes of all steps' trees; leaf_box: the target's boxes by element
-// (read for instances whose root is a leaf); nq: virtual query count (steps x rows).
+// n_int: internal nodes of all steps' trees; root_box: box of each combined instance
+// whose root is a leaf; nq: virtual query count (steps x rows).
 // qorder: NULL (identity), nq entries (order of all virtual queries) or nq_base entries
 // (order of one step, repeated per step).
-void launch_traverse(const Node *nodes, int64_t n_int, const PBox *leaf_box, const PBox *qbox,
+void launch_traverse(const Node *nodes, int64_t n_int, const PBox *root_box, const PBox *qbox,
                      const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
                      const int32_t *inst_root, int32_t *cand_i, int32_t *cand_j,
                      int64_t cand_cap, DevCounters *c, int block, hipStream_t st);
@@ -305,7 +308,7 @@ void launch_st_mask_bins(const int32_t *bins, int64_t n, const uint8_t *mark, in
 void launch_fill_keys(long long *p, int64_t n, hipStream_t st);
 void launch_st_clear(long long *keys, double *vals, int64_t cap, double *slots, hipStream_t st);
 // Arguments as for launch_traverse.
-void launch_st_traverse(const Node *nodes, int64_t n_int, const PBox *leaf_box, const PBox *qbox,
+void launch_st_traverse(const Node *nodes, int64_t n_int, const PBox *root_box, const PBox *qbox,
                         const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
                         const int32_t *inst_root,
                         const BeamDev &q, const BeamDev &t, const int32_t *q_bins,
