@@ -51,9 +51,10 @@ def traverse_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic(steps_per_dispatch=None):
+def committed_traffic(dispatches=None):
     """HBM bytes per traversal launch from the committed counter summary, or None
-    when it was taken from a different kernel source."""
+    when it was taken from a different kernel source or another batching (traversal
+    launches per collision run)."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     vals = {}
@@ -64,7 +65,7 @@ def committed_traffic(steps_per_dispatch=None):
                 vals[k.strip()] = v.strip()
     if vals.get("source_sha256") != traverse_source_hash():
         return None
-    if steps_per_dispatch is not None and vals.get("steps_per_dispatch") != str(steps_per_dispatch):
+    if dispatches is not None and vals.get("dispatches") != str(dispatches):
         return None
     try:
         return float(vals["traffic_bytes_per_dispatch"])
@@ -315,8 +316,7 @@ def main():
     ms_per_step = 1e3 * elapsed / max(args.steps, 1)
     value = pairs_per_step * n_steps / (elapsed / max(args.steps, 1))
     launches_per_run = st["n_timed_launches"] // max(args.steps, 1) if timing else 0
-    steps_per_dispatch = (n_steps // launches_per_run
-                          if launches_per_run and n_steps % launches_per_run == 0 else None)
+    steps_per_dispatch = round(n_steps / launches_per_run, 3) if launches_per_run else None
 
     variants = {}
     if not args.no_variants and not (args.flags & T.TRIL_SORT_QUERIES_ONCE):
@@ -332,7 +332,7 @@ def main():
         # traversal bytes over the timed region: 36 B per query (order entry + box), 64 B per
         # node load (both children's boxes and links), 8 B per candidate written
         alg_bytes = 36.0 * nA * st["n_collides"] + 64.0 * st["n_node_visits"] + 8.0 * st["n_candidates"]
-        traffic = committed_traffic(steps_per_dispatch)
+        traffic = committed_traffic(launches_per_run or None)
         if st["n_timed_launches"] > 0 and st["ms_traverse"] > 0:
             n_launch = st["n_timed_launches"]
             per_launch = alg_bytes / n_launch
