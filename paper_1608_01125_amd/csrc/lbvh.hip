@@ -644,8 +644,9 @@ __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cl
                                                        int32_t *__restrict__ slots,
                                                        const DevCounters *__restrict__ cnt,
                                                        unsigned int *err) {
-    __shared__ float s_leaf[6][kRefitChunk];
-    __shared__ float s_int[6][kRefitChunk];
+    // boxes (lo, hi as two float4) of the chunk's leaves and of its internal nodes
+    __shared__ float4 s_leaf[2][kRefitChunk];
+    __shared__ float4 s_int[2][kRefitChunk];
     __shared__ int32_t s_flag[kRefitChunk];
     // records: [0, chunk) the chunk's leaves, [chunk, 2 chunk) internal ids in the chunk
     __shared__ i32x4 s_rec[2 * kRefitChunk];
@@ -685,8 +686,8 @@ __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cl
             cn.link = leaf_link((int64_t)step * n + row);
             cn.pad = 0;
             cur = (int32_t)(leaf0 + j);
-            s_leaf[0][tid] = cn.lox; s_leaf[1][tid] = cn.loy; s_leaf[2][tid] = cn.loz;
-            s_leaf[3][tid] = cn.hix; s_leaf[4][tid] = cn.hiy; s_leaf[5][tid] = cn.hiz;
+            s_leaf[0][tid] = make_float4(cn.lox, cn.loy, cn.loz, 0.0f);
+            s_leaf[1][tid] = make_float4(cn.hix, cn.hiy, cn.hiz, 0.0f);
         }
         __syncthreads();
         int32_t *sflags = flags + (int64_t)step * (n - 1);
@@ -695,8 +696,8 @@ __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cl
         // climb for the step is over (first to arrive somewhere, or the root reached).
         bool done = !in;
         i32x4 r = {0, 0, 0, 0};
+        if (in) r = s_rec[tid];  // cur is this thread's leaf
         while (!done) {
-            r = s_rec[cur >= leaf0 ? (int32_t)(cur - leaf0 - c0) : (int32_t)(kRefitChunk + cur - c0)];
             const int32_t p = r.x;
             if (p < 0) {  // cur is the root
                 done = true;
@@ -706,11 +707,13 @@ __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cl
             if (!(plo >= c0 && phi <= c1)) break;  // the parent crosses the chunk
             const int side = r.y < 0 ? 1 : 0;
             const int32_t sib = (int32_t)((uint32_t)r.y & 0x7fffffffu);
+            // the parent's record (its id lies in the chunk), read ahead of the arrival
+            const i32x4 rp = s_rec[kRefitChunk + (p - c0)];
             store_half_plain(&nodes[step_node(p, step, n)].c[side], cn);
             if (cur < leaf0) {
                 const int64_t k = cur - c0;
-                s_int[0][k] = cn.lox; s_int[1][k] = cn.loy; s_int[2][k] = cn.loz;
-                s_int[3][k] = cn.hix; s_int[4][k] = cn.hiy; s_int[5][k] = cn.hiz;
+                s_int[0][k] = make_float4(cn.lox, cn.loy, cn.loz, 0.0f);
+                s_int[1][k] = make_float4(cn.hix, cn.hiy, cn.hiz, 0.0f);
             }
             // the sibling's thread reads this box from LDS only: order LDS accesses
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -722,14 +725,12 @@ __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cl
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
             const bool sleaf = sib >= leaf0;
             const int64_t k = sleaf ? sib - leaf0 - c0 : sib - c0;
-            float slo[3], shi[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                slo[a] = sleaf ? s_leaf[a][k] : s_int[a][k];
-                shi[a] = sleaf ? s_leaf[3 + a][k] : s_int[3 + a][k];
-            }
+            const float4 blo = sleaf ? s_leaf[0][k] : s_int[0][k];
+            const float4 bhi = sleaf ? s_leaf[1][k] : s_int[1][k];
+            const float slo[3] = {blo.x, blo.y, blo.z}, shi[3] = {bhi.x, bhi.y, bhi.z};
             cn = merge_halves(cn, slo, shi, step_node(p, step, n));
             cur = p;
+            r = rp;
         }
         if (!done) {  // the parent of cur crosses the chunk
             bool handed = false;
