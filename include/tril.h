@@ -381,7 +381,10 @@ int tril_mlp_train(tril_mlp *m, const float *x, const float *y, int64_t n, int32
  * output, per row (device, n each). Synchronous. */
 int tril_mlp_predict(tril_mlp *m, const float *x, int64_t n, float *mean, float *sdev);
 
-/* Zero the accumulated counters and device error flags (asynchronous). */
+/* Zero the accumulated counters and device error flags (synchronises the context
+ * stream). After a call that left a device error flag set, later builds are valid only
+ * once this has run: it also clears the hierarchy's scratch that such an interrupted
+ * build may have left behind. */
 int tril_reset_counters(tril_ctx *ctx);
 
 void tril_destroy(tril_ctx *ctx);

@@ -235,6 +235,8 @@ int ensure_target(tril_ctx *c, int64_t nv, int64_t n, int64_t n_comb, int32_t n_
         const int64_t m = std::max<int64_t>(nv, 1);
         CHK(dev_alloc(&c->t_box, m));
         CHK(dev_alloc(&c->nflags, m));
+        // the refit expects cleared arrival flags and leaves them cleared
+        HIPCHK(hipMemset(c->nflags, 0, (size_t)m * sizeof(int32_t)));
         CHK(dev_alloc(&c->nodes, m));  // m' (n' - 1) internal nodes of m' steps over n' rows
         // a launch of m' steps over n' > 512 rows has m' ceil(n' / 512) <= nv / 256 chunks
         // (fewer rows need no hand-offs), 64 slots each
@@ -1687,6 +1689,10 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
 int tril_reset_counters(tril_ctx *c) {
     if (!c) return TRIL_E_INVAL;
     HIPCHK(hipStreamSynchronize(c->st));
+    HIPCHK(hipMemcpy(c->h_cnt, c->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost));
+    // a launch stopped by a device error may have left refit arrival flags set
+    if (c->h_cnt->err != 0u && c->nflags != nullptr)
+        HIPCHK(hipMemset(c->nflags, 0, (size_t)c->t_cap * sizeof(int32_t)));
     std::memset(c->h_cnt, 0, sizeof(DevCounters));
     HIPCHK(hipMemcpy(c->d_cnt, c->h_cnt, sizeof(DevCounters), hipMemcpyHostToDevice));
     c->ev_build.clear(); c->ev_prep.clear(); c->ev_trav.clear(); c->ev_narrow.clear();

@@ -536,11 +536,6 @@ __global__ void k_inst_roots(BeamDev b, CloudBox cloud, double dt,
     }
 }
 
-__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 // ------------------------------------------------------------------- refit
 
 // Child halves that another thread of the same launch may read are stored with
@@ -616,6 +611,8 @@ __device__ __forceinline__ void climb_crossing(int32_t cur, Half cn, i32x4 r, bo
         const int32_t old = __hip_atomic_fetch_add(flags + p, 1, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
         if (old == 0) return;
+        // the second arrival is the flag's last use in this launch: leave it cleared
+        __hip_atomic_store(flags + p, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         float slo[3], shi[3];
         load_half_box(&pn->c[side ^ 1], slo, shi);
@@ -888,8 +885,6 @@ void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint
     const int64_t n = b.n;
     const int32_t m = b.m;
     if (n <= 1 || m <= 0) return;  // no internal node: a single leaf is its step's root
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for((int64_t)m * (n - 1), 256)), dim3(256), 0, st,
-                       flags, 0, (int64_t)m * (n - 1));
     const int64_t chunks = (n + kRefitChunk - 1) / kRefitChunk;
     const int64_t n_slots = refit_slots_needed(n, m);
     if (slots == nullptr || n_slots == 0 || n_slots > slot_cap) slots = nullptr;

@@ -203,7 +203,9 @@ void launch_inst_roots(const BeamDev &b, const CloudBox &cloud, double dt, const
                        const DevCounters *c, hipStream_t st);
 // Nodes of the b.m steps of view b sharing the shape over its b.n rows, each step's
 // leaf boxes computed from the photons (sorted_rows: row of each sorted position;
-// flags: b.m (b.n - 1) arrival flags, cleared here; slots: hand-off slots for the
+// flags: b.m (b.n - 1) arrival flags, zero on entry and left zero (the second arrival at
+// a node clears its flag; a launch that stops on a device error may leave some set);
+// slots: hand-off slots for the
 // levels above the chunks, refit_slots_needed(b.n, b.m) of them, or NULL / too few:
 // the chunk kernel climbs those levels itself).
 int64_t refit_slots_needed(int64_t n, int32_t m);
