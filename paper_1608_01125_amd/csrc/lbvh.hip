@@ -583,6 +583,7 @@ __device__ __forceinline__ Half merge_halves(const Half &a, const float lo[3], c
 
 constexpr int kRefitChunk = 512;  // leaves (and threads) per workgroup
 constexpr int kRefitSlots = 64;   // hand-offs to the crossing-level kernel per workgroup
+constexpr int kRefitStepGroups = 3;  // workgroups per chunk, each for a share of the steps
 
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
@@ -636,7 +637,8 @@ __device__ __forceinline__ void climb_crossing(int32_t cur, Half cn, i32x4 r, bo
 // the slots full, or none given, the thread climbs on itself.
 __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cloud, double dt,
                                                        const uint32_t *__restrict__ rows,
-                                                       int64_t chunks, const PRec *__restrict__ prec,
+                                                       int64_t chunks, int32_t group_steps,
+                                                       const PRec *__restrict__ prec,
                                                        int32_t *flags, Node *nodes,
                                                        int32_t *__restrict__ slots,
                                                        const DevCounters *__restrict__ cnt,
@@ -650,7 +652,11 @@ __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cl
     __shared__ int32_t s_nslot;
     const i32x4 *grec = reinterpret_cast<const i32x4 *>(prec);
     const int64_t n = b.n;
-    const int64_t c0 = blockIdx.x * (int64_t)kRefitChunk;
+    // workgroup: chunk `chunk` for the steps of group `group`
+    const int64_t group = blockIdx.x / chunks, chunk = blockIdx.x - group * chunks;
+    const int32_t s_begin = (int32_t)(group * group_steps);
+    const int32_t s_end = s_begin + group_steps < b.m ? s_begin + group_steps : b.m;
+    const int64_t c0 = chunk * kRefitChunk;
     const int64_t c1 = (c0 + kRefitChunk < n ? c0 + kRefitChunk : n) - 1;  // last leaf of the chunk
     const int64_t leaf0 = n - 1;
     const int tid = threadIdx.x;
@@ -668,10 +674,10 @@ __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cl
         ph = load_photon(b, row, E, w);
     }
     const unsigned step0 = cnt->step;
-    for (int32_t step = 0; step < b.m; ++step) {
+    for (int32_t step = s_begin; step < s_end; ++step) {
         s_flag[tid] = 0;
         if (tid == 0) s_nslot = 0;
-        int32_t *slot = slots ? slots + ((int64_t)step * chunks + blockIdx.x) * kRefitSlots : nullptr;
+        int32_t *slot = slots ? slots + ((int64_t)step * chunks + chunk) * kRefitSlots : nullptr;
         if (slot != nullptr && tid < kRefitSlots) slot[tid] = -1;
         Half cn;  // box and link of `cur` as its parent holds them, not yet stored
         int32_t cur = -1;
@@ -888,8 +894,12 @@ void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint
     const int64_t chunks = (n + kRefitChunk - 1) / kRefitChunk;
     const int64_t n_slots = refit_slots_needed(n, m);
     if (slots == nullptr || n_slots == 0 || n_slots > slot_cap) slots = nullptr;
-    hipLaunchKernelGGL(k_refit, dim3((unsigned)chunks), dim3(kRefitChunk), 0, st, b, cloud, dt,
-                       sorted_rows, chunks, prec, flags, nodes, slots, c, err);
+    // the steps of a batch are split over kRefitStepGroups workgroups per chunk
+    const int32_t group_steps = (m + kRefitStepGroups - 1) / kRefitStepGroups;
+    const int64_t groups = (m + group_steps - 1) / group_steps;
+    hipLaunchKernelGGL(k_refit, dim3((unsigned)(chunks * groups)), dim3(kRefitChunk), 0, st, b,
+                       cloud, dt, sorted_rows, chunks, group_steps, prec, flags, nodes, slots, c,
+                       err);
     if (slots != nullptr)
         hipLaunchKernelGGL(k_refit_top, dim3(grid_for(n_slots, 256)), dim3(256), 0, st, slots,
                            n_slots, n, chunks, prec, flags, nodes, err);
