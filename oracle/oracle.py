@@ -76,6 +76,8 @@ def lib():
         L.orc_invariant.argtypes = [d] * 8
         L.orc_step_d2.restype = d
         L.orc_step_d2.argtypes = [d] * 14
+        L.orc_step_tau.restype = d
+        L.orc_step_tau.argtypes = [d] * 14
         L.orc_sigma_max.restype = d
         L.orc_sigma_max.argtypes = []
         L.orc_collide.restype = None
@@ -223,6 +225,47 @@ def summarize(raw: RawHits, A, B, n_steps: int, edges: np.ndarray, k0: int = 0) 
     spec = np.zeros(len(edges) - 1)
     np.add.at(spec, b[ok], wij[ok])
     return Summary(ui, uj, uk, counts, int(len(uniq)), y, spec)
+
+
+def step_tau(t, dt, xi, ui, xj, uj) -> float:
+    """Time of closest approach within the window [t, t + dt], measured from t."""
+    return lib().orc_step_tau(t, dt, *xi, *ui, *xj, *uj)
+
+
+def hit_tau(raw: RawHits, A, B, dt: float) -> np.ndarray:
+    """tau* of every raw hit (i, j, k): the time of closest approach inside step k."""
+    out = np.empty(len(raw.i))
+    for h in range(len(raw.i)):
+        i, j, k = int(raw.i[h]), int(raw.j[h]), int(raw.k[h])
+        ui = (A["px"][i] / A["E"][i], A["py"][i] / A["E"][i], A["pz"][i] / A["E"][i])
+        uj = (B["px"][j] / B["E"][j], B["py"][j] / B["E"][j], B["pz"][j] / B["E"][j])
+        out[h] = step_tau(k * dt, dt, (A["x"][i], A["y"][i], A["z"][i]), ui,
+                          (B["x"][j], B["y"][j], B["z"][j]), uj)
+    return out
+
+
+def annihilate(raw: RawHits, A, B, dt: float) -> RawHits:
+    """Photons that collide are consumed (annihilation, Sec. 2.1), and the collisions of a
+    step are taken in chronological order (Sec. 2.2): the raw hits are ordered by step,
+    then by the time of closest approach inside the step, then by i and j (a strict
+    order), and a hit is kept when neither of its photons was consumed by a hit kept
+    before it. Hits of photons consumed in earlier steps are dropped the same way, as if
+    those photons had left the beams. Returns the kept hits, sorted by (i, j, k)."""
+    tau = hit_tau(raw, A, B, dt)
+    order = sorted(range(len(raw.i)),
+                   key=lambda h: (int(raw.k[h]), float(tau[h]), int(raw.i[h]), int(raw.j[h])))
+    used_a, used_b, kept = set(), set(), []
+    for h in order:
+        i, j = int(raw.i[h]), int(raw.j[h])
+        if i in used_a or j in used_b:
+            continue
+        used_a.add(i)
+        used_b.add(j)
+        kept.append(h)
+    kept = np.array(sorted(kept, key=lambda h: (int(raw.i[h]), int(raw.j[h]), int(raw.k[h]))),
+                    dtype=np.int64)
+    return RawHits(raw.i[kept], raw.j[kept], raw.k[kept], raw.margin[kept], raw.knife_margin,
+                   raw.knife_s, raw.pairs_tested, raw.pairs_full)
 
 
 def run(A, B, dt: float, n_steps: int, edges: np.ndarray, strict: bool = False,

@@ -94,10 +94,13 @@ double orc_invariant(double Ei, double uix, double uiy, double uiz,
 
 /* Smallest squared distance of two photons over [t, t + dt] (positions at equal time).
    Xi(t) = xi + t ui, Xj(t) = xj + t uj; the minimum of |Xi - Xj|^2 over the window is at
-   tau* = -(Delta . v)/(v . v) clamped to [0, dt], Delta = Xi(t) - Xj(t), v = ui - uj. */
-double orc_step_d2(double t, double dt,
-                   double xi, double yi, double zi, double uix, double uiy, double uiz,
-                   double xj, double yj, double zj, double ujx, double ujy, double ujz)
+   tau* = -(Delta . v)/(v . v) clamped to [0, dt], Delta = Xi(t) - Xj(t), v = ui - uj.
+   orc_step_closest gives both; *tau_out receives tau*, the time of closest approach
+   measured from t. */
+static double orc_step_closest(double t, double dt,
+                               double xi, double yi, double zi, double uix, double uiy,
+                               double uiz, double xj, double yj, double zj, double ujx,
+                               double ujy, double ujz, double *tau_out)
 {
     double Xix = xi + t * uix, Xiy = yi + t * uiy, Xiz = zi + t * uiz;
     double Xjx = xj + t * ujx, Xjy = yj + t * ujy, Xjz = zj + t * ujz;
@@ -109,7 +112,25 @@ double orc_step_d2(double t, double dt,
     if (!(tau > 0.0)) tau = 0.0;   /* also catches vv == 0 (NaN / -inf) */
     if (tau > dt) tau = dt;
     double px = dx + tau * vx, py = dy + tau * vy, pz = dz + tau * vz;
+    *tau_out = tau;
     return (px * px + py * py) + pz * pz;
+}
+
+double orc_step_d2(double t, double dt,
+                   double xi, double yi, double zi, double uix, double uiy, double uiz,
+                   double xj, double yj, double zj, double ujx, double ujy, double ujz)
+{
+    double tau;
+    return orc_step_closest(t, dt, xi, yi, zi, uix, uiy, uiz, xj, yj, zj, ujx, ujy, ujz, &tau);
+}
+
+double orc_step_tau(double t, double dt,
+                    double xi, double yi, double zi, double uix, double uiy, double uiz,
+                    double xj, double yj, double zj, double ujx, double ujy, double ujz)
+{
+    double tau;
+    (void)orc_step_closest(t, dt, xi, yi, zi, uix, uiy, uiz, xj, yj, zj, ujx, ujy, ujz, &tau);
+    return tau;
 }
 
 /* Largest value of sigma over all s, found by golden-section search on orc_sigma
