@@ -326,6 +326,14 @@ def main():
         variants["query_order_from_first_step"] = {
             "value": pairs_per_step * n_steps / (e2 / max(args.steps, 1)),
             "ms_per_step": 1e3 * e2 / max(args.steps, 1), "pairs": st2["n_pairs"]}
+    if not args.no_variants:
+        # annihilation mode: photons that collide are consumed; the run's raw hits are
+        # resolved chronologically on the device inside the timed stats call
+        e3, st3 = timed(args.flags | T.TRIL_ANNIHILATE | timing)
+        variants["annihilation"] = {
+            "value": pairs_per_step * n_steps / (e3 / max(args.steps, 1)),
+            "ms_per_step": 1e3 * e3 / max(args.steps, 1), "kept_hits": st3["n_hits"],
+            "pairs": st3["n_pairs"]}
 
     roofline = None
     if st["n_collides"] > 0:

@@ -70,6 +70,11 @@ extern "C" {
 #define TRIL_TIMING        0x1u  /* record HIP events around each phase (ms_* in tril_stats_t) */
 #define TRIL_SORT_QUERIES_ONCE 0x2u /* Morton-order the query beam at its first step only */
 #define TRIL_FP64_NARROW   0x4u  /* decide every candidate in FP64 (no FP32 stage) */
+#define TRIL_ANNIHILATE    0x8u  /* photons that collide are consumed: tril_stats keeps a
+                                    raw hit only if neither photon was consumed by a hit
+                                    before it in the order (step, time of closest approach
+                                    inside the step, i, j); Sec. 2.1 (annihilating photons)
+                                    and Sec. 2.2 (collisions sorted in time) */
 
 typedef struct tril_ctx tril_ctx;
 typedef struct tril_mlp tril_mlp;
@@ -180,6 +185,10 @@ int tril_run(tril_ctx *ctx, const tril_beam *target, const tril_beam *query,
 /* Synchronise the stream, then finish the run held in `pairs`:
  *   * if *count > cap: return TRIL_E_OVERFLOW, leave the buffers untouched and
  *     report the required capacity in out->n_hits;
+ *   * with TRIL_ANNIHILATE, first reduce the raw hits to the kept ones (see the flag;
+ *     the query and target beams of the last tril_run / tril_collide must still hold
+ *     their data): each photon then appears in at most one kept hit, out->n_hits
+ *     counts kept hits and the step counts count kept hits per step;
  *   * otherwise rewrite pairs->i/j/step in place as the unique pairs in ascending
  *     (i, j) order with their first step, set *count to the number of unique
  *     pairs, and fill `out` (yield, spectrum, step counts, counters).

@@ -169,6 +169,7 @@ struct tril_ctx {
 
     SortScratch ss;
     StatsScratch sst;
+    AnnScratch ann;                        // annihilation-mode resolution
     int32_t max_step = -1;
 
     // timing (TRIL_TIMING)
@@ -553,6 +554,43 @@ int note_query_sorted(tril_ctx *c, const tril_beam *q, int32_t m, hipStream_t st
     return TRIL_OK;
 }
 
+int ensure_annihilation(tril_ctx *c, int64_t n_hits, int64_t nq, int64_t nt) {
+    AnnScratch &a = c->ann;
+    if (n_hits > a.cap) {
+        dev_free(a.ka); dev_free(a.kb); dev_free(a.va); dev_free(a.vb); dev_free(a.rank);
+        dev_free(a.alive); dev_free(a.kept); dev_free(a.ti); dev_free(a.tj); dev_free(a.tk);
+        a.cap = 0;
+        const int64_t m = std::max<int64_t>(n_hits, 1024);
+        CHK(dev_alloc(&a.ka, m)); CHK(dev_alloc(&a.kb, m));
+        CHK(dev_alloc(&a.va, m)); CHK(dev_alloc(&a.vb, m)); CHK(dev_alloc(&a.rank, m));
+        CHK(dev_alloc(&a.alive, m)); CHK(dev_alloc(&a.kept, m));
+        CHK(dev_alloc(&a.ti, m)); CHK(dev_alloc(&a.tj, m)); CHK(dev_alloc(&a.tk, m));
+        a.cap = m;
+    }
+    if (nq > a.cap_q) {
+        dev_free(a.mq); dev_free(a.cq);
+        a.cap_q = 0;
+        CHK(dev_alloc(&a.mq, nq)); CHK(dev_alloc(&a.cq, nq));
+        a.cap_q = nq;
+    }
+    if (nt > a.cap_t) {
+        dev_free(a.mt); dev_free(a.ct);
+        a.cap_t = 0;
+        CHK(dev_alloc(&a.mt, nt)); CHK(dev_alloc(&a.ct, nt));
+        a.cap_t = nt;
+    }
+    if (!a.counter) CHK(dev_alloc(&a.counter, 1));
+    return ensure_sort_scratch(c, n_hits);
+}
+
+void free_annihilation(tril_ctx *c) {
+    AnnScratch &a = c->ann;
+    dev_free(a.ka); dev_free(a.kb); dev_free(a.va); dev_free(a.vb); dev_free(a.rank);
+    dev_free(a.alive); dev_free(a.kept); dev_free(a.ti); dev_free(a.tj); dev_free(a.tk);
+    dev_free(a.mq); dev_free(a.cq); dev_free(a.mt); dev_free(a.ct); dev_free(a.counter);
+    a = AnnScratch{};
+}
+
 int ensure_stats(tril_ctx *c, int64_t n_hits, int32_t n_steps) {
     StatsScratch &s = c->sst;
     if (n_hits > s.cap) {
@@ -686,7 +724,8 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
     if (!std::isfinite(p->dt) || !(p->dt > 0.0)) return TRIL_E_INVAL;
     if (p->n_bins < 0 || p->cand_cap < 0 || p->step_batch < 0) return TRIL_E_INVAL;
     if (p->morton_bits != 0 && (p->morton_bits < 3 || p->morton_bits > 30)) return TRIL_E_INVAL;
-    if (p->flags & ~(TRIL_TIMING | TRIL_SORT_QUERIES_ONCE | TRIL_FP64_NARROW)) return TRIL_E_NOTIMPL;
+    if (p->flags & ~(TRIL_TIMING | TRIL_SORT_QUERIES_ONCE | TRIL_FP64_NARROW | TRIL_ANNIHILATE))
+        return TRIL_E_NOTIMPL;
     if (p->n_bins > 0) {
         if (!p->bin_edges) return TRIL_E_INVAL;
         for (int32_t b = 0; b <= p->n_bins; ++b)
@@ -948,6 +987,16 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     out->n_hits = n_hits;
     if (n_hits > p->cap || (err & kErrPairOverflow)) return TRIL_E_OVERFLOW;
     if (n_hits > 0 && (!c->built || c->last_q.n <= 0)) return TRIL_E_STATE;
+    if ((c->flags & TRIL_ANNIHILATE) && n_hits > 0) {
+        CHK(ensure_annihilation(c, n_hits, c->last_q.n, c->res_t.n));
+        int64_t kept = 0;
+        const hipError_t e = annihilate_hits(*p, n_hits, c->last_q, c->res_t, c->dt,
+                                             std::max(c->max_step, 0), c->ann, c->ss,
+                                             &c->d_cnt->err, c->st, &kept);
+        if (e != hipSuccess) return hip_fail(e);
+        n_hits = kept;
+        out->n_hits = kept;
+    }
     const int step_bits = std::max(1, bits_for((uint64_t)std::max(c->max_step, 0)));
     const int pair_bits = bits_for((uint64_t)std::max<int64_t>(c->max_nq, 1) *
                                    (uint64_t)std::max<int64_t>(c->nt, 1));
@@ -1711,6 +1760,7 @@ void tril_destroy(tril_ctx *c) {
         if (g) (void)hipGraphExecDestroy(g);
     free_target(c);
     free_target_rows(c);
+    free_annihilation(c);
     for (int p = 0; p < 2; ++p) {
         free_work(c->wt[p]);
         free_work(c->wq[p]);

@@ -319,6 +319,30 @@ void launch_st_traverse(const Node *nodes, int64_t n_int, const PBox *root_box, 
                         long long *keys, double *vals, int64_t cap, double *slots, DevCounters *c,
                         hipStream_t st);
 
+// ------------------------------------------------------------ annihilation mode
+// Scratch of annihilate_hits: per raw hit (cap) two sort key/value buffer pairs, rank,
+// live and kept flags and a copy of (i, j, step); per query photon (cap_q) and target
+// photon (cap_t) the lowest live rank and a consumed flag; two counters.
+struct AnnScratch {
+    unsigned long long *ka = nullptr, *kb = nullptr;
+    uint32_t *va = nullptr, *vb = nullptr;
+    int32_t *rank = nullptr;
+    uint8_t *alive = nullptr, *kept = nullptr;
+    int32_t *ti = nullptr, *tj = nullptr, *tk = nullptr;
+    int64_t cap = 0;
+    int32_t *mq = nullptr, *mt = nullptr;
+    uint8_t *cq = nullptr, *ct = nullptr;
+    int64_t cap_q = 0, cap_t = 0;
+    unsigned long long *counter = nullptr;
+};
+// Resolve the n raw hits (i, j, step) in p in annihilation mode (rows of the query view
+// q and target view t, the callers' beams; steps up to max_step): the kept hits are
+// written back to p's first *n_kept entries (order unspecified) and *p.count is set to
+// their number. Synchronises the stream (one round trip per resolution round).
+hipError_t annihilate_hits(const tril_pairs &p, int64_t n, const BeamDev &q, const BeamDev &t,
+                           double dt, int32_t max_step, AnnScratch &a, SortScratch &ss,
+                           unsigned int *err, hipStream_t st, int64_t *n_kept);
+
 // ------------------------------------------------------------------ run stats
 struct StatsScratch {
     unsigned long long *keys = nullptr, *keys_alt = nullptr;
