@@ -83,6 +83,9 @@ def make_workload(name: str, physics_steps: int):
         wl = beams.mono_headon_2k()
     elif name == "broadband_16m":
         wl = beams.broadband_16m()
+    elif name in ("positron_spectra_1m_5_5", "positron_spectra_1m_7_3"):
+        g1, g2 = (5.0, 5.0) if name.endswith("5_5") else (7.0, 3.0)
+        wl = beams.positron_spectra_1m(g1, g2)
     elif name == "batch64":
         parts_a, parts_b = [], []
         for m in range(64):
@@ -170,6 +173,46 @@ def st_bench(args):
                   "cloud_pair_steps_per_run": st["n_candidates"] // max(args.steps + args.warmup, 1)},
     }
     print(json.dumps(out), flush=True)
+
+
+KIN_BYTES_PER_PAIR = 12 + 2 * 5 * 8 + 64  # (i, j, k), E p w of both photons, 8 lepton doubles
+
+
+def kinematics_variant(T, torch, A, B, wl, n_steps, edges, reps=5):
+    """Pair kinematics after one collision run (the run's unique pairs) and on a bulk list
+    of 2^22 random pairs over the same beams: kernel time from HIP events on the library's
+    stream, pairs per second and algorithmic GB/s."""
+    import numpy as np
+    g_edges = np.linspace(1.0, 40.0, 391)
+    ctx = T.Context(wl.dt, edges)
+    try:
+        qb, tb = T.Beam(A), T.Beam(B)
+        pairs = T.Pairs(1 << 21)
+        T.run_steps(ctx, tb, qb, n_steps, pairs, graph=True)
+        st = ctx.stats(pairs)
+        n_run = st["n_pairs"]
+        ms_run = min(T.tril_pair_kinematics(ctx, qb, tb, pairs, n_run, 1, g_edges, 90)["ms"]
+                     for _ in range(reps))
+        n = 1 << 22
+        rng = np.random.default_rng(5)
+        bulk = T.Pairs(n)
+        bulk.i.copy_(torch.from_numpy(rng.integers(0, len(A["E"]), n).astype(np.int32)))
+        bulk.j.copy_(torch.from_numpy(rng.integers(0, len(B["E"]), n).astype(np.int32)))
+        bulk.step.copy_(torch.from_numpy(rng.integers(0, n_steps, n).astype(np.int32)))
+        T.tril_pair_kinematics(ctx, qb, tb, bulk, n, 1, g_edges, 90)  # warm-up
+        ms = [T.tril_pair_kinematics(ctx, qb, tb, bulk, n, 1, g_edges, 90)["ms"]
+              for _ in range(reps)]
+    finally:
+        ctx.close()
+    avg = sum(ms) / len(ms)
+    gbs = KIN_BYTES_PER_PAIR * n / (avg * 1e-3) / 1e9
+    return {"run_pairs": n_run, "run_pairs_ms": round(ms_run, 4),
+            "bulk_pairs": n, "bulk_ms": round(avg, 4),
+            "bulk_pairs_per_s": n / (avg * 1e-3),
+            "roofline": {"bound": "hbm", "kernel": "k_pair_kin", "achieved": round(gbs, 2),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "alg_bytes_per_pair": KIN_BYTES_PER_PAIR}}
 
 
 def cpu_baseline(A, offA, B, offB, dt, n_steps, target_s: float):
@@ -334,6 +377,9 @@ def main():
             "value": pairs_per_step * n_steps / (e3 / max(args.steps, 1)),
             "ms_per_step": 1e3 * e3 / max(args.steps, 1), "kept_hits": st3["n_hits"],
             "pairs": st3["n_pairs"]}
+
+    if not args.no_variants and offA is None:
+        variants["pair_kinematics"] = kinematics_variant(T, torch, A, B, wl, n_steps, edges)
 
     roofline = None
     if st["n_collides"] > 0:

@@ -198,6 +198,53 @@ int tril_run(tril_ctx *ctx, const tril_beam *target, const tril_beam *query,
  * counters only. */
 int tril_stats(tril_ctx *ctx, tril_pairs *pairs, tril_stats_t *out);
 
+/* ---------------------------------------------------------------------------------
+ * Pair kinematics (Sec. 1, Eq. pTotal and Eq. Lorentz): the electron and positron each
+ * colliding photon pair creates, in the lab frame. Per pair (i a query row, j a target
+ * row, k its step), FP64:
+ *   E_tot = E_i + E_j, p_tot = p_i + p_j;
+ *   CoM lepton momentum p' = sqrt((E_tot^2 - p_tot^2) / 4 - m_e^2) (c = 1; the mass term
+ *   of Eq. pTotal squared, as its dimensions require), CoM energy E' = sqrt(p'^2 + m_e^2);
+ *   isotropic CoM direction n of the positron (the electron takes -n): cos(theta) =
+ *   2 u0 - 1, phi = 2 pi u1, u0, u1 = (word >> 11) 2^-53 of the first two 64-bit words of
+ *   Philox4x64-10 (Salmon et al., SC'11) at counter (k, i, j, 0), key (seed, 0);
+ *   lab velocity by velocity addition (Eq. Lorentz) of b_CoM = p_tot / E_tot and
+ *   b' = +-(p'/E') n: (b_CoM + b'_par + b'_perp sqrt(1 - b_CoM^2)) / (1 + b'.b_CoM), with
+ *   b'_par the component of b' along b_CoM and b'_perp = b' - b'_par;
+ *   gamma = 1 / sqrt(1 - b^2), E = gamma m_e, p = gamma m_e b.
+ * A pair below threshold (s_ij <= 1, never a hit) gets p' = 0: both leptons move with the
+ * CoM. Histograms of the positron, each pair weighted by sqrt(w_i w_j): Lorentz factor
+ * gamma = E / m_e on caller edges (bin b holds edges[b] <= gamma < edges[b+1]; values
+ * outside are dropped) and polar angle of its momentum to +z, n_theta equal bins over
+ * [0, pi] (angle pi falls in the last bin).
+ * ------------------------------------------------------------------------------- */
+#define TRIL_KIN_MAX_BINS 2048
+
+typedef struct {
+    uint64_t seed;                /* key word 0 of the direction generator */
+    int32_t n_gamma;              /* Lorentz-factor bins, 0 .. TRIL_KIN_MAX_BINS */
+    int32_t n_theta;              /* polar-angle bins, 0 .. TRIL_KIN_MAX_BINS */
+    const double *gamma_edges;    /* host, n_gamma + 1 finite, strictly increasing; may be
+                                     NULL if n_gamma == 0 */
+} tril_kin_params;
+
+typedef struct {
+    double *gamma_hist;           /* host, n_gamma, caller-owned (NULL if n_gamma == 0) */
+    double *theta_hist;           /* host, n_theta, caller-owned (NULL if n_theta == 0) */
+    double ms_kernel;             /* output: kernel time from HIP events on the stream */
+} tril_kin_out;
+
+/* Leptons and positron histograms of the first n entries of `pairs` (pairs->count is not
+ * read; n <= pairs->cap), typically the unique pairs tril_stats leaves in the buffer or the
+ * kept hits of TRIL_ANNIHILATE. query and target are the beams the rows index (instance
+ * offsets are not used). leptons: device, 8 n doubles (positron E px py pz, then electron E
+ * px py pz, per pair), or NULL. Synchronises the context's stream. TRIL_E_INVAL for bad
+ * arguments or when a pair names a row outside its beam or a negative step (such pairs are
+ * skipped; the others are written). */
+int tril_pair_kinematics(tril_ctx *ctx, const tril_beam *query, const tril_beam *target,
+                         const tril_pairs *pairs, int64_t n, const tril_kin_params *params,
+                         double *leptons, tril_kin_out *out);
+
 /* Launch configuration of tril_run (performance only: the results do not depend on it). */
 typedef struct {
     int32_t block_traverse;       /* traversal workgroup size: 64, 128, 256 or 512 */

@@ -82,6 +82,14 @@ def main():
     if args.only in (None, "batch64"):
         for m in range(beams.BATCH64_INSTANCES):
             put(f"batch64/{m}", calibrate(lambda w: beams.batch64_instance(m, w=w), 6000, 2.0e14))
+    if args.only in (None, "positron_spectra_1m"):
+        for g1, g2 in ((5.0, 5.0), (7.0, 3.0)):
+            put(f"positron_spectra_1m/{g1:g}_{g2:g}",
+                calibrate(lambda w: beams.positron_spectra_1m(g1, g2, w=w), 20000, 2.0e16))
+    if args.only in (None, "crossing_angle_1e4"):
+        for phi in (180.0, 90.0, 45.0):
+            put(f"crossing_angle_1e4/{phi:g}",
+                calibrate(lambda w: beams.crossing_angle_1e4(phi, w=w), 10000, 2.0e12))
     with open(out_path, "w") as f:
         json.dump(res, f, indent=1, sort_keys=True)
     print("wrote", out_path)

@@ -54,6 +54,8 @@ class BeamSpec:
     e_par: Tuple[float, ...]  # (E,) | (mean, rms) | (E_min, E_max)
     opening: float          # full opening angle in radians
     w: float                # macro-particle weight (physical photons per photon record)
+    advance: float = 0.0    # every photon moved this far [um] along its own direction after
+                            # the draw (a later time origin for beams that start far away)
 
 
 @dataclass(frozen=True)
@@ -115,6 +117,8 @@ def draw_beam(spec: BeamSpec, rng: np.random.Generator) -> Dict[str, np.ndarray]
                 + cos_t[:, None] * ez)
     else:
         dirs = np.repeat(ez[None, :], n, axis=0)
+    if spec.advance != 0.0:
+        pos = pos + spec.advance * dirs
 
     # energies
     if spec.energy == "mono":
@@ -232,6 +236,39 @@ def broadband_16m(seed: int = 0, w: Optional[float] = None, n: int = 16_000_000)
     a = BeamSpec(n, "gauss", 2.0, 5.0, 20.0, 0.0, "powerlaw", (0.1, 10.0), 0.030, w)
     b = replace(a, phi_deg=150.0)
     return Workload("broadband_16m", a, b, 0.04, 1000, seed)
+
+
+ME = 0.51099895  # electron rest energy [MeV]
+
+
+def positron_spectra_1m(g1: float = 5.0, g2: float = 5.0, seed: int = 0, w: Optional[float] = None,
+                        n: int = 1_000_000) -> Workload:
+    """Positron-spectrum set-up: two head-on mono-energetic cylinder beams of 4 um length and
+    diameter (R = 2 um, L = 4 um), photon energies g1 m_e and g2 m_e (5/5 or 7/3), 20 deg full
+    opening, sources 1 mm apart. Every photon is moved 480 um along its own direction after
+    the draw (time origin 480 um/c after the start), so that 400 steps of 0.1 um/c cover the
+    crossing at t = 20 um/c without the empty approach; by then each beam is a disc of about
+    85 um radius."""
+    key = f"positron_spectra_1m/{g1:g}_{g2:g}"
+    w = _w(key, 1e14) if w is None else w
+    a = BeamSpec(n, "cylinder", 2.0, 4.0, 500.0, 0.0, "mono", (g1 * ME,), math.radians(20.0), w,
+                 advance=480.0)
+    b = replace(a, phi_deg=180.0, e_par=(g2 * ME,))
+    return Workload(key, a, b, 0.1, 400, seed)
+
+
+def crossing_angle_1e4(phi_b: float = 180.0, seed: int = 0, w: Optional[float] = None,
+                       n: int = 10_000) -> Workload:
+    """Crossing-angle study: two beams of 1e4 photon records with gamma = 4 photons
+    (E = 4 m_e), each a cylinder of 1 um^3 (L = 1 um, R = 1/sqrt(pi) um), collimated, the
+    second beam's axis at phi_b degrees to the first; centres start 3 um from the origin,
+    120 steps of 0.05 um/c."""
+    key = f"crossing_angle_1e4/{phi_b:g}"
+    w = _w(key, 1e11) if w is None else w
+    a = BeamSpec(n, "cylinder", 1.0 / math.sqrt(math.pi), 1.0, 3.0, 0.0, "mono", (4.0 * ME,),
+                 0.0, w)
+    b = replace(a, phi_deg=float(phi_b))
+    return Workload(key, a, b, 0.05, 120, seed)
 
 
 def st_headon(n_mp: int = 10_000_000, physical: float = 1e9, seed: int = 0) -> Workload:

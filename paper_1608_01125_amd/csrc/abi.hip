@@ -170,6 +170,9 @@ struct tril_ctx {
     SortScratch ss;
     StatsScratch sst;
     AnnScratch ann;                        // annihilation-mode resolution
+    double *kin_buf = nullptr;             // pair kinematics: edges, histogram bins
+    unsigned int *kin_err = nullptr;
+    hipEvent_t ev_kin[2] = {nullptr, nullptr};
     int32_t max_step = -1;
 
     // timing (TRIL_TIMING)
@@ -1028,6 +1031,59 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     return TRIL_OK;
 }
 
+int tril_pair_kinematics(tril_ctx *c, const tril_beam *q, const tril_beam *t,
+                         const tril_pairs *p, int64_t n, const tril_kin_params *kp,
+                         double *leptons, tril_kin_out *out) {
+    if (!c || !kp || !out || n < 0) return TRIL_E_INVAL;
+    CHK(check_beam(q));
+    CHK(check_beam(t));
+    if (n > 0) {
+        CHK(check_pairs(p));
+        if (n > p->cap) return TRIL_E_INVAL;
+    }
+    const int32_t ng = kp->n_gamma, nth = kp->n_theta;
+    if (ng < 0 || ng > TRIL_KIN_MAX_BINS || nth < 0 || nth > TRIL_KIN_MAX_BINS) return TRIL_E_INVAL;
+    if (ng > 0) {
+        if (!kp->gamma_edges) return TRIL_E_INVAL;
+        for (int32_t b = 0; b <= ng; ++b)
+            if (!std::isfinite(kp->gamma_edges[b]) || (b > 0 && !(kp->gamma_edges[b] > kp->gamma_edges[b - 1])))
+                return TRIL_E_INVAL;
+    }
+    if ((ng > 0 && !out->gamma_hist) || (nth > 0 && !out->theta_hist)) return TRIL_E_INVAL;
+    out->ms_kernel = 0.0;
+    constexpr int64_t kBuf = 3 * TRIL_KIN_MAX_BINS + 1;  // edges, then the histogram bins
+    if (!c->kin_buf) {
+        CHK(dev_alloc(&c->kin_buf, (size_t)kBuf));
+        CHK(dev_alloc(&c->kin_err, 1));
+        for (hipEvent_t &e : c->ev_kin) HIPCHK(hipEventCreate(&e));
+    }
+    double *d_edges = c->kin_buf, *d_hist = c->kin_buf + (ng + 1);
+    const int32_t nb = ng + nth;
+    if (ng > 0)
+        HIPCHK(hipMemcpyAsync(d_edges, kp->gamma_edges, (size_t)(ng + 1) * sizeof(double),
+                              hipMemcpyHostToDevice, c->st));
+    if (nb > 0) HIPCHK(hipMemsetAsync(d_hist, 0, (size_t)nb * sizeof(double), c->st));
+    HIPCHK(hipMemsetAsync(c->kin_err, 0, sizeof(unsigned int), c->st));
+    HIPCHK(hipEventRecord(c->ev_kin[0], c->st));
+    if (n > 0)
+        launch_pair_kinematics(view(q, nullptr, 1), view(t, nullptr, 1), p->i, p->j, p->step, n,
+                               kp->seed, leptons, d_edges, ng, nth, d_hist, c->kin_err, c->st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(c->ev_kin[1], c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev_kin[0], c->ev_kin[1]));
+    out->ms_kernel = ms;
+    std::vector<double> h((size_t)std::max(nb, 1), 0.0);
+    if (nb > 0)
+        HIPCHK(hipMemcpy(h.data(), d_hist, (size_t)nb * sizeof(double), hipMemcpyDeviceToHost));
+    for (int32_t b = 0; b < ng; ++b) out->gamma_hist[b] = h[b];
+    for (int32_t b = 0; b < nth; ++b) out->theta_hist[b] = h[ng + b];
+    unsigned int err = 0;
+    HIPCHK(hipMemcpy(&err, c->kin_err, sizeof(err), hipMemcpyDeviceToHost));
+    return err ? TRIL_E_INVAL : TRIL_OK;
+}
+
 int tril_st_bin(const tril_beam *b, const tril_st_grid *g, int32_t *bins, double *sums,
                 void *stream) {
     CHK(check_beam(b));
@@ -1761,6 +1817,10 @@ void tril_destroy(tril_ctx *c) {
     free_target(c);
     free_target_rows(c);
     free_annihilation(c);
+    dev_free(c->kin_buf);
+    dev_free(c->kin_err);
+    for (hipEvent_t e : c->ev_kin)
+        if (e) (void)hipEventDestroy(e);
     for (int p = 0; p < 2; ++p) {
         free_work(c->wt[p]);
         free_work(c->wq[p]);

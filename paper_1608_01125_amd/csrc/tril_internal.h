@@ -343,6 +343,18 @@ hipError_t annihilate_hits(const tril_pairs &p, int64_t n, const BeamDev &q, con
                            double dt, int32_t max_step, AnnScratch &a, SortScratch &ss,
                            unsigned int *err, hipStream_t st, int64_t *n_kept);
 
+// ------------------------------------------------------------ pair kinematics
+// Leptons of the n pairs (pi[h] a row of q, pj[h] a row of t, pk[h] its step): 8 doubles
+// per pair (positron E px py pz, electron E px py pz) to leptons when not null, and the
+// positron histograms added to hist (n_gamma Lorentz-factor bins on edges[0..n_gamma], then
+// n_theta polar-angle bins; hist zeroed by the caller). A pair naming a row outside its beam
+// or a negative step sets bit 1 of *err and is skipped. LDS: (2 n_gamma + 1 + n_theta)
+// doubles per workgroup.
+void launch_pair_kinematics(const BeamDev &q, const BeamDev &t, const int32_t *pi,
+                            const int32_t *pj, const int32_t *pk, int64_t n, uint64_t seed,
+                            double *leptons, const double *edges, int32_t n_gamma,
+                            int32_t n_theta, double *hist, unsigned int *err, hipStream_t st);
+
 // ------------------------------------------------------------------ run stats
 struct StatsScratch {
     unsigned long long *keys = nullptr, *keys_alt = nullptr;

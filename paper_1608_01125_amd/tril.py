@@ -97,7 +97,19 @@ class tril_st_sur_result(ctypes.Structure):
                 ("predicted_spread", ctypes.c_double)]
 
 
+class tril_kin_params(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("n_gamma", ctypes.c_int32),
+                ("n_theta", ctypes.c_int32), ("gamma_edges", _dp)]
+
+
+class tril_kin_out(ctypes.Structure):
+    _fields_ = [("gamma_hist", _dp), ("theta_hist", _dp), ("ms_kernel", ctypes.c_double)]
+
+
+TRIL_KIN_MAX_BINS = 2048
+
 EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats",
+           "tril_pair_kinematics",
            "tril_autotune", "tril_set_tune", "tril_st_bin", "tril_st_exact",
            "tril_mlp_create", "tril_mlp_destroy", "tril_mlp_set_params", "tril_mlp_get_params",
            "tril_mlp_set_norm", "tril_mlp_fit_norm", "tril_mlp_grad", "tril_mlp_train",
@@ -126,6 +138,10 @@ def lib() -> ctypes.CDLL:
     L.tril_run.argtypes = [vp, ctypes.POINTER(tril_beam), ctypes.POINTER(tril_beam), i32, i32,
                            ctypes.POINTER(tril_pairs)]
     L.tril_stats.argtypes = [vp, ctypes.POINTER(tril_pairs), ctypes.POINTER(tril_stats_t)]
+    L.tril_pair_kinematics.argtypes = [vp, ctypes.POINTER(tril_beam), ctypes.POINTER(tril_beam),
+                                       ctypes.POINTER(tril_pairs), i64,
+                                       ctypes.POINTER(tril_kin_params), vp,
+                                       ctypes.POINTER(tril_kin_out)]
     L.tril_autotune.argtypes = [vp, ctypes.POINTER(tril_beam), ctypes.POINTER(tril_beam), i32, i32,
                                 ctypes.POINTER(tril_tune)]
     L.tril_set_tune.argtypes = [vp, ctypes.POINTER(tril_tune)]
@@ -293,6 +309,40 @@ def tril_collide(ctx, query: Beam, step: int, pairs: Pairs) -> None:
 def tril_run(ctx, target: Beam, query: Beam, k0: int, n_steps: int, pairs: Pairs) -> None:
     _check(lib().tril_run(ctx, ctypes.byref(target.c), ctypes.byref(query.c), int(k0),
                           int(n_steps), ctypes.byref(pairs.c)), "tril_run")
+
+
+def tril_pair_kinematics(ctx, query: Beam, target: Beam, pairs: Pairs, n: int, seed: int,
+                         gamma_edges: Optional[np.ndarray] = None, n_theta: int = 0,
+                         leptons: bool = True, check: bool = True) -> dict:
+    """Leptons (device float64 tensor (n, 8): positron E px py pz, electron E px py pz) of
+    the first n pairs, and the positron Lorentz-factor and polar-angle histograms."""
+    import torch
+    kp = tril_kin_params()
+    kp.seed = int(seed) & ((1 << 64) - 1)
+    keep = None
+    if gamma_edges is not None and len(gamma_edges) > 1:
+        keep = np.ascontiguousarray(gamma_edges, dtype=np.float64)
+        kp.n_gamma = len(keep) - 1
+        kp.gamma_edges = keep.ctypes.data_as(_dp)
+    else:
+        kp.n_gamma = 0
+        kp.gamma_edges = None
+    kp.n_theta = int(n_theta)
+    gh = np.zeros(max(kp.n_gamma, 1))
+    th = np.zeros(max(kp.n_theta, 1))
+    out = tril_kin_out()
+    out.gamma_hist = gh.ctypes.data_as(_dp) if kp.n_gamma > 0 else None
+    out.theta_hist = th.ctypes.data_as(_dp) if kp.n_theta > 0 else None
+    lep = (torch.empty((max(int(n), 1), 8), dtype=torch.float64, device=pairs.i.device)
+           if leptons else None)
+    code = lib().tril_pair_kinematics(_h(ctx), ctypes.byref(query.c), ctypes.byref(target.c),
+                                      ctypes.byref(pairs.c), int(n), ctypes.byref(kp),
+                                      lep.data_ptr() if lep is not None else None,
+                                      ctypes.byref(out))
+    if check:
+        _check(code, "tril_pair_kinematics")
+    return {"code": code, "leptons": lep[:int(n)] if lep is not None else None,
+            "gamma_hist": gh[:kp.n_gamma], "theta_hist": th[:kp.n_theta], "ms": out.ms_kernel}
 
 
 TUNE_KEYS = ("block_traverse", "step_batch", "morton_bits")
