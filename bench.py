@@ -176,6 +176,25 @@ def st_bench(args):
 
 
 KIN_BYTES_PER_PAIR = 12 + 2 * 5 * 8 + 64  # (i, j, k), E p w of both photons, 8 lepton doubles
+KIN_SUMMARY = os.path.join(ROOT, "profiles", "pair_kin_positron_spectra_1m.md")
+
+
+def kinematics_traffic(n_pairs):
+    """HBM bytes per bulk launch of the kinematics kernel from the committed counter summary,
+    or None when it belongs to another kernel source or another bulk size."""
+    if not os.path.exists(KIN_SUMMARY):
+        return None
+    vals = {}
+    with open(KIN_SUMMARY) as f:
+        for line in f:
+            if ":" in line and line.startswith("    "):
+                k, v = line.strip().split(":", 1)
+                vals[k.strip()] = v.strip()
+    with open(os.path.join(ROOT, "paper_1608_01125_amd/csrc/kinematics.hip"), "rb") as f:
+        src = hashlib.sha256(f.read()).hexdigest()[:16]
+    if vals.get("source_sha256") != src or vals.get("bulk_pairs") != str(n_pairs):
+        return None
+    return float(vals["traffic_bytes_per_dispatch"])
 
 
 def kinematics_variant(T, torch, A, B, wl, n_steps, edges, reps=5):
@@ -206,12 +225,15 @@ def kinematics_variant(T, torch, A, B, wl, n_steps, edges, reps=5):
         ctx.close()
     avg = sum(ms) / len(ms)
     gbs = KIN_BYTES_PER_PAIR * n / (avg * 1e-3) / 1e9
+    traffic = kinematics_traffic(n)
     return {"run_pairs": n_run, "run_pairs_ms": round(ms_run, 4),
             "bulk_pairs": n, "bulk_ms": round(avg, 4),
             "bulk_pairs_per_s": n / (avg * 1e-3),
             "roofline": {"bound": "hbm", "kernel": "k_pair_kin", "achieved": round(gbs, 2),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                         "traffic_achieved_GBs": (round(traffic / (avg * 1e-3) / 1e9, 2)
+                                                  if traffic else None),
                          "alg_bytes_per_pair": KIN_BYTES_PER_PAIR}}
 
 
