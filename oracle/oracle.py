@@ -90,6 +90,8 @@ def lib():
                                    ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, d,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(d),
                                    ctypes.POINTER(d)]
+        L.orc_st_exposure.restype = None
+        L.orc_st_exposure.argtypes = L.orc_st_pairs.argtypes
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -129,6 +131,26 @@ def st_pairs(A, B, dt: float, k0: int, n_steps: int, cell, rows: Optional[np.nda
     lib().orc_st_pairs(ctypes.byref(a), ctypes.byref(b), rp, nr, float(dt), int(k0), int(n_steps),
                        c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def st_exposure(A, B, dt: float, k0: int, n_steps: int, cell,
+                rows: Optional[np.ndarray] = None) -> np.ndarray:
+    """Exposure S of every (query row, target photon) cloud pair summed over steps k0 ..
+    k0+n_steps-1 (see orc_st_exposure). Shape (rows, n_B)."""
+    keep: list = []
+    a, b = _as_beam(A, keep), _as_beam(B, keep)
+    c = np.ascontiguousarray(cell, dtype=np.float64)
+    nr = len(A["E"]) if rows is None else len(rows)
+    out = np.zeros((nr, len(B["E"])), dtype=np.float64)
+    rp = None
+    if rows is not None:
+        rws = np.ascontiguousarray(rows, dtype=np.int64)
+        keep.append(rws)
+        rp = rws.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    lib().orc_st_exposure(ctypes.byref(a), ctypes.byref(b), rp, nr, float(dt), int(k0),
+                          int(n_steps), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return out
 
 

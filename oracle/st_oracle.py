@@ -101,3 +101,73 @@ def st_table(A, bins_a, B, bins_b, n_bins_b: int, dt: float, k0: int, n_steps: i
     tot = np.zeros(len(uk))
     np.add.at(tot, inv, v)
     return dict(zip(uk.tolist(), tot.tolist())), float(Y.sum())
+
+
+# --------------------------------------------------------------------------------------
+# Depletion (Sec. 2.2, the rate equation with the loss of collision partners). Two clouds of
+# densities n_I(0), n_II(0) create pairs at the rate dn/dt = k (n_I(0) - n)(n_II(0) - n), with
+# n0 = n_I(0) + n_II(0) and alpha = n_I(0) / n0. The printed reactivity 2 pi sigma c is read as
+# k = sigma c (1 - cos phi), the factor the closed form n_alpha carries (the two printed
+# closed forms use different constants; both solve the same equation).
+#
+# Per cloud pair the overlap changes from step to step. With the densities of the shared
+# volume depleted only by the pair's own creations, the equation is autonomous in n with the
+# rate scaled by V_ov(t) / V, so its solution is the closed form at the pair's exposure
+#   k tau -> S = sum_k sigma (1 - cos phi) dt V_ov(t_k) / V      (orc_st_exposure),
+# and the pair's depleted yield (physical pairs) is V n(S).
+# --------------------------------------------------------------------------------------
+
+
+def n_half(n0: float, k_tau: float) -> float:
+    """Closed form for equal densities (alpha = 1/2): (n0/2)^2 k tau / (1 + (n0/2) k tau)."""
+    h = n0 / 2.0
+    return (h * h * k_tau) / (1.0 + h * k_tau)
+
+
+def n_alpha(n0: float, alpha: float, k_tau: float) -> float:
+    """Closed form for alpha != 1/2: (alpha - 1) alpha n0 (1 - e^X) / (alpha e^X + alpha - 1),
+    X = n0 (2 alpha - 1) k tau, with e^X written as 1 + expm1(X) (the same expression; it
+    keeps the small-X regime, where 1 - e^X cancels, at full precision)."""
+    X = n0 * (2.0 * alpha - 1.0) * k_tau
+    E = np.expm1(X)
+    return ((alpha - 1.0) * alpha * n0 * (-E)) / (alpha * E + (2.0 * alpha - 1.0))
+
+
+def depleted_density(a: float, b: float, k_tau: float) -> float:
+    """Pair density created by two clouds of densities a and b at exposure k tau. The equation
+    is symmetric in a and b; alpha is taken as the smaller share so that X <= 0 (e^X never
+    overflows)."""
+    if a <= 0.0 or b <= 0.0 or k_tau <= 0.0:
+        return 0.0
+    n0 = a + b
+    if a == b:
+        return n_half(n0, k_tau)
+    return n_alpha(n0, min(a, b) / n0, k_tau)
+
+
+def st_depleted_pairs(A, B, dt: float, k0: int, n_steps: int, cell,
+                      rows: Optional[np.ndarray] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """Depleted yield and exposure of every (query row, target photon) cloud pair: (Y, S),
+    shape (rows, n_B); Y = V n(w_i / V, w_j / V, S)."""
+    S = O.st_exposure(A, B, dt, k0, n_steps, cell, rows=rows)
+    V = (cell[0] * cell[1]) * cell[2]
+    wa = A["w"] if rows is None else A["w"][rows]
+    Y = np.zeros_like(S)
+    for a, b in zip(*np.nonzero(S > 0.0)):
+        Y[a, b] = V * depleted_density(wa[a] / V, B["w"][b] / V, S[a, b])
+    return Y, S
+
+
+def st_depleted_table(A, bins_a, B, bins_b, n_bins_b: int, dt: float, k0: int, n_steps: int,
+                      cell) -> Tuple[Dict[int, float], float, Dict[int, float]]:
+    """Bin-pair depleted yields {bin_a * n_bins_b + bin_b: Y}, their total, and the per-pair
+    yields {i * n_B + j: Y} (pairs with a positive exposure whose rows both have a bin)."""
+    Y, S = st_depleted_pairs(A, B, dt, k0, n_steps, cell)
+    keys = bins_a[:, None].astype(np.int64) * n_bins_b + bins_b[None, :]
+    ok = (S > 0.0) & (bins_a[:, None] >= 0) & (bins_b[None, :] >= 0)
+    tab: Dict[int, float] = {}
+    for k, v in zip(keys[ok].tolist(), Y[ok].tolist()):
+        tab[k] = tab.get(k, 0.0) + v
+    ia, jb = np.nonzero(ok)
+    pairs = {int(i) * len(B["E"]) + int(j): float(Y[i, j]) for i, j in zip(ia, jb)}
+    return tab, float(sum(pairs.values())), pairs

@@ -309,6 +309,47 @@ void orc_st_pairs(const orc_beam *A, const orc_beam *B, const int64_t *rows, int
     }
 }
 
+/* Exposure of every cloud pair for the depletion picture (Sec. 2.2, the rate equation
+ * integrated with the loss of collision partners): per pair, summed over steps k0 ..
+ * k0+n_steps-1 at mid-step,
+ *   S = sum_k sigma(s) (1 - u_i.u_j) dt V_ov / V,
+ * i.e. k tau of the closed forms with k = sigma c (1 - cos phi) and the time weighted by the
+ * fraction of a cloud's volume the two clouds share. out[a * nB + j] as in orc_st_pairs. */
+void orc_st_exposure(const orc_beam *A, const orc_beam *B, const int64_t *rows, int64_t n_rows,
+                     double dt, int32_t k0, int32_t n_steps, const double *cell, double *out)
+{
+    const int64_t nr = rows ? n_rows : A->n;
+    const double vol = cell[0] * cell[1] * cell[2];
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (int64_t a = 0; a < nr; ++a) {
+        const int64_t i = rows ? rows[a] : a;
+        const double Ei = A->E[i];
+        const double ui[3] = {A->px[i] / Ei, A->py[i] / Ei, A->pz[i] / Ei};
+        for (int64_t j = 0; j < B->n; ++j) {
+            const double Ej = B->E[j];
+            const double uj[3] = {B->px[j] / Ej, B->py[j] / Ej, B->pz[j] / Ej};
+            const double s = orc_invariant(Ei, ui[0], ui[1], ui[2], Ej, uj[0], uj[1], uj[2]);
+            double x = 0.0;
+            if (s > 1.0) {
+                const double sig = orc_sigma(s);
+                const double cosphi = (ui[0] * uj[0] + ui[1] * uj[1]) + ui[2] * uj[2];
+                for (int32_t k = k0; k < k0 + n_steps; ++k) {
+                    const double tm = (double)k * dt + 0.5 * dt;
+                    const double dx = (A->x[i] + tm * ui[0]) - (B->x[j] + tm * uj[0]);
+                    const double dy = (A->y[i] + tm * ui[1]) - (B->y[j] + tm * uj[1]);
+                    const double dz = (A->z[i] + tm * ui[2]) - (B->z[j] + tm * uj[2]);
+                    const double ov = orc_cloud_overlap(dx, dy, dz, cell);
+                    if (ov > 0.0)
+                        x += (((sig * (1.0 - cosphi)) * dt) * ov) / vol;
+                }
+            }
+            out[a * B->n + j] = x;
+        }
+    }
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
