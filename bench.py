@@ -147,10 +147,29 @@ def st_bench(args):
             res = inst.surrogate(ctx, net, p)
         torch.cuda.synchronize()
         t_sur = (time.perf_counter() - t1) / max(args.steps, 1)
+        # depletion (closed forms per cloud pair) against the linear exact yields, at a photon
+        # number where depletion matters, on a smaller instance (one table slot per cloud pair)
+        dinst = surrogate.Instance(beams.st_headon(args.st_dep_mp, physical=args.st_dep_physical))
+        dinst.exact(ctx)
+        dinst.exact_depleted(ctx, pair_log2=26)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            _, lin_total = dinst.exact(ctx)
+        torch.cuda.synchronize()
+        t_lin = (time.perf_counter() - t1) / max(args.steps, 1)
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            _, pt, dep_total = dinst.exact_depleted(ctx, pair_log2=26)
+        torch.cuda.synchronize()
+        t_dep = (time.perf_counter() - t1) / max(args.steps, 1)
+        n_cloud_pairs = int((pt.key >= 0).sum().item())
+        del dinst, pt
     finally:
         net.close()
         ctx.close()
     n = args.st_mp
+    nd = args.st_dep_mp
     q = float(n) * n * 400
     out = {
         "metric": METRIC, "value": q / t_sur, "unit": "queries/s", "n_gpus": 1,
@@ -169,6 +188,12 @@ def st_bench(args):
                       "exact_part": res["exact_part"] / max(res["total"], 1e-300),
                       "predicted_spread": res["predicted_spread"],
                       "speedup_vs_exact": t_exact / t_sur},
+        "exact_depleted": {"macro_particles_per_beam": nd,
+                           "physical_photons_per_beam": args.st_dep_physical,
+                           "queries_per_s": float(nd) * nd * 400 / t_dep, "ms": 1e3 * t_dep,
+                           "ms_linear": 1e3 * t_lin, "total": dep_total,
+                           "linear_total": lin_total, "ratio_to_linear": dep_total / lin_total,
+                           "cloud_pairs": n_cloud_pairs},
         "exact": {"queries_per_s": q / t_exact, "ms": 1e3 * t_exact, "total": exact_total,
                   "cloud_pair_steps_per_run": st["n_candidates"] // max(args.steps + args.warmup, 1)},
     }
@@ -300,6 +325,10 @@ def main():
     ap.add_argument("--st-mp", type=int, default=200_000,
                     help="st_headon: macro-particles per beam")
     ap.add_argument("--st-train", type=int, default=8, help="st_headon: training instances")
+    ap.add_argument("--st-dep-mp", type=int, default=20_000,
+                    help="st_headon: macro-particles per beam of the depletion measurement")
+    ap.add_argument("--st-dep-physical", type=float, default=1e20,
+                    help="st_headon: physical photons per beam of the depletion measurement")
     ap.add_argument("--st-train-steps", type=int, default=4000, help="st_headon: Adam steps")
     ap.add_argument("--autotune", action="store_true",
                     help="pick steps per launch, traversal workgroup size and Morton bits with "

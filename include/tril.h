@@ -328,6 +328,26 @@ int tril_st_exact(tril_ctx *ctx, const tril_beam *target, const int32_t *t_bins,
                   const double cell[3], int32_t k0, int32_t n_steps, tril_st_table *table,
                   double *total);
 
+/* Exact ST yields with depletion (Sec. 2.2: the rate equation with the loss of collision
+ * partners, integrated in closed form). The printed reactivity is read as
+ * k = sigma c (1 - cos phi). Per cloud pair (i, j) the exposure over steps k0 ..
+ * k0+n_steps-1,
+ *   S_ij = sum_k sigma(s_ij) (1 - u_i.u_j) dt V_ov(t_m) / V        (k tau of the closed forms),
+ * takes the place of k tau; with a = w_i / V, b = w_j / V, n0 = a + b:
+ *   a == b:  n = (n0/2)^2 S / (1 + (n0/2) S)                                      (n_1/2)
+ *   a != b:  n = (alpha - 1) alpha n0 (1 - e^X) / (alpha e^X + alpha - 1),         (n_alpha)
+ *            alpha = min(a, b) / n0, X = n0 (2 alpha - 1) S,
+ * and the pair yields V n (never more than min(w_i, w_j); V n -> the linear yield of
+ * tril_st_exact as a S, b S -> 0). Each pair is depleted by its own creations only.
+ * pair_table (cleared first, cap a power of two) receives one slot per cloud pair with a
+ * positive exposure: key i * target->n + j (caller rows), yield = the pair's depleted yield;
+ * table and *total as for tril_st_exact, with depleted yields. Synchronous; errors as for
+ * tril_st_exact (TRIL_E_OVERFLOW when either table filled up). */
+int tril_st_exact_depleted(tril_ctx *ctx, const tril_beam *target, const int32_t *t_bins,
+                           int64_t n_target_bins, const tril_beam *query, const int32_t *q_bins,
+                           const double cell[3], int32_t k0, int32_t n_steps,
+                           tril_st_table *pair_table, tril_st_table *table, double *total);
+
 /* ---------------------------------------------------------------------------------
  * Surrogate path of the statistical regime (uses the network declared below).
  *

@@ -1290,6 +1290,35 @@ int tril_st_exact(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_
     return st_finish(c, total);
 }
 
+int tril_st_exact_depleted(tril_ctx *c, const tril_beam *t, const int32_t *t_bins,
+                           int64_t n_t_bins, const tril_beam *q, const int32_t *q_bins,
+                           const double cell[3], int32_t k0, int32_t n_steps,
+                           tril_st_table *pair_tab, tril_st_table *tab, double *total) {
+    if (!c || !cell || !tab || !pair_tab || !total || k0 < 0 || n_steps < 0) return TRIL_E_INVAL;
+    CHK(check_beam(t));
+    CHK(check_beam(q));
+    if ((t->n > 0 && !t_bins) || (q->n > 0 && !q_bins)) return TRIL_E_INVAL;
+    if (n_t_bins < 1 || n_t_bins > INT32_MAX) return TRIL_E_INVAL;
+    CHK(check_cell(cell));
+    for (const tril_st_table *tb : {tab, pair_tab})
+        if (tb->cap < 1 || (tb->cap & (tb->cap - 1)) != 0 || !tb->key || !tb->yield)
+            return TRIL_E_INVAL;
+    if (q->n_inst != t->n_inst) return TRIL_E_STATE;
+    if ((int64_t)k0 + n_steps - 1 > INT32_MAX) return TRIL_E_INVAL;
+    *total = 0.0;
+    long long *pkeys = reinterpret_cast<long long *>(pair_tab->key);
+    CHK(st_run(c, t, t_bins, n_t_bins, q, q_bins, cell, k0, n_steps, 2, nullptr, 0, pkeys,
+               pair_tab->yield, pair_tab->cap));
+    long long *keys = reinterpret_cast<long long *>(tab->key);
+    launch_st_clear(keys, tab->yield, tab->cap, c->st_slots, c->st);
+    const StCell sc{{cell[0], cell[1], cell[2]}};
+    launch_st_deplete(pkeys, pair_tab->yield, pair_tab->cap, view(q, c->d_q_off, 1),
+                      view(t, c->d_t_off, 1), q_bins, t_bins, n_t_bins, sc, keys, tab->yield,
+                      tab->cap, c->st_slots, c->d_cnt, c->st);
+    HIPCHK(hipGetLastError());
+    return st_finish(c, total);
+}
+
 int tril_st_features(tril_ctx *c, const double *q_sums, const tril_st_grid *gq,
                      const double *t_sums, const tril_st_grid *gt, int32_t k0, int32_t n_steps,
                      const tril_st_sur_params *p, float *x, double *y0, int64_t *key, int64_t cap,

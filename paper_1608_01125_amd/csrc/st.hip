@@ -18,6 +18,18 @@
 // keeps a running sum while consecutive leaves fall in the same bin pair (neighbouring
 // leaves in Morton order usually share their cell) and adds it to the table once.
 //
+// Depletion (the rate equation of Sec. 2.2 with the loss of collision partners): in
+// exposure mode the traversal adds, per cloud pair (key = i * n_target + j), the pair's
+// exposure S_k = sigma (1 - u_i.u_j) dt V_ov(t_m) / V, evaluated in the order
+// (((sigma (1 - u_i.u_j)) dt) V_ov) / V; afterwards every pair gets the closed-form pair
+// density at its summed exposure (k tau -> S, k = sigma c (1 - cos phi)): with
+// n0 = a + b, a = w_i / V, b = w_j / V,
+//     a == b:  (n0/2)^2 S / (1 + (n0/2) S)
+//     a != b:  (alpha - 1) alpha n0 (-expm1(X)) / (alpha expm1(X) + 2 alpha - 1),
+//              alpha = min(a, b) / n0, X = n0 (2 alpha - 1) S <= 0,
+// and the depleted yield V n(S) replaces the pair's exposure in its slot and is added to
+// the bin-pair table.
+//
 // Binning: 3-D cell of the position at the grid time t_bin, log-spaced energy bin,
 // polar-angle bin of the direction about the beam axis; values outside a range go to
 // its edge bin; bin = (((ix ny + iy) nz + iz) n_e + ie) n_th + ith.
@@ -151,8 +163,9 @@ __device__ __forceinline__ double st_yield(const BeamDev &q, int64_t i, const Be
     const double oz = cell.c[2] - fabs((q.z[i] + tm * uiz) - (t.z[j] + tm * ujz));
     if (!(ox > 0.0 && oy > 0.0 && oz > 0.0)) return 0.0;
     const double vov = (ox * oy) * oz;
-    if (geometric) return dt * vov;
+    if (geometric == 1) return dt * vov;
     const double V = (cell.c[0] * cell.c[1]) * cell.c[2];
+    if (geometric == 2) return (((bw_sigma(s) * (1.0 - cphi)) * dt) * vov) / V;
     return (((((q.w[i] * t.w[j]) / (V * V)) * bw_sigma(s)) * (1.0 - cphi)) * dt) * vov;
 }
 
@@ -168,7 +181,8 @@ __device__ __forceinline__ void st_leaf(const BeamDev &q, int64_t i, const BeamD
                                         uint32_t &n_pairs, DevCounters *c) {
     const int64_t j = e - so * t.n;
     const int32_t bt = t_bins[j];
-    const long long key = (long long)bq * n_t_bins + bt;
+    // bin-pair key, or in exposure mode the cloud pair (caller rows)
+    const long long key = geometric == 2 ? (long long)i * t.n + j : (long long)bq * n_t_bins + bt;
     const bool keep = bt >= 0 && (filter == nullptr || set_has(filter, fmask, key));
     const double Y = keep ? st_yield(q, i, t, j, tk, dt, cell, geometric) : 0.0;
     if (Y > 0.0) {
@@ -288,6 +302,47 @@ __global__ void __launch_bounds__(BLOCK) k_st_traverse(
         if (np_) atomicAdd(&c->st_pairs, np_);
         if (tot != 0.0) atomicAdd(&slots[slot], tot);
     }
+}
+
+// Closed-form pair density of two clouds of densities a, b at exposure S (file comment).
+__device__ __forceinline__ double depleted_density(double a, double b, double S) {
+    if (!(a > 0.0) || !(b > 0.0) || !(S > 0.0)) return 0.0;
+    const double n0 = a + b;
+    if (a == b) {
+        const double h = n0 / 2.0;
+        return ((h * h) * S) / (1.0 + h * S);
+    }
+    const double alpha = fmin(a, b) / n0;
+    const double X = (n0 * (2.0 * alpha - 1.0)) * S;
+    const double E = expm1(X);
+    return ((((alpha - 1.0) * alpha) * n0) * (-E)) / (alpha * E + (2.0 * alpha - 1.0));
+}
+
+// Every occupied slot of the cloud-pair table: exposure -> depleted yield (in place), added
+// to the bin-pair table; per-wave totals into the slots.
+__global__ void __launch_bounds__(256) k_st_deplete(long long *__restrict__ pkeys,
+                                                    double *__restrict__ pvals, int64_t pcap,
+                                                    BeamDev q, BeamDev t,
+                                                    const int32_t *__restrict__ q_bins,
+                                                    const int32_t *__restrict__ t_bins,
+                                                    int64_t n_t_bins, StCell cell,
+                                                    long long *keys, double *vals, uint64_t mask,
+                                                    double *__restrict__ slots, DevCounters *c) {
+    const double V = (cell.c[0] * cell.c[1]) * cell.c[2];
+    double tot = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < pcap; h += stride) {
+        const long long key = pkeys[h];
+        if (key < 0) continue;
+        const int64_t i = key / t.n, j = key - i * t.n;
+        const double Y = V * depleted_density(q.w[i] / V, t.w[j] / V, pvals[h]);
+        pvals[h] = Y;
+        tot += Y;
+        table_add(keys, vals, mask, (long long)q_bins[i] * n_t_bins + t_bins[j], Y, &c->err);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) tot += __shfl_xor(tot, off);
+    if ((threadIdx.x & 63) == 0 && tot != 0.0) atomicAdd(&slots[blockIdx.x & (kCounterSlots - 1)], tot);
 }
 
 // One cloud per occupied bin: weighted-mean energy, direction and position (at the grid
@@ -524,6 +579,16 @@ void launch_st_bin(const BeamDev &b, const StGridDev &g, int32_t *bins, double *
                    hipStream_t st) {
     if (b.n <= 0) return;
     hipLaunchKernelGGL(k_st_bin, dim3(grid_for(b.n, 256)), dim3(256), 0, st, b, g, bins, sums);
+}
+
+void launch_st_deplete(long long *pkeys, double *pvals, int64_t pcap, const BeamDev &q,
+                       const BeamDev &t, const int32_t *q_bins, const int32_t *t_bins,
+                       int64_t n_t_bins, const StCell &cell, long long *keys, double *vals,
+                       int64_t cap, double *slots, DevCounters *c, hipStream_t st) {
+    if (pcap <= 0 || t.n <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>(grid_for(pcap, 256), 4096);
+    hipLaunchKernelGGL(k_st_deplete, dim3(grid), dim3(256), 0, st, pkeys, pvals, pcap, q, t,
+                       q_bins, t_bins, n_t_bins, cell, keys, vals, (uint64_t)(cap - 1), slots, c);
 }
 
 void launch_st_clear(long long *keys, double *vals, int64_t cap, double *slots, hipStream_t st) {

@@ -310,6 +310,13 @@ void launch_st_mask_bins(const int32_t *bins, int64_t n, const uint8_t *mark, in
 void launch_fill_keys(long long *p, int64_t n, hipStream_t st);
 void launch_st_clear(long long *keys, double *vals, int64_t cap, double *slots, hipStream_t st);
 // Arguments as for launch_traverse.
+// Depletion pass over the cloud-pair table (pkeys = i * t.n + j, pvals = exposure): every
+// pair's exposure becomes its depleted yield, which is added to the bin-pair table
+// (keys/vals, cap a power of two) under (q_bins[i], t_bins[j]); totals into slots.
+void launch_st_deplete(long long *pkeys, double *pvals, int64_t pcap, const BeamDev &q,
+                       const BeamDev &t, const int32_t *q_bins, const int32_t *t_bins,
+                       int64_t n_t_bins, const StCell &cell, long long *keys, double *vals,
+                       int64_t cap, double *slots, DevCounters *c, hipStream_t st);
 void launch_st_traverse(const Node *nodes, int64_t n_int, const PBox *root_box, const PBox *qbox,
                         const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
                         const int32_t *inst_root,

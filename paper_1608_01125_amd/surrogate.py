@@ -50,6 +50,13 @@ class Instance:
                               self.ga.cell, 0, self.wl.n_steps, tab)
         return tab, tot
 
+    def exact_depleted(self, ctx: T.Context, cap_log2: int = 22, pair_log2: int = 24):
+        """Depleted cell-pair yields (table), per-cloud-pair yields (pair table), total."""
+        tab, pt = T.StTable(cap_log2), T.StTable(pair_log2)
+        tot = T.tril_st_exact_depleted(ctx, self.tb, self.tbins, self.gb.n_bins, self.qa,
+                                       self.qbins, self.ga.cell, 0, self.wl.n_steps, pt, tab)
+        return tab, pt, tot
+
     def features(self, ctx: T.Context, params=None):
         return T.tril_st_features(ctx, self.qsums, self.ga, self.tsums, self.gb, 0,
                                   self.wl.n_steps, params)
