@@ -92,6 +92,14 @@ def lib():
                                    ctypes.POINTER(d)]
         L.orc_st_exposure.restype = None
         L.orc_st_exposure.argtypes = L.orc_st_pairs.argtypes
+        L.orc_swarm_pairs.restype = None
+        L.orc_swarm_pairs.argtypes = [ctypes.POINTER(_Beam), ctypes.POINTER(_Beam),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, d,
+                                      ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(d),
+                                      ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64)]
+        L.orc_swarm_offsets.restype = None
+        L.orc_swarm_offsets.argtypes = [ctypes.c_int64, ctypes.POINTER(d), ctypes.POINTER(d)]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -152,6 +160,37 @@ def st_exposure(A, B, dt: float, k0: int, n_steps: int, cell,
                           int(n_steps), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     return out
+
+
+def swarm_offsets(n: int, cell) -> np.ndarray:
+    """Offsets (n, 3) of the real photons of a swarm of n from its macro-particle's position
+    (see orc_swarm_pairs)."""
+    c = np.ascontiguousarray(cell, dtype=np.float64)
+    out = np.zeros((max(int(n), 0), 3), dtype=np.float64)
+    lib().orc_swarm_offsets(int(n), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def swarm_pairs(A, B, dt: float, k0: int, n_steps: int, cell,
+                rows: Optional[np.ndarray] = None):
+    """Colliding real-photon pairs of every (query row, target) macro-particle pair over the
+    run window (IP regime swarms; see orc_swarm_pairs): (counts (rows, n_B) int64, knife)."""
+    keep: list = []
+    a, b = _as_beam(A, keep), _as_beam(B, keep)
+    c = np.ascontiguousarray(cell, dtype=np.float64)
+    nr = len(A["E"]) if rows is None else len(rows)
+    out = np.zeros((nr, len(B["E"])), dtype=np.int64)
+    kn = ctypes.c_int64(0)
+    rp = None
+    if rows is not None:
+        rws = np.ascontiguousarray(rows, dtype=np.int64)
+        keep.append(rws)
+        rp = rws.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    lib().orc_swarm_pairs(ctypes.byref(a), ctypes.byref(b), rp, nr, float(dt), int(k0),
+                          int(n_steps), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(kn))
+    return out, int(kn.value)
 
 
 def num_threads() -> int:

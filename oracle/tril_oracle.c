@@ -350,6 +350,98 @@ void orc_st_exposure(const orc_beam *A, const orc_beam *B, const int64_t *rows, 
     }
 }
 
+/* ---- individual-particle (IP) regime: swarms --------------------------------------
+ *
+ * Sec. 2.2: when two macro-particles meet, each is split into a swarm of real photons with
+ * its momentum, placed as evenly as possible over its volume and held in an octree. Here a
+ * macro-particle of weight w is floor(w + 1/2) real photons filling its cloud box (edges
+ * cell[0..2] about its position). Real photon k sits at the centre of the level-L octree
+ * cell (8^L >= n, L smallest) whose octant at level l is base-8 digit l of k (lowest digit =
+ * top level; bits 2, 1, 0 of a digit pick the upper half along x, y, z), so that the first 8
+ * photons take one octant each, the first 64 one sub-octant each, and so on. Two real
+ * photons collide when their time-synchronous distance over the run window
+ * [k0 dt, (k0 + n_steps) dt] comes within r, r^2 = sigma(s) / pi (weight 1 each), s that of
+ * their macro-particles. out[a * nB + j] = colliding real pairs of macro-particle pair
+ * (rows[a], j); *knife counts real pairs with |d^2 - r^2| < 2^-40 r^2. */
+static int orc_swarm_level(int64_t n)
+{
+    int L = 0;
+    int64_t cells = 1;
+    while (cells < n) {
+        cells *= 8;
+        ++L;
+    }
+    return L;
+}
+
+static void orc_swarm_offset(int64_t k, int L, const double *cell, double o[3])
+{
+    int64_t c[3] = {0, 0, 0};
+    for (int l = 0; l < L; ++l) {
+        const int d = (int)((k >> (3 * l)) & 7);
+        c[0] = 2 * c[0] + ((d >> 2) & 1);
+        c[1] = 2 * c[1] + ((d >> 1) & 1);
+        c[2] = 2 * c[2] + (d & 1);
+    }
+    const double cells = (double)((int64_t)1 << L);
+    for (int a = 0; a < 3; ++a) {
+        const double h = cell[a] / cells;
+        o[a] = ((double)c[a] + 0.5) * h - 0.5 * cell[a];
+    }
+}
+
+void orc_swarm_offsets(int64_t n, const double *cell, double *out)
+{
+    const int L = orc_swarm_level(n);
+    for (int64_t k = 0; k < n; ++k) orc_swarm_offset(k, L, cell, out + 3 * k);
+}
+
+void orc_swarm_pairs(const orc_beam *A, const orc_beam *B, const int64_t *rows, int64_t n_rows,
+                     double dt, int32_t k0, int32_t n_steps, const double *cell, int64_t *out,
+                     int64_t *knife)
+{
+    const int64_t nr = rows ? n_rows : A->n;
+    const double T0 = (double)k0 * dt, Tw = (double)n_steps * dt;
+    int64_t kn = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : kn)
+#endif
+    for (int64_t a = 0; a < nr; ++a) {
+        const int64_t i = rows ? rows[a] : a;
+        const double Ei = A->E[i];
+        const double ui[3] = {A->px[i] / Ei, A->py[i] / Ei, A->pz[i] / Ei};
+        const int64_t ni = (int64_t)floor(A->w[i] + 0.5);
+        const int Li = orc_swarm_level(ni);
+        for (int64_t j = 0; j < B->n; ++j) {
+            const double Ej = B->E[j];
+            const double uj[3] = {B->px[j] / Ej, B->py[j] / Ej, B->pz[j] / Ej};
+            const double s = orc_invariant(Ei, ui[0], ui[1], ui[2], Ej, uj[0], uj[1], uj[2]);
+            int64_t cnt = 0;
+            const int64_t nj = (int64_t)floor(B->w[j] + 0.5);
+            if (s > 1.0 && ni > 0 && nj > 0) {
+                const double r2 = orc_sigma(s) / M_PI;
+                const int Lj = orc_swarm_level(nj);
+                for (int64_t p = 0; p < ni; ++p) {
+                    double op[3];
+                    orc_swarm_offset(p, Li, cell, op);
+                    for (int64_t q = 0; q < nj; ++q) {
+                        double oq[3], tau;
+                        orc_swarm_offset(q, Lj, cell, oq);
+                        const double d2 = orc_step_closest(
+                            T0, Tw, A->x[i] + op[0], A->y[i] + op[1], A->z[i] + op[2], ui[0],
+                            ui[1], ui[2], B->x[j] + oq[0], B->y[j] + oq[1], B->z[j] + oq[2],
+                            uj[0], uj[1], uj[2], &tau);
+                        if (fabs(r2 - d2) < 0x1p-40 * r2) ++kn;
+                        if (d2 <= r2) ++cnt;
+                    }
+                }
+            }
+            out[a * B->n + j] = cnt;
+        }
+    }
+    *knife = kn;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
