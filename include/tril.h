@@ -348,6 +348,26 @@ int tril_st_exact_depleted(tril_ctx *ctx, const tril_beam *target, const int32_t
                            const double cell[3], int32_t k0, int32_t n_steps,
                            tril_st_table *pair_table, tril_st_table *table, double *total);
 
+/* Individual-particle (IP) regime with swarms (Sec. 2.2): when two macro-particles meet,
+ * each is split into real photons with its momentum, spread over its volume and held in an
+ * octree, and the real photons are tested one by one. Here macro-particle i is
+ * floor(w_i + 1/2) real photons (at most 2^30; more is TRIL_E_DATA) at the centres of the
+ * cells of a level-L octree over its cloud box (edges `cell` about its position; 8^L >= n,
+ * L smallest); real photon k takes, at level l, the octant given by base-8 digit l of k
+ * (lowest digit = top level; digit bits 2, 1, 0 = upper half along x, y, z), so any count
+ * spreads evenly. Two real photons collide when their time-synchronous distance over the
+ * run window [k0 dt, (k0 + n_steps) dt] comes within r, r^2 = sigma(s) / pi (weight 1 each;
+ * s of their macro-particles, s > 1). Macro-particle pairs are found through the hierarchy
+ * of the clouds swept over each step. pair_table (cleared first) receives one slot per
+ * macro-particle pair whose swept clouds meet above threshold: key i * target->n + j,
+ * yield = its number of colliding real pairs (an integer, as a double); table (cleared
+ * first) the counts per (q_bins[i], t_bins[j]); *total (host) their sum. No consumption:
+ * a real photon may collide with several. Synchronous; errors as for tril_st_exact. */
+int tril_ip_swarm(tril_ctx *ctx, const tril_beam *target, const int32_t *t_bins,
+                  int64_t n_target_bins, const tril_beam *query, const int32_t *q_bins,
+                  const double cell[3], int32_t k0, int32_t n_steps, tril_st_table *pair_table,
+                  tril_st_table *table, int64_t *total);
+
 /* ---------------------------------------------------------------------------------
  * Surrogate path of the statistical regime (uses the network declared below).
  *

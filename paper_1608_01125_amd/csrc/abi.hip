@@ -170,6 +170,7 @@ struct tril_ctx {
     SortScratch ss;
     StatsScratch sst;
     AnnScratch ann;                        // annihilation-mode resolution
+    unsigned long long *swarm_total = nullptr;  // IP regime: colliding real pairs
     double *kin_buf = nullptr;             // pair kinematics: edges, histogram bins
     unsigned int *kin_err = nullptr;
     hipEvent_t ev_kin[2] = {nullptr, nullptr};
@@ -1146,7 +1147,8 @@ int st_run(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_t n_t_b
     launch_beam_stats(t1, c->t_spart, c->t_stats, c->d_cnt, c->st);
     launch_beam_stats(q1, c->q_spart, c->q_stats, c->d_cnt, c->st);
     const StCell sc{{cell[0], cell[1], cell[2]}};
-    c->cloud = CloudBox{1, {0.5 * cell[0], 0.5 * cell[1], 0.5 * cell[2]}};
+    // clouds at mid-step; swarms (geometric 3): clouds swept over the step
+    c->cloud = CloudBox{geometric == 3 ? 2 : 1, {0.5 * cell[0], 0.5 * cell[1], 0.5 * cell[2]}};
     c->morton_bits = c->morton_param > 0 ? c->morton_param : 30;
     int rc = TRIL_OK;
     for (int32_t k = k0, left = n_steps; left > 0 && rc == TRIL_OK;) {
@@ -1317,6 +1319,41 @@ int tril_st_exact_depleted(tril_ctx *c, const tril_beam *t, const int32_t *t_bin
                       tab->cap, c->st_slots, c->d_cnt, c->st);
     HIPCHK(hipGetLastError());
     return st_finish(c, total);
+}
+
+int tril_ip_swarm(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_t n_t_bins,
+                  const tril_beam *q, const int32_t *q_bins, const double cell[3], int32_t k0,
+                  int32_t n_steps, tril_st_table *pair_tab, tril_st_table *tab, int64_t *total) {
+    if (!c || !cell || !tab || !pair_tab || !total || k0 < 0 || n_steps < 0) return TRIL_E_INVAL;
+    CHK(check_beam(t));
+    CHK(check_beam(q));
+    if ((t->n > 0 && !t_bins) || (q->n > 0 && !q_bins)) return TRIL_E_INVAL;
+    if (n_t_bins < 1 || n_t_bins > INT32_MAX) return TRIL_E_INVAL;
+    CHK(check_cell(cell));
+    for (const tril_st_table *tb : {tab, pair_tab})
+        if (tb->cap < 1 || (tb->cap & (tb->cap - 1)) != 0 || !tb->key || !tb->yield)
+            return TRIL_E_INVAL;
+    if (q->n_inst != t->n_inst) return TRIL_E_STATE;
+    if ((int64_t)k0 + n_steps - 1 > INT32_MAX) return TRIL_E_INVAL;
+    *total = 0;
+    if (!c->swarm_total) CHK(dev_alloc(&c->swarm_total, 1));
+    long long *pkeys = reinterpret_cast<long long *>(pair_tab->key);
+    CHK(st_run(c, t, t_bins, n_t_bins, q, q_bins, cell, k0, n_steps, 3, nullptr, 0, pkeys,
+               pair_tab->yield, pair_tab->cap));
+    long long *keys = reinterpret_cast<long long *>(tab->key);
+    launch_st_clear(keys, tab->yield, tab->cap, c->st_slots, c->st);
+    HIPCHK(hipMemsetAsync(c->swarm_total, 0, sizeof(unsigned long long), c->st));
+    const StCell sc{{cell[0], cell[1], cell[2]}};
+    launch_swarm(pkeys, pair_tab->yield, pair_tab->cap, view(q, c->d_q_off, 1),
+                 view(t, c->d_t_off, 1), q_bins, t_bins, n_t_bins, sc, (double)k0 * c->dt,
+                 (double)n_steps * c->dt, keys, tab->yield, tab->cap, c->swarm_total, c->d_cnt,
+                 c->st);
+    HIPCHK(hipGetLastError());
+    CHK(st_finish(c, nullptr));
+    unsigned long long tot = 0;
+    HIPCHK(hipMemcpy(&tot, c->swarm_total, sizeof(tot), hipMemcpyDeviceToHost));
+    *total = (int64_t)tot;
+    return TRIL_OK;
 }
 
 int tril_st_features(tril_ctx *c, const double *q_sums, const tril_st_grid *gq,
@@ -1847,6 +1884,7 @@ void tril_destroy(tril_ctx *c) {
     free_target_rows(c);
     free_annihilation(c);
     dev_free(c->kin_buf);
+    dev_free(c->swarm_total);
     dev_free(c->kin_err);
     for (hipEvent_t e : c->ev_kin)
         if (e) (void)hipEventDestroy(e);

@@ -299,8 +299,10 @@ __device__ __forceinline__ RowPhoton load_photon(const BeamDev &b, int64_t i, do
 
 // Box of photon r in the step window [t, t + dt], padded by pad and rounded outward to
 // FP32, and its centre: the swept segment (position at t exactly as the narrow phase
-// forms it, and one step later) or, in the statistical regime, the cloud (half-widths
-// cloud.h about the mid-step position). A photon with unusable data gets an empty box.
+// forms it, and one step later); in the statistical regime (cloud.on == 1) the cloud
+// (half-widths cloud.h about the mid-step position); for swarms (cloud.on == 2) the cloud
+// swept over the step (the segment's box widened by cloud.h). A photon with unusable data
+// gets an empty box.
 __device__ __forceinline__ void photon_box(const RowPhoton &r, double t, double dt,
                                            const CloudBox &cloud, double pad, float lo32[3],
                                            float hi32[3], float cen[3]) {
@@ -314,7 +316,7 @@ __device__ __forceinline__ void photon_box(const RowPhoton &r, double t, double 
         return;
     }
     double lo[3], hi[3];
-    if (cloud.on) {
+    if (cloud.on == 1) {
         const double tm = t + 0.5 * dt;
         const double cx = r.x + tm * r.ux, cy = r.y + tm * r.uy, cz = r.z + tm * r.uz;
         lo[0] = cx - cloud.h[0]; lo[1] = cy - cloud.h[1]; lo[2] = cz - cloud.h[2];
@@ -324,6 +326,13 @@ __device__ __forceinline__ void photon_box(const RowPhoton &r, double t, double 
         const double bx = ax + dt * r.ux, by = ay + dt * r.uy, bz = az + dt * r.uz;
         lo[0] = fmin(ax, bx); lo[1] = fmin(ay, by); lo[2] = fmin(az, bz);
         hi[0] = fmax(ax, bx); hi[1] = fmax(ay, by); hi[2] = fmax(az, bz);
+        if (cloud.on == 2) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lo[a] -= cloud.h[a];
+                hi[a] += cloud.h[a];
+            }
+        }
     }
     // slack far above FP64 rounding of the positions (1e-12 of the magnitude)
 #pragma unroll
@@ -372,6 +381,7 @@ __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, CloudB
         const double smax = (E * emax_t) / (kMe * kMe);
         below = !(smax > 1.0);
         if (!cloud.on) pad = sqrt((sqrt(w * wmax_t) * sigma_up) / M_PI) * (1.0 + 1e-6);
+        if (cloud.on == 2) pad = sqrt(sigma_up / M_PI) * (1.0 + 1e-6);  // real photons, weight 1
     }
     const unsigned step0 = c->step;
     for (int32_t s = 0; s < b.m; ++s) {

@@ -157,6 +157,7 @@ __device__ __forceinline__ double st_yield(const BeamDev &q, int64_t i, const Be
     const double cphi = (uix * ujx + uiy * ujy) + uiz * ujz;
     const double s = ((Ei * Ej) * (1.0 - cphi)) / (2.0 * kMe * kMe);
     if (!(s > 1.0)) return 0.0;
+    if (geometric == 3) return 1.0;  // swarms: the swept clouds meet, above threshold
     const double tm = tk + 0.5 * dt;
     const double ox = cell.c[0] - fabs((q.x[i] + tm * uix) - (t.x[j] + tm * ujx));
     const double oy = cell.c[1] - fabs((q.y[i] + tm * uiy) - (t.y[j] + tm * ujy));
@@ -182,7 +183,7 @@ __device__ __forceinline__ void st_leaf(const BeamDev &q, int64_t i, const BeamD
     const int64_t j = e - so * t.n;
     const int32_t bt = t_bins[j];
     // bin-pair key, or in exposure mode the cloud pair (caller rows)
-    const long long key = geometric == 2 ? (long long)i * t.n + j : (long long)bq * n_t_bins + bt;
+    const long long key = geometric >= 2 ? (long long)i * t.n + j : (long long)bq * n_t_bins + bt;
     const bool keep = bt >= 0 && (filter == nullptr || set_has(filter, fmask, key));
     const double Y = keep ? st_yield(q, i, t, j, tk, dt, cell, geometric) : 0.0;
     if (Y > 0.0) {
@@ -343,6 +344,190 @@ __global__ void __launch_bounds__(256) k_st_deplete(long long *__restrict__ pkey
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) tot += __shfl_xor(tot, off);
     if ((threadIdx.x & 63) == 0 && tot != 0.0) atomicAdd(&slots[blockIdx.x & (kCounterSlots - 1)], tot);
+}
+
+// ---- IP regime: swarms of real photons -------------------------------------------------
+// A macro-particle of weight w is floor(w + 1/2) real photons with its momentum, at the
+// centres of the cells of a level-L octree over its cloud box (8^L >= n, L smallest): real
+// photon k takes, at level l, the octant given by base-8 digit l of k (lowest digit = top
+// level; digit bits 2, 1, 0 = upper half along x, y, z), which spreads any n evenly.
+// The octree needs no storage: the node at level l whose octants are the low l digits of
+// `base` holds the real photons base, base + 8^l, base + 2 8^l, ... below n.
+// Real photons p (of the query's swarm) and q (of the target's) collide when their
+// time-synchronous distance over the run window [T0, T0 + Tw] comes within r,
+// r^2 = sigma(s) / pi (weight 1 each), evaluated in FP64 as the narrow phase does over a
+// step window. One workgroup per macro-particle pair of the pair table, one lane per real
+// photon p: its path relative to the target swarm's centre, a segment over the window,
+// descends the target's octree (a node is entered when the segment meets its box widened
+// by r and a rounding slack); the walk needs no stack: the next node is the next sibling
+// that holds photons, else the parent's.
+constexpr int64_t kSwarmMax = (int64_t)1 << 30;  // real photons per macro-particle
+
+__device__ __forceinline__ int swarm_level(int64_t n) {
+    int L = 0;
+    int64_t cells = 1;
+    while (cells < n) {
+        cells *= 8;
+        ++L;
+    }
+    return L;
+}
+
+// Integer cell coordinates, at level `lvl`, of the octants in the low lvl digits of k.
+__device__ __forceinline__ void swarm_cell(int64_t k, int lvl, int64_t c[3]) {
+    c[0] = c[1] = c[2] = 0;
+    for (int l = 0; l < lvl; ++l) {
+        const int d = (int)((k >> (3 * l)) & 7);
+        c[0] = 2 * c[0] + ((d >> 2) & 1);
+        c[1] = 2 * c[1] + ((d >> 1) & 1);
+        c[2] = 2 * c[2] + (d & 1);
+    }
+}
+
+__device__ __forceinline__ void swarm_offset(int64_t k, int L, const StCell &cell, double o[3]) {
+    int64_t c[3];
+    swarm_cell(k, L, c);
+    const double cells = (double)((int64_t)1 << L);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double h = cell.c[a] / cells;
+        o[a] = ((double)c[a] + 0.5) * h - 0.5 * cell.c[a];
+    }
+}
+
+// Does the segment P + tau v, tau in [0, Tw], meet the box [lo - pad, hi + pad]?
+__device__ __forceinline__ bool segment_meets_box(const double P[3], const double v[3], double Tw,
+                                                  const double lo[3], const double hi[3],
+                                                  double pad) {
+    double ta = 0.0, tb = Tw;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double l = lo[a] - pad, h = hi[a] + pad;
+        if (v[a] == 0.0) {
+            if (P[a] < l || P[a] > h) return false;
+        } else {
+            double t1 = (l - P[a]) / v[a], t2 = (h - P[a]) / v[a];
+            if (t1 > t2) {
+                const double x = t1;
+                t1 = t2;
+                t2 = x;
+            }
+            ta = fmax(ta, t1);
+            tb = fmin(tb, t2);
+        }
+    }
+    return ta <= tb;
+}
+
+__global__ void __launch_bounds__(256) k_swarm(const long long *__restrict__ pkeys,
+                                               double *__restrict__ pvals, int64_t pcap,
+                                               BeamDev q, BeamDev t,
+                                               const int32_t *__restrict__ q_bins,
+                                               const int32_t *__restrict__ t_bins,
+                                               int64_t n_t_bins, StCell cell, double T0,
+                                               double Tw, long long *keys, double *vals,
+                                               uint64_t mask, unsigned long long *total,
+                                               DevCounters *c) {
+    __shared__ unsigned long long s_part[4];
+    for (int64_t slot = blockIdx.x; slot < pcap; slot += gridDim.x) {
+        const long long key = pkeys[slot];
+        if (key < 0) continue;  // uniform over the workgroup
+        const int64_t i = key / t.n, j = key - i * t.n;
+        const double Ei = q.E[i], Ej = t.E[j];
+        const double ui[3] = {q.px[i] / Ei, q.py[i] / Ei, q.pz[i] / Ei};
+        const double uj[3] = {t.px[j] / Ej, t.py[j] / Ej, t.pz[j] / Ej};
+        const double cphi = (ui[0] * uj[0] + ui[1] * uj[1]) + ui[2] * uj[2];
+        const double s = ((Ei * Ej) * (1.0 - cphi)) / (2.0 * kMe * kMe);
+        const int64_t ni = (int64_t)floor(q.w[i] + 0.5), nj = (int64_t)floor(t.w[j] + 0.5);
+        const bool big = ni > kSwarmMax || nj > kSwarmMax;
+        if (big && threadIdx.x == 0) atomicOr(&c->err, kErrData);
+        unsigned long long cnt = 0;
+        if (s > 1.0 && ni > 0 && nj > 0 && !big) {
+            const double r2 = bw_sigma(s) / M_PI;
+            const int Li = swarm_level(ni), Lj = swarm_level(nj);
+            const double v[3] = {ui[0] - uj[0], ui[1] - uj[1], ui[2] - uj[2]};
+            const double Xjc[3] = {t.x[j] + T0 * uj[0], t.y[j] + T0 * uj[1], t.z[j] + T0 * uj[2]};
+            const double pad = sqrt(r2) * (1.0 + 1e-6) +
+                               1e-9 * (1.0 + fabs(Xjc[0]) + fabs(Xjc[1]) + fabs(Xjc[2]) + 2.0 * Tw);
+            for (int64_t p = threadIdx.x; p < ni; p += blockDim.x) {
+                double op[3];
+                swarm_offset(p, Li, cell, op);
+                const double xi0[3] = {q.x[i] + op[0], q.y[i] + op[1], q.z[i] + op[2]};
+                const double Xi[3] = {xi0[0] + T0 * ui[0], xi0[1] + T0 * ui[1], xi0[2] + T0 * ui[2]};
+                const double P[3] = {Xi[0] - Xjc[0], Xi[1] - Xjc[1], Xi[2] - Xjc[2]};
+                int lvl = 0;
+                int64_t base = 0;
+                uint32_t guard = 0;
+                const uint32_t max_guard = 16u * (uint32_t)min<int64_t>(nj, 1 << 27) + 64u;
+                while (true) {
+                    if (++guard > max_guard) {
+                        atomicOr(&c->err, kErrSpin);
+                        break;
+                    }
+                    int64_t cc[3];
+                    swarm_cell(base, lvl, cc);
+                    const double cells = (double)((int64_t)1 << lvl);
+                    double lo[3], hi[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const double h = cell.c[a] / cells;
+                        lo[a] = (double)cc[a] * h - 0.5 * cell.c[a];
+                        hi[a] = lo[a] + h;
+                    }
+                    bool down = segment_meets_box(P, v, Tw, lo, hi, pad);
+                    if (down && lvl == Lj) {  // a real photon of the target swarm
+                        double oq[3];
+                        swarm_offset(base, Lj, cell, oq);
+                        const double xj0[3] = {t.x[j] + oq[0], t.y[j] + oq[1], t.z[j] + oq[2]};
+                        const double dx = Xi[0] - (xj0[0] + T0 * uj[0]);
+                        const double dy = Xi[1] - (xj0[1] + T0 * uj[1]);
+                        const double dz = Xi[2] - (xj0[2] + T0 * uj[2]);
+                        const double vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+                        const double dv = (dx * v[0] + dy * v[1]) + dz * v[2];
+                        double tau = -dv / vv;
+                        if (!(tau > 0.0)) tau = 0.0;
+                        if (tau > Tw) tau = Tw;
+                        const double ex = dx + tau * v[0], ey = dy + tau * v[1], ez = dz + tau * v[2];
+                        if ((ex * ex + ey * ey) + ez * ez <= r2) ++cnt;
+                        down = false;
+                    }
+                    if (down) {  // first child: octant digit 0 at level lvl + 1
+                        ++lvl;
+                        continue;
+                    }
+                    // next sibling holding photons, else up
+                    bool moved = false;
+                    while (lvl > 0) {
+                        const int64_t step = (int64_t)1 << (3 * (lvl - 1));
+                        const int64_t d = (base >> (3 * (lvl - 1))) & 7;
+                        if (d < 7 && base + step < nj) {
+                            base += step;
+                            moved = true;
+                            break;
+                        }
+                        base -= d * step;
+                        --lvl;
+                    }
+                    if (!moved) break;
+                }
+            }
+        }
+        // workgroup sum of the lanes' counts
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+        if ((threadIdx.x & 63) == 0) s_part[threadIdx.x >> 6] = cnt;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned long long tot = (s_part[0] + s_part[1]) + (s_part[2] + s_part[3]);
+            pvals[slot] = (double)tot;
+            if (tot) {
+                atomicAdd(total, tot);
+                table_add(keys, vals, mask, (long long)q_bins[i] * n_t_bins + t_bins[j],
+                          (double)tot, &c->err);
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // One cloud per occupied bin: weighted-mean energy, direction and position (at the grid
@@ -589,6 +774,17 @@ void launch_st_deplete(long long *pkeys, double *pvals, int64_t pcap, const Beam
     const unsigned grid = (unsigned)std::min<int64_t>(grid_for(pcap, 256), 4096);
     hipLaunchKernelGGL(k_st_deplete, dim3(grid), dim3(256), 0, st, pkeys, pvals, pcap, q, t,
                        q_bins, t_bins, n_t_bins, cell, keys, vals, (uint64_t)(cap - 1), slots, c);
+}
+
+void launch_swarm(const long long *pkeys, double *pvals, int64_t pcap, const BeamDev &q,
+                  const BeamDev &t, const int32_t *q_bins, const int32_t *t_bins,
+                  int64_t n_t_bins, const StCell &cell, double T0, double Tw, long long *keys,
+                  double *vals, int64_t cap, unsigned long long *total, DevCounters *c,
+                  hipStream_t st) {
+    if (pcap <= 0 || t.n <= 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>(pcap, 16384);
+    hipLaunchKernelGGL(k_swarm, dim3(grid), dim3(256), 0, st, pkeys, pvals, pcap, q, t, q_bins,
+                       t_bins, n_t_bins, cell, T0, Tw, keys, vals, (uint64_t)(cap - 1), total, c);
 }
 
 void launch_st_clear(long long *keys, double *vals, int64_t cap, double *slots, hipStream_t st) {

@@ -317,6 +317,14 @@ void launch_st_deplete(long long *pkeys, double *pvals, int64_t pcap, const Beam
                        const BeamDev &t, const int32_t *q_bins, const int32_t *t_bins,
                        int64_t n_t_bins, const StCell &cell, long long *keys, double *vals,
                        int64_t cap, double *slots, DevCounters *c, hipStream_t st);
+// IP-regime swarms over the macro-particle pairs of the pair table (pkeys = i * t.n + j):
+// colliding real-photon pairs of each pair over the window [T0, T0 + Tw] into pvals (as
+// doubles), into the bin-pair table under (q_bins[i], t_bins[j]) and into *total.
+void launch_swarm(const long long *pkeys, double *pvals, int64_t pcap, const BeamDev &q,
+                  const BeamDev &t, const int32_t *q_bins, const int32_t *t_bins,
+                  int64_t n_t_bins, const StCell &cell, double T0, double Tw, long long *keys,
+                  double *vals, int64_t cap, unsigned long long *total, DevCounters *c,
+                  hipStream_t st);
 void launch_st_traverse(const Node *nodes, int64_t n_int, const PBox *root_box, const PBox *qbox,
                         const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
                         const int32_t *inst_root,

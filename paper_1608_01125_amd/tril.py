@@ -111,7 +111,7 @@ TRIL_KIN_MAX_BINS = 2048
 EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats",
            "tril_pair_kinematics",
            "tril_autotune", "tril_set_tune", "tril_st_bin", "tril_st_exact",
-           "tril_st_exact_depleted",
+           "tril_st_exact_depleted", "tril_ip_swarm",
            "tril_mlp_create", "tril_mlp_destroy", "tril_mlp_set_params", "tril_mlp_get_params",
            "tril_mlp_set_norm", "tril_mlp_fit_norm", "tril_mlp_grad", "tril_mlp_train",
            "tril_mlp_predict", "tril_st_features", "tril_st_targets", "tril_st_surrogate",
@@ -156,6 +156,10 @@ def lib() -> ctypes.CDLL:
                                          ctypes.POINTER(tril_st_table),
                                          ctypes.POINTER(tril_st_table),
                                          ctypes.POINTER(ctypes.c_double)]
+    L.tril_ip_swarm.argtypes = [vp, ctypes.POINTER(tril_beam), vp, i64, ctypes.POINTER(tril_beam),
+                                vp, ctypes.POINTER(ctypes.c_double), i32, i32,
+                                ctypes.POINTER(tril_st_table), ctypes.POINTER(tril_st_table),
+                                ctypes.POINTER(ctypes.c_int64)]
     fp, dp = ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)
     L.tril_mlp_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_uint64, vp]
     L.tril_mlp_destroy.argtypes = [vp]
@@ -440,6 +444,20 @@ def tril_st_exact_depleted(ctx, target: Beam, t_bins, n_target_bins: int, query:
         c3, int(k0), int(n_steps), ctypes.byref(pair_table.c), ctypes.byref(table.c),
         ctypes.byref(tot)), "tril_st_exact_depleted")
     return tot.value
+
+
+def tril_ip_swarm(ctx, target: Beam, t_bins, n_target_bins: int, query: Beam, q_bins, cell,
+                  k0: int, n_steps: int, pair_table: StTable, table: StTable) -> int:
+    """IP-regime swarms: colliding real-photon pairs per macro-particle pair in pair_table
+    (key i * n_target + j), per bin pair in table; returns the total."""
+    c3 = (ctypes.c_double * 3)(*[float(v) for v in cell])
+    tot = ctypes.c_int64(0)
+    _check(lib().tril_ip_swarm(
+        _h(ctx), ctypes.byref(target.c), t_bins.data_ptr() if target.n > 0 else None,
+        int(n_target_bins), ctypes.byref(query.c), q_bins.data_ptr() if query.n > 0 else None,
+        c3, int(k0), int(n_steps), ctypes.byref(pair_table.c), ctypes.byref(table.c),
+        ctypes.byref(tot)), "tril_ip_swarm")
+    return int(tot.value)
 
 
 MLP_PARAMS = 133_633
