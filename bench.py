@@ -165,6 +165,7 @@ def st_bench(args):
         t_dep = (time.perf_counter() - t1) / max(args.steps, 1)
         n_cloud_pairs = int((pt.key >= 0).sum().item())
         del dinst, pt
+        swarm = swarm_measure(T, torch)
     finally:
         net.close()
         ctx.close()
@@ -194,10 +195,48 @@ def st_bench(args):
                            "ms_linear": 1e3 * t_lin, "total": dep_total,
                            "linear_total": lin_total, "ratio_to_linear": dep_total / lin_total,
                            "cloud_pairs": n_cloud_pairs},
+        "ip_swarm": swarm,
         "exact": {"queries_per_s": q / t_exact, "ms": 1e3 * t_exact, "total": exact_total,
                   "cloud_pair_steps_per_run": st["n_candidates"] // max(args.steps + args.warmup, 1)},
     }
     print(json.dumps(out), flush=True)
+
+
+def swarm_measure(T, torch, n_mp=200, n_real=4096, reps=3):
+    """IP-regime swarms: two head-on beams of n_mp macro-particles of n_real real photons each
+    in clouds of 4e-9 um (the size of the collision radius, so that real photons meet),
+    transverse spread 2e-9 um, 10 steps of 0.1 um/c across the crossing. Reports the time of
+    tril_ip_swarm and the real-pair tests it resolves per second (sum of n_i n_j over the
+    macro-particle pairs it examines)."""
+    import numpy as np
+    rng = np.random.default_rng(0)
+
+    def beam(sgn):
+        n = n_mp
+        return {"x": rng.normal(0, 2e-9, n), "y": rng.normal(0, 2e-9, n),
+                "z": -sgn * 0.5 + rng.normal(0, 0.05, n), "px": np.zeros(n), "py": np.zeros(n),
+                "pz": np.full(n, sgn * 2.0), "E": np.full(n, 2.0), "w": np.full(n, float(n_real))}
+    A, B = beam(1.0), beam(-1.0)
+    cell = (4e-9, 4e-9, 4e-9)
+    qa, tb = T.Beam(A), T.Beam(B)
+    bins = torch.zeros(n_mp, dtype=torch.int32, device="cuda")
+    ctx = T.Context(0.1, None)
+    pt, tab = T.StTable(20), T.StTable(4)
+    try:
+        T.tril_ip_swarm(ctx, tb, bins, 1, qa, bins, cell, 0, 10, pt, tab)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            tot = T.tril_ip_swarm(ctx, tb, bins, 1, qa, bins, cell, 0, 10, pt, tab)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        n_pairs = int((pt.key >= 0).sum().item())
+    finally:
+        ctx.close()
+    tests = float(n_pairs) * n_real * n_real
+    return {"macro_particles_per_beam": n_mp, "real_photons_per_mp": n_real,
+            "mp_pairs": n_pairs, "real_pair_tests_implied": tests, "colliding_real_pairs": tot,
+            "ms": 1e3 * sec, "real_pair_tests_per_s": tests / sec}
 
 
 KIN_BYTES_PER_PAIR = 12 + 2 * 5 * 8 + 64  # (i, j, k), E p w of both photons, 8 lepton doubles
