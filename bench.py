@@ -81,6 +81,8 @@ def make_workload(name: str, physics_steps: int):
         wl = beams.gauss_headon_1m()
     elif name == "mono_headon_2k":
         wl = beams.mono_headon_2k()
+    elif name == "uniform_headon_1m":
+        wl = beams.uniform_headon_1m()
     elif name == "broadband_16m":
         wl = beams.broadband_16m()
     elif name in ("positron_spectra_1m_5_5", "positron_spectra_1m_7_3"):
@@ -469,6 +471,16 @@ def main():
             "pairs": st3["n_pairs"]}
 
     if not args.no_variants and offA is None:
+        # the same run with the uniform-grid broad phase (the mesh alternative to the
+        # hierarchy; one step per launch, identical pair set)
+        e4, st4 = timed(args.flags | T.TRIL_GRID | timing)
+        variants["grid_broad_phase"] = {
+            "value": pairs_per_step * n_steps / (e4 / max(args.steps, 1)),
+            "ms_per_step": 1e3 * e4 / max(args.steps, 1), "pairs": st4["n_pairs"],
+            "target_boxes_tested_per_query": round(st4["n_node_visits"] / max(st4["n_queries"], 1), 3),
+            "candidates_per_run": st4["n_candidates"] // max(args.steps, 1),
+            "ms_phases_per_run": {k: round(st4[k] / max(args.steps, 1), 3) for k in
+                                  ("ms_build", "ms_query_prep", "ms_traverse", "ms_narrow")}}
         variants["pair_kinematics"] = kinematics_variant(T, torch, A, B, wl, n_steps, edges)
 
     roofline = None

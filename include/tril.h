@@ -75,6 +75,13 @@ extern "C" {
                                     before it in the order (step, time of closest approach
                                     inside the step, i, j); Sec. 2.1 (annihilating photons)
                                     and Sec. 2.2 (collisions sorted in time) */
+#define TRIL_GRID          0x10u /* broad phase on a uniform grid instead of the hierarchy (the
+                                    mesh the paper compares its tree against, Sec. 3): per
+                                    step, target boxes sorted by the cell of their centre
+                                    (about one cell per photon over the step's bounds), each
+                                    query scanning the cells its box meets; same candidates'
+                                    superset, same narrow phase and results. One instance only
+                                    (else TRIL_E_NOTIMPL); tril_run then goes step by step */
 
 typedef struct tril_ctx tril_ctx;
 typedef struct tril_mlp tril_mlp;

@@ -82,6 +82,8 @@ def main():
     if args.only in (None, "batch64"):
         for m in range(beams.BATCH64_INSTANCES):
             put(f"batch64/{m}", calibrate(lambda w: beams.batch64_instance(m, w=w), 6000, 2.0e14))
+    if args.only in (None, "uniform_headon_1m"):
+        put("uniform_headon_1m", calibrate(beams.uniform_headon_1m, 20000, 1.0e12))
     if args.only in (None, "positron_spectra_1m"):
         for g1, g2 in ((5.0, 5.0), (7.0, 3.0)):
             put(f"positron_spectra_1m/{g1:g}_{g2:g}",

@@ -199,6 +199,16 @@ def mono_headon_2k(seed: int = 0, w: Optional[float] = None, n: int = 2000) -> W
     return Workload("mono_headon_2k", a, b, 0.1, 200, seed)
 
 
+def uniform_headon_1m(seed: int = 0, w: Optional[float] = None, n: int = 1_000_000) -> Workload:
+    """The 2k cylinder set-up at 1e6 photons per beam: uniform density (R = 1 um, L = 10 um),
+    mono-energetic 1 MeV, directions exactly +-z, 200 steps of 0.1 um/c; the case most
+    favourable to a uniform grid."""
+    w = _w("uniform_headon_1m", 1e7) if w is None else w
+    a = BeamSpec(n, "cylinder", 1.0, 10.0, 10.0, 0.0, "mono", (1.0,), 0.0, w)
+    b = replace(a, phi_deg=180.0)
+    return Workload("uniform_headon_1m", a, b, 0.1, 200, seed)
+
+
 def gauss_headon_1m(seed: int = 0, w: Optional[float] = None, n: int = 1_000_000) -> Workload:
     """1e6 photons per beam, Gaussian sigma_r = 2 um, sigma_z = 5 um, energies
     N(2 MeV, 0.2 MeV), 10 mrad full opening, head-on, 400 steps of 0.1 um/c

@@ -21,7 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtril.so")
 
 SOURCES = ["abi.hip", "radix_sort.hip", "lbvh.hip", "traverse.hip", "narrow.hip", "stats.hip",
-           "st.hip", "mlp.hip", "annihilate.hip", "kinematics.hip"]
+           "st.hip", "mlp.hip", "annihilate.hip", "kinematics.hip",
+           "grid.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

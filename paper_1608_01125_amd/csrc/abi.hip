@@ -171,6 +171,9 @@ struct tril_ctx {
     StatsScratch sst;
     AnnScratch ann;                        // annihilation-mode resolution
     unsigned long long *swarm_total = nullptr;  // IP regime: colliding real pairs
+    GridDev *grid_dev = nullptr;    // uniform-grid broad phase (TRIL_GRID)
+    int32_t *grid_start = nullptr, *grid_end = nullptr;
+    int64_t grid_cap = 0;
     double *kin_buf = nullptr;             // pair kinematics: edges, histogram bins
     unsigned int *kin_err = nullptr;
     hipEvent_t ev_kin[2] = {nullptr, nullptr};
@@ -518,6 +521,63 @@ int enqueue_query_prep(tril_ctx *c, const BeamDev &q, hipStream_t st, bool sort_
     return TRIL_OK;
 }
 
+// Uniform-grid broad phase (TRIL_GRID, one step, one instance): target boxes, grid of the
+// step, target rows sorted by cell, cell ranges.
+int enqueue_grid_build(tril_ctx *c, hipStream_t st, bool timed) {
+    const BeamDev &t = c->tgt;
+    const int64_t n = t.n;
+    const int64_t max_cells = std::max<int64_t>(n, 1);
+    if (max_cells > c->grid_cap) {
+        dev_free(c->grid_start);
+        dev_free(c->grid_end);
+        c->grid_cap = 0;
+        CHK(dev_alloc(&c->grid_start, (size_t)max_cells));
+        CHK(dev_alloc(&c->grid_end, (size_t)max_cells));
+        c->grid_cap = max_cells;
+    }
+    if (!c->grid_dev) CHK(dev_alloc(&c->grid_dev, 1));
+    if (timed) CHK(timing_pair(c, st, c->ev_build, true));
+    launch_prologue(c->d_cnt, 0, 1, st);
+    const KeyLayout kl = key_layout(1, c->morton_bits);
+    launch_boxes_keys(t, false, c->cloud, c->dt, c->sigma_up, c->t_stats, c->t_stats, kl, 0,
+                      c->t_box, nullptr, nullptr, nullptr, c->d_cnt, st);
+    launch_grid_build(c->t_box, n, c->t_stats, c->d_cnt, c->dt, max_cells, c->grid_dev,
+                      c->t_k32a, c->t_va, c->grid_start, c->grid_end, st);
+    const uint32_t *keys = c->t_k32a;
+    c->t_rows = c->t_va;
+    if (n > 1) {
+        const bool alt = radix_sort_u32(c->t_k32a, c->t_va, c->t_k32b, c->t_vb, n,
+                                        std::max(1, bits_for((uint64_t)(max_cells - 1))), c->ss,
+                                        &c->d_cnt->err, st);
+        keys = alt ? c->t_k32b : c->t_k32a;
+        c->t_rows = alt ? c->t_vb : c->t_va;
+    }
+    launch_grid_ranges(keys, n, c->grid_start, c->grid_end, st);
+    c->n_int = 0;
+    if (timed) CHK(timing_pair(c, st, c->ev_build, false));
+    HIPCHK(hipGetLastError());
+    return TRIL_OK;
+}
+
+int enqueue_grid_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStream_t st,
+                         bool timed, bool sort_queries) {
+    if (timed) CHK(timing_pair(c, st, c->ev_prep, true));
+    launch_prologue(c->d_cnt, 1, 1, st);
+    CHK(enqueue_query_prep(c, q, st, sort_queries));
+    if (timed) CHK(timing_pair(c, st, c->ev_prep, false));
+    if (timed) CHK(timing_pair(c, st, c->ev_trav, true));
+    launch_grid_query(c->grid_dev, c->t_box, c->t_rows, c->grid_start, c->grid_end, c->q_box,
+                      q.n > 0 ? c->q_order : nullptr, q.n, c->cand_i, c->cand_j, c->cand_cap,
+                      c->d_cnt, st);
+    if (timed) CHK(timing_pair(c, st, c->ev_trav, false));
+    if (timed) CHK(timing_pair(c, st, c->ev_narrow, true));
+    launch_narrow(q, c->tgt, c->dt, c->sigma_up, c->cand_i, c->cand_j, c->cand_cap, out, c->d_cnt,
+                  (c->flags & TRIL_FP64_NARROW) == 0, st);
+    if (timed) CHK(timing_pair(c, st, c->ev_narrow, false));
+    HIPCHK(hipGetLastError());
+    return TRIL_OK;
+}
+
 int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStream_t st,
                     bool timed, bool sort_queries) {
     const int64_t nv = (int64_t)q.m * q.n;
@@ -728,7 +788,8 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
     if (!std::isfinite(p->dt) || !(p->dt > 0.0)) return TRIL_E_INVAL;
     if (p->n_bins < 0 || p->cand_cap < 0 || p->step_batch < 0) return TRIL_E_INVAL;
     if (p->morton_bits != 0 && (p->morton_bits < 3 || p->morton_bits > 30)) return TRIL_E_INVAL;
-    if (p->flags & ~(TRIL_TIMING | TRIL_SORT_QUERIES_ONCE | TRIL_FP64_NARROW | TRIL_ANNIHILATE))
+    if (p->flags &
+        ~(TRIL_TIMING | TRIL_SORT_QUERIES_ONCE | TRIL_FP64_NARROW | TRIL_ANNIHILATE | TRIL_GRID))
         return TRIL_E_NOTIMPL;
     if (p->n_bins > 0) {
         if (!p->bin_edges) return TRIL_E_INVAL;
@@ -780,6 +841,7 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
 int tril_build(tril_ctx *c, const tril_beam *b, int32_t step) {
     if (!c || step < 0) return TRIL_E_INVAL;
     CHK(check_beam(b));
+    if ((c->flags & TRIL_GRID) && b->n_inst > 1) return TRIL_E_NOTIMPL;
     c->morton_bits = c->morton_param > 0 ? c->morton_param : 30;
     CHK(ensure_target(c, b->n, b->n, b->n_inst, b->n_inst));
     CHK(upload_offsets(c, b, c->d_t_off, c->h_t_off));
@@ -788,7 +850,10 @@ int tril_build(tril_ctx *c, const tril_beam *b, int32_t step) {
     c->res_t = c->tgt;
     launch_set_step(c->d_cnt, step, c->st);
     launch_beam_stats(c->tgt, c->t_spart, c->t_stats, c->d_cnt, c->st);
-    CHK(enqueue_build(c, c->st, (c->flags & TRIL_TIMING) != 0));
+    if (c->flags & TRIL_GRID)
+        CHK(enqueue_grid_build(c, c->st, (c->flags & TRIL_TIMING) != 0));
+    else
+        CHK(enqueue_build(c, c->st, (c->flags & TRIL_TIMING) != 0));
     c->built = true;
     c->built_step = step;
     c->tgt_k0 = step;
@@ -808,7 +873,10 @@ int tril_collide(tril_ctx *c, const tril_beam *q, int32_t step, tril_pairs *out)
     const BeamDev qv = view(q, c->d_q_off, 1);
     const bool sort = need_query_sort(c, q);
     launch_beam_stats(qv, c->q_spart, c->q_stats, c->d_cnt, c->st);
-    CHK(enqueue_collide(c, qv, *out, c->st, (c->flags & TRIL_TIMING) != 0, sort));
+    if (c->flags & TRIL_GRID)
+        CHK(enqueue_grid_collide(c, qv, *out, c->st, (c->flags & TRIL_TIMING) != 0, sort));
+    else
+        CHK(enqueue_collide(c, qv, *out, c->st, (c->flags & TRIL_TIMING) != 0, sort));
     if (sort) CHK(note_query_sorted(c, q, 1, c->st));
     c->last_q = qv;
     c->max_nq = std::max(c->max_nq, q->n);
@@ -824,6 +892,13 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     if (q->n_inst != t->n_inst) return TRIL_E_STATE;
     if (n_steps == 0) return TRIL_OK;
     if ((int64_t)k0 + n_steps - 1 > INT32_MAX) return TRIL_E_INVAL;
+    if (c->flags & TRIL_GRID) {  // the grid broad phase runs step by step
+        for (int32_t k = k0; k < k0 + n_steps; ++k) {
+            CHK(tril_build(c, t, k));
+            CHK(tril_collide(c, q, k, out));
+        }
+        return TRIL_OK;
+    }
     const int32_t m = pick_batch(c, t, q, n_steps);
     // capacities for the largest batch first, so that nothing is reallocated later
     CHK(ensure_target(c, (int64_t)m * t->n, t->n, (int64_t)m * t->n_inst, t->n_inst));
@@ -1885,6 +1960,9 @@ void tril_destroy(tril_ctx *c) {
     free_annihilation(c);
     dev_free(c->kin_buf);
     dev_free(c->swarm_total);
+    dev_free(c->grid_dev);
+    dev_free(c->grid_start);
+    dev_free(c->grid_end);
     dev_free(c->kin_err);
     for (hipEvent_t e : c->ev_kin)
         if (e) (void)hipEventDestroy(e);

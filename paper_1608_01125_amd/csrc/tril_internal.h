@@ -217,6 +217,30 @@ void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint
 // whose root is a leaf; nq: virtual query count (steps x rows).
 // qorder: NULL (identity), nq entries (order of all virtual queries) or nq_base entries
 // (order of one step, repeated per step).
+// ---------------------------------------------------------- uniform-grid broad phase
+struct GridDev {
+    double lo[3];       // grid origin (step's target box centres, lower bound)
+    double inv_cs[3];   // cells per unit length
+    int32_t dim[3];
+    int32_t n_cells;
+    float hmax[3];      // largest half extent of a target box plus rounding slack
+};
+// Grid of the current step from the target's bounds (g, device), then the cell key of every
+// target box centre (keys/vals for the radix sort) and cleared cell ranges (max_cells).
+void launch_grid_build(const PBox *tbox, int64_t n, const InstStats *t_stats,
+                       const DevCounters *c, double dt, int64_t max_cells, GridDev *g,
+                       uint32_t *keys, uint32_t *vals, int32_t *cstart, int32_t *cend,
+                       hipStream_t st);
+// Cell ranges [cstart, cend) of the sorted target keys.
+void launch_grid_ranges(const uint32_t *sorted_keys, int64_t n, int32_t *cstart, int32_t *cend,
+                        hipStream_t st);
+// Candidates of every query box (in qorder) against the target boxes of the cells its box,
+// widened by the largest target half extent, meets.
+void launch_grid_query(const GridDev *g, const PBox *tbox, const uint32_t *trows,
+                       const int32_t *cstart, const int32_t *cend, const PBox *qbox,
+                       const uint32_t *qorder, int64_t nq, int32_t *cand_i, int32_t *cand_j,
+                       int64_t cand_cap, DevCounters *c, hipStream_t st);
+
 void launch_traverse(const Node *nodes, int64_t n_int, const PBox *root_box, const PBox *qbox,
                      const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
                      const int32_t *inst_root, int32_t *cand_i, int32_t *cand_j,

@@ -30,6 +30,7 @@ TRIL_TIMING = 0x1
 TRIL_SORT_QUERIES_ONCE = 0x2
 TRIL_FP64_NARROW = 0x4
 TRIL_ANNIHILATE = 0x8
+TRIL_GRID = 0x10
 
 FIELDS = ("x", "y", "z", "px", "py", "pz", "E", "w")
 _dp = ctypes.POINTER(ctypes.c_double)
