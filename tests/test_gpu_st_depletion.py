@@ -145,3 +145,29 @@ def test_pair_table_overflow_reported(torch):
     with pytest.raises(T.TrilError) as e:
         _gpu(torch, A, B, wl, 150, 100, _grids(wl, A, B), pair_log2=4)
     assert e.value.code == T.TRIL_E_OVERFLOW
+
+
+def test_depleted_benchmark_size_sampled_rows(torch):
+    """The benchmark's depletion configuration (2e4 macro-particles per beam, 1e20 photons,
+    all 400 steps): the per-cloud-pair yields of 40 sampled query rows against the oracle."""
+    wl = beams.st_headon(20_000, physical=1e20)
+    A, B = beams.draw_pair(wl)
+    grids = _grids(wl, A, B)
+    items, pitems, tot, _ = _gpu(torch, A, B, wl, 0, wl.n_steps, grids, cap_log2=23, pair_log2=25)
+    keys, ys = pitems
+    nB = len(B["E"])
+    rows = np.sort(np.random.default_rng(2).choice(len(A["E"]), 40, replace=False))
+    ga, _ = grids
+    Y, S = SO.st_depleted_pairs(A, B, wl.dt, 0, wl.n_steps, ga.cell, rows=rows)
+    ba, _ = SO.bin_beam(A, grids[0])
+    bb, _ = SO.bin_beam(B, grids[1])
+    ref = {}
+    for a, r in enumerate(rows):
+        for j in np.nonzero((S[a] > 0) & (bb >= 0))[0]:
+            if ba[r] >= 0:
+                ref[int(r) * nB + int(j)] = float(Y[a, j])
+    sel = np.isin(keys // nB, rows)
+    got = dict(zip(keys[sel].tolist(), ys[sel].tolist()))
+    assert len(ref) > 100 and set(got) == set(ref)
+    for k, v in ref.items():
+        assert abs(got[k] - v) <= 1e-9 * v

@@ -136,3 +136,29 @@ def test_oversized_swarm_reported(torch):
     with pytest.raises(T.TrilError) as e:
         _run(torch, A, B, (4e-9,) * 3)
     assert e.value.code == T.TRIL_E_DATA
+
+
+def test_benchmark_configuration_sampled_pairs(torch):
+    """The benchmark's swarm configuration (200 macro-particles per beam, 4096 real photons
+    each, clouds of 4e-9 um, 10 steps): every macro-particle pair among 6 sampled rows of each
+    beam against the brute-force oracle (1.7e7 real pairs per macro-particle pair)."""
+    rng = np.random.default_rng(0)
+    n, n_real = 200, 4096
+
+    def beam(sgn):
+        return {"x": rng.normal(0, 2e-9, n), "y": rng.normal(0, 2e-9, n),
+                "z": -sgn * 0.5 + rng.normal(0, 0.05, n), "px": np.zeros(n), "py": np.zeros(n),
+                "pz": np.full(n, sgn * 2.0), "E": np.full(n, 2.0), "w": np.full(n, float(n_real))}
+    A, B = beam(1.0), beam(-1.0)
+    cell = (4e-9, 4e-9, 4e-9)
+    tot, pk, pv, _, _ = _run(torch, A, B, cell, pair_log2=20)
+    got = dict(zip(pk.tolist(), pv.tolist()))
+    ra = np.sort(rng.choice(n, 6, replace=False))
+    rb = np.sort(rng.choice(n, 6, replace=False))
+    As = {k: v[ra] for k, v in A.items()}
+    Bs = {k: v[rb] for k, v in B.items()}
+    cnt, knife = O.swarm_pairs(As, Bs, 0.1, 0, 10, cell)
+    assert knife == 0 and cnt.sum() > 0
+    for a, i in enumerate(ra):
+        for b, j in enumerate(rb):
+            assert got.get(int(i) * n + int(j), 0.0) == float(cnt[a, b])
