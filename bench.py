@@ -167,6 +167,14 @@ def st_bench(args):
         t_dep = (time.perf_counter() - t1) / max(args.steps, 1)
         n_cloud_pairs = int((pt.key >= 0).sum().item())
         del dinst, pt
+        from oracle import st_oracle as SO
+        dwl = beams.st_headon(args.st_dep_mp, physical=args.st_dep_physical)
+        DA, DB = beams.draw_pair(dwl)
+        drows = np.arange(20)
+        t1 = time.perf_counter()
+        SO.st_depleted_pairs(DA, DB, dwl.dt, 0, dwl.n_steps,
+                             surrogate.cell_grid(dwl, "a", DA).cell, rows=drows)
+        dep_cpu_s = time.perf_counter() - t1
         swarm = swarm_measure(T, torch)
     finally:
         net.close()
@@ -196,12 +204,20 @@ def st_bench(args):
                            "queries_per_s": float(nd) * nd * 400 / t_dep, "ms": 1e3 * t_dep,
                            "ms_linear": 1e3 * t_lin, "total": dep_total,
                            "linear_total": lin_total, "ratio_to_linear": dep_total / lin_total,
-                           "cloud_pairs": n_cloud_pairs},
+                           "cloud_pairs": n_cloud_pairs,
+                           "cpu_oracle": {"queries_per_s": 20.0 * nd * 400 / dep_cpu_s,
+                                          "kind": "oracle", "cores": _oracle_threads(),
+                                          "sample": "20 query rows x all target clouds x 400 steps"}},
         "ip_swarm": swarm,
         "exact": {"queries_per_s": q / t_exact, "ms": 1e3 * t_exact, "total": exact_total,
                   "cloud_pair_steps_per_run": st["n_candidates"] // max(args.steps + args.warmup, 1)},
     }
     print(json.dumps(out), flush=True)
+
+
+def _oracle_threads():
+    from oracle import oracle as O
+    return O.num_threads()
 
 
 def swarm_measure(T, torch, n_mp=200, n_real=4096, reps=3):
@@ -236,7 +252,16 @@ def swarm_measure(T, torch, n_mp=200, n_real=4096, reps=3):
     finally:
         ctx.close()
     tests = float(n_pairs) * n_real * n_real
-    return {"macro_particles_per_beam": n_mp, "real_photons_per_mp": n_real,
+    from oracle import oracle as O
+    sub_a = {k: v[:3] for k, v in A.items()}
+    sub_b = {k: v[:3] for k, v in B.items()}
+    t0 = time.perf_counter()
+    O.swarm_pairs(sub_a, sub_b, 0.1, 0, 10, cell)
+    cpu_s = time.perf_counter() - t0
+    return {"cpu_oracle": {"real_pair_tests_per_s": 9.0 * n_real * n_real / cpu_s,
+                           "cores": O.num_threads(), "kind": "oracle",
+                           "sample": "3 x 3 macro-particle pairs, brute force over real pairs"},
+            "macro_particles_per_beam": n_mp, "real_photons_per_mp": n_real,
             "mp_pairs": n_pairs, "real_pair_tests_implied": tests, "colliding_real_pairs": tot,
             "ms": 1e3 * sec, "real_pair_tests_per_s": tests / sec}
 
@@ -292,7 +317,20 @@ def kinematics_variant(T, torch, A, B, wl, n_steps, edges, reps=5):
     avg = sum(ms) / len(ms)
     gbs = KIN_BYTES_PER_PAIR * n / (avg * 1e-3) / 1e9
     traffic = kinematics_traffic(n)
-    return {"run_pairs": n_run, "run_pairs_ms": round(ms_run, 4),
+    # the oracle beside it: the same kinematics in plain Python floats, 3000 seeded pairs
+    from oracle import kinematics_oracle as K
+    rs = np.random.default_rng(6)
+    ns = 3000
+    si = rs.integers(0, len(A["E"]), ns)
+    sj = rs.integers(0, len(B["E"]), ns)
+    sk = rs.integers(0, n_steps, ns)
+    t0 = time.perf_counter()
+    pos, _ = K.kinematics(A, B, si, sj, sk, 1)
+    K.histograms(A, B, si, sj, pos, g_edges, 90)
+    cpu_s = time.perf_counter() - t0
+    return {"cpu_oracle": {"pairs_per_s": ns / cpu_s, "cores": 1, "kind": "oracle",
+                           "sample": f"{ns} seeded random pairs, Python floats, one thread"},
+            "run_pairs": n_run, "run_pairs_ms": round(ms_run, 4),
             "bulk_pairs": n, "bulk_ms": round(avg, 4),
             "bulk_pairs_per_s": n / (avg * 1e-3),
             "roofline": {"bound": "hbm", "kernel": "k_pair_kin", "achieved": round(gbs, 2),
