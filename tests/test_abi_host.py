@@ -94,3 +94,14 @@ def test_null_arguments():
 def test_pair_kinematics_rejects_null_arguments():
     L = T.lib()
     assert L.tril_pair_kinematics(None, None, None, None, 0, None, None, None) == T.TRIL_E_INVAL
+
+
+def test_new_entry_points_reject_null_arguments():
+    L = T.lib()
+    c3 = (ctypes.c_double * 3)(0.5, 0.5, 0.5)
+    tot = ctypes.c_double(0.0)
+    assert L.tril_st_exact_depleted(None, None, None, 1, None, None, c3, 0, 1, None, None,
+                                    ctypes.byref(tot)) == T.TRIL_E_INVAL
+    n = ctypes.c_int64(0)
+    assert L.tril_ip_swarm(None, None, None, 1, None, None, c3, 0, 1, None, None,
+                           ctypes.byref(n)) == T.TRIL_E_INVAL
