@@ -170,6 +170,9 @@ struct tril_ctx {
     SortScratch ss;
     StatsScratch sst;
     AnnScratch ann;                        // annihilation-mode resolution
+    uint8_t *dead_q = nullptr, *dead_t = nullptr;  // photons consumed in this run (per row)
+    int64_t dead_cap_q = 0, dead_cap_t = 0;
+    int64_t *ann_count = nullptr;                  // kept hits of one batch (device)
     unsigned long long *swarm_total = nullptr;  // IP regime: colliding real pairs
     GridDev *grid_dev = nullptr;    // uniform-grid broad phase (TRIL_GRID)
     int32_t *grid_start = nullptr, *grid_end = nullptr;
@@ -655,6 +658,28 @@ void free_annihilation(tril_ctx *c) {
     a = AnnScratch{};
 }
 
+// Consumed-photon flags of both beams for a run with TRIL_ANNIHILATE, cleared.
+int ensure_dead(tril_ctx *c, int64_t nq, int64_t nt) {
+    if (nq > c->dead_cap_q) {
+        ++c->alloc_gen;
+        dev_free(c->dead_q);
+        c->dead_cap_q = 0;
+        CHK(dev_alloc(&c->dead_q, (size_t)nq));
+        c->dead_cap_q = nq;
+    }
+    if (nt > c->dead_cap_t) {
+        ++c->alloc_gen;
+        dev_free(c->dead_t);
+        c->dead_cap_t = 0;
+        CHK(dev_alloc(&c->dead_t, (size_t)nt));
+        c->dead_cap_t = nt;
+    }
+    if (!c->ann_count) CHK(dev_alloc(&c->ann_count, 1));
+    if (nq > 0) HIPCHK(hipMemsetAsync(c->dead_q, 0, (size_t)nq, c->st));
+    if (nt > 0) HIPCHK(hipMemsetAsync(c->dead_t, 0, (size_t)nt, c->st));
+    return TRIL_OK;
+}
+
 int ensure_stats(tril_ctx *c, int64_t n_hits, int32_t n_steps) {
     StatsScratch &s = c->sst;
     if (n_hits > s.cap) {
@@ -924,12 +949,53 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     const bool once = (c->flags & TRIL_SORT_QUERIES_ONCE) != 0;
     bool q_sorted = false;
     const bool timed = (c->flags & TRIL_TIMING) != 0;
+    // annihilation: after every batch its hits are resolved in chronological order and the
+    // photons of the kept hits are marked consumed, so that later batches leave them out of
+    // their hierarchies and queries (the kept set is the same as resolving at the end)
+    const bool ann = (c->flags & TRIL_ANNIHILATE) != 0;
+    int64_t ann_done = 0;  // hits in the buffer that are resolved (kept hits and older hits)
+    bool ann_ok = true;    // false once the pair buffer overflowed: tril_stats reports it
+    if (ann) {
+        CHK(ensure_annihilation(c, std::max<int64_t>(out->cap, 1), q->n, t->n));
+        CHK(ensure_dead(c, q->n, t->n));
+        HIPCHK(hipStreamSynchronize(c->st));
+        HIPCHK(hipMemcpy(&ann_done, out->count, sizeof(ann_done), hipMemcpyDeviceToHost));
+        if (ann_done > out->cap) ann_ok = false;
+    }
+    auto resolve = [&](hipStream_t st, int32_t last_step) -> int {
+        if (!ann || !ann_ok) return TRIL_OK;
+        HIPCHK(hipStreamSynchronize(st));
+        int64_t cnt = 0;
+        HIPCHK(hipMemcpy(&cnt, out->count, sizeof(cnt), hipMemcpyDeviceToHost));
+        if (cnt > out->cap) {
+            ann_ok = false;
+            return TRIL_OK;
+        }
+        const int64_t nb = cnt - ann_done;
+        if (nb <= 0) return TRIL_OK;
+        const tril_pairs v{out->cap - ann_done, out->i + ann_done, out->j + ann_done,
+                           out->step + ann_done, c->ann_count};
+        int64_t kept = 0;
+        const hipError_t e = annihilate_hits(v, nb, view(q, c->d_q_off, 1), view(t, c->d_t_off, 1),
+                                             c->dt, last_step, c->ann, c->ss, &c->d_cnt->err, st,
+                                             &kept);
+        if (e != hipSuccess) return hip_fail(e);
+        launch_ann_mark(v, kept, c->dead_q, c->dead_t, st);
+        ann_done += kept;
+        HIPCHK(hipMemcpyAsync(out->count, &ann_done, sizeof(ann_done), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return TRIL_OK;
+    };
 
     // Batch of mb steps with working buffers (pt, pq) on stream st: build, collide, and
     // rewrite the working copies for the next batch.
     auto enqueue_batch = [&](int32_t mb, bool sort, hipStream_t st, bool tm) -> int {
         c->tgt = wview(t, c->d_t_off, mb, c->wt[pt]);
-        const BeamDev qv = wview(q, c->d_q_off, mb, c->wq[pq]);
+        BeamDev qv = wview(q, c->d_q_off, mb, c->wq[pq]);
+        if (ann) {
+            c->tgt.dead = c->dead_t;
+            qv.dead = c->dead_q;
+        }
         CHK(enqueue_build(c, st, tm));
         if (!sort) {
             c->q_order = nullptr;  // the working copy is already in Morton order
@@ -959,6 +1025,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
             launch_set_step(c->d_cnt, k, c->st);
             CHK(enqueue_batch(mb, sort, c->st, timed));
             flip(sort);
+            CHK(resolve(c->st, k + mb - 1));
             q_sorted = q_sorted || sort;
             k += mb;
             left -= mb;
@@ -1008,6 +1075,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
             }
             HIPCHK(hipGraphLaunch(c->gexec[slot], c->gst));
             flip(sort);
+            CHK(resolve(c->gst, k + (r + 1) * m - 1));
         }
         HIPCHK(hipEventRecord(c->ev_join_b, c->gst));
         HIPCHK(hipStreamWaitEvent(c->st, c->ev_join_b, 0));
@@ -1958,6 +2026,9 @@ void tril_destroy(tril_ctx *c) {
     free_target(c);
     free_target_rows(c);
     free_annihilation(c);
+    dev_free(c->dead_q);
+    dev_free(c->dead_t);
+    dev_free(c->ann_count);
     dev_free(c->kin_buf);
     dev_free(c->swarm_total);
     dev_free(c->grid_dev);

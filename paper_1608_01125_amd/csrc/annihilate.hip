@@ -147,9 +147,23 @@ __global__ void k_ann_compact(int64_t n, const int32_t *__restrict__ ti,
     p.step[pos] = tk[h];
 }
 
+__global__ void k_ann_mark(tril_pairs p, int64_t n, uint8_t *__restrict__ dead_q,
+                           uint8_t *__restrict__ dead_t) {
+    const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (h >= n) return;
+    dead_q[p.i[h]] = 1;
+    dead_t[p.j[h]] = 1;
+}
+
 inline unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
+
+void launch_ann_mark(const tril_pairs &p, int64_t n, uint8_t *dead_q, uint8_t *dead_t,
+                     hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_ann_mark, dim3(grid_of(n)), dim3(256), 0, st, p, n, dead_q, dead_t);
+}
 
 hipError_t annihilate_hits(const tril_pairs &p, int64_t n, const BeamDev &q, const BeamDev &t,
                            double dt, int32_t max_step, AnnScratch &a, SortScratch &ss,

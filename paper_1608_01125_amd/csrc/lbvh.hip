@@ -293,6 +293,8 @@ __device__ __forceinline__ RowPhoton load_photon(const BeamDev &b, int64_t i, do
     r.x = b.x[i]; r.y = b.y[i]; r.z = b.z[i];
     r.ok = isfinite(E) && isfinite(w) && isfinite(px) && isfinite(py) && isfinite(pz) &&
            isfinite(r.x) && isfinite(r.y) && isfinite(r.z) && E > 0.0 && w >= 0.0;
+    // a photon consumed by an earlier collision (annihilation) takes no further part
+    if (b.dead != nullptr && b.dead[b.perm != nullptr ? b.perm[i] : i]) r.ok = false;
     r.ux = px / E; r.uy = py / E; r.uz = pz / E;
     return r;
 }

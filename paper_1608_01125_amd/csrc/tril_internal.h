@@ -126,6 +126,7 @@ struct BeamDev {
     const int64_t *inst_off;   // device copy, n_inst + 1
     int32_t m;                 // steps covered by the launch (>= 1)
     const int32_t *perm;       // row of this view -> caller's row (nullptr: identity)
+    const uint8_t *dead = nullptr;  // per caller row: consumed (annihilation), drops out
 };
 
 // Per-instance statistics of a beam over its rows (the same for every step):
@@ -378,6 +379,9 @@ struct AnnScratch {
 // q and target view t, the callers' beams; steps up to max_step): the kept hits are
 // written back to p's first *n_kept entries (order unspecified) and *p.count is set to
 // their number. Synchronises the stream (one round trip per resolution round).
+// Marks both photons of the first n hits of p consumed (dead_q[i] = dead_t[j] = 1).
+void launch_ann_mark(const tril_pairs &p, int64_t n, uint8_t *dead_q, uint8_t *dead_t,
+                     hipStream_t st);
 hipError_t annihilate_hits(const tril_pairs &p, int64_t n, const BeamDev &q, const BeamDev &t,
                            double dt, int32_t max_step, AnnScratch &a, SortScratch &ss,
                            unsigned int *err, hipStream_t st, int64_t *n_kept);

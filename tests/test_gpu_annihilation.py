@@ -89,6 +89,24 @@ def test_gauss_headon_reduced_boosted(torch, graph, step_batch, flags):
     assert_parity(gpu, kept, S, wl.n_steps)
 
 
+@pytest.mark.parametrize("step_batch", [50, 7, 1])
+def test_consumed_photons_drop_out_of_later_batches(torch, step_batch):
+    """tril_run resolves every batch of steps as it finishes and leaves the photons it consumed
+    out of the later batches' hierarchies and queries: the kept hits are still the oracle's,
+    and the broad phase finds fewer candidates than the same run without annihilation (photons
+    consumed early meet nobody later)."""
+    wl = beams.gauss_headon_1m(seed=2)
+    wl = beams.gauss_headon_1m(seed=2, n=20_000, w=wl.a.w * 2500.0)
+    A, B = beams.draw_pair(wl)
+    raw, kept, S = _oracle(A, B, wl.dt, wl.n_steps, key="gauss_reduced")
+    plain = gpu_run(A, B, wl.dt, wl.n_steps, EDGES, graph=True, step_batch=step_batch)
+    gpu = gpu_run(A, B, wl.dt, wl.n_steps, EDGES, graph=True, step_batch=step_batch,
+                  flags=T.TRIL_ANNIHILATE)
+    assert_parity(gpu, kept, S, wl.n_steps)
+    assert gpu[3]["n_candidates"] < plain[3]["n_candidates"]
+    assert plain[3]["n_hits"] == len(raw.i)
+
+
 def test_batched_instances_ragged(torch):
     parts_a, parts_b = [], []
     for m, (na, nb) in enumerate([(3000, 2000), (0, 500), (1, 1), (2500, 4000), (700, 0)]):
