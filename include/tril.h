@@ -74,7 +74,11 @@ extern "C" {
                                     raw hit only if neither photon was consumed by a hit
                                     before it in the order (step, time of closest approach
                                     inside the step, i, j); Sec. 2.1 (annihilating photons)
-                                    and Sec. 2.2 (collisions sorted in time) */
+                                    and Sec. 2.2 (collisions sorted in time). tril_run
+                                    resolves each batch of steps as it finishes and leaves
+                                    the photons consumed so far out of the later batches'
+                                    hierarchies and queries (same kept hits; the run then
+                                    synchronises once per batch) */
 #define TRIL_GRID          0x10u /* broad phase on a uniform grid instead of the hierarchy (the
                                     mesh the paper compares its tree against, Sec. 3): per
                                     step, target boxes sorted by the cell of their centre
