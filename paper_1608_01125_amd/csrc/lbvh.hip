@@ -397,7 +397,8 @@ __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, CloudB
             o.lox = lo32[0]; o.loy = lo32[1]; o.loz = lo32[2];
             o.hix = hi32[0]; o.hiy = hi32[1]; o.hiz = hi32[2];
             o.tag = (!r.ok || below) ? -1 : cc;
-            o.pad = cc;
+            // queries carry their energy rounded up (the traversal's threshold prune)
+            o.pad = query ? __float_as_int(r.ok ? f32_up(E) : 0.0f) : cc;
             out[(int64_t)s * b.n + i] = o;
         }
         if (vals == nullptr || s != key_step) continue;
@@ -565,10 +566,11 @@ __device__ __forceinline__ void store_half_coherent(Half *h, const Half &v) {
 __device__ __forceinline__ void store_half_plain(Half *h, const Half &v) {
     float4 *p = reinterpret_cast<float4 *>(h);
     p[0] = make_float4(v.lox, v.loy, v.loz, __int_as_float(v.link));
-    p[1] = make_float4(v.hix, v.hiy, v.hiz, 0.0f);
+    p[1] = make_float4(v.hix, v.hiy, v.hiz, __int_as_float(v.pad));
 }
 
-__device__ __forceinline__ void load_half_box(const Half *h, float lo[3], float hi[3]) {
+__device__ __forceinline__ void load_half_box(const Half *h, float lo[3], float hi[3],
+                                              float &emax) {
     const unsigned long long *p = reinterpret_cast<const unsigned long long *>(h);
     unsigned long long w[4];
 #pragma unroll
@@ -581,15 +583,16 @@ __device__ __forceinline__ void load_half_box(const Half *h, float lo[3], float 
     hi[0] = __uint_as_float((uint32_t)w[2]);
     hi[1] = __uint_as_float((uint32_t)(w[2] >> 32));
     hi[2] = __uint_as_float((uint32_t)w[3]);
+    emax = __uint_as_float((uint32_t)(w[3] >> 32));
 }
 
 __device__ __forceinline__ Half merge_halves(const Half &a, const float lo[3], const float hi[3],
-                                             int32_t link) {
+                                             float emax, int32_t link) {
     Half u;
     u.lox = fminf(a.lox, lo[0]); u.loy = fminf(a.loy, lo[1]); u.loz = fminf(a.loz, lo[2]);
     u.hix = fmaxf(a.hix, hi[0]); u.hiy = fmaxf(a.hiy, hi[1]); u.hiz = fmaxf(a.hiz, hi[2]);
     u.link = link;
-    u.pad = 0;
+    u.pad = __float_as_int(fmaxf(__int_as_float(a.pad), emax));  // subtree energy bound
     return u;
 }
 
@@ -627,9 +630,9 @@ __device__ __forceinline__ void climb_crossing(int32_t cur, Half cn, i32x4 r, bo
         // the second arrival is the flag's last use in this launch: leave it cleared
         __hip_atomic_store(flags + p, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        float slo[3], shi[3];
-        load_half_box(&pn->c[side ^ 1], slo, shi);
-        cn = merge_halves(cn, slo, shi, step_node(p, step, n));
+        float slo[3], shi[3], semax;
+        load_half_box(&pn->c[side ^ 1], slo, shi, semax);
+        cn = merge_halves(cn, slo, shi, semax, step_node(p, step, n));
         cur = p;
         r = grec[cur];
     }
@@ -678,12 +681,14 @@ __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cl
     RowPhoton ph;
     ph.ok = false;
     ph.x = ph.y = ph.z = ph.ux = ph.uy = ph.uz = 0.0;
+    float eup = 0.0f;  // the leaf's energy rounded up: the subtree bound of the prune
     if (in) {
         row = rows[j];
         s_rec[tid] = grec[leaf0 + j];
         s_rec[kRefitChunk + tid] = (j < leaf0) ? grec[j] : i32x4{0, 0, 0, 0};
         double E, w;
         ph = load_photon(b, row, E, w);
+        eup = ph.ok ? f32_up(E) : 0.0f;
     }
     const unsigned step0 = cnt->step;
     for (int32_t step = s_begin; step < s_end; ++step) {
@@ -699,10 +704,10 @@ __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cl
             cn.lox = lo[0]; cn.loy = lo[1]; cn.loz = lo[2];
             cn.hix = hi[0]; cn.hiy = hi[1]; cn.hiz = hi[2];
             cn.link = leaf_link((int64_t)step * n + row);
-            cn.pad = 0;
+            cn.pad = __float_as_int(eup);
             cur = (int32_t)(leaf0 + j);
             s_leaf[0][tid] = make_float4(cn.lox, cn.loy, cn.loz, 0.0f);
-            s_leaf[1][tid] = make_float4(cn.hix, cn.hiy, cn.hiz, 0.0f);
+            s_leaf[1][tid] = make_float4(cn.hix, cn.hiy, cn.hiz, eup);
         }
         __syncthreads();
         int32_t *sflags = flags + (int64_t)step * (n - 1);
@@ -728,7 +733,7 @@ __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cl
             if (cur < leaf0) {
                 const int64_t k = cur - c0;
                 s_int[0][k] = make_float4(cn.lox, cn.loy, cn.loz, 0.0f);
-                s_int[1][k] = make_float4(cn.hix, cn.hiy, cn.hiz, 0.0f);
+                s_int[1][k] = make_float4(cn.hix, cn.hiy, cn.hiz, __int_as_float(cn.pad));
             }
             // the sibling's thread reads this box from LDS only: order LDS accesses
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -743,7 +748,7 @@ __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cl
             const float4 blo = sleaf ? s_leaf[0][k] : s_int[0][k];
             const float4 bhi = sleaf ? s_leaf[1][k] : s_int[1][k];
             const float slo[3] = {blo.x, blo.y, blo.z}, shi[3] = {bhi.x, bhi.y, bhi.z};
-            cn = merge_halves(cn, slo, shi, step_node(p, step, n));
+            cn = merge_halves(cn, slo, shi, bhi.w, step_node(p, step, n));
             cur = p;
             r = rp;
         }
@@ -782,7 +787,7 @@ __global__ void __launch_bounds__(256) k_refit_top(const int32_t *__restrict__ s
     const float4 a = hp[0], b = hp[1];
     Half cn;
     cn.lox = a.x; cn.loy = a.y; cn.loz = a.z; cn.link = __float_as_int(a.w);
-    cn.hix = b.x; cn.hiy = b.y; cn.hiz = b.z; cn.pad = 0;
+    cn.hix = b.x; cn.hiy = b.y; cn.hiz = b.z; cn.pad = __float_as_int(b.w);
     climb_crossing(cur, cn, r, true, step, n, grec, flags + (int64_t)step * (n - 1), nodes, err);
 }
 

@@ -7,6 +7,12 @@
 // overlap, the right one waits on a per-lane stack (four entries in registers, the
 // rest in a private spill array).
 //
+// Threshold prune (Eq. 2): a node's child half also holds the largest photon energy of
+// its subtree, rounded up, and a query box its photon's energy, rounded up. Since
+// s = E_i E_j (1 - u_i.u_j) / (2 m_e^2) <= E_i E_j / m_e^2, a child whose bound gives
+// E_q E_max < m_e^2 (1 - 1e-5) holds no photon above threshold with the query and is
+// skipped (the FP32 product's rounding is far inside the margin).
+//
 // The overlap test is closed (<=) on both sides, so touching boxes stay
 // candidates; boxes are rounded outward, so the candidate set contains every
 // pair the exact narrow phase can accept.
@@ -55,6 +61,8 @@ __device__ __forceinline__ bool box_overlap(const float q[6], float4 lo, float4 
            (q[5] >= lo.z);
 }
 
+constexpr float kPruneProduct = (float)(kMe * kMe * (1.0 - 1e-5));
+
 constexpr int kStackRegs = 4;
 constexpr int kStackSpill = 124;  // deeper than any radix tree over (key, index) pairs
 
@@ -71,6 +79,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
     const int64_t q = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
     int32_t node = -1, qi = 0, tag = -1;
     float qb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float qe = 0.f;
     if (q < nq) {
         if (qorder == nullptr) {
             qi = (int32_t)q;
@@ -84,6 +93,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
         const float4 a = bp[0], b = bp[1];
         qb[0] = a.x; qb[1] = a.y; qb[2] = a.z;
         qb[3] = b.x; qb[4] = b.y; qb[5] = b.z;
+        qe = b.w;
         tag = __float_as_int(a.w);
         if (tag >= 0) node = inst_root[tag];
     }
@@ -116,7 +126,8 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
         const float4 l0 = np[0], l1 = np[1], r0 = np[2], r1 = np[3];
         ++visits;
         const int32_t lc = __float_as_int(l0.w), rc = __float_as_int(r0.w);
-        const bool ovl = box_overlap(qb, l0, l1), ovr = box_overlap(qb, r0, r1);
+        const bool ovl = box_overlap(qb, l0, l1) & (qe * l1.w >= kPruneProduct);
+        const bool ovr = box_overlap(qb, r0, r1) & (qe * r1.w >= kPruneProduct);
         const bool leafl = lc < 0, leafr = rc < 0;
         emit_candidate(ovl & leafl, qi, link_elem(lc), cand_i, cand_j, cand_cap, c);
         emit_candidate(ovr & leafr, qi, link_elem(rc), cand_i, cand_j, cand_cap, c);
