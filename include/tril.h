@@ -116,7 +116,8 @@ typedef struct {
     int64_t cand_cap;             /* broad-phase candidates one step may hold (0 = default) */
     int32_t block_traverse;       /* traversal workgroup size: 64, 128, 256, 512 or 0 = default */
     int32_t step_batch;           /* tril_run: steps per launch, >= 0 (0 = as many as keep one
-                                     launch near 2^24 photon-steps) */
+                                     launch within 2^26 photon-steps, or, for beams of more
+                                     than 2^22 photons, 16 steps within 2^28) */
     int32_t morton_bits;          /* Morton bits of the sort keys, 3..30, or 0 = automatic:
                                      30 (10 per axis) for tril_build/tril_collide; for tril_run,
                                      which first puts both beams in the order of their full

@@ -71,6 +71,10 @@ int comb_key_bits(int64_t n_comb) { return 30 + bits_for((uint64_t)(n_comb > 1 ?
 constexpr int64_t kMaxN = (int64_t)1 << 30;       // node ids 2n-1 fit int32, sort counts fit 30 bits
 constexpr int64_t kMaxComb = (int64_t)1 << 24;    // combined instances (steps x instances) per launch
 constexpr int64_t kBatchBudget = (int64_t)1 << 26;  // default virtual elements per launch
+// large beams may take up to kBatchBudgetMax virtual elements per launch (about 140 bytes of
+// scratch each) so that a launch still covers kBatchStepsMin steps
+constexpr int64_t kBatchBudgetMax = (int64_t)1 << 28;
+constexpr int64_t kBatchStepsMin = 16;
 
 }  // namespace
 
@@ -745,7 +749,9 @@ int run_morton_bits(const tril_ctx *c, int64_t n_inst) {
 // virtual element count of one launch within kBatchBudget.
 int32_t pick_batch(const tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t n_steps) {
     const int64_t rows = std::max<int64_t>(std::max(t->n, q->n), 1);
-    int64_t m = c->step_batch > 0 ? c->step_batch : std::max<int64_t>(1, kBatchBudget / rows);
+    const int64_t budget =
+        std::max(kBatchBudget, std::min(kBatchBudgetMax, kBatchStepsMin * rows));
+    int64_t m = c->step_batch > 0 ? c->step_batch : std::max<int64_t>(1, budget / rows);
     m = std::min<int64_t>(m, n_steps);
     m = std::min<int64_t>(m, std::max<int64_t>(1, (kMaxN - 1) / rows));
     m = std::min<int64_t>(m, std::max<int64_t>(1, kMaxComb / std::max(t->n_inst, 1)));

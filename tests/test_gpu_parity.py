@@ -221,3 +221,24 @@ def test_counters_and_threshold_prune(torch):
     assert st["n_queries"] == 50 * 4000
     assert st["n_node_visits"] >= st["n_queries"]
     assert st["n_candidates"] >= st["n_hits"]
+
+
+def test_broadband_full_size_sampled_rows(torch):
+    """Full size of the broadband workload (1.6e7 photons per beam, calibrated weight, 1000
+    steps, graph replay, the benchmark's launch configuration of 16 steps per launch): every
+    pair of 120 sampled query rows, 60 of them among the rows that collided, against the
+    oracle."""
+    wl = beams.broadband_16m()
+    A, B = beams.draw_pair(wl)
+    i, j, k, st = gpu_run(A, B, wl.dt, wl.n_steps, EDGES, graph=True, cap=1 << 22)
+    assert 200_000 < st["n_pairs"] < 500_000
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([rng.choice(np.unique(i), 60, replace=False),
+                                     rng.choice(len(A["E"]), 60, replace=False)]))
+    raw = O.collide(A, B, wl.dt, wl.n_steps, rows=rows)
+    S = O.summarize(raw, A, B, wl.n_steps, EDGES)
+    assert raw.knife_margin == 0 and raw.knife_s == 0
+    keep = np.isin(i, rows)
+    assert np.array_equal(i[keep], S.i)
+    assert np.array_equal(j[keep], S.j)
+    assert np.array_equal(k[keep], S.first_step)
