@@ -269,7 +269,8 @@ typedef struct {
 
 /* Autotuner: time tril_run over steps k0 .. k0+n_probe-1 of the given beams for a set of
  * launch configurations and keep the fastest in the context (and in *best). Coordinate
- * descent: steps per launch (1 .. 64, within 2^26 photon-steps per launch), then the
+ * descent: steps per launch (1 .. 128, within 2^27 photon-steps per launch, or within the
+ * default batch budget where that is larger), then the
  * traversal workgroup size (64 .. 512), then the Morton bits (automatic or 30). Every
  * configuration runs twice (the first run captures its graphs and sizes the scratch);
  * the second is timed with HIP events on the context stream. Hits go to a scratch buffer

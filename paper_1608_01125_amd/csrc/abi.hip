@@ -1972,7 +1972,9 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
         return rc;
     }
     for (int sb : {1, 2, 4, 8, 16, 32, 64, 128}) {
-        if (sb == cur.step_batch || sb > n_probe || (int64_t)sb * rows > ((int64_t)1 << 27)) continue;
+        const int64_t lim = std::max<int64_t>((int64_t)1 << 27,
+                                              std::min(kBatchBudgetMax, kBatchStepsMin * rows));
+        if (sb == cur.step_batch || sb > n_probe || (int64_t)sb * rows > lim) continue;
         double ms = 0.0;
         if ((rc = probe(cur.block_traverse, sb, cur.morton_bits, ms)) != TRIL_OK) break;
         if (ms < best_ms) {
