@@ -184,6 +184,8 @@ struct tril_ctx {
     double *kin_buf = nullptr;             // pair kinematics: edges, histogram bins
     unsigned int *kin_err = nullptr;
     hipEvent_t ev_kin[2] = {nullptr, nullptr};
+    double *kin_rec = nullptr;            // packed photon records (8 doubles each)
+    int64_t kin_rec_cap = 0;
     int32_t max_step = -1;
 
     // timing (TRIL_TIMING)
@@ -1214,10 +1216,18 @@ int tril_pair_kinematics(tril_ctx *c, const tril_beam *q, const tril_beam *t,
                               hipMemcpyHostToDevice, c->st));
     if (nb > 0) HIPCHK(hipMemsetAsync(d_hist, 0, (size_t)nb * sizeof(double), c->st));
     HIPCHK(hipMemsetAsync(c->kin_err, 0, sizeof(unsigned int), c->st));
+    const int64_t nrec = pair_kinematics_records(n, q->n, t->n);
+    if (nrec > c->kin_rec_cap) {
+        dev_free(c->kin_rec);
+        c->kin_rec_cap = 0;
+        CHK(dev_alloc(&c->kin_rec, (size_t)(8 * nrec)));
+        c->kin_rec_cap = nrec;
+    }
     HIPCHK(hipEventRecord(c->ev_kin[0], c->st));
     if (n > 0)
         launch_pair_kinematics(view(q, nullptr, 1), view(t, nullptr, 1), p->i, p->j, p->step, n,
-                               kp->seed, leptons, d_edges, ng, nth, d_hist, c->kin_err, c->st);
+                               kp->seed, leptons, d_edges, ng, nth, d_hist, c->kin_err,
+                               nrec > 0 ? c->kin_rec : nullptr, c->st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev_kin[1], c->st));
     HIPCHK(hipStreamSynchronize(c->st));
@@ -2038,6 +2048,7 @@ void tril_destroy(tril_ctx *c) {
     dev_free(c->dead_t);
     dev_free(c->ann_count);
     dev_free(c->kin_buf);
+    dev_free(c->kin_rec);
     dev_free(c->swarm_total);
     dev_free(c->grid_dev);
     dev_free(c->grid_start);

@@ -22,6 +22,12 @@
 // gather of 5 doubles per photon, about 200 FP64 operations, two sqrt and the generator's
 // 20 64-bit products, and a 64-byte store. Histograms accumulate in LDS per workgroup and
 // are added to the device histogram once per bin at the end.
+//
+// The photon data are the caller's SoA arrays, so a pair's gathers touch ten cache lines.
+// For long pair lists (at least one pair per eight photons of the two beams) both beams are
+// first copied into 64-byte records (E, px, py, pz, w, padding), one cache line per photon,
+// which costs one streaming pass over the beams and cuts the gather traffic about fourfold;
+// the arithmetic reads the same values either way.
 #include "tril_internal.h"
 
 namespace tril {
@@ -74,7 +80,39 @@ __device__ __forceinline__ void add_velocity(const double bc[3], const double bp
     }
 }
 
+// One photon's record: E, px, py, pz, w (then padding to 64 bytes).
+struct alignas(16) PhotonRec {
+    double E, px, py, pz, w, pad0, pad1, pad2;
+};
+
+__global__ void __launch_bounds__(256) k_pack_photons(BeamDev b, PhotonRec *__restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= b.n) return;
+    PhotonRec r;
+    r.E = b.E[i];
+    r.px = b.px[i];
+    r.py = b.py[i];
+    r.pz = b.pz[i];
+    r.w = b.w[i];
+    r.pad0 = r.pad1 = r.pad2 = 0.0;
+    out[i] = r;
+}
+
+__device__ __forceinline__ void fetch_photon(const BeamDev &b, const PhotonRec *rec, int64_t i,
+                                             double &E, double &px, double &py, double &pz,
+                                             double &w) {
+    if (rec != nullptr) {
+        const double2 *p = reinterpret_cast<const double2 *>(rec + i);
+        const double2 a = p[0], c = p[1], d = p[2];
+        E = a.x; px = a.y; py = c.x; pz = c.y; w = d.x;
+    } else {
+        E = b.E[i]; px = b.px[i]; py = b.py[i]; pz = b.pz[i]; w = b.w[i];
+    }
+}
+
 __global__ void __launch_bounds__(256) k_pair_kin(BeamDev q, BeamDev t,
+                                                  const PhotonRec *__restrict__ qrec,
+                                                  const PhotonRec *__restrict__ trec,
                                                   const int32_t *__restrict__ pi,
                                                   const int32_t *__restrict__ pj,
                                                   const int32_t *__restrict__ pk, int64_t n,
@@ -99,9 +137,11 @@ __global__ void __launch_bounds__(256) k_pair_kin(BeamDev q, BeamDev t,
             atomicOr(err, 1u);
             continue;
         }
-        const double Ei = q.E[i], Ej = t.E[j];
+        double Ei, pxi, pyi, pzi, wi, Ej, pxj, pyj, pzj, wj;
+        fetch_photon(q, qrec, i, Ei, pxi, pyi, pzi, wi);
+        fetch_photon(t, trec, j, Ej, pxj, pyj, pzj, wj);
         const double Et = Ei + Ej;
-        const double pt[3] = {q.px[i] + t.px[j], q.py[i] + t.py[j], q.pz[i] + t.pz[j]};
+        const double pt[3] = {pxi + pxj, pyi + pyj, pzi + pzj};
         const double p2 = (pt[0] * pt[0] + pt[1] * pt[1]) + pt[2] * pt[2];
         const double pcm = sqrt(fmax(0.0, (Et * Et - p2) / 4.0 - kMe * kMe));
         const double ecm = sqrt(pcm * pcm + kMe * kMe);
@@ -138,7 +178,7 @@ __global__ void __launch_bounds__(256) k_pair_kin(BeamDev q, BeamDev t,
             dst[1] = make_double4(out[4], out[5], out[6], out[7]);
         }
         if (n_bins == 0) continue;
-        const double wt = sqrt(q.w[i] * t.w[j]);
+        const double wt = sqrt(wi * wj);
         if (n_gamma > 0) {
             const double gam = out[0] / kMe;
             if (s_edge[0] <= gam && gam < s_edge[n_gamma]) {  // largest b with edges[b] <= gam
@@ -166,17 +206,33 @@ __global__ void __launch_bounds__(256) k_pair_kin(BeamDev q, BeamDev t,
 
 }  // namespace
 
+int64_t pair_kinematics_records(int64_t n, int64_t nq, int64_t nt) {
+    return 8 * n >= nq + nt ? nq + nt : 0;
+}
+
 void launch_pair_kinematics(const BeamDev &q, const BeamDev &t, const int32_t *pi,
                             const int32_t *pj, const int32_t *pk, int64_t n, uint64_t seed,
                             double *leptons, const double *edges, int32_t n_gamma,
-                            int32_t n_theta, double *hist, unsigned int *err, hipStream_t st) {
+                            int32_t n_theta, double *hist, unsigned int *err, void *records,
+                            hipStream_t st) {
     if (n <= 0) return;
     constexpr int kBlock = 256;
+    PhotonRec *qrec = nullptr, *trec = nullptr;
+    if (records != nullptr && pair_kinematics_records(n, q.n, t.n) > 0) {
+        qrec = static_cast<PhotonRec *>(records);
+        trec = qrec + q.n;
+        if (q.n > 0)
+            hipLaunchKernelGGL(k_pack_photons, dim3((unsigned)((q.n + 255) / 256)), dim3(256), 0,
+                               st, q, qrec);
+        if (t.n > 0)
+            hipLaunchKernelGGL(k_pack_photons, dim3((unsigned)((t.n + 255) / 256)), dim3(256), 0,
+                               st, t, trec);
+    }
     const int64_t want = (n + kBlock - 1) / kBlock;
     const unsigned grid = (unsigned)std::min<int64_t>(want, 2048);
     const size_t lds = (size_t)(2 * n_gamma + 1 + n_theta) * sizeof(double);
-    hipLaunchKernelGGL(k_pair_kin, dim3(grid), dim3(kBlock), lds, st, q, t, pi, pj, pk, n, seed,
-                       leptons, edges, n_gamma, n_theta, hist, err);
+    hipLaunchKernelGGL(k_pair_kin, dim3(grid), dim3(kBlock), lds, st, q, t, qrec, trec, pi, pj,
+                       pk, n, seed, leptons, edges, n_gamma, n_theta, hist, err);
 }
 
 }  // namespace tril

@@ -393,10 +393,15 @@ hipError_t annihilate_hits(const tril_pairs &p, int64_t n, const BeamDev &q, con
 // n_theta polar-angle bins; hist zeroed by the caller). A pair naming a row outside its beam
 // or a negative step sets bit 1 of *err and is skipped. LDS: (2 n_gamma + 1 + n_theta)
 // doubles per workgroup.
+// Photon records (64 bytes each) the call will use for n pairs over beams of nq and nt
+// photons: nq + nt when the pair list is long enough to pay for packing, else 0.
+int64_t pair_kinematics_records(int64_t n, int64_t nq, int64_t nt);
+// records: device scratch of pair_kinematics_records(n, q.n, t.n) * 64 bytes, or NULL.
 void launch_pair_kinematics(const BeamDev &q, const BeamDev &t, const int32_t *pi,
                             const int32_t *pj, const int32_t *pk, int64_t n, uint64_t seed,
                             double *leptons, const double *edges, int32_t n_gamma,
-                            int32_t n_theta, double *hist, unsigned int *err, hipStream_t st);
+                            int32_t n_theta, double *hist, unsigned int *err, void *records,
+                            hipStream_t st);
 
 // ------------------------------------------------------------------ run stats
 struct StatsScratch {
