@@ -372,6 +372,34 @@ def cpu_baseline(A, offA, B, offB, dt, n_steps, target_s: float):
         if el >= 0.5 * target_s or r >= nA:
             break
         r = int(min(nA, r * max(2.0, 1.1 * target_s / max(el, 1e-3))))
+    # the paper's setting: one core (a tenth of the sample's rows, at least 8)
+    r1 = max(8, r // 10)
+    rows1 = np.sort(rng.choice(nA, r1, replace=False))
+    O.set_threads(1)
+    try:
+        pairs1 = 0
+        t = time.perf_counter()
+        for m in np.unique(inst_of[rows1]):
+            a0, a1, b0, b1 = offA[m], offA[m + 1], offB[m], offB[m + 1]
+            if b1 <= b0:
+                continue
+            Am = {k: v[a0:a1] for k, v in A.items()}
+            Bm = {k: v[b0:b1] for k, v in B.items()}
+            sel = rows1[inst_of[rows1] == m] - a0
+            O.collide(Am, Bm, dt, n_steps, rows=sel)
+            pairs1 += len(sel) * (b1 - b0)
+        el1 = time.perf_counter() - t
+    finally:
+        O.set_threads(threads)
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": pairs_tested * n_steps / el,
         "unit": "queries/s",
@@ -379,6 +407,9 @@ def cpu_baseline(A, offA, B, offB, dt, n_steps, target_s: float):
         "kind": "oracle",
         "sample": f"{r} random query rows x all target photons of their instance x {n_steps} "
                   f"steps ({pairs_tested} row-photon pairs, {el:.1f} s, FP64, pruned mode, OpenMP)",
+        "value_one_thread": pairs1 * n_steps / el1,
+        "sample_one_thread": f"{r1} random query rows, one thread, {el1:.1f} s",
+        "host": {"nproc": os.cpu_count(), "cpu": cpu_model},
     }
 
 
@@ -447,6 +478,7 @@ def main():
         del src, dst
 
     graph = args.mode != "per-step"
+    run_ms = []  # wall time of each timed run (filled by timed())
 
     def timed(flags):
         """Warm-up runs, then args.steps timed collision runs; returns (seconds, stats)."""
@@ -455,6 +487,7 @@ def main():
         if tune is not None:
             T.tril_set_tune(ctx.h, tune)
         pairs = T.Pairs(max(1 << 20, 4 * min(nA, nB)))
+        run_ms.clear()
 
         def one_run():
             pairs.reset()
@@ -468,7 +501,9 @@ def main():
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(args.steps):
-                st = one_run()
+                tr = time.perf_counter()
+                st = one_run()  # ends with tril_stats, which synchronises the stream
+                run_ms.append(1e3 * (time.perf_counter() - tr))
             torch.cuda.synchronize()
             return time.perf_counter() - t0, st
         finally:
@@ -486,6 +521,7 @@ def main():
             probe_ctx.close()
     timing = T.TRIL_TIMING if args.mode != "graph" else 0
     elapsed, st = timed(args.flags | timing)
+    main_run_ms = sorted(run_ms)
     ms_per_step = 1e3 * elapsed / max(args.steps, 1)
     value = pairs_per_step * n_steps / (elapsed / max(args.steps, 1))
     launches_per_run = st["n_timed_launches"] // max(args.steps, 1) if timing else 0
@@ -554,6 +590,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_min_median_max": [round(main_run_ms[0], 3),
+                                       round(main_run_ms[len(main_run_ms) // 2], 3),
+                                       round(main_run_ms[-1], 3)] if main_run_ms else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
