@@ -176,6 +176,34 @@ def st_bench(args):
                              surrogate.cell_grid(dwl, "a", DA).cell, rows=drows)
         dep_cpu_s = time.perf_counter() - t1
         swarm = swarm_measure(T, torch)
+        large = None
+        if args.st_eval_mp > 0:
+            big = surrogate.Instance(beams.st_headon(args.st_eval_mp))
+            big.surrogate(ctx, net, p)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                rbig = big.surrogate(ctx, net, p)
+            torch.cuda.synchronize()
+            t_big = (time.perf_counter() - t1) / max(args.steps, 1)
+            nb = args.st_eval_mp
+            big_exact = None
+            if args.st_eval_exact:
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                _, big_exact = big.exact(ctx, cap_log2=24)
+                torch.cuda.synchronize()
+                t_big_exact = time.perf_counter() - t1
+            large = {"macro_particles_per_beam": nb, "ms": 1e3 * t_big,
+                     "exact_total": big_exact,
+                     "exact_ms": 1e3 * t_big_exact if big_exact is not None else None,
+                     "rel_error_vs_exact": (abs(rbig["total"] - big_exact) / big_exact
+                                            if big_exact else None),
+                     "queries_per_s": float(nb) * nb * 400 / t_big, "total": rbig["total"],
+                     "rel_diff_vs_exact_at_training_size": abs(rbig["total"] - exact_total) / exact_total,
+                     "bin_pairs": rbig["n_bin_pairs"], "bin_pairs_exact": rbig["n_gated"],
+                     "predicted_spread": rbig["predicted_spread"]}
+            del big
     finally:
         net.close()
         ctx.close()
@@ -209,6 +237,7 @@ def st_bench(args):
                                           "kind": "oracle", "cores": _oracle_threads(),
                                           "sample": "20 query rows x all target clouds x 400 steps"}},
         "ip_swarm": swarm,
+        "surrogate_large": large,
         "exact": {"queries_per_s": q / t_exact, "ms": 1e3 * t_exact, "total": exact_total,
                   "cloud_pair_steps_per_run": st["n_candidates"] // max(args.steps + args.warmup, 1)},
     }
@@ -435,6 +464,11 @@ def main():
     ap.add_argument("--st-mp", type=int, default=200_000,
                     help="st_headon: macro-particles per beam")
     ap.add_argument("--st-train", type=int, default=8, help="st_headon: training instances")
+    ap.add_argument("--st-eval-mp", type=int, default=0,
+                    help="st_headon: also run the surrogate on an instance of this many "
+                         "macro-particles per beam (same physical beams)")
+    ap.add_argument("--st-eval-exact", action="store_true",
+                    help="st_headon: also run the exact path once on the --st-eval-mp instance")
     ap.add_argument("--st-dep-mp", type=int, default=20_000,
                     help="st_headon: macro-particles per beam of the depletion measurement")
     ap.add_argument("--st-dep-physical", type=float, default=1e20,
