@@ -114,3 +114,44 @@ def test_set_tune_rejects_bad_values(torch, bad):
         assert e.value.code == T.TRIL_E_INVAL
     finally:
         ctx.close()
+
+
+def test_batch64_full_size_sampled_rows(torch):
+    """The full batched workload (64 instances at their drawn sizes, calibrated weights, 400
+    steps, the benchmark's launch configuration): per instance, up to two colliding and two
+    random query rows, every pair of those rows against the oracle."""
+    from oracle import oracle as O
+    parts_a, parts_b = [], []
+    for m in range(beams.BATCH64_INSTANCES):
+        A_m, B_m = beams.draw_pair(beams.batch64_instance(m))
+        parts_a.append(A_m)
+        parts_b.append(B_m)
+    A, offA = beams.concat(parts_a)
+    B, offB = beams.concat(parts_b)
+    ctx = T.Context(0.1, EDGES)
+    try:
+        tb, qb = T.Beam(B, offB), T.Beam(A, offA)
+        pairs = T.Pairs(1 << 21)
+        T.run_steps(ctx, tb, qb, 400, pairs, graph=True)
+        st = ctx.stats(pairs)
+        i, j, k = pairs.numpy()
+    finally:
+        ctx.close()
+    assert st["n_pairs"] > 50_000
+    rng = np.random.default_rng(4)
+    rows_per_inst, chosen = [], []
+    for m in range(len(offA) - 1):
+        a0, a1 = int(offA[m]), int(offA[m + 1])
+        hit = np.unique(i[(i >= a0) & (i < a1)]) - a0
+        pick = list(rng.choice(hit, min(2, len(hit)), replace=False)) if len(hit) else []
+        pick += list(rng.choice(a1 - a0, min(2, a1 - a0), replace=False))
+        loc = np.unique(np.array(pick, dtype=np.int64))
+        rows_per_inst.append(loc)
+        chosen.append(loc + a0)
+    raw, S = O.run_instances(A, offA, B, offB, 0.1, 400, EDGES, rows_per_inst=rows_per_inst)
+    assert raw.knife_margin == 0 and raw.knife_s == 0
+    keep = np.isin(i, np.concatenate(chosen))
+    assert keep.sum() > 64
+    assert np.array_equal(i[keep], S.i)
+    assert np.array_equal(j[keep], S.j)
+    assert np.array_equal(k[keep], S.first_step)
