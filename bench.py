@@ -119,9 +119,10 @@ def st_bench(args):
     net = T.Mlp(4, seed=11)
     try:
         t0 = time.perf_counter()
-        insts = [surrogate.Instance(beams.st_headon(args.st_mp, seed=2000 + m))
+        train_mp = [int(v) for v in args.st_train_mp.split(",") if v] or [args.st_mp]
+        insts = [surrogate.Instance(beams.st_headon(train_mp[m % len(train_mp)], seed=2000 + m))
                  for m in range(args.st_train)]
-        x, t, y0, y = surrogate.training_rows(ctx, insts, eps=eps)
+        x, t, y0, y = surrogate.training_rows(ctx, insts, eps=eps, log=_progress)
         g = torch.Generator(device="cuda")
         g.manual_seed(0)
         keep = (y > 0) | (torch.rand(y.shape[0], device="cuda", generator=g) < 0.25)
@@ -189,6 +190,7 @@ def st_bench(args):
             nb = args.st_eval_mp
             big_exact = None
             if args.st_eval_exact:
+                _progress(f"exact path on {nb} macro-particles per beam")
                 torch.cuda.synchronize()
                 t1 = time.perf_counter()
                 _, big_exact = big.exact(ctx, cap_log2=24)
@@ -219,6 +221,7 @@ def st_bench(args):
                    "physical_photons_per_beam": 1e9, "time_steps": 400,
                    "grid": "32^3 cells (surrogate on cell pairs)", "ensemble": 4,
                    "training": {"instances": args.st_train, "rows": n_rows,
+                             "macro_particles": args.st_train_mp or args.st_mp,
                                 "adam_steps": args.st_train_steps, "seconds": round(train_s, 1),
                                 "yield_scale": round(scale, 5)}},
         "surrogate": {"queries_per_s": q / t_sur, "ms": 1e3 * t_sur, "total": res["total"],
@@ -242,6 +245,11 @@ def st_bench(args):
                   "cloud_pair_steps_per_run": st["n_candidates"] // max(args.steps + args.warmup, 1)},
     }
     print(json.dumps(out), flush=True)
+
+
+def _progress(msg):
+    """A progress line on stderr (long statistical-regime runs)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _oracle_threads():
@@ -464,6 +472,9 @@ def main():
     ap.add_argument("--st-mp", type=int, default=200_000,
                     help="st_headon: macro-particles per beam")
     ap.add_argument("--st-train", type=int, default=8, help="st_headon: training instances")
+    ap.add_argument("--st-train-mp", default="",
+                    help="st_headon: comma-separated macro-particle counts the training instances "
+                         "cycle through (default: --st-mp for all)")
     ap.add_argument("--st-eval-mp", type=int, default=0,
                     help="st_headon: also run the surrogate on an instance of this many "
                          "macro-particles per beam (same physical beams)")

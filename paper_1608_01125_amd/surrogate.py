@@ -43,8 +43,12 @@ class Instance:
         self.qbins, self.qsums = bin_device(self.qa, self.ga)
         self.tbins, self.tsums = bin_device(self.tb, self.gb)
 
-    def exact(self, ctx: T.Context, cap_log2: int = 22):
-        """Exact cell-pair yields (table) and their total."""
+    def exact(self, ctx: T.Context, cap_log2: int = 0):
+        """Exact cell-pair yields (table) and their total. cap_log2 = 0: a table size that
+        grows with the instance (2^22 slots up to 2.5e5 macro-particles per beam, 2^24
+        above)."""
+        if cap_log2 <= 0:
+            cap_log2 = 22 if self.wl.a.n <= 250_000 else 24
         tab = T.StTable(cap_log2)
         tot = T.tril_st_exact(ctx, self.tb, self.tbins, self.gb.n_bins, self.qa, self.qbins,
                               self.ga.cell, 0, self.wl.n_steps, tab)
@@ -66,13 +70,15 @@ class Instance:
                                    self.qbins, self.qsums, self.ga, 0, self.wl.n_steps, params)
 
 
-def training_rows(ctx: T.Context, insts: List[Instance], eps: float = 1e-3):
+def training_rows(ctx: T.Context, insts: List[Instance], eps: float = 1e-3, log=None):
     """Features and targets log((Y + eps Y0) / Y0) of every candidate cell pair of the
     instances, concatenated on the device, with their Y0 and exact Y."""
     import torch
     xs, ts, y0s, ys = [], [], [], []
-    for inst in insts:
+    for n, inst in enumerate(insts):
         tab, _ = inst.exact(ctx)
+        if log is not None:
+            log(f"training instance {n + 1}/{len(insts)}: exact yields done")
         x, y0, key = inst.features(ctx, T.sur_params(eps=eps))
         t, y = T.tril_st_targets(key, y0, tab, eps)
         xs.append(x), ts.append(t), y0s.append(y0), ys.append(y)
