@@ -638,33 +638,38 @@ __device__ __forceinline__ void climb_crossing(int32_t cur, Half cn, i32x4 r, bo
     }
 }
 
-// Bottom-up box refit for the m steps that share one tree shape. A workgroup owns a
-// chunk of consecutive leaves (sorted positions) for all m steps: the chunk's parent
-// records are staged in LDS and each leaf's photon is read once, and every step's leaf
-// boxes are computed from it in registers, so a step costs no global traffic but its
-// node stores. Every node writes its box and link into its half of its parent. Every
-// internal node whose leaf range lies inside the chunk has its id in the chunk too (a
-// node's id is one end of its range); the arrival flag and the box of such a node
-// live in LDS, and the second child to arrive merges the boxes there. A node whose
-// parent crosses the chunk boundary is stored and handed to the crossing-level kernel
-// through the (step, chunk) slots (the climb above it needs device atomics and
-// coherent loads whose latency would otherwise stall this LDS-heavy workgroup); with
-// the slots full, or none given, the thread climbs on itself.
-__global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cloud, double dt,
-                                                       const uint32_t *__restrict__ rows,
-                                                       int64_t chunks, int32_t group_steps,
-                                                       const PRec *__restrict__ prec,
-                                                       int32_t *flags, Node *nodes,
-                                                       int32_t *__restrict__ slots,
-                                                       const DevCounters *__restrict__ cnt,
-                                                       unsigned int *err) {
-    // boxes (lo, hi as two float4) of the chunk's leaves and of its internal nodes
-    __shared__ float4 s_leaf[2][kRefitChunk];
-    __shared__ float4 s_int[2][kRefitChunk];
-    __shared__ int32_t s_flag[kRefitChunk];
-    // records: [0, chunk) the chunk's leaves, [chunk, 2 chunk) internal ids in the chunk
-    __shared__ i32x4 s_rec[2 * kRefitChunk];
-    __shared__ int32_t s_nslot;
+// Bottom-up box refit for the m steps that share one tree shape, level by level. A
+// workgroup owns a chunk of consecutive leaves (sorted positions) for a group of steps.
+// The shape is the same for every step, so the chunk's part of it is read once: the
+// children of every internal node whose leaf range lies in the chunk (such a node's id
+// is one end of its range, so it is in the chunk too), each such node's height above
+// its leaves, and the chunk's top nodes (leaves or internal nodes whose parent's range
+// leaves the chunk). Each leaf's photon is read once and kept in registers. Per step,
+// the leaves' boxes are formed, then the heights 1, 2, ... are merged one after the
+// other with a barrier between them (each node merges its two children's halves held in
+// LDS; no flags or atomics), and the chunk's complete nodes are written whole, with
+// consecutive lanes storing consecutive 16-byte words. Every top node's half goes into
+// its parent, which the crossing-level kernel finishes through the (step, chunk) slots;
+// with the slots full, or none given, the thread climbs on itself. Merges are exact
+// (min, max), so the boxes do not depend on the order of merging.
+__global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cloud, double dt,
+                                                    const uint32_t *__restrict__ rows,
+                                                    int64_t chunks, int32_t group_steps,
+                                                    const PRec *__restrict__ prec,
+                                                    int32_t *flags, Node *nodes,
+                                                    int32_t *__restrict__ slots,
+                                                    const DevCounters *__restrict__ cnt,
+                                                    unsigned int *err) {
+    // halves of the chunk's nodes as their parents hold them, lo (xyz, link) and hi
+    // (xyz, energy bound): [0, chunk) internal node c0 + k, [chunk, 2 chunk) leaf c0 + k
+    // (before the first step the same memory holds the nodes' heights)
+    __shared__ float4 s_lo[2 * kRefitChunk];
+    __shared__ float4 s_hi[2 * kRefitChunk];
+    // half indices of the children of internal node c0 + k (-1: its range leaves the chunk)
+    __shared__ int2 s_child[kRefitChunk];
+    __shared__ int16_t s_top[2 * kRefitChunk];  // half indices of the top nodes
+    __shared__ int32_t s_ntop, s_hmax;
+    int32_t *s_height = reinterpret_cast<int32_t *>(s_lo);  // [0, 2 chunk): as the halves
     const i32x4 *grec = reinterpret_cast<const i32x4 *>(prec);
     const int64_t n = b.n;
     // workgroup: chunk `chunk` for the steps of group `group`
@@ -674,9 +679,68 @@ __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cl
     const int64_t c0 = chunk * kRefitChunk;
     const int64_t c1 = (c0 + kRefitChunk < n ? c0 + kRefitChunk : n) - 1;  // last leaf of the chunk
     const int64_t leaf0 = n - 1;
+    // internal nodes with ids in the chunk: c0 .. c0 + n_int - 1 (ids stop at n - 2)
+    const int32_t n_int = (int32_t)(leaf0 - c0 < kRefitChunk ? leaf0 - c0 : kRefitChunk);
     const int tid = threadIdx.x;
     const int64_t j = c0 + tid;
-    const bool in = j < n;
+    const bool in = j < n;           // this thread's leaf c0 + tid exists
+    const bool has_int = tid < n_int;  // and internal node c0 + tid
+
+    // ---- the chunk's part of the shape
+    s_child[tid] = make_int2(-1, -1);
+    s_height[tid] = -1;
+    s_height[kRefitChunk + tid] = 0;
+    if (tid == 0) {
+        s_ntop = 0;
+        s_hmax = 0;
+    }
+    i32x4 rl = {-1, 0, 0, 0}, ri = {-1, 0, 0, 0};
+    if (in) rl = grec[leaf0 + j];
+    if (has_int) ri = grec[j];
+    // the parent of a node lies in the chunk iff the parent's range does
+    const bool pin_l = in && rl.x >= 0 && rl.z >= c0 && rl.w <= c1;
+    const bool pin_i = has_int && ri.x >= 0 && ri.z >= c0 && ri.w <= c1;
+    __syncthreads();
+    if (pin_l) {
+        int *ch = reinterpret_cast<int *>(&s_child[rl.x - c0]);
+        ch[rl.y < 0 ? 1 : 0] = kRefitChunk + tid;
+    }
+    if (pin_i) {
+        int *ch = reinterpret_cast<int *>(&s_child[ri.x - c0]);
+        ch[ri.y < 0 ? 1 : 0] = tid;
+    }
+    __syncthreads();
+    const bool inside = has_int && s_child[tid].x >= 0;  // node c0 + tid lies in the chunk
+    if (in && !pin_l) s_top[atomicAdd(&s_ntop, 1)] = (int16_t)(kRefitChunk + tid);
+    if (inside && !pin_i) s_top[atomicAdd(&s_ntop, 1)] = (int16_t)tid;
+    // heights: a node is resolved once both children are; at least one node resolves
+    // per round in a well-formed tree, so the rounds stop by the chunk's height + 1
+    int32_t myh = inside ? -1 : 0;
+    for (int round = 0;; ++round) {
+        bool pending = myh < 0;
+        if (pending) {
+            const int2 ch = s_child[tid];
+            const int32_t ha = s_height[ch.x], hb = s_height[ch.y];
+            if (ha >= 0 && hb >= 0) {
+                myh = 1 + (ha > hb ? ha : hb);
+                s_height[tid] = myh;
+                pending = false;
+            }
+        }
+        __syncthreads();
+        if (!__syncthreads_or(pending)) break;
+        if (round > kRefitChunk) {  // uniform: the tree is malformed; merge and hand off nothing
+            if (tid == 0) {
+                atomicOr(err, kErrSpin);
+                s_ntop = 0;
+            }
+            myh = 0;
+            break;
+        }
+    }
+    if (myh > 0) atomicMax(&s_hmax, myh);
+
+    // ---- the leaf's photon, read once for all steps of the group
     uint32_t row = 0;
     RowPhoton ph;
     ph.ok = false;
@@ -684,87 +748,64 @@ __global__ void __launch_bounds__(kRefitChunk, 6) k_refit(BeamDev b, CloudBox cl
     float eup = 0.0f;  // the leaf's energy rounded up: the subtree bound of the prune
     if (in) {
         row = rows[j];
-        s_rec[tid] = grec[leaf0 + j];
-        s_rec[kRefitChunk + tid] = (j < leaf0) ? grec[j] : i32x4{0, 0, 0, 0};
         double E, w;
         ph = load_photon(b, row, E, w);
         eup = ph.ok ? f32_up(E) : 0.0f;
     }
+    __syncthreads();
+    const int32_t H = s_hmax, ntop = s_ntop;
     const unsigned step0 = cnt->step;
     for (int32_t step = s_begin; step < s_end; ++step) {
-        s_flag[tid] = 0;
-        if (tid == 0) s_nslot = 0;
         int32_t *slot = slots ? slots + ((int64_t)step * chunks + chunk) * kRefitSlots : nullptr;
         if (slot != nullptr && tid < kRefitSlots) slot[tid] = -1;
-        Half cn;  // box and link of `cur` as its parent holds them, not yet stored
-        int32_t cur = -1;
         if (in) {
             float lo[3], hi[3], cen[3];
             photon_box(ph, (double)(step0 + (unsigned)step) * dt, dt, cloud, 0.0, lo, hi, cen);
-            cn.lox = lo[0]; cn.loy = lo[1]; cn.loz = lo[2];
-            cn.hix = hi[0]; cn.hiy = hi[1]; cn.hiz = hi[2];
-            cn.link = leaf_link((int64_t)step * n + row);
-            cn.pad = __float_as_int(eup);
-            cur = (int32_t)(leaf0 + j);
-            s_leaf[0][tid] = make_float4(cn.lox, cn.loy, cn.loz, 0.0f);
-            s_leaf[1][tid] = make_float4(cn.hix, cn.hiy, cn.hiz, eup);
+            s_lo[kRefitChunk + tid] =
+                make_float4(lo[0], lo[1], lo[2], __int_as_float(leaf_link((int64_t)step * n + row)));
+            s_hi[kRefitChunk + tid] = make_float4(hi[0], hi[1], hi[2], eup);
         }
         __syncthreads();
+        const int32_t base = step_node(c0, step, n);  // node c0 + k of the step: base + k
+        for (int32_t h = 1; h <= H; ++h) {
+            if (myh == h) {
+                const int2 ch = s_child[tid];
+                const float4 alo = s_lo[ch.x], ahi = s_hi[ch.x];
+                const float4 blo = s_lo[ch.y], bhi = s_hi[ch.y];
+                s_lo[tid] = make_float4(fminf(alo.x, blo.x), fminf(alo.y, blo.y),
+                                        fminf(alo.z, blo.z), __int_as_float(base + tid));
+                s_hi[tid] = make_float4(fmaxf(ahi.x, bhi.x), fmaxf(ahi.y, bhi.y),
+                                        fmaxf(ahi.z, bhi.z), fmaxf(ahi.w, bhi.w));
+            }
+            __syncthreads();
+        }
+        // complete nodes, whole: word f of the chunk's node block is quarter f % 4 of node
+        // c0 + f / 4 (lo, hi of the left child, then of the right child)
+        float4 *dst = reinterpret_cast<float4 *>(nodes + base);
+        for (int32_t f = tid; f < 4 * n_int; f += kRefitChunk) {
+            const int2 ch = s_child[f >> 2];
+            const int32_t c = (f & 2) ? ch.y : ch.x;
+            if (c >= 0) dst[f] = (f & 1) ? s_hi[c] : s_lo[c];
+        }
+        // top nodes: their halves go into their parents (none for the root)
         int32_t *sflags = flags + (int64_t)step * (n - 1);
-        // Inside the chunk: cur is one of the chunk's leaves (first level) or an internal
-        // node with its id in the chunk, so its record is in LDS. done: this thread's
-        // climb for the step is over (first to arrive somewhere, or the root reached).
-        bool done = !in;
-        i32x4 r = {0, 0, 0, 0};
-        if (in) r = s_rec[tid];  // cur is this thread's leaf
-        while (!done) {
-            const int32_t p = r.x;
-            if (p < 0) {  // cur is the root
-                done = true;
-                break;
+        for (int32_t t = tid; t < ntop; t += kRefitChunk) {
+            const int32_t hs = s_top[t];
+            const int32_t id = (int32_t)(hs >= kRefitChunk ? leaf0 + c0 + (hs - kRefitChunk) : c0 + hs);
+            const i32x4 r = grec[id];
+            if (r.x < 0) continue;
+            const float4 lo = s_lo[hs], hi = s_hi[hs];
+            Half cn;
+            cn.lox = lo.x; cn.loy = lo.y; cn.loz = lo.z; cn.link = __float_as_int(lo.w);
+            cn.hix = hi.x; cn.hiy = hi.y; cn.hiz = hi.z; cn.pad = __float_as_int(hi.w);
+            if (slot != nullptr && t < kRefitSlots) {
+                store_half_plain(&nodes[step_node(r.x, step, n)].c[r.y < 0 ? 1 : 0], cn);
+                slot[t] = id;
+            } else {
+                climb_crossing(id, cn, r, false, step, n, grec, sflags, nodes, err);
             }
-            const int32_t plo = r.z, phi = r.w;
-            if (!(plo >= c0 && phi <= c1)) break;  // the parent crosses the chunk
-            const int side = r.y < 0 ? 1 : 0;
-            const int32_t sib = (int32_t)((uint32_t)r.y & 0x7fffffffu);
-            // the parent's record (its id lies in the chunk), read ahead of the arrival
-            const i32x4 rp = s_rec[kRefitChunk + (p - c0)];
-            store_half_plain(&nodes[step_node(p, step, n)].c[side], cn);
-            if (cur < leaf0) {
-                const int64_t k = cur - c0;
-                s_int[0][k] = make_float4(cn.lox, cn.loy, cn.loz, 0.0f);
-                s_int[1][k] = make_float4(cn.hix, cn.hiy, cn.hiz, __int_as_float(cn.pad));
-            }
-            // the sibling's thread reads this box from LDS only: order LDS accesses
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-            const int32_t old = atomicAdd(&s_flag[p - c0], 1);
-            if (old == 0) {  // the sibling subtree is not finished; its thread continues
-                done = true;
-                break;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-            const bool sleaf = sib >= leaf0;
-            const int64_t k = sleaf ? sib - leaf0 - c0 : sib - c0;
-            const float4 blo = sleaf ? s_leaf[0][k] : s_int[0][k];
-            const float4 bhi = sleaf ? s_leaf[1][k] : s_int[1][k];
-            const float slo[3] = {blo.x, blo.y, blo.z}, shi[3] = {bhi.x, bhi.y, bhi.z};
-            cn = merge_halves(cn, slo, shi, bhi.w, step_node(p, step, n));
-            cur = p;
-            r = rp;
         }
-        if (!done) {  // the parent of cur crosses the chunk
-            bool handed = false;
-            if (slot != nullptr) {
-                const int k = atomicAdd(&s_nslot, 1);
-                if (k < kRefitSlots) {
-                    store_half_plain(&nodes[step_node(r.x, step, n)].c[r.y < 0 ? 1 : 0], cn);
-                    slot[k] = cur;
-                    handed = true;
-                }
-            }
-            if (!handed) climb_crossing(cur, cn, r, false, step, n, grec, sflags, nodes, err);
-        }
-        __syncthreads();  // the chunk's LDS boxes and flags are reused by the next step
+        __syncthreads();  // the chunk's LDS halves are reused by the next step
     }
 }
 
