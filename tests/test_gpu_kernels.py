@@ -273,6 +273,53 @@ def test_batched_tree_copies_and_instance_roots(torch):
     _check_boxes(tree, boxes)
 
 
+def _degenerate_beam(kind, n, seed=31):
+    B = beams.head(beams.draw_pair(beams.gauss_headon_1m(n=max(n, 2), seed=seed))[1], n)
+    if kind == "same_point":  # every key equal: the emission splits by index alone
+        for k in ("x", "y", "z"):
+            B[k][:] = B[k][0]
+    elif kind == "geometric":  # positions halving toward one point: a deep, skewed tree
+        f = 2.0 ** -(np.arange(n) % 40)
+        for k in ("x", "y", "z"):
+            B[k][:] = B[k][0] + 3.0 * f
+    return B
+
+
+@pytest.mark.parametrize("kind", ["same_point", "geometric", "gauss"])
+@pytest.mark.parametrize("n", [513, 1025, 1500])
+def test_tree_invariants_degenerate_shapes(torch, kind, n):
+    """The chunked refit on trees of awkward shape: a last chunk of one leaf (513 rows),
+    ragged chunks, all keys equal, and a deep skewed tree; one step per build and a batch
+    of 7 steps sharing one shape. Every node is reached once from the root and every box
+    is the photon's box or the exact union of its children."""
+    B = _degenerate_beam(kind, n)
+    wl = beams.gauss_headon_1m(n=1000)
+    ctx = T.Context(wl.dt)
+    tb = T.Beam(B)
+    ctx.build(tb, 170)
+    tree = T.tril_dbg_tree(ctx, n)
+    boxes = T.tril_dbg_boxes(ctx, 0, n)
+    ctx.close()
+    seen, leaves = _walk(tree, 0, n - 1)
+    assert np.all(seen == 1)
+    assert np.array_equal(np.sort(leaves), np.arange(n))
+    _check_boxes(tree, boxes)
+    m = 7
+    ctx = T.Context(wl.dt, step_batch=m)
+    tb = T.Beam(B)
+    pairs = T.Pairs(1 << 12)
+    ctx.run(tb, tb, 170, m, pairs)
+    tree = T.tril_dbg_tree(ctx, n, 1, m)
+    boxes = T.tril_dbg_boxes(ctx, 0, m * n)
+    ctx.close()
+    for s in range(m):
+        r = int(tree["roots"][s])
+        assert r == s * (n - 1)
+        _, leaves = _walk(tree, r, m * (n - 1))
+        assert np.array_equal(np.sort(leaves), np.arange(n) + s * n)
+    _check_boxes(tree, boxes)
+
+
 def test_boxes_contain_swept_segments(torch):
     wl, A, B = _small_beams(n=2000)
     step = 150
