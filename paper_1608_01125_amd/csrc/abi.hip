@@ -144,6 +144,7 @@ struct tril_ctx {
     int32_t *inst_base = nullptr;          // instance roots of the shared tree shape
     PBox *root_box = nullptr;              // boxes of combined instances of one row
     int32_t *refit_slots = nullptr;        // refit hand-offs to the crossing-level kernel
+    int32_t *xlev = nullptr;               // crossing levels of the shape (batches of many steps)
     int64_t refit_slot_cap = 0;
     int64_t n_int = -1;                    // internal nodes of the last build (all steps)
     int32_t tgt_k0 = 0;                    // first step of the last build
@@ -238,7 +239,7 @@ void free_target(tril_ctx *c) {
 void free_target_rows(tril_ctx *c) {
     dev_free(c->t_spart); dev_free(c->t_k32a); dev_free(c->t_k32b);
     dev_free(c->t_k64a); dev_free(c->t_k64b); dev_free(c->t_va); dev_free(c->t_vb);
-    dev_free(c->prec);
+    dev_free(c->prec); dev_free(c->xlev);
     c->t_row_cap = 0;
 }
 
@@ -271,6 +272,7 @@ int ensure_target(tril_ctx *c, int64_t nv, int64_t n, int64_t n_comb, int32_t n_
         CHK(dev_alloc(&c->t_k64a, m)); CHK(dev_alloc(&c->t_k64b, m));
         CHK(dev_alloc(&c->t_va, m)); CHK(dev_alloc(&c->t_vb, m));
         CHK(dev_alloc(&c->prec, 2 * m));
+        CHK(dev_alloc(&c->xlev, (size_t)xlevel_ints(m)));
         c->t_row_cap = m;
     }
     if (n_comb > c->t_comb_cap) {
@@ -502,8 +504,14 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
     c->tgt_cloud = c->cloud;
     launch_inst_roots(t, c->cloud, c->dt, c->inst_base, rows, c->inst_root, c->root_box, c->d_cnt,
                       st);
+    int32_t *xbase = nullptr;
+    bool xalt = false;
+    if (refit_by_levels(n, t.m)) {
+        xbase = c->xlev;
+        xalt = enqueue_xlevels(c->prec, n, xbase, c->ss, &c->d_cnt->err, st);
+    }
     launch_refit(t, c->cloud, c->dt, rows, c->prec, c->nflags, c->nodes, c->refit_slots,
-                 c->refit_slot_cap, c->d_cnt, &c->d_cnt->err, st);
+                 c->refit_slot_cap, xbase, xalt, c->d_cnt, &c->d_cnt->err, st);
     if (timed) CHK(timing_pair(c, st, c->ev_build, false));
     HIPCHK(hipGetLastError());
     return TRIL_OK;

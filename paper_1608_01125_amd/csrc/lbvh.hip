@@ -649,8 +649,9 @@ __device__ __forceinline__ void climb_crossing(int32_t cur, Half cn, i32x4 r, bo
 // other with a barrier between them (each node merges its two children's halves held in
 // LDS; no flags or atomics), and the chunk's complete nodes are written whole, with
 // consecutive lanes storing consecutive 16-byte words. Every top node's half goes into
-// its parent, which the crossing-level kernel finishes through the (step, chunk) slots;
-// with the slots full, or none given, the thread climbs on itself. Merges are exact
+// its parent. The levels above are finished either level by level for all steps of the
+// batch (store_only: the halves are only stored), or by the crossing-level climb through
+// the (step, chunk) slots; with the slots full, or none given, the thread climbs on itself. Merges are exact
 // (min, max), so the boxes do not depend on the order of merging.
 __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cloud, double dt,
                                                     const uint32_t *__restrict__ rows,
@@ -658,6 +659,7 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
                                                     const PRec *__restrict__ prec,
                                                     int32_t *flags, Node *nodes,
                                                     int32_t *__restrict__ slots,
+                                                    int32_t store_only,
                                                     const DevCounters *__restrict__ cnt,
                                                     unsigned int *err) {
     // halves of the chunk's nodes as their parents hold them, lo (xyz, link) and hi
@@ -798,7 +800,9 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
             Half cn;
             cn.lox = lo.x; cn.loy = lo.y; cn.loz = lo.z; cn.link = __float_as_int(lo.w);
             cn.hix = hi.x; cn.hiy = hi.y; cn.hiz = hi.z; cn.pad = __float_as_int(hi.w);
-            if (slot != nullptr && t < kRefitSlots) {
+            if (store_only) {  // the crossing levels are merged level by level afterwards
+                store_half_plain(&nodes[step_node(r.x, step, n)].c[r.y < 0 ? 1 : 0], cn);
+            } else if (slot != nullptr && t < kRefitSlots) {
                 store_half_plain(&nodes[step_node(r.x, step, n)].c[r.y < 0 ? 1 : 0], cn);
                 slot[t] = id;
             } else {
@@ -830,6 +834,129 @@ __global__ void __launch_bounds__(256) k_refit_top(const int32_t *__restrict__ s
     cn.lox = a.x; cn.loy = a.y; cn.loz = a.z; cn.link = __float_as_int(a.w);
     cn.hix = b.x; cn.hiy = b.y; cn.hiz = b.z; cn.pad = __float_as_int(b.w);
     climb_crossing(cur, cn, r, true, step, n, grec, flags + (int64_t)step * (n - 1), nodes, err);
+}
+
+// ---------------------------------------------- crossing levels, level by level
+// The internal nodes whose leaf range crosses a chunk boundary ("crossing" nodes) are the
+// same for every step of a batch, and every ancestor of one is one too. Once per batch:
+// mark them (a node's record holds its parent's range), give each its depth (parent
+// records followed up to the root: plain loads, no atomics) and sort them by depth.
+// Then one workgroup per step merges them from the deepest level up with a block barrier
+// between levels (a node's crossing children lie one level deeper): plain loads of both
+// halves of a node (stored by the chunk refit or by a deeper level of the same
+// workgroup) and a plain store of the merged half into the parent.
+constexpr int kXLevels = 120;       // a radix tree over (key, index) pairs is at most 96 deep
+constexpr uint32_t kXNone = 255u;   // sort key of a node that does not cross
+constexpr int kXThreads = 1024;
+constexpr int kXUnroll = 4;
+constexpr int32_t kXMinSteps = 32;  // fewer steps per batch leave too few workgroups
+
+struct XLev {
+    int32_t *flag;
+    uint32_t *ka, *kb, *va, *vb;
+    int32_t *start;  // [0, kXLevels + 2): first sorted position of each depth
+};
+
+__host__ __device__ inline XLev xlev_layout(int32_t *base, int64_t n) {
+    const int64_t N = n > 1 ? n - 1 : 1;
+    XLev x;
+    x.flag = base;
+    x.ka = reinterpret_cast<uint32_t *>(base + N);
+    x.kb = reinterpret_cast<uint32_t *>(base + 2 * N);
+    x.va = reinterpret_cast<uint32_t *>(base + 3 * N);
+    x.vb = reinterpret_cast<uint32_t *>(base + 4 * N);
+    x.start = base + 5 * N;
+    return x;
+}
+
+__global__ void k_xclear(XLev x, int64_t n_int) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n_int) x.flag[i] = 0;
+}
+
+// v: every node but the root (internal v < n - 1, leaf n - 1 + j)
+__global__ void k_xmark(const PRec *__restrict__ prec, int64_t n, XLev x) {
+    const int64_t v = 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (v >= 2 * n - 1) return;
+    const i32x4 r = reinterpret_cast<const i32x4 *>(prec)[v];
+    if (r.x >= 0 && r.z / kRefitChunk != r.w / kRefitChunk) x.flag[r.x] = 1;
+}
+
+// sort key of internal node i: its depth if it crosses, else kXNone
+__global__ void k_xdepth(const PRec *__restrict__ prec, XLev x, int64_t n_int, unsigned int *err) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_int) return;
+    uint32_t k = kXNone;
+    if (x.flag[i] != 0) {
+        const i32x4 *grec = reinterpret_cast<const i32x4 *>(prec);
+        int32_t p = (int32_t)i, d = 0;
+        while ((p = grec[p].x) >= 0) {
+            if (++d > kXLevels) {
+                atomicOr(err, kErrSpin);
+                d = 0;
+                break;
+            }
+        }
+        k = (uint32_t)d;
+    }
+    x.ka[i] = k;
+    x.va[i] = (uint32_t)i;
+}
+
+// start[d] = first sorted position with depth >= d, for d in [0, kXLevels + 1] (the last:
+// where the nodes that do not cross begin, or the end); each entry is written once
+__global__ void k_xbounds(const uint32_t *__restrict__ key, int64_t n_int, XLev x) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_int) return;
+    constexpr int32_t top = kXLevels + 1;
+    const int32_t k = key[i] < (uint32_t)top ? (int32_t)key[i] : top;
+    const int32_t kp = i == 0 ? -1 : (key[i - 1] < (uint32_t)top ? (int32_t)key[i - 1] : top);
+    for (int32_t d = kp + 1; d <= k; ++d) x.start[d] = (int32_t)i;
+    if (i == n_int - 1)
+        for (int32_t d = k + 1; d <= top; ++d) x.start[d] = (int32_t)n_int;
+}
+
+__global__ void __launch_bounds__(kXThreads) k_refit_levels(const uint32_t *__restrict__ order,
+                                                          const int32_t *__restrict__ start,
+                                                          const PRec *__restrict__ prec, int64_t n,
+                                                          Node *nodes) {
+    const int32_t step = blockIdx.x;
+    const i32x4 *grec = reinterpret_cast<const i32x4 *>(prec);
+    const int tid = threadIdx.x;
+    for (int32_t d = kXLevels; d >= 0; --d) {
+        const int32_t a = start[d], e = start[d + 1];
+        if (a >= e) continue;  // uniform: no node at this depth
+        for (int32_t i0 = a + tid; i0 < e; i0 += kXUnroll * kXThreads) {
+            int32_t id[kXUnroll];
+            float4 q[kXUnroll][4];
+#pragma unroll
+            for (int u = 0; u < kXUnroll; ++u) {
+                const int32_t i = i0 + u * kXThreads;
+                id[u] = i < e ? (int32_t)order[i] : -1;
+                if (id[u] >= 0) {
+                    const float4 *np = reinterpret_cast<const float4 *>(nodes + step_node(id[u], step, n));
+                    q[u][0] = np[0]; q[u][1] = np[1]; q[u][2] = np[2]; q[u][3] = np[3];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kXUnroll; ++u) {
+                if (id[u] < 0) continue;
+                const i32x4 r = grec[id[u]];
+                if (r.x < 0) continue;  // the root: its box is kept nowhere
+                Half cn;
+                cn.lox = fminf(q[u][0].x, q[u][2].x);
+                cn.loy = fminf(q[u][0].y, q[u][2].y);
+                cn.loz = fminf(q[u][0].z, q[u][2].z);
+                cn.link = step_node(id[u], step, n);
+                cn.hix = fmaxf(q[u][1].x, q[u][3].x);
+                cn.hiy = fmaxf(q[u][1].y, q[u][3].y);
+                cn.hiz = fmaxf(q[u][1].z, q[u][3].z);
+                cn.pad = __float_as_int(fmaxf(q[u][1].w, q[u][3].w));
+                store_half_plain(&nodes[step_node(r.x, step, n)].c[r.y < 0 ? 1 : 0], cn);
+            }
+        }
+        __syncthreads();  // the next level up reads what this one stored
+    }
 }
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
@@ -943,24 +1070,48 @@ int64_t refit_slots_needed(int64_t n, int32_t m) {
     return chunks > 1 ? chunks * m * kRefitSlots : 0;
 }
 
+bool refit_by_levels(int64_t n, int32_t m) { return m >= kXMinSteps && n > kRefitChunk; }
+
+int64_t xlevel_ints(int64_t n) { return 5 * (n > 1 ? n - 1 : 1) + kXLevels + 2; }
+
+bool enqueue_xlevels(const PRec *prec, int64_t n, int32_t *base, const SortScratch &ss,
+                     unsigned int *err, hipStream_t st) {
+    const XLev x = xlev_layout(base, n);
+    const int64_t n_int = n - 1;
+    hipLaunchKernelGGL(k_xclear, dim3(grid_for(n_int, 256)), dim3(256), 0, st, x, n_int);
+    hipLaunchKernelGGL(k_xmark, dim3(grid_for(2 * n - 2, 256)), dim3(256), 0, st, prec, n, x);
+    hipLaunchKernelGGL(k_xdepth, dim3(grid_for(n_int, 256)), dim3(256), 0, st, prec, x, n_int, err);
+    const bool alt = radix_sort_u32(x.ka, x.va, x.kb, x.vb, n_int, 8, ss, err, st);
+    hipLaunchKernelGGL(k_xbounds, dim3(grid_for(n_int, 256)), dim3(256), 0, st,
+                       alt ? x.kb : x.ka, n_int, x);
+    return alt;
+}
+
 void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint32_t *sorted_rows,
                   const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots, int64_t slot_cap,
-                  const DevCounters *c, unsigned int *err, hipStream_t st) {
+                  int32_t *xbase, bool xalt, const DevCounters *c, unsigned int *err,
+                  hipStream_t st) {
     const int64_t n = b.n;
     const int32_t m = b.m;
     if (n <= 1 || m <= 0) return;  // no internal node: a single leaf is its step's root
     const int64_t chunks = (n + kRefitChunk - 1) / kRefitChunk;
     const int64_t n_slots = refit_slots_needed(n, m);
-    if (slots == nullptr || n_slots == 0 || n_slots > slot_cap) slots = nullptr;
+    const bool levels = xbase != nullptr && refit_by_levels(n, m);
+    if (levels || slots == nullptr || n_slots == 0 || n_slots > slot_cap) slots = nullptr;
     // the steps of a batch are split over kRefitStepGroups workgroups per chunk
     const int32_t group_steps = (m + kRefitStepGroups - 1) / kRefitStepGroups;
     const int64_t groups = (m + group_steps - 1) / group_steps;
     hipLaunchKernelGGL(k_refit, dim3((unsigned)(chunks * groups)), dim3(kRefitChunk), 0, st, b,
-                       cloud, dt, sorted_rows, chunks, group_steps, prec, flags, nodes, slots, c,
-                       err);
-    if (slots != nullptr)
+                       cloud, dt, sorted_rows, chunks, group_steps, prec, flags, nodes, slots,
+                       levels ? 1 : 0, c, err);
+    if (levels) {
+        const XLev x = xlev_layout(xbase, n);
+        hipLaunchKernelGGL(k_refit_levels, dim3((unsigned)m), dim3(kXThreads), 0, st,
+                           xalt ? x.vb : x.va, x.start, prec, n, nodes);
+    } else if (slots != nullptr) {
         hipLaunchKernelGGL(k_refit_top, dim3(grid_for(n_slots, 256)), dim3(256), 0, st, slots,
                            n_slots, n, chunks, prec, flags, nodes, err);
+    }
 }
 
 }  // namespace tril

@@ -210,9 +210,19 @@ void launch_inst_roots(const BeamDev &b, const CloudBox &cloud, double dt, const
 // levels above the chunks, refit_slots_needed(b.n, b.m) of them, or NULL / too few:
 // the chunk kernel climbs those levels itself).
 int64_t refit_slots_needed(int64_t n, int32_t m);
+// Crossing levels of the refit merged level by level (batches of many steps): whether a
+// batch of m steps over n rows takes that path, the int32 words of its per-shape
+// buffer, and its once-per-batch setup (returns where the sort left the order).
+bool refit_by_levels(int64_t n, int32_t m);
+int64_t xlevel_ints(int64_t n);
+bool enqueue_xlevels(const PRec *prec, int64_t n, int32_t *base, const SortScratch &ss,
+                     unsigned int *err, hipStream_t st);
+// xbase: the level buffer set up by enqueue_xlevels for this shape (xalt: its result), or
+// nullptr for the crossing-level climb through the hand-off slots
 void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint32_t *sorted_rows,
                   const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots, int64_t slot_cap,
-                  const DevCounters *c, unsigned int *err, hipStream_t st);
+                  int32_t *xbase, bool xalt, const DevCounters *c, unsigned int *err,
+                  hipStream_t st);
 
 // n_int: internal nodes of all steps' trees; root_box: box of each combined instance
 // whose root is a leaf; nq: virtual query count (steps x rows).

@@ -287,11 +287,13 @@ def _degenerate_beam(kind, n, seed=31):
 
 @pytest.mark.parametrize("kind", ["same_point", "geometric", "gauss"])
 @pytest.mark.parametrize("n", [513, 1025, 1500])
-def test_tree_invariants_degenerate_shapes(torch, kind, n):
+@pytest.mark.parametrize("m", [7, 40])
+def test_tree_invariants_degenerate_shapes(torch, kind, n, m):
     """The chunked refit on trees of awkward shape: a last chunk of one leaf (513 rows),
     ragged chunks, all keys equal, and a deep skewed tree; one step per build and a batch
-    of 7 steps sharing one shape. Every node is reached once from the root and every box
-    is the photon's box or the exact union of its children."""
+    of m steps sharing one shape (7: the levels above the chunks climbed through hand-off
+    slots; 40: merged level by level). Every node is reached once from the root and every
+    box is the photon's box or the exact union of its children."""
     B = _degenerate_beam(kind, n)
     wl = beams.gauss_headon_1m(n=1000)
     ctx = T.Context(wl.dt)
@@ -304,7 +306,6 @@ def test_tree_invariants_degenerate_shapes(torch, kind, n):
     assert np.all(seen == 1)
     assert np.array_equal(np.sort(leaves), np.arange(n))
     _check_boxes(tree, boxes)
-    m = 7
     ctx = T.Context(wl.dt, step_batch=m)
     tb = T.Beam(B)
     pairs = T.Pairs(1 << 12)
