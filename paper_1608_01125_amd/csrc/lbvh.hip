@@ -850,6 +850,7 @@ constexpr uint32_t kXNone = 255u;   // sort key of a node that does not cross
 constexpr int kXThreads = 1024;
 constexpr int kXUnroll = 4;
 constexpr int32_t kXMinSteps = 32;  // fewer steps per batch leave too few workgroups
+constexpr int64_t kXMinChunks = 4;  // up to 4 chunks the climb costs less than the setup
 
 struct XLev {
     int32_t *flag;
@@ -1070,7 +1071,9 @@ int64_t refit_slots_needed(int64_t n, int32_t m) {
     return chunks > 1 ? chunks * m * kRefitSlots : 0;
 }
 
-bool refit_by_levels(int64_t n, int32_t m) { return m >= kXMinSteps && n > kRefitChunk; }
+bool refit_by_levels(int64_t n, int32_t m) {
+    return m >= kXMinSteps && n > kXMinChunks * kRefitChunk;
+}
 
 int64_t xlevel_ints(int64_t n) { return 5 * (n > 1 ? n - 1 : 1) + kXLevels + 2; }
 

@@ -229,17 +229,20 @@ def test_tree_invariants(torch):
     _check_boxes(tree, boxes)
 
 
-def test_batched_tree_copies_and_instance_roots(torch):
+@pytest.mark.parametrize("m", [5, 40])
+def test_batched_tree_copies_and_instance_roots(torch, m):
     """A batch of m steps over several instances: every step has its own copy of one
     shape (same links up to the step's offsets); each (step, instance) root reaches
     exactly that instance's rows at that step; an instance of one row is a leaf root and
-    an empty one has none; every box is the photon's box at its step or an exact union."""
+    an empty one has none; every box is the photon's box at its step or an exact union.
+    (5 steps: the levels above the refit's chunks climbed through hand-off slots; 40
+    steps over more than 2048 rows: merged level by level.)"""
     parts = []
-    for k, n_k in enumerate([700, 1, 0, 900, 2]):
+    for k, n_k in enumerate([700 if m < 32 else 1700, 1, 0, 900, 2]):
         wl = beams.gauss_headon_1m(n=max(n_k, 1), seed=20 + k)
         parts.append(beams.head(beams.draw_pair(wl)[1], n_k))
     Bc, off = beams.concat(parts)
-    n, n_inst, m = len(Bc["E"]), len(off) - 1, 5
+    n, n_inst = len(Bc["E"]), len(off) - 1
     wl = beams.gauss_headon_1m(n=1000)
     ctx = T.Context(wl.dt, step_batch=m)
     tb = T.Beam(Bc, off)
@@ -286,14 +289,14 @@ def _degenerate_beam(kind, n, seed=31):
 
 
 @pytest.mark.parametrize("kind", ["same_point", "geometric", "gauss"])
-@pytest.mark.parametrize("n", [513, 1025, 1500])
-@pytest.mark.parametrize("m", [7, 40])
+@pytest.mark.parametrize("n,m", [(513, 7), (1025, 7), (1500, 7), (2561, 40), (4100, 40)])
 def test_tree_invariants_degenerate_shapes(torch, kind, n, m):
-    """The chunked refit on trees of awkward shape: a last chunk of one leaf (513 rows),
-    ragged chunks, all keys equal, and a deep skewed tree; one step per build and a batch
-    of m steps sharing one shape (7: the levels above the chunks climbed through hand-off
-    slots; 40: merged level by level). Every node is reached once from the root and every
-    box is the photon's box or the exact union of its children."""
+    """The chunked refit on trees of awkward shape: a last chunk of one leaf (513 and
+    2561 rows), ragged chunks, all keys equal, and a deep skewed tree; one step per build
+    and a batch of m steps sharing one shape (7 steps: the levels above the chunks
+    climbed through hand-off slots; 40 steps over more than 2048 rows: merged level by
+    level). Every node is reached once from the root and every box is the photon's box
+    or the exact union of its children."""
     B = _degenerate_beam(kind, n)
     wl = beams.gauss_headon_1m(n=1000)
     ctx = T.Context(wl.dt)
