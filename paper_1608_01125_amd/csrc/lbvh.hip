@@ -598,7 +598,8 @@ __device__ __forceinline__ Half merge_halves(const Half &a, const float lo[3], c
 
 constexpr int kRefitChunk = 512;  // leaves (and threads) per workgroup
 constexpr int kRefitSlots = 64;   // hand-offs to the crossing-level kernel per workgroup
-constexpr int kRefitStepGroups = 3;  // workgroups per chunk, each for a share of the steps
+constexpr int kRefitStepGroups = 3;  // at most this many workgroups per chunk, each for a share of the steps
+constexpr int64_t kRefitWorkgroups = 4096;  // four rounds of the chip's resident refit workgroups
 
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
@@ -1101,8 +1102,12 @@ void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint
     const int64_t n_slots = refit_slots_needed(n, m);
     const bool levels = xbase != nullptr && refit_by_levels(n, m);
     if (levels || slots == nullptr || n_slots == 0 || n_slots > slot_cap) slots = nullptr;
-    // the steps of a batch are split over kRefitStepGroups workgroups per chunk
-    const int32_t group_steps = (m + kRefitStepGroups - 1) / kRefitStepGroups;
+    // the steps of a batch are split over up to kRefitStepGroups workgroups per chunk, as
+    // many as bring the launch near kRefitWorkgroups (every workgroup reads the chunk's
+    // shape once, so more chunks take fewer groups)
+    int64_t want = (kRefitWorkgroups + chunks - 1) / chunks;
+    want = want < 1 ? 1 : (want > kRefitStepGroups ? kRefitStepGroups : want);
+    const int32_t group_steps = (int32_t)((m + want - 1) / want);
     const int64_t groups = (m + group_steps - 1) / group_steps;
     hipLaunchKernelGGL(k_refit, dim3((unsigned)(chunks * groups)), dim3(kRefitChunk), 0, st, b,
                        cloud, dt, sorted_rows, chunks, group_steps, prec, flags, nodes, slots,
