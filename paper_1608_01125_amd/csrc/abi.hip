@@ -73,8 +73,8 @@ constexpr int64_t kMaxComb = (int64_t)1 << 24;    // combined instances (steps x
 constexpr int64_t kBatchBudget = (int64_t)1 << 26;  // default virtual elements per launch
 // large beams may take up to kBatchBudgetMax virtual elements per launch (about 140 bytes of
 // scratch each) so that a launch still covers kBatchStepsMin steps
-constexpr int64_t kBatchBudgetMax = (int64_t)1 << 28;
-constexpr int64_t kBatchStepsMin = 16;
+constexpr int64_t kBatchBudgetMax = (int64_t)1 << 29;
+constexpr int64_t kBatchStepsMin = 32;
 
 }  // namespace
 

@@ -225,7 +225,7 @@ def test_counters_and_threshold_prune(torch):
 
 def test_broadband_full_size_sampled_rows(torch):
     """Full size of the broadband workload (1.6e7 photons per beam, calibrated weight, 1000
-    steps, graph replay, the benchmark's launch configuration of 16 steps per launch): every
+    steps, graph replay, the benchmark's launch configuration of 32 steps per launch): every
     pair of 120 sampled query rows, 60 of them among the rows that collided, against the
     oracle."""
     wl = beams.broadband_16m()
