@@ -116,8 +116,8 @@ typedef struct {
     int64_t cand_cap;             /* broad-phase candidates one step may hold (0 = default) */
     int32_t block_traverse;       /* traversal workgroup size: 64, 128, 256, 512 or 0 = default */
     int32_t step_batch;           /* tril_run: steps per launch, >= 0 (0 = as many as keep one
-                                     launch within 2^26 photon-steps, or, for beams of more
-                                     than 2^21 photons, 32 steps within 2^29) */
+                                     launch within 2^27 photon-steps, or, for beams of more
+                                     than 2^22 photons, 32 steps within 2^29) */
     int32_t morton_bits;          /* Morton bits of the sort keys, 3..30, or 0 = automatic:
                                      30 (10 per axis) for tril_build/tril_collide; for tril_run,
                                      which first puts both beams in the order of their full

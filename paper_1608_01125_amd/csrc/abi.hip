@@ -70,7 +70,7 @@ int comb_key_bits(int64_t n_comb) { return 30 + bits_for((uint64_t)(n_comb > 1 ?
 
 constexpr int64_t kMaxN = (int64_t)1 << 30;       // node ids 2n-1 fit int32, sort counts fit 30 bits
 constexpr int64_t kMaxComb = (int64_t)1 << 24;    // combined instances (steps x instances) per launch
-constexpr int64_t kBatchBudget = (int64_t)1 << 26;  // default virtual elements per launch
+constexpr int64_t kBatchBudget = (int64_t)1 << 27;  // default virtual elements per launch
 // large beams may take up to kBatchBudgetMax virtual elements per launch (about 140 bytes of
 // scratch each) so that a launch still covers kBatchStepsMin steps
 constexpr int64_t kBatchBudgetMax = (int64_t)1 << 29;
