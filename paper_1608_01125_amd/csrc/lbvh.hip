@@ -1,5 +1,5 @@
 // Per-step hierarchy over swept photon boxes: beam statistics, box + Morton key
-// kernel, Karras emission, instance roots and the atomic bottom-up refit.
+// kernel, Karras emission, instance roots and the bottom-up refit.
 //
 // The paper's hierarchy (Sec. 2.1) uses axis-aligned boxes enlarged by the
 // distance a particle travels in one step, so that collisions are found before
@@ -7,9 +7,10 @@
 // per level. Here every step gets a linear BVH: photons are ordered along a
 // Morton curve, a binary radix tree is emitted directly from the sorted keys
 // (Karras, "Maximizing parallelism in the construction of BVHs, octrees and k-d
-// trees", HPG 2012), and boxes are filled bottom-up, the second child to arrive at
-// a node writing the union. A node stores the boxes of its two children, so the
-// descent tests both with one load.
+// trees", HPG 2012), and boxes are filled bottom-up: inside chunks of 512 leaves level
+// by level in LDS; above them either level by level in depth order (batches of many
+// steps) or by a climb in which the second child to arrive at a node writes the union.
+// A node stores the boxes of its two children, so the descent tests both with one load.
 //
 // One launch may cover m consecutive time steps of a beam. Photon row i at step
 // offset s is the virtual element e = s n + i; it belongs to the combined instance
