@@ -11,8 +11,9 @@ per-step counts. Inputs are resident in HBM before timing starts.
     value = N_A * N_B * n_time_steps / (seconds per benchmark step)
 
 The JSON line also carries
-  * roofline: the traversal kernel's algorithmic bytes per launch (36 B per query
-    for its order entry and box, 32 B per node visit, 8 B per candidate written)
+  * roofline: the traversal kernel's algorithmic bytes per launch (per query its order
+    entry and its box, 4 + 32 B, or in a batch of steps its row's record, 4 + 48 B; 64 B
+    per node load; 8 B per candidate written)
     divided by its average launch time from HIP events recorded on the library's
     stream during the timed region; HBM traffic per launch from the committed
     rocprofv3 counter summary when it belongs to the current kernel source;
@@ -604,9 +605,11 @@ def main():
 
     roofline = None
     if st["n_collides"] > 0:
-        # traversal bytes over the timed region: 36 B per query (order entry + box), 64 B per
-        # node load (both children's boxes and links), 8 B per candidate written
-        alg_bytes = 36.0 * nA * st["n_collides"] + 64.0 * st["n_node_visits"] + 8.0 * st["n_candidates"]
+        # traversal bytes over the timed region: per query its order entry and its box (4 + 32
+        # B) or, in batches of two or more steps, its row's record (4 + 48 B); 64 B per node
+        # load (both children's boxes and links); 8 B per candidate written
+        q_bytes = 52.0 if (steps_per_dispatch or 1) >= 2 else 36.0
+        alg_bytes = q_bytes * nA * st["n_collides"] + 64.0 * st["n_node_visits"] + 8.0 * st["n_candidates"]
         traffic = committed_traffic(launches_per_run or None)
         if st["n_timed_launches"] > 0 and st["ms_traverse"] > 0:
             n_launch = st["n_timed_launches"]

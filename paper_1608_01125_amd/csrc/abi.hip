@@ -157,6 +157,7 @@ struct tril_ctx {
     int64_t *d_q_off = nullptr;
     std::vector<int64_t> h_q_off;
     PBox *q_box = nullptr;
+    QRec *q_rec = nullptr;                 // per-row query records of a batch (plain regime)
     StatsPartial *q_spart = nullptr;
     InstStats *q_stats = nullptr;
     uint32_t *q_keep = nullptr;            // query order kept from a first step (n entries)
@@ -311,13 +312,14 @@ int ensure_query(tril_ctx *c, int64_t nv, int64_t n, int64_t n_comb, int32_t n_i
         ++c->alloc_gen;
         dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
         dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
-        dev_free(c->q_keep);
+        dev_free(c->q_keep); dev_free(c->q_rec);
         c->q_row_cap = 0;
         c->q_order = nullptr;
         c->q_order_key = nullptr;
         const int64_t m = std::max<int64_t>(n, 1);
         CHK(dev_alloc(&c->q_spart, (size_t)stats_partials_needed(m)));
         CHK(dev_alloc(&c->q_keep, m));
+        CHK(dev_alloc(&c->q_rec, m));
         CHK(dev_alloc(&c->q_k32a, m)); CHK(dev_alloc(&c->q_k32b, m));
         CHK(dev_alloc(&c->q_k64a, m)); CHK(dev_alloc(&c->q_k64b, m));
         CHK(dev_alloc(&c->q_va, m)); CHK(dev_alloc(&c->q_vb, m));
@@ -520,10 +522,12 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
 // Query boxes of every step of the view and, when sort_queries, the order of its rows
 // by their Morton codes at the batch's key step (c->q_order, q.n entries: the traversal
 // repeats it for every step).
-int enqueue_query_prep(tril_ctx *c, const BeamDev &q, hipStream_t st, bool sort_queries) {
+int enqueue_query_prep(tril_ctx *c, const BeamDev &q, hipStream_t st, bool sort_queries,
+                       bool records = false) {
     const KeyLayout kl = key_layout(q.n_inst, c->morton_bits);
     launch_boxes_keys(q, true, c->cloud, c->dt, c->sigma_up, c->t_stats, c->q_stats, kl,
-                      key_step(q.m), c->q_box, c->q_k32a, c->q_k64a, c->q_va, c->d_cnt, st);
+                      key_step(q.m), records ? nullptr : c->q_box, c->q_k32a, c->q_k64a, c->q_va,
+                      c->d_cnt, st, records ? c->q_rec : nullptr);
     if (sort_queries && q.n > 0 && q.m > 0) {
         bool alt;
         if (!kl.wide)
@@ -600,11 +604,15 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
     const int64_t nv = (int64_t)q.m * q.n;
     if (timed) CHK(timing_pair(c, st, c->ev_prep, true));
     launch_prologue(c->d_cnt, 1, q.m, st);
-    CHK(enqueue_query_prep(c, q, st, sort_queries));
+    // a batch of steps in the plain regime: one record per query row instead of a box per
+    // query and step
+    const bool records = q.m >= 2 && c->cloud.on == 0;
+    CHK(enqueue_query_prep(c, q, st, sort_queries, records));
     if (timed) CHK(timing_pair(c, st, c->ev_prep, false));
     if (timed) CHK(timing_pair(c, st, c->ev_trav, true));
     launch_traverse(c->nodes, c->n_int, c->root_box, c->q_box, c->q_order, c->q_order_len, nv, q.n,
-                    c->inst_root, c->cand_i, c->cand_j, c->cand_cap, c->d_cnt, c->block, st);
+                    c->inst_root, c->cand_i, c->cand_j, c->cand_cap, c->d_cnt, c->block, st,
+                    records ? c->q_rec : nullptr, q.n_inst);
     if (timed) CHK(timing_pair(c, st, c->ev_trav, false));
     if (timed) CHK(timing_pair(c, st, c->ev_narrow, true));
     launch_narrow(q, c->tgt, c->dt, c->sigma_up, c->cand_i, c->cand_j, c->cand_cap, out, c->d_cnt,
@@ -2077,7 +2085,7 @@ void tril_destroy(tril_ctx *c) {
     dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->inst_root); dev_free(c->inst_base); dev_free(c->root_box);
     dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
     dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
-    dev_free(c->q_keep); dev_free(c->d_q_off); dev_free(c->q_stats); dev_free(c->cand_i);
+    dev_free(c->q_keep); dev_free(c->q_rec); dev_free(c->d_q_off); dev_free(c->q_stats); dev_free(c->cand_i);
     dev_free(c->cand_j);
     dev_free(c->ss.hist); dev_free(c->ss.tile_ctr); dev_free(c->ss.status);
     StatsScratch &s = c->sst;

@@ -369,7 +369,8 @@ __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, CloudB
                                                     uint32_t *__restrict__ keys32,
                                                     unsigned long long *__restrict__ keys64,
                                                     uint32_t *__restrict__ vals,
-                                                    const DevCounters *__restrict__ c) {
+                                                    const DevCounters *__restrict__ c,
+                                                    QRec *__restrict__ rec) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= b.n) return;
     const int32_t mi = b.n_inst > 1 ? find_inst(b.inst_off, b.n_inst, i) : 0;
@@ -387,6 +388,20 @@ __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, CloudB
         if (cloud.on == 2) pad = sqrt(sigma_up / M_PI) * (1.0 + 1e-6);  // real photons, weight 1
     }
     const unsigned step0 = c->step;
+    if (rec != nullptr) {  // the batch's record of the row: its box at offset 0, moved per step
+        float lo32[3], hi32[3], cen[3];
+        photon_box(r, (double)step0 * dt, dt, cloud, pad, lo32, hi32, cen);
+        QRec q;
+        q.lox = lo32[0]; q.loy = lo32[1]; q.loz = lo32[2];
+        q.inst = (!r.ok || below) ? -1 : mi;
+        q.dx = (float)(dt * r.ux); q.dy = (float)(dt * r.uy); q.dz = (float)(dt * r.uz);
+        q.e = r.ok ? f32_up(E) : 0.0f;
+        q.wx = r.ok ? f32_up((double)hi32[0] - (double)lo32[0]) : 0.0f;
+        q.wy = r.ok ? f32_up((double)hi32[1] - (double)lo32[1]) : 0.0f;
+        q.wz = r.ok ? f32_up((double)hi32[2] - (double)lo32[2]) : 0.0f;
+        q.unused = 0.0f;
+        rec[i] = q;
+    }
     for (int32_t s = 0; s < b.m; ++s) {
         if (out == nullptr && (vals == nullptr || s != key_step)) continue;
         const int32_t cc = s * b.n_inst + mi;
@@ -1019,16 +1034,16 @@ void launch_beam_stats(const BeamDev &b, StatsPartial *partials, InstStats *stat
 void launch_boxes_keys(const BeamDev &b, bool query, const CloudBox &cloud, double dt, double sigma_up,
                        const InstStats *t_stats, const InstStats *self_stats, KeyLayout kl,
                        int32_t key_step, PBox *out, uint32_t *keys32, unsigned long long *keys64,
-                       uint32_t *vals, DevCounters *c, hipStream_t st) {
+                       uint32_t *vals, DevCounters *c, hipStream_t st, QRec *rec) {
     if (b.n <= 0 || b.m <= 0) return;
     if (kl.wide)
         hipLaunchKernelGGL(k_boxes_keys<true>, dim3(grid_for(b.n, 256)), dim3(256), 0, st, b,
                            query ? 1 : 0, cloud, dt, sigma_up, t_stats, self_stats, kl, key_step,
-                           out, keys32, keys64, vals, c);
+                           out, keys32, keys64, vals, c, rec);
     else
         hipLaunchKernelGGL(k_boxes_keys<false>, dim3(grid_for(b.n, 256)), dim3(256), 0, st, b,
                            query ? 1 : 0, cloud, dt, sigma_up, t_stats, self_stats, kl, key_step,
-                           out, keys32, keys64, vals, c);
+                           out, keys32, keys64, vals, c, rec);
 }
 
 void launch_gather_beam(const BeamDev &src, const uint32_t *order, double *dst_soa,

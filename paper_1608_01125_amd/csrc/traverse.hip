@@ -66,10 +66,30 @@ constexpr float kPruneProduct = (float)(kMe * kMe * (1.0 - 1e-5));
 constexpr int kStackRegs = 4;
 constexpr int kStackSpill = 124;  // deeper than any radix tree over (key, index) pairs
 
-template <int BLOCK>
+// Box of a query of step offset s from the row's record for the batch: the offset-0 box
+// moved by s d (d = u dt), widened by a bound on the FP32 arithmetic. Each of the rounded
+// quantities carries at most 2^-24 relative error: d (as rounded from u dt, scaled by s),
+// the fma lo + s d, the sum hi = lo + w, and the final widening itself; together less
+// than 2^-23 (|lo| + |hi| + s |d|), and the widening is four times that. The result
+// contains the box that the step's own FP64 computation rounds outward (whose 1e-12
+// relative slack grows by less than 1e-12 s |d| over the batch).
+__device__ __forceinline__ void record_box(const float4 a, const float4 d, const float4 w,
+                                           float s, float qb[6]) {
+    const float lx = fmaf(s, d.x, a.x), ly = fmaf(s, d.y, a.y), lz = fmaf(s, d.z, a.z);
+    const float hx = lx + w.x, hy = ly + w.y, hz = lz + w.z;
+    constexpr float k = 0x1p-21f;
+    const float ex = ((fabsf(lx) + fabsf(hx)) + s * fabsf(d.x)) * k;
+    const float ey = ((fabsf(ly) + fabsf(hy)) + s * fabsf(d.y)) * k;
+    const float ez = ((fabsf(lz) + fabsf(hz)) + s * fabsf(d.z)) * k;
+    qb[0] = lx - ex; qb[1] = ly - ey; qb[2] = lz - ez;
+    qb[3] = hx + ex; qb[4] = hy + ey; qb[5] = hz + ez;
+}
+
+template <int BLOCK, bool kRec>
 __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nodes, int32_t n_int,
                                                     const PBox *__restrict__ root_box,
                                                     const PBox *__restrict__ qbox,
+                                                    const QRec *__restrict__ qrec, int32_t n_inst,
                                                     const uint32_t *__restrict__ qorder,
                                                     int64_t order_len, int64_t nq, int64_t nq_base,
                                                     const int32_t *__restrict__ inst_root,
@@ -89,12 +109,24 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
             const int64_t s = q / nq_base;
             qi = (int32_t)(s * nq_base + qorder[q - s * nq_base]);
         }
-        const float4 *bp = reinterpret_cast<const float4 *>(qbox + qi);
-        const float4 a = bp[0], b = bp[1];
-        qb[0] = a.x; qb[1] = a.y; qb[2] = a.z;
-        qb[3] = b.x; qb[4] = b.y; qb[5] = b.z;
-        qe = b.w;
-        tag = __float_as_int(a.w);
+        if (kRec) {
+            const int64_t s = qi / nq_base;
+            const float4 *rp = reinterpret_cast<const float4 *>(qrec + (qi - s * nq_base));
+            const float4 a = rp[0], d = rp[1], w = rp[2];
+            const int32_t inst = __float_as_int(a.w);
+            if (inst >= 0) {
+                record_box(a, d, w, (float)s, qb);
+                qe = d.w;
+                tag = (int32_t)(s * n_inst + inst);
+            }
+        } else {
+            const float4 *bp = reinterpret_cast<const float4 *>(qbox + qi);
+            const float4 a = bp[0], b = bp[1];
+            qb[0] = a.x; qb[1] = a.y; qb[2] = a.z;
+            qb[3] = b.x; qb[4] = b.y; qb[5] = b.z;
+            qe = b.w;
+            tag = __float_as_int(a.w);
+        }
         if (tag >= 0) node = inst_root[tag];
     }
     const unsigned long long active_q = __ballot(node != -1);
@@ -167,35 +199,47 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
     }
 }
 
+template <int BLOCK>
+void launch_traverse_b(const Node *nodes, int32_t n_int, const PBox *root_box, const PBox *qbox,
+                       const QRec *qrec, int32_t n_inst, const uint32_t *qorder, int64_t order_len,
+                       int64_t nq, int64_t nq_base, const int32_t *inst_root, int32_t *cand_i,
+                       int32_t *cand_j, int64_t cand_cap, DevCounters *c, hipStream_t st) {
+    const unsigned grid = (unsigned)((nq + BLOCK - 1) / BLOCK);
+    if (qrec != nullptr)
+        hipLaunchKernelGGL((k_traverse<BLOCK, true>), dim3(grid), dim3(BLOCK), 0, st, nodes, n_int,
+                           root_box, qbox, qrec, n_inst, qorder, order_len, nq, nq_base, inst_root,
+                           cand_i, cand_j, cand_cap, c);
+    else
+        hipLaunchKernelGGL((k_traverse<BLOCK, false>), dim3(grid), dim3(BLOCK), 0, st, nodes, n_int,
+                           root_box, qbox, qrec, n_inst, qorder, order_len, nq, nq_base, inst_root,
+                           cand_i, cand_j, cand_cap, c);
+}
+
 }  // namespace
 
 void launch_traverse(const Node *nodes, int64_t n_int64, const PBox *root_box, const PBox *qbox,
                      const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
                      const int32_t *inst_root, int32_t *cand_i, int32_t *cand_j,
-                     int64_t cand_cap, DevCounters *c, int block, hipStream_t st) {
+                     int64_t cand_cap, DevCounters *c, int block, hipStream_t st,
+                     const QRec *qrec, int32_t n_inst) {
     if (nq <= 0 || n_int64 < 0) return;
     const int32_t n_int = (int32_t)n_int64;
-    const unsigned grid = (unsigned)((nq + block - 1) / block);
     switch (block) {
     case 64:
-        hipLaunchKernelGGL(k_traverse<64>, dim3(grid), dim3(64), 0, st, nodes, n_int, root_box,
-                           qbox, qorder, order_len, nq, nq_base, inst_root, cand_i, cand_j,
-                           cand_cap, c);
+        launch_traverse_b<64>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
+                              nq_base, inst_root, cand_i, cand_j, cand_cap, c, st);
         break;
     case 128:
-        hipLaunchKernelGGL(k_traverse<128>, dim3(grid), dim3(128), 0, st, nodes, n_int, root_box,
-                           qbox, qorder, order_len, nq, nq_base, inst_root, cand_i, cand_j,
-                           cand_cap, c);
+        launch_traverse_b<128>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
+                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, st);
         break;
     case 512:
-        hipLaunchKernelGGL(k_traverse<512>, dim3(grid), dim3(512), 0, st, nodes, n_int, root_box,
-                           qbox, qorder, order_len, nq, nq_base, inst_root, cand_i, cand_j,
-                           cand_cap, c);
+        launch_traverse_b<512>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
+                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, st);
         break;
     default:
-        hipLaunchKernelGGL(k_traverse<256>, dim3(grid), dim3(256), 0, st, nodes, n_int, root_box,
-                           qbox, qorder, order_len, nq, nq_base, inst_root, cand_i, cand_j,
-                           cand_cap, c);
+        launch_traverse_b<256>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
+                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, st);
         break;
     }
 }

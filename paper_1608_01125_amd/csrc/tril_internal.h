@@ -77,6 +77,24 @@ struct alignas(16) PBox {
 };
 static_assert(sizeof(PBox) == 32, "box layout");
 
+// Query record of one photon for a batch of steps (48 bytes): a photon moves on a
+// straight line, so its swept box at step offset s is the box at offset 0 moved by
+// s u dt. lo: the offset-0 box's low corner (FP32, rounded outward, radius pad
+// included); inst: its instance, or -1 when it can collide with nothing; d: u dt
+// (FP32, nearest); e: its energy rounded up (the threshold prune); w: the box widths
+// (FP32, rounded up). The traversal forms lo + s d and lo + s d + w and widens both by a
+// bound on that FP32 arithmetic, so the box contains the one the step's own FP64
+// computation rounds outward.
+struct alignas(16) QRec {
+    float lox, loy, loz;
+    int32_t inst;
+    float dx, dy, dz;
+    float e;
+    float wx, wy, wz;
+    float unused;
+};
+static_assert(sizeof(QRec) == 48, "query record layout");
+
 // Counters accumulated on the device across steps. Counters that every wave of a
 // large launch updates are spread over kCounterSlots addresses (slot = block index
 // modulo kCounterSlots): device-scope atomics to one address serialise at roughly
@@ -175,10 +193,11 @@ struct CloudBox {
 
 // Boxes of all b.m steps at s b.n + i; sort keys (key layout kl, base-instance prefix)
 // and row values of step offset key_step only, at i.
+// rec (queries of the plain regime only, else nullptr): one QRec per row for the batch
 void launch_boxes_keys(const BeamDev &b, bool query, const CloudBox &cloud, double dt, double sigma_up,
                        const InstStats *t_stats, const InstStats *self_stats, KeyLayout kl,
                        int32_t key_step, PBox *out, uint32_t *keys32, unsigned long long *keys64,
-                       uint32_t *vals, DevCounters *c, hipStream_t st);
+                       uint32_t *vals, DevCounters *c, hipStream_t st, QRec *rec = nullptr);
 // Morton keys of given boxes over given bounds (6 ordered floats), 30 bits.
 // dst_soa holds x, y, z, px, py, pz, E, w of src.n rows, array a at offset a * src.n.
 // Row k of dst is row order[k] of src (order nullptr: row k); dst_perm[k] is the caller's
@@ -252,10 +271,13 @@ void launch_grid_query(const GridDev *g, const PBox *tbox, const uint32_t *trows
                        const uint32_t *qorder, int64_t nq, int32_t *cand_i, int32_t *cand_j,
                        int64_t cand_cap, DevCounters *c, hipStream_t st);
 
+// Queries from per-step boxes (qbox) or, when qrec is given, from per-row records of the
+// batch (element s nq_base + row; n_inst: instances of the query view).
 void launch_traverse(const Node *nodes, int64_t n_int, const PBox *root_box, const PBox *qbox,
                      const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
                      const int32_t *inst_root, int32_t *cand_i, int32_t *cand_j,
-                     int64_t cand_cap, DevCounters *c, int block, hipStream_t st);
+                     int64_t cand_cap, DevCounters *c, int block, hipStream_t st,
+                     const QRec *qrec = nullptr, int32_t n_inst = 1);
 void launch_narrow(const BeamDev &q, const BeamDev &t, double dt, double sigma_up,
                    const int32_t *cand_i, const int32_t *cand_j, int64_t cand_cap,
                    const tril_pairs &out, DevCounters *c, bool fp32_stage, hipStream_t st);
