@@ -114,7 +114,7 @@ typedef struct {
     const double *bin_edges;      /* host, n_bins + 1 strictly increasing edges [MeV]; bin b
                                      holds edges[b] <= E_i + E_j < edges[b+1] */
     int64_t cand_cap;             /* broad-phase candidates one step may hold (0 = default) */
-    int32_t block_traverse;       /* traversal workgroup size: 64, 128, 256, 512 or 0 = default */
+    int32_t block_traverse;       /* traversal workgroup size: 64, 128, 256, 512 or 0 = default (64) */
     int32_t step_batch;           /* tril_run: steps per launch, >= 0 (0 = as many as keep one
                                      launch within 2^27 photon-steps, or, for beams of more
                                      than 2^22 photons, 32 steps within 2^29) */

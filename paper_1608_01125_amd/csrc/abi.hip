@@ -97,7 +97,7 @@ struct tril_ctx {
     int32_t n_bins = 0;
     double *d_edges = nullptr;
     int64_t cand_cap_param = 0;
-    int block = 256;
+    int block = 64;
     int32_t step_batch = 0;         // steps per launch in tril_run (0 = automatic)
     int morton_param = 0;           // Morton bits requested (0 = automatic)
     CloudBox cloud{0, {0.0, 0.0, 0.0}};  // box kind of the builds (statistical regime: clouds)
@@ -847,7 +847,9 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
         for (int32_t b = 0; b < p->n_bins; ++b)
             if (!(p->bin_edges[b + 1] > p->bin_edges[b])) return TRIL_E_INVAL;
     }
-    const int blk = p->block_traverse == 0 ? 256 : p->block_traverse;
+    // one wave per traversal workgroup: a slot is freed as soon as its wave's queries are
+    // done, not when the slowest of several waves is
+    const int blk = p->block_traverse == 0 ? 64 : p->block_traverse;
     if (blk != 64 && blk != 128 && blk != 256 && blk != 512) return TRIL_E_INVAL;
 
     tril_ctx *c = new tril_ctx();
@@ -1990,7 +1992,7 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
         ms = (double)f / n_probe;
         return TRIL_OK;
     };
-    tril_tune cur{256, 0, 0, 0, 0.0};
+    tril_tune cur{64, 0, 0, 0, 0.0};
     cur.step_batch = pick_batch(c, t, q, n_probe);
     double best_ms = 0.0;
     if ((rc = probe(cur.block_traverse, cur.step_batch, cur.morton_bits, best_ms)) != TRIL_OK) {
