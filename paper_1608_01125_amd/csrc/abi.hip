@@ -2242,9 +2242,7 @@ int tril_dbg_boxes(tril_ctx *c, int which, void *boxes, int64_t cap, int64_t *n)
             // the refit forms the target's leaf boxes itself: recompute them as it did
             if (!c->built) return TRIL_E_STATE;
             launch_set_step(c->d_cnt, c->tgt_k0, c->st);
-            launch_boxes_keys(c->tgt, false, c->tgt_cloud, c->dt, c->sigma_up, c->t_stats,
-                              c->t_stats, key_layout(1, 30), -1, c->t_box, nullptr, nullptr,
-                              nullptr, c->d_cnt, c->st);
+            launch_leaf_boxes(c->tgt, c->tgt_cloud, c->dt, c->d_cnt, c->t_box, c->st);
             HIPCHK(hipGetLastError());
             HIPCHK(hipStreamSynchronize(c->st));
         }

@@ -670,6 +670,43 @@ __device__ __forceinline__ void climb_crossing(int32_t cur, Half cn, i32x4 r, bo
 // batch (store_only: the halves are only stored), or by the crossing-level climb through
 // the (step, chunk) slots; with the slots full, or none given, the thread climbs on itself. Merges are exact
 // (min, max), so the boxes do not depend on the order of merging.
+// Leaf box of a photon at step offset s of a batch: in the plain regime (kMoved) formed in
+// FP32 from its box at offset 0 (l0, widths w0) moved by s d0 (moved_box), else in FP64
+// (photon_box: the statistical clouds and swarms). The debug dump of the target boxes
+// forms them the same way.
+struct LeafMotion {
+    float l0[3], w0[3], d0[3];
+};
+
+__device__ __forceinline__ LeafMotion leaf_motion(const RowPhoton &ph, double t0, double dt,
+                                                  const CloudBox &cloud) {
+    LeafMotion m;
+    float lo[3], hi[3], cen[3];
+    photon_box(ph, t0, dt, cloud, 0.0, lo, hi, cen);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        m.l0[a] = lo[a];
+        m.w0[a] = ph.ok ? f32_up((double)hi[a] - (double)lo[a]) : 0.0f;
+    }
+    m.d0[0] = (float)(dt * ph.ux); m.d0[1] = (float)(dt * ph.uy); m.d0[2] = (float)(dt * ph.uz);
+    return m;
+}
+
+__device__ __forceinline__ void leaf_box_moved(const LeafMotion &m, bool ok, int32_t s,
+                                               float lo[3], float hi[3]) {
+    if (!ok) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = INFINITY;
+            hi[a] = -INFINITY;
+        }
+        return;
+    }
+    moved_box(m.l0[0], m.l0[1], m.l0[2], m.d0[0], m.d0[1], m.d0[2], m.w0[0], m.w0[1], m.w0[2],
+              (float)s, lo, hi);
+}
+
+template <bool kMoved>
 __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cloud, double dt,
                                                     const uint32_t *__restrict__ rows,
                                                     int64_t chunks, int32_t group_steps,
@@ -760,26 +797,34 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
     if (myh > 0) atomicMax(&s_hmax, myh);
 
     // ---- the leaf's photon, read once for all steps of the group
+    const unsigned step0 = cnt->step;
     uint32_t row = 0;
     RowPhoton ph;
     ph.ok = false;
     ph.x = ph.y = ph.z = ph.ux = ph.uy = ph.uz = 0.0;
     float eup = 0.0f;  // the leaf's energy rounded up: the subtree bound of the prune
+    LeafMotion lm = {};
     if (in) {
         row = rows[j];
         double E, w;
         ph = load_photon(b, row, E, w);
         eup = ph.ok ? f32_up(E) : 0.0f;
+        if (kMoved) lm = leaf_motion(ph, (double)step0 * dt, dt, cloud);
     }
+    const bool ok = ph.ok;
     __syncthreads();
     const int32_t H = s_hmax, ntop = s_ntop;
-    const unsigned step0 = cnt->step;
     for (int32_t step = s_begin; step < s_end; ++step) {
         int32_t *slot = slots ? slots + ((int64_t)step * chunks + chunk) * kRefitSlots : nullptr;
         if (slot != nullptr && tid < kRefitSlots) slot[tid] = -1;
         if (in) {
-            float lo[3], hi[3], cen[3];
-            photon_box(ph, (double)(step0 + (unsigned)step) * dt, dt, cloud, 0.0, lo, hi, cen);
+            float lo[3], hi[3];
+            if (kMoved) {
+                leaf_box_moved(lm, ok, step, lo, hi);
+            } else {
+                float cen[3];
+                photon_box(ph, (double)(step0 + (unsigned)step) * dt, dt, cloud, 0.0, lo, hi, cen);
+            }
             s_lo[kRefitChunk + tid] =
                 make_float4(lo[0], lo[1], lo[2], __int_as_float(leaf_link((int64_t)step * n + row)));
             s_hi[kRefitChunk + tid] = make_float4(hi[0], hi[1], hi[2], eup);
@@ -977,6 +1022,35 @@ __global__ void __launch_bounds__(kXThreads) k_refit_levels(const uint32_t *__re
     }
 }
 
+// Target leaf boxes of every step of the launch, formed as the refit forms them (tag: the
+// combined instance, or -1 for an unusable photon; pad: the combined instance).
+__global__ void k_leaf_boxes(BeamDev b, CloudBox cloud, double dt, const DevCounters *c,
+                             PBox *out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= b.n) return;
+    const int32_t mi = b.n_inst > 1 ? find_inst(b.inst_off, b.n_inst, i) : 0;
+    double E, w;
+    const RowPhoton r = load_photon(b, i, E, w);
+    const unsigned step0 = c->step;
+    const LeafMotion lm = leaf_motion(r, (double)step0 * dt, dt, cloud);
+    for (int32_t s = 0; s < b.m; ++s) {
+        float lo[3], hi[3];
+        if (cloud.on == 0) {
+            leaf_box_moved(lm, r.ok, s, lo, hi);
+        } else {
+            float cen[3];
+            photon_box(r, (double)(step0 + (unsigned)s) * dt, dt, cloud, 0.0, lo, hi, cen);
+        }
+        const int32_t cc = s * b.n_inst + mi;
+        PBox o;
+        o.lox = lo[0]; o.loy = lo[1]; o.loz = lo[2];
+        o.hix = hi[0]; o.hiy = hi[1]; o.hiz = hi[2];
+        o.tag = r.ok ? cc : -1;
+        o.pad = cc;
+        out[(int64_t)s * b.n + i] = o;
+    }
+}
+
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace
@@ -1044,6 +1118,13 @@ void launch_boxes_keys(const BeamDev &b, bool query, const CloudBox &cloud, doub
         hipLaunchKernelGGL(k_boxes_keys<false>, dim3(grid_for(b.n, 256)), dim3(256), 0, st, b,
                            query ? 1 : 0, cloud, dt, sigma_up, t_stats, self_stats, kl, key_step,
                            out, keys32, keys64, vals, c, rec);
+}
+
+void launch_leaf_boxes(const BeamDev &b, const CloudBox &cloud, double dt, const DevCounters *c,
+                       PBox *out, hipStream_t st) {
+    if (b.n <= 0 || b.m <= 0) return;
+    hipLaunchKernelGGL(k_leaf_boxes, dim3(grid_for(b.n, 256)), dim3(256), 0, st, b, cloud, dt, c,
+                       out);
 }
 
 void launch_gather_beam(const BeamDev &src, const uint32_t *order, double *dst_soa,
@@ -1125,9 +1206,14 @@ void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint
     want = want < 1 ? 1 : (want > kRefitStepGroups ? kRefitStepGroups : want);
     const int32_t group_steps = (int32_t)((m + want - 1) / want);
     const int64_t groups = (m + group_steps - 1) / group_steps;
-    hipLaunchKernelGGL(k_refit, dim3((unsigned)(chunks * groups)), dim3(kRefitChunk), 0, st, b,
-                       cloud, dt, sorted_rows, chunks, group_steps, prec, flags, nodes, slots,
-                       levels ? 1 : 0, c, err);
+    if (cloud.on == 0)
+        hipLaunchKernelGGL(k_refit<true>, dim3((unsigned)(chunks * groups)), dim3(kRefitChunk), 0,
+                           st, b, cloud, dt, sorted_rows, chunks, group_steps, prec, flags, nodes,
+                           slots, levels ? 1 : 0, c, err);
+    else
+        hipLaunchKernelGGL(k_refit<false>, dim3((unsigned)(chunks * groups)), dim3(kRefitChunk), 0,
+                           st, b, cloud, dt, sorted_rows, chunks, group_steps, prec, flags, nodes,
+                           slots, levels ? 1 : 0, c, err);
     if (levels) {
         const XLev x = xlev_layout(xbase, n);
         hipLaunchKernelGGL(k_refit_levels, dim3((unsigned)m), dim3(kXThreads), 0, st,

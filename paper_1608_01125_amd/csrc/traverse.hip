@@ -66,23 +66,10 @@ constexpr float kPruneProduct = (float)(kMe * kMe * (1.0 - 1e-5));
 constexpr int kStackRegs = 4;
 constexpr int kStackSpill = 124;  // deeper than any radix tree over (key, index) pairs
 
-// Box of a query of step offset s from the row's record for the batch: the offset-0 box
-// moved by s d (d = u dt), widened by a bound on the FP32 arithmetic. Each of the rounded
-// quantities carries at most 2^-24 relative error: d (as rounded from u dt, scaled by s),
-// the fma lo + s d, the sum hi = lo + w, and the final widening itself; together less
-// than 2^-23 (|lo| + |hi| + s |d|), and the widening is four times that. The result
-// contains the box that the step's own FP64 computation rounds outward (whose 1e-12
-// relative slack grows by less than 1e-12 s |d| over the batch).
+// Box of a query of step offset s from the row's record for the batch (moved_box).
 __device__ __forceinline__ void record_box(const float4 a, const float4 d, const float4 w,
                                            float s, float qb[6]) {
-    const float lx = fmaf(s, d.x, a.x), ly = fmaf(s, d.y, a.y), lz = fmaf(s, d.z, a.z);
-    const float hx = lx + w.x, hy = ly + w.y, hz = lz + w.z;
-    constexpr float k = 0x1p-21f;
-    const float ex = ((fabsf(lx) + fabsf(hx)) + s * fabsf(d.x)) * k;
-    const float ey = ((fabsf(ly) + fabsf(hy)) + s * fabsf(d.y)) * k;
-    const float ez = ((fabsf(lz) + fabsf(hz)) + s * fabsf(d.z)) * k;
-    qb[0] = lx - ex; qb[1] = ly - ey; qb[2] = lz - ez;
-    qb[3] = hx + ex; qb[4] = hy + ey; qb[5] = hz + ez;
+    moved_box(a.x, a.y, a.z, d.x, d.y, d.z, w.x, w.y, w.z, s, qb, qb + 3);
 }
 
 template <int BLOCK, bool kRec>

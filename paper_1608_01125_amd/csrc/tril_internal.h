@@ -95,6 +95,26 @@ struct alignas(16) QRec {
 };
 static_assert(sizeof(QRec) == 48, "query record layout");
 
+// Box at step offset s of a batch from the box at offset 0 (low corner lo0, widths w
+// rounded up) and its motion per step d = u dt (FP32, nearest). Each of the rounded
+// quantities carries at most 2^-24 relative error: d (as rounded from u dt, scaled by s),
+// the fma lo0 + s d, the sum hi = lo + w, and the final widening itself; together less
+// than 2^-23 (|lo| + |hi| + s |d|), and the widening is four times that. The result
+// contains the box that the step's own FP64 computation rounds outward (whose 1e-12
+// relative slack grows by less than 1e-12 s |d| over the batch).
+__device__ __forceinline__ void moved_box(float lox, float loy, float loz, float dx, float dy,
+                                          float dz, float wx, float wy, float wz, float s,
+                                          float lo[3], float hi[3]) {
+    const float lx = fmaf(s, dx, lox), ly = fmaf(s, dy, loy), lz = fmaf(s, dz, loz);
+    const float hx = lx + wx, hy = ly + wy, hz = lz + wz;
+    constexpr float k = 0x1p-21f;
+    const float ex = ((fabsf(lx) + fabsf(hx)) + s * fabsf(dx)) * k;
+    const float ey = ((fabsf(ly) + fabsf(hy)) + s * fabsf(dy)) * k;
+    const float ez = ((fabsf(lz) + fabsf(hz)) + s * fabsf(dz)) * k;
+    lo[0] = lx - ex; lo[1] = ly - ey; lo[2] = lz - ez;
+    hi[0] = hx + ex; hi[1] = hy + ey; hi[2] = hz + ez;
+}
+
 // Counters accumulated on the device across steps. Counters that every wave of a
 // large launch updates are spread over kCounterSlots addresses (slot = block index
 // modulo kCounterSlots): device-scope atomics to one address serialise at roughly
@@ -193,6 +213,9 @@ struct CloudBox {
 
 // Boxes of all b.m steps at s b.n + i; sort keys (key layout kl, base-instance prefix)
 // and row values of step offset key_step only, at i.
+// Target leaf boxes of all b.m steps at s b.n + i, formed exactly as the refit forms them.
+void launch_leaf_boxes(const BeamDev &b, const CloudBox &cloud, double dt, const DevCounters *c,
+                       PBox *out, hipStream_t st);
 // rec (queries of the plain regime only, else nullptr): one QRec per row for the batch
 void launch_boxes_keys(const BeamDev &b, bool query, const CloudBox &cloud, double dt, double sigma_up,
                        const InstStats *t_stats, const InstStats *self_stats, KeyLayout kl,

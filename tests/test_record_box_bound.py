@@ -1,6 +1,7 @@
 """Bound of the query records (host check, no GPU).
 
-In a batch of steps a query photon's swept box at step offset s is formed in FP32 from
+In a batch of steps a photon's swept box at step offset s (a query's, or a leaf's in the
+tree) is formed in FP32 from
 its offset-0 box (rounded outward) moved by s d, d = u dt rounded to FP32, with the
 box widths rounded up, and widened by 2^-21 (|lo| + |hi| + s |d|). It must contain
 the box the per-step path forms in FP64 for that step and rounds outward (swept
