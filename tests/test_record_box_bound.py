@@ -1,11 +1,11 @@
-"""Bound of the query records (host check, no GPU).
+"""Bound of the moved boxes: query records and tree leaves (host check, no GPU).
 
-In a batch of steps a photon's swept box at step offset s (a query's, or a leaf's in the
-tree) is formed in FP32 from
-its offset-0 box (rounded outward) moved by s d, d = u dt rounded to FP32, with the
-box widths rounded up, and widened by 2^-21 (|lo| + |hi| + s |d|). It must contain
-the box the per-step path forms in FP64 for that step and rounds outward (swept
-segment over [t, t + dt], padded by the radius bound and a 1e-12 relative slack).
+In a batch of steps a photon's swept box at step offset s, a query's or a leaf's in the
+tree, is formed in FP32 from its offset-0 box (rounded outward) moved by s d, where
+d = u dt is rounded to FP32 and the box widths are rounded up. It is then widened by
+2^-21 (|lo| + |hi| + s |d|). It must contain the box the per-step path forms in FP64 for
+that step and rounds outward: the swept segment over [t, t + dt], padded by the radius
+bound (none for leaves) and a 1e-12 relative slack.
 
 The traversal's FP32 steps are emulated with numpy float32; the fused multiply-add is
 an exact FP64 product plus the FP64 sum, rounded once to FP32. Inputs are adversarial:
