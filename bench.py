@@ -561,8 +561,10 @@ def main():
         from paper_1608_01125_amd import autotune
         probe_ctx = T.Context(wl.dt, edges)
         try:
-            tune = autotune.tuned(probe_ctx, tb, qb, wl.dt, k0=int(0.4 * n_steps),
-                                  n_probe=min(64, n_steps), cache=autotune.DEFAULT_CACHE)
+            # probe the whole run: a window of the densest steps favours other settings
+            # than the run as timed
+            tune = autotune.tuned(probe_ctx, tb, qb, wl.dt, k0=0, n_probe=n_steps,
+                                  cache=autotune.DEFAULT_CACHE)
         finally:
             probe_ctx.close()
     timing = T.TRIL_TIMING if args.mode != "graph" else 0
