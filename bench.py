@@ -10,13 +10,17 @@ per-step counts. Inputs are resident in HBM before timing starts.
 
     value = N_A * N_B * n_time_steps / (seconds per benchmark step)
 
-The JSON line also carries
-  * roofline: the traversal kernel's algorithmic bytes per launch (per query its order
-    entry and its box, 4 + 32 B, or in a batch of steps its row's record, 4 + 48 B; 64 B
-    per node load; 8 B per candidate written)
-    divided by its average launch time from HIP events recorded on the library's
-    stream during the timed region; HBM traffic per launch from the committed
-    rocprofv3 counter summary when it belongs to the current kernel source;
+with the step batches replayed from captured HIP graphs. The same runs are then repeated
+eagerly with HIP events around every phase launch, which give the phase times and the
+traversal's launch durations. The JSON line also carries
+  * roofline (HBM): the bytes the traversal must fetch per launch (per query-step its
+    order entry and row record, 4 + 48 B; each step's tree copy once, 64 B per internal
+    node; 8 B per candidate written) over its average launch duration, against 8 TB/s;
+    `traffic` is the HBM bytes per launch measured with rocprofv3 counters (the
+    committed summary, when it belongs to the current kernel source);
+  * roofline_vmem: the bytes the traversal's loads deliver to its lanes (every node load
+    counted, 64 B) over the same duration, against the rate of the same access pattern
+    from L1 measured by tril_dbg_vmem_rate on this device;
   * cpu_baseline: the FP64 CPU oracle timed on a bounded sample of query rows of
     the same workload (all pairs of those rows, all time steps).
 """
@@ -457,9 +461,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="timed benchmark steps (collision runs)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="gauss_headon_1m")
-    ap.add_argument("--mode", choices=("batched", "graph", "per-step"), default="batched",
-                    help="batched: tril_run over step batches with HIP events around each phase; "
-                         "graph: tril_run replaying a captured step batch (no per-phase events); "
+    ap.add_argument("--mode", choices=("batched", "graph", "per-step"), default="graph",
+                    help="graph: value from tril_run replaying captured step batches, then the "
+                         "same runs eagerly with HIP events around each phase for the phase "
+                         "times and the roofline; batched: value from the eager runs; "
                          "per-step: one tril_build/tril_collide call per time step with events")
     ap.add_argument("--step-batch", type=int, default=0, help="time steps per launch (0 = automatic)")
     ap.add_argument("--physics-steps", type=int, default=0, help="0 = the workload's full run")
@@ -567,12 +572,25 @@ def main():
                                   cache=autotune.DEFAULT_CACHE)
         finally:
             probe_ctx.close()
-    timing = T.TRIL_TIMING if args.mode != "graph" else 0
-    elapsed, st = timed(args.flags | timing)
-    main_run_ms = sorted(run_ms)
-    ms_per_step = 1e3 * elapsed / max(args.steps, 1)
-    value = pairs_per_step * n_steps / (elapsed / max(args.steps, 1))
-    launches_per_run = st["n_timed_launches"] // max(args.steps, 1) if timing else 0
+    timing = T.TRIL_TIMING
+    if args.mode == "graph":
+        # the value: full step batches replayed from captured graphs, no per-phase events
+        g_elapsed, g_st = timed(args.flags)
+        main_run_ms = sorted(run_ms)
+        # the same runs eagerly with HIP events around every phase launch: phase times and
+        # the traversal's launch durations (the kernels are the same)
+        elapsed, st = timed(args.flags | timing)
+        eager_ms = 1e3 * elapsed / max(args.steps, 1)
+        assert g_st["n_pairs"] == st["n_pairs"] and g_st["n_hits"] == st["n_hits"]
+        elapsed_value = g_elapsed
+    else:
+        elapsed, st = timed(args.flags | timing)
+        main_run_ms = sorted(run_ms)
+        eager_ms = 1e3 * elapsed / max(args.steps, 1)
+        elapsed_value = elapsed
+    ms_per_step = 1e3 * elapsed_value / max(args.steps, 1)
+    value = pairs_per_step * n_steps / (elapsed_value / max(args.steps, 1))
+    launches_per_run = st["n_timed_launches"] // max(args.steps, 1)
     steps_per_dispatch = round(n_steps / launches_per_run, 3) if launches_per_run else None
 
     variants = {}
@@ -605,32 +623,46 @@ def main():
                                   ("ms_build", "ms_query_prep", "ms_traverse", "ms_narrow")}}
         variants["pair_kinematics"] = kinematics_variant(T, torch, A, B, wl, n_steps, edges)
 
-    roofline = None
-    if st["n_collides"] > 0:
-        # traversal bytes over the timed region: per query its order entry and its box (4 + 32
-        # B) or, in batches of two or more steps, its row's record (4 + 48 B); 64 B per node
-        # load (both children's boxes and links); 8 B per candidate written
+    roofline = roofline_vmem = None
+    if st["n_collides"] > 0 and st["n_timed_launches"] > 0 and st["ms_traverse"] > 0:
+        # Two roofs of the traversal (k_traverse), each with bytes over the timed region,
+        # per launch, divided by the average launch duration from HIP events recorded
+        # around every traversal launch on the library's stream.
+        # HBM roof: the bytes the method must fetch from memory at least once per step: per
+        # query-step its order entry and its row's record (4 + 48 B; 4 + 32 B box when every
+        # step is its own launch), each step's tree copy read once (64 B per internal node),
+        # 8 B per candidate written.
         q_bytes = 52.0 if (steps_per_dispatch or 1) >= 2 else 36.0
-        alg_bytes = q_bytes * nA * st["n_collides"] + 64.0 * st["n_node_visits"] + 8.0 * st["n_candidates"]
+        n_inst = 1 if offB is None else len(offB) - 1
+        n_int_step = max(nB - n_inst, 0)
+        n_launch = st["n_timed_launches"]
+        hbm_bytes = (q_bytes * nA + 64.0 * n_int_step) * st["n_collides"] + 8.0 * st["n_candidates"]
+        # vector-memory roof: the bytes the kernel's loads deliver to its lanes, every node
+        # load counted (64 B: both children's boxes and links), plus the query bytes and
+        # candidate stores above
+        lane_bytes = q_bytes * nA * st["n_collides"] + 64.0 * st["n_node_visits"] + 8.0 * st["n_candidates"]
         traffic = committed_traffic(launches_per_run or None)
-        if st["n_timed_launches"] > 0 and st["ms_traverse"] > 0:
-            n_launch = st["n_timed_launches"]
-            per_launch = alg_bytes / n_launch
-            avg_s = st["ms_traverse"] * 1e-3 / n_launch
-            achieved = per_launch / avg_s / 1e9
-            roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                        "traffic": traffic,
-                        "kernel": "k_traverse", "avg_launch_us": round(avg_s * 1e6, 3),
-                        "steps_per_launch": steps_per_dispatch,
-                        "alg_bytes_per_launch": round(per_launch, 1),
-                        "traffic_achieved_GBs": (round(traffic / avg_s / 1e9, 2)
-                                                 if traffic else None),
-                        "node_visits_per_query": round(st["n_node_visits"] / max(st["n_queries"], 1), 3)}
-        else:
-            roofline = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": None, "traffic": None, "kernel": "k_traverse",
-                        "note": "graph mode records no per-phase events; use --mode batched"}
+        avg_s = st["ms_traverse"] * 1e-3 / n_launch
+        achieved = hbm_bytes / n_launch / avg_s / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic,
+                    "kernel": "k_traverse", "avg_launch_us": round(avg_s * 1e6, 3),
+                    "steps_per_launch": steps_per_dispatch,
+                    "alg_bytes_per_launch": round(hbm_bytes / n_launch, 1),
+                    "traffic_achieved_GBs": (round(traffic / avg_s / 1e9, 2) if traffic else None),
+                    "traffic_frac": (round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+                                     if traffic else None),
+                    "node_visits_per_query": round(st["n_node_visits"] / max(st["n_queries"], 1), 3)}
+        probe_div = T.tril_dbg_vmem_rate(True) / 1e9
+        probe_coal = T.tril_dbg_vmem_rate(False) / 1e9
+        ach_v = lane_bytes / n_launch / avg_s / 1e9
+        roofline_vmem = {"bound": "vmem", "achieved": round(ach_v, 2), "peak": round(probe_div, 1),
+                         "unit": "GB/s", "frac": round(ach_v / probe_div, 4), "kernel": "k_traverse",
+                         "peak_source": "tril_dbg_vmem_rate: 64-B records as four 16-B loads per "
+                                        "lane, 64 different records per wave, L1-resident",
+                         "probe_coalesced_GBs": round(probe_coal, 1),
+                         "lane_bytes_per_launch": round(lane_bytes / n_launch, 1)}
 
     out = {
         "metric": METRIC,
@@ -640,6 +672,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_eager": round(eager_ms, 3),
         "ms_per_step_min_median_max": [round(main_run_ms[0], 3),
                                        round(main_run_ms[len(main_run_ms) // 2], 3),
                                        round(main_run_ms[-1], 3)] if main_run_ms else None,
@@ -656,6 +689,7 @@ def main():
                    "step_batch": args.step_batch, "steps_per_launch": steps_per_dispatch,
                    "query_order": ("first step's Morton order" if args.flags & T.TRIL_SORT_QUERIES_ONCE
                                    else "Morton order of every step"),
+                   "timing": ("graph replay" if args.mode == "graph" else "eager, per-phase events"),
                    "traversal_launches": st["n_timed_launches"],
                    "pairs": st["n_pairs"], "hits": st["n_hits"],
                    "candidates_per_run": st["n_candidates"] // max(args.steps, 1),
@@ -664,6 +698,7 @@ def main():
                    "ms_phases_per_run": {k: round(st[k] / max(args.steps, 1), 3) for k in
                                          ("ms_build", "ms_query_prep", "ms_traverse", "ms_narrow")}},
         "roofline": roofline,
+        "roofline_vmem": roofline_vmem,
     }
     if variants:
         out["variants"] = variants

@@ -63,7 +63,9 @@ extern "C" {
 #define TRIL_E_HIP       -4  /* HIP runtime error; tril_last_hip_error gives its text */
 #define TRIL_E_NOTIMPL   -5  /* flag or mode not implemented */
 #define TRIL_E_STATE     -6  /* call order: collide before any build, or beams of different instance counts */
-#define TRIL_E_DATA      -7  /* photon data rejected on the device: non-finite value, E <= 0 or w < 0 */
+#define TRIL_E_DATA      -7  /* photon data rejected on the device: non-finite value, E <= 0,
+                                  w < 0, or a momentum whose magnitude |p| c differs from E
+                                  by more than 1e-12 relative (photons are massless) */
 #define TRIL_E_INTERNAL  -8  /* a device-side wait exceeded its bound (should not happen) */
 
 /* tril_params.flags */
@@ -99,7 +101,8 @@ typedef struct tril_mlp tril_mlp;
 typedef struct {
     int64_t n;
     const double *x, *y, *z;      /* device, n each: position at t = 0 [um] */
-    const double *px, *py, *pz;   /* device, n each: momentum [MeV/c] */
+    const double *px, *py, *pz;   /* device, n each: momentum [MeV/c], |p| c = E to 1e-12
+                                     relative (checked on the device, TRIL_E_DATA) */
     const double *E;              /* device, n: energy [MeV], finite and > 0 */
     const double *w;              /* device, n: macro-particle weight, finite and >= 0 */
     int32_t n_inst;               /* >= 1 */

@@ -52,6 +52,15 @@ int tril_dbg_pair_eval32(int64_t n, const double *in, double *out, void *stream)
 int tril_dbg_gemm_bf16(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk,
                        int64_t sbn, int32_t M, int32_t N, int32_t K, float *C, void *stream);
 
+/* Rate of the vector-memory path for the traversal's access pattern: `blocks` workgroups
+ * of 256 lanes, each lane loading `iters` 64-byte records as four 16-byte loads from an
+ * 8 KB window that every CU's L1 holds (divergent != 0: the 64 lanes of a wave read 64
+ * different records; 0: consecutive lanes read consecutive 16-byte words). The second of
+ * two launches is timed with HIP events; *bytes_per_s (host) receives the bytes the loads
+ * delivered per second. Allocates and frees its own 8 KB window. Synchronises the stream. */
+int tril_dbg_vmem_rate(int divergent, int32_t blocks, int32_t iters, double *bytes_per_s,
+                       void *stream);
+
 /* Copy the last built hierarchy to host memory (synchronises the context stream).
  * nodes: host, cap_nodes x 16 words, one internal node each: its left child's box and
  * link (lox loy loz link hix hiy hiz pad), then its right child's, as float/int32; a
@@ -67,6 +76,20 @@ int tril_dbg_tree(tril_ctx *ctx, void *nodes, int64_t cap_nodes, int64_t *n_node
  * (which = 1) beam to host memory as n x 8 words (lox loy loz tag hix hiy hiz
  * instance). Synchronises the context stream. */
 int tril_dbg_boxes(tril_ctx *ctx, int which, void *boxes, int64_t cap, int64_t *n);
+
+/* Caller row of each row of the last build's target view (host, n entries): the element
+ * s n + r of tril_dbg_boxes (which = 0) and of the hierarchy's leaves is the photon of
+ * caller row rows[r] at step offset s (tril_run builds over Morton-ordered working
+ * copies; tril_build over the caller's rows, rows[r] = r). Synchronises the stream. */
+int tril_dbg_target_rows(tril_ctx *ctx, int32_t *rows, int64_t cap, int64_t *n);
+
+/* Query boxes of step offset s (0 <= s < m) of the last step batch of tril_run, formed
+ * from the batch's per-row query records exactly as the traversal forms them, in the
+ * caller's row order: host, n x 8 words (lox loy loz tag hix hiy hiz working-row) as in
+ * tril_dbg_boxes; tag -1 marks a row that can collide with nothing. *n receives the
+ * query rows. TRIL_E_STATE when the last batch had no records (one step per launch).
+ * Synchronises the context stream. */
+int tril_dbg_query_records(tril_ctx *ctx, int32_t s, void *boxes, int64_t cap, int64_t *n);
 
 /* Copy the candidate pairs of the last tril_collide to host memory. *count gets the
  * number found (may exceed cap; only min(count, cap) are written). */

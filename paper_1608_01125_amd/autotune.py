@@ -5,6 +5,7 @@ the speed of tril_run, never its results. They are stored per workload shape and
 device in a JSON file so that a later process reuses them without probing again."""
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 from typing import Optional
@@ -15,9 +16,21 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1608_0112
                              "tune.json")
 
 
-def shape_key(target: T.Beam, query: T.Beam, dt: float, device_name: str) -> str:
-    """Key of a workload shape: beam sizes, instance count, step length, device."""
-    return f"{device_name}|nt={target.n}|nq={query.n}|inst={target.n_inst}|dt={dt:.6g}"
+def library_digest() -> str:
+    """Digest of the built library: a rebuilt kernel invalidates every cached setting."""
+    h = hashlib.sha256()
+    with open(T.LIB_PATH, "rb") as f:
+        for chunk in iter(lambda: f.read(1 << 20), b""):
+            h.update(chunk)
+    return h.hexdigest()[:16]
+
+
+def shape_key(target: T.Beam, query: T.Beam, dt: float, device_name: str, k0: int = 0,
+              n_probe: int = 0) -> str:
+    """Key of a workload shape and probe: beam sizes, instance count, step length, device,
+    the probed steps and the library build."""
+    return (f"{device_name}|nt={target.n}|nq={query.n}|inst={target.n_inst}|dt={dt:.6g}"
+            f"|k0={k0}|probe={n_probe}|lib={library_digest()}")
 
 
 def _load(path: str) -> dict:
@@ -37,7 +50,7 @@ def tuned(ctx: T.Context, target: T.Beam, query: T.Beam, dt: float, k0: int, n_p
     if device_name is None:
         import torch
         device_name = torch.cuda.get_device_name(0)
-    key = shape_key(target, query, dt, device_name)
+    key = shape_key(target, query, dt, device_name, k0, n_probe)
     data = _load(cache) if cache else {}
     if key in data:
         cfg = data[key]

@@ -211,6 +211,8 @@ struct tril_ctx {
 
     BeamDev res_t{};                // caller's target beam of the last build or run (statistics)
     BeamDev last_q{};               // caller's query beam of the last collide (statistics)
+    BeamDev last_qrec{};            // working view whose rows the query records of the last
+                                    // step batch of tril_run describe (m = 0: none)
     int64_t max_nq = 0;
 };
 
@@ -900,7 +902,7 @@ int tril_build(tril_ctx *c, const tril_beam *b, int32_t step) {
     c->tgt = view(b, c->d_t_off, 1);
     c->res_t = c->tgt;
     launch_set_step(c->d_cnt, step, c->st);
-    launch_beam_stats(c->tgt, c->t_spart, c->t_stats, c->d_cnt, c->st);
+    launch_beam_stats(c->tgt, c->t_spart, c->t_stats, c->d_cnt, c->st, true);
     if (c->flags & TRIL_GRID)
         CHK(enqueue_grid_build(c, c->st, (c->flags & TRIL_TIMING) != 0));
     else
@@ -923,7 +925,7 @@ int tril_collide(tril_ctx *c, const tril_beam *q, int32_t step, tril_pairs *out)
     CHK(upload_offsets(c, q, c->d_q_off, c->h_q_off));
     const BeamDev qv = view(q, c->d_q_off, 1);
     const bool sort = need_query_sort(c, q);
-    launch_beam_stats(qv, c->q_spart, c->q_stats, c->d_cnt, c->st);
+    launch_beam_stats(qv, c->q_spart, c->q_stats, c->d_cnt, c->st, true);
     if (c->flags & TRIL_GRID)
         CHK(enqueue_grid_collide(c, qv, *out, c->st, (c->flags & TRIL_TIMING) != 0, sort));
     else
@@ -961,8 +963,8 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     c->nt = t->n;
     c->q_order_key = nullptr;  // the sort buffers are reused below
     const BeamDev t1 = view(t, c->d_t_off, 1), q1 = view(q, c->d_q_off, 1);
-    launch_beam_stats(t1, c->t_spart, c->t_stats, c->d_cnt, c->st);
-    launch_beam_stats(q1, c->q_spart, c->q_stats, c->d_cnt, c->st);
+    launch_beam_stats(t1, c->t_spart, c->t_stats, c->d_cnt, c->st, true);
+    launch_beam_stats(q1, c->q_spart, c->q_stats, c->d_cnt, c->st, true);
     // working copies in the caller's order; after every batch they are rewritten in the
     // Morton order of that batch's first step (a relabelling of rows: the pair set does
     // not depend on it, and the narrow phase reports caller rows)
@@ -1035,6 +1037,8 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
                                c->wq[pq ^ 1].perm, st);
         return TRIL_OK;
     };
+    int last_pq = 0;            // query working buffer of the last batch enqueued
+    int32_t last_mb = 0;
     auto flip = [&](bool sort) {
         pt ^= 1;
         if (sort) pq ^= 1;
@@ -1050,6 +1054,8 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
             // orders the queries when they are ordered once)
             launch_set_step(c->d_cnt, k, c->st);
             CHK(enqueue_batch(mb, sort, c->st, timed));
+            last_pq = pq;
+            last_mb = mb;
             flip(sort);
             CHK(resolve(c->st, k + mb - 1));
             q_sorted = q_sorted || sort;
@@ -1071,7 +1077,10 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
                 (const void *)(intptr_t)t->n_inst, (const void *)(intptr_t)out->cap,
                 (const void *)(intptr_t)sort, c->d_t_off, c->d_q_off,
                 (const void *)(intptr_t)m, (const void *)(intptr_t)c->morton_bits,
-                (const void *)(uintptr_t)c->alloc_gen};
+                (const void *)(uintptr_t)c->alloc_gen,
+                // every launch parameter read while the batch is captured
+                (const void *)(intptr_t)c->block, (const void *)(uintptr_t)c->flags,
+                (const void *)(intptr_t)c->cand_cap};
             int slot = (c->gexec[0] && key == c->gkey[0]) ? 0
                        : (c->gexec[1] && key == c->gkey[1]) ? 1 : -1;
             if (slot < 0) {
@@ -1100,6 +1109,8 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
                 c->gkey[slot] = key;
             }
             HIPCHK(hipGraphLaunch(c->gexec[slot], c->gst));
+            last_pq = pq;
+            last_mb = m;
             flip(sort);
             CHK(resolve(c->gst, k + (r + 1) * m - 1));
         }
@@ -1111,6 +1122,8 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     // the last batch's view (its working-copy buffer: graph replays leave the host view
     // of the last capture)
     c->tgt = wview(t, c->d_t_off, c->tgt.m, c->wt[pt ^ 1]);
+    c->last_qrec = wview(q, c->d_q_off, last_mb, c->wq[last_pq]);
+    if (!(last_mb >= 2 && c->cloud.on == 0)) c->last_qrec.m = 0;  // boxes, not records
     c->built = true;
     c->built_step = k0 + n_steps - 1;
     c->tgt_k0 = k0 + n_steps - c->tgt.m;
@@ -1321,8 +1334,10 @@ int st_run(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, int64_t n_t_b
     c->nt = t->n;
     c->q_order_key = nullptr;
     const BeamDev t1 = view(t, c->d_t_off, 1), q1 = view(q, c->d_q_off, 1);
-    launch_beam_stats(t1, c->t_spart, c->t_stats, c->d_cnt, c->st);
-    launch_beam_stats(q1, c->q_spart, c->q_stats, c->d_cnt, c->st);
+    // caller photons must be light-like; the bin clouds of the surrogate's geometric pass
+    // (mode 1) carry mean directions
+    launch_beam_stats(t1, c->t_spart, c->t_stats, c->d_cnt, c->st, geometric != 1);
+    launch_beam_stats(q1, c->q_spart, c->q_stats, c->d_cnt, c->st, geometric != 1);
     const StCell sc{{cell[0], cell[1], cell[2]}};
     // clouds at mid-step; swarms (geometric 3): clouds swept over the step
     c->cloud = CloudBox{geometric == 3 ? 2 : 1, {0.5 * cell[0], 0.5 * cell[1], 0.5 * cell[2]}};
@@ -2249,6 +2264,44 @@ int tril_dbg_boxes(tril_ctx *c, int which, void *boxes, int64_t cap, int64_t *n)
         HIPCHK(hipMemcpy(boxes, which == 0 ? c->t_box : c->q_box, nn * sizeof(PBox),
                          hipMemcpyDeviceToHost));
     }
+    return TRIL_OK;
+}
+
+int tril_dbg_target_rows(tril_ctx *c, int32_t *rows, int64_t cap, int64_t *n) {
+    if (!c || !n) return TRIL_E_INVAL;
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (!c->built) return TRIL_E_STATE;
+    const BeamDev &t = c->tgt;
+    *n = t.n;
+    if (t.n > cap) return TRIL_E_OVERFLOW;
+    if (t.n == 0) return TRIL_OK;
+    if (!rows) return TRIL_E_INVAL;
+    if (t.perm) {
+        HIPCHK(hipMemcpy(rows, t.perm, t.n * sizeof(int32_t), hipMemcpyDeviceToHost));
+    } else {
+        for (int64_t r = 0; r < t.n; ++r) rows[r] = (int32_t)r;
+    }
+    return TRIL_OK;
+}
+
+int tril_dbg_query_records(tril_ctx *c, int32_t s, void *boxes, int64_t cap, int64_t *n) {
+    if (!c || !n) return TRIL_E_INVAL;
+    HIPCHK(hipStreamSynchronize(c->st));
+    const BeamDev &v = c->last_qrec;
+    if (v.m < 2 || c->q_rec == nullptr) return TRIL_E_STATE;
+    if (s < 0 || s >= v.m) return TRIL_E_INVAL;
+    *n = v.n;
+    if (v.n > cap) return TRIL_E_OVERFLOW;
+    if (v.n == 0) return TRIL_OK;
+    if (!boxes) return TRIL_E_INVAL;
+    PBox *tmp = nullptr;
+    CHK(dev_alloc(&tmp, (size_t)v.n));
+    launch_record_boxes(c->q_rec, v.n, v.perm, s, tmp, c->st);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e == hipSuccess) e = hipMemcpy(boxes, tmp, v.n * sizeof(PBox), hipMemcpyDeviceToHost);
+    dev_free(tmp);
+    if (e != hipSuccess) return hip_fail(e);
     return TRIL_OK;
 }
 

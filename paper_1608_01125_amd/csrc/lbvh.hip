@@ -190,7 +190,8 @@ __global__ void k_stats_clear(InstStats *stats, int32_t n_inst) {
 // smaller than a block) go to the instance totals with atomics. Invalid rows
 // (non-finite values, E <= 0, w < 0) raise the data error flag and are left out.
 __global__ void __launch_bounds__(kStatThreads) k_beam_stats(BeamDev b, StatsPartial *partials,
-                                                            InstStats *stats, DevCounters *c) {
+                                                            InstStats *stats, DevCounters *c,
+                                                            int light_like) {
     __shared__ InstStats s_red[kStatThreads / 64][2];
     const int64_t base = blockIdx.x * (int64_t)kStatSpan;
     const int64_t last = (base + kStatSpan < b.n ? base + kStatSpan : b.n) - 1;
@@ -208,11 +209,16 @@ __global__ void __launch_bounds__(kStatThreads) k_beam_stats(BeamDev b, StatsPar
         const bool ok = isfinite(E) && isfinite(w) && isfinite(px) && isfinite(py) &&
                         isfinite(pz) && isfinite(x) && isfinite(y) && isfinite(z) && E > 0.0 &&
                         w >= 0.0;
-        if (!ok) {
+        // a photon's momentum has magnitude E (c = 1): |u|^2 = |p/E|^2 within 2e-12 of 1,
+        // i.e. |p| c = E to 1e-12 relative (u is formed as the kernels form it)
+        const double ux = px / E, uy = py / E, uz = pz / E;
+        const bool on_shell =
+            !light_like || fabs(((ux * ux + uy * uy) + uz * uz) - 1.0) <= 2e-12;
+        if (!ok || !on_shell) {
             atomicOr(&c->err, kErrData);
             continue;
         }
-        const double v[6] = {x, y, z, px / E, py / E, pz / E};
+        const double v[6] = {x, y, z, ux, uy, uz};
         InstStats one;
         for (int a = 0; a < 6; ++a) {
             one.mn[a] = d2ord(v[a]);
@@ -1095,12 +1101,12 @@ void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st) {
 int64_t stats_partials_needed(int64_t n) { return 2 * ((n + kStatSpan - 1) / kStatSpan) + 2; }
 
 void launch_beam_stats(const BeamDev &b, StatsPartial *partials, InstStats *stats, DevCounters *c,
-                       hipStream_t st) {
+                       hipStream_t st, bool light_like) {
     hipLaunchKernelGGL(k_stats_clear, dim3(grid_for(b.n_inst, 64)), dim3(64), 0, st, stats,
                        b.n_inst);
     if (b.n <= 0) return;
     hipLaunchKernelGGL(k_beam_stats, dim3(grid_for(b.n, kStatSpan)), dim3(kStatThreads), 0, st, b,
-                       partials, stats, c);
+                       partials, stats, c, light_like ? 1 : 0);
     hipLaunchKernelGGL(k_fold_stats, dim3((unsigned)b.n_inst), dim3(256), 0, st, partials, b,
                        stats);
 }

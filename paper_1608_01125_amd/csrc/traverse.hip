@@ -202,7 +202,30 @@ void launch_traverse_b(const Node *nodes, int32_t n_int, const PBox *root_box, c
                            cand_i, cand_j, cand_cap, c);
 }
 
+__global__ void k_record_boxes(const QRec *__restrict__ qrec, int64_t n,
+                               const int32_t *__restrict__ perm, float s, PBox *__restrict__ out) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const float4 *rp = reinterpret_cast<const float4 *>(qrec + r);
+    const float4 a = rp[0], d = rp[1], w = rp[2];
+    float qb[6];
+    record_box(a, d, w, s, qb);
+    PBox b;
+    b.lox = qb[0]; b.loy = qb[1]; b.loz = qb[2];
+    b.hix = qb[3]; b.hiy = qb[4]; b.hiz = qb[5];
+    b.tag = __float_as_int(a.w);
+    b.pad = (int32_t)r;
+    out[perm ? perm[r] : r] = b;
+}
+
 }  // namespace
+
+void launch_record_boxes(const QRec *qrec, int64_t n, const int32_t *perm, int32_t s, PBox *out,
+                         hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_record_boxes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, qrec, n,
+                       perm, (float)s, out);
+}
 
 void launch_traverse(const Node *nodes, int64_t n_int64, const PBox *root_box, const PBox *qbox,
                      const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,

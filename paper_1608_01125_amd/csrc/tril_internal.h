@@ -15,7 +15,7 @@ constexpr double kMe = 0.51099895000;      // electron rest energy [MeV]
 constexpr double kRe = 2.8179403262e-9;    // classical electron radius [um]
 
 // Device-side error bits (DevCounters::err).
-constexpr uint32_t kErrData = 1u;          // non-finite input, E <= 0 or w < 0
+constexpr uint32_t kErrData = 1u;          // non-finite input, E <= 0, w < 0 or |p| != E
 constexpr uint32_t kErrCandOverflow = 2u;  // broad-phase candidate buffer full
 constexpr uint32_t kErrSpin = 4u;          // a bounded device loop or stack ran out
 constexpr uint32_t kErrPairOverflow = 8u;  // caller pair buffer full
@@ -198,9 +198,12 @@ void launch_set_step(DevCounters *c, int32_t step, hipStream_t st);
 void launch_advance_step(DevCounters *c, int32_t m, hipStream_t st);
 void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st);
 
-// Per-instance statistics of beam b (rows only; b.m is ignored); flags invalid data.
+// Per-instance statistics of beam b (rows only; b.m is ignored); flags invalid data
+// (light_like: also a momentum whose magnitude differs from E by more than 1e-12
+// relative; off for the bin clouds of the statistical regime, whose mean directions are
+// shorter than one).
 void launch_beam_stats(const BeamDev &b, StatsPartial *partials, InstStats *stats, DevCounters *c,
-                       hipStream_t st);
+                       hipStream_t st, bool light_like);
 // Swept boxes of all virtual elements of b plus their sort keys and values (the
 // virtual element index). Morton quantisation bounds come from self_stats; query
 // padding and the threshold prune from t_stats (target instance statistics).
@@ -294,6 +297,11 @@ void launch_grid_query(const GridDev *g, const PBox *tbox, const uint32_t *trows
                        const uint32_t *qorder, int64_t nq, int32_t *cand_i, int32_t *cand_j,
                        int64_t cand_cap, DevCounters *c, hipStream_t st);
 
+// Boxes of n query rows at step offset s of a batch, formed from their records exactly as
+// the traversal forms them, written at out[perm[row]] (perm nullptr: at out[row]); tag:
+// the record's instance (-1: the row can collide with nothing); pad: the row.
+void launch_record_boxes(const QRec *qrec, int64_t n, const int32_t *perm, int32_t s, PBox *out,
+                         hipStream_t st);
 // Queries from per-step boxes (qbox) or, when qrec is given, from per-row records of the
 // batch (element s nq_base + row; n_inst: instances of the query view).
 void launch_traverse(const Node *nodes, int64_t n_int, const PBox *root_box, const PBox *qbox,

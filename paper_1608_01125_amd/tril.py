@@ -119,8 +119,8 @@ EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats"
            "tril_dbg_gemm_bf16",
            "tril_reset_counters", "tril_destroy", "tril_strerror", "tril_last_hip_error",
            "tril_dbg_sort_u32", "tril_dbg_sort_u64", "tril_dbg_morton", "tril_dbg_pair_eval",
-           "tril_dbg_pair_eval32",
-           "tril_dbg_tree", "tril_dbg_boxes", "tril_dbg_candidates")
+           "tril_dbg_pair_eval32", "tril_dbg_vmem_rate",
+           "tril_dbg_tree", "tril_dbg_boxes", "tril_dbg_target_rows", "tril_dbg_query_records", "tril_dbg_candidates")
 
 _lib = None
 
@@ -194,8 +194,11 @@ def lib() -> ctypes.CDLL:
     L.tril_dbg_morton.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_float), vp, vp]
     L.tril_dbg_pair_eval.argtypes = [i64, vp, vp, vp]
     L.tril_dbg_pair_eval32.argtypes = [i64, vp, vp, vp]
+    L.tril_dbg_vmem_rate.argtypes = [ctypes.c_int, i32, i32, ctypes.POINTER(ctypes.c_double), vp]
     L.tril_dbg_tree.argtypes = [vp, vp, i64, _i64p, _i32p]
     L.tril_dbg_boxes.argtypes = [vp, ctypes.c_int, vp, i64, _i64p]
+    L.tril_dbg_query_records.argtypes = [vp, i32, vp, i64, _i64p]
+    L.tril_dbg_target_rows.argtypes = [vp, _i32p, i64, _i64p]
     L.tril_dbg_candidates.argtypes = [vp, _i32p, _i32p, i64, _i64p]
     _lib = L
     return L
@@ -651,6 +654,16 @@ def _h(ctx):
     return ctx.h if isinstance(ctx, Context) else ctx
 
 
+def tril_dbg_vmem_rate(divergent: bool, blocks: int = 4096, iters: int = 2048,
+                       stream=None) -> float:
+    """Bytes per second the vector-memory path delivers for 64-byte records read as four
+    16-byte loads per lane from an L1-resident window."""
+    out = ctypes.c_double(0.0)
+    _check(lib().tril_dbg_vmem_rate(1 if divergent else 0, blocks, iters, ctypes.byref(out),
+                                    _stream(stream)), "tril_dbg_vmem_rate")
+    return out.value
+
+
 def tril_dbg_tree(ctx, n_target: int, n_inst: int = 1, m: int = 1):
     """Internal nodes of the last build: lo/hi (k, 2, 3) child boxes, link (k, 2) child
     links (>= 0 internal, <= -2 leaf of element -2 - link), roots (m n_inst)."""
@@ -677,6 +690,29 @@ def tril_dbg_boxes(ctx, which: int, n: int):
     ints = boxes.view(np.int32)
     return {"lo": boxes[:, 0:3].copy(), "hi": boxes[:, 4:7].copy(), "tag": ints[:, 3].copy(),
             "inst": ints[:, 7].copy()}
+
+
+def tril_dbg_target_rows(ctx, n: int) -> np.ndarray:
+    """Caller row of each row of the last build's target view."""
+    ctx = _h(ctx)
+    rows = np.zeros(max(n, 1), dtype=np.int32)
+    nn = ctypes.c_int64(0)
+    _check(lib().tril_dbg_target_rows(ctx, rows.ctypes.data_as(_i32p), max(n, 1),
+                                      ctypes.byref(nn)), "tril_dbg_target_rows")
+    return rows[: nn.value]
+
+
+def tril_dbg_query_records(ctx, s: int, n: int):
+    """Query boxes of step offset s of the last step batch, formed from the batch's
+    per-row records as the traversal forms them, in the caller's row order."""
+    ctx = _h(ctx)
+    boxes = np.zeros((max(n, 1), 8), dtype=np.float32)
+    nn = ctypes.c_int64(0)
+    _check(lib().tril_dbg_query_records(ctx, int(s), boxes.ctypes.data, max(n, 1),
+                                        ctypes.byref(nn)), "tril_dbg_query_records")
+    boxes = boxes[: nn.value]
+    ints = boxes.view(np.int32)
+    return {"lo": boxes[:, 0:3].copy(), "hi": boxes[:, 4:7].copy(), "tag": ints[:, 3].copy()}
 
 
 def tril_dbg_candidates(ctx, cap: int = 1 << 22):

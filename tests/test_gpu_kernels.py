@@ -360,3 +360,49 @@ def test_candidates_equal_bruteforce_box_overlap(torch):
     ref = set(zip(*[x.tolist() for x in np.nonzero(ov)]))
     assert got == ref
     assert cnt > 10
+
+
+SIGMA_MAX_UM2 = 1.7006316535613484e-17  # largest Breit-Wheeler cross-section (mpmath pin)
+
+
+def test_batched_boxes_contain_segments_far_from_origin(torch):
+    """Step batches form every step's box in FP32 from the batch's first step (leaves in
+    the refit, queries in the traversal) with a proven widening. Far from the origin
+    (|x| ~ 1e3 um, where one FP32 ulp is ~6e-5 um) and over a 48-step batch, each step's
+    target leaf box must contain both ends of the photon's FP64 segment over the step, and
+    each query box both ends widened by an upper bound of the photon's collision radius
+    with any target photon."""
+    wl, A, B = _small_beams(n=2000, boost=3e4)
+    shift = np.array([1000.0, -700.0, 900.0])
+    for X in (A, B):
+        for a, f in enumerate(("x", "y", "z")):
+            X[f] = X[f] + shift[a]
+    m, k0 = 48, 176
+    ctx = T.Context(wl.dt, step_batch=m)
+    pairs = T.Pairs(1 << 16)
+    ctx.run(T.Beam(B), T.Beam(A), k0, m, pairs)
+    nB, nA = len(B["E"]), len(A["E"])
+    boxes = T.tril_dbg_boxes(ctx, 0, m * nB)
+    rows = T.tril_dbg_target_rows(ctx, nB)
+    qboxes = [T.tril_dbg_query_records(ctx, s, nA) for s in range(m)]
+    ctx.close()
+    assert sorted(rows.tolist()) == list(range(nB))
+    XB = np.c_[B["x"], B["y"], B["z"]][rows]
+    UB = (np.c_[B["px"], B["py"], B["pz"]] / B["E"][:, None])[rows]
+    XA = np.c_[A["x"], A["y"], A["z"]]
+    UA = np.c_[A["px"], A["py"], A["pz"]] / A["E"][:, None]
+    rA = np.sqrt(np.sqrt(A["w"] * B["w"].max()) * SIGMA_MAX_UM2 / np.pi)
+    for s in range(m):
+        t = (k0 + s) * wl.dt
+        lo = boxes["lo"][s * nB:(s + 1) * nB].astype(np.float64)
+        hi = boxes["hi"][s * nB:(s + 1) * nB].astype(np.float64)
+        q = qboxes[s]
+        live = q["tag"] >= 0
+        qlo, qhi = q["lo"].astype(np.float64), q["hi"].astype(np.float64)
+        for tau in (0.0, wl.dt):
+            P = XB + (t + tau) * UB
+            assert np.all(lo <= P) and np.all(hi >= P), (s, tau)
+            Q = XA + (t + tau) * UA
+            assert np.all(qlo[live] <= Q[live] - rA[live, None]), (s, tau)
+            assert np.all(qhi[live] >= Q[live] + rA[live, None]), (s, tau)
+    assert live.sum() > 0.5 * nA

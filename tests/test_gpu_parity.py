@@ -210,6 +210,28 @@ def test_invalid_photon_data_reported(torch):
     assert st["code"] == T.TRIL_E_DATA
 
 
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("rel,rejected", [(1e-9, True), (-3e-12, True), (1e-13, False),
+                                          (-1e-13, False)])
+def test_momentum_off_shell_reported(torch, graph, rel, rejected):
+    """A photon's momentum magnitude must equal its energy (c = 1) to 1e-12 relative:
+    one photon of either beam scaled off the light cone by rel is rejected as bad data,
+    one within the bound is accepted."""
+    wl = beams.mono_headon_2k(n=100)
+    A, B = beams.draw_pair(wl)
+    for X, row in ((B, 17), (A, 53)):
+        for f in ("px", "py", "pz"):
+            X[f][row] *= 1.0 + rel
+        ctx = T.Context(wl.dt, EDGES)
+        pairs = T.Pairs(1024)
+        T.run_steps(ctx, T.Beam(B), T.Beam(A), 3, pairs, graph=graph)
+        st = ctx.stats(pairs, check=False)
+        ctx.close()
+        assert (st["code"] == T.TRIL_E_DATA) == rejected, (rel, st["code"])
+        for f in ("px", "py", "pz"):
+            X[f][row] /= 1.0 + rel
+
+
 def test_counters_and_threshold_prune(torch):
     wl, A, B = _gauss_small(4000, 1e3, seed=5)
     ctx = T.Context(wl.dt, EDGES)

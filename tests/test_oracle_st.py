@@ -145,3 +145,33 @@ def test_table_adds_up_to_total():
     tab, tot = SO.st_table(A, ba, B, bb, ga.n_bins, 0.1, 0, 40, cell)
     assert len(tab) > 5
     assert sum(tab.values()) == pytest.approx(tot, rel=1e-12)
+
+
+def test_table_keys_two_by_two_bins_closed_form():
+    """Hand-built keying of the bin-pair table: query photons of bins 3 and 7, target
+    photons of bins 1 and 5, with 11 target bins, so the keys are 3*11+1 = 34, 38, 78 and
+    82 (a swapped key b*n + a, or a stride other than the target's bin count, gives other
+    numbers). All four clouds meet head-on in one step, fully overlapping, so each pair's
+    yield is the single-step closed form w_i w_j sigma(s_ij) (1 - cos pi) dt / V with
+    s_ij = 2 E_i E_j / (2 m_e^2); the four yields differ, so a key mapped to the wrong pair
+    of photons fails too."""
+    dt, k = 0.1, 7
+    t_star = k * dt + 0.5 * dt
+    cell = (1.0, 1.0, 0.15)
+    Ea, wa = [2.0, 3.0], [3.0e5, 5.0e5]
+    Eb, wb = [2.0, 4.0], [7.0e5, 2.0e5]
+    A = _beam([[0.0, 0.0, -t_star]] * 2, [[0.0, 0.0, e] for e in Ea], Ea, wa)
+    B = _beam([[0.0, 0.0, t_star]] * 2, [[0.0, 0.0, -e] for e in Eb], Eb, wb)
+    bins_a, bins_b = np.array([3, 7]), np.array([1, 5])
+    tab, tot = SO.st_table(A, bins_a, B, bins_b, 11, dt, 0, 20, cell)
+    V = cell[0] * cell[1] * cell[2]
+    expect = {}
+    for i in range(2):
+        for j in range(2):
+            s = Ea[i] * Eb[j] * 2.0 / (2.0 * ME * ME)
+            expect[int(bins_a[i]) * 11 + int(bins_b[j])] = wa[i] * wb[j] * O.sigma(s) * 2.0 * dt / V
+    assert sorted(tab) == [34, 38, 78, 82]
+    for key, y in expect.items():
+        assert tab[key] == pytest.approx(y, rel=1e-13), key
+    assert len(set(round(v / max(expect.values()), 12) for v in expect.values())) == 4
+    assert tot == pytest.approx(sum(expect.values()), rel=1e-13)
