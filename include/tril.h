@@ -260,6 +260,26 @@ int tril_pair_kinematics(tril_ctx *ctx, const tril_beam *query, const tril_beam 
                          const tril_pairs *pairs, int64_t n, const tril_kin_params *params,
                          double *leptons, tril_kin_out *out);
 
+/* tril_pair_kinematics for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): no context, no
+ * allocation, no synchronisation; everything is enqueued on `stream`. Its scratch (the
+ * histogram accumulators, an error flag and up to 2^18 packed photon records, 16 MiB in
+ * all) is a device array inside the library that every device holds from the first call
+ * on it until the process ends; calls that overlap on one device share it and race.
+ * Same leptons and histograms as tril_pair_kinematics for the same arguments (histogram
+ * sums up to their order); when the two beams together hold more than 2^18 photons the
+ * kernel reads them unpacked. gamma_edges: device, n_gamma + 1 finite, strictly
+ * increasing; gamma_hist (n_gamma) and theta_hist (n_theta): device, caller-owned,
+ * overwritten; status: device int32, receives TRIL_OK, or TRIL_E_INVAL when the edges are
+ * not increasing or a pair names a row outside its beam or a negative step (such pairs are
+ * skipped). Returns TRIL_E_INVAL for bad arguments (including n_gamma or n_theta above
+ * TRIL_KIN_MAX_BINS, the bins its accumulators hold), TRIL_E_HIP for a launch failure. */
+int tril_pair_kinematics_noalloc(const tril_beam *query, const tril_beam *target,
+                                 const tril_pairs *pairs, int64_t n, uint64_t seed,
+                                 int32_t n_gamma, const double *gamma_edges, int32_t n_theta,
+                                 double *leptons, double *gamma_hist, double *theta_hist,
+                                 int32_t *status, void *hip_stream);
+
 /* Launch configuration of tril_run (performance only: the results do not depend on it). */
 typedef struct {
     int32_t block_traverse;       /* traversal workgroup size: 64, 128, 256 or 512 */

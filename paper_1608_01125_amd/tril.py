@@ -110,7 +110,7 @@ class tril_kin_out(ctypes.Structure):
 TRIL_KIN_MAX_BINS = 2048
 
 EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats",
-           "tril_pair_kinematics",
+           "tril_pair_kinematics", "tril_pair_kinematics_noalloc",
            "tril_autotune", "tril_set_tune", "tril_st_bin", "tril_st_exact",
            "tril_st_exact_depleted", "tril_ip_swarm",
            "tril_mlp_create", "tril_mlp_destroy", "tril_mlp_set_params", "tril_mlp_get_params",
@@ -140,6 +140,9 @@ def lib() -> ctypes.CDLL:
     L.tril_run.argtypes = [vp, ctypes.POINTER(tril_beam), ctypes.POINTER(tril_beam), i32, i32,
                            ctypes.POINTER(tril_pairs)]
     L.tril_stats.argtypes = [vp, ctypes.POINTER(tril_pairs), ctypes.POINTER(tril_stats_t)]
+    L.tril_pair_kinematics_noalloc.argtypes = [ctypes.POINTER(tril_beam), ctypes.POINTER(tril_beam),
+                                               ctypes.POINTER(tril_pairs), i64, ctypes.c_uint64,
+                                               i32, vp, i32, vp, vp, vp, vp, vp]
     L.tril_pair_kinematics.argtypes = [vp, ctypes.POINTER(tril_beam), ctypes.POINTER(tril_beam),
                                        ctypes.POINTER(tril_pairs), i64,
                                        ctypes.POINTER(tril_kin_params), vp,
@@ -358,6 +361,24 @@ def tril_pair_kinematics(ctx, query: Beam, target: Beam, pairs: Pairs, n: int, s
         _check(code, "tril_pair_kinematics")
     return {"code": code, "leptons": lep[:int(n)] if lep is not None else None,
             "gamma_hist": gh[:kp.n_gamma], "theta_hist": th[:kp.n_theta], "ms": out.ms_kernel}
+
+
+def tril_pair_kinematics_noalloc(query: Beam, target: Beam, pairs: Pairs, n: int, seed: int,
+                                 gamma_edges, gamma_hist, n_theta: int, theta_hist, leptons,
+                                 status, stream=None) -> int:
+    """The no-allocation variant: every array is a caller-owned device tensor (gamma_edges
+    float64 n_gamma + 1 or None, gamma_hist float64 n_gamma, theta_hist float64 n_theta,
+    leptons float64 (n, 8) or None, status int32 (1,)); asynchronous on the stream.
+    Returns the call's return code (the device status lands in `status`)."""
+    n_gamma = 0 if gamma_edges is None else int(gamma_edges.numel()) - 1
+    return lib().tril_pair_kinematics_noalloc(
+        ctypes.byref(query.c), ctypes.byref(target.c), ctypes.byref(pairs.c), int(n),
+        int(seed) & ((1 << 64) - 1), n_gamma,
+        gamma_edges.data_ptr() if gamma_edges is not None else None, int(n_theta),
+        leptons.data_ptr() if leptons is not None else None,
+        gamma_hist.data_ptr() if gamma_hist is not None else None,
+        theta_hist.data_ptr() if theta_hist is not None else None, status.data_ptr(),
+        _stream(stream))
 
 
 TUNE_KEYS = ("block_traverse", "step_batch", "morton_bits")
