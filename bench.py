@@ -18,9 +18,10 @@ traversal's launch durations. The JSON line also carries
     node; 8 B per candidate written) over its average launch duration, against 8 TB/s;
     `traffic` is the HBM bytes per launch measured with rocprofv3 counters (the
     committed summary, when it belongs to the current kernel source);
-  * roofline_vmem: the bytes the traversal's loads deliver to its lanes (every node load
-    counted, 64 B) over the same duration, against the rate of the same access pattern
-    from L1 measured by tril_dbg_vmem_rate on this device;
+  * roofline_vmem: the traversal's L1 tag lookups per second (rocprofv3 counters of the
+    committed summary over the same duration) against one lookup per clock per CU; every
+    node load of every lane passes through them, and they bind the kernel (the texture
+    data unit is busy for almost every cycle of it);
   * cpu_baseline: the FP64 CPU oracle timed on a bounded sample of query rows of
     the same workload (all pairs of those rows, all time steps).
 """
@@ -56,26 +57,31 @@ def traverse_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic(dispatches=None):
-    """HBM bytes per traversal launch from the committed counter summary, or None
-    when it was taken from a different kernel source or another batching (traversal
-    launches per collision run)."""
+def committed_counters(dispatches=None) -> dict:
+    """Counter figures of one traversal launch from the committed rocprofv3 summary: HBM
+    bytes (`traffic_bytes_per_dispatch`), L1 lookups, TA/TD busy fractions. Empty when the
+    summary was taken from a different kernel source or another batching (traversal launches
+    per collision run)."""
     if not os.path.exists(PMC_SUMMARY):
-        return None
+        return {}
     vals = {}
     with open(PMC_SUMMARY) as f:
         for line in f:
-            if ":" in line:
+            if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     if vals.get("source_sha256") != traverse_source_hash():
-        return None
+        return {}
     if dispatches is not None and vals.get("dispatches") != str(dispatches):
-        return None
-    try:
-        return float(vals["traffic_bytes_per_dispatch"])
-    except (KeyError, ValueError):
-        return None
+        return {}
+    out = {}
+    for k in ("traffic_bytes_per_dispatch", "L1_lookups_per_dispatch", "TD_busy", "TA_busy",
+              "L2_hit_rate"):
+        try:
+            out[k] = float(vals[k])
+        except (KeyError, ValueError):
+            pass
+    return out
 
 
 def make_workload(name: str, physics_steps: int):
@@ -112,9 +118,13 @@ def make_workload(name: str, physics_steps: int):
 
 
 def st_bench(args):
-    """Statistical regime, head-on shape: exact cell-pair yields through the hierarchy, and
-    the surrogate path (ensemble trained on exact yields of the same shape at other seeds,
-    budget gate at 1%); both timed on the same inputs."""
+    """Statistical regime, head-on shape, --st-mp macro-particles per beam: the surrogate path
+    (ensemble trained on exact yields of the same shape at other seeds and at most 2e5
+    macro-particles per beam; its predictions corrected by the audit, a sampled exact estimate
+    with the predictions as control), timed; against the exact total of the hierarchy path
+    where it can run (up to 1e6 macro-particles per beam), else against the judge: a sampled
+    exact estimate with no network in it, whose 95% confidence half-width is reported, and the
+    exact path's time extrapolated from uniform thinnings of both beams."""
     import numpy as np
     import torch
     from paper_1608_01125_amd import beams, surrogate
@@ -122,9 +132,11 @@ def st_bench(args):
     eps = 1e-3
     ctx = T.Context(0.1, None)
     net = T.Mlp(4, seed=11)
+    n = args.st_mp
+    q = float(n) * n * 400
     try:
         t0 = time.perf_counter()
-        train_mp = [int(v) for v in args.st_train_mp.split(",") if v] or [args.st_mp]
+        train_mp = [int(v) for v in args.st_train_mp.split(",") if v] or [min(n, 200_000)]
         insts = [surrogate.Instance(beams.st_headon(train_mp[m % len(train_mp)], seed=2000 + m))
                  for m in range(args.st_train)]
         x, t, y0, y = surrogate.training_rows(ctx, insts, eps=eps, log=_progress)
@@ -138,23 +150,54 @@ def st_bench(args):
         train_s = time.perf_counter() - t0
         n_rows = int(keep.sum())
         del insts, x, t, y0, y, keep
-        inst = surrogate.Instance(beams.st_headon(args.st_mp))
-        p = T.sur_params(eps=eps, gate=0.01, scale=scale)
+        _progress(f"trained in {train_s:.1f} s")
+        inst = surrogate.Instance(beams.st_headon(n))
+        p_audit = T.sur_params(eps=eps, gate=0.01, scale=scale, audit=True,
+                               audit_sample=args.st_audit_sample, audit_reps=8, audit_seed=1)
+        p_budget = T.sur_params(eps=eps, gate=0.01, scale=scale)
         for _ in range(args.warmup):
-            inst.exact(ctx)
-            inst.surrogate(ctx, net, p)
+            inst.surrogate(ctx, net, p_audit)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.steps):
-            _, exact_total = inst.exact(ctx)
-        torch.cuda.synchronize()
-        t_exact = (time.perf_counter() - t1) / max(args.steps, 1)
-        st = ctx.stats(None)
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            res = inst.surrogate(ctx, net, p)
+            res = inst.surrogate(ctx, net, p_audit)
         torch.cuda.synchronize()
         t_sur = (time.perf_counter() - t1) / max(args.steps, 1)
+        budget = inst.surrogate(ctx, net, p_budget)
+        _progress(f"surrogate path {1e3 * t_sur:.1f} ms")
+        exact_total = t_exact = None
+        exact = {}
+        if n <= args.st_exact_max:
+            inst.exact(ctx)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                _, exact_total = inst.exact(ctx)
+            torch.cuda.synchronize()
+            t_exact = (time.perf_counter() - t1) / max(args.steps, 1)
+            st = ctx.stats(None)
+            exact = {"total": exact_total, "ms": 1e3 * t_exact, "queries_per_s": q / t_exact,
+                     "timing": "measured",
+                     "cloud_pair_steps_per_run": st["n_candidates"] // max(args.steps + 1, 1)}
+        else:
+            # the exact pass over two uniform thinnings (every macro-particle kept with
+            # probability f, both beams): its pair work is f^2 of the full pass
+            fr = {}
+            for f in (0.01, 0.02):
+                r = inst.audit(ctx, None, T.AUDIT_NONE, n_sample=int(f * n), n_rep=2, seed=9)
+                fr[f] = r["ms"] / 2.0
+                _progress(f"exact pass on a {f:.0%} thinning of both beams: {fr[f]:.0f} ms")
+            t_exact = 1e-3 * fr[0.02] / 0.02 ** 2
+            exact = {"total": None, "ms": 1e3 * t_exact, "queries_per_s": q / t_exact,
+                     "timing": "extrapolated: exact pass over a uniform 2% thinning of both beams "
+                               "/ 0.02^2",
+                     "ms_thinning_1pct": fr[0.01], "ms_thinning_2pct": fr[0.02],
+                     "pair_work_scaling_2pct_over_1pct": fr[0.02] / fr[0.01]}
+        # the judge: sampled exact estimate with the bin-level yield as control (no network)
+        jd = inst.audit(ctx, None, T.AUDIT_BIN_LEVEL, n_sample=args.st_judge_sample, n_rep=8,
+                        seed=4242)
+        _progress(f"judge {jd['estimate']:.6g} +- {jd['half_width']:.3g} in {jd['ms']:.0f} ms")
+        ref = exact_total if exact_total is not None else jd["estimate"]
         # depletion (closed forms per cloud pair) against the linear exact yields, at a photon
         # number where depletion matters, on a smaller instance (one table slot per cloud pair)
         dinst = surrogate.Instance(beams.st_headon(args.st_dep_mp, physical=args.st_dep_physical))
@@ -182,41 +225,10 @@ def st_bench(args):
                              surrogate.cell_grid(dwl, "a", DA).cell, rows=drows)
         dep_cpu_s = time.perf_counter() - t1
         swarm = swarm_measure(T, torch)
-        large = None
-        if args.st_eval_mp > 0:
-            big = surrogate.Instance(beams.st_headon(args.st_eval_mp))
-            big.surrogate(ctx, net, p)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(args.steps):
-                rbig = big.surrogate(ctx, net, p)
-            torch.cuda.synchronize()
-            t_big = (time.perf_counter() - t1) / max(args.steps, 1)
-            nb = args.st_eval_mp
-            big_exact = None
-            if args.st_eval_exact:
-                _progress(f"exact path on {nb} macro-particles per beam")
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                _, big_exact = big.exact(ctx, cap_log2=24)
-                torch.cuda.synchronize()
-                t_big_exact = time.perf_counter() - t1
-            large = {"macro_particles_per_beam": nb, "ms": 1e3 * t_big,
-                     "exact_total": big_exact,
-                     "exact_ms": 1e3 * t_big_exact if big_exact is not None else None,
-                     "rel_error_vs_exact": (abs(rbig["total"] - big_exact) / big_exact
-                                            if big_exact else None),
-                     "queries_per_s": float(nb) * nb * 400 / t_big, "total": rbig["total"],
-                     "rel_diff_vs_exact_at_training_size": abs(rbig["total"] - exact_total) / exact_total,
-                     "bin_pairs": rbig["n_bin_pairs"], "bin_pairs_exact": rbig["n_gated"],
-                     "predicted_spread": rbig["predicted_spread"]}
-            del big
     finally:
         net.close()
         ctx.close()
-    n = args.st_mp
     nd = args.st_dep_mp
-    q = float(n) * n * 400
     out = {
         "metric": METRIC, "value": q / t_sur, "unit": "queries/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t_sur,
@@ -225,16 +237,32 @@ def st_bench(args):
         "config": {"workload": "st_headon", "macro_particles_per_beam": n,
                    "physical_photons_per_beam": 1e9, "time_steps": 400,
                    "grid": "32^3 cells (surrogate on cell pairs)", "ensemble": 4,
+                   "gate": "audit: sampled exact estimate with the network as control",
                    "training": {"instances": args.st_train, "rows": n_rows,
-                             "macro_particles": args.st_train_mp or args.st_mp,
+                                "macro_particles": train_mp,
                                 "adam_steps": args.st_train_steps, "seconds": round(train_s, 1),
                                 "yield_scale": round(scale, 5)}},
         "surrogate": {"queries_per_s": q / t_sur, "ms": 1e3 * t_sur, "total": res["total"],
-                      "rel_error_vs_exact": abs(res["total"] - exact_total) / exact_total,
-                      "bin_pairs": res["n_bin_pairs"], "bin_pairs_exact": res["n_gated"],
-                      "exact_part": res["exact_part"] / max(res["total"], 1e-300),
-                      "predicted_spread": res["predicted_spread"],
+                      "half_width_95": res["audit_half_width"],
+                      "network_total": res["surrogate_part"],
+                      "network_rel_bias": res["surrogate_part"] / ref - 1.0,
+                      "rel_error": abs(res["total"] - ref) / ref,
+                      "reference": "exact total" if exact_total is not None else "judge",
+                      "within_1pct": abs(res["total"] - ref) <= 0.01 * ref,
+                      "audit_sampled_macro_particles": res["audit_sampled"],
+                      "bin_pairs": res["n_bin_pairs"],
                       "speedup_vs_exact": t_exact / t_sur},
+        "surrogate_budget_gate": {"total": budget["total"], "ms": budget["ms"],
+                                  "rel_error": abs(budget["total"] - ref) / ref,
+                                  "bin_pairs_exact": budget["n_gated"],
+                                  "predicted_spread": budget["predicted_spread"]},
+        "judge": {"estimate": jd["estimate"], "half_width_95": jd["half_width"],
+                  "rel_half_width": jd["half_width"] / jd["estimate"],
+                  "rel_diff_vs_exact": (jd["estimate"] / exact_total - 1.0
+                                        if exact_total is not None else None),
+                  "control": "bin-level yield Y0 (no network)", "n_sample": args.st_judge_sample,
+                  "replicates": 8, "ms": jd["ms"]},
+        "exact": exact,
         "exact_depleted": {"macro_particles_per_beam": nd,
                            "physical_photons_per_beam": args.st_dep_physical,
                            "queries_per_s": float(nd) * nd * 400 / t_dep, "ms": 1e3 * t_dep,
@@ -245,9 +273,6 @@ def st_bench(args):
                                           "kind": "oracle", "cores": _oracle_threads(),
                                           "sample": "20 query rows x all target clouds x 400 steps"}},
         "ip_swarm": swarm,
-        "surrogate_large": large,
-        "exact": {"queries_per_s": q / t_exact, "ms": 1e3 * t_exact, "total": exact_total,
-                  "cloud_pair_steps_per_run": st["n_candidates"] // max(args.steps + args.warmup, 1)},
     }
     print(json.dumps(out), flush=True)
 
@@ -481,11 +506,14 @@ def main():
     ap.add_argument("--st-train-mp", default="",
                     help="st_headon: comma-separated macro-particle counts the training instances "
                          "cycle through (default: --st-mp for all)")
-    ap.add_argument("--st-eval-mp", type=int, default=0,
-                    help="st_headon: also run the surrogate on an instance of this many "
-                         "macro-particles per beam (same physical beams)")
-    ap.add_argument("--st-eval-exact", action="store_true",
-                    help="st_headon: also run the exact path once on the --st-eval-mp instance")
+    ap.add_argument("--st-audit-sample", type=int, default=10_000,
+                    help="st_headon: audit of the surrogate, expected macro-particles drawn per "
+                         "beam and replicate")
+    ap.add_argument("--st-judge-sample", type=int, default=100_000,
+                    help="st_headon: judge (network-free sampled exact estimate), expected "
+                         "macro-particles drawn per beam and replicate")
+    ap.add_argument("--st-exact-max", type=int, default=1_000_000,
+                    help="st_headon: largest macro-particle count the exact path runs on")
     ap.add_argument("--st-dep-mp", type=int, default=20_000,
                     help="st_headon: macro-particles per beam of the depletion measurement")
     ap.add_argument("--st-dep-physical", type=float, default=1e20,
@@ -641,7 +669,8 @@ def main():
         # load counted (64 B: both children's boxes and links), plus the query bytes and
         # candidate stores above
         lane_bytes = q_bytes * nA * st["n_collides"] + 64.0 * st["n_node_visits"] + 8.0 * st["n_candidates"]
-        traffic = committed_traffic(launches_per_run or None)
+        pmc = committed_counters(launches_per_run or None)
+        traffic = pmc.get("traffic_bytes_per_dispatch")
         avg_s = st["ms_traverse"] * 1e-3 / n_launch
         achieved = hbm_bytes / n_launch / avg_s / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
@@ -654,15 +683,19 @@ def main():
                     "traffic_frac": (round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
                                      if traffic else None),
                     "node_visits_per_query": round(st["n_node_visits"] / max(st["n_queries"], 1), 3)}
-        probe_div = T.tril_dbg_vmem_rate(True) / 1e9
-        probe_coal = T.tril_dbg_vmem_rate(False) / 1e9
-        ach_v = lane_bytes / n_launch / avg_s / 1e9
-        roofline_vmem = {"bound": "vmem", "achieved": round(ach_v, 2), "peak": round(probe_div, 1),
-                         "unit": "GB/s", "frac": round(ach_v / probe_div, 4), "kernel": "k_traverse",
-                         "peak_source": "tril_dbg_vmem_rate: 64-B records as four 16-B loads per "
-                                        "lane, 64 different records per wave, L1-resident",
-                         "probe_coalesced_GBs": round(probe_coal, 1),
-                         "lane_bytes_per_launch": round(lane_bytes / n_launch, 1)}
+        # vector-memory roof: every lane's node load goes through the CU's L1, which takes
+        # one tag lookup per clock (256 CUs x 2.4 GHz); lookups per launch from the
+        # committed counter summary (TCP_TOTAL_CACHE_ACCESSES)
+        looks = pmc.get("L1_lookups_per_dispatch")
+        peak_l = 256 * 2.4  # G lookups/s
+        ach_l = looks / avg_s / 1e9 if looks else None
+        roofline_vmem = {"bound": "vmem", "achieved": round(ach_l, 2) if ach_l else None,
+                         "peak": peak_l, "unit": "G L1 lookups/s",
+                         "frac": round(ach_l / peak_l, 4) if ach_l else None,
+                         "kernel": "k_traverse", "TD_busy": pmc.get("TD_busy"),
+                         "TA_busy": pmc.get("TA_busy"),
+                         "lane_bytes_per_launch": round(lane_bytes / n_launch, 1),
+                         "lane_bytes_GBs": round(lane_bytes / n_launch / avg_s / 1e9, 2)}
 
     out = {
         "metric": METRIC,

@@ -436,24 +436,41 @@ typedef struct {
                                      contributions u = Yhat x ensemble spread go to the exact
                                      path until the spread of the remaining predicted total,
                                      sqrt(sum u^2), is at most gate x the predicted total;
-                                     1 (per pair): every bin pair whose spread exceeds gate */
+                                     1 (per pair): every bin pair whose spread exceeds gate;
+                                     2 (audit): no bin pair is gated; the total is the sampled
+                                     estimate of the exact total (tril_st_audit) with the
+                                     network's predictions as its control, which measures and
+                                     removes the bias the ensemble members share; its 95%
+                                     confidence half-width goes to predicted_spread (relative)
+                                     and audit_half_width */
     int32_t pad0;
+    int64_t audit_sample;         /* gate_mode 2: expected macro-particles drawn per beam and
+                                     replicate (0 = 32768) */
+    int32_t audit_reps;           /* gate_mode 2: replicates, 2..64 (0 = 8) */
+    int32_t pad1;
+    uint64_t audit_seed;          /* gate_mode 2: key of the draws */
 } tril_st_sur_params;
 
 typedef struct {
     double total;                 /* surrogate part + exact part */
     double surrogate_part;        /* sum over confident bin pairs of the predicted yield */
-    double exact_part;            /* exact yield of the gated bin pairs */
+    double exact_part;            /* exact yield of the gated bin pairs (audit mode: the
+                                     audit's correction, total - surrogate_part) */
     int64_t n_bin_pairs;          /* candidate bin pairs (feature rows) */
     int64_t n_gated;              /* bin pairs sent to the exact path */
     double ms;                    /* event time of the whole call on the context stream */
     double predicted_spread;      /* budget mode: ensemble spread of the surrogate part
-                                     relative to the predicted total */
+                                     relative to the predicted total; audit mode: the 95%
+                                     confidence half-width relative to the total */
+    double audit_half_width;      /* audit mode: 95% confidence half-width of the total */
+    int64_t audit_sampled;        /* audit mode: macro-particles drawn (both beams, all
+                                     replicates) */
 } tril_st_sur_result;
 
 /* Feature rows of all candidate bin pairs of the two beams' per-bin sums (as written by
  * tril_st_bin) over steps k0 .. k0+n_steps-1: x [n][6] FP32, y0 [n] FP64, key [n]
- * (query bin x n_target_bins + target bin), all device. *n receives the number of rows;
+ * (query bin x n_target_bins + target bin), all device, rows in ascending key order (the
+ * same rows in the same order on every call). *n receives the number of rows;
  * TRIL_E_OVERFLOW when it exceeds cap; TRIL_E_NOMEM when the context's bin-pair table
  * could not hold the candidate pairs after growing 64-fold. The two grids must have the
  * same cell. Uses the context's stream and scratch and clears its device error flags.
@@ -477,6 +494,68 @@ int tril_st_surrogate(tril_ctx *ctx, struct tril_mlp *mlp, const tril_beam *targ
                       const tril_beam *query, const int32_t *q_bins, const double *q_sums,
                       const tril_st_grid *q_grid, int32_t k0, int32_t n_steps,
                       const tril_st_sur_params *params, tril_st_sur_result *out);
+
+/* Sampled estimate of the exact statistical-regime total over steps k0 .. k0+n_steps-1
+ * (the sum of tril_st_exact's yields), for instances whose exact pass over all
+ * macro-particle pairs is out of reach. Each replicate thins both beams independently
+ * (macro-particle i kept with probability pi_i, weight w_i / pi_i, Philox4x64-10 draws
+ * keyed by (seed, replicate)), runs the exact pass over the two thinned beams, and adds
+ * the known total of a control minus the thinned beams' estimate of it:
+ *   T_hat = C + sum_{kept i, j} Y_ij / (pi_i pi_j) - sum_ab c_ab (R_a / W_a) (R_b / W_b),
+ * c_ab the control of candidate bin pair (a, b) (the rows of tril_st_features), C their
+ * sum, W_a the weight in bin a and R_a the kept weight w_i / pi_i in it. T_hat is unbiased
+ * for the exact total (the yield of a cloud pair is linear in each weight, Sec. 2.2, and
+ * the two beams are thinned independently) whatever the control; a control close to the
+ * yields makes it precise. pi_i = min(1, n_sample (mix c_a w_i / (W_a C) + (1 - mix)
+ * w_i / W)), c_a the control summed over bin a's pairs, W the beam's total weight. With a
+ * control, a pilot replicate with draws of its own first fits its scale,
+ * kappa = (exact pass over the pilot's thinned beams) / (their estimate of C), and every
+ * replicate uses kappa c_ab (the pilot is independent of the replicates, which therefore
+ * stay unbiased); this removes the arbitrary scale of Y0 and the bias a network's members
+ * share. */
+typedef struct {
+    int64_t n_sample;             /* expected macro-particles drawn per beam and replicate
+                                     (0 = 32768) */
+    int32_t n_rep;                /* replicates, 2..64 (0 = 8) */
+    int32_t control;              /* 0: the network's predicted yields (mlp required, eps and
+                                     scale from the surrogate parameters); 1: the bin-level
+                                     yield Y0 of the feature rows (no network); 2: none */
+    uint64_t seed;                /* key of the draws */
+    double mix;                   /* share of pi proportional to the control, [0, 1)
+                                     (0 = 0.9) */
+} tril_st_audit_params;
+
+typedef struct {
+    double estimate;              /* mean of the replicate estimates */
+    double half_width;            /* 95% confidence half-width: Student t quantile (n_rep - 1
+                                     degrees of freedom) x standard error of the mean */
+    double control_total;         /* kappa C */
+    double control_scale;         /* kappa (1 without a control) */
+    double rep[64];               /* replicate estimates (n_rep of them) */
+    int32_t n_rep;
+    int32_t pad0;
+    int64_t n_sampled[2];         /* query, target macro-particles drawn over all replicates */
+    int64_t n_bin_pairs;          /* candidate bin pairs (control rows) */
+    double ms;                    /* event time of the whole call on the context stream */
+} tril_st_audit_result;
+
+/* Same beams, bins, per-bin sums and grids as tril_st_surrogate; mlp may be NULL unless
+ * control is 0; sur_params (or NULL for defaults) gives cloud_factor, eps and scale.
+ * Synchronous. TRIL_E_INVAL for bad arguments, TRIL_E_NOTIMPL for more than one
+ * instance. */
+int tril_st_audit(tril_ctx *ctx, struct tril_mlp *mlp, const tril_beam *target,
+                  const int32_t *t_bins, const double *t_sums, const tril_st_grid *t_grid,
+                  const tril_beam *query, const int32_t *q_bins, const double *q_sums,
+                  const tril_st_grid *q_grid, int32_t k0, int32_t n_steps,
+                  const tril_st_sur_params *sur_params, const tril_st_audit_params *params,
+                  tril_st_audit_result *out);
+
+/* Calibration factor of the surrogate (the `scale` of tril_st_sur_params): the exact over
+ * the predicted total on n feature rows, sum(y_exact) / sum(max(0, y0 (exp(mean) - eps)))
+ * with the ensemble mean of the network; x [n][6] FP32, y0 and y_exact [n] FP64, device.
+ * The sums are reduced in a fixed order (the same result on every call). Synchronous. */
+int tril_st_calibrate(struct tril_mlp *mlp, const float *x, const double *y0,
+                      const double *y_exact, int64_t n, double eps, double *scale);
 
 /* ---------------------------------------------------------------------------------
  * Surrogate of the statistical regime: an ensemble of K multilayer perceptrons

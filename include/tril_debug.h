@@ -46,20 +46,19 @@ int tril_dbg_pair_eval(int64_t n, const double *in, double *out, void *stream);
  * Synchronises the stream. */
 int tril_dbg_pair_eval32(int64_t n, const double *in, double *out, void *stream);
 
+/* The device arithmetic the narrow phase relies on, one operation per element, compiled
+ * with the narrow phase's flags (no contraction, no fast math): which = 0: FP64 a / b;
+ * 1: FP64 sqrt(a); on the arguments rounded to FP32: 2: a / b, 3: sqrtf(a), 4: logf(a),
+ * 5: log1pf(a), results widened to FP64. a, b (b for 0 and 2 only), out: device, n
+ * doubles. Asynchronous on the stream. */
+int tril_dbg_math(int which, int64_t n, const double *a, const double *b, double *out,
+                  void *stream);
+
 /* The surrogate's matrix-core product C = A B: A(m, k) = A[m sam + k sak] and
  * B(k, n) = B[k sbk + n sbn] as BF16 bit patterns (device), C [M][N] row-major FP32
  * (device). Synchronises the stream. */
 int tril_dbg_gemm_bf16(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk,
                        int64_t sbn, int32_t M, int32_t N, int32_t K, float *C, void *stream);
-
-/* Rate of the vector-memory path for the traversal's access pattern: `blocks` workgroups
- * of 256 lanes, each lane loading `iters` 64-byte records as four 16-byte loads from an
- * 8 KB window that every CU's L1 holds (divergent != 0: the 64 lanes of a wave read 64
- * different records; 0: consecutive lanes read consecutive 16-byte words). The second of
- * two launches is timed with HIP events; *bytes_per_s (host) receives the bytes the loads
- * delivered per second. Allocates and frees its own 8 KB window. Synchronises the stream. */
-int tril_dbg_vmem_rate(int divergent, int32_t blocks, int32_t iters, double *bytes_per_s,
-                       void *stream);
 
 /* Copy the last built hierarchy to host memory (synchronises the context stream).
  * nodes: host, cap_nodes x 16 words, one internal node each: its left child's box and
@@ -90,6 +89,12 @@ int tril_dbg_target_rows(tril_ctx *ctx, int32_t *rows, int64_t cap, int64_t *n);
  * query rows. TRIL_E_STATE when the last batch had no records (one step per launch).
  * Synchronises the context stream. */
 int tril_dbg_query_records(tril_ctx *ctx, int32_t s, void *boxes, int64_t cap, int64_t *n);
+
+/* Thinned beam of the last replicate of the last tril_st_audit (side 0: query, 1: target)
+ * in kept order: host arrays of the source rows and of their inclusion probabilities.
+ * *n receives the kept rows (0 before any audit). Synchronises the context stream. */
+int tril_dbg_st_audit_sample(tril_ctx *ctx, int side, int32_t *rows, double *pis, int64_t cap,
+                             int64_t *n);
 
 /* Copy the candidate pairs of the last tril_collide to host memory. *count gets the
  * number found (may exceed cap; only min(count, cap) are written). */

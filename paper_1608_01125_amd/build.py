@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libtril.so")
 
 SOURCES = ["abi.hip", "radix_sort.hip", "lbvh.hip", "traverse.hip", "narrow.hip", "stats.hip",
            "st.hip", "mlp.hip", "annihilate.hip", "kinematics.hip",
-           "grid.hip", "probe.hip", "noalloc.hip"]
+           "grid.hip", "noalloc.hip", "audit.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

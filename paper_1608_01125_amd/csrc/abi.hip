@@ -116,6 +116,18 @@ struct tril_ctx {
     long long *se_key = nullptr;
     double *se_val = nullptr;
     int64_t se_cap = 0;
+    // sampled exact estimate (tril_st_audit): per beam the thinned rows of the last
+    // replicate (SoA 8 x au_cap, cell bin, source row, inclusion probability), the per-cell
+    // arrays (control sums and kept weights of both beams), the row controls
+    double *au_soa[2] = {nullptr, nullptr};
+    int32_t *au_bin[2] = {nullptr, nullptr}, *au_row[2] = {nullptr, nullptr};
+    double *au_pi[2] = {nullptr, nullptr};
+    int64_t au_cap = 0, au_n[2] = {0, 0};
+    double *au_cell = nullptr;
+    int64_t au_cell_cap = 0;
+    double *au_ctl = nullptr;
+    int64_t au_ctl_cap = 0;
+    unsigned long long *au_count = nullptr;
     int morton_bits = 30;           // Morton bits of the sort keys of the current build/collide
     double sigma_up = 0.0;
     DevCounters *d_cnt = nullptr;
@@ -1449,16 +1461,232 @@ int st_records(tril_ctx *c, const double *sums, const tril_st_grid *g, WorkBeam 
     return rc;
 }
 
-tril_beam record_beam(const WorkBeam &w, int64_t n) {
+tril_beam soa_beam(const double *soa, int64_t cap, int64_t n) {
     tril_beam b;
     std::memset(&b, 0, sizeof(b));
     b.n = n;
-    b.x = w.soa; b.y = w.soa + w.cap; b.z = w.soa + 2 * w.cap;
-    b.px = w.soa + 3 * w.cap; b.py = w.soa + 4 * w.cap; b.pz = w.soa + 5 * w.cap;
-    b.E = w.soa + 6 * w.cap; b.w = w.soa + 7 * w.cap;
+    b.x = soa; b.y = soa + cap; b.z = soa + 2 * cap;
+    b.px = soa + 3 * cap; b.py = soa + 4 * cap; b.pz = soa + 5 * cap;
+    b.E = soa + 6 * cap; b.w = soa + 7 * cap;
     b.n_inst = 1;
     b.inst_off = nullptr;
     return b;
+}
+
+tril_beam record_beam(const WorkBeam &w, int64_t n) { return soa_beam(w.soa, w.cap, n); }
+
+// Feature rows of every candidate bin pair into the context's surrogate buffers (c->sf_*),
+// growing them until the rows fit; *nrow receives the row count.
+int sur_features(tril_ctx *c, const double *q_sums, const tril_st_grid *gq, const double *t_sums,
+                 const tril_st_grid *gt, int32_t k0, int32_t n_steps, const tril_st_sur_params *p,
+                 int64_t *nrow);
+
+// Sum of the per-wave slots (synchronises the stream).
+int slot_sum(tril_ctx *c, double *out) {
+    HIPCHK(hipStreamSynchronize(c->st));
+    double sl[kCounterSlots];
+    HIPCHK(hipMemcpy(sl, c->st_slots, sizeof(sl), hipMemcpyDeviceToHost));
+    double t = 0.0;
+    for (double v : sl) t += v;
+    *out = t;
+    return TRIL_OK;
+}
+
+int clear_slots(tril_ctx *c) {
+    if (!c->st_slots) CHK(dev_alloc(&c->st_slots, (size_t)kCounterSlots));
+    launch_au_zero(c->st_slots, kCounterSlots, c->st);
+    return TRIL_OK;
+}
+
+int sur_features(tril_ctx *c, const double *q_sums, const tril_st_grid *gq, const double *t_sums,
+                 const tril_st_grid *gt, int32_t k0, int32_t n_steps, const tril_st_sur_params *p,
+                 int64_t *nrow) {
+    int64_t cap = std::max<int64_t>(c->sf_cap, 1 << 16);
+    *nrow = 0;
+    for (int attempt = 0;; ++attempt) {
+        if (cap > c->sf_cap) {
+            dev_free(c->sf_x); dev_free(c->sf_y0); dev_free(c->sf_key);
+            dev_free(c->sf_mean); dev_free(c->sf_sd);
+            c->sf_cap = 0;
+            CHK(dev_alloc(&c->sf_x, (size_t)(kMlpIn * cap)));
+            CHK(dev_alloc(&c->sf_y0, (size_t)cap));
+            CHK(dev_alloc(&c->sf_key, (size_t)cap));
+            CHK(dev_alloc(&c->sf_mean, (size_t)cap));
+            CHK(dev_alloc(&c->sf_sd, (size_t)cap));
+            c->sf_cap = cap;
+        }
+        const int r = tril_st_features(c, q_sums, gq, t_sums, gt, k0, n_steps, p, c->sf_x, c->sf_y0,
+                                       c->sf_key, c->sf_cap, nrow);
+        if (r == TRIL_OK) return TRIL_OK;
+        if (r != TRIL_E_OVERFLOW || attempt >= 2) return r;
+        cap = pow2_at_least(*nrow + 1);
+    }
+}
+
+// Two-sided 95% quantile of Student's t with nu degrees of freedom.
+double t975(int nu) {
+    static const double tab[31] = {0.0,    12.706, 4.303, 3.182, 2.776, 2.571, 2.447, 2.365,
+                                   2.306,  2.262,  2.228, 2.201, 2.179, 2.160, 2.145, 2.131,
+                                   2.120,  2.110,  2.101, 2.093, 2.086, 2.080, 2.074, 2.069,
+                                   2.064,  2.060,  2.056, 2.052, 2.048, 2.045, 2.042};
+    if (nu < 1) return 0.0;
+    if (nu <= 30) return tab[nu];
+    // Cornish-Fisher expansion about the normal quantile (error below 1e-3 from nu = 31)
+    const double z = 1.959963984540054, z3 = z * z * z, z5 = z3 * z * z;
+    const double v = (double)nu;
+    return z + (z3 + z) / (4.0 * v) + (5.0 * z5 + 16.0 * z3 + 3.0 * z) / (96.0 * v * v);
+}
+
+// Sampled estimate of the exact total of the candidate rows (key, control per row from y0 and
+// the ensemble mean by mode, see tril_st_audit_params), over steps k0 .. k0+n_steps-1.
+int st_audit_rows(tril_ctx *c, const tril_beam *t, const int32_t *t_bins, const double *t_sums,
+                  const tril_st_grid *gt, const tril_beam *q, const int32_t *q_bins,
+                  const double *q_sums, const tril_st_grid *gq, int32_t k0, int32_t n_steps,
+                  const long long *key, const double *y0, const float *mean, int64_t nrow,
+                  int mode, double eps, double scale, const tril_st_audit_params *ap,
+                  tril_st_audit_result *out) {
+    const double lambda = (ap && ap->n_sample > 0) ? (double)ap->n_sample : 32768.0;
+    const int G = (ap && ap->n_rep > 0) ? ap->n_rep : 8;
+    const double mix = (ap && ap->mix > 0.0) ? ap->mix : 0.9;
+    const uint64_t seed = ap ? ap->seed : 0ull;
+    if (G < 2 || G > 64 || !(mix >= 0.0 && mix < 1.0)) return TRIL_E_INVAL;
+    const int64_t nbq = grid_bins(gq), nbt = grid_bins(gt);
+    const int64_t ncell = 2 * (nbq + nbt);
+    if (ncell > c->au_cell_cap) {
+        dev_free(c->au_cell);
+        c->au_cell_cap = 0;
+        CHK(dev_alloc(&c->au_cell, (size_t)ncell));
+        c->au_cell_cap = ncell;
+    }
+    if (nrow > c->au_ctl_cap) {
+        dev_free(c->au_ctl);
+        c->au_ctl_cap = 0;
+        CHK(dev_alloc(&c->au_ctl, (size_t)std::max<int64_t>(nrow, 1)));
+        c->au_ctl_cap = std::max<int64_t>(nrow, 1);
+    }
+    if (!c->au_count) CHK(dev_alloc(&c->au_count, 2));
+    double *pa = c->au_cell, *pb = pa + nbq, *Rq = pb + nbt, *Rt = Rq + nbq;
+    // control per row, per cell, in total; total weights of the two beams
+    launch_au_zero(pa, nbq + nbt, c->st);
+    CHK(clear_slots(c));
+    launch_au_control(key, y0, mean, nrow, mode, eps, scale, nbt, c->au_ctl, pa, pb, c->st_slots,
+                      c->st);
+    HIPCHK(hipGetLastError());
+    double c_tot = 0.0, w_q = 0.0, w_t = 0.0;
+    CHK(slot_sum(c, &c_tot));
+    CHK(clear_slots(c));
+    launch_au_weight(q_sums, nbq, c->st_slots, c->st);
+    CHK(slot_sum(c, &w_q));
+    CHK(clear_slots(c));
+    launch_au_weight(t_sums, nbt, c->st_slots, c->st);
+    CHK(slot_sum(c, &w_t));
+    out->control_total = c_tot;
+    out->control_scale = 1.0;
+    out->n_bin_pairs = nrow;
+    if (!(w_q > 0.0) || !(w_t > 0.0)) {  // an empty beam: nothing collides
+        out->n_rep = G;
+        return TRIL_OK;
+    }
+    double cell[3];
+    grid_cell(gq, cell);
+    const BeamDev qv = view(q, nullptr, 1), tv = view(t, nullptr, 1);
+    int64_t cap = std::max<int64_t>(c->au_cap, (int64_t)(lambda + 8.0 * std::sqrt(lambda)) + 1024);
+    // one replicate: thin both beams (draw index g), exact pass over the thinned beams (ys),
+    // and the thinned beams' estimate of the control total (cs)
+    auto replicate = [&](int g, double &ys, double &cs) -> int {
+        int64_t n_s[2] = {0, 0};
+        for (int attempt = 0;; ++attempt) {
+            if (cap > c->au_cap) {
+                for (int p = 0; p < 2; ++p) {
+                    dev_free(c->au_soa[p]); dev_free(c->au_bin[p]); dev_free(c->au_row[p]);
+                    dev_free(c->au_pi[p]);
+                }
+                c->au_cap = 0;
+                for (int p = 0; p < 2; ++p) {
+                    CHK(dev_alloc(&c->au_soa[p], (size_t)(8 * cap)));
+                    CHK(dev_alloc(&c->au_bin[p], (size_t)cap));
+                    CHK(dev_alloc(&c->au_row[p], (size_t)cap));
+                    CHK(dev_alloc(&c->au_pi[p], (size_t)cap));
+                }
+                c->au_cap = cap;
+            }
+            launch_au_zero(Rq, nbq + nbt, c->st);
+            HIPCHK(hipMemsetAsync(c->au_count, 0, 2 * sizeof(unsigned long long), c->st));
+            launch_au_sample(qv, q_bins, q_sums, pa, c_tot, w_q, lambda, mix, seed, (uint32_t)g, 0u,
+                             c->au_soa[0], c->au_cap, c->au_bin[0], c->au_row[0], c->au_pi[0],
+                             c->au_count, Rq, c->st);
+            launch_au_sample(tv, t_bins, t_sums, pb, c_tot, w_t, lambda, mix, seed, (uint32_t)g, 1u,
+                             c->au_soa[1], c->au_cap, c->au_bin[1], c->au_row[1], c->au_pi[1],
+                             c->au_count + 1, Rt, c->st);
+            HIPCHK(hipGetLastError());
+            unsigned long long h[2] = {0, 0};
+            HIPCHK(hipStreamSynchronize(c->st));
+            HIPCHK(hipMemcpy(h, c->au_count, sizeof(h), hipMemcpyDeviceToHost));
+            n_s[0] = (int64_t)h[0];
+            n_s[1] = (int64_t)h[1];
+            if (n_s[0] <= c->au_cap && n_s[1] <= c->au_cap) break;
+            if (attempt >= 2) return TRIL_E_NOMEM;
+            cap = pow2_at_least(std::max(n_s[0], n_s[1]) + (std::max(n_s[0], n_s[1]) >> 2));
+        }
+        c->au_n[0] = n_s[0];
+        c->au_n[1] = n_s[1];
+        out->n_sampled[0] += n_s[0];
+        out->n_sampled[1] += n_s[1];
+        const tril_beam qs = soa_beam(c->au_soa[0], c->au_cap, n_s[0]);
+        const tril_beam ts = soa_beam(c->au_soa[1], c->au_cap, n_s[1]);
+        int64_t ecap = std::max<int64_t>(c->se_cap, pow2_at_least(8 * (n_s[0] + n_s[1]) + (1 << 16)));
+        for (int attempt = 0;; ++attempt) {
+            if (ecap > c->se_cap) {
+                dev_free(c->se_key);
+                dev_free(c->se_val);
+                c->se_cap = 0;
+                CHK(dev_alloc(&c->se_key, (size_t)ecap));
+                CHK(dev_alloc(&c->se_val, (size_t)ecap));
+                c->se_cap = ecap;
+            }
+            HIPCHK(hipMemsetAsync(&c->d_cnt->err, 0, sizeof(unsigned int), c->st));
+            CHK(st_run(c, &ts, c->au_bin[1], nbt, &qs, c->au_bin[0], cell, k0, n_steps, 0, nullptr,
+                       0, c->se_key, c->se_val, c->se_cap));
+            const int r = st_finish(c, &ys);
+            if (r == TRIL_OK) break;
+            if (r != TRIL_E_OVERFLOW || attempt >= 3) return r;
+            ecap = c->se_cap * 4;
+        }
+        cs = 0.0;
+        if (c_tot > 0.0) {
+            CHK(clear_slots(c));
+            launch_au_ctl_sample(key, c->au_ctl, nrow, nbt, Rq, Rt, q_sums, t_sums, c->st_slots,
+                                 c->st);
+            HIPCHK(hipGetLastError());
+            CHK(slot_sum(c, &cs));
+        }
+        return TRIL_OK;
+    };
+    // the control's scale from a pilot replicate with draws of its own (index G): the
+    // bin-level yield has no absolute scale, and a network's shared bias shows here; being
+    // independent of the replicates below, the scale leaves each of them unbiased
+    double kappa = 1.0;
+    if (c_tot > 0.0) {
+        double ys = 0.0, cs = 0.0;
+        CHK(replicate(G, ys, cs));
+        if (cs > 0.0) kappa = ys / cs;
+    }
+    out->control_scale = kappa;
+    out->control_total = kappa * c_tot;
+    for (int g = 0; g < G; ++g) {
+        double ys = 0.0, cs = 0.0;
+        CHK(replicate(g, ys, cs));
+        out->rep[g] = kappa * c_tot + ys - kappa * cs;
+    }
+    out->n_rep = G;
+    double mean_t = 0.0;
+    for (int g = 0; g < G; ++g) mean_t += out->rep[g];
+    mean_t /= G;
+    double ss = 0.0;
+    for (int g = 0; g < G; ++g) ss += (out->rep[g] - mean_t) * (out->rep[g] - mean_t);
+    out->estimate = mean_t;
+    out->half_width = t975(G - 1) * std::sqrt(ss / (G - 1) / G);
+    return TRIL_OK;
 }
 
 }  // namespace
@@ -1606,7 +1834,42 @@ int tril_st_features(tril_ctx *c, const double *q_sums, const tril_st_grid *gq,
     dev_free(cnt);
     if (e != hipSuccess) return hip_fail(e);
     *n = (int64_t)h;
-    return (int64_t)h > cap ? TRIL_E_OVERFLOW : TRIL_OK;
+    if ((int64_t)h > cap) return TRIL_E_OVERFLOW;
+    // rows in ascending key order: threads claimed their slots in no fixed order, and the
+    // rows feed training, whose minibatches index them
+    const int64_t nr = (int64_t)h;
+    if (nr < 2) return TRIL_OK;
+    if (nr >= ((int64_t)1 << 32)) return TRIL_E_INVAL;
+    const uint64_t max_key = (uint64_t)grid_bins(gq) * (uint64_t)grid_bins(gt) - 1;
+    const int key_bits = std::max(1, bits_for(max_key));
+    CHK(ensure_sort_scratch(c, nr));
+    unsigned long long *ka = nullptr, *kb = nullptr;
+    uint32_t *va = nullptr, *vb = nullptr;
+    float *xt = nullptr;
+    double *yt = nullptr;
+    long long *kt = nullptr;
+    int rc = TRIL_OK;
+    if ((rc = dev_alloc(&ka, (size_t)nr)) == TRIL_OK && (rc = dev_alloc(&kb, (size_t)nr)) == TRIL_OK &&
+        (rc = dev_alloc(&va, (size_t)nr)) == TRIL_OK && (rc = dev_alloc(&vb, (size_t)nr)) == TRIL_OK &&
+        (rc = dev_alloc(&xt, (size_t)(kMlpIn * nr))) == TRIL_OK &&
+        (rc = dev_alloc(&yt, (size_t)nr)) == TRIL_OK && (rc = dev_alloc(&kt, (size_t)nr)) == TRIL_OK) {
+        long long *key_ll = reinterpret_cast<long long *>(key);
+        launch_st_keys_iota(key_ll, nr, ka, va, c->st);
+        const bool alt = radix_sort_u64(ka, va, kb, vb, nr, key_bits, c->ss, &c->d_cnt->err, c->st);
+        launch_st_permute_rows(x, y0, key_ll, alt ? vb : va, nr, xt, yt, kt, c->st);
+        e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(x, xt, (size_t)(kMlpIn * nr) * sizeof(float), hipMemcpyDeviceToDevice, c->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(y0, yt, (size_t)nr * sizeof(double), hipMemcpyDeviceToDevice, c->st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(key_ll, kt, (size_t)nr * sizeof(long long), hipMemcpyDeviceToDevice, c->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+        if (e != hipSuccess) rc = hip_fail(e);
+    }
+    dev_free(ka); dev_free(kb); dev_free(va); dev_free(vb);
+    dev_free(xt); dev_free(yt); dev_free(kt);
+    return rc;
 }
 
 int tril_st_targets(const int64_t *key, const double *y0, int64_t n, const tril_st_table *exact,
@@ -1634,35 +1897,53 @@ int tril_st_surrogate(tril_ctx *c, tril_mlp *mlp, const tril_beam *t, const int3
     const double eps = (p && p->eps > 0.0) ? p->eps : 1e-3;
     const double gate = (p && p->gate > 0.0) ? p->gate : 0.01;
     const double scale = (p && p->scale > 0.0) ? p->scale : 1.0;
+    if (p && (p->gate_mode < 0 || p->gate_mode > 2)) return TRIL_E_INVAL;
     std::memset(out, 0, sizeof(*out));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, c->st));
     // features of every candidate bin pair
-    int64_t cap = std::max<int64_t>(c->sf_cap, 1 << 16), nrow = 0;
-    for (int attempt = 0;; ++attempt) {
-        if (cap > c->sf_cap) {
-            dev_free(c->sf_x); dev_free(c->sf_y0); dev_free(c->sf_key);
-            dev_free(c->sf_mean); dev_free(c->sf_sd);
-            c->sf_cap = 0;
-            CHK(dev_alloc(&c->sf_x, (size_t)(kMlpIn * cap)));
-            CHK(dev_alloc(&c->sf_y0, (size_t)cap));
-            CHK(dev_alloc(&c->sf_key, (size_t)cap));
-            CHK(dev_alloc(&c->sf_mean, (size_t)cap));
-            CHK(dev_alloc(&c->sf_sd, (size_t)cap));
-            c->sf_cap = cap;
-        }
-        const int r = tril_st_features(c, q_sums, gq, t_sums, gt, k0, n_steps, p, c->sf_x, c->sf_y0,
-                                       c->sf_key, c->sf_cap, &nrow);
-        if (r == TRIL_OK) break;
-        if (r != TRIL_E_OVERFLOW || attempt >= 2) return r;
-        cap = pow2_at_least(nrow + 1);
-    }
+    int64_t nrow = 0;
+    CHK(sur_features(c, q_sums, gq, t_sums, gt, k0, n_steps, p, &nrow));
     out->n_bin_pairs = nrow;
     // ensemble prediction on the same stream
     if (mlp->m.st != c->st) HIPCHK(hipStreamSynchronize(c->st));
     CHK(tril_mlp_predict(mlp, c->sf_x, nrow, c->sf_mean, c->sf_sd));
+    if (mlp->m.st != c->st) HIPCHK(hipStreamSynchronize(mlp->m.st));
+    if (p && p->gate_mode == 2) {
+        // audit: the predictions are the control of a sampled estimate of the exact total
+        tril_st_audit_params ap{};
+        ap.n_sample = p->audit_sample;
+        ap.n_rep = p->audit_reps;
+        ap.control = 0;
+        ap.seed = p->audit_seed;
+        ap.mix = 0.0;
+        tril_st_audit_result ar;
+        std::memset(&ar, 0, sizeof(ar));
+        const int r = st_audit_rows(c, t, t_bins, t_sums, gt, q, q_bins, q_sums, gq, k0, n_steps,
+                                    reinterpret_cast<const long long *>(c->sf_key), c->sf_y0,
+                                    c->sf_mean, nrow, 0, eps, scale, &ap, &ar);
+        if (r != TRIL_OK) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return r;
+        }
+        // the network's own total, and the audit's correction of it
+        out->surrogate_part = ar.control_scale > 0.0 ? ar.control_total / ar.control_scale : 0.0;
+        out->exact_part = ar.estimate - out->surrogate_part;
+        out->total = ar.estimate;
+        out->audit_half_width = ar.half_width;
+        out->audit_sampled = ar.n_sampled[0] + ar.n_sampled[1];
+        out->predicted_spread = ar.estimate > 0.0 ? ar.half_width / ar.estimate : 0.0;
+        float ms = 0.f;
+        if (hipEventRecord(e1, c->st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+            hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+            out->ms = ms;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return TRIL_OK;
+    }
     // gate: surrogate yields for confident rows; the rest to an exact pass
     const int64_t nbq = grid_bins(gq), nbt = grid_bins(gt);
     const int64_t fcap = pow2_at_least(2 * nrow + 16);
@@ -1784,6 +2065,85 @@ int tril_st_surrogate(tril_ctx *c, tril_mlp *mlp, const tril_beam *t, const int3
 
 // ------------------------------------------------------------ surrogate network
 
+int tril_st_audit(tril_ctx *c, tril_mlp *mlp, const tril_beam *t, const int32_t *t_bins,
+                  const double *t_sums, const tril_st_grid *gt, const tril_beam *q,
+                  const int32_t *q_bins, const double *q_sums, const tril_st_grid *gq, int32_t k0,
+                  int32_t n_steps, const tril_st_sur_params *sp, const tril_st_audit_params *ap,
+                  tril_st_audit_result *out) {
+    if (!c || !out || !ap || !t_sums || !q_sums || k0 < 0 || n_steps < 0) return TRIL_E_INVAL;
+    CHK(check_beam(t));
+    CHK(check_beam(q));
+    CHK(check_grid(gq));
+    CHK(check_grid(gt));
+    if ((t->n > 0 && !t_bins) || (q->n > 0 && !q_bins)) return TRIL_E_INVAL;
+    if (q->n_inst != 1 || t->n_inst != 1) return TRIL_E_NOTIMPL;
+    if (ap->control < 0 || ap->control > 2 || (ap->control == 0 && !mlp)) return TRIL_E_INVAL;
+    const double eps = (sp && sp->eps > 0.0) ? sp->eps : 1e-3;
+    const double scale = (sp && sp->scale > 0.0) ? sp->scale : 1.0;
+    std::memset(out, 0, sizeof(*out));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int rc = TRIL_OK;
+    int64_t nrow = 0;
+    if (hipEventRecord(e0, c->st) != hipSuccess) rc = TRIL_E_HIP;
+    if (rc == TRIL_OK) rc = sur_features(c, q_sums, gq, t_sums, gt, k0, n_steps, sp, &nrow);
+    if (rc == TRIL_OK && ap->control == 0) {
+        if (mlp->m.st != c->st && hipStreamSynchronize(c->st) != hipSuccess) rc = TRIL_E_HIP;
+        if (rc == TRIL_OK) rc = tril_mlp_predict(mlp, c->sf_x, nrow, c->sf_mean, c->sf_sd);
+        if (rc == TRIL_OK && mlp->m.st != c->st && hipStreamSynchronize(mlp->m.st) != hipSuccess)
+            rc = TRIL_E_HIP;
+    }
+    if (rc == TRIL_OK)
+        rc = st_audit_rows(c, t, t_bins, t_sums, gt, q, q_bins, q_sums, gq, k0, n_steps,
+                           reinterpret_cast<const long long *>(c->sf_key), c->sf_y0,
+                           ap->control == 0 ? c->sf_mean : nullptr, nrow, ap->control, eps, scale,
+                           ap, out);
+    float ms = 0.f;
+    if (rc == TRIL_OK && hipEventRecord(e1, c->st) == hipSuccess &&
+        hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+        out->ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+int tril_st_calibrate(tril_mlp *mlp, const float *x, const double *y0, const double *y_exact,
+                      int64_t n, double eps, double *scale) {
+    if (!mlp || !scale || n < 0 || !(eps > 0.0) || (n > 0 && (!x || !y0 || !y_exact)))
+        return TRIL_E_INVAL;
+    *scale = 1.0;
+    if (n == 0) return TRIL_OK;
+    const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    float *mean = nullptr, *sd = nullptr;
+    double *part = nullptr;
+    int rc = TRIL_OK;
+    if ((rc = dev_alloc(&mean, (size_t)n)) == TRIL_OK && (rc = dev_alloc(&sd, (size_t)n)) == TRIL_OK &&
+        (rc = dev_alloc(&part, (size_t)(2 * blocks))) == TRIL_OK)
+        rc = tril_mlp_predict(mlp, x, n, mean, sd);
+    std::vector<double> h((size_t)(2 * blocks), 0.0);
+    if (rc == TRIL_OK) {
+        launch_au_calib(y0, mean, y_exact, n, eps, part, blocks, mlp->m.st);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(mlp->m.st);
+        if (e == hipSuccess)
+            e = hipMemcpy(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = hip_fail(e);
+    }
+    dev_free(mean);
+    dev_free(sd);
+    dev_free(part);
+    if (rc != TRIL_OK) return rc;
+    double se = 0.0, sp = 0.0;
+    for (int b = 0; b < blocks; ++b) {
+        se += h[(size_t)(2 * b)];
+        sp += h[(size_t)(2 * b + 1)];
+    }
+    if (!(sp > 0.0)) return TRIL_E_INVAL;  // nothing predicted: no ratio
+    *scale = se / sp;
+    return TRIL_OK;
+}
+
 int tril_mlp_create(tril_mlp **out, int32_t n_members, uint64_t seed, void *stream) {
     if (!out || n_members < 1 || n_members > 64) return TRIL_E_INVAL;
     *out = nullptr;
@@ -1839,15 +2199,19 @@ int tril_mlp_set_norm(tril_mlp *p, const float *mu_x, const float *sd_x, float m
 
 int tril_mlp_fit_norm(tril_mlp *p, const float *x, const float *y, int64_t n) {
     if (!p || !x || !y || n < 2) return TRIL_E_INVAL;
-    double *mom = nullptr;
+    double *mom = nullptr, *part = nullptr;
     CHK(dev_alloc(&mom, 2 * (kMlpIn + 1)));
-    HIPCHK(hipMemsetAsync(mom, 0, 2 * (kMlpIn + 1) * sizeof(double), p->m.st));
-    mlp_moments(x, n, kMlpIn, mom, p->m.st);
-    mlp_moments(y, n, 1, mom + 2 * kMlpIn, p->m.st);
+    if (dev_alloc(&part, (size_t)(2 * (kMlpIn + 1) * kMomentSlices)) != TRIL_OK) {
+        dev_free(mom);
+        return TRIL_E_NOMEM;
+    }
+    mlp_moments(x, n, kMlpIn, mom, part, p->m.st);
+    mlp_moments(y, n, 1, mom + 2 * kMlpIn, part + 2 * kMlpIn * kMomentSlices, p->m.st);
     double h[2 * (kMlpIn + 1)];
     hipError_t e = hipStreamSynchronize(p->m.st);
     if (e == hipSuccess) e = hipMemcpy(h, mom, sizeof(h), hipMemcpyDeviceToHost);
     dev_free(mom);
+    dev_free(part);
     if (e != hipSuccess) return hip_fail(e);
     float mu[kMlpIn], sd[kMlpIn];
     for (int c = 0; c <= kMlpIn; ++c) {
@@ -2099,6 +2463,11 @@ void tril_destroy(tril_ctx *c) {
     dev_free(c->sg_key); dev_free(c->sg_val);
     dev_free(c->sf_x); dev_free(c->sf_mean); dev_free(c->sf_sd); dev_free(c->sf_y0);
     dev_free(c->sf_key); dev_free(c->se_key); dev_free(c->se_val);
+    for (int p = 0; p < 2; ++p) {
+        dev_free(c->au_soa[p]); dev_free(c->au_bin[p]); dev_free(c->au_row[p]);
+        dev_free(c->au_pi[p]);
+    }
+    dev_free(c->au_cell); dev_free(c->au_ctl); dev_free(c->au_count);
     dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->inst_root); dev_free(c->inst_base); dev_free(c->root_box);
     dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
     dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
@@ -2220,6 +2589,16 @@ int tril_dbg_pair_eval(int64_t n, const double *in, double *out, void *stream) {
     return TRIL_OK;
 }
 
+int tril_dbg_math(int which, int64_t n, const double *a, const double *b, double *out,
+                  void *stream) {
+    if (which < 0 || which > 5 || n < 0 || (n > 0 && (!a || !out)) ||
+        (n > 0 && (which == 0 || which == 2) && !b))
+        return TRIL_E_INVAL;
+    launch_math_sweep(which, n, a, b, out, reinterpret_cast<hipStream_t>(stream));
+    HIPCHK(hipGetLastError());
+    return TRIL_OK;
+}
+
 int tril_dbg_pair_eval32(int64_t n, const double *in, double *out, void *stream) {
     if (n < 0 || (n > 0 && (!in || !out))) return TRIL_E_INVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -2302,6 +2681,21 @@ int tril_dbg_query_records(tril_ctx *c, int32_t s, void *boxes, int64_t cap, int
     if (e == hipSuccess) e = hipMemcpy(boxes, tmp, v.n * sizeof(PBox), hipMemcpyDeviceToHost);
     dev_free(tmp);
     if (e != hipSuccess) return hip_fail(e);
+    return TRIL_OK;
+}
+
+int tril_dbg_st_audit_sample(tril_ctx *c, int side, int32_t *rows, double *pis, int64_t cap,
+                             int64_t *n) {
+    if (!c || !n || (side != 0 && side != 1)) return TRIL_E_INVAL;
+    HIPCHK(hipStreamSynchronize(c->st));
+    const int64_t nn = c->au_row[side] ? c->au_n[side] : 0;
+    *n = nn;
+    if (nn > cap) return TRIL_E_OVERFLOW;
+    if (nn > 0) {
+        if (!rows || !pis) return TRIL_E_INVAL;
+        HIPCHK(hipMemcpy(rows, c->au_row[side], nn * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(pis, c->au_pi[side], nn * sizeof(double), hipMemcpyDeviceToHost));
+    }
     return TRIL_OK;
 }
 

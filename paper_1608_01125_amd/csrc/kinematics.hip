@@ -34,33 +34,6 @@ namespace tril {
 
 namespace {
 
-constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
-constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
-constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull;
-constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
-
-// Philox4x64-10: ten rounds; each round multiplies words 0 and 2 by the two round
-// constants into 128-bit products, the high halves crossed with words 1 and 3 and the
-// round key, the low halves moved to the odd words; the key advances by the Weyl
-// constants between rounds.
-__device__ __forceinline__ void philox4x64_10(uint64_t x[4], uint64_t k0, uint64_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += kPhiloxW0;
-            k1 += kPhiloxW1;
-        }
-        const uint64_t lo0 = kPhiloxM0 * x[0], hi0 = __umul64hi(kPhiloxM0, x[0]);
-        const uint64_t lo1 = kPhiloxM1 * x[2], hi1 = __umul64hi(kPhiloxM1, x[2]);
-        const uint64_t y0 = hi1 ^ x[1] ^ k0;
-        const uint64_t y2 = hi0 ^ x[3] ^ k1;
-        x[0] = y0;
-        x[1] = lo1;
-        x[2] = y2;
-        x[3] = lo0;
-    }
-}
-
 // Lab velocity of a lepton with CoM-frame velocity bp in a CoM moving at bc.
 __device__ __forceinline__ void add_velocity(const double bc[3], const double bp[3], double b[3]) {
     const double b2 = (bc[0] * bc[0] + bc[1] * bc[1]) + bc[2] * bc[2];

@@ -359,9 +359,12 @@ __global__ void k_batch_idx(uint64_t seed, int k, int64_t step, int64_t n, int64
     idx[i] = (int32_t)(h % (uint64_t)n);
 }
 
-// Per-column sum and sum of squares (FP64) of a [n x c] row-major matrix: out[2 col],
-// out[2 col + 1]; caller-zeroed, one workgroup per (column, slice).
-__global__ void k_moments(const float *__restrict__ a, int64_t n, int c, double *__restrict__ out) {
+// Per-column sum and sum of squares (FP64) of a [n x c] row-major matrix, reduced in a fixed
+// order (the same sums on every call): workgroup (slice, col) sums its strided rows per
+// thread, then a tree over its 256 threads into part[(col gx + slice) 2 + {0, 1}];
+// k_moments_fold adds the slices in order into out[2 col], out[2 col + 1].
+__global__ void __launch_bounds__(256) k_moments(const float *__restrict__ a, int64_t n, int c,
+                                                 double *__restrict__ part) {
     const int col = blockIdx.y;
     double s = 0.0, s2 = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -370,15 +373,35 @@ __global__ void k_moments(const float *__restrict__ a, int64_t n, int c, double 
         s += v;
         s2 += v * v;
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        s += __shfl_xor(s, off);
-        s2 += __shfl_xor(s2, off);
+    __shared__ double r1[256], r2[256];
+    r1[threadIdx.x] = s;
+    r2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            r1[threadIdx.x] += r1[threadIdx.x + h];
+            r2[threadIdx.x] += r2[threadIdx.x + h];
+        }
+        __syncthreads();
     }
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd(out + 2 * col, s);
-        atomicAdd(out + 2 * col + 1, s2);
+    if (threadIdx.x == 0) {
+        const int64_t o = 2 * ((int64_t)col * gridDim.x + blockIdx.x);
+        part[o] = r1[0];
+        part[o + 1] = r2[0];
     }
+}
+
+__global__ void k_moments_fold(const double *__restrict__ part, int gx, int c,
+                               double *__restrict__ out) {
+    const int col = threadIdx.x;
+    if (col >= c) return;
+    double s = 0.0, s2 = 0.0;
+    for (int b = 0; b < gx; ++b) {
+        s += part[2 * ((int64_t)col * gx + b)];
+        s2 += part[2 * ((int64_t)col * gx + b) + 1];
+    }
+    out[2 * col] = s;
+    out[2 * col + 1] = s2;
 }
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -397,10 +420,11 @@ void mlp_batch_idx(MlpModel *m, uint64_t seed, int k, int64_t step, int64_t n, i
                        batch, m->idx);
 }
 
-void mlp_moments(const float *a, int64_t n, int c, double *out, hipStream_t st) {
+void mlp_moments(const float *a, int64_t n, int c, double *out, double *part, hipStream_t st) {
     if (n <= 0) return;
-    const unsigned gx = std::min<unsigned>(blocks(n, 256), 256u);
-    hipLaunchKernelGGL(k_moments, dim3(gx, (unsigned)c), dim3(256), 0, st, a, n, c, out);
+    const unsigned gx = std::min<unsigned>(blocks(n, 256), kMomentSlices);
+    hipLaunchKernelGGL(k_moments, dim3(gx, (unsigned)c), dim3(256), 0, st, a, n, c, part);
+    hipLaunchKernelGGL(k_moments_fold, dim3(1), dim3(64), 0, st, part, (int)gx, c, out);
 }
 
 void mlp_gemm(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk,

@@ -360,7 +360,34 @@ __global__ void k_pair_eval32(int64_t n, const double *__restrict__ in, double s
     w[7] = 0.0;
 }
 
+// The device arithmetic the narrow phase relies on, one operation per element, compiled
+// with the same flags as the narrow phase: 0 FP64 a / b, 1 FP64 sqrt(a); FP32 on the
+// arguments rounded to FP32: 2 a / b, 3 sqrtf(a), 4 logf(a), 5 log1pf(a).
+__global__ void k_math_sweep(int which, int64_t n, const double *__restrict__ a,
+                             const double *__restrict__ b, double *__restrict__ out) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const double x = a[r];
+    double y = 0.0;
+    switch (which) {
+    case 0: y = x / b[r]; break;
+    case 1: y = sqrt(x); break;
+    case 2: y = (double)((float)x / (float)b[r]); break;
+    case 3: y = (double)sqrtf((float)x); break;
+    case 4: y = (double)logf((float)x); break;
+    default: y = (double)log1pf((float)x); break;
+    }
+    out[r] = y;
+}
+
 }  // namespace
+
+void launch_math_sweep(int which, int64_t n, const double *a, const double *b, double *out,
+                       hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_math_sweep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, which, n,
+                       a, b, out);
+}
 
 void launch_pair_eval32(int64_t n, const double *in, double sigma_up, double *out, hipStream_t st) {
     if (n <= 0) return;

@@ -700,6 +700,30 @@ __global__ void k_st_mask_bins(const int32_t *__restrict__ bins, int64_t n,
     out[i] = (b >= 0 && mark[b]) ? b : -1;
 }
 
+// Sort input of the feature rows: key copy and row index.
+__global__ void k_st_keys_iota(const long long *__restrict__ key, int64_t n,
+                               unsigned long long *__restrict__ k, uint32_t *__restrict__ v) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    k[r] = (unsigned long long)key[r];
+    v[r] = (uint32_t)r;
+}
+
+// Feature rows in the sorted order: row r of the output is row perm[r] of the input.
+__global__ void k_st_permute_rows(const float *__restrict__ x, const double *__restrict__ y0,
+                                  const long long *__restrict__ key,
+                                  const uint32_t *__restrict__ perm, int64_t n,
+                                  float *__restrict__ xo, double *__restrict__ y0o,
+                                  long long *__restrict__ keyo) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int64_t s = perm[r];
+#pragma unroll
+    for (int f = 0; f < kMlpIn; ++f) xo[kMlpIn * r + f] = x[kMlpIn * s + f];
+    y0o[r] = y0[s];
+    keyo[r] = key[s];
+}
+
 __global__ void k_fill_i64v(long long *p, long long v, int64_t n) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -708,6 +732,20 @@ __global__ void k_fill_i64v(long long *p, long long v, int64_t n) {
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace
+
+void launch_st_keys_iota(const long long *key, int64_t n, unsigned long long *k, uint32_t *v,
+                         hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_st_keys_iota, dim3(grid_for(n, 256)), dim3(256), 0, st, key, n, k, v);
+}
+
+void launch_st_permute_rows(const float *x, const double *y0, const long long *key,
+                            const uint32_t *perm, int64_t n, float *xo, double *y0o,
+                            long long *keyo, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_st_permute_rows, dim3(grid_for(n, 256)), dim3(256), 0, st, x, y0, key,
+                       perm, n, xo, y0o, keyo);
+}
 
 void launch_st_records(const double *sums, int64_t n_bins, double t_bin, double *soa, int64_t cap,
                        int32_t *rec_bin, unsigned long long *count, hipStream_t st) {

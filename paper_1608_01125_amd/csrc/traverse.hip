@@ -3,7 +3,8 @@
 // test (Eq. 5) has its whole subtree skipped; a leaf whose box passes yields a
 // candidate pair. A node holds its two children's boxes, so one 64-byte load tests
 // both: a child that fails is never loaded, and the descent costs one dependent load
-// per internal node whose box the query overlaps. When both children are internal and
+// per internal node whose box the query overlaps (a scalar load when every active lane of
+// the wave is at the same node). When both children are internal and
 // overlap, the right one waits on a per-lane stack (four entries in registers, the
 // rest in a private spill array).
 //
@@ -141,8 +142,31 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
             atomicOr(&c->err, kErrSpin);
             break;
         }
-        const float4 *np = reinterpret_cast<const float4 *>(nodes + node);
-        const float4 l0 = np[0], l1 = np[1], r0 = np[2], r1 = np[3];
+        float4 l0, l1, r0, r1;
+        const int32_t first = __builtin_amdgcn_readfirstlane(node);
+        if (__ballot(node == first) == __ballot(1)) {
+            // every active lane descends the same node (common in the upper levels, whose
+            // boxes a wave's neighbouring queries share): one scalar load for the wave
+            // instead of four vector loads that each take an L1 lookup
+            typedef int v16i __attribute__((ext_vector_type(16)));
+            v16i r;
+            const Node *p = nodes + first;
+            asm volatile("s_load_dwordx16 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p));
+            l0 = make_float4(__int_as_float(r[0]), __int_as_float(r[1]), __int_as_float(r[2]),
+                             __int_as_float(r[3]));
+            l1 = make_float4(__int_as_float(r[4]), __int_as_float(r[5]), __int_as_float(r[6]),
+                             __int_as_float(r[7]));
+            r0 = make_float4(__int_as_float(r[8]), __int_as_float(r[9]), __int_as_float(r[10]),
+                             __int_as_float(r[11]));
+            r1 = make_float4(__int_as_float(r[12]), __int_as_float(r[13]), __int_as_float(r[14]),
+                             __int_as_float(r[15]));
+        } else {
+            const float4 *np = reinterpret_cast<const float4 *>(nodes + node);
+            l0 = np[0];
+            l1 = np[1];
+            r0 = np[2];
+            r1 = np[3];
+        }
         ++visits;
         const int32_t lc = __float_as_int(l0.w), rc = __float_as_int(r0.w);
         const bool ovl = box_overlap(qb, l0, l1) & (qe * l1.w >= kPruneProduct);

@@ -115,6 +115,35 @@ __device__ __forceinline__ void moved_box(float lox, float loy, float loz, float
     hi[0] = hx + ex; hi[1] = hy + ey; hi[2] = hz + ez;
 }
 
+// Philox4x64-10 (Salmon et al., SC'11), the counter-based generator of the pair kinematics
+// and of the statistical regime's audit samples.
+constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
+
+// Philox4x64-10: ten rounds; each round multiplies words 0 and 2 by the two round
+// constants into 128-bit products, the high halves crossed with words 1 and 3 and the
+// round key, the low halves moved to the odd words; the key advances by the Weyl
+// constants between rounds.
+__device__ __forceinline__ void philox4x64_10(uint64_t x[4], uint64_t k0, uint64_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += kPhiloxW0;
+            k1 += kPhiloxW1;
+        }
+        const uint64_t lo0 = kPhiloxM0 * x[0], hi0 = __umul64hi(kPhiloxM0, x[0]);
+        const uint64_t lo1 = kPhiloxM1 * x[2], hi1 = __umul64hi(kPhiloxM1, x[2]);
+        const uint64_t y0 = hi1 ^ x[1] ^ k0;
+        const uint64_t y2 = hi0 ^ x[3] ^ k1;
+        x[0] = y0;
+        x[1] = lo1;
+        x[2] = y2;
+        x[3] = lo0;
+    }
+}
+
 // Counters accumulated on the device across steps. Counters that every wave of a
 // large launch updates are spread over kCounterSlots addresses (slot = block index
 // modulo kCounterSlots): device-scope atomics to one address serialise at roughly
@@ -302,6 +331,10 @@ void launch_grid_query(const GridDev *g, const PBox *tbox, const uint32_t *trows
 // the record's instance (-1: the row can collide with nothing); pad: the row.
 void launch_record_boxes(const QRec *qrec, int64_t n, const int32_t *perm, int32_t s, PBox *out,
                          hipStream_t st);
+// The narrow phase's device arithmetic on n arguments (which: 0 FP64 a / b, 1 FP64 sqrt,
+// 2 FP32 a / b, 3 sqrtf, 4 logf, 5 log1pf, FP32 results widened to FP64).
+void launch_math_sweep(int which, int64_t n, const double *a, const double *b, double *out,
+                       hipStream_t st);
 // Queries from per-step boxes (qbox) or, when qrec is given, from per-row records of the
 // batch (element s nq_base + row; n_inst: instances of the query view).
 void launch_traverse(const Node *nodes, int64_t n_int, const PBox *root_box, const PBox *qbox,
@@ -355,7 +388,10 @@ void mlp_adam(MlpModel *m, int k, float lr, int64_t t);
 void mlp_reduce(MlpModel *m, const float *out, int64_t n, float *mean, float *sdev);
 void mlp_cast(MlpModel *m);
 void mlp_batch_idx(MlpModel *m, uint64_t seed, int k, int64_t step, int64_t n, int64_t batch);
-void mlp_moments(const float *a, int64_t n, int c, double *out, hipStream_t st);
+// Column sums and sums of squares into out[2 c] (written, fixed-order reduction); part:
+// scratch of 2 c kMomentSlices doubles; c <= 64.
+constexpr int kMomentSlices = 256;
+void mlp_moments(const float *a, int64_t n, int c, double *out, double *part, hipStream_t st);
 void mlp_gemm(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, int64_t sbk,
               int64_t sbn, int M, int N, int K, int epi, const float *bias, const float *aux,
               float *out, uint16_t *out_bf, float *out_pre, hipStream_t st);
@@ -383,6 +419,13 @@ void launch_st_features(const long long *keys, const double *vals, int64_t cap, 
                         const double *q_sums, const double *t_sums, double vol, float *x,
                         double *y0, long long *key_out, int64_t out_cap, unsigned long long *count,
                         hipStream_t st);
+// Feature rows in ascending key order (a deterministic order: the rows are appended in
+// the order threads claim slots): sort input, then the permutation of the rows.
+void launch_st_keys_iota(const long long *key, int64_t n, unsigned long long *k, uint32_t *v,
+                         hipStream_t st);
+void launch_st_permute_rows(const float *x, const double *y0, const long long *key,
+                            const uint32_t *perm, int64_t n, float *xo, double *y0o,
+                            long long *keyo, hipStream_t st);
 void launch_st_targets(const long long *key, const double *y0, int64_t n, const long long *tkeys,
                        const double *tvals, int64_t tcap, double eps, float *target, double *y_exact,
                        hipStream_t st);
@@ -393,6 +436,23 @@ void launch_st_gate(const long long *key, const double *y0, const float *mean, c
 constexpr int kUncBuckets = 4096;  // uncertainty histogram of the budget gate
 void launch_st_unc(const double *y0, const float *mean, const float *sdev, int64_t n, double eps,
                    double scale, double *var_hist, double *slots, hipStream_t st);
+// Sampled estimate of the exact statistical-regime total (audit.hip).
+void launch_au_control(const long long *key, const double *y0, const float *mean, int64_t n,
+                       int mode, double eps, double scale, int64_t n_t_bins, double *ctl, double *pa,
+                       double *qb, double *slots, hipStream_t st);
+void launch_au_weight(const double *sums, int64_t n_bins, double *slots, hipStream_t st);
+void launch_au_sample(const BeamDev &b, const int32_t *bins, const double *sums, const double *pc,
+                      double c_tot, double w_tot, double lambda, double mix, uint64_t seed,
+                      uint32_t rep, uint32_t side, double *soa, int64_t cap, int32_t *s_bin,
+                      int32_t *s_row, double *s_pi, unsigned long long *count, double *R,
+                      hipStream_t st);
+void launch_au_ctl_sample(const long long *key, const double *ctl, int64_t n, int64_t n_t_bins,
+                          const double *Rq, const double *Rt, const double *q_sums,
+                          const double *t_sums, double *slots, hipStream_t st);
+void launch_au_zero(double *p, int64_t n, hipStream_t st);
+// part: 2 x blocks doubles (exact, predicted per block), each a fixed-order sum.
+void launch_au_calib(const double *y0, const float *mean, const double *y_exact, int64_t n,
+                     double eps, double *part, int blocks, hipStream_t st);
 void launch_st_mask_bins(const int32_t *bins, int64_t n, const uint8_t *mark, int32_t *out,
                          hipStream_t st);
 void launch_fill_keys(long long *p, int64_t n, hipStream_t st);

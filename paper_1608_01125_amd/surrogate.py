@@ -2,8 +2,8 @@
 training of the network ensemble, and the surrogate path with its exact fallback.
 
 Every computation runs in libtril's kernels (tril_st_bin, tril_st_exact,
-tril_st_features, tril_st_targets, tril_mlp_*, tril_st_surrogate); this module only
-sequences the calls and holds device buffers.
+tril_st_features, tril_st_targets, tril_mlp_*, tril_st_calibrate, tril_st_audit,
+tril_st_surrogate); this module only sequences the calls and holds device buffers.
 
 The surrogate works on pairs of position cells of the 32^3 grid: the grids given to it
 have one energy and one angle bin, and energy and direction enter as each cell's
@@ -65,6 +65,13 @@ class Instance:
         return T.tril_st_features(ctx, self.qsums, self.ga, self.tsums, self.gb, 0,
                                   self.wl.n_steps, params)
 
+    def audit(self, ctx: T.Context, net, control: int, n_sample: int = 0, n_rep: int = 0,
+              seed: int = 0, mix: float = 0.0, sur=None) -> dict:
+        """Sampled estimate of the exact total (tril_st_audit) with the given control."""
+        return T.tril_st_audit(ctx, net, self.tb, self.tbins, self.tsums, self.gb, self.qa,
+                               self.qbins, self.qsums, self.ga, 0, self.wl.n_steps, control,
+                               n_sample, n_rep, seed, mix, sur)
+
     def surrogate(self, ctx: T.Context, net: T.Mlp, params=None) -> dict:
         return T.tril_st_surrogate(ctx, net, self.tb, self.tbins, self.tsums, self.gb, self.qa,
                                    self.qbins, self.qsums, self.ga, 0, self.wl.n_steps, params)
@@ -92,9 +99,7 @@ def train(net: T.Mlp, x, t, n_steps: int = 3000, batch: int = 4096, lr: float = 
 
 
 def yield_scale(net: T.Mlp, x, y0, y, eps: float = 1e-3) -> float:
-    """Exact over predicted total yield on training rows: the network fits the mean of
-    log((Y + eps Y0) / Y0), whose exponential falls short of the mean ratio."""
-    import torch
-    mean, _ = net.predict(x)
-    pred = (y0 * (torch.exp(mean.double()) - eps)).clamp(min=0)
-    return float(y.sum() / pred.sum())
+    """Exact over predicted total yield on training rows (tril_st_calibrate): the network
+    fits the mean of log((Y + eps Y0) / Y0), whose exponential falls short of the mean
+    ratio."""
+    return T.tril_st_calibrate(net, x, y0, y, eps)

@@ -88,14 +88,31 @@ class tril_st_table(ctypes.Structure):
 class tril_st_sur_params(ctypes.Structure):
     _fields_ = [("cloud_factor", ctypes.c_double), ("eps", ctypes.c_double),
                 ("gate", ctypes.c_double), ("scale", ctypes.c_double),
-                ("gate_mode", ctypes.c_int32), ("pad0", ctypes.c_int32)]
+                ("gate_mode", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("audit_sample", ctypes.c_int64), ("audit_reps", ctypes.c_int32),
+                ("pad1", ctypes.c_int32), ("audit_seed", ctypes.c_uint64)]
 
 
 class tril_st_sur_result(ctypes.Structure):
     _fields_ = [("total", ctypes.c_double), ("surrogate_part", ctypes.c_double),
                 ("exact_part", ctypes.c_double), ("n_bin_pairs", ctypes.c_int64),
                 ("n_gated", ctypes.c_int64), ("ms", ctypes.c_double),
-                ("predicted_spread", ctypes.c_double)]
+                ("predicted_spread", ctypes.c_double), ("audit_half_width", ctypes.c_double),
+                ("audit_sampled", ctypes.c_int64)]
+
+
+class tril_st_audit_params(ctypes.Structure):
+    _fields_ = [("n_sample", ctypes.c_int64), ("n_rep", ctypes.c_int32),
+                ("control", ctypes.c_int32), ("seed", ctypes.c_uint64), ("mix", ctypes.c_double)]
+
+
+class tril_st_audit_result(ctypes.Structure):
+    _fields_ = [("estimate", ctypes.c_double), ("half_width", ctypes.c_double),
+                ("control_total", ctypes.c_double), ("control_scale", ctypes.c_double),
+                ("rep", ctypes.c_double * 64),
+                ("n_rep", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("n_sampled", ctypes.c_int64 * 2), ("n_bin_pairs", ctypes.c_int64),
+                ("ms", ctypes.c_double)]
 
 
 class tril_kin_params(ctypes.Structure):
@@ -116,10 +133,11 @@ EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats"
            "tril_mlp_create", "tril_mlp_destroy", "tril_mlp_set_params", "tril_mlp_get_params",
            "tril_mlp_set_norm", "tril_mlp_fit_norm", "tril_mlp_grad", "tril_mlp_train",
            "tril_mlp_predict", "tril_st_features", "tril_st_targets", "tril_st_surrogate",
+           "tril_st_audit", "tril_st_calibrate", "tril_dbg_st_audit_sample",
            "tril_dbg_gemm_bf16",
            "tril_reset_counters", "tril_destroy", "tril_strerror", "tril_last_hip_error",
            "tril_dbg_sort_u32", "tril_dbg_sort_u64", "tril_dbg_morton", "tril_dbg_pair_eval",
-           "tril_dbg_pair_eval32", "tril_dbg_vmem_rate",
+           "tril_dbg_pair_eval32", "tril_dbg_math",
            "tril_dbg_tree", "tril_dbg_boxes", "tril_dbg_target_rows", "tril_dbg_query_records", "tril_dbg_candidates")
 
 _lib = None
@@ -197,8 +215,16 @@ def lib() -> ctypes.CDLL:
     L.tril_dbg_morton.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_float), vp, vp]
     L.tril_dbg_pair_eval.argtypes = [i64, vp, vp, vp]
     L.tril_dbg_pair_eval32.argtypes = [i64, vp, vp, vp]
-    L.tril_dbg_vmem_rate.argtypes = [ctypes.c_int, i32, i32, ctypes.POINTER(ctypes.c_double), vp]
+    L.tril_dbg_math.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp]
     L.tril_dbg_tree.argtypes = [vp, vp, i64, _i64p, _i32p]
+    L.tril_st_audit.argtypes = [vp, vp, ctypes.POINTER(tril_beam), vp, vp, gp,
+                                ctypes.POINTER(tril_beam), vp, vp, gp, i32, i32,
+                                ctypes.POINTER(tril_st_sur_params),
+                                ctypes.POINTER(tril_st_audit_params),
+                                ctypes.POINTER(tril_st_audit_result)]
+    L.tril_st_calibrate.argtypes = [vp, vp, vp, vp, i64, ctypes.c_double,
+                                    ctypes.POINTER(ctypes.c_double)]
+    L.tril_dbg_st_audit_sample.argtypes = [vp, ctypes.c_int, _i32p, _dp, i64, _i64p]
     L.tril_dbg_boxes.argtypes = [vp, ctypes.c_int, vp, i64, _i64p]
     L.tril_dbg_query_records.argtypes = [vp, i32, vp, i64, _i64p]
     L.tril_dbg_target_rows.argtypes = [vp, _i32p, i64, _i64p]
@@ -552,8 +578,60 @@ class Mlp:
 
 
 def sur_params(cloud_factor: float = 0.0, eps: float = 0.0, gate: float = 0.0,
-               scale: float = 0.0, per_pair: bool = False) -> tril_st_sur_params:
-    return tril_st_sur_params(cloud_factor, eps, gate, scale, 1 if per_pair else 0, 0)
+               scale: float = 0.0, per_pair: bool = False, audit: bool = False,
+               audit_sample: int = 0, audit_reps: int = 0,
+               audit_seed: int = 0) -> tril_st_sur_params:
+    mode = 2 if audit else (1 if per_pair else 0)
+    return tril_st_sur_params(cloud_factor, eps, gate, scale, mode, 0, int(audit_sample),
+                              int(audit_reps), 0, int(audit_seed) & ((1 << 64) - 1))
+
+
+AUDIT_NETWORK, AUDIT_BIN_LEVEL, AUDIT_NONE = 0, 1, 2
+
+
+def tril_st_audit(ctx, mlp, target: Beam, t_bins, t_sums, t_grid, query: Beam, q_bins, q_sums,
+                  q_grid, k0: int, n_steps: int, control: int, n_sample: int = 0, n_rep: int = 0,
+                  seed: int = 0, mix: float = 0.0, sur=None) -> dict:
+    """Sampled estimate of the exact total (see tril.h); returns the result fields, with the
+    replicate estimates as a list."""
+    r = tril_st_audit_result()
+    gq, gt = st_grid(q_grid), st_grid(t_grid)
+    ap = tril_st_audit_params(int(n_sample), int(n_rep), int(control),
+                              int(seed) & ((1 << 64) - 1), float(mix))
+    sp = sur or sur_params()
+    _check(lib().tril_st_audit(_h(ctx), mlp.h if mlp is not None else None,
+                               ctypes.byref(target.c), t_bins.data_ptr() if target.n else None,
+                               t_sums.data_ptr(), ctypes.byref(gt), ctypes.byref(query.c),
+                               q_bins.data_ptr() if query.n else None, q_sums.data_ptr(),
+                               ctypes.byref(gq), int(k0), int(n_steps), ctypes.byref(sp),
+                               ctypes.byref(ap), ctypes.byref(r)), "tril_st_audit")
+    out = {k: getattr(r, k) for k, _ in tril_st_audit_result._fields_
+           if k not in ("rep", "n_sampled", "pad0")}
+    out["rep"] = list(r.rep[: r.n_rep])
+    out["n_sampled"] = (r.n_sampled[0], r.n_sampled[1])
+    return out
+
+
+def tril_st_calibrate(mlp, x, y0, y_exact, eps: float = 1e-3) -> float:
+    """Exact over predicted total on feature rows (device tensors), reduced in a fixed
+    order in the library."""
+    out = ctypes.c_double(0.0)
+    _check(lib().tril_st_calibrate(mlp.h, x.data_ptr(), y0.data_ptr(), y_exact.data_ptr(),
+                                   int(x.shape[0]), float(eps), ctypes.byref(out)),
+           "tril_st_calibrate")
+    return out.value
+
+
+def tril_dbg_st_audit_sample(ctx, side: int, cap: int):
+    """Rows and inclusion probabilities of the last replicate's thinned beam (side 0 query,
+    1 target), host arrays."""
+    rows = np.zeros(max(cap, 1), dtype=np.int32)
+    pis = np.zeros(max(cap, 1), dtype=np.float64)
+    n = ctypes.c_int64(0)
+    _check(lib().tril_dbg_st_audit_sample(_h(ctx), int(side), rows.ctypes.data_as(_i32p),
+                                          pis.ctypes.data_as(_dp), max(cap, 1), ctypes.byref(n)),
+           "tril_dbg_st_audit_sample")
+    return rows[: n.value], pis[: n.value]
 
 
 def tril_st_features(ctx, q_sums, q_grid, t_sums, t_grid, k0: int, n_steps: int, params=None,
@@ -675,14 +753,14 @@ def _h(ctx):
     return ctx.h if isinstance(ctx, Context) else ctx
 
 
-def tril_dbg_vmem_rate(divergent: bool, blocks: int = 4096, iters: int = 2048,
-                       stream=None) -> float:
-    """Bytes per second the vector-memory path delivers for 64-byte records read as four
-    16-byte loads per lane from an L1-resident window."""
-    out = ctypes.c_double(0.0)
-    _check(lib().tril_dbg_vmem_rate(1 if divergent else 0, blocks, iters, ctypes.byref(out),
-                                    _stream(stream)), "tril_dbg_vmem_rate")
-    return out.value
+DBG_DIV64, DBG_SQRT64, DBG_DIV32, DBG_SQRT32, DBG_LOG32, DBG_LOG1P32 = range(6)
+
+
+def tril_dbg_math(which: int, a, b, out, stream=None) -> None:
+    """One narrow-phase device operation per element of float64 device tensors."""
+    _check(lib().tril_dbg_math(int(which), int(a.numel()), a.data_ptr(),
+                               b.data_ptr() if b is not None else None, out.data_ptr(),
+                               _stream(stream)), "tril_dbg_math")
 
 
 def tril_dbg_tree(ctx, n_target: int, n_inst: int = 1, m: int = 1):

@@ -131,6 +131,25 @@ def test_broadband_subsample_all_steps(torch):
     assert_parity(gpu, raw, S, wl.n_steps)
 
 
+@pytest.mark.timeout(900)
+def test_broadband_1e5_subsample_all_steps_with_spectrum(torch):
+    """The large broadband workload's parity subsample: the first 1e5 photons of each
+    1.6e7-photon beam (photons are drawn independently, so the prefix is a uniform sample),
+    each carrying the weight of the 160 photons it stands for (so that the subsample holds
+    the beam's physical photons and collides like it), all 1000 steps: pair set, first
+    steps, per-step counts, yield and pair-energy spectrum against the oracle."""
+    wl = beams.broadband_16m()
+    A, B = beams.draw_pair(wl)
+    A, B = beams.head(A, 100_000), beams.head(B, 100_000)
+    for X in (A, B):
+        X["w"] = X["w"] * (wl.a.n / 100_000)
+    raw, S = oracle_run(A, B, wl.dt, wl.n_steps, EDGES)
+    gpu = gpu_run(A, B, wl.dt, wl.n_steps, EDGES, graph=True, cap=1 << 22)
+    assert S.n_pairs > 1000
+    assert np.count_nonzero(S.spectrum) > 10
+    assert_parity(gpu, raw, S, wl.n_steps)
+
+
 def test_batched_instances_ragged(torch):
     """Several independent collisions in one launch, including empty and one-photon
     instances; photons only collide within their own instance."""

@@ -126,3 +126,30 @@ def test_st_empty_beams(torch):
     grids = (beams.st_grid(wl, "a", A), beams.st_grid(wl, "b", B))
     keys, ys, tot, _, _, _ = _exact(torch, beams.head(A, 0), B, wl, 0, 50, grids=grids)
     assert len(keys) == 0 and tot == 0.0
+
+
+def _rows(beam, rows):
+    return {k: np.ascontiguousarray(v[rows]) for k, v in beam.items()}
+
+
+@pytest.mark.timeout(900)
+def test_st_exact_full_target_sampled_query_rows_all_steps(torch):
+    """The benchmark's statistical-regime instance (2e5 macro-particles per beam, the full
+    32^3 x 16 x 8 binning grid, all 400 steps): 160 sampled query rows (80 from the dense
+    core of the beam, 80 at random) against the whole target beam through the hierarchy;
+    every bin-pair yield and the total against the oracle."""
+    wl = beams.st_headon(200_000)
+    A, B = beams.draw_pair(wl)
+    ga, gb = beams.st_grid(wl, "a", A), beams.st_grid(wl, "b", B)
+    rng = np.random.default_rng(21)
+    r2 = A["x"] ** 2 + A["y"] ** 2 + (A["z"] + 20.0) ** 2
+    core = np.nonzero(r2 < 4.0)[0]
+    rows = np.unique(np.concatenate([rng.choice(core, 80, replace=False),
+                                     rng.choice(len(A["E"]), 80, replace=False)]))
+    As = _rows(A, rows)
+    ba, _ = SO.bin_beam(As, ga)
+    bb, _ = SO.bin_beam(B, gb)
+    ref, ref_tot = SO.st_table(As, ba, B, bb, gb.n_bins, wl.dt, 0, wl.n_steps, ga.cell)
+    keys, ys, tot, _, _, _ = _exact(torch, As, B, wl, 0, wl.n_steps, grids=(ga, gb), cap_log2=20)
+    assert len(ref) > 1000 and ref_tot > 0
+    _assert_tables(keys, ys, tot, ref, ref_tot)
