@@ -18,10 +18,9 @@ traversal's launch durations. The JSON line also carries
     node; 8 B per candidate written) over its average launch duration, against 8 TB/s;
     `traffic` is the HBM bytes per launch measured with rocprofv3 counters (the
     committed summary, when it belongs to the current kernel source);
-  * roofline_vmem: the traversal's L1 tag lookups per second (rocprofv3 counters of the
-    committed summary over the same duration) against one lookup per clock per CU; every
-    node load of every lane passes through them, and they bind the kernel (the texture
-    data unit is busy for almost every cycle of it);
+  * roofline_vmem: the busy cycles of the texture data units (one per CU, through which
+    every lane's node load returns; rocprofv3 counters of the committed summary) against
+    all their cycles: the resource that binds the traversal;
   * cpu_baseline: the FP64 CPU oracle timed on a bounded sample of query rows of
     the same workload (all pairs of those rows, all time steps).
 """
@@ -277,6 +276,67 @@ def st_bench(args):
     print(json.dumps(out), flush=True)
 
 
+MLP_FLOP_PER_ROW = 2 * (6 * 256 + 2 * 256 * 256 + 256)  # one member, one row, forward
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def mlp_bench(args):
+    """The surrogate network's kernels alone (4-member ensemble, 6 -> 256 -> 256 -> 256 -> 1):
+    inference of --mlp-rows rows (the fused forward kernel, all members, plus the ensemble
+    reduction) and training member-steps at batch 8192 (forward, loss, backward, Adam),
+    timed with HIP events; FLOPs against the BF16 dense matrix-core peak."""
+    import numpy as np
+    import torch
+    from paper_1608_01125_amd import tril as T
+    n = args.mlp_rows
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.normal(0, 1, (n, 6)).astype(np.float32)).cuda()
+    y = torch.from_numpy(rng.normal(0, 1, n).astype(np.float32)).cuda()
+    net = T.Mlp(4, seed=3)
+    try:
+        net.fit_norm(x, y)
+        for _ in range(max(args.warmup, 1)):
+            net.predict(x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = []
+        for _ in range(args.steps):
+            e0.record()
+            net.predict(x)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        t_inf = sorted(ms)[len(ms) // 2]
+        net.train(x, y, 20, 8192, 1e-3, 0)
+        torch.cuda.synchronize()
+        steps = args.mlp_train_steps
+        e0.record()
+        net.train(x, y, steps, 8192, 1e-3, 1)
+        e1.record()
+        torch.cuda.synchronize()
+        t_step = e0.elapsed_time(e1) / (steps * 4)
+    finally:
+        net.close()
+    inf_flop = float(MLP_FLOP_PER_ROW) * n * 4
+    tr_flop = 3.0 * MLP_FLOP_PER_ROW * 8192
+    tf_inf = inf_flop / (t_inf * 1e-3) / 1e12
+    tf_tr = tr_flop / (t_step * 1e-3) / 1e12
+    out = {"metric": "surrogate ensemble rows/s (4 members)", "value": n / (t_inf * 1e-3),
+           "unit": "rows/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": t_inf, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "mlp", "rows": n, "members": 4,
+                      "layers": "6-256-256-256-1 SiLU"},
+           "roofline": {"bound": "mfma", "achieved": round(tf_inf, 1),
+                        "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(tf_inf / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
+                        "kernel": "k_mlp_fused", "flop_per_row_member": MLP_FLOP_PER_ROW},
+           "training": {"ms_per_member_step": t_step, "batch": 8192,
+                        "tflops_3x_forward": round(tf_tr, 2),
+                        "frac": round(tf_tr / MFMA_BF16_PEAK_TFLOPS, 5)}}
+    print(json.dumps(out), flush=True)
+
+
 def _progress(msg):
     """A progress line on stderr (long statistical-regime runs)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -522,6 +582,10 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick steps per launch, traversal workgroup size and Morton bits with "
                          "tril_autotune before timing (cached per workload shape)")
+    ap.add_argument("--mlp-rows", type=int, default=1_000_000, help="mlp: inference rows")
+    ap.add_argument("--mlp-train-steps", type=int, default=200, help="mlp: timed Adam steps")
+    ap.add_argument("--traverse-queue", action="store_true",
+                    help="traversal as a persistent grid taking queries from a work queue")
     ap.add_argument("--flags", type=int, default=0)
     args = ap.parse_args()
 
@@ -539,6 +603,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "st_headon":
         return st_bench(args)
+    if args.workload == "mlp":
+        return mlp_bench(args)
     wl, A, offA, B, offB, n_steps = make_workload(args.workload, args.physics_steps)
     nA, nB = len(A["E"]), len(B["E"])
     if offA is None:
@@ -590,6 +656,9 @@ def main():
 
     tb, qb = T.Beam(B, offB), T.Beam(A, offA)
     tune = None
+    if args.traverse_queue:
+        tune = {"block_traverse": args.block or 64, "step_batch": args.step_batch,
+                "morton_bits": 0, "traverse_queue": 1}
     if args.autotune:
         from paper_1608_01125_amd import autotune
         probe_ctx = T.Context(wl.dt, edges)
@@ -683,17 +752,17 @@ def main():
                     "traffic_frac": (round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
                                      if traffic else None),
                     "node_visits_per_query": round(st["n_node_visits"] / max(st["n_queries"], 1), 3)}
-        # vector-memory roof: every lane's node load goes through the CU's L1, which takes
-        # one tag lookup per clock (256 CUs x 2.4 GHz); lookups per launch from the
-        # committed counter summary (TCP_TOTAL_CACHE_ACCESSES)
-        looks = pmc.get("L1_lookups_per_dispatch")
-        peak_l = 256 * 2.4  # G lookups/s
-        ach_l = looks / avg_s / 1e9 if looks else None
-        roofline_vmem = {"bound": "vmem", "achieved": round(ach_l, 2) if ach_l else None,
-                         "peak": peak_l, "unit": "G L1 lookups/s",
-                         "frac": round(ach_l / peak_l, 4) if ach_l else None,
-                         "kernel": "k_traverse", "TD_busy": pmc.get("TD_busy"),
-                         "TA_busy": pmc.get("TA_busy"),
+        # vector-memory roof: every lane's node load returns through the CU's texture data
+        # unit (TD), one unit per CU at the 2.4 GHz clock; its busy cycles per launch come
+        # from the committed counter summary (TD_TD_BUSY over 256 CUs), so achieved / peak
+        # is the fraction of the kernel's time that unit is busy
+        td = pmc.get("TD_busy")
+        peak_td = 256 * 2.4  # G TD cycles/s
+        roofline_vmem = {"bound": "vmem", "achieved": round(td * peak_td, 2) if td else None,
+                         "peak": peak_td, "unit": "G TD-busy cycles/s",
+                         "frac": round(td, 4) if td else None,
+                         "kernel": "k_traverse", "TA_busy": pmc.get("TA_busy"),
+                         "L1_lookups_per_launch": pmc.get("L1_lookups_per_dispatch"),
                          "lane_bytes_per_launch": round(lane_bytes / n_launch, 1),
                          "lane_bytes_GBs": round(lane_bytes / n_launch / avg_s / 1e9, 2)}
 

@@ -285,7 +285,9 @@ typedef struct {
     int32_t block_traverse;       /* traversal workgroup size: 64, 128, 256 or 512 */
     int32_t step_batch;           /* steps per launch, >= 1 (0 = automatic) */
     int32_t morton_bits;          /* 0 (automatic) or 3..30, as in tril_params */
-    int32_t pad0;
+    int32_t traverse_queue;       /* 0: one traversal workgroup per block of queries (a flat
+                                     grid); 1: a persistent grid whose waves take chunks of
+                                     1024 queries from device-wide work queues */
     double ms_per_step;           /* tril_autotune: measured time per step of the best
                                      configuration (output; ignored by tril_set_tune) */
 } tril_tune;
@@ -294,7 +296,8 @@ typedef struct {
  * launch configurations and keep the fastest in the context (and in *best). Coordinate
  * descent: steps per launch (1 .. 128, within 2^27 photon-steps per launch, or within the
  * default batch budget where that is larger), then the
- * traversal workgroup size (64 .. 512), then the Morton bits (automatic or 30). Every
+ * traversal workgroup size (64 .. 512), then the Morton bits (automatic or 30), then the
+ * persistent work-queue traversal against the flat grid. Every
  * configuration runs twice (the first run captures its graphs and sizes the scratch);
  * the second is timed with HIP events on the context stream. Hits go to a scratch buffer
  * owned by the call; the counters are reset at the end (as tril_reset_counters).

@@ -98,6 +98,7 @@ struct tril_ctx {
     double *d_edges = nullptr;
     int64_t cand_cap_param = 0;
     int block = 64;
+    int trav_queue = 0;             // traversal as a persistent work queue (tril_tune)
     int32_t step_batch = 0;         // steps per launch in tril_run (0 = automatic)
     int morton_param = 0;           // Morton bits requested (0 = automatic)
     CloudBox cloud{0, {0.0, 0.0, 0.0}};  // box kind of the builds (statistical regime: clouds)
@@ -626,7 +627,7 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
     if (timed) CHK(timing_pair(c, st, c->ev_trav, true));
     launch_traverse(c->nodes, c->n_int, c->root_box, c->q_box, c->q_order, c->q_order_len, nv, q.n,
                     c->inst_root, c->cand_i, c->cand_j, c->cand_cap, c->d_cnt, c->block, st,
-                    records ? c->q_rec : nullptr, q.n_inst);
+                    records ? c->q_rec : nullptr, q.n_inst, c->trav_queue != 0);
     if (timed) CHK(timing_pair(c, st, c->ev_trav, false));
     if (timed) CHK(timing_pair(c, st, c->ev_narrow, true));
     launch_narrow(q, c->tgt, c->dt, c->sigma_up, c->cand_i, c->cand_j, c->cand_cap, out, c->d_cnt,
@@ -1092,6 +1093,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
                 (const void *)(uintptr_t)c->alloc_gen,
                 // every launch parameter read while the batch is captured
                 (const void *)(intptr_t)c->block, (const void *)(uintptr_t)c->flags,
+                (const void *)(intptr_t)c->trav_queue,
                 (const void *)(intptr_t)c->cand_cap};
             int slot = (c->gexec[0] && key == c->gkey[0]) ? 0
                        : (c->gexec[1] && key == c->gkey[1]) ? 1 : -1;
@@ -2290,6 +2292,7 @@ int tril_mlp_predict(tril_mlp *p, const float *x, int64_t n, float *mean, float 
     const int64_t chunk = std::min<int64_t>(n, (int64_t)1 << 20);
     float *outs = nullptr;
     CHK(dev_alloc(&outs, (size_t)(m.K * chunk)));
+    mlp_pack_inference(&m);
     for (int64_t a = 0; a < n; a += chunk) {
         const int64_t c = std::min(chunk, n - a);
         for (int k = 0; k < m.K; ++k) mlp_fused_forward(&m, k, x + a * kMlpIn, c, outs + (int64_t)k * c);
@@ -2318,7 +2321,9 @@ int tril_set_tune(tril_ctx *c, const tril_tune *tu) {
     if (blk != 64 && blk != 128 && blk != 256 && blk != 512) return TRIL_E_INVAL;
     if (tu->step_batch < 0) return TRIL_E_INVAL;
     if (tu->morton_bits != 0 && (tu->morton_bits < 3 || tu->morton_bits > 30)) return TRIL_E_INVAL;
+    if (tu->traverse_queue != 0 && tu->traverse_queue != 1) return TRIL_E_INVAL;
     c->block = blk;
+    c->trav_queue = tu->traverse_queue;
     c->step_batch = tu->step_batch;
     c->morton_param = tu->morton_bits;
     return TRIL_OK;
@@ -2355,10 +2360,12 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
     }
     c->flags &= ~TRIL_TIMING;  // time graph replays, as a run without per-phase events
     const int64_t rows = std::max<int64_t>(std::max(t->n, q->n), 1);
+    int cur_queue = 0;
     auto probe = [&](int blk, int sb, int mb, double &ms) -> int {
         c->block = blk;
         c->step_batch = sb;
         c->morton_param = mb;
+        c->trav_queue = cur_queue;
         for (int rep = 0; rep < 2; ++rep) {
             HIPCHK(hipMemsetAsync(pr.count, 0, sizeof(int64_t), c->st));
             HIPCHK(hipEventRecord(e0, c->st));
@@ -2373,6 +2380,7 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
     };
     tril_tune cur{64, 0, 0, 0, 0.0};
     cur.step_batch = pick_batch(c, t, q, n_probe);
+    cur_queue = 0;
     double best_ms = 0.0;
     if ((rc = probe(cur.block_traverse, cur.step_batch, cur.morton_bits, best_ms)) != TRIL_OK) {
         cleanup();
@@ -2405,12 +2413,23 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
             cur.morton_bits = 30;
         }
     }
+    if (rc == TRIL_OK) {  // the persistent work-queue traversal against the flat grid
+        double ms = 0.0;
+        cur_queue = 1;
+        if ((rc = probe(cur.block_traverse, cur.step_batch, cur.morton_bits, ms)) == TRIL_OK &&
+            ms < best_ms) {
+            best_ms = ms;
+            cur.traverse_queue = 1;
+        }
+        cur_queue = cur.traverse_queue;
+    }
     cleanup();
     if (rc != TRIL_OK) return rc;
     cur.ms_per_step = best_ms;
     c->block = cur.block_traverse;
     c->step_batch = cur.step_batch;
     c->morton_param = cur.morton_bits;
+    c->trav_queue = cur.traverse_queue;
     *best = cur;
     return tril_reset_counters(c);
 }

@@ -98,13 +98,14 @@ __device__ __forceinline__ uint32_t morton30(const float c[3], const float lo[3]
 }
 
 // Per-batch bookkeeping. kind 0: build (counts m steps built); kind 1: collide
-// (counts m steps, resets the candidate counter of the batch).
+// (counts m steps, resets the candidate counter and the traversal's work-queue cursor).
 __global__ void k_prologue(DevCounters *c, int kind, int32_t m) {
     if (kind == 0) {
         c->builds += (unsigned long long)m;
     } else {
         c->collides += (unsigned long long)m;
         c->cand_step = 0ull;
+        for (int x = 0; x < kTravCursors; ++x) c->trav_next[x] = 0ull;
     }
 }
 

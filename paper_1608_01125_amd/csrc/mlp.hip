@@ -67,6 +67,8 @@ struct GemmArgs {
     float *out;         // [M x N] row-major FP32 (z, silu(z) or the gradient), or null
     uint16_t *out_bf;   // [M x N] row-major BF16 copy, or null
     float *out_pre;     // [M x N] pre-activation (with kEpiSilu), or null
+    int kc;             // K per slice: workgroup z takes k in [z kc, (z + 1) kc) and writes
+                        // its partial product to out + z M N (no epilogue); kc >= K: one slice
 };
 
 // One 64 x 32 operand tile into LDS as [row][k]: element (r, k) at P[(r0 + r) sr + (k0 + k) sk],
@@ -122,14 +124,16 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int kb = blockIdx.z * g.kc, ke = min(g.K, kb + g.kc);
+    float *outp = g.out ? g.out + (int64_t)blockIdx.z * g.M * g.N : nullptr;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += kTK) {
-        load_tile(g.A, g.sam, g.sak, m0, g.M, k0, g.K, sA, tid);
-        load_tile(g.B, g.sbn, g.sbk, n0, g.N, k0, g.K, sB, tid);
+    for (int k0 = kb; k0 < ke; k0 += kTK) {
+        load_tile(g.A, g.sam, g.sak, m0, g.M, k0, ke, sA, tid);
+        load_tile(g.B, g.sbn, g.sbk, n0, g.N, k0, ke, sB, tid);
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -164,7 +168,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
                     const float sg = sigmoidf_(z);
                     v = v * (sg * (1.0f + z * (1.0f - sg)));
                 }
-                if (g.out) g.out[o] = v;
+                if (outp) outp[o] = v;
                 if (g.out_bf) g.out_bf[o] = to_bf16(v);
             }
 }
@@ -201,19 +205,29 @@ __global__ void k_mlp_loss(const float *__restrict__ yhat, const float *__restri
     if ((threadIdx.x & 63) == 0 && l != 0.f) atomicAdd(loss_sum, l);
 }
 
-// Column sums of a [n x c] row-major FP32 matrix (bias gradients).
-__global__ void k_colsum(const float *__restrict__ a, int64_t n, int c, float *__restrict__ out) {
-    const int col = blockIdx.x;
+// Column sums of a [n x c] row-major FP32 matrix (bias gradients, c <= 256), in a fixed
+// order: workgroup z sums rows [z rs, (z + 1) rs) with one thread per column (rows read
+// whole), into part[z c + col]; k_slices_add folds the slices in order.
+__global__ void __launch_bounds__(256) k_colsum(const float *__restrict__ a, int64_t n, int c,
+                                                int64_t rs, float *__restrict__ part) {
+    const int col = threadIdx.x;
+    if (col >= c) return;
+    const int64_t i0 = blockIdx.x * rs, i1 = min(n, i0 + rs);
     float s = 0.f;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) s += a[i * c + col];
-    __shared__ float red[256];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[col] = red[0];
+#pragma unroll 8
+    for (int64_t i = i0; i < i1; ++i) s += a[i * c + col];
+    part[(int64_t)blockIdx.x * c + col] = s;
+}
+
+// out[e] = sum over slices z (in order) of part[z m + e], e < m.
+__global__ void k_slices_add(const float *__restrict__ part, int n_slices, int64_t m,
+                             float *__restrict__ out) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    float s = 0.f;
+#pragma unroll 8
+    for (int z = 0; z < n_slices; ++z) s += part[(int64_t)z * m + e];
+    out[e] = s;
 }
 
 __global__ void k_cast_bf16(const float *__restrict__ a, int64_t n, uint16_t *__restrict__ b) {
@@ -253,16 +267,30 @@ __global__ void k_mlp_reduce(const float *__restrict__ out, int64_t n, int K, fl
     sdev[i] = K > 1 ? sqrtf(fmaxf(s2 / (float)K - mu * mu, 0.0f) * (float)K / (float)(K - 1)) : 0.0f;
 }
 
-// Inference of one member, all four layers in one kernel: a workgroup takes 128 rows; the
-// standardised input (rounded to BF16) and layer 1 (K = 6) run on the vector units; the
-// 128 x 256 hidden activations stay in LDS as BF16; layers 2 and 3 run on the matrix cores
-// (each wave 64 output columns for all 128 rows: 8 x 4 tiles of 16 x 16, weight fragments
-// read once per k step from L2 and reused over the 8 row tiles), their results held in
-// registers until every wave has read the old activations, then written back in place;
-// layer 4 is a dot product per row. Same rounding points as the layer-by-layer path; the
-// activation uses the hardware exponential and reciprocal.
+// Inference of one member, all four layers in one kernel. A workgroup takes 128 rows; its
+// four waves each own 64 output features of every hidden layer. The products run on the
+// matrix cores with the weights as the A operand (16 features x 32 inputs per fragment,
+// read from an aligned copy of the member's BF16 weights, the next k step's fragments in
+// flight while the current ones multiply) and the activations as the B operand (16 rows x
+// 32 inputs from LDS); a lane's result is then 4 consecutive features of one row, which the
+// epilogue (bias, SiLU from the hardware exponential and reciprocal, two-at-a-time BF16
+// conversion) stores as one 8-byte LDS write. Layer 1 runs the same way with its 6 inputs
+// padded with zeros to 32; layer 4 is a dot product per row on pairs of BF16 values. The
+// 128 x 256 activations live in LDS as BF16 and are overwritten in place layer by layer.
+// Same rounding points as the layer-by-layer path (input, every hidden activation to BF16,
+// FP32 accumulation); the activation uses the hardware exponential and reciprocal.
 constexpr int kFR = 128;                 // rows per workgroup
-constexpr int kHL = kMlpHidden + 8;      // LDS row stride (BF16 elements), padded
+constexpr int kHL = kMlpHidden + 8;      // LDS row stride of the activations (BF16), padded
+constexpr int kXL = 40;                  // LDS row stride of the padded input (BF16)
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack2_bf16(float a, float b) {
+    bf16x2_t v;
+    v[0] = (__bf16)a;
+    v[1] = (__bf16)b;
+    return __builtin_bit_cast(uint32_t, v);
+}
 
 __global__ void __launch_bounds__(256, 2) k_mlp_fused(const float *__restrict__ x, int64_t n,
                                                       const float *__restrict__ norm,
@@ -270,78 +298,112 @@ __global__ void __launch_bounds__(256, 2) k_mlp_fused(const float *__restrict__ 
                                                       const float *__restrict__ w,
                                                       float *__restrict__ out) {
     __shared__ __align__(16) uint16_t sH[kFR][kHL];
-    __shared__ float sX[kFR][kMlpIn];
+    __shared__ __align__(16) uint16_t sX[kFR][kXL];
+    __shared__ __align__(16) uint16_t sW4[kMlpHidden];
     const int64_t r0 = blockIdx.x * (int64_t)kFR;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = tid; i < kFR * kMlpIn; i += 256) {
-        const int r = i / kMlpIn, c = i - r * kMlpIn;
+    // standardised input rounded to BF16, inputs 6..31 zero
+    for (int i = tid; i < kFR * 32; i += 256) {
+        const int r = i >> 5, c = i & 31;
         float v = 0.0f;
-        if (r0 + r < n) v = from_bf16(to_bf16((x[(r0 + r) * kMlpIn + c] - norm[c]) / norm[kMlpIn + c]));
-        sX[r][c] = v;
+        if (c < kMlpIn && r0 + r < n) v = (x[(r0 + r) * kMlpIn + c] - norm[c]) / norm[kMlpIn + c];
+        sX[r][c] = __builtin_bit_cast(uint16_t, (__bf16)v);
     }
+    sW4[tid] = wb[kOffW4 + tid];
     __syncthreads();
-    {   // layer 1: thread = output column
-        const int j = tid;
-        float wj[kMlpIn];
-#pragma unroll
-        for (int c = 0; c < kMlpIn; ++c) wj[c] = from_bf16(wb[kOffW1 + j * kMlpIn + c]);
-        const float bj = w[kOffB1 + j];
-        for (int r = 0; r < kFR; ++r) {
-            float z = 0.0f;
-#pragma unroll
-            for (int c = 0; c < kMlpIn; ++c) z += sX[r][c] * wj[c];
-            z += bj;
-            sH[r][j] = to_bf16(silu_fast(z));
-        }
-    }
-    __syncthreads();
-    const int nb = wave * 64;
+    const int f0 = wave * 64;              // this wave's output features
+    const int lr = lane & 15, lk = 8 * (lane >> 4), lf = 4 * (lane >> 4);
 #pragma unroll 1
-    for (int layer = 0; layer < 2; ++layer) {
-        const uint16_t *W = wb + (layer == 0 ? kOffW2 : kOffW3);
-        const float *bias = w + (layer == 0 ? kOffB2 : kOffB3);
-        f32x4 acc[8][4];
+    for (int layer = 0; layer < 3; ++layer) {
+        f32x4 acc[4][8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < kMlpHidden; k0 += 32) {
-            bf16x8 bfr[4];
+            for (int j = 0; j < 8; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (layer == 0) {
+            bf16x8 a[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int ncol = nb + j * 16 + (lane & 15);
-                bfr[j] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)ncol * kMlpHidden + k0 + 8 * (lane >> 4));
+            for (int mt = 0; mt < 4; ++mt) {
+                const uint16_t *wr = wb + kOffW1 + (int64_t)(f0 + mt * 16 + lr) * kMlpIn;
+                uint16_t e[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) e[c] = (lk == 0 && c < kMlpIn) ? wr[c] : (uint16_t)0;
+                a[mt] = __builtin_bit_cast(bf16x8, e);
             }
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sH[i * 16 + (lane & 15)][k0 + 8 * (lane >> 4)]);
+            for (int nt = 0; nt < 8; ++nt) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&sX[nt * 16 + lr][lk]);
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[j], acc[i][j], 0, 0, 0);
+                for (int mt = 0; mt < 4; ++mt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bv, acc[mt][nt], 0, 0, 0);
+            }
+        } else {
+            const uint16_t *W = wb + (layer == 1 ? kOffW2 : kOffW3);
+            bf16x8 a[4], an[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                a[mt] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)(f0 + mt * 16 + lr) * kMlpHidden + lk);
+#pragma unroll
+            for (int k0 = 0; k0 < kMlpHidden; k0 += 32) {
+                if (k0 + 32 < kMlpHidden) {
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+                        an[mt] = *reinterpret_cast<const bf16x8 *>(
+                            W + (int64_t)(f0 + mt * 16 + lr) * kMlpHidden + k0 + 32 + lk);
+                }
+#pragma unroll
+                for (int nt = 0; nt < 8; ++nt) {
+                    const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&sH[nt * 16 + lr][k0 + lk]);
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], bv, acc[mt][nt], 0, 0, 0);
+                }
+                if (k0 + 32 < kMlpHidden) {
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt) a[mt] = an[mt];
+                }
             }
         }
         __syncthreads();  // every wave has read the previous activations
+        const float *bias = w + (layer == 0 ? kOffB1 : (layer == 1 ? kOffB2 : kOffB3));
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
+        for (int mt = 0; mt < 4; ++mt) {
+            const int f = f0 + mt * 16 + lf;
+            const float b0 = bias[f], b1 = bias[f + 1], b2 = bias[f + 2], b3 = bias[f + 3];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = i * 16 + 4 * (lane >> 4) + r;
-                    const int col = nb + j * 16 + (lane & 15);
-                    const float z = acc[i][j][r] + bias[col];
-                    sH[row][col] = to_bf16(silu_fast(z));
-                }
+            for (int nt = 0; nt < 8; ++nt) {
+                const f32x4 z = acc[mt][nt];
+                uint2 pk;
+                pk.x = pack2_bf16(silu_fast(z[0] + b0), silu_fast(z[1] + b1));
+                pk.y = pack2_bf16(silu_fast(z[2] + b2), silu_fast(z[3] + b3));
+                *reinterpret_cast<uint2 *>(&sH[nt * 16 + lr][f]) = pk;
+            }
+        }
         __syncthreads();
     }
-    {   // layer 4: two threads per row
+    {   // layer 4: two threads per row, 64 pairs of BF16 products each
         const int row = tid >> 1, half = tid & 1;
+        const uint32_t *hrow = reinterpret_cast<const uint32_t *>(&sH[row][half * 128]);
+        const uint32_t *wrow = reinterpret_cast<const uint32_t *>(&sW4[half * 128]);
         float s = 0.0f;
-        for (int c = half * 128; c < half * 128 + 128; ++c)
-            s += from_bf16(sH[row][c]) * from_bf16(wb[kOffW4 + c]);
+#pragma unroll 8
+        for (int c = 0; c < 64; ++c)
+            s = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, hrow[c]),
+                                                __builtin_bit_cast(bf16x2_t, wrow[c]), s, false);
         s += __shfl_xor(s, 1);
         if (half == 0 && r0 + row < n) out[r0 + row] = s + w[kOffB4];
     }
+}
+
+// Member weights in BF16 at a stride that keeps every layer's rows 16-byte aligned.
+constexpr int64_t kMlpInfStride = (kMlpParams + 63) / 64 * 64;
+
+__global__ void k_mlp_pack_inference(const uint16_t *__restrict__ wb, int K,
+                                     uint16_t *__restrict__ wbi) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)K * kMlpParams) return;
+    const int64_t k = i / kMlpParams;
+    wbi[k * kMlpInfStride + (i - k * kMlpParams)] = wb[i];
 }
 
 // Minibatch rows of member k at a training step: a counter-based hash of (seed, k,
@@ -408,11 +470,15 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
+void mlp_pack_inference(MlpModel *m) {
+    hipLaunchKernelGGL(k_mlp_pack_inference, dim3(blocks((int64_t)m->K * kMlpParams, 256)), dim3(256),
+                       0, m->st, m->wb, m->K, m->wbi);
+}
+
 void mlp_fused_forward(MlpModel *m, int k, const float *x, int64_t n, float *out) {
     if (n <= 0) return;
-    const int64_t o = (int64_t)k * kMlpParams;
     hipLaunchKernelGGL(k_mlp_fused, dim3(blocks(n, kFR)), dim3(256), 0, m->st, x, n, m->norm,
-                       m->wb + o, m->w + o, out);
+                       m->wbi + (int64_t)k * kMlpInfStride, m->w + (int64_t)k * kMlpParams, out);
 }
 
 void mlp_batch_idx(MlpModel *m, uint64_t seed, int k, int64_t step, int64_t n, int64_t batch) {
@@ -431,8 +497,33 @@ void mlp_gemm(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B, in
               int64_t sbn, int M, int N, int K, int epi, const float *bias, const float *aux,
               float *out, uint16_t *out_bf, float *out_pre, hipStream_t st) {
     if (M <= 0 || N <= 0) return;
-    GemmArgs g{A, sam, sak, B, sbk, sbn, M, N, K, epi, bias, aux, out, out_bf, out_pre};
+    GemmArgs g{A, sam, sak, B, sbk, sbn, M, N, K, epi, bias, aux, out, out_bf, out_pre,
+               std::max(K, 1)};
     hipLaunchKernelGGL(k_gemm, dim3(blocks(N, kTN), blocks(M, kTM)), dim3(256), 0, st, g);
+}
+
+// C = A B over a long K (the weight gradients: K = batch rows) in kMlpSlices slices of K, each
+// slice's partial product into part (kMlpSlices M N floats), then added in a fixed order.
+static void mlp_gemm_sliced(const uint16_t *A, int64_t sam, int64_t sak, const uint16_t *B,
+                            int64_t sbk, int64_t sbn, int M, int N, int K, float *part, float *out,
+                            hipStream_t st) {
+    if (M <= 0 || N <= 0) return;
+    const int kc = std::max(kTK, ((K + kMlpSlices - 1) / kMlpSlices + kTK - 1) / kTK * kTK);
+    const int ns = std::max(1, (K + kc - 1) / kc);
+    GemmArgs g{A, sam, sak, B, sbk, sbn, M, N, K, 0, nullptr, nullptr, part, nullptr, nullptr, kc};
+    hipLaunchKernelGGL(k_gemm, dim3(blocks(N, kTN), blocks(M, kTM), (unsigned)ns), dim3(256), 0, st,
+                       g);
+    const int64_t m = (int64_t)M * N;
+    hipLaunchKernelGGL(k_slices_add, dim3(blocks(m, 256)), dim3(256), 0, st, part, ns, m, out);
+}
+
+static void mlp_colsum(const float *a, int64_t n, int c, float *part, float *out, hipStream_t st) {
+    // 64 rows per slice (at least n / 4096 so that the slices fit the partial buffer)
+    const int64_t rs = std::max<int64_t>(64, (n + 4095) / 4096);
+    const int ns = (int)std::max<int64_t>(1, (n + rs - 1) / rs);
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)ns), dim3(256), 0, st, a, n, c, rs, part);
+    hipLaunchKernelGGL(k_slices_add, dim3(blocks(c, 256)), dim3(256), 0, st, part, ns, (int64_t)c,
+                       out);
 }
 
 // ---------------------------------------------------------------------------- model
@@ -458,6 +549,7 @@ int mlp_init(MlpModel *m, int K, uint64_t seed, hipStream_t st) {
     const size_t P = (size_t)K * kMlpParams;
     int r;
     if ((r = mlp_alloc(m, &m->w, P)) || (r = mlp_alloc(m, &m->wb, P)) ||
+        (r = mlp_alloc(m, &m->wbi, (size_t)K * kMlpInfStride)) ||
         (r = mlp_alloc(m, &m->g, kMlpParams)) || (r = mlp_alloc(m, &m->am, P)) ||
         (r = mlp_alloc(m, &m->av, P)) || (r = mlp_alloc(m, &m->norm, 2 * kMlpIn)))
         return r;
@@ -505,7 +597,8 @@ int mlp_scratch(MlpModel *m, int64_t rows) {
         (r = mlp_alloc(m, &m->dz2, (size_t)(rows * H))) || (r = mlp_alloc(m, &m->dz2b, (size_t)(rows * H))) ||
         (r = mlp_alloc(m, &m->yhat, (size_t)rows)) || (r = mlp_alloc(m, &m->dy, (size_t)rows)) ||
         (r = mlp_alloc(m, &m->dyb, (size_t)rows)) || (r = mlp_alloc(m, &m->loss, 1)) ||
-        (r = mlp_alloc(m, &m->idx, (size_t)rows)))
+        (r = mlp_alloc(m, &m->idx, (size_t)rows)) ||
+        (!m->gpart && (r = mlp_alloc(m, &m->gpart, (size_t)kMlpSlices * H * H))))
         return r;
     m->rows = rows;
     return TRIL_OK;
@@ -536,28 +629,24 @@ void mlp_backward(MlpModel *m, int k, int64_t n) {
     hipStream_t st = m->st;
     float *g = m->g;
     // output layer: dW4[j] = sum_i dy_i h3[i][j]; db4 = sum_i dy_i
-    mlp_gemm(m->dyb, 0, 1, m->h3, H, 1, 1, H, (int)n, 0, nullptr, nullptr, g + kOffW4, nullptr,
-             nullptr, st);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(256), 0, st, m->dy, n, 1, g + kOffB4);
+    mlp_gemm_sliced(m->dyb, 0, 1, m->h3, H, 1, 1, H, (int)n, m->gpart, g + kOffW4, st);
+    mlp_colsum(m->dy, n, 1, m->gpart, g + kOffB4, st);
     // dZ3 = (dy w4^T) * silu'(z3)
     mlp_gemm(m->dyb, 1, 1, wb + kOffW4, 1, 1, (int)n, H, 1, kEpiDSilu, nullptr, m->z3, m->dz,
              m->dzb, nullptr, st);
     // layer 3: dW3 = dZ3^T H2, db3 = colsum dZ3, dZ2 = (dZ3 W3) * silu'(z2)
-    mlp_gemm(m->dzb, 1, H, m->h2, H, 1, H, H, (int)n, 0, nullptr, nullptr, g + kOffW3, nullptr,
-             nullptr, st);
-    hipLaunchKernelGGL(k_colsum, dim3(H), dim3(256), 0, st, m->dz, n, H, g + kOffB3);
+    mlp_gemm_sliced(m->dzb, 1, H, m->h2, H, 1, H, H, (int)n, m->gpart, g + kOffW3, st);
+    mlp_colsum(m->dz, n, H, m->gpart, g + kOffB3, st);
     mlp_gemm(m->dzb, H, 1, wb + kOffW3, H, 1, (int)n, H, H, kEpiDSilu, nullptr, m->z2, m->dz2,
              m->dz2b, nullptr, st);
     // layer 2
-    mlp_gemm(m->dz2b, 1, H, m->h1, H, 1, H, H, (int)n, 0, nullptr, nullptr, g + kOffW2, nullptr,
-             nullptr, st);
-    hipLaunchKernelGGL(k_colsum, dim3(H), dim3(256), 0, st, m->dz2, n, H, g + kOffB2);
+    mlp_gemm_sliced(m->dz2b, 1, H, m->h1, H, 1, H, H, (int)n, m->gpart, g + kOffW2, st);
+    mlp_colsum(m->dz2, n, H, m->gpart, g + kOffB2, st);
     mlp_gemm(m->dz2b, H, 1, wb + kOffW2, H, 1, (int)n, H, H, kEpiDSilu, nullptr, m->z1, m->dz,
              m->dzb, nullptr, st);
     // layer 1: dW1 = dZ1^T X, db1 = colsum dZ1
-    mlp_gemm(m->dzb, 1, H, m->xb, kMlpIn, 1, H, kMlpIn, (int)n, 0, nullptr, nullptr, g + kOffW1,
-             nullptr, nullptr, st);
-    hipLaunchKernelGGL(k_colsum, dim3(H), dim3(256), 0, st, m->dz, n, H, g + kOffB1);
+    mlp_gemm_sliced(m->dzb, 1, H, m->xb, kMlpIn, 1, H, kMlpIn, (int)n, m->gpart, g + kOffW1, st);
+    mlp_colsum(m->dz, n, H, m->gpart, g + kOffB1, st);
 }
 
 void mlp_input(MlpModel *m, const float *x, const int32_t *idx, int64_t n) {

@@ -1,3 +1,5 @@
+#include <algorithm>
+
 // Broad phase: every query photon's swept, radius-padded box descends the
 // target hierarchy depth-first (Sec. 2.2): a node whose box fails the overlap
 // test (Eq. 5) has its whole subtree skipped; a leaf whose box passes yields a
@@ -73,18 +75,19 @@ __device__ __forceinline__ void record_box(const float4 a, const float4 d, const
     moved_box(a.x, a.y, a.z, d.x, d.y, d.z, w.x, w.y, w.z, s, qb, qb + 3);
 }
 
-template <int BLOCK, bool kRec>
-__global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nodes, int32_t n_int,
-                                                    const PBox *__restrict__ root_box,
-                                                    const PBox *__restrict__ qbox,
-                                                    const QRec *__restrict__ qrec, int32_t n_inst,
-                                                    const uint32_t *__restrict__ qorder,
-                                                    int64_t order_len, int64_t nq, int64_t nq_base,
-                                                    const int32_t *__restrict__ inst_root,
-                                                    int32_t *__restrict__ cand_i,
-                                                    int32_t *__restrict__ cand_j, int64_t cand_cap,
-                                                    DevCounters *c) {
-    const int64_t q = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+// The descent of virtual query q (q >= nq: an idle lane that still takes part in the
+// wave's ballots); adds its node loads to *visits and returns whether it had a root.
+template <bool kRec>
+__device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict__ nodes,
+                                               int32_t n_int, const PBox *__restrict__ root_box,
+                                               const PBox *__restrict__ qbox,
+                                               const QRec *__restrict__ qrec, int32_t n_inst,
+                                               const uint32_t *__restrict__ qorder,
+                                               int64_t order_len, int64_t nq, int64_t nq_base,
+                                               const int32_t *__restrict__ inst_root,
+                                               int32_t *__restrict__ cand_i,
+                                               int32_t *__restrict__ cand_j, int64_t cand_cap,
+                                               DevCounters *c, uint32_t &visits) {
     int32_t node = -1, qi = 0, tag = -1;
     float qb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float qe = 0.f;
@@ -117,8 +120,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
         }
         if (tag >= 0) node = inst_root[tag];
     }
-    const unsigned long long active_q = __ballot(node != -1);
-    uint32_t visits = 0;
+    const bool active = node != -1;
     {
         // an instance of one row: its root is that leaf
         bool hit = false;
@@ -199,6 +201,27 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
             node = -1;
         }
     }
+    return active;
+}
+
+// One virtual query per lane over a flat grid.
+template <int BLOCK, bool kRec>
+__global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nodes, int32_t n_int,
+                                                    const PBox *__restrict__ root_box,
+                                                    const PBox *__restrict__ qbox,
+                                                    const QRec *__restrict__ qrec, int32_t n_inst,
+                                                    const uint32_t *__restrict__ qorder,
+                                                    int64_t order_len, int64_t nq, int64_t nq_base,
+                                                    const int32_t *__restrict__ inst_root,
+                                                    int32_t *__restrict__ cand_i,
+                                                    int32_t *__restrict__ cand_j, int64_t cand_cap,
+                                                    DevCounters *c) {
+    const int64_t q = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    uint32_t visits = 0;
+    const bool act = traverse_query<kRec>(q, nodes, n_int, root_box, qbox, qrec, n_inst, qorder,
+                                          order_len, nq, nq_base, inst_root, cand_i, cand_j,
+                                          cand_cap, c, visits);
+    const unsigned long long active_q = __ballot(act);
     // per-wave counter updates
     unsigned long long v = visits;
 #pragma unroll
@@ -210,12 +233,78 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
     }
 }
 
+
+// Persistent form: a fixed grid whose waves take chunks of kQueueChunk consecutive virtual
+// queries from device-wide cursors until the chunks run out; every wave leaves its loop once
+// its cursor passes the last chunk. Workgroup b uses cursor b mod 8 (one per XCD, as the
+// dispatcher deals workgroups out round-robin), which hands out chunks x, x + 8, x + 16, ...
+// (the cursors are cleared by the batch's prologue): one device atomic per chunk, spread
+// over eight addresses, instead of one per wave of queries at one address.
+constexpr int kQueueChunk = 1024;
+
+template <int BLOCK, bool kRec>
+__global__ void __launch_bounds__(BLOCK) k_traverse_queue(const Node *__restrict__ nodes,
+                                                          int32_t n_int,
+                                                          const PBox *__restrict__ root_box,
+                                                          const PBox *__restrict__ qbox,
+                                                          const QRec *__restrict__ qrec,
+                                                          int32_t n_inst,
+                                                          const uint32_t *__restrict__ qorder,
+                                                          int64_t order_len, int64_t nq,
+                                                          int64_t nq_base,
+                                                          const int32_t *__restrict__ inst_root,
+                                                          int32_t *__restrict__ cand_i,
+                                                          int32_t *__restrict__ cand_j,
+                                                          int64_t cand_cap, DevCounters *c) {
+    const int lane = threadIdx.x & 63;
+    const int x = blockIdx.x & (kTravCursors - 1);
+    uint32_t visits = 0;
+    unsigned long long n_active = 0;
+    for (;;) {
+        unsigned long long k = 0;
+        if (lane == 0) k = atomicAdd(&c->trav_next[x], 1ull);
+        k = __shfl(k, 0);
+        const int64_t base = ((int64_t)k * kTravCursors + x) * kQueueChunk;
+        if (base >= nq) break;
+        for (int sub = 0; sub < kQueueChunk; sub += 64) {
+            if (base + sub >= nq) break;
+            const bool act = traverse_query<kRec>(base + sub + lane, nodes, n_int, root_box, qbox,
+                                                  qrec, n_inst, qorder, order_len, nq, nq_base,
+                                                  inst_root, cand_i, cand_j, cand_cap, c, visits);
+            n_active += (unsigned long long)__popcll(__ballot(act));
+        }
+    }
+    unsigned long long v = visits;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) {
+        const int slot = blockIdx.x & (kCounterSlots - 1);
+        if (v) atomicAdd(&c->visits[slot], v);
+        if (n_active) atomicAdd(&c->queries[slot], n_active);
+    }
+}
+
 template <int BLOCK>
 void launch_traverse_b(const Node *nodes, int32_t n_int, const PBox *root_box, const PBox *qbox,
                        const QRec *qrec, int32_t n_inst, const uint32_t *qorder, int64_t order_len,
                        int64_t nq, int64_t nq_base, const int32_t *inst_root, int32_t *cand_i,
-                       int32_t *cand_j, int64_t cand_cap, DevCounters *c, hipStream_t st) {
-    const unsigned grid = (unsigned)((nq + BLOCK - 1) / BLOCK);
+                       int32_t *cand_j, int64_t cand_cap, DevCounters *c, bool queue,
+                       hipStream_t st) {
+    const int64_t want = (nq + BLOCK - 1) / BLOCK;
+    if (queue) {
+        // as many workgroups as keep 32 waves on each of the 256 CUs
+        const unsigned grid = (unsigned)std::min<int64_t>(want, 8192 * 64 / BLOCK);
+        if (qrec != nullptr)
+            hipLaunchKernelGGL((k_traverse_queue<BLOCK, true>), dim3(grid), dim3(BLOCK), 0, st, nodes,
+                               n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq, nq_base,
+                               inst_root, cand_i, cand_j, cand_cap, c);
+        else
+            hipLaunchKernelGGL((k_traverse_queue<BLOCK, false>), dim3(grid), dim3(BLOCK), 0, st,
+                               nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
+                               nq_base, inst_root, cand_i, cand_j, cand_cap, c);
+        return;
+    }
+    const unsigned grid = (unsigned)want;
     if (qrec != nullptr)
         hipLaunchKernelGGL((k_traverse<BLOCK, true>), dim3(grid), dim3(BLOCK), 0, st, nodes, n_int,
                            root_box, qbox, qrec, n_inst, qorder, order_len, nq, nq_base, inst_root,
@@ -255,25 +344,25 @@ void launch_traverse(const Node *nodes, int64_t n_int64, const PBox *root_box, c
                      const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
                      const int32_t *inst_root, int32_t *cand_i, int32_t *cand_j,
                      int64_t cand_cap, DevCounters *c, int block, hipStream_t st,
-                     const QRec *qrec, int32_t n_inst) {
+                     const QRec *qrec, int32_t n_inst, bool queue) {
     if (nq <= 0 || n_int64 < 0) return;
     const int32_t n_int = (int32_t)n_int64;
     switch (block) {
     case 64:
         launch_traverse_b<64>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
-                              nq_base, inst_root, cand_i, cand_j, cand_cap, c, st);
+                              nq_base, inst_root, cand_i, cand_j, cand_cap, c, queue, st);
         break;
     case 128:
         launch_traverse_b<128>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
-                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, st);
+                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, queue, st);
         break;
     case 512:
         launch_traverse_b<512>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
-                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, st);
+                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, queue, st);
         break;
     default:
         launch_traverse_b<256>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
-                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, st);
+                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, queue, st);
         break;
     }
 }

@@ -149,6 +149,7 @@ __device__ __forceinline__ void philox4x64_10(uint64_t x[4], uint64_t k0, uint64
 // modulo kCounterSlots): device-scope atomics to one address serialise at roughly
 // 10 ns each, so one address per counter would cost ~0.3 ms per million queries.
 constexpr int kCounterSlots = 256;
+constexpr int kTravCursors = 8;
 struct DevCounters {
     unsigned long long cand_step;      // candidates of the current step (reset per step)
     unsigned long long cand_total;
@@ -157,6 +158,7 @@ struct DevCounters {
     unsigned long long st_pairs;       // statistical regime: cloud pair-steps with a yield
     unsigned long long builds;
     unsigned long long collides;
+    unsigned long long trav_next[8];   // work-queue cursors of the persistent traversal
     unsigned int err;
     unsigned int step;                 // current step index (device-resident for graphs)
     unsigned long long visits[kCounterSlots];
@@ -341,7 +343,7 @@ void launch_traverse(const Node *nodes, int64_t n_int, const PBox *root_box, con
                      const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
                      const int32_t *inst_root, int32_t *cand_i, int32_t *cand_j,
                      int64_t cand_cap, DevCounters *c, int block, hipStream_t st,
-                     const QRec *qrec = nullptr, int32_t n_inst = 1);
+                     const QRec *qrec = nullptr, int32_t n_inst = 1, bool queue = false);
 void launch_narrow(const BeamDev &q, const BeamDev &t, double dt, double sigma_up,
                    const int32_t *cand_i, const int32_t *cand_j, int64_t cand_cap,
                    const tril_pairs &out, DevCounters *c, bool fp32_stage, hipStream_t st);
@@ -351,6 +353,7 @@ void launch_pair_eval(int64_t n, const double *in, double *out, hipStream_t st);
 // Surrogate network (mlp.hip): 6 -> 256 -> 256 -> 256 -> 1, K members.
 constexpr int kMlpIn = 6;
 constexpr int kMlpHidden = 256;
+constexpr int kMlpSlices = 16;  // K slices of the weight-gradient products (batch rows)
 constexpr int64_t kMlpParams = (int64_t)kMlpHidden * kMlpIn + kMlpHidden +
                                2 * ((int64_t)kMlpHidden * kMlpHidden + kMlpHidden) + kMlpHidden + 1;
 
@@ -359,6 +362,7 @@ struct MlpModel {
     hipStream_t st = nullptr;
     float *w = nullptr;         // FP32 master parameters, K x kMlpParams
     uint16_t *wb = nullptr;     // BF16 copy
+    uint16_t *wbi = nullptr;    // BF16 copy at an aligned member stride (inference)
     float *g = nullptr;         // gradient of one member
     float *am = nullptr, *av = nullptr;  // Adam moments
     float *norm = nullptr;      // input mean [6], sd [6]
@@ -373,6 +377,7 @@ struct MlpModel {
     uint16_t *dyb = nullptr;
     float *loss = nullptr;
     int32_t *idx = nullptr;
+    float *gpart = nullptr;     // slice partials of the weight gradients (kMlpSlices x H x H)
     int64_t adam_t = 0;
     std::vector<void *> allocs;
     ~MlpModel();
@@ -381,6 +386,9 @@ int mlp_init(MlpModel *m, int K, uint64_t seed, hipStream_t st);
 int mlp_scratch(MlpModel *m, int64_t rows);
 void mlp_input(MlpModel *m, const float *x, const int32_t *idx, int64_t n);
 void mlp_forward(MlpModel *m, int k, int64_t n, float *yhat_out);
+// Inference: refresh the aligned BF16 copy (before the members' forward passes), then one
+// fused forward pass of member k.
+void mlp_pack_inference(MlpModel *m);
 void mlp_fused_forward(MlpModel *m, int k, const float *x, int64_t n, float *out);
 void mlp_loss(MlpModel *m, const float *y, const int32_t *idx, int64_t n);
 void mlp_backward(MlpModel *m, int k, int64_t n);

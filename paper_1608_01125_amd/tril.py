@@ -69,7 +69,7 @@ class tril_stats_t(ctypes.Structure):
 
 class tril_tune(ctypes.Structure):
     _fields_ = [("block_traverse", ctypes.c_int32), ("step_batch", ctypes.c_int32),
-                ("morton_bits", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("morton_bits", ctypes.c_int32), ("traverse_queue", ctypes.c_int32),
                 ("ms_per_step", ctypes.c_double)]
 
 
@@ -407,7 +407,7 @@ def tril_pair_kinematics_noalloc(query: Beam, target: Beam, pairs: Pairs, n: int
         _stream(stream))
 
 
-TUNE_KEYS = ("block_traverse", "step_batch", "morton_bits")
+TUNE_KEYS = ("block_traverse", "step_batch", "morton_bits", "traverse_queue")
 
 
 def tril_autotune(ctx, target: Beam, query: Beam, k0: int, n_probe: int) -> dict:
@@ -415,13 +415,14 @@ def tril_autotune(ctx, target: Beam, query: Beam, k0: int, n_probe: int) -> dict
     _check(lib().tril_autotune(_h(ctx), ctypes.byref(target.c), ctypes.byref(query.c), int(k0),
                                int(n_probe), ctypes.byref(t)), "tril_autotune")
     return {"block_traverse": t.block_traverse, "step_batch": t.step_batch,
-            "morton_bits": t.morton_bits, "ms_per_step": t.ms_per_step}
+            "morton_bits": t.morton_bits, "traverse_queue": t.traverse_queue,
+            "ms_per_step": t.ms_per_step}
 
 
 def tril_set_tune(ctx, tune: dict) -> None:
     t = tril_tune()
     for k in TUNE_KEYS:
-        setattr(t, k, int(tune[k]))
+        setattr(t, k, int(tune.get(k, 0)))
     _check(lib().tril_set_tune(_h(ctx), ctypes.byref(t)), "tril_set_tune")
 
 

@@ -95,7 +95,9 @@ def test_autotune_keeps_pair_set_and_caches(torch, tmp_path):
 @pytest.mark.parametrize("tune", [
     {"block_traverse": 64, "step_batch": 3, "morton_bits": 30},
     {"block_traverse": 512, "step_batch": 40, "morton_bits": 0},
-    {"block_traverse": 128, "step_batch": 1, "morton_bits": 18}])
+    {"block_traverse": 128, "step_batch": 1, "morton_bits": 18},
+    {"block_traverse": 64, "step_batch": 0, "morton_bits": 0, "traverse_queue": 1},
+    {"block_traverse": 256, "step_batch": 7, "morton_bits": 0, "traverse_queue": 1}])
 def test_any_launch_configuration_same_pairs(torch, tune):
     A, offA, B, offB = _batch(8, 3000, 300.0)
     raw, S = oracle_run(A, B, 0.1, 400, EDGES, offA=offA, offB=offB)
@@ -105,7 +107,8 @@ def test_any_launch_configuration_same_pairs(torch, tune):
 @pytest.mark.parametrize("bad", [
     {"block_traverse": 96, "step_batch": 1, "morton_bits": 0},
     {"block_traverse": 256, "step_batch": -1, "morton_bits": 0},
-    {"block_traverse": 256, "step_batch": 4, "morton_bits": 2}])
+    {"block_traverse": 256, "step_batch": 4, "morton_bits": 2},
+    {"block_traverse": 256, "step_batch": 4, "morton_bits": 0, "traverse_queue": 2}])
 def test_set_tune_rejects_bad_values(torch, bad):
     ctx = T.Context(0.1, EDGES)
     try:
