@@ -56,11 +56,11 @@ def traverse_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_counters(dispatches=None) -> dict:
+def committed_counters(dispatches=None, window=None) -> dict:
     """Counter figures of one traversal launch from the committed rocprofv3 summary: HBM
     bytes (`traffic_bytes_per_dispatch`), L1 lookups, TA/TD busy fractions. Empty when the
-    summary was taken from a different kernel source or another batching (traversal launches
-    per collision run)."""
+    summary was taken from a different kernel source, another batching (traversal launches
+    per collision run) or another number of steps per tree copy."""
     if not os.path.exists(PMC_SUMMARY):
         return {}
     vals = {}
@@ -73,6 +73,8 @@ def committed_counters(dispatches=None) -> dict:
         return {}
     if dispatches is not None and vals.get("dispatches") != str(dispatches):
         return {}
+    if window is not None and vals.get("kinetic_window", "1") != str(window):
+        return {}
     out = {}
     for k in ("traffic_bytes_per_dispatch", "L1_lookups_per_dispatch", "TD_busy", "TA_busy",
               "L2_hit_rate"):
@@ -81,6 +83,21 @@ def committed_counters(dispatches=None) -> dict:
         except (KeyError, ValueError):
             pass
     return out
+
+
+def batch_sizes(n_steps: int, launches: int) -> list:
+    """Steps of each launch of a run split as the library splits it: full batches of
+    ceil(n_steps / launches) steps, the rest in the last."""
+    if not launches:
+        return [n_steps]
+    m = -(-n_steps // launches)
+    return [m] * (launches - 1) + [n_steps - m * (launches - 1)]
+
+
+def tree_window(tune, arg: int) -> int:
+    """Steps per tree copy in step batches (the library's default for 0)."""
+    w = (tune or {}).get("kinetic_window", arg) or arg
+    return 16 if w == 0 else w
 
 
 def make_workload(name: str, physics_steps: int):
@@ -560,6 +577,8 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--kinetic-window", type=int, default=0,
+                    help="steps per copy of the target hierarchy (0 = automatic, 1 = per step)")
     ap.add_argument("--st-mp", type=int, default=200_000,
                     help="st_headon: macro-particles per beam")
     ap.add_argument("--st-train", type=int, default=8, help="st_headon: training instances")
@@ -628,7 +647,7 @@ def main():
     def timed(flags):
         """Warm-up runs, then args.steps timed collision runs; returns (seconds, stats)."""
         ctx = T.Context(wl.dt, edges, flags=flags, block_traverse=args.block,
-                        step_batch=args.step_batch)
+                        step_batch=args.step_batch, kinetic_window=args.kinetic_window)
         if tune is not None:
             T.tril_set_tune(ctx.h, tune)
         pairs = T.Pairs(max(1 << 20, 4 * min(nA, nB)))
@@ -658,7 +677,7 @@ def main():
     tune = None
     if args.traverse_queue:
         tune = {"block_traverse": args.block or 64, "step_batch": args.step_batch,
-                "morton_bits": 0, "traverse_queue": 1}
+                "morton_bits": 0, "traverse_queue": 1, "kinetic_window": args.kinetic_window}
     if args.autotune:
         from paper_1608_01125_amd import autotune
         probe_ctx = T.Context(wl.dt, edges)
@@ -725,20 +744,28 @@ def main():
         # Two roofs of the traversal (k_traverse), each with bytes over the timed region,
         # per launch, divided by the average launch duration from HIP events recorded
         # around every traversal launch on the library's stream.
-        # HBM roof: the bytes the method must fetch from memory at least once per step: per
+        # HBM roof: the bytes the method must fetch from memory at least once: per
         # query-step its order entry and its row's record (4 + 48 B; 4 + 32 B box when every
-        # step is its own launch), each step's tree copy read once (64 B per internal node),
-        # 8 B per candidate written.
+        # step is its own launch), every copy of the tree read once (64 B per internal node;
+        # a copy per step, or per window of steps), with window copies every target record
+        # once per launch (48 B), 8 B per candidate written.
         q_bytes = 52.0 if (steps_per_dispatch or 1) >= 2 else 36.0
         n_inst = 1 if offB is None else len(offB) - 1
         n_int_step = max(nB - n_inst, 0)
         n_launch = st["n_timed_launches"]
-        hbm_bytes = (q_bytes * nA + 64.0 * n_int_step) * st["n_collides"] + 8.0 * st["n_candidates"]
+        runs = max(st["n_collides"] // max(n_steps, 1), 1)
+        batches = batch_sizes(n_steps, launches_per_run)
+        win = tree_window(tune, args.kinetic_window)
+        copies = sum(b if (win <= 1 or b < 2) else -(-b // win) for b in batches) * runs
+        rec_bytes = 48.0 * nB * sum(1 for b in batches if win > 1 and b >= 2) * runs
+        hbm_bytes = (q_bytes * nA * st["n_collides"] + 64.0 * n_int_step * copies + rec_bytes
+                     + 8.0 * st["n_candidates"])
         # vector-memory roof: the bytes the kernel's loads deliver to its lanes, every node
-        # load counted (64 B: both children's boxes and links), plus the query bytes and
-        # candidate stores above
-        lane_bytes = q_bytes * nA * st["n_collides"] + 64.0 * st["n_node_visits"] + 8.0 * st["n_candidates"]
-        pmc = committed_counters(launches_per_run or None)
+        # load counted (64 B: both children's boxes and links) and every leaf record read
+        # (48 B), plus the query bytes and candidate stores above
+        lane_bytes = (q_bytes * nA * st["n_collides"] + 64.0 * st["n_node_visits"]
+                      + 48.0 * st["n_leaf_checks"] + 8.0 * st["n_candidates"])
+        pmc = committed_counters(launches_per_run or None, win)
         traffic = pmc.get("traffic_bytes_per_dispatch")
         avg_s = st["ms_traverse"] * 1e-3 / n_launch
         achieved = hbm_bytes / n_launch / avg_s / 1e9
@@ -751,7 +778,9 @@ def main():
                     "traffic_achieved_GBs": (round(traffic / avg_s / 1e9, 2) if traffic else None),
                     "traffic_frac": (round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
                                      if traffic else None),
-                    "node_visits_per_query": round(st["n_node_visits"] / max(st["n_queries"], 1), 3)}
+                    "node_visits_per_query": round(st["n_node_visits"] / max(st["n_queries"], 1), 3),
+                    "tree_copies_per_run": copies // runs, "kinetic_window": win,
+                    "leaf_checks_per_query": round(st["n_leaf_checks"] / max(st["n_queries"], 1), 5)}
         # vector-memory roof: every lane's node load returns through the CU's texture data
         # unit (TD), one unit per CU at the 2.4 GHz clock; its busy cycles per launch come
         # from the committed counter summary (TD_TD_BUSY over 256 CUs), so achieved / peak

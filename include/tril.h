@@ -128,7 +128,15 @@ typedef struct {
                                      beside the step/instance prefix (18..30). Photons with
                                      equal codes keep their order (stable sort). The pair set
                                      does not depend on it. */
-    int32_t pad0;
+    int32_t kinetic_window;       /* tril_run batches: steps served by one copy of the target
+                                     hierarchy, >= 0 (0 = automatic: 16; 1 = a copy per step).
+                                     A copy holds the boxes of its window's middle step; a
+                                     query tests its internal nodes with its own box widened
+                                     by the target instance's motion (the bounds of u dt)
+                                     over the steps in between, and every leaf that passes
+                                     at the leaf's own box of the query's step. Plain regime
+                                     only; the candidates, and so the results, do not depend
+                                     on it. */
 } tril_params;
 
 /* Caller-owned pair buffer. tril_collide appends raw hits (i, j, step) at
@@ -165,6 +173,8 @@ typedef struct {
                                  one per step batch of tril_run) */
     int64_t n_fp64_rechecks;  /* candidates the FP32 stage of the narrow phase could not decide
                                  and passed to FP64 (0 with TRIL_FP64_NARROW) */
+    int64_t n_leaf_checks;    /* hierarchy copies shared by several steps: leaves whose own box
+                                 at the query's step was formed and tested, summed over steps */
 } tril_stats_t;
 
 /* Create a context on the caller's HIP stream (hipStream_t, NULL = default stream).
@@ -288,6 +298,9 @@ typedef struct {
     int32_t traverse_queue;       /* 0: one traversal workgroup per block of queries (a flat
                                      grid); 1: a persistent grid whose waves take chunks of
                                      1024 queries from device-wide work queues */
+    int32_t kinetic_window;       /* steps per copy of the target hierarchy, as in
+                                     tril_params (0 = automatic, 1 = per step) */
+    int32_t pad0;
     double ms_per_step;           /* tril_autotune: measured time per step of the best
                                      configuration (output; ignored by tril_set_tune) */
 } tril_tune;
@@ -296,6 +309,7 @@ typedef struct {
  * launch configurations and keep the fastest in the context (and in *best). Coordinate
  * descent: steps per launch (1 .. 128, within 2^27 photon-steps per launch, or within the
  * default batch budget where that is larger), then the
+ * steps per hierarchy copy (1, 4, 8, 16, 32), then the
  * traversal workgroup size (64 .. 512), then the Morton bits (automatic or 30), then the
  * persistent work-queue traversal against the flat grid. Every
  * configuration runs twice (the first run captures its graphs and sizes the scratch);

@@ -63,12 +63,23 @@ int tril_dbg_gemm_bf16(const uint16_t *A, int64_t sam, int64_t sak, const uint16
 /* Copy the last built hierarchy to host memory (synchronises the context stream).
  * nodes: host, cap_nodes x 16 words, one internal node each: its left child's box and
  * link (lox loy loz link hix hiy hiz pad), then its right child's, as float/int32; a
- * link >= 0 is an internal node, a link <= -2 the leaf holding target element
- * -2 - link. *n_nodes receives m (n-1) for the m steps of the last build (0 below two
- * rows). roots: host, m n_inst root links (same encoding; -1: empty instance), or
- * NULL. TRIL_E_OVERFLOW if cap_nodes < *n_nodes. */
+ * link >= 0 is an internal node, a link <= -2 a leaf: with one copy per step the leaf
+ * holding target element -2 - link, with window copies (tril_params.kinetic_window)
+ * the leaf at sorted position -2 - link (tril_dbg_target_records). *n_nodes receives
+ * c (n-1) for the c copies of the last build (c = m, the build's steps, or ceil(m / W)
+ * for windows of W steps; 0 below two rows). roots: host, c n_inst root links (same
+ * encoding; -1: empty instance), or NULL. TRIL_E_OVERFLOW if cap_nodes < *n_nodes. */
 int tril_dbg_tree(tril_ctx *ctx, void *nodes, int64_t cap_nodes, int64_t *n_nodes,
                   int32_t *roots);
+
+/* Window copies of the last build: *win receives its steps per copy (1: a copy per
+ * step, and *n = 0); otherwise *n receives the target rows n and recs (host, n x 12
+ * words) the record of each sorted position: lox loy loz row, dx dy dz e, wx wy wz 0 as
+ * float/int32, the leaf's box at step offset 0 (low corner, widths) and its motion per
+ * step, from which every step's leaf box is formed as the refit forms it (copy k holds
+ * the boxes of step offset k W + (min(W, m - k W) - 1) / 2). Synchronises the stream;
+ * TRIL_E_OVERFLOW if cap < *n. */
+int tril_dbg_target_records(tril_ctx *ctx, void *recs, int64_t cap, int64_t *n, int32_t *win);
 
 /* Copy the swept boxes of the last target (which = 0: all m n of the last build's m
  * steps, formed again here exactly as the build's refit formed them) or query

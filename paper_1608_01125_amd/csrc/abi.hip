@@ -100,6 +100,7 @@ struct tril_ctx {
     int block = 64;
     int trav_queue = 0;             // traversal as a persistent work queue (tril_tune)
     int32_t step_batch = 0;         // steps per launch in tril_run (0 = automatic)
+    int32_t kwin = 0;               // steps per tree copy in batches (0 = automatic, 1 = per step)
     int morton_param = 0;           // Morton bits requested (0 = automatic)
     CloudBox cloud{0, {0.0, 0.0, 0.0}};  // box kind of the builds (statistical regime: clouds)
     double *st_slots = nullptr;     // statistical regime: per-wave yield sums (kCounterSlots)
@@ -156,6 +157,9 @@ struct tril_ctx {
     int32_t *inst_root = nullptr;
     int32_t *inst_base = nullptr;          // instance roots of the shared tree shape
     PBox *root_box = nullptr;              // boxes of combined instances of one row
+    TRec *t_rec = nullptr;                 // window copies: per sorted target position
+    WinBound *t_wb = nullptr;              // window copies: per target instance, bounds of u dt
+    int32_t win_eff = 1;                   // steps per tree copy of the last build
     int32_t *refit_slots = nullptr;        // refit hand-offs to the crossing-level kernel
     int32_t *xlev = nullptr;               // crossing levels of the shape (batches of many steps)
     int64_t refit_slot_cap = 0;
@@ -255,7 +259,7 @@ void free_target(tril_ctx *c) {
 void free_target_rows(tril_ctx *c) {
     dev_free(c->t_spart); dev_free(c->t_k32a); dev_free(c->t_k32b);
     dev_free(c->t_k64a); dev_free(c->t_k64b); dev_free(c->t_va); dev_free(c->t_vb);
-    dev_free(c->prec); dev_free(c->xlev);
+    dev_free(c->prec); dev_free(c->xlev); dev_free(c->t_rec);
     c->t_row_cap = 0;
 }
 
@@ -289,6 +293,7 @@ int ensure_target(tril_ctx *c, int64_t nv, int64_t n, int64_t n_comb, int32_t n_
         CHK(dev_alloc(&c->t_va, m)); CHK(dev_alloc(&c->t_vb, m));
         CHK(dev_alloc(&c->prec, 2 * m));
         CHK(dev_alloc(&c->xlev, (size_t)xlevel_ints(m)));
+        CHK(dev_alloc(&c->t_rec, m));
         c->t_row_cap = m;
     }
     if (n_comb > c->t_comb_cap) {
@@ -303,10 +308,11 @@ int ensure_target(tril_ctx *c, int64_t nv, int64_t n, int64_t n_comb, int32_t n_
     }
     if (n_inst > c->t_off_cap) {
         ++c->alloc_gen;
-        dev_free(c->d_t_off); dev_free(c->t_stats);
+        dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->t_wb);
         c->t_off_cap = 0;
         CHK(dev_alloc(&c->d_t_off, (size_t)n_inst + 1));
         CHK(dev_alloc(&c->t_stats, (size_t)n_inst));
+        CHK(dev_alloc(&c->t_wb, (size_t)n_inst));
         c->t_off_cap = n_inst;
         c->h_t_off.clear();
     }
@@ -488,13 +494,26 @@ int timing_pair(tril_ctx *c, hipStream_t st, std::vector<std::array<int, 2>> &ds
 // (the middle one: no step of the batch is more than m/2 steps from it).
 inline int32_t key_step(int32_t m) { return m > 0 ? (m - 1) / 2 : 0; }
 
+// Steps per tree copy for a batch of m steps: window copies only in the plain regime
+// (straight-line leaf boxes, query records), at most m.
+constexpr int32_t kDefaultWindow = 16;
+int32_t build_window(const tril_ctx *c, int32_t m) {
+    if (m < 2 || c->cloud.on != 0 || c->kwin == 1) return 1;
+    const int32_t w = c->kwin > 1 ? c->kwin : kDefaultWindow;
+    return w < m ? w : m;
+}
+
 // Kernels of one build on stream st (target view, with its step count m, in c->tgt;
 // the target statistics c->t_stats are current): boxes of every step, one sort of the
 // rows by their Morton codes at the batch's key step, the tree shape emitted from that
-// order, and its m per-step copies filled with each step's boxes.
+// order, and its copies (one per step, or one per window of steps) filled with the boxes
+// of their steps.
 int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
     const BeamDev &t = c->tgt;
     const int64_t n = t.n;
+    const int32_t win = build_window(c, t.m);
+    const int32_t copies = window_copies(t.m, win);
+    c->win_eff = win;
     const KeyLayout kl = key_layout(t.n_inst, c->morton_bits);
     if (timed) CHK(timing_pair(c, st, c->ev_build, true));
     launch_prologue(c->d_cnt, 0, t.m, st);
@@ -517,18 +536,19 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
         launch_karras_u64(keys, n, kl.prefix_shift, c->prec, roots, st);
     }
     c->t_rows = rows;
-    c->n_int = n > 0 ? (int64_t)t.m * (n - 1) : -1;
+    c->n_int = n > 0 ? (int64_t)copies * (n - 1) : -1;
     c->tgt_cloud = c->cloud;
+    if (win > 1) launch_win_bounds(c->t_stats, t.n_inst, c->dt, c->t_wb, st);
     launch_inst_roots(t, c->cloud, c->dt, c->inst_base, rows, c->inst_root, c->root_box, c->d_cnt,
-                      st);
+                      st, win, c->t_rec);
     int32_t *xbase = nullptr;
     bool xalt = false;
-    if (refit_by_levels(n, t.m)) {
+    if (refit_by_levels(n, copies)) {
         xbase = c->xlev;
         xalt = enqueue_xlevels(c->prec, n, xbase, c->ss, &c->d_cnt->err, st);
     }
     launch_refit(t, c->cloud, c->dt, rows, c->prec, c->nflags, c->nodes, c->refit_slots,
-                 c->refit_slot_cap, xbase, xalt, c->d_cnt, &c->d_cnt->err, st);
+                 c->refit_slot_cap, xbase, xalt, c->d_cnt, &c->d_cnt->err, st, win, c->t_rec);
     if (timed) CHK(timing_pair(c, st, c->ev_build, false));
     HIPCHK(hipGetLastError());
     return TRIL_OK;
@@ -622,12 +642,23 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
     // a batch of steps in the plain regime: one record per query row instead of a box per
     // query and step
     const bool records = q.m >= 2 && c->cloud.on == 0;
+    if (c->win_eff > 1 && (!records || q.m != c->tgt.m)) return TRIL_E_INTERNAL;
     CHK(enqueue_query_prep(c, q, st, sort_queries, records));
+    WinArgs wa{};
+    if (c->win_eff > 1) {
+        wa.trec = c->t_rec;
+        wa.vb = c->t_wb;
+        wa.win = c->win_eff;
+        wa.m = q.m;
+        wa.n = c->tgt.n;
+        wa.reach = (float)((double)(q.m + c->win_eff + 8) * c->dt + 1e-6);
+    }
     if (timed) CHK(timing_pair(c, st, c->ev_prep, false));
     if (timed) CHK(timing_pair(c, st, c->ev_trav, true));
     launch_traverse(c->nodes, c->n_int, c->root_box, c->q_box, c->q_order, c->q_order_len, nv, q.n,
                     c->inst_root, c->cand_i, c->cand_j, c->cand_cap, c->d_cnt, c->block, st,
-                    records ? c->q_rec : nullptr, q.n_inst, c->trav_queue != 0);
+                    records ? c->q_rec : nullptr, q.n_inst, c->trav_queue != 0,
+                    c->win_eff > 1 ? &wa : nullptr);
     if (timed) CHK(timing_pair(c, st, c->ev_trav, false));
     if (timed) CHK(timing_pair(c, st, c->ev_narrow, true));
     launch_narrow(q, c->tgt, c->dt, c->sigma_up, c->cand_i, c->cand_j, c->cand_cap, out, c->d_cnt,
@@ -850,7 +881,8 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
     if (!out || !p) return TRIL_E_INVAL;
     *out = nullptr;
     if (!std::isfinite(p->dt) || !(p->dt > 0.0)) return TRIL_E_INVAL;
-    if (p->n_bins < 0 || p->cand_cap < 0 || p->step_batch < 0) return TRIL_E_INVAL;
+    if (p->n_bins < 0 || p->cand_cap < 0 || p->step_batch < 0 || p->kinetic_window < 0)
+        return TRIL_E_INVAL;
     if (p->morton_bits != 0 && (p->morton_bits < 3 || p->morton_bits > 30)) return TRIL_E_INVAL;
     if (p->flags &
         ~(TRIL_TIMING | TRIL_SORT_QUERIES_ONCE | TRIL_FP64_NARROW | TRIL_ANNIHILATE | TRIL_GRID))
@@ -875,6 +907,7 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
     c->cand_cap_param = p->cand_cap;
     c->block = blk;
     c->step_batch = p->step_batch;
+    c->kwin = p->kinetic_window;
     c->morton_param = p->morton_bits;
     c->sigma_up = host_sigma_max() * (1.0 + 1e-6);
     int r = TRIL_OK;
@@ -1094,7 +1127,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
                 // every launch parameter read while the batch is captured
                 (const void *)(intptr_t)c->block, (const void *)(uintptr_t)c->flags,
                 (const void *)(intptr_t)c->trav_queue,
-                (const void *)(intptr_t)c->cand_cap};
+                (const void *)(intptr_t)c->cand_cap, (const void *)(intptr_t)c->kwin};
             int slot = (c->gexec[0] && key == c->gkey[0]) ? 0
                        : (c->gexec[1] && key == c->gkey[1]) ? 1 : -1;
             if (slot < 0) {
@@ -1157,12 +1190,14 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     HIPCHK(hipMemcpy(c->h_cnt, c->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost));
     const DevCounters &h = *c->h_cnt;
     out->n_candidates = (int64_t)h.cand_total + (int64_t)h.st_pairs;
-    int64_t visits = 0, queries = 0;
+    int64_t visits = 0, queries = 0, checks = 0;
     for (int k = 0; k < kCounterSlots; ++k) {
         visits += (int64_t)h.visits[k];
         queries += (int64_t)h.queries[k];
+        checks += (int64_t)h.leaf_checks[k];
     }
     out->n_node_visits = visits;
+    out->n_leaf_checks = checks;
     out->n_queries = queries;
     out->n_sigma_evals = (int64_t)h.sigma_evals;
     out->n_fp64_rechecks = (int64_t)h.fp64_rechecks;
@@ -2322,8 +2357,10 @@ int tril_set_tune(tril_ctx *c, const tril_tune *tu) {
     if (tu->step_batch < 0) return TRIL_E_INVAL;
     if (tu->morton_bits != 0 && (tu->morton_bits < 3 || tu->morton_bits > 30)) return TRIL_E_INVAL;
     if (tu->traverse_queue != 0 && tu->traverse_queue != 1) return TRIL_E_INVAL;
+    if (tu->kinetic_window < 0) return TRIL_E_INVAL;
     c->block = blk;
     c->trav_queue = tu->traverse_queue;
+    c->kwin = tu->kinetic_window;
     c->step_batch = tu->step_batch;
     c->morton_param = tu->morton_bits;
     return TRIL_OK;
@@ -2360,12 +2397,13 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
     }
     c->flags &= ~TRIL_TIMING;  // time graph replays, as a run without per-phase events
     const int64_t rows = std::max<int64_t>(std::max(t->n, q->n), 1);
-    int cur_queue = 0;
+    int cur_queue = 0, cur_win = 0;
     auto probe = [&](int blk, int sb, int mb, double &ms) -> int {
         c->block = blk;
         c->step_batch = sb;
         c->morton_param = mb;
         c->trav_queue = cur_queue;
+        c->kwin = cur_win;
         for (int rep = 0; rep < 2; ++rep) {
             HIPCHK(hipMemsetAsync(pr.count, 0, sizeof(int64_t), c->st));
             HIPCHK(hipEventRecord(e0, c->st));
@@ -2378,7 +2416,7 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
         ms = (double)f / n_probe;
         return TRIL_OK;
     };
-    tril_tune cur{64, 0, 0, 0, 0.0};
+    tril_tune cur{64, 0, 0, 0, 0, 0, 0.0};
     cur.step_batch = pick_batch(c, t, q, n_probe);
     cur_queue = 0;
     double best_ms = 0.0;
@@ -2396,6 +2434,17 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
             best_ms = ms;
             cur.step_batch = sb;
         }
+    }
+    for (int w : {1, 4, 8, 32}) {  // steps per tree copy (0: the default, 16)
+        if (rc != TRIL_OK || cur.step_batch == 1) break;
+        double ms = 0.0;
+        cur_win = w;
+        if ((rc = probe(cur.block_traverse, cur.step_batch, cur.morton_bits, ms)) != TRIL_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            cur.kinetic_window = w;
+        }
+        cur_win = cur.kinetic_window;
     }
     for (int blk : {64, 128, 512}) {
         if (rc != TRIL_OK) break;
@@ -2430,6 +2479,7 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
     c->step_batch = cur.step_batch;
     c->morton_param = cur.morton_bits;
     c->trav_queue = cur.traverse_queue;
+    c->kwin = cur.kinetic_window;
     *best = cur;
     return tril_reset_counters(c);
 }
@@ -2487,7 +2537,7 @@ void tril_destroy(tril_ctx *c) {
         dev_free(c->au_pi[p]);
     }
     dev_free(c->au_cell); dev_free(c->au_ctl); dev_free(c->au_count);
-    dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->inst_root); dev_free(c->inst_base); dev_free(c->root_box);
+    dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->t_wb); dev_free(c->inst_root); dev_free(c->inst_base); dev_free(c->root_box);
     dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
     dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
     dev_free(c->q_keep); dev_free(c->q_rec); dev_free(c->d_q_off); dev_free(c->q_stats); dev_free(c->cand_i);
@@ -2631,15 +2681,31 @@ int tril_dbg_tree(tril_ctx *c, void *nodes, int64_t cap_nodes, int64_t *n_nodes,
     if (!c || !n_nodes) return TRIL_E_INVAL;
     if (!c->built) return TRIL_E_STATE;
     HIPCHK(hipStreamSynchronize(c->st));
-    const int64_t nn = c->tgt.n > 1 ? (int64_t)c->tgt.m * (c->tgt.n - 1) : 0;
+    const int32_t copies = window_copies(c->tgt.m, c->win_eff);
+    const int64_t nn = c->tgt.n > 1 ? (int64_t)copies * (c->tgt.n - 1) : 0;
     *n_nodes = nn;
     if (nn > cap_nodes) return TRIL_E_OVERFLOW;
     if (nn > 0) {
         if (!nodes) return TRIL_E_INVAL;
         HIPCHK(hipMemcpy(nodes, c->nodes, nn * sizeof(Node), hipMemcpyDeviceToHost));
     }
-    const size_t n_comb = (size_t)c->tgt.m * c->tgt.n_inst;
+    const size_t n_comb = (size_t)copies * c->tgt.n_inst;
     if (roots) HIPCHK(hipMemcpy(roots, c->inst_root, n_comb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return TRIL_OK;
+}
+
+int tril_dbg_target_records(tril_ctx *c, void *recs, int64_t cap, int64_t *n, int32_t *win) {
+    if (!c || !n || !win) return TRIL_E_INVAL;
+    if (!c->built) return TRIL_E_STATE;
+    HIPCHK(hipStreamSynchronize(c->st));
+    *win = c->win_eff;
+    const int64_t nn = c->win_eff > 1 ? c->tgt.n : 0;
+    *n = nn;
+    if (nn > cap) return TRIL_E_OVERFLOW;
+    if (nn > 0) {
+        if (!recs) return TRIL_E_INVAL;
+        HIPCHK(hipMemcpy(recs, c->t_rec, nn * sizeof(TRec), hipMemcpyDeviceToHost));
+    }
     return TRIL_OK;
 }
 

@@ -536,16 +536,66 @@ __device__ __forceinline__ int32_t step_node(int64_t x, int32_t s, int64_t n) {
     return (int32_t)((int64_t)s * (n - 1) + x);
 }
 
-// Root link of every combined instance (s, mi). base_root: roots of the base instances
-// written by the emission (read only when there are several); an instance with one row
-// is a leaf, whose box at step s (kept in no node) goes to root_box[cc]; the only
-// instance of a tree is the tree's root (internal node 0).
+// Leaf box of a photon at step offset s of a batch: in the plain regime (kMoved) formed in
+// FP32 from its box at offset 0 (l0, widths w0) moved by s d0 (moved_box), else in FP64
+// (photon_box: the statistical clouds and swarms). The debug dump of the target boxes
+// forms them the same way.
+struct LeafMotion {
+    float l0[3], w0[3], d0[3];
+};
+
+__device__ __forceinline__ LeafMotion leaf_motion(const RowPhoton &ph, double t0, double dt,
+                                                  const CloudBox &cloud) {
+    LeafMotion m;
+    float lo[3], hi[3], cen[3];
+    photon_box(ph, t0, dt, cloud, 0.0, lo, hi, cen);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        m.l0[a] = lo[a];
+        m.w0[a] = ph.ok ? f32_up((double)hi[a] - (double)lo[a]) : 0.0f;
+    }
+    m.d0[0] = (float)(dt * ph.ux); m.d0[1] = (float)(dt * ph.uy); m.d0[2] = (float)(dt * ph.uz);
+    return m;
+}
+
+__device__ __forceinline__ void leaf_box_moved(const LeafMotion &m, bool ok, int32_t s,
+                                               float lo[3], float hi[3]) {
+    if (!ok) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = INFINITY;
+            hi[a] = -INFINITY;
+        }
+        return;
+    }
+    moved_box(m.l0[0], m.l0[1], m.l0[2], m.d0[0], m.d0[1], m.d0[2], m.w0[0], m.w0[1], m.w0[2],
+              (float)s, lo, hi);
+}
+
+// Target record of a leaf for window copies: its offset-0 box and motion as leaf_motion
+// forms them, its row and its energy rounded up (0 if the photon is unusable).
+__device__ __forceinline__ void write_trec(TRec *dst, const RowPhoton &ph, double E, uint32_t row,
+                                           double t0, double dt, const CloudBox &cloud) {
+    const LeafMotion lm = leaf_motion(ph, t0, dt, cloud);
+    float4 *o = reinterpret_cast<float4 *>(dst);
+    o[0] = make_float4(lm.l0[0], lm.l0[1], lm.l0[2], __int_as_float((int32_t)row));
+    o[1] = make_float4(lm.d0[0], lm.d0[1], lm.d0[2], ph.ok ? f32_up(E) : 0.0f);
+    o[2] = make_float4(lm.w0[0], lm.w0[1], lm.w0[2], 0.0f);
+}
+
+// Root link of every combined instance (s, mi) of the n_copies copies of the shape. base_root:
+// roots of the base instances written by the emission (read only when there are several);
+// an instance with one row is a leaf: with per-step copies (win <= 1) its box at step s
+// (kept in no node) goes to root_box[cc]; with window copies the root is the leaf's sorted
+// position, whose record (written here for copy 0) gives the traversal its box at every
+// step. The only instance of a tree is the tree's root (internal node 0).
 __global__ void k_inst_roots(BeamDev b, CloudBox cloud, double dt,
                              const int32_t *__restrict__ base_root,
                              const uint32_t *__restrict__ rows, int32_t *inst_root,
-                             PBox *__restrict__ root_box, const DevCounters *__restrict__ c) {
+                             PBox *__restrict__ root_box, const DevCounters *__restrict__ c,
+                             int32_t win, int32_t n_copies, TRec *__restrict__ trec) {
     const int32_t cc = blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t n_comb = b.m * b.n_inst;
+    const int32_t n_comb = n_copies * b.n_inst;
     if (cc >= n_comb) return;
     const int32_t s = cc / b.n_inst;
     const int32_t mi = cc - s * b.n_inst;
@@ -556,9 +606,14 @@ __global__ void k_inst_roots(BeamDev b, CloudBox cloud, double dt,
         inst_root[cc] = -1;
     } else if (o1 - o0 == 1) {
         const uint32_t row = rows[o0];
-        inst_root[cc] = leaf_link((int64_t)s * n + row);
         double E, w;
         const RowPhoton r = load_photon(b, row, E, w);
+        if (win > 1) {
+            inst_root[cc] = leaf_link(o0);
+            if (s == 0) write_trec(trec + o0, r, E, row, (double)c->step * dt, dt, cloud);
+            return;
+        }
+        inst_root[cc] = leaf_link((int64_t)s * n + row);
         float lo[3], hi[3], cen[3];
         photon_box(r, (double)(c->step + (unsigned)s) * dt, dt, cloud, 0.0, lo, hi, cen);
         PBox o;
@@ -572,13 +627,32 @@ __global__ void k_inst_roots(BeamDev b, CloudBox cloud, double dt,
     }
 }
 
+// Per target instance: bounds of u dt as the refit rounds it ((float)(dt u), FP64 product
+// then nearest FP32; both roundings are monotone, so the rounded bounds bound every
+// photon's), widened by one FP32 step outward.
+__global__ void k_win_bounds(const InstStats *__restrict__ stats, int32_t n_inst, double dt,
+                             WinBound *__restrict__ vb) {
+    const int32_t mi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mi >= n_inst) return;
+    float lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = nextafterf((float)(dt * ord2d(stats[mi].mn[3 + a])), -INFINITY);
+        hi[a] = nextafterf((float)(dt * ord2d(stats[mi].mx[3 + a])), INFINITY);
+    }
+    WinBound o;
+    o.lo = make_float4(lo[0], lo[1], lo[2], 0.0f);
+    o.hi = make_float4(hi[0], hi[1], hi[2], 0.0f);
+    vb[mi] = o;
+}
+
 // ------------------------------------------------------------------- refit
 
 // Child halves that another thread of the same launch may read are stored with
 // device-scope relaxed atomics (write-through, coherent across the chip's L2 slices),
 // so a box written on one XCD is seen by the sibling's thread on another without a
-// full L2 write-back fence. Ordering within a thread comes from workgroup-scope fences
-// (wait for the thread's own memory operations to complete).
+// full L2 write-back fence. The climbing thread waits for these stores to complete
+// before it increments the parent's arrival flag (climb_crossing).
 __device__ __forceinline__ void store_half_coherent(Half *h, const Half &v) {
     unsigned long long *p = reinterpret_cast<unsigned long long *>(h);
     const unsigned long long *s = reinterpret_cast<const unsigned long long *>(&v);
@@ -626,6 +700,10 @@ constexpr int64_t kRefitWorkgroups = 4096;  // four rounds of the chip's residen
 
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
+// s_waitcnt operand that waits for every outstanding vector memory operation of the wave
+// (vmcnt 0; expcnt and lgkmcnt at their maxima, i.e. not waited for).
+constexpr int kWaitVmem = 0x0F70;
+
 // Climb from node cur (the shape's local id; r: its record; cn: its box and link as its
 // parent holds them) through parents whose ranges cross chunks, with global arrival
 // flags and device-coherent stores and loads of the child halves: the first of two
@@ -647,7 +725,13 @@ __device__ __forceinline__ void climb_crossing(int32_t cur, Half cn, i32x4 r, bo
         Node *pn = nodes + step_node(p, step, n);
         if (!stored) store_half_coherent(&pn->c[side], cn);
         stored = false;
+        // the half must be visible device-wide before the flag counts this arrival: wait
+        // until the device-scope stores have completed (a workgroup-scope release fence
+        // only keeps the compiler from moving them and emits no such wait, so the sibling
+        // could read the previous contents of this half). The full device-scope release
+        // would also write back the XCD's whole L2, which these stores do not need.
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_s_waitcnt(kWaitVmem);
         const int32_t old = __hip_atomic_fetch_add(flags + p, 1, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
         if (old == 0) return;
@@ -676,43 +760,10 @@ __device__ __forceinline__ void climb_crossing(int32_t cur, Half cn, i32x4 r, bo
 // its parent. The levels above are finished either level by level for all steps of the
 // batch (store_only: the halves are only stored), or by the crossing-level climb through
 // the (step, chunk) slots; with the slots full, or none given, the thread climbs on itself. Merges are exact
-// (min, max), so the boxes do not depend on the order of merging.
-// Leaf box of a photon at step offset s of a batch: in the plain regime (kMoved) formed in
-// FP32 from its box at offset 0 (l0, widths w0) moved by s d0 (moved_box), else in FP64
-// (photon_box: the statistical clouds and swarms). The debug dump of the target boxes
-// forms them the same way.
-struct LeafMotion {
-    float l0[3], w0[3], d0[3];
-};
-
-__device__ __forceinline__ LeafMotion leaf_motion(const RowPhoton &ph, double t0, double dt,
-                                                  const CloudBox &cloud) {
-    LeafMotion m;
-    float lo[3], hi[3], cen[3];
-    photon_box(ph, t0, dt, cloud, 0.0, lo, hi, cen);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        m.l0[a] = lo[a];
-        m.w0[a] = ph.ok ? f32_up((double)hi[a] - (double)lo[a]) : 0.0f;
-    }
-    m.d0[0] = (float)(dt * ph.ux); m.d0[1] = (float)(dt * ph.uy); m.d0[2] = (float)(dt * ph.uz);
-    return m;
-}
-
-__device__ __forceinline__ void leaf_box_moved(const LeafMotion &m, bool ok, int32_t s,
-                                               float lo[3], float hi[3]) {
-    if (!ok) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = INFINITY;
-            hi[a] = -INFINITY;
-        }
-        return;
-    }
-    moved_box(m.l0[0], m.l0[1], m.l0[2], m.d0[0], m.d0[1], m.d0[2], m.w0[0], m.w0[1], m.w0[2],
-              (float)s, lo, hi);
-}
-
+// (min, max), so the boxes do not depend on the order of merging. With window copies
+// (win > 1) the loop runs over the n_copies copies instead of the steps, each copy's leaf
+// boxes are those of its window's middle step, a leaf's link is its sorted position, and
+// the first group's workgroups write every leaf's record.
 template <bool kMoved>
 __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cloud, double dt,
                                                     const uint32_t *__restrict__ rows,
@@ -722,7 +773,8 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
                                                     int32_t *__restrict__ slots,
                                                     int32_t store_only,
                                                     const DevCounters *__restrict__ cnt,
-                                                    unsigned int *err) {
+                                                    unsigned int *err, int32_t win,
+                                                    int32_t n_copies, TRec *__restrict__ trec) {
     // halves of the chunk's nodes as their parents hold them, lo (xyz, link) and hi
     // (xyz, energy bound): [0, chunk) internal node c0 + k, [chunk, 2 chunk) leaf c0 + k
     // (before the first step the same memory holds the nodes' heights)
@@ -738,7 +790,7 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
     // workgroup: chunk `chunk` for the steps of group `group`
     const int64_t group = blockIdx.x / chunks, chunk = blockIdx.x - group * chunks;
     const int32_t s_begin = (int32_t)(group * group_steps);
-    const int32_t s_end = s_begin + group_steps < b.m ? s_begin + group_steps : b.m;
+    const int32_t s_end = s_begin + group_steps < n_copies ? s_begin + group_steps : n_copies;
     const int64_t c0 = chunk * kRefitChunk;
     const int64_t c1 = (c0 + kRefitChunk < n ? c0 + kRefitChunk : n) - 1;  // last leaf of the chunk
     const int64_t leaf0 = n - 1;
@@ -817,6 +869,12 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
         ph = load_photon(b, row, E, w);
         eup = ph.ok ? f32_up(E) : 0.0f;
         if (kMoved) lm = leaf_motion(ph, (double)step0 * dt, dt, cloud);
+        if (kMoved && win > 1 && group == 0) {
+            float4 *o = reinterpret_cast<float4 *>(trec + j);
+            o[0] = make_float4(lm.l0[0], lm.l0[1], lm.l0[2], __int_as_float((int32_t)row));
+            o[1] = make_float4(lm.d0[0], lm.d0[1], lm.d0[2], eup);
+            o[2] = make_float4(lm.w0[0], lm.w0[1], lm.w0[2], 0.0f);
+        }
     }
     const bool ok = ph.ok;
     __syncthreads();
@@ -827,13 +885,14 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
         if (in) {
             float lo[3], hi[3];
             if (kMoved) {
-                leaf_box_moved(lm, ok, step, lo, hi);
+                leaf_box_moved(lm, ok, window_ref_step(step, win, b.m), lo, hi);
             } else {
                 float cen[3];
                 photon_box(ph, (double)(step0 + (unsigned)step) * dt, dt, cloud, 0.0, lo, hi, cen);
             }
+            const int64_t elem = win > 1 ? j : (int64_t)step * n + row;
             s_lo[kRefitChunk + tid] =
-                make_float4(lo[0], lo[1], lo[2], __int_as_float(leaf_link((int64_t)step * n + row)));
+                make_float4(lo[0], lo[1], lo[2], __int_as_float(leaf_link(elem)));
             s_hi[kRefitChunk + tid] = make_float4(hi[0], hi[1], hi[2], eup);
         }
         __syncthreads();
@@ -1164,11 +1223,19 @@ void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shi
 
 void launch_inst_roots(const BeamDev &b, const CloudBox &cloud, double dt, const int32_t *base_root,
                        const uint32_t *sorted_rows, int32_t *inst_root, PBox *root_box,
-                       const DevCounters *c, hipStream_t st) {
-    const int32_t n_comb = b.m * b.n_inst;
+                       const DevCounters *c, hipStream_t st, int32_t win, TRec *trec) {
+    const int32_t n_copies = window_copies(b.m, win);
+    const int32_t n_comb = n_copies * b.n_inst;
     if (n_comb <= 0) return;
     hipLaunchKernelGGL(k_inst_roots, dim3(grid_for(n_comb, 64)), dim3(64), 0, st, b, cloud, dt,
-                       base_root, sorted_rows, inst_root, root_box, c);
+                       base_root, sorted_rows, inst_root, root_box, c, win, n_copies, trec);
+}
+
+void launch_win_bounds(const InstStats *stats, int32_t n_inst, double dt, WinBound *vb,
+                       hipStream_t st) {
+    if (n_inst <= 0) return;
+    hipLaunchKernelGGL(k_win_bounds, dim3(grid_for(n_inst, 64)), dim3(64), 0, st, stats, n_inst,
+                       dt, vb);
 }
 
 int64_t refit_slots_needed(int64_t n, int32_t m) {
@@ -1198,9 +1265,10 @@ bool enqueue_xlevels(const PRec *prec, int64_t n, int32_t *base, const SortScrat
 void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint32_t *sorted_rows,
                   const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots, int64_t slot_cap,
                   int32_t *xbase, bool xalt, const DevCounters *c, unsigned int *err,
-                  hipStream_t st) {
+                  hipStream_t st, int32_t win, TRec *trec) {
     const int64_t n = b.n;
-    const int32_t m = b.m;
+    if (cloud.on != 0) win = 1;  // window copies need straight-line leaf boxes
+    const int32_t m = window_copies(b.m, win);  // copies of the shape
     if (n <= 1 || m <= 0) return;  // no internal node: a single leaf is its step's root
     const int64_t chunks = (n + kRefitChunk - 1) / kRefitChunk;
     const int64_t n_slots = refit_slots_needed(n, m);
@@ -1216,11 +1284,11 @@ void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint
     if (cloud.on == 0)
         hipLaunchKernelGGL(k_refit<true>, dim3((unsigned)(chunks * groups)), dim3(kRefitChunk), 0,
                            st, b, cloud, dt, sorted_rows, chunks, group_steps, prec, flags, nodes,
-                           slots, levels ? 1 : 0, c, err);
+                           slots, levels ? 1 : 0, c, err, win, m, trec);
     else
         hipLaunchKernelGGL(k_refit<false>, dim3((unsigned)(chunks * groups)), dim3(kRefitChunk), 0,
                            st, b, cloud, dt, sorted_rows, chunks, group_steps, prec, flags, nodes,
-                           slots, levels ? 1 : 0, c, err);
+                           slots, levels ? 1 : 0, c, err, 1, m, trec);
     if (levels) {
         const XLev x = xlev_layout(xbase, n);
         hipLaunchKernelGGL(k_refit_levels, dim3((unsigned)m), dim3(kXThreads), 0, st,

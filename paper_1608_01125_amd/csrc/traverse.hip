@@ -23,6 +23,13 @@
 // Candidates are compacted per wave: a 64-lane ballot of the lanes that found
 // one, a single atomicAdd by the first such lane, and each lane's slot from the
 // count of set ballot bits below it.
+//
+// Window copies: when one copy of the target hierarchy serves W consecutive steps (its
+// boxes those of the window's middle step r), a query of step s tests internal nodes
+// with its box widened by the target instance's motion over s - r plus a rounding slack
+// (wslack), and a leaf that passes against the leaf's own box at step s, formed from the
+// leaf's record as the per-step refit would form it: the candidates are those of per-step
+// copies.
 #include "tril_internal.h"
 
 namespace tril {
@@ -75,9 +82,24 @@ __device__ __forceinline__ void record_box(const float4 a, const float4 d, const
     moved_box(a.x, a.y, a.z, d.x, d.y, d.z, w.x, w.y, w.z, s, qb, qb + 3);
 }
 
+// Window copies: the box of target leaf j (sorted position) at step offset s tested
+// against the query's box at s (closed test and the threshold prune); elem receives the
+// element s n + row.
+__device__ __forceinline__ bool leaf_exact(const WinArgs &wa, int64_t j, int32_t s,
+                                           const float qb[6], float qe, int64_t &elem) {
+    const float4 *tp = reinterpret_cast<const float4 *>(wa.trec + j);
+    const float4 a = tp[0], d = tp[1], w = tp[2];
+    float lo[3], hi[3];
+    moved_box(a.x, a.y, a.z, d.x, d.y, d.z, w.x, w.y, w.z, (float)s, lo, hi);
+    elem = (int64_t)s * wa.n + __float_as_int(a.w);
+    return (qb[0] <= hi[0]) & (qb[3] >= lo[0]) & (qb[1] <= hi[1]) & (qb[4] >= lo[1]) &
+           (qb[2] <= hi[2]) & (qb[5] >= lo[2]) & (qe * d.w >= kPruneProduct);
+}
+
 // The descent of virtual query q (q >= nq: an idle lane that still takes part in the
-// wave's ballots); adds its node loads to *visits and returns whether it had a root.
-template <bool kRec>
+// wave's ballots); adds its node loads to visits (and, over window copies, its leaf
+// record loads to checks) and returns whether it had a root.
+template <bool kRec, bool kWin>
 __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict__ nodes,
                                                int32_t n_int, const PBox *__restrict__ root_box,
                                                const PBox *__restrict__ qbox,
@@ -87,9 +109,11 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
                                                const int32_t *__restrict__ inst_root,
                                                int32_t *__restrict__ cand_i,
                                                int32_t *__restrict__ cand_j, int64_t cand_cap,
-                                               DevCounters *c, uint32_t &visits) {
-    int32_t node = -1, qi = 0, tag = -1;
+                                               DevCounters *c, uint32_t &visits,
+                                               const WinArgs &wa, uint32_t &checks) {
+    int32_t node = -1, qi = 0, tag = -1, qs = 0;
     float qb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float qw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // window copies: the widened box
     float qe = 0.f;
     if (q < nq) {
         if (qorder == nullptr) {
@@ -108,7 +132,24 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
             if (inst >= 0) {
                 record_box(a, d, w, (float)s, qb);
                 qe = d.w;
-                tag = (int32_t)(s * n_inst + inst);
+                if (kWin) {
+                    qs = (int32_t)s;
+                    const int32_t cp = qs / wa.win;
+                    const float delta = (float)(qs - window_ref_step(cp, wa.win, wa.m));
+                    const float4 *vp = reinterpret_cast<const float4 *>(wa.vb + inst);
+                    const float4 vlo = vp[0], vhi = vp[1];
+                    const float lo3[3] = {vlo.x, vlo.y, vlo.z}, hi3[3] = {vhi.x, vhi.y, vhi.z};
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const float e1 = delta * lo3[k], e2 = delta * hi3[k];
+                        const float sl = wslack(qb[k], qb[k + 3], wa.reach);
+                        qw[k] = (qb[k] - fmaxf(e1, e2)) - sl;
+                        qw[k + 3] = (qb[k + 3] - fminf(e1, e2)) + sl;
+                    }
+                    tag = cp * n_inst + inst;
+                } else {
+                    tag = (int32_t)(s * n_inst + inst);
+                }
             }
         } else {
             const float4 *bp = reinterpret_cast<const float4 *>(qbox + qi);
@@ -127,8 +168,13 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
         int64_t e = 0;
         if (node <= -2) {
             e = link_elem(node);
-            const float4 *lp = reinterpret_cast<const float4 *>(root_box + tag);
-            hit = box_overlap(qb, lp[0], lp[1]);
+            if (kWin) {
+                hit = leaf_exact(wa, e, qs, qb, qe, e);
+                ++checks;
+            } else {
+                const float4 *lp = reinterpret_cast<const float4 *>(root_box + tag);
+                hit = box_overlap(qb, lp[0], lp[1]);
+            }
             ++visits;
             node = -1;
         }
@@ -171,11 +217,23 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
         }
         ++visits;
         const int32_t lc = __float_as_int(l0.w), rc = __float_as_int(r0.w);
-        const bool ovl = box_overlap(qb, l0, l1) & (qe * l1.w >= kPruneProduct);
-        const bool ovr = box_overlap(qb, r0, r1) & (qe * r1.w >= kPruneProduct);
+        const bool ovl = box_overlap(kWin ? qw : qb, l0, l1) & (qe * l1.w >= kPruneProduct);
+        const bool ovr = box_overlap(kWin ? qw : qb, r0, r1) & (qe * r1.w >= kPruneProduct);
         const bool leafl = lc < 0, leafr = rc < 0;
-        emit_candidate(ovl & leafl, qi, link_elem(lc), cand_i, cand_j, cand_cap, c);
-        emit_candidate(ovr & leafr, qi, link_elem(rc), cand_i, cand_j, cand_cap, c);
+        bool el = ovl & leafl, er = ovr & leafr;
+        int64_t jl = link_elem(lc), jr = link_elem(rc);
+        if (kWin) {
+            if (el) {
+                el = leaf_exact(wa, jl, qs, qb, qe, jl);
+                ++checks;
+            }
+            if (er) {
+                er = leaf_exact(wa, jr, qs, qb, qe, jr);
+                ++checks;
+            }
+        }
+        emit_candidate(el, qi, jl, cand_i, cand_j, cand_cap, c);
+        emit_candidate(er, qi, jr, cand_i, cand_j, cand_cap, c);
         const bool gol = ovl & !leafl, gor = ovr & !leafr;
         if (gol) {
             if (gor) {  // push the right child
@@ -204,8 +262,25 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
     return active;
 }
 
+// Per-wave counter updates of a traversal workgroup's wave (lane 0 adds).
+__device__ __forceinline__ void add_counts(uint32_t visits, uint32_t checks,
+                                           unsigned long long n_active, DevCounters *c) {
+    unsigned long long v = visits, k = checks;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        v += __shfl_xor(v, off);
+        k += __shfl_xor(k, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        const int slot = blockIdx.x & (kCounterSlots - 1);
+        if (v) atomicAdd(&c->visits[slot], v);
+        if (k) atomicAdd(&c->leaf_checks[slot], k);
+        if (n_active) atomicAdd(&c->queries[slot], n_active);
+    }
+}
+
 // One virtual query per lane over a flat grid.
-template <int BLOCK, bool kRec>
+template <int BLOCK, bool kRec, bool kWin>
 __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nodes, int32_t n_int,
                                                     const PBox *__restrict__ root_box,
                                                     const PBox *__restrict__ qbox,
@@ -215,22 +290,13 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
                                                     const int32_t *__restrict__ inst_root,
                                                     int32_t *__restrict__ cand_i,
                                                     int32_t *__restrict__ cand_j, int64_t cand_cap,
-                                                    DevCounters *c) {
+                                                    DevCounters *c, WinArgs wa) {
     const int64_t q = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
-    uint32_t visits = 0;
-    const bool act = traverse_query<kRec>(q, nodes, n_int, root_box, qbox, qrec, n_inst, qorder,
-                                          order_len, nq, nq_base, inst_root, cand_i, cand_j,
-                                          cand_cap, c, visits);
-    const unsigned long long active_q = __ballot(act);
-    // per-wave counter updates
-    unsigned long long v = visits;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    if ((threadIdx.x & 63) == 0) {
-        const int slot = blockIdx.x & (kCounterSlots - 1);
-        if (v) atomicAdd(&c->visits[slot], v);
-        if (active_q) atomicAdd(&c->queries[slot], (unsigned long long)__popcll(active_q));
-    }
+    uint32_t visits = 0, checks = 0;
+    const bool act = traverse_query<kRec, kWin>(q, nodes, n_int, root_box, qbox, qrec, n_inst,
+                                                qorder, order_len, nq, nq_base, inst_root, cand_i,
+                                                cand_j, cand_cap, c, visits, wa, checks);
+    add_counts(visits, checks, (unsigned long long)__popcll(__ballot(act)), c);
 }
 
 
@@ -242,7 +308,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
 // over eight addresses, instead of one per wave of queries at one address.
 constexpr int kQueueChunk = 1024;
 
-template <int BLOCK, bool kRec>
+template <int BLOCK, bool kRec, bool kWin>
 __global__ void __launch_bounds__(BLOCK) k_traverse_queue(const Node *__restrict__ nodes,
                                                           int32_t n_int,
                                                           const PBox *__restrict__ root_box,
@@ -255,10 +321,11 @@ __global__ void __launch_bounds__(BLOCK) k_traverse_queue(const Node *__restrict
                                                           const int32_t *__restrict__ inst_root,
                                                           int32_t *__restrict__ cand_i,
                                                           int32_t *__restrict__ cand_j,
-                                                          int64_t cand_cap, DevCounters *c) {
+                                                          int64_t cand_cap, DevCounters *c,
+                                                          WinArgs wa) {
     const int lane = threadIdx.x & 63;
     const int x = blockIdx.x & (kTravCursors - 1);
-    uint32_t visits = 0;
+    uint32_t visits = 0, checks = 0;
     unsigned long long n_active = 0;
     for (;;) {
         unsigned long long k = 0;
@@ -268,20 +335,33 @@ __global__ void __launch_bounds__(BLOCK) k_traverse_queue(const Node *__restrict
         if (base >= nq) break;
         for (int sub = 0; sub < kQueueChunk; sub += 64) {
             if (base + sub >= nq) break;
-            const bool act = traverse_query<kRec>(base + sub + lane, nodes, n_int, root_box, qbox,
-                                                  qrec, n_inst, qorder, order_len, nq, nq_base,
-                                                  inst_root, cand_i, cand_j, cand_cap, c, visits);
+            const bool act = traverse_query<kRec, kWin>(
+                base + sub + lane, nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len,
+                nq, nq_base, inst_root, cand_i, cand_j, cand_cap, c, visits, wa, checks);
             n_active += (unsigned long long)__popcll(__ballot(act));
         }
     }
-    unsigned long long v = visits;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) {
-        const int slot = blockIdx.x & (kCounterSlots - 1);
-        if (v) atomicAdd(&c->visits[slot], v);
-        if (n_active) atomicAdd(&c->queries[slot], n_active);
+    add_counts(visits, checks, n_active, c);
+}
+
+template <int BLOCK, bool kRec, bool kWin>
+void launch_traverse_k(const Node *nodes, int32_t n_int, const PBox *root_box, const PBox *qbox,
+                       const QRec *qrec, int32_t n_inst, const uint32_t *qorder, int64_t order_len,
+                       int64_t nq, int64_t nq_base, const int32_t *inst_root, int32_t *cand_i,
+                       int32_t *cand_j, int64_t cand_cap, DevCounters *c, bool queue,
+                       const WinArgs &wa, hipStream_t st) {
+    const int64_t want = (nq + BLOCK - 1) / BLOCK;
+    if (queue) {
+        // as many workgroups as keep 32 waves on each of the 256 CUs
+        const unsigned grid = (unsigned)std::min<int64_t>(want, 8192 * 64 / BLOCK);
+        hipLaunchKernelGGL((k_traverse_queue<BLOCK, kRec, kWin>), dim3(grid), dim3(BLOCK), 0, st,
+                           nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
+                           nq_base, inst_root, cand_i, cand_j, cand_cap, c, wa);
+        return;
     }
+    hipLaunchKernelGGL((k_traverse<BLOCK, kRec, kWin>), dim3((unsigned)want), dim3(BLOCK), 0, st,
+                       nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq, nq_base,
+                       inst_root, cand_i, cand_j, cand_cap, c, wa);
 }
 
 template <int BLOCK>
@@ -289,30 +369,22 @@ void launch_traverse_b(const Node *nodes, int32_t n_int, const PBox *root_box, c
                        const QRec *qrec, int32_t n_inst, const uint32_t *qorder, int64_t order_len,
                        int64_t nq, int64_t nq_base, const int32_t *inst_root, int32_t *cand_i,
                        int32_t *cand_j, int64_t cand_cap, DevCounters *c, bool queue,
-                       hipStream_t st) {
-    const int64_t want = (nq + BLOCK - 1) / BLOCK;
-    if (queue) {
-        // as many workgroups as keep 32 waves on each of the 256 CUs
-        const unsigned grid = (unsigned)std::min<int64_t>(want, 8192 * 64 / BLOCK);
-        if (qrec != nullptr)
-            hipLaunchKernelGGL((k_traverse_queue<BLOCK, true>), dim3(grid), dim3(BLOCK), 0, st, nodes,
-                               n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq, nq_base,
-                               inst_root, cand_i, cand_j, cand_cap, c);
-        else
-            hipLaunchKernelGGL((k_traverse_queue<BLOCK, false>), dim3(grid), dim3(BLOCK), 0, st,
-                               nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
-                               nq_base, inst_root, cand_i, cand_j, cand_cap, c);
-        return;
+                       const WinArgs *win, hipStream_t st) {
+    WinArgs wa = {};
+    if (qrec != nullptr && win != nullptr) {
+        wa = *win;
+        launch_traverse_k<BLOCK, true, true>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder,
+                                             order_len, nq, nq_base, inst_root, cand_i, cand_j,
+                                             cand_cap, c, queue, wa, st);
+    } else if (qrec != nullptr) {
+        launch_traverse_k<BLOCK, true, false>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder,
+                                              order_len, nq, nq_base, inst_root, cand_i, cand_j,
+                                              cand_cap, c, queue, wa, st);
+    } else {
+        launch_traverse_k<BLOCK, false, false>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder,
+                                               order_len, nq, nq_base, inst_root, cand_i, cand_j,
+                                               cand_cap, c, queue, wa, st);
     }
-    const unsigned grid = (unsigned)want;
-    if (qrec != nullptr)
-        hipLaunchKernelGGL((k_traverse<BLOCK, true>), dim3(grid), dim3(BLOCK), 0, st, nodes, n_int,
-                           root_box, qbox, qrec, n_inst, qorder, order_len, nq, nq_base, inst_root,
-                           cand_i, cand_j, cand_cap, c);
-    else
-        hipLaunchKernelGGL((k_traverse<BLOCK, false>), dim3(grid), dim3(BLOCK), 0, st, nodes, n_int,
-                           root_box, qbox, qrec, n_inst, qorder, order_len, nq, nq_base, inst_root,
-                           cand_i, cand_j, cand_cap, c);
 }
 
 __global__ void k_record_boxes(const QRec *__restrict__ qrec, int64_t n,
@@ -344,25 +416,25 @@ void launch_traverse(const Node *nodes, int64_t n_int64, const PBox *root_box, c
                      const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
                      const int32_t *inst_root, int32_t *cand_i, int32_t *cand_j,
                      int64_t cand_cap, DevCounters *c, int block, hipStream_t st,
-                     const QRec *qrec, int32_t n_inst, bool queue) {
+                     const QRec *qrec, int32_t n_inst, bool queue, const WinArgs *win) {
     if (nq <= 0 || n_int64 < 0) return;
     const int32_t n_int = (int32_t)n_int64;
     switch (block) {
     case 64:
         launch_traverse_b<64>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
-                              nq_base, inst_root, cand_i, cand_j, cand_cap, c, queue, st);
+                              nq_base, inst_root, cand_i, cand_j, cand_cap, c, queue, win, st);
         break;
     case 128:
         launch_traverse_b<128>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
-                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, queue, st);
+                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, queue, win, st);
         break;
     case 512:
         launch_traverse_b<512>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
-                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, queue, st);
+                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, queue, win, st);
         break;
     default:
         launch_traverse_b<256>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
-                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, queue, st);
+                               nq_base, inst_root, cand_i, cand_j, cand_cap, c, queue, win, st);
         break;
     }
 }

@@ -115,6 +115,66 @@ __device__ __forceinline__ void moved_box(float lox, float loy, float loz, float
     hi[0] = hx + ex; hi[1] = hy + ey; hi[2] = hz + ez;
 }
 
+// Window copies of a batch's hierarchy. Photons move on straight lines, so the box of a
+// target leaf at step offset s lies in its box at another offset r moved by (s - r) u dt,
+// and u dt of every photon of an instance lies in that instance's per-axis bounds. A
+// batch of m steps may therefore keep one copy of the shape per window of W consecutive
+// steps, filled with the boxes of the window's middle step r, instead of one per step:
+// a query of step s tests internal nodes with its box widened by the instance's motion
+// over s - r (plus a rounding slack), which holds every box the subtree's leaves have at
+// step s, and tests a leaf that passes against the leaf's own box at step s, formed from
+// the leaf's record exactly as the per-step refit forms it. The candidates are those of
+// per-step copies; only the internal nodes a query visits change.
+__host__ __device__ inline int32_t window_copies(int32_t m, int32_t win) {
+    return win > 1 ? (m + win - 1) / win : m;
+}
+__host__ __device__ inline int32_t window_ref_step(int32_t cp, int32_t win, int32_t m) {
+    if (win <= 1) return cp;
+    const int32_t a = cp * win;
+    const int32_t len = a + win <= m ? win : m - a;
+    return a + (len - 1) / 2;
+}
+
+// Target record of one sorted leaf position for a batch (48 bytes): the leaf's box at
+// step offset 0 (low corner lo, widths w rounded up) and its motion per step d = u dt,
+// as the refit forms every step's leaf box from them (moved_box); row: the target row;
+// e: the photon's energy rounded up, 0 for a photon that can collide with nothing.
+struct alignas(16) TRec {
+    float lox, loy, loz;
+    int32_t row;
+    float dx, dy, dz;
+    float e;
+    float wx, wy, wz;
+    int32_t pad;
+};
+static_assert(sizeof(TRec) == 48, "target record layout");
+
+// Bounds of u dt over the photons of one target instance, per axis, as FP32 values the
+// refit's rounding of u dt cannot leave (lo: lowest, hi: highest; .w unused).
+struct WinBound {
+    float4 lo, hi;
+};
+
+// What a traversal over window copies needs besides the nodes.
+struct WinArgs {
+    const TRec *trec;      // per sorted target position
+    const WinBound *vb;    // per target instance
+    int32_t win;           // steps per copy (>= 2)
+    int32_t m;             // steps of the launch
+    int64_t n;             // target rows (element of row j at step s: s n + j)
+    float reach;           // (m + win + 8) dt + 1e-6: the slack's length term (wslack)
+};
+
+// Slack of the widened query box on one axis (ql, qh: the query's box at step s). If a
+// leaf's box at step s (moved_box, every FP32 operation within 2^-24 relative) meets
+// [ql, qh], its coordinates are at most M = max(|ql|, |qh|) plus its width (at most
+// 1.01 dt + 1e-11 (1 + M): target boxes carry no radius pad), so the rounding of its
+// boxes at s and at the copy's step r, and of the widened box itself, stays below
+// (M + (m + 2) dt) 2^-19: the slack below is at least twice that.
+__device__ __forceinline__ float wslack(float ql, float qh, float reach) {
+    return (fmaxf(fabsf(ql), fabsf(qh)) + reach) * 0x1p-18f;
+}
+
 // Philox4x64-10 (Salmon et al., SC'11), the counter-based generator of the pair kinematics
 // and of the statistical regime's audit samples.
 constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
@@ -163,6 +223,7 @@ struct DevCounters {
     unsigned int step;                 // current step index (device-resident for graphs)
     unsigned long long visits[kCounterSlots];
     unsigned long long queries[kCounterSlots];
+    unsigned long long leaf_checks[kCounterSlots];  // window copies: leaf records read
 };
 
 // ---------------------------------------------------------------- radix sort
@@ -275,9 +336,15 @@ void launch_karras_u64(const unsigned long long *keys, int64_t n, int prefix_shi
 // (whose box, kept in no node, goes to root_box[combined instance]), -1 for an empty
 // one (base_root: the emission's instance roots; sorted_rows: row of each sorted
 // position).
+// With window copies (win > 1: window_copies(b.m, win) copies), an instance of one row has
+// its sorted position as root link and its record written to trec.
 void launch_inst_roots(const BeamDev &b, const CloudBox &cloud, double dt, const int32_t *base_root,
                        const uint32_t *sorted_rows, int32_t *inst_root, PBox *root_box,
-                       const DevCounters *c, hipStream_t st);
+                       const DevCounters *c, hipStream_t st, int32_t win = 1,
+                       TRec *trec = nullptr);
+// Per-instance bounds of u dt of a target beam from its statistics (window copies).
+void launch_win_bounds(const InstStats *stats, int32_t n_inst, double dt, WinBound *vb,
+                       hipStream_t st);
 // Nodes of the b.m steps of view b sharing the shape over its b.n rows, each step's
 // leaf boxes computed from the photons (sorted_rows: row of each sorted position;
 // flags: b.m (b.n - 1) arrival flags, zero on entry and left zero (the second arrival at
@@ -294,11 +361,13 @@ int64_t xlevel_ints(int64_t n);
 bool enqueue_xlevels(const PRec *prec, int64_t n, int32_t *base, const SortScratch &ss,
                      unsigned int *err, hipStream_t st);
 // xbase: the level buffer set up by enqueue_xlevels for this shape (xalt: its result), or
-// nullptr for the crossing-level climb through the hand-off slots
+// nullptr for the crossing-level climb through the hand-off slots. win > 1 (plain regime
+// only): window copies, window_copies(b.m, win) of them, and every leaf's record in trec
+// (b.n entries, by sorted position).
 void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint32_t *sorted_rows,
                   const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots, int64_t slot_cap,
                   int32_t *xbase, bool xalt, const DevCounters *c, unsigned int *err,
-                  hipStream_t st);
+                  hipStream_t st, int32_t win = 1, TRec *trec = nullptr);
 
 // n_int: internal nodes of all steps' trees; root_box: box of each combined instance
 // whose root is a leaf; nq: virtual query count (steps x rows).
@@ -338,12 +407,14 @@ void launch_record_boxes(const QRec *qrec, int64_t n, const int32_t *perm, int32
 void launch_math_sweep(int which, int64_t n, const double *a, const double *b, double *out,
                        hipStream_t st);
 // Queries from per-step boxes (qbox) or, when qrec is given, from per-row records of the
-// batch (element s nq_base + row; n_inst: instances of the query view).
+// batch (element s nq_base + row; n_inst: instances of the query view); win (with qrec
+// only): the target hierarchy holds window copies.
 void launch_traverse(const Node *nodes, int64_t n_int, const PBox *root_box, const PBox *qbox,
                      const uint32_t *qorder, int64_t order_len, int64_t nq, int64_t nq_base,
                      const int32_t *inst_root, int32_t *cand_i, int32_t *cand_j,
                      int64_t cand_cap, DevCounters *c, int block, hipStream_t st,
-                     const QRec *qrec = nullptr, int32_t n_inst = 1, bool queue = false);
+                     const QRec *qrec = nullptr, int32_t n_inst = 1, bool queue = false,
+                     const WinArgs *win = nullptr);
 void launch_narrow(const BeamDev &q, const BeamDev &t, double dt, double sigma_up,
                    const int32_t *cand_i, const int32_t *cand_j, int64_t cand_cap,
                    const tril_pairs &out, DevCounters *c, bool fp32_stage, hipStream_t st);

@@ -47,7 +47,7 @@ class tril_params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("flags", ctypes.c_uint32), ("n_bins", ctypes.c_int32),
                 ("bin_edges", _dp), ("cand_cap", ctypes.c_int64),
                 ("block_traverse", ctypes.c_int32), ("step_batch", ctypes.c_int32),
-                ("morton_bits", ctypes.c_int32), ("pad0", ctypes.c_int32)]
+                ("morton_bits", ctypes.c_int32), ("kinetic_window", ctypes.c_int32)]
 
 
 class tril_pairs(ctypes.Structure):
@@ -64,12 +64,14 @@ class tril_stats_t(ctypes.Structure):
                 ("n_step_counts", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("ms_build", ctypes.c_double), ("ms_query_prep", ctypes.c_double),
                 ("ms_traverse", ctypes.c_double), ("ms_narrow", ctypes.c_double),
-                ("n_timed_launches", ctypes.c_int64), ("n_fp64_rechecks", ctypes.c_int64)]
+                ("n_timed_launches", ctypes.c_int64), ("n_fp64_rechecks", ctypes.c_int64),
+                ("n_leaf_checks", ctypes.c_int64)]
 
 
 class tril_tune(ctypes.Structure):
     _fields_ = [("block_traverse", ctypes.c_int32), ("step_batch", ctypes.c_int32),
                 ("morton_bits", ctypes.c_int32), ("traverse_queue", ctypes.c_int32),
+                ("kinetic_window", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("ms_per_step", ctypes.c_double)]
 
 
@@ -138,7 +140,7 @@ EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats"
            "tril_reset_counters", "tril_destroy", "tril_strerror", "tril_last_hip_error",
            "tril_dbg_sort_u32", "tril_dbg_sort_u64", "tril_dbg_morton", "tril_dbg_pair_eval",
            "tril_dbg_pair_eval32", "tril_dbg_math",
-           "tril_dbg_tree", "tril_dbg_boxes", "tril_dbg_target_rows", "tril_dbg_query_records", "tril_dbg_candidates")
+           "tril_dbg_tree", "tril_dbg_target_records", "tril_dbg_boxes", "tril_dbg_target_rows", "tril_dbg_query_records", "tril_dbg_candidates")
 
 _lib = None
 
@@ -217,6 +219,7 @@ def lib() -> ctypes.CDLL:
     L.tril_dbg_pair_eval32.argtypes = [i64, vp, vp, vp]
     L.tril_dbg_math.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp]
     L.tril_dbg_tree.argtypes = [vp, vp, i64, _i64p, _i32p]
+    L.tril_dbg_target_records.argtypes = [vp, vp, i64, _i64p, _i32p]
     L.tril_st_audit.argtypes = [vp, vp, ctypes.POINTER(tril_beam), vp, vp, gp,
                                 ctypes.POINTER(tril_beam), vp, vp, gp, i32, i32,
                                 ctypes.POINTER(tril_st_sur_params),
@@ -318,7 +321,7 @@ class Pairs:
 
 def tril_create(dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
                 cand_cap: int = 0, block_traverse: int = 0, step_batch: int = 0,
-                stream=None, morton_bits: int = 0) -> ctypes.c_void_p:
+                stream=None, morton_bits: int = 0, kinetic_window: int = 0) -> ctypes.c_void_p:
     L = lib()
     p = tril_params()
     p.dt = float(dt)
@@ -335,6 +338,7 @@ def tril_create(dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
     p.block_traverse = int(block_traverse)
     p.step_batch = int(step_batch)
     p.morton_bits = int(morton_bits)
+    p.kinetic_window = int(kinetic_window)
     h = ctypes.c_void_p()
     _check(L.tril_create(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(_stream(stream))),
            "tril_create")
@@ -407,7 +411,7 @@ def tril_pair_kinematics_noalloc(query: Beam, target: Beam, pairs: Pairs, n: int
         _stream(stream))
 
 
-TUNE_KEYS = ("block_traverse", "step_batch", "morton_bits", "traverse_queue")
+TUNE_KEYS = ("block_traverse", "step_batch", "morton_bits", "traverse_queue", "kinetic_window")
 
 
 def tril_autotune(ctx, target: Beam, query: Beam, k0: int, n_probe: int) -> dict:
@@ -416,7 +420,7 @@ def tril_autotune(ctx, target: Beam, query: Beam, k0: int, n_probe: int) -> dict
                                int(n_probe), ctypes.byref(t)), "tril_autotune")
     return {"block_traverse": t.block_traverse, "step_batch": t.step_batch,
             "morton_bits": t.morton_bits, "traverse_queue": t.traverse_queue,
-            "ms_per_step": t.ms_per_step}
+            "kinetic_window": t.kinetic_window, "ms_per_step": t.ms_per_step}
 
 
 def tril_set_tune(ctx, tune: dict) -> None:
@@ -766,7 +770,8 @@ def tril_dbg_math(which: int, a, b, out, stream=None) -> None:
 
 def tril_dbg_tree(ctx, n_target: int, n_inst: int = 1, m: int = 1):
     """Internal nodes of the last build: lo/hi (k, 2, 3) child boxes, link (k, 2) child
-    links (>= 0 internal, <= -2 leaf of element -2 - link), roots (m n_inst)."""
+    links (>= 0 internal, <= -2 leaf: element -2 - link, or sorted position with window
+    copies), roots (copies x n_inst), copies (per step: m)."""
     ctx = _h(ctx)
     cap = max(m * (n_target - 1), 1)
     nodes = np.zeros((cap, 16), dtype=np.float32)
@@ -774,10 +779,28 @@ def tril_dbg_tree(ctx, n_target: int, n_inst: int = 1, m: int = 1):
     roots = np.zeros(max(m * n_inst, 1), dtype=np.int32)
     _check(lib().tril_dbg_tree(ctx, nodes.ctypes.data, cap, ctypes.byref(nn),
                                roots.ctypes.data_as(_i32p)), "tril_dbg_tree")
+    copies = nn.value // (n_target - 1) if n_target > 1 else m
     nodes = nodes[: nn.value].reshape(-1, 2, 8)
     ints = nodes.view(np.int32)
     return {"lo": nodes[:, :, 0:3].copy(), "hi": nodes[:, :, 4:7].copy(),
-            "link": ints[:, :, 3].copy(), "roots": roots[: m * n_inst]}
+            "link": ints[:, :, 3].copy(), "roots": roots[: copies * n_inst], "copies": copies}
+
+
+def tril_dbg_target_records(ctx, n_target: int):
+    """Window copies of the last build: (win, records) with records a dict of lo (n, 3),
+    d (n, 3), w (n, 3), e (n,), row (n,) per sorted position; (1, None) for per-step copies."""
+    ctx = _h(ctx)
+    rec = np.zeros((max(n_target, 1), 12), dtype=np.float32)
+    nn = ctypes.c_int64(0)
+    win = ctypes.c_int32(0)
+    _check(lib().tril_dbg_target_records(ctx, rec.ctypes.data, max(n_target, 1), ctypes.byref(nn),
+                                         ctypes.byref(win)), "tril_dbg_target_records")
+    if win.value <= 1:
+        return win.value, None
+    rec = rec[: nn.value]
+    ints = rec.view(np.int32)
+    return win.value, {"lo": rec[:, 0:3].copy(), "d": rec[:, 4:7].copy(), "w": rec[:, 8:11].copy(),
+                       "e": rec[:, 7].copy(), "row": ints[:, 3].copy()}
 
 
 def tril_dbg_boxes(ctx, which: int, n: int):
@@ -834,10 +857,10 @@ class Context:
 
     def __init__(self, dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
                  cand_cap: int = 0, block_traverse: int = 0, step_batch: int = 0, stream=None,
-                 morton_bits: int = 0):
+                 morton_bits: int = 0, kinetic_window: int = 0):
         self.n_bins = 0 if edges is None else max(len(edges) - 1, 0)
         self.h = tril_create(dt, edges, flags, cand_cap, block_traverse, step_batch, stream,
-                             morton_bits)
+                             morton_bits, kinetic_window)
 
     def build(self, target: Beam, step: int) -> None:
         tril_build(self.h, target, step)

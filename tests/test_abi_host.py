@@ -31,6 +31,14 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(T.EXPORTS)
 
 
+def test_binding_declares_every_argument_list():
+    """ctypes passes an undeclared pointer argument as a C int, which truncates a 64-bit
+    address: every entry point the binding exports has its argument types declared."""
+    L = T.lib()
+    missing = [n for n in T.EXPORTS if getattr(L, n).argtypes is None]
+    assert not missing, missing
+
+
 def test_strerror_texts():
     for code in range(0, -9, -1):
         assert T.tril_strerror(code) not in ("", "unknown error")

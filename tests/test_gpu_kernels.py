@@ -231,7 +231,7 @@ def test_tree_invariants(torch):
 
 @pytest.mark.parametrize("m", [5, 40])
 def test_batched_tree_copies_and_instance_roots(torch, m):
-    """A batch of m steps over several instances: every step has its own copy of one
+    """A batch of m steps over several instances, one copy per step: every step has its own copy of one
     shape (same links up to the step's offsets); each (step, instance) root reaches
     exactly that instance's rows at that step; an instance of one row is a leaf root and
     an empty one has none; every box is the photon's box at its step or an exact union.
@@ -244,7 +244,7 @@ def test_batched_tree_copies_and_instance_roots(torch, m):
     Bc, off = beams.concat(parts)
     n, n_inst = len(Bc["E"]), len(off) - 1
     wl = beams.gauss_headon_1m(n=1000)
-    ctx = T.Context(wl.dt, step_batch=m)
+    ctx = T.Context(wl.dt, step_batch=m, kinetic_window=1)
     tb = T.Beam(Bc, off)
     pairs = T.Pairs(1 << 12)
     ctx.run(tb, tb, 180, m, pairs)
@@ -309,7 +309,7 @@ def test_tree_invariants_degenerate_shapes(torch, kind, n, m):
     assert np.all(seen == 1)
     assert np.array_equal(np.sort(leaves), np.arange(n))
     _check_boxes(tree, boxes)
-    ctx = T.Context(wl.dt, step_batch=m)
+    ctx = T.Context(wl.dt, step_batch=m, kinetic_window=1)
     tb = T.Beam(B)
     pairs = T.Pairs(1 << 12)
     ctx.run(tb, tb, 170, m, pairs)

@@ -1,0 +1,228 @@
+"""Window copies of the target hierarchy (GPU, through the C ABI): one copy of a batch's
+tree shape serves W consecutive steps. The copies must hold exactly the boxes of their
+window's middle step, every step's leaf box of the window must lie inside the copy's box
+widened as the traversal widens it (the proof obligation of the slack, checked on every
+leaf and step), and the candidates, hits and pairs must be those of one copy per step."""
+import numpy as np
+import pytest
+
+from paper_1608_01125_amd import beams
+from paper_1608_01125_amd import tril as T
+from tests.gpu_common import assert_parity, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+EDGES = beams.spectrum_edges()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a GPU"
+    return _t
+
+
+def _beams(n=3000, seed=2, boost=3e3, shift=None):
+    wl = beams.gauss_headon_1m(n=n, seed=seed)
+    wl = beams.gauss_headon_1m(n=n, seed=seed, w=wl.a.w * boost)
+    A, B = beams.draw_pair(wl)
+    if shift is not None:
+        for X in (A, B):
+            for a, f in enumerate(("x", "y", "z")):
+                X[f] = X[f] + shift[a]
+    return wl, A, B
+
+
+def _ref_step(cp, win, m):
+    a = cp * win
+    return a + (min(win, m - a) - 1) // 2
+
+
+def _run(wl, A, B, k0, n_steps, m, win, offA=None, offB=None):
+    ctx = T.Context(wl.dt, EDGES, step_batch=m, kinetic_window=win)
+    try:
+        pairs = T.Pairs(1 << 18)
+        ctx.run(T.Beam(B, offB), T.Beam(A, offA), k0, n_steps, pairs)
+        ci, cj, _ = T.tril_dbg_candidates(ctx)
+        st = ctx.stats(pairs, n_step_counts=k0 + n_steps)
+        i, j, k = pairs.numpy()
+    finally:
+        ctx.close()
+    cand = np.sort(ci.astype(np.int64) << 32 | cj.astype(np.int64))
+    return (i, j, k, st), cand
+
+
+@pytest.mark.parametrize("m,wins", [(40, (2, 5, 16, 40)), (7, (2, 3, 7))])
+def test_candidates_and_pairs_equal_per_step_copies(torch, m, wins):
+    """Same candidates (the last launch's, as a multiset, and the count over the run),
+    hits and pairs as one copy per step, for windows that divide the batch, leave a short
+    last window, and span the whole batch; the leaf records read are at least the
+    candidates."""
+    wl, A, B = _beams(n=3000, boost=3e3)
+    k0, n_steps = 150, 3 * m + m // 2 + 1  # full batches (graphs) and a shorter last one
+    base, cand1 = _run(wl, A, B, k0, n_steps, m, 1)
+    assert base[3]["n_leaf_checks"] == 0
+    assert base[3]["n_pairs"] > 5 and base[3]["n_candidates"] > 20
+    for win in wins:
+        got, cand = _run(wl, A, B, k0, n_steps, m, win)
+        st, st1 = got[3], base[3]
+        assert np.array_equal(cand, cand1), win
+        assert st["n_candidates"] == st1["n_candidates"], win
+        assert st["n_hits"] == st1["n_hits"] and st["n_pairs"] == st1["n_pairs"]
+        for a, b in zip(got[:3], base[:3]):
+            assert np.array_equal(a, b), win
+        # the same pairs; the yield's FP64 sum runs in no fixed order
+        assert st["yield"] == pytest.approx(st1["yield"], rel=1e-12)
+        assert st["n_leaf_checks"] >= st["n_candidates"]
+
+
+def test_window_copies_match_oracle(torch):
+    """Default window (16 steps per copy) over a whole 400-step run against the oracle."""
+    wl, A, B = _beams(n=3000, boost=3e3, seed=5)
+    raw, S = oracle_run(A, B, wl.dt, 400, EDGES)
+    got, _ = _run(wl, A, B, 0, 400, 0, 0)
+    assert S.n_pairs > 5
+    assert_parity(got, raw, S, 400)
+
+
+def test_far_from_origin_candidates_equal(torch):
+    """Far from the origin (|x| ~ 1e3 um, one FP32 ulp ~ 6e-5 um) the rounding slack of
+    the widened boxes grows with the magnitude: the candidates still equal those of one copy
+    per step."""
+    wl, A, B = _beams(n=2000, boost=3e4, shift=np.array([1000.0, -700.0, 900.0]))
+    base, cand1 = _run(wl, A, B, 176, 48, 48, 1)
+    got, cand = _run(wl, A, B, 176, 48, 48, 16)
+    assert base[3]["n_candidates"] > 0
+    assert np.array_equal(cand, cand1)
+    assert got[3]["n_candidates"] == base[3]["n_candidates"]
+    for a, b in zip(got[:3], base[:3]):
+        assert np.array_equal(a, b)
+
+
+def _walk(link, root):
+    leaves, stack = [], [root] if root >= 0 else []
+    if root <= -2:
+        return [-2 - root]
+    while stack:
+        p = stack.pop()
+        for c in link[p]:
+            if c >= 0:
+                stack.append(int(c))
+            else:
+                leaves.append(-2 - int(c))
+    return leaves
+
+
+@pytest.mark.parametrize("m,win", [(40, 16), (40, 4), (5, 2), (9, 9)])
+def test_copies_hold_middle_step_boxes_and_contain_every_step(torch, m, win):
+    """Several instances (one of a single row, one empty): ceil(m / W) copies of one shape;
+    each (copy, instance) root reaches exactly that instance's sorted positions; a leaf's box
+    in copy k is the photon's box at the window's middle step r (bit for bit); every step s
+    of the window has every leaf's box inside the copy's box at r widened by the instance's
+    motion bounds over s - r and the slack the traversal adds, with at least a factor two to
+    spare."""
+    parts = []
+    for k, n_k in enumerate([1700, 1, 0, 900, 2]):
+        wl = beams.gauss_headon_1m(n=max(n_k, 1), seed=20 + k)
+        parts.append(beams.head(beams.draw_pair(wl)[1], n_k))
+    Bc, off = beams.concat(parts)
+    n, n_inst = len(Bc["E"]), len(off) - 1
+    wl = beams.gauss_headon_1m(n=1000)
+    k0 = 180
+    ctx = T.Context(wl.dt, step_batch=m, kinetic_window=win)
+    try:
+        tb = T.Beam(Bc, off)
+        pairs = T.Pairs(1 << 12)
+        ctx.run(tb, tb, k0, m, pairs)
+        tree = T.tril_dbg_tree(ctx, n, n_inst, m)
+        w_got, rec = T.tril_dbg_target_records(ctx, n)
+        boxes = T.tril_dbg_boxes(ctx, 0, m * n)
+    finally:
+        ctx.close()
+    eff = min(win, m)
+    assert w_got == eff
+    copies = -(-m // eff)
+    assert tree["copies"] == copies
+    n_int = n - 1
+    link = tree["link"]
+    assert link.shape == (copies * n_int, 2)
+    base = link[:n_int]
+    for cp in range(1, copies):  # the same shape: internal links offset, leaves the same
+        lc = link[cp * n_int:(cp + 1) * n_int]
+        assert np.array_equal(lc, np.where(base >= 0, base + cp * n_int, base))
+    roots = tree["roots"].reshape(copies, n_inst)
+    for cp in range(copies):
+        for mi in range(n_inst):
+            pos = np.arange(off[mi], off[mi + 1])
+            r = int(roots[cp, mi])
+            if len(pos) == 0:
+                assert r == -1
+                continue
+            assert np.array_equal(np.sort(_walk(link, r)), pos)
+    row = rec["row"]
+    assert np.array_equal(np.sort(row), np.arange(n))
+    blo = boxes["lo"].astype(np.float64)
+    bhi = boxes["hi"].astype(np.float64)
+    leaf = link < 0
+    dt = wl.dt
+    reach = np.float32((m + eff + 8) * dt + 1e-6)
+    worst = 0.0
+    for cp in range(copies):
+        lk = link[cp * n_int:(cp + 1) * n_int]
+        lo_c = tree["lo"][cp * n_int:(cp + 1) * n_int]
+        hi_c = tree["hi"][cp * n_int:(cp + 1) * n_int]
+        r = _ref_step(cp, eff, m)
+        lf = lk < 0
+        pos = -2 - lk[lf]
+        e = r * n + row[pos]
+        assert np.array_equal(lo_c[lf], boxes["lo"][e])
+        assert np.array_equal(hi_c[lf], boxes["hi"][e])
+        c = lk[~lf] - cp * n_int
+        assert np.array_equal(lo_c[~lf], lo_c[c].min(axis=1))
+        assert np.array_equal(hi_c[~lf], hi_c[c].max(axis=1))
+        # every step of the window: leaf boxes inside the widened reference boxes
+        d = rec["d"].astype(np.float64)
+        for mi in range(n_inst):
+            p = np.arange(off[mi], off[mi + 1])
+            if len(p) == 0:
+                continue
+            dlo, dhi = d[p].min(axis=0), d[p].max(axis=0)
+            er = r * n + row[p]
+            for s in range(cp * eff, min((cp + 1) * eff, m)):
+                es = s * n + row[p]
+                delta = s - r
+                emin = np.minimum(delta * dlo, delta * dhi)
+                emax = np.maximum(delta * dlo, delta * dhi)
+                mag = np.maximum(np.abs(blo[es]), np.abs(bhi[es]))
+                sl = (mag + reach) * 2.0 ** -18
+                need_lo = (blo[er] + emin) - blo[es]   # must be <= sl
+                need_hi = bhi[es] - (bhi[er] + emax)   # must be <= sl
+                worst = max(worst, float(np.max(need_lo / sl)), float(np.max(need_hi / sl)))
+    assert leaf.any()
+    print(f"\nlargest rounding excess over the slack: {worst:.3f}")
+    assert worst <= 0.5
+
+
+def test_repeated_runs_identical(torch):
+    """Identical runs give identical candidate counts, hits and pairs, with window copies
+    and with per-step copies in short batches (both merge the levels above the refit's
+    chunks by climbing with arrival flags, whose halves must be visible device-wide before
+    the flag counts them)."""
+    wl = beams.gauss_headon_1m()
+    A, B = beams.draw_pair(wl)
+    tb, qb = T.Beam(B), T.Beam(A)
+    for win, sb in ((16, 0), (1, 16)):
+        ctx = T.Context(wl.dt, kinetic_window=win, step_batch=sb)
+        try:
+            pairs = T.Pairs(1 << 16)
+            seen = set()
+            for _ in range(4):
+                pairs.reset()
+                ctx.reset_counters()
+                T.run_steps(ctx, tb, qb, 120, pairs, k0=140)
+                st = ctx.stats(pairs)
+                seen.add((st["n_candidates"], st["n_hits"], st["n_pairs"]))
+        finally:
+            ctx.close()
+        assert len(seen) == 1, (win, sb, seen)
+        assert next(iter(seen))[2] > 1000
