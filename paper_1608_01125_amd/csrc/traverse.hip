@@ -136,8 +136,27 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
                     qs = (int32_t)s;
                     const int32_t cp = qs / wa.win;
                     const float delta = (float)(qs - window_ref_step(cp, wa.win, wa.m));
-                    const float4 *vp = reinterpret_cast<const float4 *>(wa.vb + inst);
-                    const float4 vlo = vp[0], vhi = vp[1];
+                    // the instance's motion bounds: one scalar load when the wave's queries
+                    // share their instance (nearly always: queries run in instance order),
+                    // keeping two vector loads per query off the texture path
+                    float4 vlo, vhi;
+                    const int32_t iu = __builtin_amdgcn_readfirstlane(inst);
+                    if (__ballot(inst == iu) == __ballot(1)) {
+                        typedef int v8i __attribute__((ext_vector_type(8)));
+                        v8i r;
+                        const WinBound *p = wa.vb + iu;
+                        asm volatile("s_load_dwordx8 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)"
+                                     : "=s"(r)
+                                     : "s"(p));
+                        vlo = make_float4(__int_as_float(r[0]), __int_as_float(r[1]),
+                                          __int_as_float(r[2]), __int_as_float(r[3]));
+                        vhi = make_float4(__int_as_float(r[4]), __int_as_float(r[5]),
+                                          __int_as_float(r[6]), __int_as_float(r[7]));
+                    } else {
+                        const float4 *vp = reinterpret_cast<const float4 *>(wa.vb + inst);
+                        vlo = vp[0];
+                        vhi = vp[1];
+                    }
                     const float lo3[3] = {vlo.x, vlo.y, vlo.z}, hi3[3] = {vhi.x, vhi.y, vhi.z};
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
