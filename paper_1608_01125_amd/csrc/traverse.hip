@@ -178,7 +178,19 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
             qe = b.w;
             tag = __float_as_int(a.w);
         }
-        if (tag >= 0) node = inst_root[tag];
+        if (tag >= 0) {
+            // the root of the query's (step, instance) tree: a scalar load when the wave's
+            // queries share it (they nearly always do), else a vector load
+            const int32_t tu = __builtin_amdgcn_readfirstlane(tag);
+            if (__ballot(tag == tu) == __ballot(1)) {
+                int32_t r;
+                const int32_t *p = inst_root + tu;
+                asm volatile("s_load_dword %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p));
+                node = r;
+            } else {
+                node = inst_root[tag];
+            }
+        }
     }
     const bool active = node != -1;
     {
