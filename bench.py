@@ -434,8 +434,9 @@ def kinematics_traffic(n_pairs):
 
 def kinematics_variant(T, torch, A, B, wl, n_steps, edges, reps=5):
     """Pair kinematics after one collision run (the run's unique pairs) and on a bulk list
-    of 2^22 random pairs over the same beams: kernel time from HIP events on the library's
-    stream, pairs per second and algorithmic GB/s."""
+    of 2^22 random pairs over the same beams, in random order and in the ascending (i, j)
+    order tril_stats gives a run's pairs (the roofline's case): kernel time from HIP events on
+    the library's stream, pairs per second and algorithmic GB/s."""
     import numpy as np
     g_edges = np.linspace(1.0, 40.0, 391)
     ctx = T.Context(wl.dt, edges)
@@ -449,16 +450,25 @@ def kinematics_variant(T, torch, A, B, wl, n_steps, edges, reps=5):
                      for _ in range(reps))
         n = 1 << 22
         rng = np.random.default_rng(5)
+        bi = rng.integers(0, len(A["E"]), n).astype(np.int32)
+        bj = rng.integers(0, len(B["E"]), n).astype(np.int32)
+        bk = rng.integers(0, n_steps, n).astype(np.int32)
         bulk = T.Pairs(n)
-        bulk.i.copy_(torch.from_numpy(rng.integers(0, len(A["E"]), n).astype(np.int32)))
-        bulk.j.copy_(torch.from_numpy(rng.integers(0, len(B["E"]), n).astype(np.int32)))
-        bulk.step.copy_(torch.from_numpy(rng.integers(0, n_steps, n).astype(np.int32)))
-        T.tril_pair_kinematics(ctx, qb, tb, bulk, n, 1, g_edges, 90)  # warm-up
-        ms = [T.tril_pair_kinematics(ctx, qb, tb, bulk, n, 1, g_edges, 90)["ms"]
-              for _ in range(reps)]
+        ms_by_order = {}
+        # random order, then ascending (i, j) as tril_stats leaves a run's pairs
+        for order in ("random", "sorted"):
+            o = np.arange(n) if order == "random" else np.lexsort((bj, bi))
+            bulk.i.copy_(torch.from_numpy(bi[o]))
+            bulk.j.copy_(torch.from_numpy(bj[o]))
+            bulk.step.copy_(torch.from_numpy(bk[o]))
+            T.tril_pair_kinematics(ctx, qb, tb, bulk, n, 1, g_edges, 90)  # warm-up
+            ms_by_order[order] = [T.tril_pair_kinematics(ctx, qb, tb, bulk, n, 1, g_edges, 90)["ms"]
+                                  for _ in range(reps)]
     finally:
         ctx.close()
+    ms = ms_by_order["sorted"]
     avg = sum(ms) / len(ms)
+    avg_random = sum(ms_by_order["random"]) / reps
     gbs = KIN_BYTES_PER_PAIR * n / (avg * 1e-3) / 1e9
     traffic = kinematics_traffic(n)
     # the oracle beside it: the same kinematics in plain Python floats, 3000 seeded pairs
@@ -475,8 +485,9 @@ def kinematics_variant(T, torch, A, B, wl, n_steps, edges, reps=5):
     return {"cpu_oracle": {"pairs_per_s": ns / cpu_s, "cores": 1, "kind": "oracle",
                            "sample": f"{ns} seeded random pairs, Python floats, one thread"},
             "run_pairs": n_run, "run_pairs_ms": round(ms_run, 4),
-            "bulk_pairs": n, "bulk_ms": round(avg, 4),
-            "bulk_pairs_per_s": n / (avg * 1e-3),
+            "bulk_pairs": n, "bulk_order": "ascending (i, j), as a run's pairs",
+            "bulk_ms": round(avg, 4), "bulk_pairs_per_s": n / (avg * 1e-3),
+            "bulk_random_order_ms": round(avg_random, 4),
             "roofline": {"bound": "hbm", "kernel": "k_pair_kin", "achieved": round(gbs, 2),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
