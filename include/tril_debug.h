@@ -81,6 +81,21 @@ int tril_dbg_tree(tril_ctx *ctx, void *nodes, int64_t cap_nodes, int64_t *n_node
  * TRIL_E_OVERFLOW if cap < *n. */
 int tril_dbg_target_records(tril_ctx *ctx, void *recs, int64_t cap, int64_t *n, int32_t *win);
 
+/* Four-child forms of the window copies of the last build, which the traversal descends:
+ * *n_copies receives the copies (0 without them, and *n = 0), *n their count (copies x
+ * (n - 1), one per internal node in the order of tril_dbg_tree); nodes (host, cap x 16
+ * words): slot k's box in words 3k..3k+2 as 16-bit frame cells (lo x | lo y << 16,
+ * lo z | hi x << 16, hi y | hi z << 16; lo > hi: empty), word 12 the first child g0 of the
+ * node's left child (slots 0 and 1 are g0 and g0 + 1: internal nodes of the same copy, or
+ * sorted leaf positions; a leaf left child is slot 0 itself), word 13 likewise g2 for slots
+ * 2 and 3, words 14 and 15 the slots' energy bounds (bits 0-14 and 16-30: the top 15 bits of
+ * the FP32 bound, rounded up) and leaf flags (bits 15 and 31) for slots 0, 1 and 2, 3;
+ * frames (host, 8 floats per copy): base x y z, 0, cells per unit x y z, 0 (cell k of an axis
+ * spans [base + k / inv, base + (k + 1) / inv]). Synchronises the stream; TRIL_E_OVERFLOW if
+ * cap < *n. */
+int tril_dbg_quad_nodes(tril_ctx *ctx, void *nodes, int64_t cap, int64_t *n, float *frames,
+                        int32_t *n_copies);
+
 /* Copy the swept boxes of the last target (which = 0: all m n of the last build's m
  * steps, formed again here exactly as the build's refit formed them) or query
  * (which = 1) beam to host memory as n x 8 words (lox loy loz tag hix hiy hiz

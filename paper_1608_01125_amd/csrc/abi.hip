@@ -158,8 +158,13 @@ struct tril_ctx {
     int32_t *inst_base = nullptr;          // instance roots of the shared tree shape
     PBox *root_box = nullptr;              // boxes of combined instances of one row
     TRec *t_rec = nullptr;                 // window copies: per sorted target position
+    CNode4 *nodes4 = nullptr;              // window copies: four-child forms of the nodes
+    int64_t nodes4_cap = 0;
+    WinFrame *t_frames = nullptr;          // window copies: quantisation frame per copy
+    int32_t frames_cap = 0;
     WinBound *t_wb = nullptr;              // window copies: per target instance, bounds of u dt
     int32_t win_eff = 1;                   // steps per tree copy of the last build
+    bool quad = false;                     // the last build has four-child forms
     int32_t *refit_slots = nullptr;        // refit hand-offs to the crossing-level kernel
     int32_t *xlev = nullptr;               // crossing levels of the shape (batches of many steps)
     int64_t refit_slot_cap = 0;
@@ -539,6 +544,8 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
     c->n_int = n > 0 ? (int64_t)copies * (n - 1) : -1;
     c->tgt_cloud = c->cloud;
     if (win > 1) launch_win_bounds(c->t_stats, t.n_inst, c->dt, c->t_wb, st);
+    c->quad = win > 1 && n > 1 && (int64_t)copies * (n - 1) <= c->nodes4_cap &&
+              copies <= c->frames_cap;
     launch_inst_roots(t, c->cloud, c->dt, c->inst_base, rows, c->inst_root, c->root_box, c->d_cnt,
                       st, win, c->t_rec);
     int32_t *xbase = nullptr;
@@ -549,6 +556,10 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
     }
     launch_refit(t, c->cloud, c->dt, rows, c->prec, c->nflags, c->nodes, c->refit_slots,
                  c->refit_slot_cap, xbase, xalt, c->d_cnt, &c->d_cnt->err, st, win, c->t_rec);
+    if (c->quad) {
+        launch_win_frames(c->t_stats, t.n_inst, c->dt, win, t.m, c->d_cnt, c->t_frames, st);
+        launch_collapse4(c->nodes, n, copies, c->t_frames, c->nodes4, &c->d_cnt->err, st);
+    }
     if (timed) CHK(timing_pair(c, st, c->ev_build, false));
     HIPCHK(hipGetLastError());
     return TRIL_OK;
@@ -648,6 +659,8 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
     if (c->win_eff > 1) {
         wa.trec = c->t_rec;
         wa.vb = c->t_wb;
+        wa.nodes4 = c->quad ? c->nodes4 : nullptr;
+        wa.frames = c->t_frames;
         wa.win = c->win_eff;
         wa.m = q.m;
         wa.n = c->tgt.n;
@@ -1001,6 +1014,24 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     const int32_t m = pick_batch(c, t, q, n_steps);
     // capacities for the largest batch first, so that nothing is reallocated later
     CHK(ensure_target(c, (int64_t)m * t->n, t->n, (int64_t)m * t->n_inst, t->n_inst));
+    if (build_window(c, m) > 1 && t->n > 1) {  // four-child forms of the window copies
+        const int64_t need = (int64_t)window_copies(m, build_window(c, m)) * (t->n - 1);
+        if (need > c->nodes4_cap) {
+            ++c->alloc_gen;
+            dev_free(c->nodes4); dev_free(c->t_frames);
+            c->nodes4_cap = 0;
+            CHK(dev_alloc(&c->nodes4, (size_t)need));
+            c->nodes4_cap = need;
+        }
+        const int32_t nf = window_copies(m, build_window(c, m));
+        if (nf > c->frames_cap) {
+            ++c->alloc_gen;
+            dev_free(c->t_frames);
+            c->frames_cap = 0;
+            CHK(dev_alloc(&c->t_frames, (size_t)nf));
+            c->frames_cap = nf;
+        }
+    }
     CHK(ensure_query(c, (int64_t)m * q->n, q->n, (int64_t)m * q->n_inst, q->n_inst));
     CHK(ensure_work(c, c->wt, t->n));
     CHK(ensure_work(c, c->wq, q->n));
@@ -1214,7 +1245,7 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     out->n_hits = 0;
     out->yield = 0.0;
     if (err & kErrData) return TRIL_E_DATA;
-    if (err & kErrSpin) return TRIL_E_INTERNAL;
+    if (err & (kErrSpin | kErrInternal)) return TRIL_E_INTERNAL;
     if (err & kErrCandOverflow) return TRIL_E_OVERFLOW;
     if (!p) return TRIL_OK;
     int64_t n_hits = 0;
@@ -1259,7 +1290,7 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     }
     unsigned int err2 = 0;
     HIPCHK(hipMemcpy(&err2, &c->d_cnt->err, sizeof(err2), hipMemcpyDeviceToHost));
-    if (err2 & kErrSpin) return TRIL_E_INTERNAL;
+    if (err2 & (kErrSpin | kErrInternal)) return TRIL_E_INTERNAL;
     return TRIL_OK;
 }
 
@@ -2538,6 +2569,7 @@ void tril_destroy(tril_ctx *c) {
     }
     dev_free(c->au_cell); dev_free(c->au_ctl); dev_free(c->au_count);
     dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->t_wb); dev_free(c->inst_root); dev_free(c->inst_base); dev_free(c->root_box);
+    dev_free(c->nodes4);
     dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
     dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
     dev_free(c->q_keep); dev_free(c->q_rec); dev_free(c->d_q_off); dev_free(c->q_stats); dev_free(c->cand_i);
@@ -2705,6 +2737,24 @@ int tril_dbg_target_records(tril_ctx *c, void *recs, int64_t cap, int64_t *n, in
     if (nn > 0) {
         if (!recs) return TRIL_E_INVAL;
         HIPCHK(hipMemcpy(recs, c->t_rec, nn * sizeof(TRec), hipMemcpyDeviceToHost));
+    }
+    return TRIL_OK;
+}
+
+int tril_dbg_quad_nodes(tril_ctx *c, void *nodes, int64_t cap, int64_t *n, float *frames,
+                        int32_t *n_copies) {
+    if (!c || !n || !n_copies) return TRIL_E_INVAL;
+    if (!c->built) return TRIL_E_STATE;
+    HIPCHK(hipStreamSynchronize(c->st));
+    const int32_t copies = c->quad ? window_copies(c->tgt.m, c->win_eff) : 0;
+    const int64_t nn = copies > 0 ? (int64_t)copies * (c->tgt.n - 1) : 0;
+    *n = nn;
+    *n_copies = copies;
+    if (nn > cap) return TRIL_E_OVERFLOW;
+    if (nn > 0) {
+        if (!nodes || !frames) return TRIL_E_INVAL;
+        HIPCHK(hipMemcpy(nodes, c->nodes4, nn * sizeof(CNode4), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(frames, c->t_frames, copies * sizeof(WinFrame), hipMemcpyDeviceToHost));
     }
     return TRIL_OK;
 }

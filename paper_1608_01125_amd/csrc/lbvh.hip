@@ -646,6 +646,135 @@ __global__ void k_win_bounds(const InstStats *__restrict__ stats, int32_t n_inst
     vb[mi] = o;
 }
 
+// Quantisation frame of every window copy: the union over instances of where the
+// photons can be during the copy's step (positions at t = 0 and directions bounded by the
+// statistics; x0 + u t over the step's time window is extremal at the corners), widened by
+// a margin eight times the rounding of the FP32 leaf boxes (below 2^-19 (|x| + m dt)).
+__global__ void k_win_frames(const InstStats *__restrict__ stats, int32_t n_inst, double dt,
+                             int32_t win, int32_t m, const DevCounters *__restrict__ c,
+                             WinFrame *__restrict__ frames) {
+    const int32_t cp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cp >= window_copies(m, win)) return;
+    const int32_t r = window_ref_step(cp, win, m);
+    const double t0 = (double)(c->step + (unsigned)r) * dt, t1 = t0 + dt;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t mi = 0; mi < n_inst; ++mi) {
+        const InstStats &st = stats[mi];
+        if (st.mn[0] > st.mx[0]) continue;  // no usable photon
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double ul = ord2d(st.mn[3 + a]), uh = ord2d(st.mx[3 + a]);
+            const double e = fmin(fmin(ul * t0, ul * t1), fmin(uh * t0, uh * t1));
+            const double f = fmax(fmax(ul * t0, ul * t1), fmax(uh * t0, uh * t1));
+            lo[a] = fmin(lo[a], ord2d(st.mn[a]) + e);
+            hi[a] = fmax(hi[a], ord2d(st.mx[a]) + f);
+        }
+    }
+    float base[3], inv[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!(lo[a] <= hi[a])) {  // no usable photon at all: any frame
+            base[a] = 0.0f;
+            inv[a] = 1.0f;
+            continue;
+        }
+        const double mg = 0x1p-16 * (fmax(fabs(lo[a]), fabs(hi[a])) + (double)m * dt) + 1e-9;
+        const double b = (double)f32_down(lo[a] - mg);
+        base[a] = (float)b;
+        inv[a] = f32_down(65535.0 / ((hi[a] + mg) - b));  // rounded down: the top only grows
+    }
+    WinFrame fr;
+    fr.base = make_float4(base[0], base[1], base[2], 0.0f);
+    fr.inv = make_float4(inv[0], inv[1], inv[2], 0.0f);
+    frames[cp] = fr;
+}
+
+// Cells [ql, qh] of [lo, hi] on one axis of a frame; bad: the box leaves the frame. An empty
+// interval (lo > hi) becomes ql = 65535 > qh = 0.
+__device__ __forceinline__ void quantise(float lo, float hi, float base, float inv, uint32_t &ql,
+                                         uint32_t &qh, bool &bad) {
+    if (!(lo <= hi)) {
+        ql = 65535u;
+        qh = 0u;
+        return;
+    }
+    const float a = (lo - base) * inv, b = (hi - base) * inv;
+    bad = bad || !(a >= -1.0f) || !(b <= 65536.0f);
+    ql = (uint32_t)fminf(fmaxf(floorf(a) - 1.0f, 0.0f), 65535.0f);
+    qh = (uint32_t)fminf(fmaxf(ceilf(b) + 1.0f, 0.0f), 65535.0f);
+}
+
+// Top 15 bits of a non-negative FP32 value, rounded up.
+__device__ __forceinline__ uint32_t e15_up(float e) {
+    return ((__float_as_uint(e) + 0xFFFFu) >> 16) & 0x7FFFu;
+}
+
+// One slot of a four-child form: the box words and the energy/leaf half-word of a half.
+__device__ __forceinline__ void cslot(float4 lo, float4 hi, const float fb[3], const float fi[3],
+                                      uint32_t *w3, uint32_t &eh, bool &bad) {
+    uint32_t ql[3], qh[3];
+    quantise(lo.x, hi.x, fb[0], fi[0], ql[0], qh[0], bad);
+    quantise(lo.y, hi.y, fb[1], fi[1], ql[1], qh[1], bad);
+    quantise(lo.z, hi.z, fb[2], fi[2], ql[2], qh[2], bad);
+    w3[0] = ql[0] | (ql[1] << 16);
+    w3[1] = ql[2] | (qh[0] << 16);
+    w3[2] = qh[1] | (qh[2] << 16);
+    eh = e15_up(hi.w) | ((__float_as_int(lo.w) < 0 ? 1u : 0u) << 15);
+}
+
+// Local id of the node or sorted leaf position a link of copy base cbase names.
+__device__ __forceinline__ int64_t local_id(int32_t link, int64_t cbase) {
+    return link >= 0 ? (int64_t)link - cbase : -2 - (int64_t)link;
+}
+
+// Four-child forms (CNode4) of every internal node of the copies: one thread per node reads
+// the node and, for each internal child, that child's node.
+__global__ void __launch_bounds__(256) k_collapse4(const Node *__restrict__ nodes, int64_t n,
+                                                   int32_t copies,
+                                                   const WinFrame *__restrict__ frames,
+                                                   CNode4 *__restrict__ out, unsigned int *err) {
+    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t per = n - 1;
+    if (idx >= per * copies) return;
+    const int32_t cp = (int32_t)(idx / per);
+    const int64_t cbase = (int64_t)cp * per;
+    const WinFrame fr = frames[cp];
+    const float fb[3] = {fr.base.x, fr.base.y, fr.base.z}, fi[3] = {fr.inv.x, fr.inv.y, fr.inv.z};
+    const float4 *np = reinterpret_cast<const float4 *>(nodes + idx);
+    uint32_t w[16];
+    uint32_t eh[4];
+    bool bad = false;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const float4 lo = np[2 * side], hi = np[2 * side + 1];
+        const int32_t link = __float_as_int(lo.w);
+        int64_t g;
+        if (link >= 0) {  // the child's two children
+            const float4 *cq = reinterpret_cast<const float4 *>(nodes + link);
+            const float4 a0 = cq[0], a1 = cq[1], b0 = cq[2], b1 = cq[3];
+            cslot(a0, a1, fb, fi, w + 6 * side, eh[2 * side], bad);
+            cslot(b0, b1, fb, fi, w + 6 * side + 3, eh[2 * side + 1], bad);
+            g = local_id(__float_as_int(a0.w), cbase);
+            if (local_id(__float_as_int(b0.w), cbase) != g + 1) bad = true;
+        } else {  // the leaf itself, then an empty slot
+            cslot(lo, hi, fb, fi, w + 6 * side, eh[2 * side], bad);
+            w[6 * side + 3] = 65535u | (65535u << 16);
+            w[6 * side + 4] = 65535u;
+            w[6 * side + 5] = 0u;
+            eh[2 * side + 1] = 0u;
+            g = -2 - (int64_t)link;
+        }
+        if (g < 0 || g >= n) bad = true;
+        w[12 + side] = (uint32_t)g;
+    }
+    w[14] = eh[0] | (eh[1] << 16);
+    w[15] = eh[2] | (eh[3] << 16);
+    if (bad) atomicOr(err, kErrInternal);
+    uint4 *op = reinterpret_cast<uint4 *>(out + idx);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) op[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+}
+
 // ------------------------------------------------------------------- refit
 
 // Child halves that another thread of the same launch may read are stored with
@@ -1229,6 +1358,22 @@ void launch_inst_roots(const BeamDev &b, const CloudBox &cloud, double dt, const
     if (n_comb <= 0) return;
     hipLaunchKernelGGL(k_inst_roots, dim3(grid_for(n_comb, 64)), dim3(64), 0, st, b, cloud, dt,
                        base_root, sorted_rows, inst_root, root_box, c, win, n_copies, trec);
+}
+
+void launch_win_frames(const InstStats *stats, int32_t n_inst, double dt, int32_t win, int32_t m,
+                       const DevCounters *c, WinFrame *frames, hipStream_t st) {
+    const int32_t nc = window_copies(m, win);
+    if (nc <= 0) return;
+    hipLaunchKernelGGL(k_win_frames, dim3(grid_for(nc, 64)), dim3(64), 0, st, stats, n_inst, dt,
+                       win, m, c, frames);
+}
+
+void launch_collapse4(const Node *nodes, int64_t n, int32_t copies, const WinFrame *frames,
+                      CNode4 *out, unsigned int *err, hipStream_t st) {
+    const int64_t total = n > 1 ? (n - 1) * copies : 0;
+    if (total <= 0) return;
+    hipLaunchKernelGGL(k_collapse4, dim3(grid_for(total, 256)), dim3(256), 0, st, nodes, n, copies,
+                       frames, out, err);
 }
 
 void launch_win_bounds(const InstStats *stats, int32_t n_inst, double dt, WinBound *vb,

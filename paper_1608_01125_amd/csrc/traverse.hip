@@ -75,6 +75,8 @@ constexpr float kPruneProduct = (float)(kMe * kMe * (1.0 - 1e-5));
 
 constexpr int kStackRegs = 4;
 constexpr int kStackSpill = 124;  // deeper than any radix tree over (key, index) pairs
+// four-child descent: at most three pushes per level of a tree at most 48 levels deep
+constexpr int kStackSpill4 = 144;
 
 // Box of a query of step offset s from the row's record for the batch (moved_box).
 __device__ __forceinline__ void record_box(const float4 a, const float4 d, const float4 w,
@@ -99,7 +101,7 @@ __device__ __forceinline__ bool leaf_exact(const WinArgs &wa, int64_t j, int32_t
 // The descent of virtual query q (q >= nq: an idle lane that still takes part in the
 // wave's ballots); adds its node loads to visits (and, over window copies, its leaf
 // record loads to checks) and returns whether it had a root.
-template <bool kRec, bool kWin>
+template <bool kRec, bool kWin, bool kQuad>
 __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict__ nodes,
                                                int32_t n_int, const PBox *__restrict__ root_box,
                                                const PBox *__restrict__ qbox,
@@ -114,6 +116,8 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
     int32_t node = -1, qi = 0, tag = -1, qs = 0;
     float qb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float qw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // window copies: the widened box
+    int32_t qc[6] = {0, 0, 0, 0, 0, 0};  // four-child forms: the widened box in frame cells
+    int32_t cbase = 0;                   // four-child forms: first node of the query's copy
     float qe = 0.f;
     if (q < nq) {
         if (qorder == nullptr) {
@@ -166,6 +170,37 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
                         qw[k + 3] = (qb[k + 3] - fminf(e1, e2)) + sl;
                     }
                     tag = cp * n_inst + inst;
+                    if (kQuad) {
+                        // the widened box in the copy's frame cells (floor - 1, ceil + 1: the
+                        // one-cell margins cover the FP32 rounding), kept within [-1, 65536]
+                        const int32_t cu = __builtin_amdgcn_readfirstlane(cp);
+                        float4 fb, fi;
+                        if (__ballot(cp == cu) == __ballot(1)) {
+                            typedef int v8i __attribute__((ext_vector_type(8)));
+                            v8i r;
+                            const WinFrame *p = wa.frames + cu;
+                            asm volatile("s_load_dwordx8 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)"
+                                         : "=s"(r)
+                                         : "s"(p));
+                            fb = make_float4(__int_as_float(r[0]), __int_as_float(r[1]),
+                                             __int_as_float(r[2]), 0.0f);
+                            fi = make_float4(__int_as_float(r[4]), __int_as_float(r[5]),
+                                             __int_as_float(r[6]), 0.0f);
+                        } else {
+                            const float4 *fp = reinterpret_cast<const float4 *>(wa.frames + cp);
+                            fb = fp[0];
+                            fi = fp[1];
+                        }
+                        const float b3[3] = {fb.x, fb.y, fb.z}, i3[3] = {fi.x, fi.y, fi.z};
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            const float lo = (qw[k] - b3[k]) * i3[k];
+                            const float hi = (qw[k + 3] - b3[k]) * i3[k];
+                            qc[k] = (int32_t)fminf(fmaxf(floorf(lo) - 1.0f, -1.0f), 65536.0f);
+                            qc[k + 3] = (int32_t)fminf(fmaxf(ceilf(hi) + 1.0f, -1.0f), 65536.0f);
+                        }
+                        cbase = cp * (int32_t)(wa.n - 1);
+                    }
                 } else {
                     tag = (int32_t)(s * n_inst + inst);
                 }
@@ -212,10 +247,107 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
         emit_candidate(hit, qi, e, cand_i, cand_j, cand_cap, c);
     }
     int32_t st0 = -1, st1 = -1, st2 = -1, st3 = -1;
-    int32_t spill[kStackSpill];
+    int32_t spill[kQuad ? kStackSpill4 : kStackSpill];
     int32_t depth = 0;
     // every internal node is loaded at most once per query in a well-formed tree
     const uint32_t max_visits = (uint32_t)n_int + 2u;
+    if (kQuad) {
+        // four-child descent: every load brings the boxes of the node's grandchildren, so the
+        // chain of dependent loads is half as long; up to three overlapping internal
+        // children wait on the stack
+        while (node >= 0) {
+            if (visits > max_visits) {
+                atomicOr(&c->err, kErrSpin);
+                break;
+            }
+            uint32_t w[16];
+            const int32_t first = __builtin_amdgcn_readfirstlane(node);
+            if (__ballot(node == first) == __ballot(1)) {
+                typedef int v16i __attribute__((ext_vector_type(16)));
+                v16i r;
+                const CNode4 *p = wa.nodes4 + first;
+                asm volatile("s_load_dwordx16 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p));
+#pragma unroll
+                for (int k = 0; k < 16; ++k) w[k] = (uint32_t)r[k];
+            } else {
+                const uint4 *np = reinterpret_cast<const uint4 *>(wa.nodes4 + node);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint4 v = np[k];
+                    w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+                }
+            }
+            ++visits;
+            int32_t lk[4];
+            bool ov[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t a0 = w[3 * k], a1 = w[3 * k + 1], a2 = w[3 * k + 2];
+                const uint32_t eh = (k & 1) ? (w[14 + (k >> 1)] >> 16) : (w[14 + (k >> 1)] & 0xFFFFu);
+                const float e = __uint_as_float((eh & 0x7FFFu) << 16);
+                ov[k] = ((int32_t)(a0 & 0xFFFFu) <= qc[3]) & ((int32_t)(a1 >> 16) >= qc[0]) &
+                        ((int32_t)(a0 >> 16) <= qc[4]) & ((int32_t)(a2 & 0xFFFFu) >= qc[1]) &
+                        ((int32_t)(a1 & 0xFFFFu) <= qc[5]) & ((int32_t)(a2 >> 16) >= qc[2]) &
+                        (qe * e >= kPruneProduct);
+                const int32_t g = (int32_t)w[12 + (k >> 1)] + (k & 1);
+                lk[k] = (eh & 0x8000u) ? leaf_link(g) : cbase + g;
+            }
+            // leaves: nothing to do in most visits of most waves (one ballot decides)
+            const bool any_leaf = (ov[0] & (lk[0] <= -2)) | (ov[1] & (lk[1] <= -2)) |
+                                  (ov[2] & (lk[2] <= -2)) | (ov[3] & (lk[3] <= -2));
+            if (__ballot(any_leaf) != 0ull)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                bool e = ov[k] & (lk[k] <= -2);
+                int64_t j = link_elem(lk[k]);
+                if (e) {
+                    // the query's exact box, formed again from its record (kept out of the
+                    // registers the descent holds)
+                    float qx[6];
+                    const float4 *rp =
+                        reinterpret_cast<const float4 *>(qrec + (qi - (int64_t)qs * nq_base));
+                    record_box(rp[0], rp[1], rp[2], (float)qs, qx);
+                    e = leaf_exact(wa, j, qs, qx, qe, j);
+                    ++checks;
+                }
+                emit_candidate(e, qi, j, cand_i, cand_j, cand_cap, c);
+            }
+            int32_t nxt = -1;
+            bool full = false;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!(ov[k] & (lk[k] >= 0))) continue;
+                if (nxt < 0) {
+                    nxt = lk[k];
+                    continue;
+                }
+                if (depth >= kStackRegs) {
+                    if (depth - kStackRegs >= kStackSpill4) {
+                        full = true;
+                        continue;
+                    }
+                    spill[depth - kStackRegs] = st3;
+                }
+                st3 = st2; st2 = st1; st1 = st0; st0 = lk[k];
+                ++depth;
+            }
+            if (full) {
+                atomicOr(&c->err, kErrSpin);
+                break;
+            }
+            if (nxt >= 0) {
+                node = nxt;
+            } else if (depth > 0) {  // pop
+                node = st0;
+                st0 = st1; st1 = st2; st2 = st3;
+                --depth;
+                if (depth >= kStackRegs) st3 = spill[depth - kStackRegs];
+            } else {
+                node = -1;
+            }
+        }
+        return active;
+    }
     while (node >= 0) {
         if (visits > max_visits) {
             atomicOr(&c->err, kErrSpin);
@@ -252,19 +384,22 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
         const bool ovr = box_overlap(kWin ? qw : qb, r0, r1) & (qe * r1.w >= kPruneProduct);
         const bool leafl = lc < 0, leafr = rc < 0;
         bool el = ovl & leafl, er = ovr & leafr;
-        int64_t jl = link_elem(lc), jr = link_elem(rc);
-        if (kWin) {
-            if (el) {
-                el = leaf_exact(wa, jl, qs, qb, qe, jl);
-                ++checks;
+        // leaves: nothing to do in most visits of most waves (one ballot decides)
+        if (__ballot(el | er) != 0ull) {
+            int64_t jl = link_elem(lc), jr = link_elem(rc);
+            if (kWin) {
+                if (el) {
+                    el = leaf_exact(wa, jl, qs, qb, qe, jl);
+                    ++checks;
+                }
+                if (er) {
+                    er = leaf_exact(wa, jr, qs, qb, qe, jr);
+                    ++checks;
+                }
             }
-            if (er) {
-                er = leaf_exact(wa, jr, qs, qb, qe, jr);
-                ++checks;
-            }
+            emit_candidate(el, qi, jl, cand_i, cand_j, cand_cap, c);
+            emit_candidate(er, qi, jr, cand_i, cand_j, cand_cap, c);
         }
-        emit_candidate(el, qi, jl, cand_i, cand_j, cand_cap, c);
-        emit_candidate(er, qi, jr, cand_i, cand_j, cand_cap, c);
         const bool gol = ovl & !leafl, gor = ovr & !leafr;
         if (gol) {
             if (gor) {  // push the right child
@@ -311,8 +446,8 @@ __device__ __forceinline__ void add_counts(uint32_t visits, uint32_t checks,
 }
 
 // One virtual query per lane over a flat grid.
-template <int BLOCK, bool kRec, bool kWin>
-__global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nodes, int32_t n_int,
+template <int BLOCK, bool kRec, bool kWin, bool kQuad>
+__global__ void __launch_bounds__(BLOCK, kQuad ? 8 : 1) k_traverse(const Node *__restrict__ nodes, int32_t n_int,
                                                     const PBox *__restrict__ root_box,
                                                     const PBox *__restrict__ qbox,
                                                     const QRec *__restrict__ qrec, int32_t n_inst,
@@ -324,7 +459,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
                                                     DevCounters *c, WinArgs wa) {
     const int64_t q = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
     uint32_t visits = 0, checks = 0;
-    const bool act = traverse_query<kRec, kWin>(q, nodes, n_int, root_box, qbox, qrec, n_inst,
+    const bool act = traverse_query<kRec, kWin, kQuad>(q, nodes, n_int, root_box, qbox, qrec, n_inst,
                                                 qorder, order_len, nq, nq_base, inst_root, cand_i,
                                                 cand_j, cand_cap, c, visits, wa, checks);
     add_counts(visits, checks, (unsigned long long)__popcll(__ballot(act)), c);
@@ -339,7 +474,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse(const Node *__restrict__ nod
 // over eight addresses, instead of one per wave of queries at one address.
 constexpr int kQueueChunk = 1024;
 
-template <int BLOCK, bool kRec, bool kWin>
+template <int BLOCK, bool kRec, bool kWin, bool kQuad>
 __global__ void __launch_bounds__(BLOCK) k_traverse_queue(const Node *__restrict__ nodes,
                                                           int32_t n_int,
                                                           const PBox *__restrict__ root_box,
@@ -366,7 +501,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse_queue(const Node *__restrict
         if (base >= nq) break;
         for (int sub = 0; sub < kQueueChunk; sub += 64) {
             if (base + sub >= nq) break;
-            const bool act = traverse_query<kRec, kWin>(
+            const bool act = traverse_query<kRec, kWin, kQuad>(
                 base + sub + lane, nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len,
                 nq, nq_base, inst_root, cand_i, cand_j, cand_cap, c, visits, wa, checks);
             n_active += (unsigned long long)__popcll(__ballot(act));
@@ -375,7 +510,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse_queue(const Node *__restrict
     add_counts(visits, checks, n_active, c);
 }
 
-template <int BLOCK, bool kRec, bool kWin>
+template <int BLOCK, bool kRec, bool kWin, bool kQuad>
 void launch_traverse_k(const Node *nodes, int32_t n_int, const PBox *root_box, const PBox *qbox,
                        const QRec *qrec, int32_t n_inst, const uint32_t *qorder, int64_t order_len,
                        int64_t nq, int64_t nq_base, const int32_t *inst_root, int32_t *cand_i,
@@ -385,12 +520,12 @@ void launch_traverse_k(const Node *nodes, int32_t n_int, const PBox *root_box, c
     if (queue) {
         // as many workgroups as keep 32 waves on each of the 256 CUs
         const unsigned grid = (unsigned)std::min<int64_t>(want, 8192 * 64 / BLOCK);
-        hipLaunchKernelGGL((k_traverse_queue<BLOCK, kRec, kWin>), dim3(grid), dim3(BLOCK), 0, st,
+        hipLaunchKernelGGL((k_traverse_queue<BLOCK, kRec, kWin, kQuad>), dim3(grid), dim3(BLOCK), 0, st,
                            nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq,
                            nq_base, inst_root, cand_i, cand_j, cand_cap, c, wa);
         return;
     }
-    hipLaunchKernelGGL((k_traverse<BLOCK, kRec, kWin>), dim3((unsigned)want), dim3(BLOCK), 0, st,
+    hipLaunchKernelGGL((k_traverse<BLOCK, kRec, kWin, kQuad>), dim3((unsigned)want), dim3(BLOCK), 0, st,
                        nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq, nq_base,
                        inst_root, cand_i, cand_j, cand_cap, c, wa);
 }
@@ -402,19 +537,24 @@ void launch_traverse_b(const Node *nodes, int32_t n_int, const PBox *root_box, c
                        int32_t *cand_j, int64_t cand_cap, DevCounters *c, bool queue,
                        const WinArgs *win, hipStream_t st) {
     WinArgs wa = {};
-    if (qrec != nullptr && win != nullptr) {
+    if (qrec != nullptr && win != nullptr && win->nodes4 != nullptr) {
         wa = *win;
-        launch_traverse_k<BLOCK, true, true>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder,
-                                             order_len, nq, nq_base, inst_root, cand_i, cand_j,
-                                             cand_cap, c, queue, wa, st);
+        launch_traverse_k<BLOCK, true, true, true>(nodes, n_int, root_box, qbox, qrec, n_inst,
+                                                   qorder, order_len, nq, nq_base, inst_root,
+                                                   cand_i, cand_j, cand_cap, c, queue, wa, st);
+    } else if (qrec != nullptr && win != nullptr) {
+        wa = *win;
+        launch_traverse_k<BLOCK, true, true, false>(nodes, n_int, root_box, qbox, qrec, n_inst,
+                                                    qorder, order_len, nq, nq_base, inst_root,
+                                                    cand_i, cand_j, cand_cap, c, queue, wa, st);
     } else if (qrec != nullptr) {
-        launch_traverse_k<BLOCK, true, false>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder,
-                                              order_len, nq, nq_base, inst_root, cand_i, cand_j,
-                                              cand_cap, c, queue, wa, st);
+        launch_traverse_k<BLOCK, true, false, false>(nodes, n_int, root_box, qbox, qrec, n_inst,
+                                                     qorder, order_len, nq, nq_base, inst_root,
+                                                     cand_i, cand_j, cand_cap, c, queue, wa, st);
     } else {
-        launch_traverse_k<BLOCK, false, false>(nodes, n_int, root_box, qbox, qrec, n_inst, qorder,
-                                               order_len, nq, nq_base, inst_root, cand_i, cand_j,
-                                               cand_cap, c, queue, wa, st);
+        launch_traverse_k<BLOCK, false, false, false>(nodes, n_int, root_box, qbox, qrec, n_inst,
+                                                      qorder, order_len, nq, nq_base, inst_root,
+                                                      cand_i, cand_j, cand_cap, c, queue, wa, st);
     }
 }
 

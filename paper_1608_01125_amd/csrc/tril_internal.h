@@ -20,6 +20,7 @@ constexpr uint32_t kErrCandOverflow = 2u;  // broad-phase candidate buffer full
 constexpr uint32_t kErrSpin = 4u;          // a bounded device loop or stack ran out
 constexpr uint32_t kErrPairOverflow = 8u;  // caller pair buffer full
 constexpr uint32_t kErrTableFull = 16u;    // statistical-regime bin-pair table full
+constexpr uint32_t kErrInternal = 32u;     // an internal invariant failed (four-child forms)
 
 // Breit-Wheeler total cross-section (Eq. 1) [um^2], 0 at and below threshold, written
 // as (pi r_e^2 / 2) / s [ (3 - b^4) L - 2 b (2 - b^2) ] with b^2 = (s-1)/s and
@@ -50,6 +51,31 @@ struct alignas(16) Node {
     Half c[2];
 };
 static_assert(sizeof(Half) == 32 && sizeof(Node) == 64, "node layout");
+
+// Quantisation frame of one window copy: every leaf box of the copy's step (all
+// instances) lies in the box [base, base + 65535 / inv] per axis, so a box of the copy is
+// kept as 16-bit cell indices: floor((lo - base) inv) - 1 and ceil((hi - base) inv) + 1
+// clamped to [0, 65535] (the one-cell margins cover the FP32 rounding of the products,
+// below 0.02 cells).
+struct WinFrame {
+    float4 base;  // xyz
+    float4 inv;   // xyz: cells per unit length
+};
+
+// Four-child form of internal node x of a window copy (64 bytes): the node's grandchildren
+// (or, where x's child on a side is a leaf, that leaf and an empty slot), so that a descent
+// visiting only these forms from the root tests two levels of the binary hierarchy per load
+// and halves its chain of dependent loads. Slot k's box, in the copy's frame cells, is
+// words 3k..3k+2 (lo x | lo y << 16, lo z | hi x << 16, hi y | hi z << 16; an empty slot
+// has lo > hi and meets nothing). Slots 0 and 1 are the children g0 and g0 + 1 of x's left
+// child (word 12; internal node ids of the copy or sorted leaf positions), slots 2 and 3
+// those of its right child (g2 in word 13); a leaf child of x takes slot 0 or 2 itself. Words
+// 14 and 15 hold slots 0, 1 and 2, 3: each slot's subtree energy bound as the top 15 bits of
+// its FP32 value rounded up (bits 0-14, 16-30) and its leaf flag (bit 15, 31).
+struct alignas(16) CNode4 {
+    uint32_t w[16];
+};
+static_assert(sizeof(CNode4) == 64, "four-child node layout");
 __host__ __device__ inline int32_t leaf_link(int64_t e) { return (int32_t)(-2 - e); }
 __host__ __device__ inline int64_t link_elem(int32_t l) { return -2 - (int64_t)l; }
 
@@ -159,6 +185,8 @@ struct WinBound {
 struct WinArgs {
     const TRec *trec;      // per sorted target position
     const WinBound *vb;    // per target instance
+    const CNode4 *nodes4;  // four-child forms of the copies' nodes (nullptr: binary descent)
+    const WinFrame *frames;  // per copy: the quantisation frame of nodes4
     int32_t win;           // steps per copy (>= 2)
     int32_t m;             // steps of the launch
     int64_t n;             // target rows (element of row j at step s: s n + j)
@@ -342,6 +370,15 @@ void launch_inst_roots(const BeamDev &b, const CloudBox &cloud, double dt, const
                        const uint32_t *sorted_rows, int32_t *inst_root, PBox *root_box,
                        const DevCounters *c, hipStream_t st, int32_t win = 1,
                        TRec *trec = nullptr);
+// Quantisation frame of each of the window_copies(m, win) copies of a batch of m steps
+// from the first step (device counter) and the per-instance statistics.
+void launch_win_frames(const InstStats *stats, int32_t n_inst, double dt, int32_t win, int32_t m,
+                       const DevCounters *c, WinFrame *frames, hipStream_t st);
+// Four-child forms of the copies x (n - 1) internal nodes (n rows) of window copies, in their
+// copies' frames; a child box outside its frame, or children that are not a split and its
+// successor, set kErrInternal.
+void launch_collapse4(const Node *nodes, int64_t n, int32_t copies, const WinFrame *frames,
+                      CNode4 *out, unsigned int *err, hipStream_t st);
 // Per-instance bounds of u dt of a target beam from its statistics (window copies).
 void launch_win_bounds(const InstStats *stats, int32_t n_inst, double dt, WinBound *vb,
                        hipStream_t st);

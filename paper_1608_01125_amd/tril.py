@@ -140,7 +140,7 @@ EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats"
            "tril_reset_counters", "tril_destroy", "tril_strerror", "tril_last_hip_error",
            "tril_dbg_sort_u32", "tril_dbg_sort_u64", "tril_dbg_morton", "tril_dbg_pair_eval",
            "tril_dbg_pair_eval32", "tril_dbg_math",
-           "tril_dbg_tree", "tril_dbg_target_records", "tril_dbg_boxes", "tril_dbg_target_rows", "tril_dbg_query_records", "tril_dbg_candidates")
+           "tril_dbg_tree", "tril_dbg_target_records", "tril_dbg_quad_nodes", "tril_dbg_boxes", "tril_dbg_target_rows", "tril_dbg_query_records", "tril_dbg_candidates")
 
 _lib = None
 
@@ -220,6 +220,7 @@ def lib() -> ctypes.CDLL:
     L.tril_dbg_math.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp]
     L.tril_dbg_tree.argtypes = [vp, vp, i64, _i64p, _i32p]
     L.tril_dbg_target_records.argtypes = [vp, vp, i64, _i64p, _i32p]
+    L.tril_dbg_quad_nodes.argtypes = [vp, vp, i64, _i64p, ctypes.POINTER(ctypes.c_float), _i32p]
     L.tril_st_audit.argtypes = [vp, vp, ctypes.POINTER(tril_beam), vp, vp, gp,
                                 ctypes.POINTER(tril_beam), vp, vp, gp, i32, i32,
                                 ctypes.POINTER(tril_st_sur_params),
@@ -783,7 +784,25 @@ def tril_dbg_tree(ctx, n_target: int, n_inst: int = 1, m: int = 1):
     nodes = nodes[: nn.value].reshape(-1, 2, 8)
     ints = nodes.view(np.int32)
     return {"lo": nodes[:, :, 0:3].copy(), "hi": nodes[:, :, 4:7].copy(),
-            "link": ints[:, :, 3].copy(), "roots": roots[: copies * n_inst], "copies": copies}
+            "link": ints[:, :, 3].copy(), "e": nodes[:, :, 7].copy(),
+            "roots": roots[: copies * n_inst], "copies": copies}
+
+
+def tril_dbg_quad_nodes(ctx, n_target: int, m: int):
+    """Four-child forms of the last build's window copies: (nodes (k, 16) uint32, frames
+    (copies, 8) float32), or (None, None) without them."""
+    ctx = _h(ctx)
+    cap = max(m * (n_target - 1), 1)
+    nodes = np.zeros((cap, 16), dtype=np.uint32)
+    frames = np.zeros((max(m, 1), 8), dtype=np.float32)
+    nn = ctypes.c_int64(0)
+    nc = ctypes.c_int32(0)
+    _check(lib().tril_dbg_quad_nodes(ctx, nodes.ctypes.data, cap, ctypes.byref(nn),
+                                     frames.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                     ctypes.byref(nc)), "tril_dbg_quad_nodes")
+    if nc.value == 0:
+        return None, None
+    return nodes[: nn.value].copy(), frames[: nc.value].copy()
 
 
 def tril_dbg_target_records(ctx, n_target: int):

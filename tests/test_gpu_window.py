@@ -226,3 +226,76 @@ def test_repeated_runs_identical(torch):
             ctx.close()
         assert len(seen) == 1, (win, sb, seen)
         assert next(iter(seen))[2] > 1000
+
+
+def _unpack_slots(w):
+    """Cell boxes (lo, hi: (k, 4, 3)), first-child ids (k, 4), leaf flags and energies of the
+    four-child forms (words as tril_dbg_quad_nodes gives them)."""
+    w = w.astype(np.int64)
+    lo = np.zeros((len(w), 4, 3), np.int64)
+    hi = np.zeros((len(w), 4, 3), np.int64)
+    for k in range(4):
+        a0, a1, a2 = w[:, 3 * k], w[:, 3 * k + 1], w[:, 3 * k + 2]
+        lo[:, k] = np.stack([a0 & 0xFFFF, a0 >> 16, a1 & 0xFFFF], axis=1)
+        hi[:, k] = np.stack([a1 >> 16, a2 & 0xFFFF, a2 >> 16], axis=1)
+    ids = np.stack([w[:, 12], w[:, 12] + 1, w[:, 13], w[:, 13] + 1], axis=1)
+    eh = np.stack([w[:, 14] & 0xFFFF, w[:, 14] >> 16, w[:, 15] & 0xFFFF, w[:, 15] >> 16], axis=1)
+    leaf = (eh >> 15) & 1
+    e = ((eh & 0x7FFF) << 16).astype(np.uint32).view(np.float32)
+    return lo, hi, ids, leaf, e
+
+
+@pytest.mark.parametrize("m,win", [(40, 16), (5, 2)])
+def test_four_child_forms_hold_the_copies(torch, m, win):
+    """The four-child forms the traversal descends: each node's slots are its grandchildren
+    in the FP32 tree (or a leaf child and an empty slot), each slot's 16-bit cell box holds the
+    grandchild's FP32 box in its copy's frame with no coordinate cut by the frame, and the
+    15-bit energy bounds are not below the FP32 ones."""
+    parts = []
+    for k, n_k in enumerate([1700, 1, 0, 900, 2]):
+        wl = beams.gauss_headon_1m(n=max(n_k, 1), seed=60 + k)
+        parts.append(beams.head(beams.draw_pair(wl)[1], n_k))
+    Bc, off = beams.concat(parts)
+    n, n_inst = len(Bc["E"]), len(off) - 1
+    wl = beams.gauss_headon_1m(n=1000)
+    ctx = T.Context(wl.dt, step_batch=m, kinetic_window=win)
+    try:
+        tb = T.Beam(Bc, off)
+        pairs = T.Pairs(1 << 12)
+        ctx.run(tb, tb, 170, m, pairs)
+        tree = T.tril_dbg_tree(ctx, n, n_inst, m)
+        q, frames = T.tril_dbg_quad_nodes(ctx, n, m)
+    finally:
+        ctx.close()
+    copies = tree["copies"]
+    n_int = n - 1
+    assert q.shape == (copies * n_int, 16) and frames.shape == (copies, 8)
+    lo, hi, ids, leaf, e = _unpack_slots(q)
+    link = tree["link"].astype(np.int64)
+    cp = np.repeat(np.arange(copies), n_int)
+    cbase = cp * n_int
+    # expected slots from the FP32 tree: grandchildren, or a leaf child and an empty slot
+    for side in (0, 1):
+        ch = link[:, side]
+        internal = ch >= 0
+        s0, s1 = 2 * side, 2 * side + 1
+        gi = np.where(internal, ch, 0)
+        want_link0 = np.where(internal, link[gi, 0], ch)
+        want_link1 = np.where(internal, link[gi, 1], 0)
+        for s, want, valid in ((s0, want_link0, np.ones(len(ch), bool)), (s1, want_link1, internal)):
+            got = np.where(leaf[:, s] == 1, -2 - ids[:, s], cbase + ids[:, s])
+            assert np.array_equal(got[valid], want[valid]), (side, s)
+            flo = np.where(internal[:, None], tree["lo"][gi, s - 2 * side], tree["lo"][:, side])
+            fhi = np.where(internal[:, None], tree["hi"][gi, s - 2 * side], tree["hi"][:, side])
+            fe = np.where(internal, tree["e"][gi, s - 2 * side], tree["e"][:, side])
+            if s == s1:  # a leaf child leaves its second slot empty
+                assert np.all(lo[~internal, s] > hi[~internal, s])
+                assert np.all(e[~internal, s] == 0)
+            fb = frames[cp, 0:3].astype(np.float64)
+            fi = frames[cp, 4:7].astype(np.float64)
+            full = valid & (flo <= fhi).all(axis=1)
+            a = (flo.astype(np.float64) - fb) * fi
+            b = (fhi.astype(np.float64) - fb) * fi
+            assert np.all(lo[full, s] <= a[full]) and np.all(hi[full, s] >= b[full])
+            assert np.all(a[full] >= -1.0) and np.all(b[full] <= 65536.0)
+            assert np.all(e[valid, s] >= fe[valid])
