@@ -44,14 +44,16 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "traverse_gauss_headon_1m_pmc.txt")
 
 
 def traverse_source_hash() -> str:
-    """Hash of the traversal kernel's source and of the node and box layouts it reads."""
+    """Hash of the traversal kernel's source and of what it reads from the shared header:
+    node, box and record layouts, the moved-box bound and the window-copy slack."""
     h = hashlib.sha256()
     with open(os.path.join(ROOT, TRAVERSE_SOURCES[0]), "rb") as f:
         h.update(f.read())
     with open(os.path.join(ROOT, TRAVERSE_SOURCES[1]), "rb") as f:
         text = f.read().decode()
     a = text.index("struct alignas(16) Half")
-    b = text.index("static_assert(sizeof(PBox)")
+    b = text.index("__device__ __forceinline__ float wslack")
+    b = text.index("\n}", b)
     h.update(text[a:b].encode())
     return h.hexdigest()[:16]
 
@@ -98,6 +100,23 @@ def tree_window(tune, arg: int) -> int:
     """Steps per tree copy in step batches (the library's default for 0)."""
     w = (tune or {}).get("kinetic_window", arg) or arg
     return 16 if w == 0 else w
+
+
+def descent_window(tune, arg: int, win: int) -> int:
+    """Steps per descent of a copy with four-child forms (the library's default for 0)."""
+    d = (tune or {}).get("descent_window", arg) or arg
+    return min(8 if d == 0 else d, win, 32)
+
+
+def descents(b: int, win: int, dwin: int) -> int:
+    """Descents per query row in a batch of b steps: one per step without window copies,
+    else every copy's steps split into descents of dwin steps (the library's count)."""
+    if win <= 1 or b < 2:
+        return b
+    w = min(win, b)
+    copies = -(-b // w)
+    last = b - (copies - 1) * w
+    return (copies - 1) * -(-w // dwin) + -(-last // dwin)
 
 
 def make_workload(name: str, physics_steps: int):
@@ -590,6 +609,8 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--kinetic-window", type=int, default=0,
                     help="steps per copy of the target hierarchy (0 = automatic, 1 = per step)")
+    ap.add_argument("--descent-window", type=int, default=0,
+                    help="steps per descent of a hierarchy copy (0 = automatic)")
     ap.add_argument("--st-mp", type=int, default=200_000,
                     help="st_headon: macro-particles per beam")
     ap.add_argument("--st-train", type=int, default=8, help="st_headon: training instances")
@@ -658,7 +679,8 @@ def main():
     def timed(flags):
         """Warm-up runs, then args.steps timed collision runs; returns (seconds, stats)."""
         ctx = T.Context(wl.dt, edges, flags=flags, block_traverse=args.block,
-                        step_batch=args.step_batch, kinetic_window=args.kinetic_window)
+                        step_batch=args.step_batch, kinetic_window=args.kinetic_window,
+                        descent_window=args.descent_window)
         if tune is not None:
             T.tril_set_tune(ctx.h, tune)
         pairs = T.Pairs(max(1 << 20, 4 * min(nA, nB)))
@@ -688,7 +710,8 @@ def main():
     tune = None
     if args.traverse_queue:
         tune = {"block_traverse": args.block or 64, "step_batch": args.step_batch,
-                "morton_bits": 0, "traverse_queue": 1, "kinetic_window": args.kinetic_window}
+                "morton_bits": 0, "traverse_queue": 1, "kinetic_window": args.kinetic_window,
+                "descent_window": args.descent_window}
     if args.autotune:
         from paper_1608_01125_amd import autotune
         probe_ctx = T.Context(wl.dt, edges)
@@ -756,10 +779,11 @@ def main():
         # per launch, divided by the average launch duration from HIP events recorded
         # around every traversal launch on the library's stream.
         # HBM roof: the bytes the method must fetch from memory at least once: per
-        # query-step its order entry and its row's record (4 + 48 B; 4 + 32 B box when every
-        # step is its own launch), every copy of the tree read once (64 B per internal node;
-        # a copy per step, or per window of steps), with window copies every target record
-        # once per launch (48 B), 8 B per candidate written.
+        # descent of a query row its order entry and its record (4 + 48 B; 4 + 32 B box
+        # when every step is its own launch; a descent per step, or per descent window of
+        # a copy's steps), every copy of the tree read once (64 B per internal node; a copy
+        # per step, or per window of steps), with window copies every target record once
+        # per launch (48 B), 8 B per candidate written.
         q_bytes = 52.0 if (steps_per_dispatch or 1) >= 2 else 36.0
         n_inst = 1 if offB is None else len(offB) - 1
         n_int_step = max(nB - n_inst, 0)
@@ -767,15 +791,18 @@ def main():
         runs = max(st["n_collides"] // max(n_steps, 1), 1)
         batches = batch_sizes(n_steps, launches_per_run)
         win = tree_window(tune, args.kinetic_window)
+        dwin = descent_window(tune, args.descent_window, win)
         copies = sum(b if (win <= 1 or b < 2) else -(-b // win) for b in batches) * runs
+        n_desc = sum(descents(b, win, dwin) for b in batches) * runs
         rec_bytes = 48.0 * nB * sum(1 for b in batches if win > 1 and b >= 2) * runs
-        hbm_bytes = (q_bytes * nA * st["n_collides"] + 64.0 * n_int_step * copies + rec_bytes
+        hbm_bytes = (q_bytes * nA * n_desc + 64.0 * n_int_step * copies + rec_bytes
                      + 8.0 * st["n_candidates"])
         # vector-memory roof: the bytes the kernel's loads deliver to its lanes, every node
-        # load counted (64 B: both children's boxes and links) and every leaf record read
-        # (48 B), plus the query bytes and candidate stores above
-        lane_bytes = (q_bytes * nA * st["n_collides"] + 64.0 * st["n_node_visits"]
-                      + 48.0 * st["n_leaf_checks"] + 8.0 * st["n_candidates"])
+        # load counted (64 B: all four slots' boxes, ids and bounds) and every leaf test
+        # (96 B: the target's record and the query's, read again), plus the query bytes and
+        # candidate stores above
+        lane_bytes = (q_bytes * nA * n_desc + 64.0 * st["n_node_visits"]
+                      + 96.0 * st["n_leaf_checks"] + 8.0 * st["n_candidates"])
         pmc = committed_counters(launches_per_run or None, win)
         traffic = pmc.get("traffic_bytes_per_dispatch")
         avg_s = st["ms_traverse"] * 1e-3 / n_launch
@@ -791,6 +818,7 @@ def main():
                                      if traffic else None),
                     "node_visits_per_query": round(st["n_node_visits"] / max(st["n_queries"], 1), 3),
                     "tree_copies_per_run": copies // runs, "kinetic_window": win,
+                    "descent_window": dwin, "descents_per_row_per_run": n_desc // runs,
                     "leaf_checks_per_query": round(st["n_leaf_checks"] / max(st["n_queries"], 1), 5)}
         # vector-memory roof: every lane's node load returns through the CU's texture data
         # unit (TD), one unit per CU at the 2.4 GHz clock; its busy cycles per launch come

@@ -137,6 +137,12 @@ typedef struct {
                                      at the leaf's own box of the query's step. Plain regime
                                      only; the candidates, and so the results, do not depend
                                      on it. */
+    int32_t descent_window;       /* tril_run batches with window copies: steps served by one
+                                     descent of a copy, 0..32 (0 = automatic: 8), at most the
+                                     copy's steps. The descent tests internal nodes with the
+                                     hull of the widened boxes of its first and last steps,
+                                     and every leaf that passes at the leaf's own boxes of
+                                     each of its steps. The results do not depend on it. */
 } tril_params;
 
 /* Caller-owned pair buffer. tril_collide appends raw hits (i, j, step) at
@@ -300,7 +306,8 @@ typedef struct {
                                      1024 queries from device-wide work queues */
     int32_t kinetic_window;       /* steps per copy of the target hierarchy, as in
                                      tril_params (0 = automatic, 1 = per step) */
-    int32_t pad0;
+    int32_t descent_window;       /* steps per descent of a copy, 0..32, as in tril_params
+                                     (0 = automatic) */
     double ms_per_step;           /* tril_autotune: measured time per step of the best
                                      configuration (output; ignored by tril_set_tune) */
 } tril_tune;
@@ -309,7 +316,8 @@ typedef struct {
  * launch configurations and keep the fastest in the context (and in *best). Coordinate
  * descent: steps per launch (1 .. 128, within 2^27 photon-steps per launch, or within the
  * default batch budget where that is larger), then the
- * steps per hierarchy copy (1, 4, 8, 16, 32), then the
+ * steps per hierarchy copy (1, 4, 8, 16, 32), then the steps per descent (4, 8, 16, 32,
+ * with copies of several steps), then the
  * traversal workgroup size (64 .. 512), then the Morton bits (automatic or 30), then the
  * persistent work-queue traversal against the flat grid. Every
  * configuration runs twice (the first run captures its graphs and sizes the scratch);

@@ -101,6 +101,7 @@ struct tril_ctx {
     int trav_queue = 0;             // traversal as a persistent work queue (tril_tune)
     int32_t step_batch = 0;         // steps per launch in tril_run (0 = automatic)
     int32_t kwin = 0;               // steps per tree copy in batches (0 = automatic, 1 = per step)
+    int32_t kdesc = 0;              // steps per four-child descent (0 = automatic)
     int morton_param = 0;           // Morton bits requested (0 = automatic)
     CloudBox cloud{0, {0.0, 0.0, 0.0}};  // box kind of the builds (statistical regime: clouds)
     double *st_slots = nullptr;     // statistical regime: per-wave yield sums (kCounterSlots)
@@ -508,6 +509,14 @@ int32_t build_window(const tril_ctx *c, int32_t m) {
     return w < m ? w : m;
 }
 
+// Steps per descent over the four-child forms of copies of win steps: at most win and
+// kMaxDescent.
+constexpr int32_t kDefaultDescent = 8;
+int32_t descent_window(const tril_ctx *c, int32_t win) {
+    const int32_t d = c->kdesc > 0 ? c->kdesc : kDefaultDescent;
+    return std::min(std::min(d, win), kMaxDescent);
+}
+
 // Kernels of one build on stream st (target view, with its step count m, in c->tgt;
 // the target statistics c->t_stats are current): boxes of every step, one sort of the
 // rows by their Morton codes at the batch's key step, the tree shape emitted from that
@@ -665,6 +674,7 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
         wa.m = q.m;
         wa.n = c->tgt.n;
         wa.reach = (float)((double)(q.m + c->win_eff + 8) * c->dt + 1e-6);
+        wa.dwin = descent_window(c, c->win_eff);
     }
     if (timed) CHK(timing_pair(c, st, c->ev_prep, false));
     if (timed) CHK(timing_pair(c, st, c->ev_trav, true));
@@ -894,7 +904,8 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
     if (!out || !p) return TRIL_E_INVAL;
     *out = nullptr;
     if (!std::isfinite(p->dt) || !(p->dt > 0.0)) return TRIL_E_INVAL;
-    if (p->n_bins < 0 || p->cand_cap < 0 || p->step_batch < 0 || p->kinetic_window < 0)
+    if (p->n_bins < 0 || p->cand_cap < 0 || p->step_batch < 0 || p->kinetic_window < 0 ||
+        p->descent_window < 0 || p->descent_window > kMaxDescent)
         return TRIL_E_INVAL;
     if (p->morton_bits != 0 && (p->morton_bits < 3 || p->morton_bits > 30)) return TRIL_E_INVAL;
     if (p->flags &
@@ -921,6 +932,7 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
     c->block = blk;
     c->step_batch = p->step_batch;
     c->kwin = p->kinetic_window;
+    c->kdesc = p->descent_window;
     c->morton_param = p->morton_bits;
     c->sigma_up = host_sigma_max() * (1.0 + 1e-6);
     int r = TRIL_OK;
@@ -1014,16 +1026,17 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     const int32_t m = pick_batch(c, t, q, n_steps);
     // capacities for the largest batch first, so that nothing is reallocated later
     CHK(ensure_target(c, (int64_t)m * t->n, t->n, (int64_t)m * t->n_inst, t->n_inst));
-    if (build_window(c, m) > 1 && t->n > 1) {  // four-child forms of the window copies
-        const int64_t need = (int64_t)window_copies(m, build_window(c, m)) * (t->n - 1);
+    const int32_t bw = build_window(c, m);
+    if (bw > 1 && t->n > 1) {  // four-child forms of the window copies
+        const int64_t need = (int64_t)window_copies(m, bw) * (t->n - 1);
         if (need > c->nodes4_cap) {
             ++c->alloc_gen;
-            dev_free(c->nodes4); dev_free(c->t_frames);
+            dev_free(c->nodes4);
             c->nodes4_cap = 0;
             CHK(dev_alloc(&c->nodes4, (size_t)need));
             c->nodes4_cap = need;
         }
-        const int32_t nf = window_copies(m, build_window(c, m));
+        const int32_t nf = window_copies(m, bw);
         if (nf > c->frames_cap) {
             ++c->alloc_gen;
             dev_free(c->t_frames);
@@ -1158,7 +1171,8 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
                 // every launch parameter read while the batch is captured
                 (const void *)(intptr_t)c->block, (const void *)(uintptr_t)c->flags,
                 (const void *)(intptr_t)c->trav_queue,
-                (const void *)(intptr_t)c->cand_cap, (const void *)(intptr_t)c->kwin};
+                (const void *)(intptr_t)c->cand_cap, (const void *)(intptr_t)c->kwin,
+                (const void *)(intptr_t)c->kdesc};
             int slot = (c->gexec[0] && key == c->gkey[0]) ? 0
                        : (c->gexec[1] && key == c->gkey[1]) ? 1 : -1;
             if (slot < 0) {
@@ -2389,9 +2403,11 @@ int tril_set_tune(tril_ctx *c, const tril_tune *tu) {
     if (tu->morton_bits != 0 && (tu->morton_bits < 3 || tu->morton_bits > 30)) return TRIL_E_INVAL;
     if (tu->traverse_queue != 0 && tu->traverse_queue != 1) return TRIL_E_INVAL;
     if (tu->kinetic_window < 0) return TRIL_E_INVAL;
+    if (tu->descent_window < 0 || tu->descent_window > kMaxDescent) return TRIL_E_INVAL;
     c->block = blk;
     c->trav_queue = tu->traverse_queue;
     c->kwin = tu->kinetic_window;
+    c->kdesc = tu->descent_window;
     c->step_batch = tu->step_batch;
     c->morton_param = tu->morton_bits;
     return TRIL_OK;
@@ -2428,13 +2444,14 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
     }
     c->flags &= ~TRIL_TIMING;  // time graph replays, as a run without per-phase events
     const int64_t rows = std::max<int64_t>(std::max(t->n, q->n), 1);
-    int cur_queue = 0, cur_win = 0;
+    int cur_queue = 0, cur_win = 0, cur_desc = 0;
     auto probe = [&](int blk, int sb, int mb, double &ms) -> int {
         c->block = blk;
         c->step_batch = sb;
         c->morton_param = mb;
         c->trav_queue = cur_queue;
         c->kwin = cur_win;
+        c->kdesc = cur_desc;
         for (int rep = 0; rep < 2; ++rep) {
             HIPCHK(hipMemsetAsync(pr.count, 0, sizeof(int64_t), c->st));
             HIPCHK(hipEventRecord(e0, c->st));
@@ -2477,6 +2494,17 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
         }
         cur_win = cur.kinetic_window;
     }
+    for (int d : {4, 16, 32}) {  // steps per four-child descent (0: the default, 8)
+        if (rc != TRIL_OK || cur.step_batch == 1 || cur.kinetic_window == 1) break;
+        double ms = 0.0;
+        cur_desc = d;
+        if ((rc = probe(cur.block_traverse, cur.step_batch, cur.morton_bits, ms)) != TRIL_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            cur.descent_window = d;
+        }
+        cur_desc = cur.descent_window;
+    }
     for (int blk : {64, 128, 512}) {
         if (rc != TRIL_OK) break;
         double ms = 0.0;
@@ -2511,6 +2539,7 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
     c->morton_param = cur.morton_bits;
     c->trav_queue = cur.traverse_queue;
     c->kwin = cur.kinetic_window;
+    c->kdesc = cur.descent_window;
     *best = cur;
     return tril_reset_counters(c);
 }

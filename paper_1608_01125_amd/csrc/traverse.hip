@@ -30,6 +30,13 @@
 // (wslack), and a leaf that passes against the leaf's own box at step s, formed from the
 // leaf's record as the per-step refit would form it: the candidates are those of per-step
 // copies.
+//
+// With four-child forms a query descends each window copy once for all the window's steps:
+// its box is the hull of the widened boxes of the window's first and last steps, which
+// holds the widened box of every step between them (below), and a leaf that passes is
+// tested against the query's exact box at every step of the window, each hit a candidate
+// of that step. The candidates are again those of per-step copies, found with one descent
+// and one query record read per window instead of one per step.
 #include "tril_internal.h"
 
 namespace tril {
@@ -98,11 +105,99 @@ __device__ __forceinline__ bool leaf_exact(const WinArgs &wa, int64_t j, int32_t
            (qb[2] <= hi[2]) & (qb[5] >= lo[2]) & (qe * d.w >= kPruneProduct);
 }
 
+// One descent per window: the steps s0 + t (t < len, bit t of the result) at which target
+// leaf j's box meets the box of query row `row` (both formed from their records as the
+// per-step paths form them; closed test), and the threshold prune, which does not depend on
+// the step; trow receives the leaf's target row.
+//
+// Only the steps of an interval are tested. On each axis the two boxes at step s are the
+// offset-0 boxes moved by s v (v: each one's motion per step), each widened by its rounding
+// bound, at most 2^-19 (|lo| + w + s |v|) (moved_box), so they can meet only where
+// s (vq - vl) lies in [(ll - lq) - wq - g, (ll - lq) + wl + g] with g = 2^-17 (|lq| + |ll| +
+// wq + wl + s1 (|vq| + |vl|)), more than twice the sum of the two bounds and the FP32 error
+// of forming the interval ends. Solving for s, each end moved outward by a step past its
+// FP32 quotient, gives a range of steps that holds every step the exact test can accept.
+__device__ __forceinline__ uint32_t leaf_steps(const WinArgs &wa, int64_t j,
+                                               const QRec *__restrict__ qrec, int32_t row,
+                                               int32_t s0, int32_t len, float qe, int32_t &trow) {
+    // the step range from both records in one round of loads; the exact test one axis at a
+    // time from single-word loads again (the records' words x, y, z of lo, d and w sit at
+    // 4 k, 16 + 4 k and 32 + 4 k bytes), so that few registers are live beside the descent's
+    const float *tf = reinterpret_cast<const float *>(wa.trec + j);
+    const float *qf = reinterpret_cast<const float *>(qrec + row);
+    const float4 ta = reinterpret_cast<const float4 *>(tf)[0];
+    const float4 td = reinterpret_cast<const float4 *>(tf)[1];
+    const float4 tw = reinterpret_cast<const float4 *>(tf)[2];
+    const float4 qa = reinterpret_cast<const float4 *>(qf)[0];
+    const float4 qd = reinterpret_cast<const float4 *>(qf)[1];
+    const float4 qw = reinterpret_cast<const float4 *>(qf)[2];
+    trow = __float_as_int(ta.w);
+    if (!(qe * td.w >= kPruneProduct)) return 0u;
+    const float s1 = (float)(s0 + len - 1);
+    float tlo = (float)s0, thi = s1;
+    const float lqs[3] = {qa.x, qa.y, qa.z}, vqs[3] = {qd.x, qd.y, qd.z};
+    const float wqs[3] = {qw.x, qw.y, qw.z}, lls[3] = {ta.x, ta.y, ta.z};
+    const float vls[3] = {td.x, td.y, td.z}, wls[3] = {tw.x, tw.y, tw.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float lq = lqs[k], vq = vqs[k], wq = wqs[k];
+        const float ll = lls[k], vl = vls[k], wl = wls[k];
+        const float g = (((fabsf(lq) + fabsf(ll)) + (wq + wl)) + s1 * (fabsf(vq) + fabsf(vl))) *
+                        0x1p-17f;
+        const float dd = ll - lq;
+        const float lo = (dd - wq) - g, hi = (dd + wl) + g;
+        const float rel = vq - vl;
+        if (rel == 0.0f) {
+            if (!((lo <= 0.0f) & (hi >= 0.0f))) thi = -1.0f;
+        } else {
+            const float a1 = lo / rel, a2 = hi / rel;
+            // infinite quotients clamp to the window; the comparisons keep it otherwise
+            tlo = fmaxf(tlo, floorf(fminf(a1, a2)) - 1.0f);
+            thi = fminf(thi, ceilf(fmaxf(a1, a2)) + 1.0f);
+        }
+    }
+    if (!(tlo <= thi)) return 0u;
+    // the exact test of every step of the range: the steps at which every axis meets
+    const int32_t t0 = (int32_t)tlo - s0, t1 = (int32_t)thi - s0;
+    uint32_t mask = (t1 >= 31 ? 0xFFFFFFFFu : (2u << t1) - 1u) & ~((1u << t0) - 1u);
+#pragma unroll 1
+    for (int k = 0; k < 3; ++k) {
+        const float lq = qf[k], vq = qf[4 + k], wq = qf[8 + k];
+        const float ll = tf[k], vl = tf[4 + k], wl = tf[8 + k];
+        for (int32_t t = t0; t <= t1; ++t) {
+            const float s = (float)(s0 + t);
+            float ql, qh, tl, th;
+            moved_axis(lq, vq, wq, s, ql, qh);
+            moved_axis(ll, vl, wl, s, tl, th);
+            if (!((ql <= th) & (qh >= tl))) mask &= ~(1u << t);
+        }
+    }
+    return mask;
+}
+
+// Appends one candidate per set bit t of mask: query row `row` and target row trow at step
+// s0 + t (elements s nq_base + row and s n + trow). Called by every active lane of the wave.
+__device__ __forceinline__ void emit_steps(uint32_t mask, int32_t row, int32_t trow, int32_t s0,
+                                           int64_t nq_base, int64_t n,
+                                           int32_t *__restrict__ cand_i,
+                                           int32_t *__restrict__ cand_j, int64_t cand_cap,
+                                           DevCounters *c) {
+    for (;;) {
+        const bool has = mask != 0u;
+        if (__ballot(has) == 0ull) break;
+        const int32_t s = s0 + (has ? __builtin_ctz(mask) : 0);
+        mask &= mask - 1u;
+        emit_candidate(has, (int32_t)(s * nq_base + row), (int64_t)s * n + trow, cand_i, cand_j,
+                       cand_cap, c);
+    }
+}
+
 // The descent of virtual query q (q >= nq: an idle lane that still takes part in the
 // wave's ballots); adds its node loads to visits (and, over window copies, its leaf
-// record loads to checks) and returns whether it had a root.
+// record loads to checks) and returns the number of query steps it stood for: 0 without a
+// root, else 1, or with four-child forms the steps of its window.
 template <bool kRec, bool kWin, bool kQuad>
-__device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict__ nodes,
+__device__ __forceinline__ int32_t traverse_query(int64_t q, const Node *__restrict__ nodes,
                                                int32_t n_int, const PBox *__restrict__ root_box,
                                                const PBox *__restrict__ qbox,
                                                const QRec *__restrict__ qrec, int32_t n_inst,
@@ -118,8 +213,96 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
     float qw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // window copies: the widened box
     int32_t qc[6] = {0, 0, 0, 0, 0, 0};  // four-child forms: the widened box in frame cells
     int32_t cbase = 0;                   // four-child forms: first node of the query's copy
+    int32_t qn = 1;                      // four-child forms: the steps of the query's window
     float qe = 0.f;
-    if (q < nq) {
+    if (kQuad && q < nq) {
+        // virtual query q: descent k = q / nq_base (steps qs .. qs + qn - 1, part sub of
+        // copy cp, whose descents are nd each but for the last copy's) and the row at
+        // position q - k nq_base of the step order; qi holds the row
+        const int64_t kd = q / nq_base;
+        const int64_t t = q - kd * nq_base;
+        const int32_t nd = (wa.win + wa.dwin - 1) / wa.dwin;
+        const int32_t cp = (int32_t)(kd / nd);
+        const int32_t sub = (int32_t)(kd - (int64_t)cp * nd);
+        qi = (int32_t)(qorder == nullptr ? t : qorder[t]);
+        const float4 *rp = reinterpret_cast<const float4 *>(qrec + qi);
+        const float4 a = rp[0], d = rp[1], w = rp[2];
+        const int32_t inst = __float_as_int(a.w);
+        if (inst >= 0) {
+            qs = cp * wa.win + sub * wa.dwin;
+            qn = min(wa.dwin, min(wa.win, wa.m - cp * wa.win) - sub * wa.dwin);
+            const int32_t r = window_ref_step(cp, wa.win, wa.m);
+            // the widened boxes of the first and last steps (box at the step, less the
+            // instance's motion over s - r, less the slack). In exact arithmetic the low side
+            // of a step's box less the motion is concave in the step (a line, less the
+            // rounding bound's |lo| + |hi| and the motion's max(d lo, d hi), both convex) and
+            // the high side convex, so the hull of the two ends holds every step's. The slack
+            // is taken with the larger coordinates of the two boxes, which bound those of
+            // every step between them: it is twice the rounding bound of any step of the
+            // window, and the half to spare exceeds the FP32 error of the two ends' boxes.
+            float qa[6], qz[6];
+            record_box(a, d, w, (float)qs, qa);
+            record_box(a, d, w, (float)(qs + qn - 1), qz);
+            qe = d.w;
+            const float da = (float)(qs - r), dz = (float)(qs + qn - 1 - r);
+            float4 vlo, vhi;
+            const int32_t iu = __builtin_amdgcn_readfirstlane(inst);
+            if (__ballot(inst == iu) == __ballot(1)) {
+                typedef int v8i __attribute__((ext_vector_type(8)));
+                v8i rv;
+                const WinBound *p = wa.vb + iu;
+                asm volatile("s_load_dwordx8 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)"
+                             : "=s"(rv)
+                             : "s"(p));
+                vlo = make_float4(__int_as_float(rv[0]), __int_as_float(rv[1]),
+                                  __int_as_float(rv[2]), __int_as_float(rv[3]));
+                vhi = make_float4(__int_as_float(rv[4]), __int_as_float(rv[5]),
+                                  __int_as_float(rv[6]), __int_as_float(rv[7]));
+            } else {
+                const float4 *vp = reinterpret_cast<const float4 *>(wa.vb + inst);
+                vlo = vp[0];
+                vhi = vp[1];
+            }
+            float4 fb, fi;
+            const int32_t cu = __builtin_amdgcn_readfirstlane(cp);
+            if (__ballot(cp == cu) == __ballot(1)) {
+                typedef int v8i __attribute__((ext_vector_type(8)));
+                v8i rf;
+                const WinFrame *p = wa.frames + cu;
+                asm volatile("s_load_dwordx8 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)"
+                             : "=s"(rf)
+                             : "s"(p));
+                fb = make_float4(__int_as_float(rf[0]), __int_as_float(rf[1]),
+                                 __int_as_float(rf[2]), 0.0f);
+                fi = make_float4(__int_as_float(rf[4]), __int_as_float(rf[5]),
+                                 __int_as_float(rf[6]), 0.0f);
+            } else {
+                const float4 *fp = reinterpret_cast<const float4 *>(wa.frames + cp);
+                fb = fp[0];
+                fi = fp[1];
+            }
+            const float lo3[3] = {vlo.x, vlo.y, vlo.z}, hi3[3] = {vhi.x, vhi.y, vhi.z};
+            const float b3[3] = {fb.x, fb.y, fb.z}, i3[3] = {fi.x, fi.y, fi.z};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const float e1 = da * lo3[k], e2 = da * hi3[k];
+                const float f1 = dz * lo3[k], f2 = dz * hi3[k];
+                const float sl =
+                    wslack(fminf(qa[k], qz[k]), fmaxf(qa[k + 3], qz[k + 3]), wa.reach);
+                const float wl = fminf((qa[k] - fmaxf(e1, e2)) - sl, (qz[k] - fmaxf(f1, f2)) - sl);
+                const float wh = fmaxf((qa[k + 3] - fminf(e1, e2)) + sl,
+                                       (qz[k + 3] - fminf(f1, f2)) + sl);
+                // in the copy's frame cells (floor - 1, ceil + 1: the one-cell margins cover
+                // the FP32 rounding), kept within [-1, 65536]
+                const float lo = (wl - b3[k]) * i3[k];
+                const float hi = (wh - b3[k]) * i3[k];
+                qc[k] = (int32_t)fminf(fmaxf(floorf(lo) - 1.0f, -1.0f), 65536.0f);
+                qc[k + 3] = (int32_t)fminf(fmaxf(ceilf(hi) + 1.0f, -1.0f), 65536.0f);
+            }
+            cbase = cp * (int32_t)(wa.n - 1);
+            tag = cp * n_inst + inst;
+        }
+    } else if (q < nq) {
         if (qorder == nullptr) {
             qi = (int32_t)q;
         } else if (order_len == nq) {
@@ -170,37 +353,6 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
                         qw[k + 3] = (qb[k + 3] - fminf(e1, e2)) + sl;
                     }
                     tag = cp * n_inst + inst;
-                    if (kQuad) {
-                        // the widened box in the copy's frame cells (floor - 1, ceil + 1: the
-                        // one-cell margins cover the FP32 rounding), kept within [-1, 65536]
-                        const int32_t cu = __builtin_amdgcn_readfirstlane(cp);
-                        float4 fb, fi;
-                        if (__ballot(cp == cu) == __ballot(1)) {
-                            typedef int v8i __attribute__((ext_vector_type(8)));
-                            v8i r;
-                            const WinFrame *p = wa.frames + cu;
-                            asm volatile("s_load_dwordx8 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)"
-                                         : "=s"(r)
-                                         : "s"(p));
-                            fb = make_float4(__int_as_float(r[0]), __int_as_float(r[1]),
-                                             __int_as_float(r[2]), 0.0f);
-                            fi = make_float4(__int_as_float(r[4]), __int_as_float(r[5]),
-                                             __int_as_float(r[6]), 0.0f);
-                        } else {
-                            const float4 *fp = reinterpret_cast<const float4 *>(wa.frames + cp);
-                            fb = fp[0];
-                            fi = fp[1];
-                        }
-                        const float b3[3] = {fb.x, fb.y, fb.z}, i3[3] = {fi.x, fi.y, fi.z};
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            const float lo = (qw[k] - b3[k]) * i3[k];
-                            const float hi = (qw[k + 3] - b3[k]) * i3[k];
-                            qc[k] = (int32_t)fminf(fmaxf(floorf(lo) - 1.0f, -1.0f), 65536.0f);
-                            qc[k + 3] = (int32_t)fminf(fmaxf(ceilf(hi) + 1.0f, -1.0f), 65536.0f);
-                        }
-                        cbase = cp * (int32_t)(wa.n - 1);
-                    }
                 } else {
                     tag = (int32_t)(s * n_inst + inst);
                 }
@@ -213,22 +365,33 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
             qe = b.w;
             tag = __float_as_int(a.w);
         }
-        if (tag >= 0) {
-            // the root of the query's (step, instance) tree: a scalar load when the wave's
-            // queries share it (they nearly always do), else a vector load
-            const int32_t tu = __builtin_amdgcn_readfirstlane(tag);
-            if (__ballot(tag == tu) == __ballot(1)) {
-                int32_t r;
-                const int32_t *p = inst_root + tu;
-                asm volatile("s_load_dword %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p));
-                node = r;
-            } else {
-                node = inst_root[tag];
-            }
+    }
+    if (tag >= 0) {
+        // the root of the query's (step or copy, instance) tree: a scalar load when the
+        // wave's queries share it (they nearly always do), else a vector load
+        const int32_t tu = __builtin_amdgcn_readfirstlane(tag);
+        if (__ballot(tag == tu) == __ballot(1)) {
+            int32_t r;
+            const int32_t *p = inst_root + tu;
+            asm volatile("s_load_dword %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(r) : "s"(p));
+            node = r;
+        } else {
+            node = inst_root[tag];
         }
     }
     const bool active = node != -1;
-    {
+    if (kQuad) {
+        // an instance of one row: its root is that leaf
+        uint32_t mask = 0u;
+        int32_t trow = 0;
+        if (node <= -2) {
+            mask = leaf_steps(wa, link_elem(node), qrec, qi, qs, qn, qe, trow);
+            ++checks;
+            ++visits;
+            node = -1;
+        }
+        emit_steps(mask, qi, trow, qs, nq_base, wa.n, cand_i, cand_j, cand_cap, c);
+    } else {
         // an instance of one row: its root is that leaf
         bool hit = false;
         int64_t e = 0;
@@ -292,26 +455,12 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
                 const int32_t g = (int32_t)w[12 + (k >> 1)] + (k & 1);
                 lk[k] = (eh & 0x8000u) ? leaf_link(g) : cbase + g;
             }
-            // leaves: nothing to do in most visits of most waves (one ballot decides)
-            const bool any_leaf = (ov[0] & (lk[0] <= -2)) | (ov[1] & (lk[1] <= -2)) |
-                                  (ov[2] & (lk[2] <= -2)) | (ov[3] & (lk[3] <= -2));
-            if (__ballot(any_leaf) != 0ull)
+            // the next node and the pushes first, so that only the leaf slots' ids stay live
+            // through the leaf tests
+            uint32_t pend = 0u;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                bool e = ov[k] & (lk[k] <= -2);
-                int64_t j = link_elem(lk[k]);
-                if (e) {
-                    // the query's exact box, formed again from its record (kept out of the
-                    // registers the descent holds)
-                    float qx[6];
-                    const float4 *rp =
-                        reinterpret_cast<const float4 *>(qrec + (qi - (int64_t)qs * nq_base));
-                    record_box(rp[0], rp[1], rp[2], (float)qs, qx);
-                    e = leaf_exact(wa, j, qs, qx, qe, j);
-                    ++checks;
-                }
-                emit_candidate(e, qi, j, cand_i, cand_j, cand_cap, c);
-            }
+            for (int k = 0; k < 4; ++k) pend |= (uint32_t)(ov[k] & (lk[k] <= -2)) << k;
+            const uint32_t g0 = w[12], g2 = w[13];
             int32_t nxt = -1;
             bool full = false;
 #pragma unroll
@@ -345,8 +494,29 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
             } else {
                 node = -1;
             }
+            // leaves: nothing to do in most visits of most waves (one ballot decides); else
+            // rounds in which every lane with a leaf slot left tests one, as many rounds as
+            // the most such slots of a lane
+            if (__ballot(pend != 0u) != 0ull) {
+                for (;;) {
+                    const bool has = pend != 0u;
+                    if (__ballot(has) == 0ull) break;
+                    // the query's exact boxes at the window's steps are formed again from its
+                    // record (kept out of the registers the descent holds)
+                    uint32_t mask = 0u;
+                    int32_t trow = 0;
+                    if (has) {
+                        const uint32_t k = (uint32_t)__builtin_ctz(pend);
+                        pend &= pend - 1u;
+                        const int32_t g = (int32_t)((k & 2u) ? g2 : g0) + (int32_t)(k & 1u);
+                        mask = leaf_steps(wa, g, qrec, qi, qs, qn, qe, trow);
+                        ++checks;
+                    }
+                    emit_steps(mask, qi, trow, qs, nq_base, wa.n, cand_i, cand_j, cand_cap, c);
+                }
+            }
         }
-        return active;
+        return active ? qn : 0;
     }
     while (node >= 0) {
         if (visits > max_visits) {
@@ -425,17 +595,19 @@ __device__ __forceinline__ bool traverse_query(int64_t q, const Node *__restrict
             node = -1;
         }
     }
-    return active;
+    return active ? 1 : 0;
 }
 
-// Per-wave counter updates of a traversal workgroup's wave (lane 0 adds).
-__device__ __forceinline__ void add_counts(uint32_t visits, uint32_t checks,
-                                           unsigned long long n_active, DevCounters *c) {
-    unsigned long long v = visits, k = checks;
+// Per-wave counter updates of a traversal workgroup's wave (lane 0 adds): node loads, leaf
+// record loads and query steps of the wave's lanes.
+__device__ __forceinline__ void add_counts(uint32_t visits, uint32_t checks, uint32_t qsteps,
+                                           DevCounters *c) {
+    unsigned long long v = visits, k = checks, n_active = qsteps;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         v += __shfl_xor(v, off);
         k += __shfl_xor(k, off);
+        n_active += __shfl_xor(n_active, off);
     }
     if ((threadIdx.x & 63) == 0) {
         const int slot = blockIdx.x & (kCounterSlots - 1);
@@ -459,10 +631,10 @@ __global__ void __launch_bounds__(BLOCK, kQuad ? 8 : 1) k_traverse(const Node *_
                                                     DevCounters *c, WinArgs wa) {
     const int64_t q = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
     uint32_t visits = 0, checks = 0;
-    const bool act = traverse_query<kRec, kWin, kQuad>(q, nodes, n_int, root_box, qbox, qrec, n_inst,
-                                                qorder, order_len, nq, nq_base, inst_root, cand_i,
-                                                cand_j, cand_cap, c, visits, wa, checks);
-    add_counts(visits, checks, (unsigned long long)__popcll(__ballot(act)), c);
+    const int32_t qsteps = traverse_query<kRec, kWin, kQuad>(
+        q, nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq, nq_base, inst_root,
+        cand_i, cand_j, cand_cap, c, visits, wa, checks);
+    add_counts(visits, checks, (uint32_t)qsteps, c);
 }
 
 
@@ -491,8 +663,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse_queue(const Node *__restrict
                                                           WinArgs wa) {
     const int lane = threadIdx.x & 63;
     const int x = blockIdx.x & (kTravCursors - 1);
-    uint32_t visits = 0, checks = 0;
-    unsigned long long n_active = 0;
+    uint32_t visits = 0, checks = 0, qsteps = 0;
     for (;;) {
         unsigned long long k = 0;
         if (lane == 0) k = atomicAdd(&c->trav_next[x], 1ull);
@@ -501,13 +672,12 @@ __global__ void __launch_bounds__(BLOCK) k_traverse_queue(const Node *__restrict
         if (base >= nq) break;
         for (int sub = 0; sub < kQueueChunk; sub += 64) {
             if (base + sub >= nq) break;
-            const bool act = traverse_query<kRec, kWin, kQuad>(
+            qsteps += (uint32_t)traverse_query<kRec, kWin, kQuad>(
                 base + sub + lane, nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len,
                 nq, nq_base, inst_root, cand_i, cand_j, cand_cap, c, visits, wa, checks);
-            n_active += (unsigned long long)__popcll(__ballot(act));
         }
     }
-    add_counts(visits, checks, n_active, c);
+    add_counts(visits, checks, qsteps, c);
 }
 
 template <int BLOCK, bool kRec, bool kWin, bool kQuad>
@@ -537,10 +707,14 @@ void launch_traverse_b(const Node *nodes, int32_t n_int, const PBox *root_box, c
                        int32_t *cand_j, int64_t cand_cap, DevCounters *c, bool queue,
                        const WinArgs *win, hipStream_t st) {
     WinArgs wa = {};
-    if (qrec != nullptr && win != nullptr && win->nodes4 != nullptr) {
+    if (qrec != nullptr && win != nullptr && win->nodes4 != nullptr && win->dwin >= 1 &&
+        win->dwin <= kMaxDescent && win->dwin <= win->win &&
+        (qorder == nullptr || order_len == nq_base)) {
+        // one virtual query per (descent, row) of the one step order
         wa = *win;
+        const int64_t nq_win = descent_count(wa.m, wa.win, wa.dwin) * nq_base;
         launch_traverse_k<BLOCK, true, true, true>(nodes, n_int, root_box, qbox, qrec, n_inst,
-                                                   qorder, order_len, nq, nq_base, inst_root,
+                                                   qorder, order_len, nq_win, nq_base, inst_root,
                                                    cand_i, cand_j, cand_cap, c, queue, wa, st);
     } else if (qrec != nullptr && win != nullptr) {
         wa = *win;

@@ -76,6 +76,9 @@ struct alignas(16) CNode4 {
     uint32_t w[16];
 };
 static_assert(sizeof(CNode4) == 64, "four-child node layout");
+// Most steps of one descent over four-child forms: a descent serves consecutive steps of
+// one window copy and keeps a leaf's hits as one bit per step of a 32-bit mask.
+constexpr int32_t kMaxDescent = 32;
 __host__ __device__ inline int32_t leaf_link(int64_t e) { return (int32_t)(-2 - e); }
 __host__ __device__ inline int64_t link_elem(int32_t l) { return -2 - (int64_t)l; }
 
@@ -128,17 +131,21 @@ static_assert(sizeof(QRec) == 48, "query record layout");
 // than 2^-23 (|lo| + |hi| + s |d|), and the widening is four times that. The result
 // contains the box that the step's own FP64 computation rounds outward (whose 1e-12
 // relative slack grows by less than 1e-12 s |d| over the batch).
+// One axis of it (every axis is formed on its own).
+__device__ __forceinline__ void moved_axis(float lo0, float d, float w, float s, float &lo,
+                                           float &hi) {
+    const float l = fmaf(s, d, lo0);
+    const float h = l + w;
+    const float e = ((fabsf(l) + fabsf(h)) + s * fabsf(d)) * 0x1p-21f;
+    lo = l - e;
+    hi = h + e;
+}
 __device__ __forceinline__ void moved_box(float lox, float loy, float loz, float dx, float dy,
                                           float dz, float wx, float wy, float wz, float s,
                                           float lo[3], float hi[3]) {
-    const float lx = fmaf(s, dx, lox), ly = fmaf(s, dy, loy), lz = fmaf(s, dz, loz);
-    const float hx = lx + wx, hy = ly + wy, hz = lz + wz;
-    constexpr float k = 0x1p-21f;
-    const float ex = ((fabsf(lx) + fabsf(hx)) + s * fabsf(dx)) * k;
-    const float ey = ((fabsf(ly) + fabsf(hy)) + s * fabsf(dy)) * k;
-    const float ez = ((fabsf(lz) + fabsf(hz)) + s * fabsf(dz)) * k;
-    lo[0] = lx - ex; lo[1] = ly - ey; lo[2] = lz - ez;
-    hi[0] = hx + ex; hi[1] = hy + ey; hi[2] = hz + ez;
+    moved_axis(lox, dx, wx, s, lo[0], hi[0]);
+    moved_axis(loy, dy, wy, s, lo[1], hi[1]);
+    moved_axis(loz, dz, wz, s, lo[2], hi[2]);
 }
 
 // Window copies of a batch's hierarchy. Photons move on straight lines, so the box of a
@@ -191,7 +198,15 @@ struct WinArgs {
     int32_t m;             // steps of the launch
     int64_t n;             // target rows (element of row j at step s: s n + j)
     float reach;           // (m + win + 8) dt + 1e-6: the slack's length term (wslack)
+    int32_t dwin;          // four-child forms: steps per descent, 1 .. min(win, kMaxDescent)
 };
+// Four-child forms: descents of a batch of m steps in copies of win steps, each copy's
+// steps split into descents of dwin steps (the last one of a copy shorter).
+__host__ __device__ inline int64_t descent_count(int32_t m, int32_t win, int32_t dwin) {
+    const int32_t copies = window_copies(m, win);
+    const int32_t last = m - (copies - 1) * win;
+    return (int64_t)(copies - 1) * ((win + dwin - 1) / dwin) + (last + dwin - 1) / dwin;
+}
 
 // Slack of the widened query box on one axis (ql, qh: the query's box at step s). If a
 // leaf's box at step s (moved_box, every FP32 operation within 2^-24 relative) meets

@@ -47,7 +47,8 @@ class tril_params(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("flags", ctypes.c_uint32), ("n_bins", ctypes.c_int32),
                 ("bin_edges", _dp), ("cand_cap", ctypes.c_int64),
                 ("block_traverse", ctypes.c_int32), ("step_batch", ctypes.c_int32),
-                ("morton_bits", ctypes.c_int32), ("kinetic_window", ctypes.c_int32)]
+                ("morton_bits", ctypes.c_int32), ("kinetic_window", ctypes.c_int32),
+                ("descent_window", ctypes.c_int32)]
 
 
 class tril_pairs(ctypes.Structure):
@@ -71,7 +72,7 @@ class tril_stats_t(ctypes.Structure):
 class tril_tune(ctypes.Structure):
     _fields_ = [("block_traverse", ctypes.c_int32), ("step_batch", ctypes.c_int32),
                 ("morton_bits", ctypes.c_int32), ("traverse_queue", ctypes.c_int32),
-                ("kinetic_window", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("kinetic_window", ctypes.c_int32), ("descent_window", ctypes.c_int32),
                 ("ms_per_step", ctypes.c_double)]
 
 
@@ -322,7 +323,8 @@ class Pairs:
 
 def tril_create(dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
                 cand_cap: int = 0, block_traverse: int = 0, step_batch: int = 0,
-                stream=None, morton_bits: int = 0, kinetic_window: int = 0) -> ctypes.c_void_p:
+                stream=None, morton_bits: int = 0, kinetic_window: int = 0,
+                descent_window: int = 0) -> ctypes.c_void_p:
     L = lib()
     p = tril_params()
     p.dt = float(dt)
@@ -340,6 +342,7 @@ def tril_create(dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
     p.step_batch = int(step_batch)
     p.morton_bits = int(morton_bits)
     p.kinetic_window = int(kinetic_window)
+    p.descent_window = int(descent_window)
     h = ctypes.c_void_p()
     _check(L.tril_create(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(_stream(stream))),
            "tril_create")
@@ -412,7 +415,8 @@ def tril_pair_kinematics_noalloc(query: Beam, target: Beam, pairs: Pairs, n: int
         _stream(stream))
 
 
-TUNE_KEYS = ("block_traverse", "step_batch", "morton_bits", "traverse_queue", "kinetic_window")
+TUNE_KEYS = ("block_traverse", "step_batch", "morton_bits", "traverse_queue", "kinetic_window",
+             "descent_window")
 
 
 def tril_autotune(ctx, target: Beam, query: Beam, k0: int, n_probe: int) -> dict:
@@ -421,7 +425,8 @@ def tril_autotune(ctx, target: Beam, query: Beam, k0: int, n_probe: int) -> dict
                                int(n_probe), ctypes.byref(t)), "tril_autotune")
     return {"block_traverse": t.block_traverse, "step_batch": t.step_batch,
             "morton_bits": t.morton_bits, "traverse_queue": t.traverse_queue,
-            "kinetic_window": t.kinetic_window, "ms_per_step": t.ms_per_step}
+            "kinetic_window": t.kinetic_window, "descent_window": t.descent_window,
+            "ms_per_step": t.ms_per_step}
 
 
 def tril_set_tune(ctx, tune: dict) -> None:
@@ -876,10 +881,10 @@ class Context:
 
     def __init__(self, dt: float, edges: Optional[np.ndarray] = None, flags: int = 0,
                  cand_cap: int = 0, block_traverse: int = 0, step_batch: int = 0, stream=None,
-                 morton_bits: int = 0, kinetic_window: int = 0):
+                 morton_bits: int = 0, kinetic_window: int = 0, descent_window: int = 0):
         self.n_bins = 0 if edges is None else max(len(edges) - 1, 0)
         self.h = tril_create(dt, edges, flags, cand_cap, block_traverse, step_batch, stream,
-                             morton_bits, kinetic_window)
+                             morton_bits, kinetic_window, descent_window)
 
     def build(self, target: Beam, step: int) -> None:
         tril_build(self.h, target, step)

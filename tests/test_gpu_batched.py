@@ -102,7 +102,11 @@ def test_autotune_keeps_pair_set_and_caches(torch, tmp_path):
     {"block_traverse": 64, "step_batch": 40, "morton_bits": 0, "kinetic_window": 3},
     {"block_traverse": 128, "step_batch": 64, "morton_bits": 0, "kinetic_window": 64},
     {"block_traverse": 64, "step_batch": 0, "morton_bits": 0, "kinetic_window": 8,
-     "traverse_queue": 1}])
+     "traverse_queue": 1},
+    {"block_traverse": 64, "step_batch": 40, "morton_bits": 0, "kinetic_window": 32,
+     "descent_window": 5},
+    {"block_traverse": 256, "step_batch": 64, "morton_bits": 0, "kinetic_window": 64,
+     "descent_window": 32, "traverse_queue": 1}])
 def test_any_launch_configuration_same_pairs(torch, tune):
     A, offA, B, offB = _batch(8, 3000, 300.0)
     raw, S = oracle_run(A, B, 0.1, 400, EDGES, offA=offA, offB=offB)
@@ -114,7 +118,9 @@ def test_any_launch_configuration_same_pairs(torch, tune):
     {"block_traverse": 256, "step_batch": -1, "morton_bits": 0},
     {"block_traverse": 256, "step_batch": 4, "morton_bits": 2},
     {"block_traverse": 256, "step_batch": 4, "morton_bits": 0, "traverse_queue": 2},
-    {"block_traverse": 256, "step_batch": 4, "morton_bits": 0, "kinetic_window": -1}])
+    {"block_traverse": 256, "step_batch": 4, "morton_bits": 0, "kinetic_window": -1},
+    {"block_traverse": 256, "step_batch": 4, "morton_bits": 0, "descent_window": -1},
+    {"block_traverse": 256, "step_batch": 4, "morton_bits": 0, "descent_window": 33}])
 def test_set_tune_rejects_bad_values(torch, bad):
     ctx = T.Context(0.1, EDGES)
     try:

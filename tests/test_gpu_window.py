@@ -38,8 +38,8 @@ def _ref_step(cp, win, m):
     return a + (min(win, m - a) - 1) // 2
 
 
-def _run(wl, A, B, k0, n_steps, m, win, offA=None, offB=None):
-    ctx = T.Context(wl.dt, EDGES, step_batch=m, kinetic_window=win)
+def _run(wl, A, B, k0, n_steps, m, win, offA=None, offB=None, dwin=0):
+    ctx = T.Context(wl.dt, EDGES, step_batch=m, kinetic_window=win, descent_window=dwin)
     try:
         pairs = T.Pairs(1 << 18)
         ctx.run(T.Beam(B, offB), T.Beam(A, offA), k0, n_steps, pairs)
@@ -52,28 +52,33 @@ def _run(wl, A, B, k0, n_steps, m, win, offA=None, offB=None):
     return (i, j, k, st), cand
 
 
-@pytest.mark.parametrize("m,wins", [(40, (2, 5, 16, 40)), (7, (2, 3, 7))])
+@pytest.mark.parametrize("m,wins", [
+    (40, ((2, 0), (5, 0), (16, 0), (16, 1), (16, 3), (16, 16), (32, 0), (32, 32), (40, 7),
+          (40, 32))),
+    (7, ((2, 0), (3, 2), (7, 0), (7, 7)))])
 def test_candidates_and_pairs_equal_per_step_copies(torch, m, wins):
     """Same candidates (the last launch's, as a multiset, and the count over the run),
-    hits and pairs as one copy per step, for windows that divide the batch, leave a short
-    last window, and span the whole batch; the leaf records read are at least the
-    candidates."""
+    hits and pairs as one copy per step, for windows (steps per copy, steps per descent: 0
+    the default) that divide the batch, leave a short last window, and span the whole
+    batch, with descents that divide the window or leave a shorter last one in each copy.
+    Every candidate comes from a leaf record read: at most one per step of its descent."""
     wl, A, B = _beams(n=3000, boost=3e3)
     k0, n_steps = 150, 3 * m + m // 2 + 1  # full batches (graphs) and a shorter last one
     base, cand1 = _run(wl, A, B, k0, n_steps, m, 1)
     assert base[3]["n_leaf_checks"] == 0
     assert base[3]["n_pairs"] > 5 and base[3]["n_candidates"] > 20
-    for win in wins:
-        got, cand = _run(wl, A, B, k0, n_steps, m, win)
+    for win, dwin in wins:
+        got, cand = _run(wl, A, B, k0, n_steps, m, win, dwin=dwin)
         st, st1 = got[3], base[3]
-        assert np.array_equal(cand, cand1), win
-        assert st["n_candidates"] == st1["n_candidates"], win
+        assert np.array_equal(cand, cand1), (win, dwin)
+        assert st["n_candidates"] == st1["n_candidates"], (win, dwin)
         assert st["n_hits"] == st1["n_hits"] and st["n_pairs"] == st1["n_pairs"]
         for a, b in zip(got[:3], base[:3]):
-            assert np.array_equal(a, b), win
+            assert np.array_equal(a, b), (win, dwin)
         # the same pairs; the yield's FP64 sum runs in no fixed order
         assert st["yield"] == pytest.approx(st1["yield"], rel=1e-12)
-        assert st["n_leaf_checks"] >= st["n_candidates"]
+        assert st["n_leaf_checks"] * min(win, m) >= st["n_candidates"]
+        assert st["n_queries"] == st1["n_queries"]
 
 
 def test_window_copies_match_oracle(torch):
@@ -245,7 +250,7 @@ def _unpack_slots(w):
     return lo, hi, ids, leaf, e
 
 
-@pytest.mark.parametrize("m,win", [(40, 16), (5, 2)])
+@pytest.mark.parametrize("m,win", [(40, 16), (5, 2), (40, 40)])
 def test_four_child_forms_hold_the_copies(torch, m, win):
     """The four-child forms the traversal descends: each node's slots are its grandchildren
     in the FP32 tree (or a leaf child and an empty slot), each slot's 16-bit cell box holds the
