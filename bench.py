@@ -58,11 +58,11 @@ def traverse_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def committed_counters(dispatches=None, window=None) -> dict:
+def committed_counters(dispatches=None, window=None, descent=None) -> dict:
     """Counter figures of one traversal launch from the committed rocprofv3 summary: HBM
     bytes (`traffic_bytes_per_dispatch`), L1 lookups, TA/TD busy fractions. Empty when the
     summary was taken from a different kernel source, another batching (traversal launches
-    per collision run) or another number of steps per tree copy."""
+    per collision run), another number of steps per tree copy or per descent."""
     if not os.path.exists(PMC_SUMMARY):
         return {}
     vals = {}
@@ -76,6 +76,8 @@ def committed_counters(dispatches=None, window=None) -> dict:
     if dispatches is not None and vals.get("dispatches") != str(dispatches):
         return {}
     if window is not None and vals.get("kinetic_window", "1") != str(window):
+        return {}
+    if descent is not None and vals.get("descent_window", "1") != str(descent):
         return {}
     out = {}
     for k in ("traffic_bytes_per_dispatch", "L1_lookups_per_dispatch", "TD_busy", "TA_busy",
@@ -99,7 +101,7 @@ def batch_sizes(n_steps: int, launches: int) -> list:
 def tree_window(tune, arg: int) -> int:
     """Steps per tree copy in step batches (the library's default for 0)."""
     w = (tune or {}).get("kinetic_window", arg) or arg
-    return 16 if w == 0 else w
+    return 32 if w == 0 else w
 
 
 def descent_window(tune, arg: int, win: int) -> int:
@@ -803,7 +805,7 @@ def main():
         # candidate stores above
         lane_bytes = (q_bytes * nA * n_desc + 64.0 * st["n_node_visits"]
                       + 96.0 * st["n_leaf_checks"] + 8.0 * st["n_candidates"])
-        pmc = committed_counters(launches_per_run or None, win)
+        pmc = committed_counters(launches_per_run or None, win, dwin)
         traffic = pmc.get("traffic_bytes_per_dispatch")
         avg_s = st["ms_traverse"] * 1e-3 / n_launch
         achieved = hbm_bytes / n_launch / avg_s / 1e9

@@ -502,7 +502,7 @@ inline int32_t key_step(int32_t m) { return m > 0 ? (m - 1) / 2 : 0; }
 
 // Steps per tree copy for a batch of m steps: window copies only in the plain regime
 // (straight-line leaf boxes, query records), at most m.
-constexpr int32_t kDefaultWindow = 16;
+constexpr int32_t kDefaultWindow = 32;
 int32_t build_window(const tril_ctx *c, int32_t m) {
     if (m < 2 || c->cloud.on != 0 || c->kwin == 1) return 1;
     const int32_t w = c->kwin > 1 ? c->kwin : kDefaultWindow;
@@ -2483,7 +2483,7 @@ int tril_autotune(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k
             cur.step_batch = sb;
         }
     }
-    for (int w : {1, 4, 8, 32}) {  // steps per tree copy (0: the default, 16)
+    for (int w : {1, 4, 8, 16}) {  // steps per tree copy (0: the default, 32)
         if (rc != TRIL_OK || cur.step_batch == 1) break;
         double ms = 0.0;
         cur_win = w;

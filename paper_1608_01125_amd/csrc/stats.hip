@@ -103,6 +103,14 @@ __device__ __forceinline__ int find_bin(const double *edges, int32_t n_bins, dou
     return lo;
 }
 
+// Pairs of the union in key order with their yields (sqrt(w_i w_j)) summed into the total
+// and the spectrum: each workgroup sums its share in LDS (grid-stride) and adds every
+// nonzero bin and its total to the device sums once, instead of one device atomic per
+// pair on a few contended addresses; spectra of more than kCompactLdsBins bins add
+// straight to the device sums.
+constexpr int kCompactLdsBins = 2048;
+constexpr int kCompactGrid = 256;
+
 __global__ void __launch_bounds__(256) k_compact(const unsigned long long *__restrict__ keys,
                                                  const uint32_t *__restrict__ vals,
                                                  const uint32_t *__restrict__ flags,
@@ -115,24 +123,46 @@ __global__ void __launch_bounds__(256) k_compact(const unsigned long long *__res
                                                  const double *__restrict__ edges, int32_t n_bins,
                                                  int32_t *__restrict__ ti, int32_t *__restrict__ tj,
                                                  int32_t *__restrict__ tk, double *acc) {
-    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    __shared__ double hist[kCompactLdsBins];
+    __shared__ double wsum[4];
+    const bool lds = n_bins <= kCompactLdsBins;
+    if (lds)
+        for (int b = threadIdx.x; b < n_bins; b += blockDim.x) hist[b] = 0.0;
+    __syncthreads();
     double y = 0.0;
-    if (q < n && flags[q]) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        if (!flags[q]) continue;
         const uint32_t src = vals[q];
         const int32_t i = p.i[src], j = p.j[src];
         const int64_t u = (int64_t)pos[q] + tile_pre[q / kScanTile];
         ti[u] = i;
         tj[u] = j;
         tk[u] = p.step[src];
-        y = sqrt(w_q[i] * w_t[j]);
+        const double yq = sqrt(w_q[i] * w_t[j]);
+        y += yq;
         if (n_bins > 0) {
             const int b = find_bin(edges, n_bins, E_q[i] + E_t[j]);
-            if (b >= 0) atomicAdd(acc + 1 + b, y);
+            if (b >= 0) {
+                if (lds)
+                    atomicAdd(hist + b, yq);
+                else
+                    atomicAdd(acc + 1 + b, yq);
+            }
         }
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) y += __shfl_xor(y, off);
-    if ((threadIdx.x & 63) == 0 && y != 0.0) atomicAdd(acc, y);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = y;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += wsum[w];
+        if (t != 0.0) atomicAdd(acc, t);
+    }
+    if (lds)
+        for (int b = threadIdx.x; b < n_bins; b += blockDim.x)
+            if (hist[b] != 0.0) atomicAdd(acc + 1 + b, hist[b]);
 }
 
 __global__ void k_writeback(const int32_t *ti, const int32_t *tj, const int32_t *tk,
@@ -186,7 +216,8 @@ void run_union_stats(const tril_pairs &p, int64_t n_hits, int64_t n_target, int 
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, s.flags,
                        n_hits, s.pos, s.block_sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, st, s.block_sums, tiles, s.ucount);
-    hipLaunchKernelGGL(k_compact, dim3(grid_for(n_hits, 256)), dim3(256), 0, st, keys, vals,
+    hipLaunchKernelGGL(k_compact, dim3(std::min<unsigned>(grid_for(n_hits, 256), kCompactGrid)),
+                       dim3(256), 0, st, keys, vals,
                        s.flags, s.pos, s.block_sums, n_hits, p, w_q, w_t, E_q, E_t, d_edges,
                        n_bins, s.ti, s.tj, s.tk, s.acc);
     hipLaunchKernelGGL(k_writeback, dim3(grid_for(n_hits, 256)), dim3(256), 0, st, s.ti, s.tj, s.tk,

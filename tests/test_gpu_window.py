@@ -82,7 +82,8 @@ def test_candidates_and_pairs_equal_per_step_copies(torch, m, wins):
 
 
 def test_window_copies_match_oracle(torch):
-    """Default window (16 steps per copy) over a whole 400-step run against the oracle."""
+    """Default windows (32 steps per copy, 8 per descent) over a whole 400-step run against
+    the oracle."""
     wl, A, B = _beams(n=3000, boost=3e3, seed=5)
     raw, S = oracle_run(A, B, wl.dt, 400, EDGES)
     got, _ = _run(wl, A, B, 0, 400, 0, 0)
