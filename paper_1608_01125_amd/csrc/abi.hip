@@ -161,6 +161,8 @@ struct tril_ctx {
     TRec *t_rec = nullptr;                 // window copies: per sorted target position
     CNode4 *nodes4 = nullptr;              // window copies: four-child forms of the nodes
     int64_t nodes4_cap = 0;
+    uint8_t *t_inside = nullptr;           // window copies: per internal node, formed by the refit
+    int64_t inside_cap = 0;
     WinFrame *t_frames = nullptr;          // window copies: quantisation frame per copy
     int32_t frames_cap = 0;
     WinBound *t_wb = nullptr;              // window copies: per target instance, bounds of u dt
@@ -554,7 +556,7 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
     c->tgt_cloud = c->cloud;
     if (win > 1) launch_win_bounds(c->t_stats, t.n_inst, c->dt, c->t_wb, st);
     c->quad = win > 1 && n > 1 && (int64_t)copies * (n - 1) <= c->nodes4_cap &&
-              copies <= c->frames_cap;
+              copies <= c->frames_cap && n - 1 <= c->inside_cap;
     launch_inst_roots(t, c->cloud, c->dt, c->inst_base, rows, c->inst_root, c->root_box, c->d_cnt,
                       st, win, c->t_rec);
     int32_t *xbase = nullptr;
@@ -563,12 +565,16 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
         xbase = c->xlev;
         xalt = enqueue_xlevels(c->prec, n, xbase, c->ss, &c->d_cnt->err, st);
     }
+    // four-child forms: the frames first; the refit forms the nodes whose descendants lie in
+    // one of its chunks, the collapse the others
+    if (c->quad) launch_win_frames(c->t_stats, t.n_inst, c->dt, win, t.m, c->d_cnt, c->t_frames, st);
     launch_refit(t, c->cloud, c->dt, rows, c->prec, c->nflags, c->nodes, c->refit_slots,
-                 c->refit_slot_cap, xbase, xalt, c->d_cnt, &c->d_cnt->err, st, win, c->t_rec);
-    if (c->quad) {
-        launch_win_frames(c->t_stats, t.n_inst, c->dt, win, t.m, c->d_cnt, c->t_frames, st);
-        launch_collapse4(c->nodes, n, copies, c->t_frames, c->nodes4, &c->d_cnt->err, st);
-    }
+                 c->refit_slot_cap, xbase, xalt, c->d_cnt, &c->d_cnt->err, st, win, c->t_rec,
+                 c->quad ? c->t_frames : nullptr, c->quad ? c->nodes4 : nullptr,
+                 c->quad ? c->t_inside : nullptr);
+    if (c->quad)
+        launch_collapse4(c->nodes, n, copies, c->t_frames, c->nodes4, &c->d_cnt->err, st,
+                         c->t_inside);
     if (timed) CHK(timing_pair(c, st, c->ev_build, false));
     HIPCHK(hipGetLastError());
     return TRIL_OK;
@@ -1035,6 +1041,13 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
             c->nodes4_cap = 0;
             CHK(dev_alloc(&c->nodes4, (size_t)need));
             c->nodes4_cap = need;
+        }
+        if (t->n - 1 > c->inside_cap) {
+            ++c->alloc_gen;
+            dev_free(c->t_inside);
+            c->inside_cap = 0;
+            CHK(dev_alloc(&c->t_inside, (size_t)(t->n - 1)));
+            c->inside_cap = t->n - 1;
         }
         const int32_t nf = window_copies(m, bw);
         if (nf > c->frames_cap) {
@@ -2598,7 +2611,7 @@ void tril_destroy(tril_ctx *c) {
     }
     dev_free(c->au_cell); dev_free(c->au_ctl); dev_free(c->au_count);
     dev_free(c->d_t_off); dev_free(c->t_stats); dev_free(c->t_wb); dev_free(c->inst_root); dev_free(c->inst_base); dev_free(c->root_box);
-    dev_free(c->nodes4);
+    dev_free(c->nodes4); dev_free(c->t_frames); dev_free(c->t_inside);
     dev_free(c->q_box); dev_free(c->q_spart); dev_free(c->q_k32a); dev_free(c->q_k32b);
     dev_free(c->q_k64a); dev_free(c->q_k64b); dev_free(c->q_va); dev_free(c->q_vb);
     dev_free(c->q_keep); dev_free(c->q_rec); dev_free(c->d_q_off); dev_free(c->q_stats); dev_free(c->cand_i);

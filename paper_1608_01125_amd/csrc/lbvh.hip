@@ -732,12 +732,14 @@ __device__ __forceinline__ int64_t local_id(int32_t link, int64_t cbase) {
 __global__ void __launch_bounds__(256) k_collapse4(const Node *__restrict__ nodes, int64_t n,
                                                    int32_t copies,
                                                    const WinFrame *__restrict__ frames,
-                                                   CNode4 *__restrict__ out, unsigned int *err) {
+                                                   CNode4 *__restrict__ out, unsigned int *err,
+                                                   const uint8_t *__restrict__ inside) {
     const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t per = n - 1;
     if (idx >= per * copies) return;
     const int32_t cp = (int32_t)(idx / per);
     const int64_t cbase = (int64_t)cp * per;
+    if (inside != nullptr && inside[idx - cbase] != 0) return;  // formed by the refit
     const WinFrame fr = frames[cp];
     const float fb[3] = {fr.base.x, fr.base.y, fr.base.z}, fi[3] = {fr.inv.x, fr.inv.y, fr.inv.z};
     const float4 *np = reinterpret_cast<const float4 *>(nodes + idx);
@@ -903,7 +905,10 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
                                                     int32_t store_only,
                                                     const DevCounters *__restrict__ cnt,
                                                     unsigned int *err, int32_t win,
-                                                    int32_t n_copies, TRec *__restrict__ trec) {
+                                                    int32_t n_copies, TRec *__restrict__ trec,
+                                                    const WinFrame *__restrict__ frames,
+                                                    CNode4 *__restrict__ nodes4,
+                                                    uint8_t *__restrict__ inside_flag) {
     // halves of the chunk's nodes as their parents hold them, lo (xyz, link) and hi
     // (xyz, energy bound): [0, chunk) internal node c0 + k, [chunk, 2 chunk) leaf c0 + k
     // (before the first step the same memory holds the nodes' heights)
@@ -983,6 +988,8 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
         }
     }
     if (myh > 0) atomicMax(&s_hmax, myh);
+    // four-child forms: the nodes whose forms this chunk writes, marked once per batch
+    if (kMoved && nodes4 != nullptr && group == 0 && has_int) inside_flag[c0 + tid] = inside ? 1 : 0;
 
     // ---- the leaf's photon, read once for all steps of the group
     const unsigned step0 = cnt->step;
@@ -1037,6 +1044,44 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
                                         fmaxf(ahi.z, bhi.z), fmaxf(ahi.w, bhi.w));
             }
             __syncthreads();
+        }
+        if (kMoved && nodes4 != nullptr && inside) {
+            // the node's four-child form from the merged halves of its children and
+            // grandchildren (a leaf child: itself and an empty slot), as k_collapse4 forms it
+            const WinFrame fr = frames[step];
+            const float fb[3] = {fr.base.x, fr.base.y, fr.base.z};
+            const float fi[3] = {fr.inv.x, fr.inv.y, fr.inv.z};
+            const int2 ch = s_child[tid];
+            uint32_t w4[16], eh[4];
+            bool bad = false;
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const int32_t hc = side ? ch.y : ch.x;
+                int64_t g;
+                if (hc < kRefitChunk) {  // internal child: its two children
+                    const int2 gc = s_child[hc];
+                    cslot(s_lo[gc.x], s_hi[gc.x], fb, fi, w4 + 6 * side, eh[2 * side], bad);
+                    cslot(s_lo[gc.y], s_hi[gc.y], fb, fi, w4 + 6 * side + 3, eh[2 * side + 1], bad);
+                    g = c0 + (gc.x < kRefitChunk ? gc.x : gc.x - kRefitChunk);
+                    const int64_t g1 = c0 + (gc.y < kRefitChunk ? gc.y : gc.y - kRefitChunk);
+                    if (g1 != g + 1) bad = true;
+                } else {  // the leaf itself, then an empty slot
+                    cslot(s_lo[hc], s_hi[hc], fb, fi, w4 + 6 * side, eh[2 * side], bad);
+                    w4[6 * side + 3] = 65535u | (65535u << 16);
+                    w4[6 * side + 4] = 65535u;
+                    w4[6 * side + 5] = 0u;
+                    eh[2 * side + 1] = 0u;
+                    g = c0 + (hc - kRefitChunk);
+                }
+                w4[12 + side] = (uint32_t)g;
+            }
+            w4[14] = eh[0] | (eh[1] << 16);
+            w4[15] = eh[2] | (eh[3] << 16);
+            if (bad) atomicOr(err, kErrInternal);
+            uint4 *op = reinterpret_cast<uint4 *>(nodes4 + (int64_t)step * (n - 1) + c0 + tid);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                op[k] = make_uint4(w4[4 * k], w4[4 * k + 1], w4[4 * k + 2], w4[4 * k + 3]);
         }
         // complete nodes, whole: word f of the chunk's node block is quarter f % 4 of node
         // c0 + f / 4 (lo, hi of the left child, then of the right child)
@@ -1369,11 +1414,11 @@ void launch_win_frames(const InstStats *stats, int32_t n_inst, double dt, int32_
 }
 
 void launch_collapse4(const Node *nodes, int64_t n, int32_t copies, const WinFrame *frames,
-                      CNode4 *out, unsigned int *err, hipStream_t st) {
+                      CNode4 *out, unsigned int *err, hipStream_t st, const uint8_t *inside) {
     const int64_t total = n > 1 ? (n - 1) * copies : 0;
     if (total <= 0) return;
     hipLaunchKernelGGL(k_collapse4, dim3(grid_for(total, 256)), dim3(256), 0, st, nodes, n, copies,
-                       frames, out, err);
+                       frames, out, err, inside);
 }
 
 void launch_win_bounds(const InstStats *stats, int32_t n_inst, double dt, WinBound *vb,
@@ -1410,9 +1455,11 @@ bool enqueue_xlevels(const PRec *prec, int64_t n, int32_t *base, const SortScrat
 void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint32_t *sorted_rows,
                   const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots, int64_t slot_cap,
                   int32_t *xbase, bool xalt, const DevCounters *c, unsigned int *err,
-                  hipStream_t st, int32_t win, TRec *trec) {
+                  hipStream_t st, int32_t win, TRec *trec, const WinFrame *frames,
+                  CNode4 *nodes4, uint8_t *inside) {
     const int64_t n = b.n;
     if (cloud.on != 0) win = 1;  // window copies need straight-line leaf boxes
+    if (win <= 1 || frames == nullptr || inside == nullptr) nodes4 = nullptr;
     const int32_t m = window_copies(b.m, win);  // copies of the shape
     if (n <= 1 || m <= 0) return;  // no internal node: a single leaf is its step's root
     const int64_t chunks = (n + kRefitChunk - 1) / kRefitChunk;
@@ -1429,11 +1476,11 @@ void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint
     if (cloud.on == 0)
         hipLaunchKernelGGL(k_refit<true>, dim3((unsigned)(chunks * groups)), dim3(kRefitChunk), 0,
                            st, b, cloud, dt, sorted_rows, chunks, group_steps, prec, flags, nodes,
-                           slots, levels ? 1 : 0, c, err, win, m, trec);
+                           slots, levels ? 1 : 0, c, err, win, m, trec, frames, nodes4, inside);
     else
         hipLaunchKernelGGL(k_refit<false>, dim3((unsigned)(chunks * groups)), dim3(kRefitChunk), 0,
                            st, b, cloud, dt, sorted_rows, chunks, group_steps, prec, flags, nodes,
-                           slots, levels ? 1 : 0, c, err, 1, m, trec);
+                           slots, levels ? 1 : 0, c, err, 1, m, trec, nullptr, nullptr, nullptr);
     if (levels) {
         const XLev x = xlev_layout(xbase, n);
         hipLaunchKernelGGL(k_refit_levels, dim3((unsigned)m), dim3(kXThreads), 0, st,

@@ -391,9 +391,12 @@ void launch_win_frames(const InstStats *stats, int32_t n_inst, double dt, int32_
                        const DevCounters *c, WinFrame *frames, hipStream_t st);
 // Four-child forms of the copies x (n - 1) internal nodes (n rows) of window copies, in their
 // copies' frames; a child box outside its frame, or children that are not a split and its
-// successor, set kErrInternal.
+// successor, set kErrInternal. inside: NULL, or one byte per internal node, nonzero where
+// the refit has written the node's forms already (the node and its descendants lie in one
+// of its chunks); only the other nodes are formed here.
 void launch_collapse4(const Node *nodes, int64_t n, int32_t copies, const WinFrame *frames,
-                      CNode4 *out, unsigned int *err, hipStream_t st);
+                      CNode4 *out, unsigned int *err, hipStream_t st,
+                      const uint8_t *inside = nullptr);
 // Per-instance bounds of u dt of a target beam from its statistics (window copies).
 void launch_win_bounds(const InstStats *stats, int32_t n_inst, double dt, WinBound *vb,
                        hipStream_t st);
@@ -415,11 +418,16 @@ bool enqueue_xlevels(const PRec *prec, int64_t n, int32_t *base, const SortScrat
 // xbase: the level buffer set up by enqueue_xlevels for this shape (xalt: its result), or
 // nullptr for the crossing-level climb through the hand-off slots. win > 1 (plain regime
 // only): window copies, window_copies(b.m, win) of them, and every leaf's record in trec
-// (b.n entries, by sorted position).
+// (b.n entries, by sorted position). nodes4 (window copies only, with frames formed
+// beforehand): the four-child forms of every internal node whose descendants all lie in
+// one 512-leaf chunk are written from the chunk's merged boxes, and inside (b.n - 1 bytes)
+// marks those nodes for launch_collapse4, which forms the others.
 void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint32_t *sorted_rows,
                   const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots, int64_t slot_cap,
                   int32_t *xbase, bool xalt, const DevCounters *c, unsigned int *err,
-                  hipStream_t st, int32_t win = 1, TRec *trec = nullptr);
+                  hipStream_t st, int32_t win = 1, TRec *trec = nullptr,
+                  const WinFrame *frames = nullptr, CNode4 *nodes4 = nullptr,
+                  uint8_t *inside = nullptr);
 
 // n_int: internal nodes of all steps' trees; root_box: box of each combined instance
 // whose root is a leaf; nq: virtual query count (steps x rows).
