@@ -1119,8 +1119,9 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     };
 
     // Batch of mb steps with working buffers (pt, pq) on stream st: build, collide, and
-    // rewrite the working copies for the next batch.
-    auto enqueue_batch = [&](int32_t mb, bool sort, hipStream_t st, bool tm) -> int {
+    // (regather: another batch follows) rewrite the working copies for the next batch.
+    auto enqueue_batch = [&](int32_t mb, bool sort, hipStream_t st, bool tm,
+                             bool regather) -> int {
         c->tgt = wview(t, c->d_t_off, mb, c->wt[pt]);
         BeamDev qv = wview(q, c->d_q_off, mb, c->wq[pq]);
         if (ann) {
@@ -1133,6 +1134,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
             c->q_order_len = 0;
         }
         CHK(enqueue_collide(c, qv, *out, st, tm, sort));
+        if (!regather) return TRIL_OK;
         launch_gather_beam(wview(t, c->d_t_off, 1, c->wt[pt]), c->t_rows, c->wt[pt ^ 1].soa,
                            c->wt[pt ^ 1].perm, st);
         if (sort)
@@ -1156,7 +1158,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
             // eager batch (per-phase events, the shorter last batch, or the one batch that
             // orders the queries when they are ordered once)
             launch_set_step(c->d_cnt, k, c->st);
-            CHK(enqueue_batch(mb, sort, c->st, timed));
+            CHK(enqueue_batch(mb, sort, c->st, timed, left > mb));
             last_pq = pq;
             last_mb = mb;
             flip(sort);
@@ -1197,7 +1199,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
                 }
                 hipGraph_t g = nullptr;
                 HIPCHK(hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
-                int r1 = enqueue_batch(m, sort, c->gst, false);
+                int r1 = enqueue_batch(m, sort, c->gst, false, true);
                 launch_advance_step(c->d_cnt, m, c->gst);
                 hipError_t e = hipStreamEndCapture(c->gst, &g);
                 if (r1 != TRIL_OK) {
