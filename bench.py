@@ -793,7 +793,8 @@ def main():
         runs = max(st["n_collides"] // max(n_steps, 1), 1)
         batches = batch_sizes(n_steps, launches_per_run)
         win = tree_window(tune, args.kinetic_window)
-        dwin = descent_window(tune, args.descent_window, win)
+        # the descent length the library used (automatic: adapted from run to run)
+        dwin = st.get("descent_window") or descent_window(tune, args.descent_window, win)
         copies = sum(b if (win <= 1 or b < 2) else -(-b // win) for b in batches) * runs
         n_desc = sum(descents(b, win, dwin) for b in batches) * runs
         rec_bytes = 48.0 * nB * sum(1 for b in batches if win > 1 and b >= 2) * runs

@@ -138,11 +138,15 @@ typedef struct {
                                      only; the candidates, and so the results, do not depend
                                      on it. */
     int32_t descent_window;       /* tril_run batches with window copies: steps served by one
-                                     descent of a copy, 0..32 (0 = automatic: 8), at most the
-                                     copy's steps. The descent tests internal nodes with the
-                                     hull of the widened boxes of its first and last steps,
-                                     and every leaf that passes at the leaf's own boxes of
-                                     each of its steps. The results do not depend on it. */
+                                     descent of a copy, 0..32, at most the copy's steps. The
+                                     descent tests internal nodes with the hull of the widened
+                                     boxes of its first and last steps, and every leaf that
+                                     passes at the leaf's own boxes of each of its steps.
+                                     0 = automatic: 8 steps at first; every tril_stats call
+                                     then halves the length when the runs since the previous
+                                     call tested more than 0.45 leaves per descent (and does
+                                     not take that length again), or doubles it below 0.13.
+                                     The results do not depend on it. */
 } tril_params;
 
 /* Caller-owned pair buffer. tril_collide appends raw hits (i, j, step) at
@@ -170,7 +174,8 @@ typedef struct {
     double *spectrum;         /* host, n_bins, caller-owned, or NULL */
     int64_t *step_counts;     /* host, n_step_counts, caller-owned, or NULL: raw hits per step */
     int32_t n_step_counts;    /* steps 0 .. n_step_counts-1 are counted */
-    int32_t pad0;
+    int32_t descent_window;   /* output: steps per descent of the four-child hierarchy copies
+                                 in the tril_run calls these counters cover (0: none) */
     double ms_build;          /* with TRIL_TIMING: summed event time of tril_build */
     double ms_query_prep;     /* with TRIL_TIMING: query boxes + Morton order */
     double ms_traverse;       /* with TRIL_TIMING: traversal kernel */

@@ -102,6 +102,12 @@ struct tril_ctx {
     int32_t step_batch = 0;         // steps per launch in tril_run (0 = automatic)
     int32_t kwin = 0;               // steps per tree copy in batches (0 = automatic, 1 = per step)
     int32_t kdesc = 0;              // steps per four-child descent (0 = automatic)
+    // automatic descent length: the current one, the lengths given up for reaching too many
+    // leaves (bit log2 D), and what the counters held at the last adaptation
+    int32_t kdesc_auto = 8;
+    uint32_t kdesc_rejected = 0u;
+    int64_t ad_checks0 = 0, ad_queries0 = 0;
+    bool ad_quad = false;           // a tril_run since then descended four-child forms
     int morton_param = 0;           // Morton bits requested (0 = automatic)
     CloudBox cloud{0, {0.0, 0.0, 0.0}};  // box kind of the builds (statistical regime: clouds)
     double *st_slots = nullptr;     // statistical regime: per-wave yield sums (kCounterSlots)
@@ -512,11 +518,35 @@ int32_t build_window(const tril_ctx *c, int32_t m) {
 }
 
 // Steps per descent over the four-child forms of copies of win steps: at most win and
-// kMaxDescent.
-constexpr int32_t kDefaultDescent = 8;
+// kMaxDescent; automatic (kdesc 0): the length tril_stats last chose (adapt_descent).
 int32_t descent_window(const tril_ctx *c, int32_t win) {
-    const int32_t d = c->kdesc > 0 ? c->kdesc : kDefaultDescent;
+    const int32_t d = c->kdesc > 0 ? c->kdesc : c->kdesc_auto;
     return std::min(std::min(d, win), kMaxDescent);
+}
+
+// Automatic descent length. A longer descent loads fewer nodes per step but reaches more
+// leaves (its hull stretches along the motion), each tested at every step in range. From the
+// leaf tests per descent L since the last adaptation: above kAdaptHigh the length halves
+// and is not taken again (doubling it multiplies L by about 3 to 5), below kAdaptLow it
+// doubles unless that length was given up; lengths are powers of two in 1..kMaxDescent.
+constexpr double kAdaptHigh = 0.45, kAdaptLow = 0.13;
+void adapt_descent(tril_ctx *c, int64_t checks, int64_t queries) {
+    const int32_t d = c->kdesc_auto;
+    const int64_t dq = queries - c->ad_queries0, dl = checks - c->ad_checks0;
+    if (c->kdesc == 0 && c->ad_quad && dq > 0) {
+        const double L = (double)dl * d / (double)dq;
+        int lg = 0;
+        while ((1 << lg) < d) ++lg;
+        if (L > kAdaptHigh && d > 1) {
+            c->kdesc_rejected |= 1u << lg;
+            c->kdesc_auto = d / 2;
+        } else if (L < kAdaptLow && 2 * d <= kMaxDescent && !(c->kdesc_rejected & (2u << lg))) {
+            c->kdesc_auto = 2 * d;
+        }
+    }
+    c->ad_checks0 = checks;
+    c->ad_queries0 = queries;
+    c->ad_quad = false;
 }
 
 // Kernels of one build on stream st (target view, with its step count m, in c->tgt;
@@ -1187,7 +1217,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
                 (const void *)(intptr_t)c->block, (const void *)(uintptr_t)c->flags,
                 (const void *)(intptr_t)c->trav_queue,
                 (const void *)(intptr_t)c->cand_cap, (const void *)(intptr_t)c->kwin,
-                (const void *)(intptr_t)c->kdesc};
+                (const void *)(intptr_t)c->kdesc, (const void *)(intptr_t)c->kdesc_auto};
             int slot = (c->gexec[0] && key == c->gkey[0]) ? 0
                        : (c->gexec[1] && key == c->gkey[1]) ? 1 : -1;
             if (slot < 0) {
@@ -1229,6 +1259,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     // the last batch's view (its working-copy buffer: graph replays leave the host view
     // of the last capture)
     c->tgt = wview(t, c->d_t_off, c->tgt.m, c->wt[pt ^ 1]);
+    if (c->quad) c->ad_quad = true;  // the counters now hold descents of kdesc_auto steps
     c->last_qrec = wview(q, c->d_q_off, last_mb, c->wq[last_pq]);
     if (!(last_mb >= 2 && c->cloud.on == 0)) c->last_qrec.m = 0;  // boxes, not records
     c->built = true;
@@ -1259,6 +1290,8 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     out->n_node_visits = visits;
     out->n_leaf_checks = checks;
     out->n_queries = queries;
+    out->descent_window = c->ad_quad ? descent_window(c, c->win_eff) : 0;
+    adapt_descent(c, checks, queries);
     out->n_sigma_evals = (int64_t)h.sigma_evals;
     out->n_fp64_rechecks = (int64_t)h.fp64_rechecks;
     out->n_builds = (int64_t)h.builds;
@@ -2573,6 +2606,8 @@ int tril_reset_counters(tril_ctx *c) {
     for (double &m : c->ms_acc) m = 0.0;
     c->timed_launches = 0;
     c->max_step = c->built ? c->built_step : -1;
+    c->ad_checks0 = c->ad_queries0 = 0;
+    c->ad_quad = false;
     return TRIL_OK;
 }
 

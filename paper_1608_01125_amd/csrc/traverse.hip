@@ -84,6 +84,9 @@ constexpr int kStackRegs = 4;
 constexpr int kStackSpill = 124;  // deeper than any radix tree over (key, index) pairs
 // four-child descent: at most three pushes per level of a tree at most 48 levels deep
 constexpr int kStackSpill4 = 144;
+// four-child descent: leaf slots queued per lane (in LDS) and tested together, when a lane's
+// queue would overflow and at the end of the descent
+constexpr int kLeafQ = 16;
 
 // Box of a query of step offset s from the row's record for the batch (moved_box).
 __device__ __forceinline__ void record_box(const float4 a, const float4 d, const float4 w,
@@ -207,7 +210,8 @@ __device__ __forceinline__ int32_t traverse_query(int64_t q, const Node *__restr
                                                int32_t *__restrict__ cand_i,
                                                int32_t *__restrict__ cand_j, int64_t cand_cap,
                                                DevCounters *c, uint32_t &visits,
-                                               const WinArgs &wa, uint32_t &checks) {
+                                               const WinArgs &wa, uint32_t &checks,
+                                               uint32_t *__restrict__ lq, int32_t lq_stride) {
     int32_t node = -1, qi = 0, tag = -1, qs = 0;
     float qb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     float qw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // window copies: the widened box
@@ -418,6 +422,23 @@ __device__ __forceinline__ int32_t traverse_query(int64_t q, const Node *__restr
         // four-child descent: every load brings the boxes of the node's grandchildren, so the
         // chain of dependent loads is half as long; up to three overlapping internal
         // children wait on the stack
+        uint32_t qlen = 0u;  // leaf slots queued in lq (sorted leaf positions)
+        auto flush = [&]() {
+            for (;;) {
+                const bool has = qlen != 0u;
+                if (__ballot(has) == 0ull) break;
+                // the query's exact boxes at the descent's steps are formed again from its
+                // record (kept out of the registers the descent holds)
+                uint32_t mask = 0u;
+                int32_t trow = 0;
+                if (has) {
+                    --qlen;
+                    mask = leaf_steps(wa, (int64_t)lq[qlen * lq_stride], qrec, qi, qs, qn, qe, trow);
+                    ++checks;
+                }
+                emit_steps(mask, qi, trow, qs, nq_base, wa.n, cand_i, cand_j, cand_cap, c);
+            }
+        };
         while (node >= 0) {
             if (visits > max_visits) {
                 atomicOr(&c->err, kErrSpin);
@@ -494,28 +515,20 @@ __device__ __forceinline__ int32_t traverse_query(int64_t q, const Node *__restr
             } else {
                 node = -1;
             }
-            // leaves: nothing to do in most visits of most waves (one ballot decides); else
-            // rounds in which every lane with a leaf slot left tests one, as many rounds as
-            // the most such slots of a lane
+            // leaf slots: queued, and tested in rounds in which every lane with a queued leaf
+            // tests one, once a lane's queue would overflow (and at the end of the descent),
+            // so that a round finds many lanes busy rather than the one or two of a visit
             if (__ballot(pend != 0u) != 0ull) {
-                for (;;) {
-                    const bool has = pend != 0u;
-                    if (__ballot(has) == 0ull) break;
-                    // the query's exact boxes at the window's steps are formed again from its
-                    // record (kept out of the registers the descent holds)
-                    uint32_t mask = 0u;
-                    int32_t trow = 0;
-                    if (has) {
-                        const uint32_t k = (uint32_t)__builtin_ctz(pend);
-                        pend &= pend - 1u;
-                        const int32_t g = (int32_t)((k & 2u) ? g2 : g0) + (int32_t)(k & 1u);
-                        mask = leaf_steps(wa, g, qrec, qi, qs, qn, qe, trow);
-                        ++checks;
-                    }
-                    emit_steps(mask, qi, trow, qs, nq_base, wa.n, cand_i, cand_j, cand_cap, c);
+                if (__ballot(qlen + (uint32_t)__popc(pend) > (uint32_t)kLeafQ) != 0ull) flush();
+                while (pend != 0u) {
+                    const uint32_t k = (uint32_t)__builtin_ctz(pend);
+                    pend &= pend - 1u;
+                    lq[qlen * lq_stride] = ((k & 2u) ? g2 : g0) + (k & 1u);
+                    ++qlen;
                 }
             }
         }
+        flush();
         return active ? qn : 0;
     }
     while (node >= 0) {
@@ -629,11 +642,12 @@ __global__ void __launch_bounds__(BLOCK, kQuad ? 8 : 1) k_traverse(const Node *_
                                                     int32_t *__restrict__ cand_i,
                                                     int32_t *__restrict__ cand_j, int64_t cand_cap,
                                                     DevCounters *c, WinArgs wa) {
+    __shared__ uint32_t s_lq[kQuad ? kLeafQ * BLOCK : 1];
     const int64_t q = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
     uint32_t visits = 0, checks = 0;
     const int32_t qsteps = traverse_query<kRec, kWin, kQuad>(
         q, nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq, nq_base, inst_root,
-        cand_i, cand_j, cand_cap, c, visits, wa, checks);
+        cand_i, cand_j, cand_cap, c, visits, wa, checks, kQuad ? s_lq + threadIdx.x : nullptr, BLOCK);
     add_counts(visits, checks, (uint32_t)qsteps, c);
 }
 
@@ -661,6 +675,7 @@ __global__ void __launch_bounds__(BLOCK) k_traverse_queue(const Node *__restrict
                                                           int32_t *__restrict__ cand_j,
                                                           int64_t cand_cap, DevCounters *c,
                                                           WinArgs wa) {
+    __shared__ uint32_t s_lq[kQuad ? kLeafQ * BLOCK : 1];
     const int lane = threadIdx.x & 63;
     const int x = blockIdx.x & (kTravCursors - 1);
     uint32_t visits = 0, checks = 0, qsteps = 0;
@@ -674,7 +689,8 @@ __global__ void __launch_bounds__(BLOCK) k_traverse_queue(const Node *__restrict
             if (base + sub >= nq) break;
             qsteps += (uint32_t)traverse_query<kRec, kWin, kQuad>(
                 base + sub + lane, nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len,
-                nq, nq_base, inst_root, cand_i, cand_j, cand_cap, c, visits, wa, checks);
+                nq, nq_base, inst_root, cand_i, cand_j, cand_cap, c, visits, wa, checks,
+                kQuad ? s_lq + threadIdx.x : nullptr, BLOCK);
         }
     }
     add_counts(visits, checks, qsteps, c);

@@ -62,7 +62,7 @@ class tril_stats_t(ctypes.Structure):
                 ("n_queries", ctypes.c_int64), ("n_sigma_evals", ctypes.c_int64),
                 ("n_builds", ctypes.c_int64), ("n_collides", ctypes.c_int64),
                 ("yield_", ctypes.c_double), ("spectrum", _dp), ("step_counts", _i64p),
-                ("n_step_counts", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("n_step_counts", ctypes.c_int32), ("descent_window", ctypes.c_int32),
                 ("ms_build", ctypes.c_double), ("ms_query_prep", ctypes.c_double),
                 ("ms_traverse", ctypes.c_double), ("ms_narrow", ctypes.c_double),
                 ("n_timed_launches", ctypes.c_int64), ("n_fp64_rechecks", ctypes.c_int64),

@@ -305,3 +305,34 @@ def test_four_child_forms_hold_the_copies(torch, m, win):
             assert np.all(lo[full, s] <= a[full]) and np.all(hi[full, s] >= b[full])
             assert np.all(a[full] >= -1.0) and np.all(b[full] <= 65536.0)
             assert np.all(e[valid, s] >= fe[valid])
+
+
+def test_automatic_descent_length_follows_the_leaf_tests_and_keeps_the_pairs(torch):
+    """Automatic descent length: 8 steps in a context's first run; after each tril_stats it
+    halves when the run tested more than 0.45 leaves per descent (that length is then not
+    taken again) and doubles below 0.13. Every run finds the same pairs."""
+    for boost, n in ((3e3, 3000), (3e3, 20000)):
+        wl, A, B = _beams(n=n, boost=boost, seed=9)
+        ctx = T.Context(wl.dt, EDGES)
+        try:
+            got, rejected, expect = [], set(), 8
+            for _ in range(5):
+                ctx.reset_counters()
+                pairs = T.Pairs(1 << 18)
+                ctx.run(T.Beam(B), T.Beam(A), 0, 200, pairs)
+                st = ctx.stats(pairs)
+                d = st["descent_window"]
+                assert d == expect
+                got.append(pairs.numpy())
+                L = st["n_leaf_checks"] * d / st["n_queries"]
+                if L > 0.45 and d > 1:
+                    rejected.add(d)
+                    expect = d // 2
+                elif L < 0.13 and 2 * d <= 32 and 2 * d not in rejected:
+                    expect = 2 * d
+        finally:
+            ctx.close()
+        assert len(got[0][0]) > 0
+        for g in got[1:]:
+            for a, b in zip(g, got[0]):
+                assert np.array_equal(a, b)
