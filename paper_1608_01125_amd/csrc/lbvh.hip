@@ -727,19 +727,12 @@ __device__ __forceinline__ int64_t local_id(int32_t link, int64_t cbase) {
     return link >= 0 ? (int64_t)link - cbase : -2 - (int64_t)link;
 }
 
-// Four-child forms (CNode4) of every internal node of the copies: one thread per node reads
-// the node and, for each internal child, that child's node.
-__global__ void __launch_bounds__(256) k_collapse4(const Node *__restrict__ nodes, int64_t n,
-                                                   int32_t copies,
-                                                   const WinFrame *__restrict__ frames,
-                                                   CNode4 *__restrict__ out, unsigned int *err,
-                                                   const uint8_t *__restrict__ inside) {
-    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t per = n - 1;
-    if (idx >= per * copies) return;
-    const int32_t cp = (int32_t)(idx / per);
-    const int64_t cbase = (int64_t)cp * per;
-    if (inside != nullptr && inside[idx - cbase] != 0) return;  // formed by the refit
+// Four-child form (CNode4) of internal node idx = cp (n - 1) + x of copy cp from the node and,
+// for each internal child, that child's node.
+__device__ __forceinline__ void form_node(const Node *__restrict__ nodes, int64_t n, int64_t idx,
+                                          int32_t cp, const WinFrame *__restrict__ frames,
+                                          CNode4 *__restrict__ out, unsigned int *err) {
+    const int64_t cbase = (int64_t)cp * (n - 1);
     const WinFrame fr = frames[cp];
     const float fb[3] = {fr.base.x, fr.base.y, fr.base.z}, fi[3] = {fr.inv.x, fr.inv.y, fr.inv.z};
     const float4 *np = reinterpret_cast<const float4 *>(nodes + idx);
@@ -775,6 +768,25 @@ __global__ void __launch_bounds__(256) k_collapse4(const Node *__restrict__ node
     uint4 *op = reinterpret_cast<uint4 *>(out + idx);
 #pragma unroll
     for (int k = 0; k < 4; ++k) op[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+}
+
+// Four-child forms of the copies' internal nodes: with `inside`, one thread per node of the
+// shape forms, in every copy, the nodes the refit has not formed (the crossing nodes, about
+// two per chunk); without, one thread per node and copy.
+__global__ void __launch_bounds__(256) k_collapse4(const Node *__restrict__ nodes, int64_t n,
+                                                   int32_t copies,
+                                                   const WinFrame *__restrict__ frames,
+                                                   CNode4 *__restrict__ out, unsigned int *err,
+                                                   const uint8_t *__restrict__ inside) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t per = n - 1;
+    if (inside != nullptr) {
+        if (t >= per || inside[t] != 0) return;  // formed by the refit
+        for (int32_t cp = 0; cp < copies; ++cp) form_node(nodes, n, cp * per + t, cp, frames, out, err);
+        return;
+    }
+    if (t >= per * copies) return;
+    form_node(nodes, n, t, (int32_t)(t / per), frames, out, err);
 }
 
 // ------------------------------------------------------------------- refit
@@ -1417,8 +1429,8 @@ void launch_collapse4(const Node *nodes, int64_t n, int32_t copies, const WinFra
                       CNode4 *out, unsigned int *err, hipStream_t st, const uint8_t *inside) {
     const int64_t total = n > 1 ? (n - 1) * copies : 0;
     if (total <= 0) return;
-    hipLaunchKernelGGL(k_collapse4, dim3(grid_for(total, 256)), dim3(256), 0, st, nodes, n, copies,
-                       frames, out, err, inside);
+    hipLaunchKernelGGL(k_collapse4, dim3(grid_for(inside != nullptr ? n - 1 : total, 256)), dim3(256),
+                       0, st, nodes, n, copies, frames, out, err, inside);
 }
 
 void launch_win_bounds(const InstStats *stats, int32_t n_inst, double dt, WinBound *vb,
