@@ -260,7 +260,7 @@ def test_counters_and_threshold_prune(torch):
     ctx.close()
     assert st["n_builds"] == 50 and st["n_collides"] == 50
     assert st["n_queries"] == 50 * 4000
-    # every query loads its root at least once per descent (8 steps by default)
+    # every query loads its root at least once per descent (8 steps in a context's first run)
     assert st["n_node_visits"] * 8 >= st["n_queries"]
     assert st["n_candidates"] >= st["n_hits"]
 
