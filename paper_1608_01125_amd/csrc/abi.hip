@@ -92,6 +92,10 @@ struct tril_ctx {
     hipStream_t st = nullptr;       // caller stream
     hipStream_t gst = nullptr;      // internal stream for graph replay (non-blocking)
     hipEvent_t ev_join_a = nullptr, ev_join_b = nullptr;
+    // tril_run batches: the query preparation runs on qst beside the build (fork before the
+    // build, join before the traversal), with its own sort scratch
+    hipStream_t qst = nullptr;
+    hipEvent_t ev_qfork = nullptr, ev_qjoin = nullptr;
     double dt = 0.0;
     uint32_t flags = 0;
     int32_t n_bins = 0;
@@ -205,6 +209,7 @@ struct tril_ctx {
     int32_t *cand_i = nullptr, *cand_j = nullptr;
 
     SortScratch ss;
+    SortScratch ssq;                       // the query sort of tril_run batches (beside the build)
     StatsScratch sst;
     AnnScratch ann;                        // annihilation-mode resolution
     uint8_t *dead_q = nullptr, *dead_t = nullptr;  // photons consumed in this run (per row)
@@ -249,19 +254,24 @@ struct tril_ctx {
 
 namespace {
 
-int ensure_sort_scratch(tril_ctx *c, int64_t n) {
-    if (n <= c->ss.cap_n) return TRIL_OK;
+int ensure_one_sort_scratch(tril_ctx *c, SortScratch &ss, int64_t n) {
+    if (n <= ss.cap_n) return TRIL_OK;
     ++c->alloc_gen;
-    dev_free(c->ss.hist);
-    dev_free(c->ss.tile_ctr);
-    dev_free(c->ss.status);
-    c->ss.cap_n = 0;
-    CHK(dev_alloc(&c->ss.hist, 8 * 256));
-    CHK(dev_alloc(&c->ss.tile_ctr, 8));
-    CHK(dev_alloc(&c->ss.status, sort_status_words(n, 8)));
-    c->ss.cap_n = n;
-    c->ss.cap_passes = 8;
+    dev_free(ss.hist);
+    dev_free(ss.tile_ctr);
+    dev_free(ss.status);
+    ss.cap_n = 0;
+    CHK(dev_alloc(&ss.hist, 8 * 256));
+    CHK(dev_alloc(&ss.tile_ctr, 8));
+    CHK(dev_alloc(&ss.status, sort_status_words(n, 8)));
+    ss.cap_n = n;
+    ss.cap_passes = 8;
     return TRIL_OK;
+}
+
+int ensure_sort_scratch(tril_ctx *c, int64_t n) {
+    CHK(ensure_one_sort_scratch(c, c->ss, n));
+    return ensure_one_sort_scratch(c, c->ssq, n);
 }
 
 void free_target(tril_ctx *c) {
@@ -614,7 +624,8 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
 // by their Morton codes at the batch's key step (c->q_order, q.n entries: the traversal
 // repeats it for every step).
 int enqueue_query_prep(tril_ctx *c, const BeamDev &q, hipStream_t st, bool sort_queries,
-                       bool records = false) {
+                       bool records = false, SortScratch *ss = nullptr) {
+    SortScratch &sq = ss != nullptr ? *ss : c->ss;
     const KeyLayout kl = key_layout(q.n_inst, c->morton_bits);
     launch_boxes_keys(q, true, c->cloud, c->dt, c->sigma_up, c->t_stats, c->q_stats, kl,
                       key_step(q.m), records ? nullptr : c->q_box, c->q_k32a, c->q_k64a, c->q_va,
@@ -622,10 +633,10 @@ int enqueue_query_prep(tril_ctx *c, const BeamDev &q, hipStream_t st, bool sort_
     if (sort_queries && q.n > 0 && q.m > 0) {
         bool alt;
         if (!kl.wide)
-            alt = radix_sort_u32(c->q_k32a, c->q_va, c->q_k32b, c->q_vb, q.n, kl.key_bits, c->ss,
+            alt = radix_sort_u32(c->q_k32a, c->q_va, c->q_k32b, c->q_vb, q.n, kl.key_bits, sq,
                                  &c->d_cnt->err, st);
         else
-            alt = radix_sort_u64(c->q_k64a, c->q_va, c->q_k64b, c->q_vb, q.n, kl.key_bits, c->ss,
+            alt = radix_sort_u64(c->q_k64a, c->q_va, c->q_k64b, c->q_vb, q.n, kl.key_bits, sq,
                                  &c->d_cnt->err, st);
         c->q_order = (q.n <= 1) ? c->q_va : (alt ? c->q_vb : c->q_va);
         c->q_order_len = q.n;
@@ -690,16 +701,28 @@ int enqueue_grid_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, h
     return TRIL_OK;
 }
 
-int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStream_t st,
-                    bool timed, bool sort_queries) {
-    const int64_t nv = (int64_t)q.m * q.n;
+// The collide phase's prologue and query preparation (query boxes or records, and the Morton
+// order of the query rows) on stream st.
+int enqueue_collide_prep(tril_ctx *c, const BeamDev &q, hipStream_t st, bool timed,
+                         bool sort_queries, SortScratch *ss = nullptr) {
     if (timed) CHK(timing_pair(c, st, c->ev_prep, true));
     launch_prologue(c->d_cnt, 1, q.m, st);
     // a batch of steps in the plain regime: one record per query row instead of a box per
     // query and step
     const bool records = q.m >= 2 && c->cloud.on == 0;
+    CHK(enqueue_query_prep(c, q, st, sort_queries, records, ss));
+    if (timed) CHK(timing_pair(c, st, c->ev_prep, false));
+    return TRIL_OK;
+}
+
+// Collide phase on stream st: the query preparation (unless `prepped`: already enqueued,
+// see enqueue_collide_prep), then the traversal and the narrow phase.
+int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStream_t st,
+                    bool timed, bool sort_queries, bool prepped = false) {
+    const int64_t nv = (int64_t)q.m * q.n;
+    const bool records = q.m >= 2 && c->cloud.on == 0;
     if (c->win_eff > 1 && (!records || q.m != c->tgt.m)) return TRIL_E_INTERNAL;
-    CHK(enqueue_query_prep(c, q, st, sort_queries, records));
+    if (!prepped) CHK(enqueue_collide_prep(c, q, st, timed, sort_queries));
     WinArgs wa{};
     if (c->win_eff > 1) {
         wa.trec = c->t_rec;
@@ -712,7 +735,6 @@ int enqueue_collide(tril_ctx *c, const BeamDev &q, const tril_pairs &out, hipStr
         wa.reach = (float)((double)(q.m + c->win_eff + 8) * c->dt + 1e-6);
         wa.dwin = descent_window(c, c->win_eff);
     }
-    if (timed) CHK(timing_pair(c, st, c->ev_prep, false));
     if (timed) CHK(timing_pair(c, st, c->ev_trav, true));
     launch_traverse(c->nodes, c->n_int, c->root_box, c->q_box, c->q_order, c->q_order_len, nv, q.n,
                     c->inst_root, c->cand_i, c->cand_j, c->cand_cap, c->d_cnt, c->block, st,
@@ -994,6 +1016,12 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
         return fail(hip_fail(e));
     if ((e = hipEventCreateWithFlags(&c->ev_join_b, hipEventDisableTiming)) != hipSuccess)
         return fail(hip_fail(e));
+    e = hipStreamCreateWithFlags(&c->qst, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(hip_fail(e));
+    if ((e = hipEventCreateWithFlags(&c->ev_qfork, hipEventDisableTiming)) != hipSuccess)
+        return fail(hip_fail(e));
+    if ((e = hipEventCreateWithFlags(&c->ev_qjoin, hipEventDisableTiming)) != hipSuccess)
+        return fail(hip_fail(e));
     *out = c;
     return TRIL_OK;
 }
@@ -1158,12 +1186,19 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
             c->tgt.dead = c->dead_t;
             qv.dead = c->dead_q;
         }
+        // the query preparation on qst beside the build: it reads only the query working
+        // copy and the run's statistics, and writes only query buffers
+        HIPCHK(hipEventRecord(c->ev_qfork, st));
+        HIPCHK(hipStreamWaitEvent(c->qst, c->ev_qfork, 0));
         CHK(enqueue_build(c, st, tm));
         if (!sort) {
             c->q_order = nullptr;  // the working copy is already in Morton order
             c->q_order_len = 0;
         }
-        CHK(enqueue_collide(c, qv, *out, st, tm, sort));
+        CHK(enqueue_collide_prep(c, qv, c->qst, tm, sort, &c->ssq));
+        HIPCHK(hipEventRecord(c->ev_qjoin, c->qst));
+        HIPCHK(hipStreamWaitEvent(st, c->ev_qjoin, 0));
+        CHK(enqueue_collide(c, qv, *out, st, tm, sort, true));
         if (!regather) return TRIL_OK;
         launch_gather_beam(wview(t, c->d_t_off, 1, c->wt[pt]), c->t_rows, c->wt[pt ^ 1].soa,
                            c->wt[pt ^ 1].perm, st);
@@ -2615,6 +2650,7 @@ void tril_destroy(tril_ctx *c) {
     if (!c) return;
     if (c->st) (void)hipStreamSynchronize(c->st);
     if (c->gst) (void)hipStreamSynchronize(c->gst);
+    if (c->qst) (void)hipStreamSynchronize(c->qst);
     for (hipGraphExec_t &g : c->gexec)
         if (g) (void)hipGraphExecDestroy(g);
     free_target(c);
@@ -2654,6 +2690,7 @@ void tril_destroy(tril_ctx *c) {
     dev_free(c->q_keep); dev_free(c->q_rec); dev_free(c->d_q_off); dev_free(c->q_stats); dev_free(c->cand_i);
     dev_free(c->cand_j);
     dev_free(c->ss.hist); dev_free(c->ss.tile_ctr); dev_free(c->ss.status);
+    dev_free(c->ssq.hist); dev_free(c->ssq.tile_ctr); dev_free(c->ssq.status);
     StatsScratch &s = c->sst;
     dev_free(s.keys); dev_free(s.keys_alt); dev_free(s.vals); dev_free(s.vals_alt);
     dev_free(s.flags); dev_free(s.pos); dev_free(s.block_sums); dev_free(s.ti); dev_free(s.tj);
@@ -2665,6 +2702,9 @@ void tril_destroy(tril_ctx *c) {
     if (c->ev_join_a) (void)hipEventDestroy(c->ev_join_a);
     if (c->ev_join_b) (void)hipEventDestroy(c->ev_join_b);
     if (c->gst) (void)hipStreamDestroy(c->gst);
+    if (c->ev_qfork) (void)hipEventDestroy(c->ev_qfork);
+    if (c->ev_qjoin) (void)hipEventDestroy(c->ev_qjoin);
+    if (c->qst) (void)hipStreamDestroy(c->qst);
     delete c;
 }
 
