@@ -473,7 +473,8 @@ BeamDev wview(const tril_beam *b, const int64_t *d_off, int32_t m, const WorkBea
 // Working copy w of beam b (one step) in the order of the full-precision Morton codes
 // of its boxes at the device step index, using the box and key scratch of its side
 // (sized for at least b.n elements).
-int enqueue_order(tril_ctx *c, const BeamDev &b, bool query_side, WorkBeam &w, hipStream_t st) {
+int enqueue_order(tril_ctx *c, const BeamDev &b, bool query_side, WorkBeam &w, hipStream_t st,
+                  SortScratch &ss) {
     if (b.n <= 0) return TRIL_OK;
     const KeyLayout kl = key_layout(b.n_inst, 30);
     const InstStats *stats = query_side ? c->q_stats : c->t_stats;
@@ -486,10 +487,10 @@ int enqueue_order(tril_ctx *c, const BeamDev &b, bool query_side, WorkBeam &w, h
                       va, c->d_cnt, st);
     const uint32_t *rows;
     if (!kl.wide)
-        rows = radix_sort_u32(k32a, va, k32b, vb, b.n, kl.key_bits, c->ss, &c->d_cnt->err, st)
+        rows = radix_sort_u32(k32a, va, k32b, vb, b.n, kl.key_bits, ss, &c->d_cnt->err, st)
                    ? vb : va;
     else
-        rows = radix_sort_u64(k64a, va, k64b, vb, b.n, kl.key_bits, c->ss, &c->d_cnt->err, st)
+        rows = radix_sort_u64(k64a, va, k64b, vb, b.n, kl.key_bits, ss, &c->d_cnt->err, st)
                    ? vb : va;
     launch_gather_beam(b, rows, w.soa, w.perm, st);
     return TRIL_OK;
@@ -1132,8 +1133,13 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     // first, both beams in the order of their full 30-bit Morton codes at step k0
     int pt = 0, pq = 0;
     launch_set_step(c->d_cnt, k0, c->st);
-    CHK(enqueue_order(c, t1, false, c->wt[0], c->st));
-    CHK(enqueue_order(c, q1, true, c->wq[0], c->st));
+    // the two beams side by side: the query beam on qst with its own sort scratch
+    HIPCHK(hipEventRecord(c->ev_qfork, c->st));
+    HIPCHK(hipStreamWaitEvent(c->qst, c->ev_qfork, 0));
+    CHK(enqueue_order(c, t1, false, c->wt[0], c->st, c->ss));
+    CHK(enqueue_order(c, q1, true, c->wq[0], c->qst, c->ssq));
+    HIPCHK(hipEventRecord(c->ev_qjoin, c->qst));
+    HIPCHK(hipStreamWaitEvent(c->st, c->ev_qjoin, 0));
     c->morton_bits = run_morton_bits(c, t->n_inst);
     const bool once = (c->flags & TRIL_SORT_QUERIES_ONCE) != 0;
     bool q_sorted = false;
@@ -1196,15 +1202,17 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
             c->q_order_len = 0;
         }
         CHK(enqueue_collide_prep(c, qv, c->qst, tm, sort, &c->ssq));
+        // the query working copy for the next batch in this batch's order (it writes the
+        // other buffer, which this batch does not read)
+        if (regather && sort)
+            launch_gather_beam(wview(q, c->d_q_off, 1, c->wq[pq]), c->q_order, c->wq[pq ^ 1].soa,
+                               c->wq[pq ^ 1].perm, c->qst);
         HIPCHK(hipEventRecord(c->ev_qjoin, c->qst));
         HIPCHK(hipStreamWaitEvent(st, c->ev_qjoin, 0));
         CHK(enqueue_collide(c, qv, *out, st, tm, sort, true));
         if (!regather) return TRIL_OK;
         launch_gather_beam(wview(t, c->d_t_off, 1, c->wt[pt]), c->t_rows, c->wt[pt ^ 1].soa,
                            c->wt[pt ^ 1].perm, st);
-        if (sort)
-            launch_gather_beam(wview(q, c->d_q_off, 1, c->wq[pq]), c->q_order, c->wq[pq ^ 1].soa,
-                               c->wq[pq ^ 1].perm, st);
         return TRIL_OK;
     };
     int last_pq = 0;            // query working buffer of the last batch enqueued
