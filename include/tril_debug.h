@@ -68,9 +68,19 @@ int tril_dbg_gemm_bf16(const uint16_t *A, int64_t sam, int64_t sak, const uint16
  * the leaf at sorted position -2 - link (tril_dbg_target_records). *n_nodes receives
  * c (n-1) for the c copies of the last build (c = m, the build's steps, or ceil(m / W)
  * for windows of W steps; 0 below two rows). roots: host, c n_inst root links (same
- * encoding; -1: empty instance), or NULL. TRIL_E_OVERFLOW if cap_nodes < *n_nodes. */
+ * encoding; -1: empty instance), or NULL. TRIL_E_OVERFLOW if cap_nodes < *n_nodes;
+ * TRIL_E_STATE before a build, or after a build with window copies of several steps that
+ * left the binary nodes below the refit's chunk tops unstored (tril_dbg_keep_nodes). */
 int tril_dbg_tree(tril_ctx *ctx, void *nodes, int64_t cap_nodes, int64_t *n_nodes,
                   int32_t *roots);
+
+/* With window copies of several steps the traversal descends the four-child forms, and the
+ * refit stores the binary node of an internal node only where another build step reads it:
+ * the crossing nodes (those whose leaves span two 512-leaf chunks) and the chunks' top
+ * nodes. on = 1 makes later builds of ctx store every binary node as well, so that
+ * tril_dbg_tree can return the whole tree (same forms, candidates and pairs); on = 0
+ * restores the default. TRIL_E_INVAL for a NULL ctx or another value of on. */
+int tril_dbg_keep_nodes(tril_ctx *ctx, int32_t on);
 
 /* Window copies of the last build: *win receives its steps per copy (1: a copy per
  * step, and *n = 0); otherwise *n receives the target rows n and recs (host, n x 12

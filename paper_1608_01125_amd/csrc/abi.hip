@@ -178,6 +178,8 @@ struct tril_ctx {
     WinBound *t_wb = nullptr;              // window copies: per target instance, bounds of u dt
     int32_t win_eff = 1;                   // steps per tree copy of the last build
     bool quad = false;                     // the last build has four-child forms
+    bool keep_nodes = false;  // store every binary node of window copies (tril_dbg_keep_nodes)
+    bool nodes_partial = false;  // the last build stored the binary nodes of chunk tops only
     int32_t *refit_slots = nullptr;        // refit hand-offs to the crossing-level kernel
     int32_t *xlev = nullptr;               // crossing levels of the shape (batches of many steps)
     int64_t refit_slot_cap = 0;
@@ -612,7 +614,8 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
     launch_refit(t, c->cloud, c->dt, rows, c->prec, c->nflags, c->nodes, c->refit_slots,
                  c->refit_slot_cap, xbase, xalt, c->d_cnt, &c->d_cnt->err, st, win, c->t_rec,
                  c->quad ? c->t_frames : nullptr, c->quad ? c->nodes4 : nullptr,
-                 c->quad ? c->t_inside : nullptr);
+                 c->quad ? c->t_inside : nullptr, c->keep_nodes);
+    c->nodes_partial = c->quad && !c->keep_nodes;
     if (c->quad)
         launch_collapse4(c->nodes, n, copies, c->t_frames, c->nodes4, &c->d_cnt->err, st,
                          c->t_inside);
@@ -2838,7 +2841,7 @@ int tril_dbg_pair_eval32(int64_t n, const double *in, double *out, void *stream)
 
 int tril_dbg_tree(tril_ctx *c, void *nodes, int64_t cap_nodes, int64_t *n_nodes, int32_t *roots) {
     if (!c || !n_nodes) return TRIL_E_INVAL;
-    if (!c->built) return TRIL_E_STATE;
+    if (!c->built || c->nodes_partial) return TRIL_E_STATE;
     HIPCHK(hipStreamSynchronize(c->st));
     const int32_t copies = window_copies(c->tgt.m, c->win_eff);
     const int64_t nn = c->tgt.n > 1 ? (int64_t)copies * (c->tgt.n - 1) : 0;
@@ -2850,6 +2853,12 @@ int tril_dbg_tree(tril_ctx *c, void *nodes, int64_t cap_nodes, int64_t *n_nodes,
     }
     const size_t n_comb = (size_t)copies * c->tgt.n_inst;
     if (roots) HIPCHK(hipMemcpy(roots, c->inst_root, n_comb * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return TRIL_OK;
+}
+
+int tril_dbg_keep_nodes(tril_ctx *c, int32_t on) {
+    if (!c || on < 0 || on > 1) return TRIL_E_INVAL;
+    c->keep_nodes = on != 0;
     return TRIL_OK;
 }
 

@@ -906,7 +906,11 @@ __device__ __forceinline__ void climb_crossing(int32_t cur, Half cn, i32x4 r, bo
 // (min, max), so the boxes do not depend on the order of merging. With window copies
 // (win > 1) the loop runs over the n_copies copies instead of the steps, each copy's leaf
 // boxes are those of its window's middle step, a leaf's link is its sorted position, and
-// the first group's workgroups write every leaf's record.
+// the first group's workgroups write every leaf's record. With the four-child forms
+// (nodes4) and store_inner 0, a node whose parent lies in the chunk too is written only as
+// its form: its binary node is read by nothing later in the build or the traversal (the
+// crossing nodes' forms read the binary nodes of the crossing nodes and of the chunks' top
+// nodes only), which halves the refit's stores.
 template <bool kMoved>
 __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cloud, double dt,
                                                     const uint32_t *__restrict__ rows,
@@ -920,7 +924,8 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
                                                     int32_t n_copies, TRec *__restrict__ trec,
                                                     const WinFrame *__restrict__ frames,
                                                     CNode4 *__restrict__ nodes4,
-                                                    uint8_t *__restrict__ inside_flag) {
+                                                    uint8_t *__restrict__ inside_flag,
+                                                    int32_t store_inner) {
     // halves of the chunk's nodes as their parents hold them, lo (xyz, link) and hi
     // (xyz, energy bound): [0, chunk) internal node c0 + k, [chunk, 2 chunk) leaf c0 + k
     // (before the first step the same memory holds the nodes' heights)
@@ -929,6 +934,7 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
     // half indices of the children of internal node c0 + k (-1: its range leaves the chunk)
     __shared__ int2 s_child[kRefitChunk];
     __shared__ int16_t s_top[2 * kRefitChunk];  // half indices of the top nodes
+    __shared__ uint8_t s_inner[kRefitChunk];    // internal node c0 + k has its parent in the chunk
     __shared__ int32_t s_ntop, s_hmax;
     int32_t *s_height = reinterpret_cast<int32_t *>(s_lo);  // [0, 2 chunk): as the halves
     const i32x4 *grec = reinterpret_cast<const i32x4 *>(prec);
@@ -972,6 +978,7 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
     }
     __syncthreads();
     const bool inside = has_int && s_child[tid].x >= 0;  // node c0 + tid lies in the chunk
+    s_inner[tid] = inside && pin_i ? 1 : 0;
     if (in && !pin_l) s_top[atomicAdd(&s_ntop, 1)] = (int16_t)(kRefitChunk + tid);
     if (inside && !pin_i) s_top[atomicAdd(&s_ntop, 1)] = (int16_t)tid;
     // heights: a node is resolved once both children are; at least one node resolves
@@ -1096,9 +1103,12 @@ __global__ void __launch_bounds__(kRefitChunk, 8) k_refit(BeamDev b, CloudBox cl
                 op[k] = make_uint4(w4[4 * k], w4[4 * k + 1], w4[4 * k + 2], w4[4 * k + 3]);
         }
         // complete nodes, whole: word f of the chunk's node block is quarter f % 4 of node
-        // c0 + f / 4 (lo, hi of the left child, then of the right child)
+        // c0 + f / 4 (lo, hi of the left child, then of the right child); with the forms
+        // written above, only the chunk's top nodes unless store_inner
+        const bool skip_inner = kMoved && nodes4 != nullptr && store_inner == 0;
         float4 *dst = reinterpret_cast<float4 *>(nodes + base);
         for (int32_t f = tid; f < 4 * n_int; f += kRefitChunk) {
+            if (skip_inner && s_inner[f >> 2] != 0) continue;
             const int2 ch = s_child[f >> 2];
             const int32_t c = (f & 2) ? ch.y : ch.x;
             if (c >= 0) dst[f] = (f & 1) ? s_hi[c] : s_lo[c];
@@ -1468,7 +1478,7 @@ void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint
                   const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots, int64_t slot_cap,
                   int32_t *xbase, bool xalt, const DevCounters *c, unsigned int *err,
                   hipStream_t st, int32_t win, TRec *trec, const WinFrame *frames,
-                  CNode4 *nodes4, uint8_t *inside) {
+                  CNode4 *nodes4, uint8_t *inside, bool store_inner) {
     const int64_t n = b.n;
     if (cloud.on != 0) win = 1;  // window copies need straight-line leaf boxes
     if (win <= 1 || frames == nullptr || inside == nullptr) nodes4 = nullptr;
@@ -1488,11 +1498,12 @@ void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint
     if (cloud.on == 0)
         hipLaunchKernelGGL(k_refit<true>, dim3((unsigned)(chunks * groups)), dim3(kRefitChunk), 0,
                            st, b, cloud, dt, sorted_rows, chunks, group_steps, prec, flags, nodes,
-                           slots, levels ? 1 : 0, c, err, win, m, trec, frames, nodes4, inside);
+                           slots, levels ? 1 : 0, c, err, win, m, trec, frames, nodes4, inside,
+                           store_inner ? 1 : 0);
     else
         hipLaunchKernelGGL(k_refit<false>, dim3((unsigned)(chunks * groups)), dim3(kRefitChunk), 0,
                            st, b, cloud, dt, sorted_rows, chunks, group_steps, prec, flags, nodes,
-                           slots, levels ? 1 : 0, c, err, 1, m, trec, nullptr, nullptr, nullptr);
+                           slots, levels ? 1 : 0, c, err, 1, m, trec, nullptr, nullptr, nullptr, 1);
     if (levels) {
         const XLev x = xlev_layout(xbase, n);
         hipLaunchKernelGGL(k_refit_levels, dim3((unsigned)m), dim3(kXThreads), 0, st,

@@ -421,13 +421,15 @@ bool enqueue_xlevels(const PRec *prec, int64_t n, int32_t *base, const SortScrat
 // (b.n entries, by sorted position). nodes4 (window copies only, with frames formed
 // beforehand): the four-child forms of every internal node whose descendants all lie in
 // one 512-leaf chunk are written from the chunk's merged boxes, and inside (b.n - 1 bytes)
-// marks those nodes for launch_collapse4, which forms the others.
+// marks those nodes for launch_collapse4, which forms the others. With nodes4 and
+// store_inner false, the binary nodes of the nodes whose parent lies in their chunk too are
+// not stored (nothing reads them once their forms exist).
 void launch_refit(const BeamDev &b, const CloudBox &cloud, double dt, const uint32_t *sorted_rows,
                   const PRec *prec, int32_t *flags, Node *nodes, int32_t *slots, int64_t slot_cap,
                   int32_t *xbase, bool xalt, const DevCounters *c, unsigned int *err,
                   hipStream_t st, int32_t win = 1, TRec *trec = nullptr,
                   const WinFrame *frames = nullptr, CNode4 *nodes4 = nullptr,
-                  uint8_t *inside = nullptr);
+                  uint8_t *inside = nullptr, bool store_inner = true);
 
 // n_int: internal nodes of all steps' trees; root_box: box of each combined instance
 // whose root is a leaf; nq: virtual query count (steps x rows).

@@ -141,7 +141,7 @@ EXPORTS = ("tril_create", "tril_build", "tril_collide", "tril_run", "tril_stats"
            "tril_reset_counters", "tril_destroy", "tril_strerror", "tril_last_hip_error",
            "tril_dbg_sort_u32", "tril_dbg_sort_u64", "tril_dbg_morton", "tril_dbg_pair_eval",
            "tril_dbg_pair_eval32", "tril_dbg_math",
-           "tril_dbg_tree", "tril_dbg_target_records", "tril_dbg_quad_nodes", "tril_dbg_boxes", "tril_dbg_target_rows", "tril_dbg_query_records", "tril_dbg_candidates")
+           "tril_dbg_tree", "tril_dbg_keep_nodes", "tril_dbg_target_records", "tril_dbg_quad_nodes", "tril_dbg_boxes", "tril_dbg_target_rows", "tril_dbg_query_records", "tril_dbg_candidates")
 
 _lib = None
 
@@ -220,6 +220,7 @@ def lib() -> ctypes.CDLL:
     L.tril_dbg_pair_eval32.argtypes = [i64, vp, vp, vp]
     L.tril_dbg_math.argtypes = [ctypes.c_int, i64, vp, vp, vp, vp]
     L.tril_dbg_tree.argtypes = [vp, vp, i64, _i64p, _i32p]
+    L.tril_dbg_keep_nodes.argtypes = [vp, ctypes.c_int32]
     L.tril_dbg_target_records.argtypes = [vp, vp, i64, _i64p, _i32p]
     L.tril_dbg_quad_nodes.argtypes = [vp, vp, i64, _i64p, ctypes.POINTER(ctypes.c_float), _i32p]
     L.tril_st_audit.argtypes = [vp, vp, ctypes.POINTER(tril_beam), vp, vp, gp,
@@ -808,6 +809,12 @@ def tril_dbg_quad_nodes(ctx, n_target: int, m: int):
     if nc.value == 0:
         return None, None
     return nodes[: nn.value].copy(), frames[: nc.value].copy()
+
+
+def tril_dbg_keep_nodes(ctx, on: bool = True) -> None:
+    """Later builds of ctx store every binary node of window copies (tril_dbg_tree needs
+    them; the traversal reads the four-child forms)."""
+    _check(lib().tril_dbg_keep_nodes(_h(ctx), 1 if on else 0), "tril_dbg_keep_nodes")
 
 
 def tril_dbg_target_records(ctx, n_target: int):

@@ -97,6 +97,7 @@ def test_null_arguments():
     assert L.tril_dbg_sort_u64(None, None, 10, 65, None) == T.TRIL_E_INVAL
     assert L.tril_dbg_pair_eval(-1, None, None, None) == T.TRIL_E_INVAL
     assert L.tril_dbg_tree(None, None, 0, None, None) == T.TRIL_E_INVAL
+    assert L.tril_dbg_keep_nodes(None, 1) == T.TRIL_E_INVAL
 
 
 def test_pair_kinematics_rejects_null_arguments():

@@ -136,6 +136,7 @@ def test_copies_hold_middle_step_boxes_and_contain_every_step(torch, m, win):
     wl = beams.gauss_headon_1m(n=1000)
     k0 = 180
     ctx = T.Context(wl.dt, step_batch=m, kinetic_window=win)
+    T.tril_dbg_keep_nodes(ctx)  # the whole binary tree, for the dump below
     try:
         tb = T.Beam(Bc, off)
         pairs = T.Pairs(1 << 12)
@@ -267,12 +268,25 @@ def test_four_child_forms_hold_the_copies(torch, m, win):
     ctx = T.Context(wl.dt, step_batch=m, kinetic_window=win)
     try:
         tb = T.Beam(Bc, off)
+        # by default the refit leaves the binary nodes below its chunks' tops unstored: the
+        # dump refuses, and a run that stores them all gives the same forms and pairs
+        pairs0 = T.Pairs(1 << 12)
+        ctx.run(tb, tb, 170, m, pairs0)
+        q0, _ = T.tril_dbg_quad_nodes(ctx, n, m)
+        with pytest.raises(T.TrilError) as ei:
+            T.tril_dbg_tree(ctx, n, n_inst, m)
+        assert ei.value.code == T.TRIL_E_STATE
+        T.tril_dbg_keep_nodes(ctx)
         pairs = T.Pairs(1 << 12)
         ctx.run(tb, tb, 170, m, pairs)
         tree = T.tril_dbg_tree(ctx, n, n_inst, m)
         q, frames = T.tril_dbg_quad_nodes(ctx, n, m)
     finally:
         ctx.close()
+    assert np.array_equal(q0, q)
+    got0 = sorted(zip(*(a.tolist() for a in pairs0.numpy())))
+    got = sorted(zip(*(a.tolist() for a in pairs.numpy())))
+    assert got0 == got
     copies = tree["copies"]
     n_int = n - 1
     assert q.shape == (copies * n_int, 16) and frames.shape == (copies, 8)
