@@ -119,8 +119,10 @@ typedef struct {
     int64_t cand_cap;             /* broad-phase candidates one step may hold (0 = default) */
     int32_t block_traverse;       /* traversal workgroup size: 64, 128, 256, 512 or 0 = default (64) */
     int32_t step_batch;           /* tril_run: steps per launch, >= 0 (0 = as many as keep one
-                                     launch within 2^27 photon-steps, or, for beams of more
-                                     than 2^22 photons, 32 steps within 2^29) */
+                                     launch within 2^29 photon-steps with window copies
+                                     (kinetic_window != 1, plain regime); otherwise within
+                                     2^27, or, for beams of more than 2^22 photons, 32
+                                     steps within 2^29) */
     int32_t morton_bits;          /* Morton bits of the sort keys, 3..30, or 0 = automatic:
                                      30 (10 per axis) for tril_build/tril_collide; for tril_run,
                                      which first puts both beams in the order of their full
@@ -214,7 +216,9 @@ int tril_collide(tril_ctx *ctx, const tril_beam *query, int32_t step, tril_pairs
  * traversal launch answers the queries of all m steps. Full batches are captured once
  * in a HIP graph and replayed, the step index living in device memory; with
  * TRIL_TIMING every batch runs eagerly with HIP events around each phase. Scratch
- * grows with m x (photons per beam). */
+ * grows with m x (photons per beam): about 150 bytes per photon-step with a copy per
+ * step; with window copies about 170 bytes per photon and copy (boxes, flags, binary and
+ * four-child nodes) plus 16 bytes of candidate room per photon-step. */
 int tril_run(tril_ctx *ctx, const tril_beam *target, const tril_beam *query,
              int32_t k0, int32_t n_steps, tril_pairs *out);
 

@@ -75,6 +75,10 @@ constexpr int64_t kBatchBudget = (int64_t)1 << 27;  // default virtual elements 
 // scratch each) so that a launch still covers kBatchStepsMin steps
 constexpr int64_t kBatchBudgetMax = (int64_t)1 << 29;
 constexpr int64_t kBatchStepsMin = 32;
+// with window copies (the plain regime) a launch's tree buffers hold a copy per window, not
+// per step, and its query buffers one record per row: every beam takes up to kBatchBudgetMax
+// virtual elements per launch (the whole 400-step run of two 1e6-photon beams in one launch,
+// so one order, one emission and one set of launch tails serve all its steps)
 
 }  // namespace
 
@@ -242,8 +246,11 @@ struct tril_ctx {
     const uint32_t *t_rows = nullptr;      // sorted rows of the last build
 
     // captured step-batch graphs (one per working-buffer parity)
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    std::vector<const void *> gkey[2];
+    // captured batches: the two buffer parities, each with and without the re-gather for a
+    // following batch
+    static constexpr int kGraphs = 4;
+    hipGraphExec_t gexec[kGraphs] = {};
+    std::vector<const void *> gkey[kGraphs];
     int g_next = 0;
     uint64_t alloc_gen = 0;         // bumped on every (re)allocation of scratch
 
@@ -345,13 +352,16 @@ int ensure_target(tril_ctx *c, int64_t nv, int64_t n, int64_t n_comb, int32_t n_
     return ensure_sort_scratch(c, n);
 }
 
-// Query buffers: boxes per virtual element (nv), keys and orders per row (n).
-int ensure_query(tril_ctx *c, int64_t nv, int64_t n, int64_t n_comb, int32_t n_inst) {
-    if (nv > c->q_cap) {
+// Query buffers: boxes for nv_box virtual elements (nv when negative), candidates for nv,
+// keys and orders per row (n).
+int ensure_query(tril_ctx *c, int64_t nv, int64_t n, int64_t n_comb, int32_t n_inst,
+                 int64_t nv_box = -1) {
+    if (nv_box < 0) nv_box = nv;
+    if (nv_box > c->q_cap) {
         ++c->alloc_gen;
         dev_free(c->q_box);
         c->q_cap = 0;
-        const int64_t m = std::max<int64_t>(nv, 1);
+        const int64_t m = std::max<int64_t>(nv_box, 1);
         CHK(dev_alloc(&c->q_box, m));
         c->q_cap = m;
     }
@@ -895,12 +905,22 @@ int run_morton_bits(const tril_ctx *c, int64_t n_inst) {
 }
 
 // Steps per launch for tril_run: the parameter if set, else as many as keep the
-// virtual element count of one launch within kBatchBudget.
+// virtual element count of one launch within the budget (kBatchBudgetMax with window
+// copies; else kBatchBudget, raised for large beams towards kBatchStepsMin steps).
 int32_t pick_batch(const tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t n_steps) {
     const int64_t rows = std::max<int64_t>(std::max(t->n, q->n), 1);
+    const bool windows = c->cloud.on == 0 && c->kwin != 1;
     const int64_t budget =
-        std::max(kBatchBudget, std::min(kBatchBudgetMax, kBatchStepsMin * rows));
+        windows ? kBatchBudgetMax
+                : std::max(kBatchBudget, std::min(kBatchBudgetMax, kBatchStepsMin * rows));
     int64_t m = c->step_batch > 0 ? c->step_batch : std::max<int64_t>(1, budget / rows);
+    if (c->step_batch <= 0 && windows && m < n_steps) {
+        // a batch's last copy of fewer than w/8 steps would cost a whole copy's refit for
+        // those few steps: they go to the next batch (1.6e7-photon beams: 32 steps per
+        // launch rather than 33, one copy per launch instead of two)
+        const int64_t w = c->kwin > 1 ? c->kwin : kDefaultWindow;
+        if (m > w && m % w < (w + 7) / 8) m -= m % w;
+    }
     m = std::min<int64_t>(m, n_steps);
     m = std::min<int64_t>(m, std::max<int64_t>(1, (kMaxN - 1) / rows));
     m = std::min<int64_t>(m, std::max<int64_t>(1, kMaxComb / std::max(t->n_inst, 1)));
@@ -1092,9 +1112,12 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
         return TRIL_OK;
     }
     const int32_t m = pick_batch(c, t, q, n_steps);
-    // capacities for the largest batch first, so that nothing is reallocated later
-    CHK(ensure_target(c, (int64_t)m * t->n, t->n, (int64_t)m * t->n_inst, t->n_inst));
     const int32_t bw = build_window(c, m);
+    // capacities for the largest batch first, so that nothing is reallocated later: tree
+    // buffers per copy (a batch's last, shorter one needs no more copies), query boxes only
+    // where a batch of one step or the cloud regime writes them (else per-row records)
+    const int64_t t_units = bw > 1 ? (int64_t)window_copies(m, bw) : m;
+    CHK(ensure_target(c, t_units * t->n, t->n, (int64_t)m * t->n_inst, t->n_inst));
     if (bw > 1 && t->n > 1) {  // four-child forms of the window copies
         const int64_t need = (int64_t)window_copies(m, bw) * (t->n - 1);
         if (need > c->nodes4_cap) {
@@ -1120,7 +1143,9 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
             c->frames_cap = nf;
         }
     }
-    CHK(ensure_query(c, (int64_t)m * q->n, q->n, (int64_t)m * q->n_inst, q->n_inst));
+    const bool q_records = m >= 2 && c->cloud.on == 0;
+    CHK(ensure_query(c, (int64_t)m * q->n, q->n, (int64_t)m * q->n_inst, q->n_inst,
+                     q_records ? q->n : (int64_t)m * q->n));
     CHK(ensure_work(c, c->wt, t->n));
     CHK(ensure_work(c, c->wq, q->n));
     CHK(upload_offsets(c, t, c->d_t_off, c->h_t_off));
@@ -1128,17 +1153,18 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     c->nt = t->n;
     c->q_order_key = nullptr;  // the sort buffers are reused below
     const BeamDev t1 = view(t, c->d_t_off, 1), q1 = view(q, c->d_q_off, 1);
-    launch_beam_stats(t1, c->t_spart, c->t_stats, c->d_cnt, c->st, true);
-    launch_beam_stats(q1, c->q_spart, c->q_stats, c->d_cnt, c->st, true);
     // working copies in the caller's order; after every batch they are rewritten in the
     // Morton order of that batch's first step (a relabelling of rows: the pair set does
     // not depend on it, and the narrow phase reports caller rows)
     // first, both beams in the order of their full 30-bit Morton codes at step k0
     int pt = 0, pq = 0;
     launch_set_step(c->d_cnt, k0, c->st);
-    // the two beams side by side: the query beam on qst with its own sort scratch
+    // the two beams side by side (statistics, then order): the query beam on qst with its
+    // own sort scratch
     HIPCHK(hipEventRecord(c->ev_qfork, c->st));
     HIPCHK(hipStreamWaitEvent(c->qst, c->ev_qfork, 0));
+    launch_beam_stats(t1, c->t_spart, c->t_stats, c->d_cnt, c->st, true);
+    launch_beam_stats(q1, c->q_spart, c->q_stats, c->d_cnt, c->qst, true);
     CHK(enqueue_order(c, t1, false, c->wt[0], c->st, c->ss));
     CHK(enqueue_order(c, q1, true, c->wq[0], c->qst, c->ssq));
     HIPCHK(hipEventRecord(c->ev_qjoin, c->qst));
@@ -1251,6 +1277,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
         HIPCHK(hipEventRecord(c->ev_join_a, c->st));
         HIPCHK(hipStreamWaitEvent(c->gst, c->ev_join_a, 0));
         for (int32_t r = 0; r < n_rep; ++r) {
+            const bool regather = r + 1 < n_rep || left > n_rep * m;  // another batch follows
             std::vector<const void *> key = {
                 c->wt[pt].soa, c->wq[pq].soa, c->wt[pt ^ 1].soa, c->wq[pq ^ 1].soa,
                 out->i, out->j, out->step, out->count,
@@ -1263,19 +1290,21 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
                 (const void *)(intptr_t)c->block, (const void *)(uintptr_t)c->flags,
                 (const void *)(intptr_t)c->trav_queue,
                 (const void *)(intptr_t)c->cand_cap, (const void *)(intptr_t)c->kwin,
-                (const void *)(intptr_t)c->kdesc, (const void *)(intptr_t)c->kdesc_auto};
-            int slot = (c->gexec[0] && key == c->gkey[0]) ? 0
-                       : (c->gexec[1] && key == c->gkey[1]) ? 1 : -1;
+                (const void *)(intptr_t)c->kdesc, (const void *)(intptr_t)c->kdesc_auto,
+                (const void *)(intptr_t)regather};
+            int slot = -1;
+            for (int g = 0; g < tril_ctx::kGraphs && slot < 0; ++g)
+                if (c->gexec[g] && key == c->gkey[g]) slot = g;
             if (slot < 0) {
                 slot = c->g_next;
-                c->g_next ^= 1;
+                c->g_next = (c->g_next + 1) % tril_ctx::kGraphs;
                 if (c->gexec[slot]) {
                     (void)hipGraphExecDestroy(c->gexec[slot]);
                     c->gexec[slot] = nullptr;
                 }
                 hipGraph_t g = nullptr;
                 HIPCHK(hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
-                int r1 = enqueue_batch(m, sort, c->gst, false, true);
+                int r1 = enqueue_batch(m, sort, c->gst, false, regather);
                 launch_advance_step(c->d_cnt, m, c->gst);
                 hipError_t e = hipStreamEndCapture(c->gst, &g);
                 if (r1 != TRIL_OK) {
@@ -2903,16 +2932,27 @@ int tril_dbg_boxes(tril_ctx *c, int which, void *boxes, int64_t cap, int64_t *n)
     if (nn > cap) return TRIL_E_OVERFLOW;
     if (nn > 0) {
         if (!boxes) return TRIL_E_INVAL;
+        PBox *src = which == 0 ? c->t_box : c->q_box, *tmp = nullptr;
         if (which == 0) {
-            // the refit forms the target's leaf boxes itself: recompute them as it did
+            // the refit forms the target's leaf boxes itself: recompute them as it did (into
+            // a buffer of its own where the tree buffers hold copies, not steps)
             if (!c->built) return TRIL_E_STATE;
+            if (nn > c->t_cap) {
+                CHK(dev_alloc(&tmp, (size_t)nn));
+                src = tmp;
+            }
             launch_set_step(c->d_cnt, c->tgt_k0, c->st);
-            launch_leaf_boxes(c->tgt, c->tgt_cloud, c->dt, c->d_cnt, c->t_box, c->st);
-            HIPCHK(hipGetLastError());
-            HIPCHK(hipStreamSynchronize(c->st));
+            launch_leaf_boxes(c->tgt, c->tgt_cloud, c->dt, c->d_cnt, src, c->st);
+            const hipError_t e = hipGetLastError();
+            const hipError_t e2 = hipStreamSynchronize(c->st);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                dev_free(tmp);
+                HIPCHK(e != hipSuccess ? e : e2);
+            }
         }
-        HIPCHK(hipMemcpy(boxes, which == 0 ? c->t_box : c->q_box, nn * sizeof(PBox),
-                         hipMemcpyDeviceToHost));
+        const hipError_t e = hipMemcpy(boxes, src, nn * sizeof(PBox), hipMemcpyDeviceToHost);
+        dev_free(tmp);
+        HIPCHK(e);
     }
     return TRIL_OK;
 }

@@ -770,9 +770,12 @@ __device__ __forceinline__ void form_node(const Node *__restrict__ nodes, int64_
     for (int k = 0; k < 4; ++k) op[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
 }
 
-// Four-child forms of the copies' internal nodes: with `inside`, one thread per node of the
-// shape forms, in every copy, the nodes the refit has not formed (the crossing nodes, about
-// two per chunk); without, one thread per node and copy.
+// Four-child forms of the copies' internal nodes. With `inside` (one byte per node of the
+// shape, nonzero where the refit has formed the node), a workgroup takes kCollapseSpan nodes
+// of the shape, lists the others (the crossing nodes, about two per chunk) in LDS, and forms
+// each of them in every copy, one (node, copy) pair per thread; without, one thread per node
+// and copy.
+constexpr int kCollapseSpan = 4096;
 __global__ void __launch_bounds__(256) k_collapse4(const Node *__restrict__ nodes, int64_t n,
                                                    int32_t copies,
                                                    const WinFrame *__restrict__ frames,
@@ -781,8 +784,21 @@ __global__ void __launch_bounds__(256) k_collapse4(const Node *__restrict__ node
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t per = n - 1;
     if (inside != nullptr) {
-        if (t >= per || inside[t] != 0) return;  // formed by the refit
-        for (int32_t cp = 0; cp < copies; ++cp) form_node(nodes, n, cp * per + t, cp, frames, out, err);
+        __shared__ uint32_t s_list[kCollapseSpan];
+        __shared__ uint32_t s_n;
+        if (threadIdx.x == 0) s_n = 0u;
+        __syncthreads();
+        const int64_t x0 = (int64_t)blockIdx.x * kCollapseSpan;
+        for (int k = threadIdx.x; k < kCollapseSpan; k += blockDim.x) {
+            const int64_t x = x0 + k;
+            if (x < per && inside[x] == 0) s_list[atomicAdd(&s_n, 1u)] = (uint32_t)x;
+        }
+        __syncthreads();
+        const int64_t nc = s_n;
+        for (int64_t u = threadIdx.x; u < nc * copies; u += blockDim.x) {
+            const int32_t cp = (int32_t)(u / nc);
+            form_node(nodes, n, cp * per + s_list[u - cp * nc], cp, frames, out, err);
+        }
         return;
     }
     if (t >= per * copies) return;
@@ -1439,8 +1455,10 @@ void launch_collapse4(const Node *nodes, int64_t n, int32_t copies, const WinFra
                       CNode4 *out, unsigned int *err, hipStream_t st, const uint8_t *inside) {
     const int64_t total = n > 1 ? (n - 1) * copies : 0;
     if (total <= 0) return;
-    hipLaunchKernelGGL(k_collapse4, dim3(grid_for(inside != nullptr ? n - 1 : total, 256)), dim3(256),
-                       0, st, nodes, n, copies, frames, out, err, inside);
+    hipLaunchKernelGGL(k_collapse4,
+                       dim3((unsigned)(inside != nullptr ? grid_for(n - 1, kCollapseSpan)
+                                                         : grid_for(total, 256))),
+                       dim3(256), 0, st, nodes, n, copies, frames, out, err, inside);
 }
 
 void launch_win_bounds(const InstStats *stats, int32_t n_inst, double dt, WinBound *vb,

@@ -391,9 +391,9 @@ void launch_win_frames(const InstStats *stats, int32_t n_inst, double dt, int32_
                        const DevCounters *c, WinFrame *frames, hipStream_t st);
 // Four-child forms of the copies x (n - 1) internal nodes (n rows) of window copies, in their
 // copies' frames; a child box outside its frame, or children that are not a split and its
-// successor, set kErrInternal. inside: NULL, or one byte per internal node, nonzero where
-// the refit has written the node's forms already (the node and its descendants lie in one
-// of its chunks); only the other nodes are formed here.
+// successor, set kErrInternal. inside: NULL, or one byte per internal node of the shape,
+// nonzero where the refit has written the node's forms already (the node and its
+// descendants lie in one of its chunks); only the other nodes are formed here, in every copy.
 void launch_collapse4(const Node *nodes, int64_t n, int32_t copies, const WinFrame *frames,
                       CNode4 *out, unsigned int *err, hipStream_t st,
                       const uint8_t *inside = nullptr);
