@@ -246,8 +246,8 @@ struct tril_ctx {
     const uint32_t *t_rows = nullptr;      // sorted rows of the last build
 
     // captured step-batch graphs (one per working-buffer parity)
-    // captured batches: the two buffer parities, each with and without the re-gather for a
-    // following batch
+    // captured batches: a run's first batch (no sorts), the two buffer parities with the
+    // re-gather for a following batch, and a last batch without it
     static constexpr int kGraphs = 4;
     hipGraphExec_t gexec[kGraphs] = {};
     std::vector<const void *> gkey[kGraphs];
@@ -482,21 +482,27 @@ BeamDev wview(const tril_beam *b, const int64_t *d_off, int32_t m, const WorkBea
     return v;
 }
 
-// Working copy w of beam b (one step) in the order of the full-precision Morton codes
-// of its boxes at the device step index, using the box and key scratch of its side
-// (sized for at least b.n elements).
+// Step offset within a batch of m steps whose Morton order shapes the batch's trees
+// (the middle one: no step of the batch is more than m/2 steps from it).
+inline int32_t key_step(int32_t m) { return m > 0 ? (m - 1) / 2 : 0; }
+
+// Working copy w of beam b in the order of the Morton codes a batch of b.m steps from the
+// device step index sorts it by (its key step, the run's Morton bits, each beam in its own
+// frame; the query padding moves no box centre), using the key scratch of its side (sized
+// for at least b.n elements). A stable sort of the working copy by the same keys is then
+// the identity, so that batch skips its sorts (enqueue_build's presorted, a query
+// preparation without sort).
 int enqueue_order(tril_ctx *c, const BeamDev &b, bool query_side, WorkBeam &w, hipStream_t st,
                   SortScratch &ss) {
     if (b.n <= 0) return TRIL_OK;
-    const KeyLayout kl = key_layout(b.n_inst, 30);
+    const KeyLayout kl = key_layout(b.n_inst, c->morton_bits);
     const InstStats *stats = query_side ? c->q_stats : c->t_stats;
-    PBox *box = query_side ? c->q_box : c->t_box;
     uint32_t *k32a = query_side ? c->q_k32a : c->t_k32a, *k32b = query_side ? c->q_k32b : c->t_k32b;
     unsigned long long *k64a = query_side ? c->q_k64a : c->t_k64a;
     unsigned long long *k64b = query_side ? c->q_k64b : c->t_k64b;
     uint32_t *va = query_side ? c->q_va : c->t_va, *vb = query_side ? c->q_vb : c->t_vb;
-    launch_boxes_keys(b, false, c->cloud, c->dt, c->sigma_up, stats, stats, kl, 0, box, k32a, k64a,
-                      va, c->d_cnt, st);
+    launch_boxes_keys(b, false, c->cloud, c->dt, c->sigma_up, stats, stats, kl, key_step(b.m),
+                      nullptr, k32a, k64a, va, c->d_cnt, st);
     const uint32_t *rows;
     if (!kl.wide)
         rows = radix_sort_u32(k32a, va, k32b, vb, b.n, kl.key_bits, ss, &c->d_cnt->err, st)
@@ -527,9 +533,6 @@ int timing_pair(tril_ctx *c, hipStream_t st, std::vector<std::array<int, 2>> &ds
     return TRIL_OK;
 }
 
-// Step offset within a batch of m steps whose Morton order shapes the batch's trees
-// (the middle one: no step of the batch is more than m/2 steps from it).
-inline int32_t key_step(int32_t m) { return m > 0 ? (m - 1) / 2 : 0; }
 
 // Steps per tree copy for a batch of m steps: window copies only in the plain regime
 // (straight-line leaf boxes, query records), at most m.
@@ -577,7 +580,7 @@ void adapt_descent(tril_ctx *c, int64_t checks, int64_t queries) {
 // rows by their Morton codes at the batch's key step, the tree shape emitted from that
 // order, and its copies (one per step, or one per window of steps) filled with the boxes
 // of their steps.
-int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
+int enqueue_build(tril_ctx *c, hipStream_t st, bool timed, bool presorted = false) {
     const BeamDev &t = c->tgt;
     const int64_t n = t.n;
     const int32_t win = build_window(c, t.m);
@@ -591,15 +594,16 @@ int enqueue_build(tril_ctx *c, hipStream_t st, bool timed) {
                       key_step(t.m), nullptr, c->t_k32a, c->t_k64a, c->t_va, c->d_cnt, st);
     const uint32_t *rows = nullptr;
     int32_t *roots = t.n_inst > 1 ? c->inst_base : nullptr;
+    // presorted: the working copy is in the order of these keys already (enqueue_order)
     if (!kl.wide) {
-        const bool alt = radix_sort_u32(c->t_k32a, c->t_va, c->t_k32b, c->t_vb, n, kl.key_bits,
-                                        c->ss, &c->d_cnt->err, st);
+        const bool alt = !presorted && radix_sort_u32(c->t_k32a, c->t_va, c->t_k32b, c->t_vb, n,
+                                                      kl.key_bits, c->ss, &c->d_cnt->err, st);
         const uint32_t *keys = alt ? c->t_k32b : c->t_k32a;
         rows = alt ? c->t_vb : c->t_va;
         launch_karras_u32(keys, n, kl.prefix_shift, c->prec, roots, st);
     } else {
-        const bool alt = radix_sort_u64(c->t_k64a, c->t_va, c->t_k64b, c->t_vb, n, kl.key_bits,
-                                        c->ss, &c->d_cnt->err, st);
+        const bool alt = !presorted && radix_sort_u64(c->t_k64a, c->t_va, c->t_k64b, c->t_vb, n,
+                                                      kl.key_bits, c->ss, &c->d_cnt->err, st);
         const unsigned long long *keys = alt ? c->t_k64b : c->t_k64a;
         rows = alt ? c->t_vb : c->t_va;
         launch_karras_u64(keys, n, kl.prefix_shift, c->prec, roots, st);
@@ -1156,8 +1160,11 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     // working copies in the caller's order; after every batch they are rewritten in the
     // Morton order of that batch's first step (a relabelling of rows: the pair set does
     // not depend on it, and the narrow phase reports caller rows)
-    // first, both beams in the order of their full 30-bit Morton codes at step k0
+    // first, both beams in the order the first batch's sorts would give them, which those
+    // sorts then skip
     int pt = 0, pq = 0;
+    c->morton_bits = run_morton_bits(c, t->n_inst);
+    const int32_t m0 = std::min(m, n_steps);
     launch_set_step(c->d_cnt, k0, c->st);
     // the two beams side by side (statistics, then order): the query beam on qst with its
     // own sort scratch
@@ -1165,11 +1172,10 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     HIPCHK(hipStreamWaitEvent(c->qst, c->ev_qfork, 0));
     launch_beam_stats(t1, c->t_spart, c->t_stats, c->d_cnt, c->st, true);
     launch_beam_stats(q1, c->q_spart, c->q_stats, c->d_cnt, c->qst, true);
-    CHK(enqueue_order(c, t1, false, c->wt[0], c->st, c->ss));
-    CHK(enqueue_order(c, q1, true, c->wq[0], c->qst, c->ssq));
+    CHK(enqueue_order(c, view(t, c->d_t_off, m0), false, c->wt[0], c->st, c->ss));
+    CHK(enqueue_order(c, view(q, c->d_q_off, m0), true, c->wq[0], c->qst, c->ssq));
     HIPCHK(hipEventRecord(c->ev_qjoin, c->qst));
     HIPCHK(hipStreamWaitEvent(c->st, c->ev_qjoin, 0));
-    c->morton_bits = run_morton_bits(c, t->n_inst);
     const bool once = (c->flags & TRIL_SORT_QUERIES_ONCE) != 0;
     bool q_sorted = false;
     const bool timed = (c->flags & TRIL_TIMING) != 0;
@@ -1213,8 +1219,10 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
 
     // Batch of mb steps with working buffers (pt, pq) on stream st: build, collide, and
     // (regather: another batch follows) rewrite the working copies for the next batch.
-    auto enqueue_batch = [&](int32_t mb, bool sort, hipStream_t st, bool tm,
-                             bool regather) -> int {
+    // pre: the run's first batch, whose working copies are in its order already (no sorts;
+    // sort is then false)
+    auto enqueue_batch = [&](int32_t mb, bool sort, hipStream_t st, bool tm, bool regather,
+                             bool pre) -> int {
         c->tgt = wview(t, c->d_t_off, mb, c->wt[pt]);
         BeamDev qv = wview(q, c->d_q_off, mb, c->wq[pq]);
         if (ann) {
@@ -1225,7 +1233,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
         // copy and the run's statistics, and writes only query buffers
         HIPCHK(hipEventRecord(c->ev_qfork, st));
         HIPCHK(hipStreamWaitEvent(c->qst, c->ev_qfork, 0));
-        CHK(enqueue_build(c, st, tm));
+        CHK(enqueue_build(c, st, tm, pre));
         if (!sort) {
             c->q_order = nullptr;  // the working copy is already in Morton order
             c->q_order_len = 0;
@@ -1253,26 +1261,30 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
 
     int32_t k = k0;
     int32_t left = n_steps;
+    bool presorted = true;  // the first batch's working copies are in its order
     while (left > 0) {
         const int32_t mb = std::min(m, left);
-        const bool sort = !once || !q_sorted;
-        if (timed || mb != m || sort != (!once)) {
+        const bool pre = presorted;
+        presorted = false;
+        const bool sort = (!once || !q_sorted) && !pre;
+        if (timed || mb != m || (!pre && sort != (!once))) {
             // eager batch (per-phase events, the shorter last batch, or the one batch that
             // orders the queries when they are ordered once)
             launch_set_step(c->d_cnt, k, c->st);
-            CHK(enqueue_batch(mb, sort, c->st, timed, left > mb));
+            CHK(enqueue_batch(mb, sort, c->st, timed, left > mb, pre));
             last_pq = pq;
             last_mb = mb;
             flip(sort);
             CHK(resolve(c->st, k + mb - 1));
-            q_sorted = q_sorted || sort;
+            q_sorted = q_sorted || sort || pre;
             k += mb;
             left -= mb;
             continue;
         }
-        // full batches: captured graphs (one per buffer parity), replayed; the step index
-        // lives on the device
-        const int32_t n_rep = left / m;
+        // full batches: captured graphs (the first batch, then one per buffer parity),
+        // replayed; the step index lives on the device
+        const int32_t n_rep = pre ? 1 : left / m;
+        q_sorted = q_sorted || pre;
         launch_set_step(c->d_cnt, k, c->st);
         HIPCHK(hipEventRecord(c->ev_join_a, c->st));
         HIPCHK(hipStreamWaitEvent(c->gst, c->ev_join_a, 0));
@@ -1291,7 +1303,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
                 (const void *)(intptr_t)c->trav_queue,
                 (const void *)(intptr_t)c->cand_cap, (const void *)(intptr_t)c->kwin,
                 (const void *)(intptr_t)c->kdesc, (const void *)(intptr_t)c->kdesc_auto,
-                (const void *)(intptr_t)regather};
+                (const void *)(intptr_t)regather, (const void *)(intptr_t)pre};
             int slot = -1;
             for (int g = 0; g < tril_ctx::kGraphs && slot < 0; ++g)
                 if (c->gexec[g] && key == c->gkey[g]) slot = g;
@@ -1304,7 +1316,7 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
                 }
                 hipGraph_t g = nullptr;
                 HIPCHK(hipStreamBeginCapture(c->gst, hipStreamCaptureModeThreadLocal));
-                int r1 = enqueue_batch(m, sort, c->gst, false, regather);
+                int r1 = enqueue_batch(m, sort, c->gst, false, regather, pre);
                 launch_advance_step(c->d_cnt, m, c->gst);
                 hipError_t e = hipStreamEndCapture(c->gst, &g);
                 if (r1 != TRIL_OK) {
