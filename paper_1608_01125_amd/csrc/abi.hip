@@ -149,6 +149,10 @@ struct tril_ctx {
     double sigma_up = 0.0;
     DevCounters *d_cnt = nullptr;
     DevCounters *h_cnt = nullptr;   // pinned host mirror
+    // pinned words tril_stats reads back in one round trip: hit count, unique pairs, error
+    // flags, yield and spectrum, per-step counts
+    unsigned long long *h_pin = nullptr;
+    int64_t h_pin_cap = 0;
 
     // target (hierarchy) state; capacities count virtual elements (steps x rows)
     int64_t t_cap = 0, t_row_cap = 0;  // virtual elements (steps x rows), rows
@@ -1364,8 +1368,22 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     if (p) CHK(check_pairs(p));
     if (out->n_step_counts < 0 || (out->n_step_counts > 0 && !out->step_counts))
         return TRIL_E_INVAL;
+    // host words: [0] hits, [1] unique pairs, [2] error flags, [3, 4 + n_bins) yield and
+    // spectrum, then the per-step counts; the device copies go into them asynchronously, and
+    // one synchronisation ends each group
+    const int64_t words = 4 + (int64_t)c->n_bins + out->n_step_counts;
+    if (words > c->h_pin_cap) {
+        HIPCHK(hipStreamSynchronize(c->st));
+        if (c->h_pin) (void)hipHostFree(c->h_pin);
+        c->h_pin = nullptr;
+        c->h_pin_cap = 0;
+        HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&c->h_pin), (size_t)words * sizeof(*c->h_pin)));
+        c->h_pin_cap = words;
+    }
+    unsigned long long *hp = c->h_pin;
+    HIPCHK(hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, c->st));
+    if (p) HIPCHK(hipMemcpyAsync(hp, p->count, sizeof(int64_t), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
-    HIPCHK(hipMemcpy(c->h_cnt, c->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost));
     const DevCounters &h = *c->h_cnt;
     out->n_candidates = (int64_t)h.cand_total + (int64_t)h.st_pairs;
     int64_t visits = 0, queries = 0, checks = 0;
@@ -1397,8 +1415,7 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
     if (err & (kErrSpin | kErrInternal)) return TRIL_E_INTERNAL;
     if (err & kErrCandOverflow) return TRIL_E_OVERFLOW;
     if (!p) return TRIL_OK;
-    int64_t n_hits = 0;
-    HIPCHK(hipMemcpy(&n_hits, p->count, sizeof(int64_t), hipMemcpyDeviceToHost));
+    int64_t n_hits = (int64_t)hp[0];
     out->n_hits = n_hits;
     if (n_hits > p->cap || (err & kErrPairOverflow)) return TRIL_E_OVERFLOW;
     if (n_hits > 0 && (!c->built || c->last_q.n <= 0)) return TRIL_E_STATE;
@@ -1412,34 +1429,31 @@ int tril_stats(tril_ctx *c, tril_pairs *p, tril_stats_t *out) {
         n_hits = kept;
         out->n_hits = kept;
     }
-    const int step_bits = std::max(1, bits_for((uint64_t)std::max(c->max_step, 0)));
     const int pair_bits = bits_for((uint64_t)std::max<int64_t>(c->max_nq, 1) *
                                    (uint64_t)std::max<int64_t>(c->nt, 1));
-    if (pair_bits + step_bits > 64) return TRIL_E_NOTIMPL;
+    if (pair_bits > 64) return TRIL_E_NOTIMPL;
     const int32_t nsc = out->step_counts ? out->n_step_counts : 0;
     CHK(ensure_stats(c, n_hits, std::max(nsc, 1)));
-    run_union_stats(*p, n_hits, std::max<int64_t>(c->nt, 1), step_bits, pair_bits + step_bits,
+    run_union_stats(*p, n_hits, std::max<int64_t>(c->nt, 1), pair_bits,
                     c->last_q.w, c->res_t.w, c->last_q.E, c->res_t.E, c->d_edges, c->n_bins, nsc,
                     c->sst, c->ss, &c->d_cnt->err, c->st);
     HIPCHK(hipGetLastError());
+    unsigned int *herr = reinterpret_cast<unsigned int *>(hp + 2);
+    const double *acc = reinterpret_cast<const double *>(hp + 3);
+    HIPCHK(hipMemcpyAsync(hp + 1, c->sst.ucount, sizeof(*hp), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(herr, &c->d_cnt->err, sizeof(*herr), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(hp + 3, c->sst.acc, ((size_t)c->n_bins + 1) * sizeof(double),
+                          hipMemcpyDeviceToHost, c->st));
+    if (nsc > 0)
+        HIPCHK(hipMemcpyAsync(hp + 4 + c->n_bins, c->sst.step_counts, (size_t)nsc * sizeof(*hp),
+                              hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
-    unsigned long long uc = 0;
-    HIPCHK(hipMemcpy(&uc, c->sst.ucount, sizeof(uc), hipMemcpyDeviceToHost));
-    std::vector<double> acc((size_t)c->n_bins + 1, 0.0);
-    HIPCHK(hipMemcpy(acc.data(), c->sst.acc, acc.size() * sizeof(double), hipMemcpyDeviceToHost));
-    out->n_pairs = (int64_t)uc;
+    out->n_pairs = (int64_t)hp[1];
     out->yield = acc[0];
     if (out->spectrum)
         for (int32_t b = 0; b < c->n_bins; ++b) out->spectrum[b] = acc[1 + b];
-    if (nsc > 0) {
-        std::vector<unsigned long long> sc((size_t)nsc);
-        HIPCHK(hipMemcpy(sc.data(), c->sst.step_counts, sc.size() * sizeof(unsigned long long),
-                         hipMemcpyDeviceToHost));
-        for (int32_t k = 0; k < nsc; ++k) out->step_counts[k] = (int64_t)sc[k];
-    }
-    unsigned int err2 = 0;
-    HIPCHK(hipMemcpy(&err2, &c->d_cnt->err, sizeof(err2), hipMemcpyDeviceToHost));
-    if (err2 & (kErrSpin | kErrInternal)) return TRIL_E_INTERNAL;
+    for (int32_t k = 0; k < nsc; ++k) out->step_counts[k] = (int64_t)hp[4 + c->n_bins + k];
+    if (*herr & (kErrSpin | kErrInternal)) return TRIL_E_INTERNAL;
     return TRIL_OK;
 }
 
@@ -2750,6 +2764,7 @@ void tril_destroy(tril_ctx *c) {
     dev_free(c->d_edges);
     dev_free(c->d_cnt);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+    if (c->h_pin) (void)hipHostFree(c->h_pin);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->ev_join_a) (void)hipEventDestroy(c->ev_join_a);
     if (c->ev_join_b) (void)hipEventDestroy(c->ev_join_b);

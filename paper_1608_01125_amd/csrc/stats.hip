@@ -3,9 +3,9 @@
 // pair stands for sqrt(w_i w_j) physical pairs, Sec. 2.2), the pair-energy spectrum
 // over caller edges and the raw hit count per step.
 //
-// Raw hits are sorted by the 64-bit key ((i * n_target + j) << step_bits) | step, so
-// equal pairs become adjacent with their earliest step first; run starts are
-// flagged, scanned and compacted in ascending (i, j) order.
+// Raw hits are sorted by the pair key i * n_target + j (stable, so equal pairs become
+// adjacent); run starts are flagged, scanned and compacted in ascending (i, j) order, each
+// with the earliest step of its run.
 #include "tril_internal.h"
 
 namespace tril {
@@ -16,23 +16,23 @@ constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
 
-__global__ void k_make_keys(const tril_pairs p, int64_t n, int64_t n_target, int step_bits,
+__global__ void k_make_keys(const tril_pairs p, int64_t n, int64_t n_target,
                             unsigned long long *keys, uint32_t *vals,
                             unsigned long long *step_counts, int32_t n_steps_count) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= n) return;
     const unsigned long long i = (uint32_t)p.i[q], j = (uint32_t)p.j[q];
     const uint32_t k = (uint32_t)p.step[q];
-    keys[q] = ((i * (unsigned long long)n_target + j) << step_bits) | k;
+    keys[q] = i * (unsigned long long)n_target + j;
     vals[q] = (uint32_t)q;
     if ((int32_t)k < n_steps_count) atomicAdd(step_counts + k, 1ull);
 }
 
-__global__ void k_flag_runs(const unsigned long long *__restrict__ keys, int64_t n, int step_bits,
+__global__ void k_flag_runs(const unsigned long long *__restrict__ keys, int64_t n,
                             uint32_t *__restrict__ flags) {
     const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (q >= n) return;
-    flags[q] = (q == 0 || (keys[q] >> step_bits) != (keys[q - 1] >> step_bits)) ? 1u : 0u;
+    flags[q] = (q == 0 || keys[q] != keys[q - 1]) ? 1u : 0u;
 }
 
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_tmp, uint32_t *total) {
@@ -136,9 +136,11 @@ __global__ void __launch_bounds__(256) k_compact(const unsigned long long *__res
         const uint32_t src = vals[q];
         const int32_t i = p.i[src], j = p.j[src];
         const int64_t u = (int64_t)pos[q] + tile_pre[q / kScanTile];
+        int32_t k = p.step[src];  // the earliest step of the run (most runs hold one hit)
+        for (int64_t r = q + 1; r < n && !flags[r]; ++r) k = min(k, p.step[vals[r]]);
         ti[u] = i;
         tj[u] = j;
-        tk[u] = p.step[src];
+        tk[u] = k;
         const double yq = sqrt(w_q[i] * w_t[j]);
         y += yq;
         if (n_bins > 0) {
@@ -191,8 +193,7 @@ inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b);
 
 int stats_block_sums_needed(int64_t n) { return (int)((n + kScanTile - 1) / kScanTile) + 1; }
 
-void run_union_stats(const tril_pairs &p, int64_t n_hits, int64_t n_target, int step_bits,
-                     int key_bits, const double *w_q, const double *w_t, const double *E_q, const double *E_t,
+void run_union_stats(const tril_pairs &p, int64_t n_hits, int64_t n_target, int key_bits, const double *w_q, const double *w_t, const double *E_q, const double *E_t,
                      const double *d_edges, int32_t n_bins, int32_t n_steps_count,
                      StatsScratch &s, SortScratch &ss, unsigned int *err, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(n_bins + 1, 256)), dim3(256), 0, st, s.acc,
@@ -206,12 +207,12 @@ void run_union_stats(const tril_pairs &p, int64_t n_hits, int64_t n_target, int 
         return;
     }
     hipLaunchKernelGGL(k_make_keys, dim3(grid_for(n_hits, 256)), dim3(256), 0, st, p, n_hits,
-                       n_target, step_bits, s.keys, s.vals, s.step_counts, n_steps_count);
+                       n_target, s.keys, s.vals, s.step_counts, n_steps_count);
     const bool alt = radix_sort_u64(s.keys, s.vals, s.keys_alt, s.vals_alt, n_hits, key_bits, ss, err, st);
     unsigned long long *keys = alt ? s.keys_alt : s.keys;
     uint32_t *vals = alt ? s.vals_alt : s.vals;
     hipLaunchKernelGGL(k_flag_runs, dim3(grid_for(n_hits, 256)), dim3(256), 0, st, keys, n_hits,
-                       step_bits, s.flags);
+                       s.flags);
     const int64_t tiles = (n_hits + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(kScanBlock), 0, st, s.flags,
                        n_hits, s.pos, s.block_sums);

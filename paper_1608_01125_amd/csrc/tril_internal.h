@@ -681,9 +681,9 @@ struct StatsScratch {
 };
 int stats_block_sums_needed(int64_t n);
 // Union over steps, sorted ascending (i, j), first step kept; yield, spectrum,
-// per-step counts. Writes the unique pairs back into p.i/j/step.
-void run_union_stats(const tril_pairs &p, int64_t n_hits, int64_t n_target, int step_bits,
-                     int key_bits, const double *w_q, const double *w_t, const double *E_q, const double *E_t,
+// per-step counts. Writes the unique pairs back into p.i/j/step. key_bits: bits of the
+// largest pair key i * n_target + j.
+void run_union_stats(const tril_pairs &p, int64_t n_hits, int64_t n_target, int key_bits, const double *w_q, const double *w_t, const double *E_q, const double *E_t,
                      const double *d_edges, int32_t n_bins, int32_t n_steps_count,
                      StatsScratch &s, SortScratch &ss, unsigned int *err, hipStream_t st);
 
