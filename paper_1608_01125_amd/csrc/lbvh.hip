@@ -409,8 +409,10 @@ __global__ void __launch_bounds__(256) k_boxes_keys(BeamDev b, int query, CloudB
         q.unused = 0.0f;
         rec[i] = q;
     }
-    for (int32_t s = 0; s < b.m; ++s) {
-        if (out == nullptr && (vals == nullptr || s != key_step)) continue;
+    // every step's box when boxes are wanted, else only the key step's (for its key)
+    const int32_t s_begin = out != nullptr ? 0 : key_step;
+    const int32_t s_end = out != nullptr ? b.m : (vals != nullptr && key_step < b.m ? key_step + 1 : 0);
+    for (int32_t s = s_begin; s < s_end; ++s) {
         const int32_t cc = s * b.n_inst + mi;
         const double t = (double)(step0 + (unsigned)s) * dt;
         float lo32[3], hi32[3], cen[3];
