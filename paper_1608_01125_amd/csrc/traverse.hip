@@ -631,6 +631,8 @@ __device__ __forceinline__ void add_counts(uint32_t visits, uint32_t checks, uin
 }
 
 // One virtual query per lane over a flat grid.
+constexpr int kXcdRun = 16;
+
 template <int BLOCK, bool kRec, bool kWin, bool kQuad>
 __global__ void __launch_bounds__(BLOCK, kQuad ? 8 : 1) k_traverse(const Node *__restrict__ nodes, int32_t n_int,
                                                     const PBox *__restrict__ root_box,
@@ -643,7 +645,18 @@ __global__ void __launch_bounds__(BLOCK, kQuad ? 8 : 1) k_traverse(const Node *_
                                                     int32_t *__restrict__ cand_j, int64_t cand_cap,
                                                     DevCounters *c, WinArgs wa) {
     __shared__ uint32_t s_lq[kQuad ? kLeafQ * BLOCK : 1];
-    const int64_t q = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+    // the dispatcher deals workgroups to the 8 XCDs in turn: runs of kXcdRun consecutive
+    // workgroups (neighbouring queries, which descend the same subtrees) go to one XCD and
+    // share its L2, while the runs still spread the dense part of the beam over all XCDs
+    int64_t b = blockIdx.x;
+    if (kQuad) {
+        const int64_t span = 8 * (int64_t)kXcdRun;
+        if (b < ((int64_t)gridDim.x / span) * span) {
+            const int64_t slot = b >> 3;
+            b = ((slot / kXcdRun) * 8 + (b & 7)) * kXcdRun + slot % kXcdRun;
+        }
+    }
+    const int64_t q = b * BLOCK + threadIdx.x;
     uint32_t visits = 0, checks = 0;
     const int32_t qsteps = traverse_query<kRec, kWin, kQuad>(
         q, nodes, n_int, root_box, qbox, qrec, n_inst, qorder, order_len, nq, nq_base, inst_root,
