@@ -323,8 +323,8 @@ typedef struct {
 
 /* Autotuner: time tril_run over steps k0 .. k0+n_probe-1 of the given beams for a set of
  * launch configurations and keep the fastest in the context (and in *best). Coordinate
- * descent: steps per launch (1 .. 128, within 2^27 photon-steps per launch, or within the
- * default batch budget where that is larger), then the
+ * descent: steps per launch (the automatic choice, then 1 .. 128 within 2^27 photon-steps
+ * per launch, or within 32 steps' worth for larger beams), then the
  * steps per hierarchy copy (1, 4, 8, 16, 32), then the steps per descent (4, 8, 16, 32,
  * with copies of several steps), then the
  * traversal workgroup size (64 .. 512), then the Morton bits (automatic or 30), then the
