@@ -463,6 +463,39 @@ __global__ void __launch_bounds__(256) k_gather_beam(BeamDev src, const uint32_t
     dst_perm[k] = src.perm ? src.perm[r] : (int32_t)r;
 }
 
+// A beam's rows as 64-B records (x y z, px py pz, E w), read field by field in row order:
+// a gather in a random order then reads one record per row instead of eight scattered words.
+__global__ void __launch_bounds__(256) k_beam_rows(BeamDev src, double2 *__restrict__ rec) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= src.n) return;
+    double2 *o = rec + 4 * r;
+    o[0] = make_double2(src.x[r], src.y[r]);
+    o[1] = make_double2(src.z[r], src.px[r]);
+    o[2] = make_double2(src.py[r], src.pz[r]);
+    o[3] = make_double2(src.E[r], src.w[r]);
+}
+
+// Working copy from a beam's row records (k_beam_rows) in another row order.
+__global__ void __launch_bounds__(256) k_gather_rows(const double2 *__restrict__ rec, int64_t n,
+                                                     const int32_t *__restrict__ src_perm,
+                                                     const uint32_t *__restrict__ order,
+                                                     double *__restrict__ dst,
+                                                     int32_t *__restrict__ dst_perm) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t r = order ? (int64_t)order[k] : k;
+    const double2 a = rec[4 * r], b = rec[4 * r + 1], c = rec[4 * r + 2], d = rec[4 * r + 3];
+    dst[k] = a.x;
+    dst[n + k] = a.y;
+    dst[2 * n + k] = b.x;
+    dst[3 * n + k] = b.y;
+    dst[4 * n + k] = c.x;
+    dst[5 * n + k] = c.y;
+    dst[6 * n + k] = d.x;
+    dst[7 * n + k] = d.y;
+    dst_perm[k] = src_perm ? src_perm[r] : (int32_t)r;
+}
+
 __global__ void __launch_bounds__(256) k_morton_u32(const PBox *__restrict__ box, int64_t n,
                                                     const uint32_t *__restrict__ bounds,
                                                     uint32_t *__restrict__ keys,
@@ -1412,6 +1445,15 @@ void launch_gather_beam(const BeamDev &src, const uint32_t *order, double *dst_s
     if (src.n <= 0) return;
     hipLaunchKernelGGL(k_gather_beam, dim3(grid_for(src.n, 256)), dim3(256), 0, st, src, order,
                        dst_soa, dst_perm);
+}
+
+void launch_gather_beam_staged(const BeamDev &src, const uint32_t *order, double *stage,
+                               double *dst_soa, int32_t *dst_perm, hipStream_t st) {
+    if (src.n <= 0) return;
+    double2 *rec = reinterpret_cast<double2 *>(stage);
+    hipLaunchKernelGGL(k_beam_rows, dim3(grid_for(src.n, 256)), dim3(256), 0, st, src, rec);
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(src.n, 256)), dim3(256), 0, st, rec, src.n,
+                       src.perm, order, dst_soa, dst_perm);
 }
 
 void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint32_t *keys,

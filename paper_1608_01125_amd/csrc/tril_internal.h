@@ -365,6 +365,11 @@ void launch_boxes_keys(const BeamDev &b, bool query, const CloudBox &cloud, doub
 // row of it (through src.perm).
 void launch_gather_beam(const BeamDev &src, const uint32_t *order, double *dst_soa,
                         int32_t *dst_perm, hipStream_t st);
+// The same gather for an order with no locality (a caller's rows into Morton order): the rows
+// are first written as 64-B records into stage (8 src.n doubles, not overlapping dst_soa),
+// so that each output row reads one record instead of eight scattered words.
+void launch_gather_beam_staged(const BeamDev &src, const uint32_t *order, double *stage,
+                               double *dst_soa, int32_t *dst_perm, hipStream_t st);
 void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint32_t *keys,
                        uint32_t *vals, hipStream_t st);
 // Tree shape over n sorted keys (local ids: internal [0, n-1), leaves n-1 + position).
