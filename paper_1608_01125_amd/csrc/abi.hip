@@ -100,6 +100,7 @@ struct tril_ctx {
     // build, join before the traversal), with its own sort scratch
     hipStream_t qst = nullptr;
     hipEvent_t ev_qfork = nullptr, ev_qjoin = nullptr;
+    hipEvent_t ev_tfork = nullptr, ev_tjoin = nullptr;  // target re-gather beside the traversal
     double dt = 0.0;
     uint32_t flags = 0;
     int32_t n_bins = 0;
@@ -1054,6 +1055,10 @@ int tril_create(tril_ctx **out, const tril_params *p, void *stream) {
         return fail(hip_fail(e));
     if ((e = hipEventCreateWithFlags(&c->ev_qjoin, hipEventDisableTiming)) != hipSuccess)
         return fail(hip_fail(e));
+    if ((e = hipEventCreateWithFlags(&c->ev_tfork, hipEventDisableTiming)) != hipSuccess)
+        return fail(hip_fail(e));
+    if ((e = hipEventCreateWithFlags(&c->ev_tjoin, hipEventDisableTiming)) != hipSuccess)
+        return fail(hip_fail(e));
     *out = c;
     return TRIL_OK;
 }
@@ -1251,10 +1256,17 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
                                c->wq[pq ^ 1].perm, c->qst);
         HIPCHK(hipEventRecord(c->ev_qjoin, c->qst));
         HIPCHK(hipStreamWaitEvent(st, c->ev_qjoin, 0));
+        // the target working copy for the next batch in this batch's order, on qst beside the
+        // traversal and narrow phase (they read the other buffer and the tree only)
+        if (regather) {
+            HIPCHK(hipEventRecord(c->ev_tfork, st));
+            HIPCHK(hipStreamWaitEvent(c->qst, c->ev_tfork, 0));
+            launch_gather_beam(wview(t, c->d_t_off, 1, c->wt[pt]), c->t_rows, c->wt[pt ^ 1].soa,
+                               c->wt[pt ^ 1].perm, c->qst);
+            HIPCHK(hipEventRecord(c->ev_tjoin, c->qst));
+        }
         CHK(enqueue_collide(c, qv, *out, st, tm, sort, true));
-        if (!regather) return TRIL_OK;
-        launch_gather_beam(wview(t, c->d_t_off, 1, c->wt[pt]), c->t_rows, c->wt[pt ^ 1].soa,
-                           c->wt[pt ^ 1].perm, st);
+        if (regather) HIPCHK(hipStreamWaitEvent(st, c->ev_tjoin, 0));
         return TRIL_OK;
     };
     int last_pq = 0;            // query working buffer of the last batch enqueued
@@ -2772,6 +2784,8 @@ void tril_destroy(tril_ctx *c) {
     if (c->gst) (void)hipStreamDestroy(c->gst);
     if (c->ev_qfork) (void)hipEventDestroy(c->ev_qfork);
     if (c->ev_qjoin) (void)hipEventDestroy(c->ev_qjoin);
+    if (c->ev_tfork) (void)hipEventDestroy(c->ev_tfork);
+    if (c->ev_tjoin) (void)hipEventDestroy(c->ev_tjoin);
     if (c->qst) (void)hipStreamDestroy(c->qst);
     delete c;
 }
