@@ -498,7 +498,7 @@ inline int32_t key_step(int32_t m) { return m > 0 ? (m - 1) / 2 : 0; }
 // the identity, so that batch skips its sorts (enqueue_build's presorted, a query
 // preparation without sort).
 int enqueue_order(tril_ctx *c, const BeamDev &b, bool query_side, WorkBeam &w, hipStream_t st,
-                  SortScratch &ss, double *stage) {
+                  SortScratch &ss, const double *rows_rec) {
     if (b.n <= 0) return TRIL_OK;
     const KeyLayout kl = key_layout(b.n_inst, c->morton_bits);
     const InstStats *stats = query_side ? c->q_stats : c->t_stats;
@@ -515,7 +515,7 @@ int enqueue_order(tril_ctx *c, const BeamDev &b, bool query_side, WorkBeam &w, h
     else
         rows = radix_sort_u64(k64a, va, k64b, vb, b.n, kl.key_bits, ss, &c->d_cnt->err, st)
                    ? vb : va;
-    launch_gather_beam_staged(b, rows, stage, w.soa, w.perm, st);
+    launch_gather_rows(b, rows_rec, rows, w.soa, w.perm, st);
     return TRIL_OK;
 }
 
@@ -1179,9 +1179,10 @@ int tril_run(tril_ctx *c, const tril_beam *t, const tril_beam *q, int32_t k0, in
     // own sort scratch
     HIPCHK(hipEventRecord(c->ev_qfork, c->st));
     HIPCHK(hipStreamWaitEvent(c->qst, c->ev_qfork, 0));
-    launch_beam_stats(t1, c->t_spart, c->t_stats, c->d_cnt, c->st, true);
-    launch_beam_stats(q1, c->q_spart, c->q_stats, c->d_cnt, c->qst, true);
-    // (the other working buffers, unused until the first batch's re-gather, stage the rows)
+    // (the statistics pass also writes each beam's rows as 64-B records into the other
+    // working buffer, unused until the first batch's re-gather, for the ordering's gather)
+    launch_beam_stats(t1, c->t_spart, c->t_stats, c->d_cnt, c->st, true, c->wt[1].soa);
+    launch_beam_stats(q1, c->q_spart, c->q_stats, c->d_cnt, c->qst, true, c->wq[1].soa);
     CHK(enqueue_order(c, view(t, c->d_t_off, m0), false, c->wt[0], c->st, c->ss, c->wt[1].soa));
     CHK(enqueue_order(c, view(q, c->d_q_off, m0), true, c->wq[0], c->qst, c->ssq, c->wq[1].soa));
     HIPCHK(hipEventRecord(c->ev_qjoin, c->qst));

@@ -189,10 +189,13 @@ __global__ void k_stats_clear(InstStats *stats, int32_t n_inst) {
 // Each block reduces kStatSpan rows into two partials (for the instances of its first
 // and last row); rows of an instance lying strictly inside one block (instances
 // smaller than a block) go to the instance totals with atomics. Invalid rows
-// (non-finite values, E <= 0, w < 0) raise the data error flag and are left out.
+// (non-finite values, E <= 0, w < 0) raise the data error flag and are left out. With rec,
+// every row is also written there as a 64-B record (x y z, px py pz, E w) for
+// k_gather_rows.
 __global__ void __launch_bounds__(kStatThreads) k_beam_stats(BeamDev b, StatsPartial *partials,
                                                             InstStats *stats, DevCounters *c,
-                                                            int light_like) {
+                                                            int light_like,
+                                                            double2 *__restrict__ rec) {
     __shared__ InstStats s_red[kStatThreads / 64][2];
     const int64_t base = blockIdx.x * (int64_t)kStatSpan;
     const int64_t last = (base + kStatSpan < b.n ? base + kStatSpan : b.n) - 1;
@@ -207,6 +210,13 @@ __global__ void __launch_bounds__(kStatThreads) k_beam_stats(BeamDev b, StatsPar
         const double E = b.E[i], w = b.w[i];
         const double px = b.px[i], py = b.py[i], pz = b.pz[i];
         const double x = b.x[i], y = b.y[i], z = b.z[i];
+        if (rec != nullptr) {
+            double2 *o = rec + 4 * i;
+            o[0] = make_double2(x, y);
+            o[1] = make_double2(z, px);
+            o[2] = make_double2(py, pz);
+            o[3] = make_double2(E, w);
+        }
         const bool ok = isfinite(E) && isfinite(w) && isfinite(px) && isfinite(py) &&
                         isfinite(pz) && isfinite(x) && isfinite(y) && isfinite(z) && E > 0.0 &&
                         w >= 0.0;
@@ -463,19 +473,8 @@ __global__ void __launch_bounds__(256) k_gather_beam(BeamDev src, const uint32_t
     dst_perm[k] = src.perm ? src.perm[r] : (int32_t)r;
 }
 
-// A beam's rows as 64-B records (x y z, px py pz, E w), read field by field in row order:
-// a gather in a random order then reads one record per row instead of eight scattered words.
-__global__ void __launch_bounds__(256) k_beam_rows(BeamDev src, double2 *__restrict__ rec) {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= src.n) return;
-    double2 *o = rec + 4 * r;
-    o[0] = make_double2(src.x[r], src.y[r]);
-    o[1] = make_double2(src.z[r], src.px[r]);
-    o[2] = make_double2(src.py[r], src.pz[r]);
-    o[3] = make_double2(src.E[r], src.w[r]);
-}
-
-// Working copy from a beam's row records (k_beam_rows) in another row order.
+// Working copy from a beam's row records (written by k_beam_stats) in another row order:
+// a gather in a random order reads one record per row instead of eight scattered words.
 __global__ void __launch_bounds__(256) k_gather_rows(const double2 *__restrict__ rec, int64_t n,
                                                      const int32_t *__restrict__ src_perm,
                                                      const uint32_t *__restrict__ order,
@@ -1408,12 +1407,13 @@ void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st) {
 int64_t stats_partials_needed(int64_t n) { return 2 * ((n + kStatSpan - 1) / kStatSpan) + 2; }
 
 void launch_beam_stats(const BeamDev &b, StatsPartial *partials, InstStats *stats, DevCounters *c,
-                       hipStream_t st, bool light_like) {
+                       hipStream_t st, bool light_like, double *rows) {
     hipLaunchKernelGGL(k_stats_clear, dim3(grid_for(b.n_inst, 64)), dim3(64), 0, st, stats,
                        b.n_inst);
     if (b.n <= 0) return;
     hipLaunchKernelGGL(k_beam_stats, dim3(grid_for(b.n, kStatSpan)), dim3(kStatThreads), 0, st, b,
-                       partials, stats, c, light_like ? 1 : 0);
+                       partials, stats, c, light_like ? 1 : 0,
+                       reinterpret_cast<double2 *>(rows));
     hipLaunchKernelGGL(k_fold_stats, dim3((unsigned)b.n_inst), dim3(256), 0, st, partials, b,
                        stats);
 }
@@ -1447,13 +1447,12 @@ void launch_gather_beam(const BeamDev &src, const uint32_t *order, double *dst_s
                        dst_soa, dst_perm);
 }
 
-void launch_gather_beam_staged(const BeamDev &src, const uint32_t *order, double *stage,
-                               double *dst_soa, int32_t *dst_perm, hipStream_t st) {
+void launch_gather_rows(const BeamDev &src, const double *rows, const uint32_t *order,
+                        double *dst_soa, int32_t *dst_perm, hipStream_t st) {
     if (src.n <= 0) return;
-    double2 *rec = reinterpret_cast<double2 *>(stage);
-    hipLaunchKernelGGL(k_beam_rows, dim3(grid_for(src.n, 256)), dim3(256), 0, st, src, rec);
-    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(src.n, 256)), dim3(256), 0, st, rec, src.n,
-                       src.perm, order, dst_soa, dst_perm);
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(src.n, 256)), dim3(256), 0, st,
+                       reinterpret_cast<const double2 *>(rows), src.n, src.perm, order, dst_soa,
+                       dst_perm);
 }
 
 void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint32_t *keys,

@@ -336,9 +336,10 @@ void launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t st);
 // Per-instance statistics of beam b (rows only; b.m is ignored); flags invalid data
 // (light_like: also a momentum whose magnitude differs from E by more than 1e-12
 // relative; off for the bin clouds of the statistical regime, whose mean directions are
-// shorter than one).
+// shorter than one). rows: NULL, or 8 b.n doubles that receive every row as a 64-B record
+// (x y z, px py pz, E w) for launch_gather_rows.
 void launch_beam_stats(const BeamDev &b, StatsPartial *partials, InstStats *stats, DevCounters *c,
-                       hipStream_t st, bool light_like);
+                       hipStream_t st, bool light_like, double *rows = nullptr);
 // Swept boxes of all virtual elements of b plus their sort keys and values (the
 // virtual element index). Morton quantisation bounds come from self_stats; query
 // padding and the threshold prune from t_stats (target instance statistics).
@@ -365,11 +366,11 @@ void launch_boxes_keys(const BeamDev &b, bool query, const CloudBox &cloud, doub
 // row of it (through src.perm).
 void launch_gather_beam(const BeamDev &src, const uint32_t *order, double *dst_soa,
                         int32_t *dst_perm, hipStream_t st);
-// The same gather for an order with no locality (a caller's rows into Morton order): the rows
-// are first written as 64-B records into stage (8 src.n doubles, not overlapping dst_soa),
-// so that each output row reads one record instead of eight scattered words.
-void launch_gather_beam_staged(const BeamDev &src, const uint32_t *order, double *stage,
-                               double *dst_soa, int32_t *dst_perm, hipStream_t st);
+// The same gather for an order with no locality (a caller's rows into Morton order) from the
+// rows' 64-B records (8 src.n doubles written by launch_beam_stats; not overlapping dst_soa):
+// each output row reads one record instead of eight scattered words.
+void launch_gather_rows(const BeamDev &src, const double *rows, const uint32_t *order,
+                        double *dst_soa, int32_t *dst_perm, hipStream_t st);
 void launch_morton_u32(const PBox *box, int64_t n, const uint32_t *bounds, uint32_t *keys,
                        uint32_t *vals, hipStream_t st);
 // Tree shape over n sorted keys (local ids: internal [0, n-1), leaves n-1 + position).
