@@ -55,12 +55,15 @@ def _run(wl, A, B, k0, n_steps, m, win, offA=None, offB=None, dwin=0):
 @pytest.mark.parametrize("m,wins", [
     (40, ((2, 0), (5, 0), (16, 0), (16, 1), (16, 3), (16, 16), (32, 0), (32, 32), (40, 7),
           (40, 32))),
-    (7, ((2, 0), (3, 2), (7, 0), (7, 7)))])
+    (7, ((2, 0), (3, 2), (7, 0), (7, 7))),
+    (64, ((2, 0),))])
 def test_candidates_and_pairs_equal_per_step_copies(torch, m, wins):
     """Same candidates (the last launch's, as a multiset, and the count over the run),
     hits and pairs as one copy per step, for windows (steps per copy, steps per descent: 0
     the default) that divide the batch, leave a short last window, and span the whole
     batch, with descents that divide the window or leave a shorter last one in each copy.
+    (64 steps in copies of 2: 32 copies over 3000 rows, whose levels above the refit's
+    chunks are merged level by level, with the binary nodes below the chunk tops unstored.)
     Every candidate comes from a leaf record read: at most one per step of its descent."""
     wl, A, B = _beams(n=3000, boost=3e3)
     k0, n_steps = 150, 3 * m + m // 2 + 1  # full batches (graphs) and a shorter last one
