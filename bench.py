@@ -98,10 +98,11 @@ def batch_sizes(n_steps: int, launches: int) -> list:
     return [m] * (launches - 1) + [n_steps - m * (launches - 1)]
 
 
-def tree_window(tune, arg: int) -> int:
-    """Steps per tree copy in step batches (the library's default for 0)."""
+def tree_window(tune, arg: int, dwin: int) -> int:
+    """Steps per tree copy in step batches (the library's default for 0: 32, or 16 with
+    descents of 4 steps or fewer)."""
     w = (tune or {}).get("kinetic_window", arg) or arg
-    return 32 if w == 0 else w
+    return (16 if dwin <= 4 else 32) if w == 0 else w
 
 
 def descent_window(tune, arg: int, win: int) -> int:
@@ -792,9 +793,12 @@ def main():
         n_launch = st["n_timed_launches"]
         runs = max(st["n_collides"] // max(n_steps, 1), 1)
         batches = batch_sizes(n_steps, launches_per_run)
-        win = tree_window(tune, args.kinetic_window)
-        # the descent length the library used (automatic: adapted from run to run)
-        dwin = st.get("descent_window") or descent_window(tune, args.descent_window, win)
+        # the descent length the library used (automatic: adapted from run to run), and the
+        # copy length that goes with it
+        used = st.get("descent_window")
+        win = tree_window(tune, args.kinetic_window,
+                          used or descent_window(tune, args.descent_window, 32))
+        dwin = used or descent_window(tune, args.descent_window, win)
         copies = sum(b if (win <= 1 or b < 2) else -(-b // win) for b in batches) * runs
         n_desc = sum(descents(b, win, dwin) for b in batches) * runs
         rec_bytes = 48.0 * nB * sum(1 for b in batches if win > 1 and b >= 2) * runs

@@ -131,7 +131,8 @@ typedef struct {
                                      equal codes keep their order (stable sort). The pair set
                                      does not depend on it. */
     int32_t kinetic_window;       /* tril_run batches: steps served by one copy of the target
-                                     hierarchy, >= 0 (0 = automatic: 32; 1 = a copy per step).
+                                     hierarchy, >= 0 (0 = automatic: 32, or 16 while the
+                                     descents are of 4 steps or fewer; 1 = a copy per step).
                                      A copy holds the boxes of its window's middle step; a
                                      query tests its internal nodes with its own box widened
                                      by the target instance's motion (the bounds of u dt)

@@ -541,10 +541,19 @@ int timing_pair(tril_ctx *c, hipStream_t st, std::vector<std::array<int, 2>> &ds
 
 // Steps per tree copy for a batch of m steps: window copies only in the plain regime
 // (straight-line leaf boxes, query records), at most m.
+// Automatic (kwin 0): 32 steps, or 16 while the descents are of 4 steps or fewer (the
+// automatic descent length settles there when a target's photons move apart fast enough
+// that a longer descent's hull reaches too many leaves; shorter copies then tighten the
+// node boxes the same way: broadband beams 458.7 -> 444.4 ms per run, batch64 unchanged).
 constexpr int32_t kDefaultWindow = 32;
+constexpr int32_t kShortWindow = 16;
+int32_t auto_window(const tril_ctx *c) {
+    if (c->kwin > 1) return c->kwin;
+    return (c->kdesc > 0 ? c->kdesc : c->kdesc_auto) <= 4 ? kShortWindow : kDefaultWindow;
+}
 int32_t build_window(const tril_ctx *c, int32_t m) {
     if (m < 2 || c->cloud.on != 0 || c->kwin == 1) return 1;
-    const int32_t w = c->kwin > 1 ? c->kwin : kDefaultWindow;
+    const int32_t w = auto_window(c);
     return w < m ? w : m;
 }
 
@@ -927,7 +936,7 @@ int32_t pick_batch(const tril_ctx *c, const tril_beam *t, const tril_beam *q, in
         // a batch's last copy of fewer than w/8 steps would cost a whole copy's refit for
         // those few steps: they go to the next batch (1.6e7-photon beams: 32 steps per
         // launch rather than 33, one copy per launch instead of two)
-        const int64_t w = c->kwin > 1 ? c->kwin : kDefaultWindow;
+        const int64_t w = auto_window(c);
         if (m > w && m % w < (w + 7) / 8) m -= m % w;
     }
     m = std::min<int64_t>(m, n_steps);
